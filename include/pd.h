@@ -1,0 +1,262 @@
+/*
+ * pd.h -- C ABI of libpd, the MI355X (gfx950) HOG+LBP+SVM pedestrian
+ * detection hot path of Campmany et al., "GPU-based pedestrian detection for
+ * autonomous driving" (arXiv 1611.01642).
+ *
+ * The pipeline, per frame (Section 4.1): build the scaled image pyramid,
+ * extract HOG and LBP features on every level, score every sliding window
+ * with linear SVMs, keep the windows above a threshold and refine them with
+ * non-maximum suppression.
+ *
+ * Conventions shared by every entry point:
+ *   - Every data pointer is a DEVICE pointer owned by the caller unless the
+ *     argument says "host".  The library never allocates device memory on
+ *     these calls; pd_detect takes a caller-provided workspace.
+ *   - `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *     Every call only enqueues work on that stream and returns; results are
+ *     visible after the caller synchronises the stream.
+ *   - Images are 8-bit grayscale, row-major, with a row pitch in bytes
+ *     (pitch >= width).
+ *   - Return value: PD_OK or a negative PD_E_* code; pd_last_error() gives a
+ *     message for the calling thread's last failure.  On an argument error
+ *     nothing is enqueued.
+ *   - Geometry is fixed: 8x8-pixel cells, 16x16-pixel blocks with a one-cell
+ *     stride, 9 unsigned orientation bins, 59 uniform-LBP bins, 64x128
+ *     windows anchored on the cell grid (stride 8 pixels).
+ */
+#ifndef PD_H
+#define PD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define PD_OK            0
+#define PD_E_ARG        (-1)  /* null pointer, bad pitch, unknown flag       */
+#define PD_E_SIZE       (-2)  /* non-positive or over-limit dimensions       */
+#define PD_E_WORKSPACE  (-3)  /* workspace missing or too small              */
+#define PD_E_HIP        (-4)  /* a HIP launch or copy reported an error      */
+
+/* ---- fixed geometry ---------------------------------------------------- */
+#define PD_CELL          8
+#define PD_WIN_W         64
+#define PD_WIN_H         128
+#define PD_HOG_BINS      9
+#define PD_HOG_BLOCK     36     /* 2x2 cells x 9 bins per block            */
+#define PD_LBP_BINS      59
+#define PD_WIN_BLOCKS_Y  15     /* HOG blocks per window: 15 x 7           */
+#define PD_WIN_BLOCKS_X  7
+#define PD_WIN_CELLS_Y   16     /* LBP cells per window: 16 x 8            */
+#define PD_WIN_CELLS_X   8
+#define PD_HOG_DIM       3780   /* 15 * 7 * 36                             */
+#define PD_LBP_DIM       7552   /* 16 * 8 * 59                             */
+#define PD_FEATURE_DIM   11332  /* PD_HOG_DIM + PD_LBP_DIM                 */
+#define PD_MAX_LEVELS    64
+#define PD_MAX_DIM       16384  /* largest accepted image side             */
+#define PD_MAX_MODELS    16
+#define PD_MAX_CANDIDATES 4096  /* windows above threshold kept per frame  */
+
+/* feature subsets (Section 4.1: LBP-SVM, HOG-SVM, HOGLBP-SVM) */
+#define PD_FEAT_HOG      1
+#define PD_FEAT_LBP      2
+
+/* ---- parameters -------------------------------------------------------- */
+typedef struct pd_params {
+    int32_t scale_num;   /* pyramid step as the ratio scale_num/scale_den,  */
+    int32_t scale_den;   /*   e.g. 11/10; must satisfy num > den > 0         */
+    int32_t max_levels;  /* 0: every level the 64x128 window fits in        */
+    float   clip;        /* L2-Hys clip level (0.2)                         */
+    float   eps;         /* L2-Hys epsilon (1e-3)                           */
+    int32_t features;    /* PD_FEAT_HOG | PD_FEAT_LBP                       */
+    int32_t reserved[4]; /* zero                                           */
+} pd_params;
+
+/* Fills the defaults above: 11/10, all levels, 0.2, 1e-3, HOG|LBP. */
+void pd_params_default(pd_params* p);
+
+/* One pyramid level as planned by pd_plan_pyramid (host struct). */
+typedef struct pd_level {
+    int32_t w, h;          /* level size in pixels                          */
+    int32_t pitch;         /* row pitch in bytes inside the packed pyramid  */
+    int32_t cells_x;       /* Wc = w / 8                                    */
+    int32_t cells_y;       /* Hc = h / 8                                    */
+    int32_t blocks_x;      /* Wb = Wc - 1                                   */
+    int32_t blocks_y;      /* Hb = Hc - 1                                   */
+    int32_t win_x;         /* window anchors per row: Wc - 7                */
+    int32_t win_y;         /* window anchor rows:     Hc - 15               */
+    int32_t reserved;
+    int64_t offset;        /* byte offset of the level in the pyramid       */
+} pd_level;
+
+/*
+ * pd_plan_pyramid -- host only, no GPU work.
+ * Level k has size floor(w * den^k / num^k) x floor(h * den^k / num^k)
+ * (Section 4.4, pyramidal sliding window; level 0 is the input itself);
+ * levels are kept while the 64x128 window fits, up to params->max_levels.
+ * Levels are packed one after another, each at a 256-byte aligned offset
+ * with a pitch rounded up to 16 bytes.
+ *   levels  : host array of `cap` entries, filled with the first
+ *             min(n, cap) levels
+ *   n_levels: host, receives n (0 when the image is smaller than a window:
+ *             not an error)
+ *   bytes   : host, receives the size of the packed pyramid buffer
+ * Errors: PD_E_ARG (null params/outputs, bad scale), PD_E_SIZE (w or h
+ * outside [1, PD_MAX_DIM]).
+ */
+int pd_plan_pyramid(int w, int h, const pd_params* params, pd_level* levels,
+                    int cap, int* n_levels, int64_t* bytes);
+
+/*
+ * pd_build_pyramid -- Section 4.1 step (2), Section 4.4.
+ * Writes every planned level into `pyr` (packed as planned) in one launch.
+ * Level k is resampled from the level-0 image: output pixel (x, y) samples
+ * the source at ((x + 0.5) w0 / wk - 0.5, (y + 0.5) h0 / hk - 0.5) in Q8
+ * fixed point, bilinear, rounded half up; level 0 is an exact copy.
+ *   img     : device, h rows of `pitch` bytes
+ *   levels  : host array of n entries from pd_plan_pyramid
+ *   pyr     : device, at least the `bytes` pd_plan_pyramid returned
+ */
+int pd_build_pyramid(const uint8_t* img, int w, int h, int pitch,
+                     const pd_level* levels, int n, uint8_t* pyr, void* stream);
+
+/*
+ * pd_lbp_codes -- Section 4.2, Algorithm 1.
+ * 8-bit LBP code of every pixel: neighbour k (TL,T,TR,R,BR,B,BL,L for
+ * k = 0..7) sets bit k when it is >= the centre; neighbours outside the
+ * image are clamped to the edge.
+ *   codes   : device [h][codes_pitch] bytes
+ */
+int pd_lbp_codes(const uint8_t* lvl, int w, int h, int pitch,
+                 uint8_t* codes, int codes_pitch, void* stream);
+
+/*
+ * pd_lbp -- Section 4.2, Algorithms 1 and 2.
+ * Uniform-LBP cell histograms: every pixel of the Hc x Wc whole 8x8 cells
+ * adds one count to its cell's bin (58 uniform codes in ascending order,
+ * then one bin for all other codes).
+ *   cell_hist: device uint8 [59][Hc][Wc] (bin-major planes; counts 0..64)
+ */
+int pd_lbp(const uint8_t* lvl, int w, int h, int pitch, uint8_t* cell_hist,
+           void* stream);
+
+/*
+ * pd_hog -- Section 4.3, Algorithms 4 and 5, plus L2-Hys block
+ * normalisation.  Gradient dx = I[y][x-1] - I[y][x+1],
+ * dy = I[y-1][x] - I[y+1][x] (edge-clamped); orientation folded to
+ * [0, 180) degrees; 9 bins centred at 10 + 20k degrees with linear
+ * interpolation; bilinear spatial weights towards the four cell centres of
+ * each 16x16 block; then v/sqrt(|v|^2+eps^2), clip, renormalise.
+ *   blocks  : device float [36][Hb][Wb]; entry (r*2+c)*9+bin of block
+ *             (by, bx) is plane (r*2+c)*9+bin
+ */
+int pd_hog(const uint8_t* lvl, int w, int h, int pitch, const pd_params* params,
+           float* blocks, void* stream);
+
+/*
+ * pd_features -- pd_hog and pd_lbp of one level in a single pass over the
+ * pixels (either output may be NULL when its subset is off).
+ */
+int pd_features(const uint8_t* lvl, int w, int h, int pitch, const pd_params* params,
+                float* blocks, uint8_t* cell_hist, void* stream);
+
+/*
+ * pd_score_windows -- Section 4.4, Algorithm 6.
+ * For every window anchor (i, j), 0 <= i < Hc-15, 0 <= j < Wc-7:
+ *   s_m(i,j) = sum_{a<15,b<7,c<36} blocks[c][i+a][j+b] * w_m[(a*7+b)*36+c]
+ *            + sum_{a<16,b<8,c<59} cells[c][i+a][j+b] * w_m[3780+(a*8+b)*59+c]
+ *            + bias_m
+ * in FP32 (FP32 products and sums).
+ *   blocks  : device float [36][Hc-1][Wc-1] (pd_hog layout)
+ *   cells   : device uint8 [59][Hc][Wc] (pd_lbp layout)
+ *   weights : device float [n_models][11332]
+ *   bias    : device float [n_models]
+ *   scores  : device float [n_models][Hc-15][Wc-7]
+ * Errors: PD_E_SIZE when Hc < 16 or Wc < 8 or n_models outside
+ * [1, PD_MAX_MODELS].
+ */
+int pd_score_windows(const float* blocks, const uint8_t* cells, int cells_x, int cells_y,
+                     const float* weights, const float* bias, int n_models,
+                     float* scores, void* stream);
+
+/* ---- whole pipeline ------------------------------------------------------ */
+
+/* One input frame (device image). */
+typedef struct pd_frame {
+    const uint8_t* data;
+    int32_t w, h, pitch;
+    int32_t reserved;
+} pd_frame;
+
+/* One detection, in original-image coordinates of its frame. */
+typedef struct pd_box {
+    int32_t frame, level, i, j, model;
+    int32_t x0, y0, x1, y1;  /* box in 1/256 pixels: x0 = floor(256*8j*w0/wk),
+                                x1 = floor(256*(8j+64)*w0/wk), y likewise
+                                with 128 and the heights                    */
+    float   score;           /* window score (max over models)             */
+    double  score64;         /* reserved; NaN                              */
+} pd_box;
+
+/* Per-frame result counters written by pd_detect. */
+typedef struct pd_counts {
+    int32_t candidates;  /* windows with score > threshold (true count)    */
+    int32_t kept;        /* boxes written after NMS (<= cap)               */
+    int32_t overflow;    /* 1 if candidates > PD_MAX_CANDIDATES or the kept
+                            boxes exceeded `cap` (results then incomplete) */
+    int32_t reserved;
+} pd_counts;
+
+/*
+ * pd_detect_workspace_bytes -- host only.  Size of the device workspace
+ * pd_detect needs for these frame sizes (host array `frames`, only w and h
+ * are read) and n_models.  Returns a negative PD_E_* code on bad input.
+ */
+int64_t pd_detect_workspace_bytes(const pd_frame* frames, int n_frames,
+                                  const pd_params* params, int n_models);
+
+/*
+ * pd_detect -- the whole hot path for a batch of device-resident frames of
+ * any sizes (Section 4.1 steps 2-5): pyramid, features, window scores,
+ * threshold (a window is a detection iff its score, the max over models,
+ * is > thresholds[frame]) and greedy NMS (order by score descending, then
+ * level, i, j ascending; a box is suppressed iff its IoU with a kept box is
+ * > 0.5, decided exactly as 2*inter > union on the integer boxes).  Every
+ * stage is one launch over all frames and levels.
+ *   frames     : host array of n_frames descriptors (device images)
+ *   weights    : device float [n_models][11332], bias: device [n_models]
+ *   thresholds : device double [n_frames]
+ *   workspace  : device, >= pd_detect_workspace_bytes(...) bytes
+ *   boxes      : device pd_box [n_frames][cap], kept boxes in NMS order
+ *   counts     : device pd_counts [n_frames]
+ */
+int pd_detect(const pd_frame* frames, int n_frames, const float* weights,
+              const float* bias, int n_models, const pd_params* params,
+              const double* thresholds, void* workspace, int64_t workspace_bytes,
+              pd_box* boxes, int cap, pd_counts* counts, void* stream);
+
+/*
+ * pd_nms -- greedy NMS of one candidate list (the last stage of pd_detect,
+ * exposed for testing).  Candidates are windows of one frame:
+ *   cand_score : device float [n]; cand_key: device int32 [n][4] =
+ *                (level, i, j, model)
+ *   level_wh   : host int32 [n_levels][2] level sizes, (w0, h0) = level 0
+ *   boxes      : device pd_box [cap]; counts: device pd_counts [1]
+ * Keys name levels in [0, n_levels) and anchors below 2048 (an out-of-range
+ * level is clamped).  Errors: PD_E_SIZE when n > PD_MAX_CANDIDATES.
+ */
+int pd_nms(const float* cand_score, const int32_t* cand_key, int n,
+           const int32_t* level_wh, int n_levels, pd_box* boxes, int cap,
+           pd_counts* counts, void* stream);
+
+/* ---- diagnostics ----------------------------------------------------------- */
+const char* pd_strerror(int code);
+const char* pd_last_error(void);   /* calling thread's last failure message */
+const char* pd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PD_H */

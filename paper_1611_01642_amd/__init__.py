@@ -1,0 +1,294 @@
+"""Python binding of libpd, the MI355X HOG+LBP+SVM detection hot path.
+
+Argument marshalling only: every step runs in libpd's HIP kernels.  Torch
+tensors serve as device memory (``data_ptr()``) and streams
+(``torch.cuda.current_stream()``).  If libpd.so has not been built this module
+raises on first use; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpd.so")
+
+CELL = 8
+WIN_W, WIN_H = 64, 128
+HOG_BLOCK = 36
+LBP_BINS = 59
+HOG_DIM, LBP_DIM, FEATURE_DIM = 3780, 7552, 11332
+MAX_LEVELS = 64
+MAX_MODELS = 16
+MAX_CANDIDATES = 4096
+FEAT_HOG, FEAT_LBP = 1, 2
+
+E_ARG, E_SIZE, E_WORKSPACE, E_HIP = -1, -2, -3, -4
+
+
+class PdError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libpd error {code}: {msg}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("scale_num", ctypes.c_int32), ("scale_den", ctypes.c_int32),
+                ("max_levels", ctypes.c_int32), ("clip", ctypes.c_float), ("eps", ctypes.c_float),
+                ("features", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+
+
+class Level(ctypes.Structure):
+    _fields_ = [("w", ctypes.c_int32), ("h", ctypes.c_int32), ("pitch", ctypes.c_int32),
+                ("cells_x", ctypes.c_int32), ("cells_y", ctypes.c_int32),
+                ("blocks_x", ctypes.c_int32), ("blocks_y", ctypes.c_int32),
+                ("win_x", ctypes.c_int32), ("win_y", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("offset", ctypes.c_int64)]
+
+
+class Frame(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("w", ctypes.c_int32), ("h", ctypes.c_int32),
+                ("pitch", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+BOX_DTYPE = np.dtype([("frame", "<i4"), ("level", "<i4"), ("i", "<i4"), ("j", "<i4"), ("model", "<i4"),
+                      ("x0", "<i4"), ("y0", "<i4"), ("x1", "<i4"), ("y1", "<i4"),
+                      ("score", "<f4"), ("score64", "<f8")])
+COUNTS_DTYPE = np.dtype([("candidates", "<i4"), ("kept", "<i4"), ("overflow", "<i4"), ("reserved", "<i4")])
+assert BOX_DTYPE.itemsize == 48 and COUNTS_DTYPE.itemsize == 16
+
+_lib = None
+
+_SIGS = {
+    "pd_params_default": (None, [ctypes.c_void_p]),
+    "pd_plan_pyramid": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
+    "pd_build_pyramid": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
+    "pd_lbp_codes": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                    ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
+    "pd_lbp": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                              ctypes.c_void_p]),
+    "pd_hog": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                              ctypes.c_void_p, ctypes.c_void_p]),
+    "pd_features": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "pd_score_windows": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                        ctypes.c_void_p]),
+    "pd_detect_workspace_bytes": (ctypes.c_int64, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int]),
+    "pd_detect": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                 ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
+    "pd_nms": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
+                              ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
+    "pd_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "pd_last_error": (ctypes.c_char_p, []),
+    "pd_version": (ctypes.c_char_p, []),
+}
+
+EXPORTED = tuple(_SIGS)
+
+
+def lib():
+    """The loaded libpd (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing; build it with `python -m paper_1611_01642_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int) -> None:
+    if rc != 0:
+        raise PdError(rc, lib().pd_last_error().decode())
+
+
+def params(scale=(11, 10), max_levels: int = 0, clip: float = 0.2, eps: float = 1e-3,
+           features: int = FEAT_HOG | FEAT_LBP) -> Params:
+    p = Params()
+    lib().pd_params_default(ctypes.byref(p))
+    p.scale_num, p.scale_den = scale
+    p.max_levels = max_levels
+    p.clip = clip
+    p.eps = eps
+    p.features = features
+    return p
+
+
+def plan_pyramid(w: int, h: int, prm: Params = None):
+    """(levels, bytes): exact level sizes and packed offsets (host only)."""
+    prm = prm or params()
+    arr = (Level * MAX_LEVELS)()
+    n = ctypes.c_int(0)
+    nbytes = ctypes.c_int64(0)
+    _check(lib().pd_plan_pyramid(w, h, ctypes.byref(prm), arr, MAX_LEVELS, ctypes.byref(n), ctypes.byref(nbytes)))
+    return [arr[k] for k in range(n.value)], nbytes.value
+
+
+# ---------------------------------------------------------------- device --
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    return ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
+
+
+def _image_args(img):
+    torch = _torch()
+    if img.dtype != torch.uint8 or img.dim() != 2 or not img.is_cuda or img.stride(1) != 1:
+        raise ValueError("expected a 2-D uint8 CUDA tensor with unit column stride")
+    h, w = img.shape
+    return ctypes.c_void_p(img.data_ptr()), int(w), int(h), int(img.stride(0))
+
+
+def build_pyramid(img, prm: Params = None):
+    """(pyramid bytes, levels, views): all levels in one launch; `views` are
+    [h][w] uint8 views into the packed buffer."""
+    torch = _torch()
+    p, w, h, pitch = _image_args(img)
+    levels, nbytes = plan_pyramid(w, h, prm)
+    pyr = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=img.device)
+    arr = (Level * max(len(levels), 1))(*levels)
+    _check(lib().pd_build_pyramid(p, w, h, pitch, arr, len(levels), ctypes.c_void_p(pyr.data_ptr()), _stream()))
+    views = [pyr[L.offset:L.offset + L.pitch * L.h].view(L.h, L.pitch)[:, :L.w] for L in levels]
+    return pyr, levels, views
+
+
+def lbp_codes(img):
+    torch = _torch()
+    p, w, h, pitch = _image_args(img)
+    out = torch.empty((h, w), dtype=torch.uint8, device=img.device)
+    _check(lib().pd_lbp_codes(p, w, h, pitch, ctypes.c_void_p(out.data_ptr()), w, _stream()))
+    return out
+
+
+def features(img, prm: Params = None, hog: bool = True, lbp: bool = True):
+    """(blocks [36][Hb][Wb] float32 or None, cells [59][Hc][Wc] uint8 or None)."""
+    torch = _torch()
+    prm = prm or params()
+    p, w, h, pitch = _image_args(img)
+    hc, wc = h // CELL, w // CELL
+    blocks = torch.empty((HOG_BLOCK, max(hc - 1, 0), max(wc - 1, 0)), dtype=torch.float32,
+                         device=img.device) if hog else None
+    cells = torch.empty((LBP_BINS, hc, wc), dtype=torch.uint8, device=img.device) if lbp else None
+    _check(lib().pd_features(p, w, h, pitch, ctypes.byref(prm),
+                             ctypes.c_void_p(blocks.data_ptr() if hog else 0),
+                             ctypes.c_void_p(cells.data_ptr() if lbp else 0), _stream()))
+    return blocks, cells
+
+
+def hog(img, prm: Params = None):
+    return features(img, prm, hog=True, lbp=False)[0]
+
+
+def lbp(img):
+    return features(img, None, hog=False, lbp=True)[1]
+
+
+def score_windows(blocks, cells, weights, bias):
+    """Scores [m][Hc-15][Wc-7] float32 of every window for every model."""
+    torch = _torch()
+    hc, wc = int(cells.shape[1]), int(cells.shape[2])
+    if blocks.shape != (HOG_BLOCK, hc - 1, wc - 1) or not blocks.is_contiguous() or not cells.is_contiguous():
+        raise ValueError("blocks must be [36][Hc-1][Wc-1] and cells [59][Hc][Wc], contiguous")
+    weights = weights.contiguous()
+    m = int(weights.shape[0])
+    out = torch.empty((m, max(hc - 15, 0), max(wc - 7, 0)), dtype=torch.float32, device=cells.device)
+    _check(lib().pd_score_windows(ctypes.c_void_p(blocks.data_ptr()), ctypes.c_void_p(cells.data_ptr()), wc, hc,
+                                  ctypes.c_void_p(weights.data_ptr()), ctypes.c_void_p(bias.data_ptr()), m,
+                                  ctypes.c_void_p(out.data_ptr()), _stream()))
+    return out
+
+
+def nms(cand_score, cand_key, level_wh, cap: int):
+    """Greedy NMS of one frame's candidates.  cand_score: float32 [n] device;
+    cand_key: int32 [n][4] (level, i, j, model) device; level_wh: host list of
+    (w, h).  Returns (boxes uint8 [cap*48] device, counts uint8 [16] device)."""
+    torch = _torch()
+    n = int(cand_score.numel())
+    wh = (ctypes.c_int32 * (2 * len(level_wh)))(*[v for pair in level_wh for v in pair])
+    dev = cand_score.device
+    boxes = torch.empty(max(cap, 1) * BOX_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+    counts = torch.empty(COUNTS_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+    _check(lib().pd_nms(ctypes.c_void_p(cand_score.data_ptr()), ctypes.c_void_p(cand_key.data_ptr()), n, wh,
+                        len(level_wh), ctypes.c_void_p(boxes.data_ptr()), cap,
+                        ctypes.c_void_p(counts.data_ptr()), _stream()))
+    return boxes, counts
+
+
+def _frames_array(frames):
+    arr = (Frame * len(frames))()
+    for f, img in enumerate(frames):
+        p, w, h, pitch = _image_args(img)
+        arr[f].data, arr[f].w, arr[f].h, arr[f].pitch = p.value, w, h, pitch
+    return arr
+
+
+def workspace_bytes(sizes, n_models: int = 1, prm: Params = None) -> int:
+    """Workspace bytes pd_detect needs for frames of these (w, h) sizes."""
+    prm = prm or params()
+    arr = (Frame * len(sizes))()
+    for f, (w, h) in enumerate(sizes):
+        arr[f].w, arr[f].h = w, h
+    v = lib().pd_detect_workspace_bytes(arr, len(sizes), ctypes.byref(prm), n_models)
+    if v < 0:
+        _check(int(v))
+    return int(v)
+
+
+@dataclass
+class Detector:
+    """Holds the device buffers of pd_detect for one batch shape."""
+    frames: list
+    weights: object
+    bias: object
+    prm: Params
+    cap: int = 1024
+
+    def __post_init__(self):
+        torch = _torch()
+        self.weights = self.weights.contiguous()
+        self.n_models = int(self.weights.shape[0])
+        self.sizes = [(int(f.shape[1]), int(f.shape[0])) for f in self.frames]
+        self.ws_bytes = workspace_bytes(self.sizes, self.n_models, self.prm)
+        dev = self.frames[0].device
+        self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=dev)
+        off = (-self.workspace.data_ptr()) % 256
+        self.ws_ptr = self.workspace.data_ptr() + off
+        n = len(self.frames)
+        self.boxes = torch.empty(n * max(self.cap, 1) * BOX_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+        self.counts = torch.empty(n * COUNTS_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+        self._frames = _frames_array(self.frames)
+
+    def run(self, thresholds) -> None:
+        """Enqueue the whole pipeline; thresholds: float64 CUDA tensor [n_frames]."""
+        _check(lib().pd_detect(self._frames, len(self.frames), ctypes.c_void_p(self.weights.data_ptr()),
+                               ctypes.c_void_p(self.bias.data_ptr()), self.n_models, ctypes.byref(self.prm),
+                               ctypes.c_void_p(thresholds.data_ptr()), ctypes.c_void_p(self.ws_ptr),
+                               self.ws_bytes, ctypes.c_void_p(self.boxes.data_ptr()), self.cap,
+                               ctypes.c_void_p(self.counts.data_ptr()), _stream()))
+
+    def results(self):
+        """(boxes per frame as numpy structured arrays, counts structured array)."""
+        counts = self.counts.cpu().numpy().view(COUNTS_DTYPE)
+        allb = self.boxes.cpu().numpy().view(BOX_DTYPE).reshape(len(self.frames), max(self.cap, 1))
+        return [allb[f, :counts[f]["kept"]].copy() for f in range(len(self.frames))], counts
+
+
+def decode_boxes(boxes_u8, counts_u8):
+    counts = counts_u8.cpu().numpy().view(COUNTS_DTYPE)
+    b = boxes_u8.cpu().numpy().view(BOX_DTYPE)
+    return b[:counts[0]["kept"]].copy(), counts[0]

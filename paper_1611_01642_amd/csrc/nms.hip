@@ -1,0 +1,257 @@
+// Threshold classification (Section 4.4) and non-maximum-suppression
+// refinement (Section 3; Section 4.1 step 5, done here on the GPU).
+//
+// compact: one thread per window; the window's score is the max over the
+//   models (lowest model index on ties); windows with score > threshold are
+//   appended to their frame's candidate list with an atomic counter.
+// nms: one workgroup per frame.  Candidates are sorted by (score descending,
+//   level, i, j ascending) with a bitonic sort in LDS; the greedy pass walks
+//   them in chunks of 64: a candidate is suppressed if it overlaps (IoU > 0.5,
+//   decided exactly as 2*inter > union on integer boxes) a box kept in an
+//   earlier chunk (tested in parallel) or an earlier kept box of its own chunk
+//   (a 64x64 overlap mask resolved by one lane).  This is exactly the serial
+//   greedy algorithm, and needs no n x n mask in memory.
+#include "pd_internal.h"
+
+namespace pd {
+namespace {
+
+__global__ void zero_kernel(int32_t* p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+__global__ void __launch_bounds__(256) compact_kernel(const LevelItem* __restrict__ items,
+                                                      const Tile* __restrict__ tiles, int n_models,
+                                                      const double* __restrict__ thresholds,
+                                                      int32_t* __restrict__ counters,
+                                                      float* __restrict__ cand_score,
+                                                      int4* __restrict__ cand_key) {
+    const Tile tl = tiles[blockIdx.x];
+    const LevelItem& it = items[tl.item];
+    const int n = it.nx * it.ny;
+    const int q = tl.tx * CP_N + threadIdx.x;
+    if (q >= n) return;
+    const float* s = it.scores + q;
+    float best = s[0];
+    int bm = 0;
+    for (int m = 1; m < n_models; ++m) {
+        const float v = s[(size_t)m * n];
+        if (v > best) {
+            best = v;
+            bm = m;
+        }
+    }
+    if ((double)best > thresholds[it.frame]) {
+        const int pos = atomicAdd(&counters[it.frame], 1);
+        if (pos < PD_MAX_CANDIDATES) {
+            const size_t o = (size_t)it.frame * PD_MAX_CANDIDATES + pos;
+            const int i = q / it.nx;
+            cand_score[o] = best;
+            cand_key[o] = make_int4(it.level, i, q - i * it.nx, bm);
+        }
+    }
+}
+
+struct NmsSmem {
+    unsigned long long key[PD_MAX_CANDIDATES];
+    uint16_t sidx[PD_MAX_CANDIDATES];
+    uint16_t kpos[PD_MAX_CANDIDATES];
+    int4 kbox[PD_MAX_CANDIDATES];
+    int4 cbox[64];
+    unsigned long long cmask[64];
+    uint32_t sup[2];
+    int nkept;
+};
+
+__device__ inline unsigned long long sort_key(float s, int4 k) {
+    s = s + 0.0f;  // -0 -> +0
+    uint32_t f = __float_as_uint(s);
+    f = (f & 0x80000000u) ? ~f : (f | 0x80000000u);  // ascending with the float
+    const uint32_t lo = ((uint32_t)k.x << 22) | ((uint32_t)k.y << 11) | (uint32_t)k.z;
+    // descending score first; real keys stay below the all-ones padding key
+    return ((unsigned long long)min(~f, 0xFFFFFFFEu) << 32) | lo;
+}
+
+__device__ inline int4 window_box(const NmsGeom& g, int level, int i, int j) {
+    level = min(max(level, 0), g.n_levels - 1);
+    const int64_t w0 = g.wh[0][0], h0 = g.wh[0][1];
+    const int64_t wk = g.wh[level][0], hk = g.wh[level][1];
+    int4 b;
+    b.x = (int)((256LL * PD_CELL * j * w0) / wk);
+    b.y = (int)((256LL * PD_CELL * i * h0) / hk);
+    b.z = (int)((256LL * (PD_CELL * j + PD_WIN_W) * w0) / wk);
+    b.w = (int)((256LL * (PD_CELL * i + PD_WIN_H) * h0) / hk);
+    return b;
+}
+
+__device__ inline bool overlaps(const int4& a, const int4& b) {
+    const int64_t iw = (int64_t)min(a.z, b.z) - max(a.x, b.x);
+    const int64_t ih = (int64_t)min(a.w, b.w) - max(a.y, b.y);
+    if (iw <= 0 || ih <= 0) return false;
+    const int64_t inter = iw * ih;
+    const int64_t uni = (int64_t)(a.z - a.x) * (a.w - a.y) + (int64_t)(b.z - b.x) * (b.w - b.y) - inter;
+    return 2 * inter > uni;
+}
+
+__device__ void nms_frame(const NmsGeom& g, int frame, int raw_count, const float* __restrict__ cs,
+                          const int4* __restrict__ ck, pd_box* __restrict__ boxes, int cap,
+                          pd_counts* __restrict__ counts) {
+    extern __shared__ __align__(16) uint8_t smem_raw[];
+    NmsSmem& sm = *reinterpret_cast<NmsSmem*>(smem_raw);
+    const int t = threadIdx.x;
+    const int n = min(raw_count, PD_MAX_CANDIDATES);
+    int np2 = 64;
+    while (np2 < n) np2 <<= 1;
+    for (int q = t; q < np2; q += 256) {
+        sm.key[q] = q < n ? sort_key(cs[q], ck[q]) : ~0ull;
+        sm.sidx[q] = (uint16_t)q;
+    }
+    if (t == 0) sm.nkept = 0;
+    __syncthreads();
+    for (int k = 2; k <= np2; k <<= 1) {
+        for (int jj = k >> 1; jj > 0; jj >>= 1) {
+            for (int q = t; q < np2; q += 256) {
+                const int p = q ^ jj;
+                if (p > q) {
+                    const unsigned long long a = sm.key[q], b = sm.key[p];
+                    const bool up = (q & k) == 0;
+                    if ((a > b) == up) {
+                        sm.key[q] = b;
+                        sm.key[p] = a;
+                        const uint16_t ti = sm.sidx[q];
+                        sm.sidx[q] = sm.sidx[p];
+                        sm.sidx[p] = ti;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+
+    for (int c0 = 0; c0 < n; c0 += 64) {
+        const int cn = min(64, n - c0);
+        if (t < cn) {
+            const int4 k = ck[sm.sidx[c0 + t]];
+            sm.cbox[t] = window_box(g, k.x, k.y, k.z);
+        }
+        if (t < 2) sm.sup[t] = 0u;
+        __syncthreads();
+        const int K = sm.nkept;
+        for (int e = t; e < cn * K; e += 256) {
+            const int q = e % cn, kk = e / cn;
+            if (overlaps(sm.cbox[q], sm.kbox[kk])) atomicOr(&sm.sup[q >> 5], 1u << (q & 31));
+        }
+        if (t < cn) {
+            unsigned long long m = 0;
+            for (int r = t + 1; r < cn; ++r)
+                if (overlaps(sm.cbox[t], sm.cbox[r])) m |= 1ull << r;
+            sm.cmask[t] = m;
+        }
+        __syncthreads();
+        if (t == 0) {
+            unsigned long long alive = (cn == 64) ? ~0ull : ((1ull << cn) - 1);
+            alive &= ~(((unsigned long long)sm.sup[1] << 32) | sm.sup[0]);
+            int nk = sm.nkept;
+            for (int q = 0; q < cn; ++q) {
+                if ((alive >> q) & 1ull) {
+                    sm.kbox[nk] = sm.cbox[q];
+                    sm.kpos[nk] = (uint16_t)(c0 + q);
+                    ++nk;
+                    alive &= ~sm.cmask[q];
+                }
+            }
+            sm.nkept = nk;
+        }
+        __syncthreads();
+    }
+
+    const int K = sm.nkept;
+    const int nout = min(K, cap);
+    for (int q = t; q < nout; q += 256) {
+        const int src = sm.sidx[sm.kpos[q]];
+        const int4 k = ck[src];
+        pd_box b;
+        b.frame = frame;
+        b.level = k.x;
+        b.i = k.y;
+        b.j = k.z;
+        b.model = k.w;
+        const int4 bx = sm.kbox[q];
+        b.x0 = bx.x;
+        b.y0 = bx.y;
+        b.x1 = bx.z;
+        b.y1 = bx.w;
+        b.score = cs[src];
+        b.score64 = __longlong_as_double(0x7ff8000000000000LL);
+        boxes[(size_t)frame * cap + q] = b;
+    }
+    if (t == 0) {
+        pd_counts c;
+        c.candidates = raw_count;
+        c.kept = nout;
+        c.overflow = (raw_count > PD_MAX_CANDIDATES || K > cap) ? 1 : 0;
+        c.reserved = 0;
+        counts[frame] = c;
+    }
+}
+
+__global__ void __launch_bounds__(256) nms_table_kernel(const NmsGeom* __restrict__ geoms,
+                                                        const int32_t* __restrict__ counters,
+                                                        const float* __restrict__ cand_score,
+                                                        const int4* __restrict__ cand_key,
+                                                        pd_box* __restrict__ boxes, int cap,
+                                                        pd_counts* __restrict__ counts) {
+    const int f = blockIdx.x;
+    const size_t o = (size_t)f * PD_MAX_CANDIDATES;
+    nms_frame(geoms[f], f, counters[f], cand_score + o, cand_key + o, boxes, cap, counts);
+}
+
+__global__ void __launch_bounds__(256) nms_single_kernel(NmsGeom g, int n, const float* __restrict__ cs,
+                                                         const int4* __restrict__ ck, pd_box* __restrict__ boxes,
+                                                         int cap, pd_counts* __restrict__ counts) {
+    nms_frame(g, 0, n, cs, ck, boxes, cap, counts);
+}
+
+constexpr size_t kNmsSmem = sizeof(NmsSmem);
+static_assert(kNmsSmem <= 160 * 1024, "NMS scratch exceeds LDS");
+
+}  // namespace
+
+hipError_t launch_zero_i32(int32_t* p, int n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    zero_kernel<<<ceil_div(n, 256), 256, 0, s>>>(p, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_compact_table(const LevelItem* items, const Tile* tiles, int n_tiles, int n_models,
+                                const double* thresholds, int32_t* counters, float* cand_score,
+                                int4* cand_key, hipStream_t s) {
+    if (n_tiles <= 0) return hipSuccess;
+    compact_kernel<<<n_tiles, 256, 0, s>>>(items, tiles, n_models, thresholds, counters, cand_score,
+                                           cand_key);
+    return hipGetLastError();
+}
+
+hipError_t launch_nms_table(const NmsGeom* geoms, int n_frames, const int32_t* counters,
+                            const float* cand_score, const int4* cand_key, pd_box* boxes, int cap,
+                            pd_counts* counts, hipStream_t s) {
+    if (n_frames <= 0) return hipSuccess;
+    static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&nms_table_kernel),
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kNmsSmem);
+    if (attr != hipSuccess) return attr;
+    nms_table_kernel<<<n_frames, 256, kNmsSmem, s>>>(geoms, counters, cand_score, cand_key, boxes, cap,
+                                                    counts);
+    return hipGetLastError();
+}
+
+hipError_t launch_nms_single(const NmsGeom& g, int n, const float* cand_score, const int4* cand_key,
+                             pd_box* boxes, int cap, pd_counts* counts, hipStream_t s) {
+    static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&nms_single_kernel),
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kNmsSmem);
+    if (attr != hipSuccess) return attr;
+    nms_single_kernel<<<1, 256, kNmsSmem, s>>>(g, n, cand_score, cand_key, boxes, cap, counts);
+    return hipGetLastError();
+}
+
+}  // namespace pd

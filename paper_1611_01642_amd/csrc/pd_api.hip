@@ -1,0 +1,496 @@
+// C ABI of libpd: argument checks, pyramid planning, workspace layout and the
+// launch sequence of the detection pipeline.  No allocation happens here:
+// every device buffer comes from the caller.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "pd_internal.h"
+
+using namespace pd;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int hip_status(hipError_t e, const char* what) {
+    if (e == hipSuccess) return PD_OK;
+    return fail(PD_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+constexpr int64_t kAlign = 256;
+inline int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+bool check_params(const pd_params* p) {
+    if (!p) return fail(PD_E_ARG, "params is NULL"), false;
+    if (p->scale_den <= 0 || p->scale_num <= p->scale_den || p->scale_num > 1000000)
+        return fail(PD_E_ARG, "scale must satisfy num > den > 0 (got %d/%d)", p->scale_num, p->scale_den),
+               false;
+    if (p->max_levels < 0) return fail(PD_E_ARG, "max_levels < 0"), false;
+    if (!(p->clip > 0.0f) || !(p->eps > 0.0f) || !std::isfinite(p->clip) || !std::isfinite(p->eps))
+        return fail(PD_E_ARG, "clip and eps must be positive"), false;
+    if ((p->features & ~(PD_FEAT_HOG | PD_FEAT_LBP)) != 0 || (p->features & (PD_FEAT_HOG | PD_FEAT_LBP)) == 0)
+        return fail(PD_E_ARG, "unknown feature flags 0x%x", p->features), false;
+    return true;
+}
+
+int check_image(const void* img, int w, int h, int pitch, const char* name) {
+    if (w < 1 || h < 1 || w > PD_MAX_DIM || h > PD_MAX_DIM)
+        return fail(PD_E_SIZE, "%s size %dx%d outside [1, %d]", name, w, h, PD_MAX_DIM);
+    if (!img) return fail(PD_E_ARG, "%s is NULL", name);
+    if (pitch < w) return fail(PD_E_ARG, "%s pitch %d < width %d", name, pitch, w);
+    return PD_OK;
+}
+
+// Pinned host staging for the per-call tables.  A ring of slots, each reused
+// only after the copy that last read it has finished.
+struct Staging {
+    struct Slot {
+        void* host = nullptr;
+        size_t size = 0;
+        hipEvent_t ev = nullptr;
+        bool pending = false;
+    };
+    Slot slot[4];
+    int next = 0;
+    ~Staging() {
+        for (auto& s : slot) {
+            if (s.ev) (void)hipEventDestroy(s.ev);
+            if (s.host) (void)hipHostFree(s.host);
+        }
+    }
+};
+thread_local Staging g_stage;
+
+// Unsigned big integer (32-bit limbs) for exact level sizes.
+struct Big {
+    std::vector<uint32_t> d{1};
+    void mul(uint32_t m) {
+        uint64_t carry = 0;
+        for (auto& x : d) {
+            const uint64_t v = (uint64_t)x * m + carry;
+            x = (uint32_t)v;
+            carry = v >> 32;
+        }
+        if (carry) d.push_back((uint32_t)carry);
+    }
+    // -1, 0, 1 for this <, ==, > o
+    int cmp(const Big& o) const {
+        size_t n = std::max(d.size(), o.d.size());
+        for (size_t i = n; i-- > 0;) {
+            const uint32_t a = i < d.size() ? d[i] : 0u, b = i < o.d.size() ? o.d[i] : 0u;
+            if (a != b) return a < b ? -1 : 1;
+        }
+        return 0;
+    }
+};
+
+// floor(a / b) for a result known to lie in [0, limit]: largest q with q*b <= a.
+int big_floor_div(const Big& a, const Big& b, int limit) {
+    int lo = 0, hi = limit;
+    while (lo < hi) {
+        const int mid = lo + (hi - lo + 1) / 2;
+        Big t = b;
+        t.mul((uint32_t)mid);
+        if (t.cmp(a) <= 0) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Exact level sizes floor(n * den^k / num^k), kept while the window fits.
+int plan_sizes(int w, int h, const pd_params* p, int (*wh)[2]) {
+    Big num_k, den_w, den_h;
+    den_w.mul((uint32_t)w);
+    den_h.mul((uint32_t)h);
+    int n = 0;
+    for (int k = 0; k < PD_MAX_LEVELS; ++k) {
+        const int wk = big_floor_div(den_w, num_k, w);
+        const int hk = big_floor_div(den_h, num_k, h);
+        if (wk < PD_WIN_W || hk < PD_WIN_H) break;
+        wh[n][0] = wk;
+        wh[n][1] = hk;
+        ++n;
+        if (p->max_levels && n >= p->max_levels) break;
+        num_k.mul((uint32_t)p->scale_num);
+        den_w.mul((uint32_t)p->scale_den);
+        den_h.mul((uint32_t)p->scale_den);
+    }
+    return n;
+}
+
+void fill_level(pd_level& L, int w, int h) {
+    std::memset(&L, 0, sizeof(L));
+    L.w = w;
+    L.h = h;
+    L.pitch = (int)align_up(w, 16);
+    L.cells_x = w / PD_CELL;
+    L.cells_y = h / PD_CELL;
+    L.blocks_x = L.cells_x - 1;
+    L.blocks_y = L.cells_y - 1;
+    L.win_x = L.cells_x - PD_WIN_CELLS_X + 1;
+    L.win_y = L.cells_y - PD_WIN_CELLS_Y + 1;
+}
+
+void item_geometry(LevelItem& it, int w, int h) {
+    it.w = w;
+    it.h = h;
+    it.wc = w / PD_CELL;
+    it.hc = h / PD_CELL;
+    it.wb = it.wc - 1;
+    it.hb = it.hc - 1;
+    it.nx = it.wc - PD_WIN_CELLS_X + 1;
+    it.ny = it.hc - PD_WIN_CELLS_Y + 1;
+}
+
+// Layout of the pd_detect workspace; computed identically by the size query
+// and by pd_detect.
+struct DetectLayout {
+    int n_items = 0;
+    int n_rs = 0, n_ft = 0, n_sc = 0, n_cp = 0;
+    int64_t off_items = 0, off_tiles = 0, off_geoms = 0, off_counters = 0, off_cscore = 0, off_ckey = 0;
+    int64_t off_data = 0, total = 0;
+    int64_t table_bytes = 0;  // bytes uploaded from the host (items .. geoms)
+    std::vector<int> level_count;         // per frame
+    std::vector<int> sizes;               // per item: w, h
+    std::vector<int64_t> pyr_off, hog_off, lbp_off, sc_off;  // per item, from off_data
+};
+
+bool plan_detect(const pd_frame* frames, int n_frames, const pd_params* p, int n_models, DetectLayout& L) {
+    L = DetectLayout();
+    L.level_count.resize(n_frames);
+    int wh[PD_MAX_LEVELS][2];
+    int64_t data = 0;
+    for (int f = 0; f < n_frames; ++f) {
+        const int w = frames[f].w, h = frames[f].h;
+        if (w < 1 || h < 1 || w > PD_MAX_DIM || h > PD_MAX_DIM)
+            return fail(PD_E_SIZE, "frame %d size %dx%d outside [1, %d]", f, w, h, PD_MAX_DIM), false;
+        const int n = plan_sizes(w, h, p, wh);
+        L.level_count[f] = n;
+        for (int k = 0; k < n; ++k) {
+            LevelItem it{};
+            item_geometry(it, wh[k][0], wh[k][1]);
+            L.sizes.push_back(wh[k][0]);
+            L.sizes.push_back(wh[k][1]);
+            // level 0 is the frame itself: no pyramid copy
+            L.pyr_off.push_back(data);
+            if (k > 0) data = align_up(data + (int64_t)align_up(it.w, 16) * it.h, kAlign);
+            L.hog_off.push_back(data);
+            data = align_up(data + (int64_t)PD_HOG_BLOCK * it.hb * it.wb * 4, kAlign);
+            L.lbp_off.push_back(data);
+            data = align_up(data + (int64_t)PD_LBP_BINS * it.hc * it.wc, kAlign);
+            L.sc_off.push_back(data);
+            data = align_up(data + (int64_t)n_models * it.ny * it.nx * 4, kAlign);
+            L.n_rs += k > 0 ? resize_tiles_x(it.w) * resize_tiles_y(it.h) : 0;
+            L.n_ft += feat_tiles_x(it.wc) * feat_tiles_y(it.hc);
+            L.n_sc += score_tiles_x(it.nx) * score_tiles_y(it.ny) * n_models;
+            L.n_cp += ceil_div(it.nx * it.ny, CP_N);
+            ++L.n_items;
+        }
+    }
+    int64_t o = 0;
+    L.off_items = o;
+    o = align_up(o + (int64_t)L.n_items * sizeof(LevelItem), kAlign);
+    L.off_tiles = o;
+    o = align_up(o + (int64_t)(L.n_rs + L.n_ft + L.n_sc + L.n_cp) * sizeof(Tile), kAlign);
+    L.off_geoms = o;
+    o = align_up(o + (int64_t)n_frames * sizeof(NmsGeom), kAlign);
+    L.table_bytes = o;
+    L.off_counters = o;
+    o = align_up(o + (int64_t)n_frames * 4, kAlign);
+    L.off_cscore = o;
+    o = align_up(o + (int64_t)n_frames * PD_MAX_CANDIDATES * 4, kAlign);
+    L.off_ckey = o;
+    o = align_up(o + (int64_t)n_frames * PD_MAX_CANDIDATES * 16, kAlign);
+    L.off_data = o;
+    L.total = o + data;
+    return true;
+}
+
+
+}  // namespace
+
+extern "C" {
+
+void pd_params_default(pd_params* p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->scale_num = 11;
+    p->scale_den = 10;
+    p->max_levels = 0;
+    p->clip = 0.2f;
+    p->eps = 1e-3f;
+    p->features = PD_FEAT_HOG | PD_FEAT_LBP;
+}
+
+const char* pd_strerror(int code) {
+    switch (code) {
+        case PD_OK: return "ok";
+        case PD_E_ARG: return "invalid argument";
+        case PD_E_SIZE: return "invalid size";
+        case PD_E_WORKSPACE: return "workspace missing or too small";
+        case PD_E_HIP: return "HIP error";
+        default: return "unknown error";
+    }
+}
+
+const char* pd_last_error(void) { return g_last_error.c_str(); }
+
+const char* pd_version(void) { return "pd 0.1 gfx950"; }
+
+int pd_plan_pyramid(int w, int h, const pd_params* params, pd_level* levels, int cap, int* n_levels,
+                    int64_t* bytes) {
+    if (!check_params(params)) return PD_E_ARG;
+    if (!n_levels || !bytes || (cap > 0 && !levels) || cap < 0) return fail(PD_E_ARG, "null output");
+    if (w < 1 || h < 1 || w > PD_MAX_DIM || h > PD_MAX_DIM)
+        return fail(PD_E_SIZE, "image size %dx%d outside [1, %d]", w, h, PD_MAX_DIM);
+    int wh[PD_MAX_LEVELS][2];
+    const int n = plan_sizes(w, h, params, wh);
+    int64_t off = 0;
+    for (int k = 0; k < n; ++k) {
+        pd_level L;
+        fill_level(L, wh[k][0], wh[k][1]);
+        L.offset = off;
+        off = align_up(off + (int64_t)L.pitch * L.h, kAlign);
+        if (k < cap) levels[k] = L;
+    }
+    *n_levels = n;
+    *bytes = off;
+    return PD_OK;
+}
+
+int pd_build_pyramid(const uint8_t* img, int w, int h, int pitch, const pd_level* levels, int n, uint8_t* pyr,
+                     void* stream) {
+    if (int rc = check_image(img, w, h, pitch, "img")) return rc;
+    if (n < 0 || n > PD_MAX_LEVELS) return fail(PD_E_SIZE, "level count %d outside [0, %d]", n, PD_MAX_LEVELS);
+    if (n == 0) return PD_OK;
+    if (!levels || !pyr) return fail(PD_E_ARG, "levels or pyr is NULL");
+    LevelItem items[PD_MAX_LEVELS];
+    for (int k = 0; k < n; ++k) {
+        const pd_level& L = levels[k];
+        if (L.w < 1 || L.h < 1 || L.w > w || L.h > h || L.pitch < L.w || (L.pitch & 15) || (L.offset & 255))
+            return fail(PD_E_ARG, "level %d is not a valid plan entry", k);
+        items[k] = LevelItem{};
+        items[k].src = img;
+        items[k].src_w = w;
+        items[k].src_h = h;
+        items[k].src_pitch = pitch;
+        items[k].pyr = pyr + L.offset;
+        items[k].w = L.w;
+        items[k].h = L.h;
+        items[k].pitch = L.pitch;
+    }
+    return hip_status(launch_resize_single(items, n, (hipStream_t)stream), "pyramid launch");
+}
+
+int pd_lbp_codes(const uint8_t* lvl, int w, int h, int pitch, uint8_t* codes, int codes_pitch, void* stream) {
+    if (int rc = check_image(lvl, w, h, pitch, "level")) return rc;
+    if (!codes || codes_pitch < w) return fail(PD_E_ARG, "codes is NULL or its pitch < width");
+    return hip_status(launch_lbp_codes(lvl, w, h, pitch, codes, codes_pitch, (hipStream_t)stream), "lbp codes");
+}
+
+int pd_features(const uint8_t* lvl, int w, int h, int pitch, const pd_params* params, float* blocks,
+                uint8_t* cell_hist, void* stream) {
+    if (int rc = check_image(lvl, w, h, pitch, "level")) return rc;
+    if (!check_params(params)) return PD_E_ARG;
+    int feat = 0;
+    if (blocks) feat |= PD_FEAT_HOG;
+    if (cell_hist) feat |= PD_FEAT_LBP;
+    if (!feat) return fail(PD_E_ARG, "both outputs are NULL");
+    LevelItem it{};
+    item_geometry(it, w, h);
+    it.pyr = const_cast<uint8_t*>(lvl);
+    it.pitch = pitch;
+    it.hog = blocks;
+    it.lbp = cell_hist;
+    if (it.hc < 1 || it.wc < 1) return PD_OK;  // no whole cell: nothing to write
+    if ((feat & PD_FEAT_HOG) && (it.hb < 1 || it.wb < 1)) feat &= ~PD_FEAT_HOG;
+    if (!feat) return PD_OK;
+    return hip_status(launch_features_single(it, feat, params->clip, params->eps, (hipStream_t)stream),
+                      "features launch");
+}
+
+int pd_lbp(const uint8_t* lvl, int w, int h, int pitch, uint8_t* cell_hist, void* stream) {
+    if (!cell_hist) return fail(PD_E_ARG, "cell_hist is NULL");
+    pd_params p;
+    pd_params_default(&p);
+    return pd_features(lvl, w, h, pitch, &p, nullptr, cell_hist, stream);
+}
+
+int pd_hog(const uint8_t* lvl, int w, int h, int pitch, const pd_params* params, float* blocks, void* stream) {
+    if (!blocks) return fail(PD_E_ARG, "blocks is NULL");
+    return pd_features(lvl, w, h, pitch, params, blocks, nullptr, stream);
+}
+
+int pd_score_windows(const float* blocks, const uint8_t* cells, int cells_x, int cells_y, const float* weights,
+                     const float* bias, int n_models, float* scores, void* stream) {
+    if (cells_x < PD_WIN_CELLS_X || cells_y < PD_WIN_CELLS_Y || cells_x > PD_MAX_DIM / PD_CELL ||
+        cells_y > PD_MAX_DIM / PD_CELL)
+        return fail(PD_E_SIZE, "cell grid %dx%d cannot hold a window", cells_x, cells_y);
+    if (n_models < 1 || n_models > PD_MAX_MODELS) return fail(PD_E_SIZE, "n_models %d outside [1, %d]", n_models, PD_MAX_MODELS);
+    if (!blocks || !cells || !weights || !bias || !scores) return fail(PD_E_ARG, "NULL pointer argument");
+    LevelItem it{};
+    item_geometry(it, cells_x * PD_CELL, cells_y * PD_CELL);
+    it.hog = const_cast<float*>(blocks);
+    it.lbp = const_cast<uint8_t*>(cells);
+    it.scores = scores;
+    return hip_status(launch_score_single(it, weights, bias, n_models, PD_FEAT_HOG | PD_FEAT_LBP,
+                                          (hipStream_t)stream),
+                      "score launch");
+}
+
+int64_t pd_detect_workspace_bytes(const pd_frame* frames, int n_frames, const pd_params* params, int n_models) {
+    if (!check_params(params)) return PD_E_ARG;
+    if (!frames || n_frames < 1) return fail(PD_E_ARG, "frames is NULL or n_frames < 1");
+    if (n_models < 1 || n_models > PD_MAX_MODELS) return fail(PD_E_SIZE, "n_models outside [1, %d]", PD_MAX_MODELS);
+    DetectLayout L;
+    if (!plan_detect(frames, n_frames, params, n_models, L)) return PD_E_SIZE;
+    return L.total;
+}
+
+int pd_detect(const pd_frame* frames, int n_frames, const float* weights, const float* bias, int n_models,
+              const pd_params* params, const double* thresholds, void* workspace, int64_t workspace_bytes,
+              pd_box* boxes, int cap, pd_counts* counts, void* stream) {
+    if (!check_params(params)) return PD_E_ARG;
+    if (!frames || n_frames < 1) return fail(PD_E_ARG, "frames is NULL or n_frames < 1");
+    if (n_models < 1 || n_models > PD_MAX_MODELS) return fail(PD_E_SIZE, "n_models outside [1, %d]", PD_MAX_MODELS);
+    if (!weights || !bias || !thresholds || !counts || (cap > 0 && !boxes) || cap < 0)
+        return fail(PD_E_ARG, "NULL pointer argument");
+    for (int f = 0; f < n_frames; ++f) {
+        if (int rc = check_image(frames[f].data, frames[f].w, frames[f].h, frames[f].pitch, "frame")) return rc;
+    }
+    DetectLayout L;
+    if (!plan_detect(frames, n_frames, params, n_models, L)) return PD_E_SIZE;
+    if (!workspace || workspace_bytes < L.total)
+        return fail(PD_E_WORKSPACE, "workspace of %lld bytes, need %lld", (long long)workspace_bytes,
+                    (long long)L.total);
+    if ((uintptr_t)workspace & (kAlign - 1)) return fail(PD_E_ARG, "workspace must be 256-byte aligned");
+    uint8_t* ws = static_cast<uint8_t*>(workspace);
+    uint8_t* data = ws + L.off_data;
+    hipStream_t s = (hipStream_t)stream;
+
+    // host tables, built in a pinned staging slot
+    Staging::Slot& slot = g_stage.slot[g_stage.next];
+    g_stage.next = (g_stage.next + 1) % 4;
+    if (slot.pending) {
+        if (int rc = hip_status(hipEventSynchronize(slot.ev), "staging wait")) return rc;
+        slot.pending = false;
+    }
+    if (!slot.ev) {
+        if (int rc = hip_status(hipEventCreateWithFlags(&slot.ev, hipEventDisableTiming), "staging event")) return rc;
+    }
+    if (slot.size < (size_t)L.table_bytes) {
+        if (slot.host) (void)hipHostFree(slot.host);
+        slot.host = nullptr;
+        slot.size = 0;
+        const size_t want = (size_t)align_up(L.table_bytes, 1 << 16);
+        if (int rc = hip_status(hipHostMalloc(&slot.host, want, hipHostMallocDefault), "staging alloc")) return rc;
+        slot.size = want;
+    }
+    uint8_t* stage = static_cast<uint8_t*>(slot.host);
+    std::memset(stage, 0, (size_t)L.table_bytes);
+    LevelItem* items = reinterpret_cast<LevelItem*>(stage + L.off_items);
+    Tile* tiles = reinterpret_cast<Tile*>(stage + L.off_tiles);
+    NmsGeom* geoms = reinterpret_cast<NmsGeom*>(stage + L.off_geoms);
+    Tile* t_rs = tiles;
+    Tile* t_ft = t_rs + L.n_rs;
+    Tile* t_sc = t_ft + L.n_ft;
+    Tile* t_cp = t_sc + L.n_sc;
+    int q = 0, nrs = 0, nft = 0, nsc = 0, ncp = 0;
+    for (int f = 0; f < n_frames; ++f) {
+        geoms[f].n_levels = L.level_count[f];
+        for (int k = 0; k < L.level_count[f]; ++k, ++q) {
+            LevelItem& it = items[q];
+            item_geometry(it, L.sizes[2 * q], L.sizes[2 * q + 1]);
+            it.src = frames[f].data;
+            it.src_w = frames[f].w;
+            it.src_h = frames[f].h;
+            it.src_pitch = frames[f].pitch;
+            if (k == 0) {
+                it.pyr = const_cast<uint8_t*>(frames[f].data);
+                it.pitch = frames[f].pitch;
+            } else {
+                it.pyr = data + L.pyr_off[q];
+                it.pitch = (int)align_up(it.w, 16);
+            }
+            it.hog = reinterpret_cast<float*>(data + L.hog_off[q]);
+            it.lbp = data + L.lbp_off[q];
+            it.scores = reinterpret_cast<float*>(data + L.sc_off[q]);
+            it.frame = f;
+            it.level = k;
+            geoms[f].wh[k][0] = it.w;
+            geoms[f].wh[k][1] = it.h;
+            if (k > 0)
+                for (int ty = 0; ty < resize_tiles_y(it.h); ++ty)
+                    for (int tx = 0; tx < resize_tiles_x(it.w); ++tx) t_rs[nrs++] = Tile{q, ty, tx, 0};
+            for (int ty = 0; ty < feat_tiles_y(it.hc); ++ty)
+                for (int tx = 0; tx < feat_tiles_x(it.wc); ++tx) t_ft[nft++] = Tile{q, ty, tx, 0};
+            for (int m = 0; m < n_models; ++m)
+                for (int ty = 0; ty < score_tiles_y(it.ny); ++ty)
+                    for (int tx = 0; tx < score_tiles_x(it.nx); ++tx) t_sc[nsc++] = Tile{q, ty, tx, m};
+            for (int c = 0; c < ceil_div(it.nx * it.ny, CP_N); ++c) t_cp[ncp++] = Tile{q, 0, c, 0};
+        }
+    }
+    const LevelItem* d_items = reinterpret_cast<const LevelItem*>(ws + L.off_items);
+    const Tile* d_tiles = reinterpret_cast<const Tile*>(ws + L.off_tiles);
+    const NmsGeom* d_geoms = reinterpret_cast<const NmsGeom*>(ws + L.off_geoms);
+    int32_t* d_counters = reinterpret_cast<int32_t*>(ws + L.off_counters);
+    float* d_cscore = reinterpret_cast<float*>(ws + L.off_cscore);
+    int4* d_ckey = reinterpret_cast<int4*>(ws + L.off_ckey);
+
+    int rc;
+    if ((rc = hip_status(hipMemcpyAsync(ws, stage, (size_t)L.table_bytes, hipMemcpyHostToDevice, s),
+                         "table upload")))
+        return rc;
+    if ((rc = hip_status(hipEventRecord(slot.ev, s), "staging record"))) return rc;
+    slot.pending = true;
+    if ((rc = hip_status(launch_zero_i32(d_counters, n_frames, s), "zero"))) return rc;
+    if ((rc = hip_status(launch_resize_table(d_items, d_tiles, L.n_rs, s), "resize"))) return rc;
+    if ((rc = hip_status(launch_features_table(d_items, d_tiles + L.n_rs, L.n_ft, params->features,
+                                               params->clip, params->eps, s),
+                         "features")))
+        return rc;
+    if ((rc = hip_status(launch_score_table(d_items, d_tiles + L.n_rs + L.n_ft, L.n_sc, weights, bias, n_models,
+                                            params->features, s),
+                         "score")))
+        return rc;
+    if ((rc = hip_status(launch_compact_table(d_items, d_tiles + L.n_rs + L.n_ft + L.n_sc, L.n_cp, n_models,
+                                              thresholds, d_counters, d_cscore, d_ckey, s),
+                         "compact")))
+        return rc;
+    return hip_status(launch_nms_table(d_geoms, n_frames, d_counters, d_cscore, d_ckey, boxes, cap, counts, s),
+                      "nms");
+}
+
+int pd_nms(const float* cand_score, const int32_t* cand_key, int n, const int32_t* level_wh, int n_levels,
+           pd_box* boxes, int cap, pd_counts* counts, void* stream) {
+    if (n < 0 || n > PD_MAX_CANDIDATES) return fail(PD_E_SIZE, "n = %d outside [0, %d]", n, PD_MAX_CANDIDATES);
+    if (n_levels < 1 || n_levels > PD_MAX_LEVELS) return fail(PD_E_SIZE, "n_levels outside [1, %d]", PD_MAX_LEVELS);
+    if (!level_wh || !counts || (n > 0 && (!cand_score || !cand_key)) || (cap > 0 && !boxes) || cap < 0)
+        return fail(PD_E_ARG, "NULL pointer argument");
+    NmsGeom g{};
+    g.n_levels = n_levels;
+    for (int k = 0; k < n_levels; ++k) {
+        g.wh[k][0] = level_wh[2 * k];
+        g.wh[k][1] = level_wh[2 * k + 1];
+        if (g.wh[k][0] < 1 || g.wh[k][1] < 1) return fail(PD_E_SIZE, "level %d has an empty size", k);
+    }
+    return hip_status(launch_nms_single(g, n, cand_score, reinterpret_cast<const int4*>(cand_key), boxes, cap,
+                                        counts, (hipStream_t)stream),
+                      "nms launch");
+}
+
+}  // extern "C"

@@ -1,0 +1,90 @@
+// Internal declarations shared by the libpd HIP sources (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/pd.h"
+
+namespace pd {
+
+// Everything one kernel needs to know about one (frame, level) pair.  In a
+// batched launch these live in a device table; single-level entry points
+// pass one by value.
+struct LevelItem {
+    const uint8_t* src;   // level-0 image of the frame
+    uint8_t* pyr;         // this level inside the pyramid buffer
+    float* hog;           // [36][hb][wb]
+    uint8_t* lbp;         // [59][hc][wc]
+    float* scores;        // [n_models][ny][nx]
+    int32_t src_w, src_h, src_pitch;
+    int32_t w, h, pitch;
+    int32_t wc, hc, wb, hb, nx, ny;
+    int32_t frame, level;
+};
+
+// One workgroup's share of a batched launch: which item and which tile.
+struct Tile {
+    int32_t item;
+    int32_t ty, tx;
+    int32_t pad;
+};
+
+// Greedy-NMS geometry of one frame: sizes of its levels, level 0 first.
+struct NmsGeom {
+    int32_t n_levels;
+    int32_t pad;
+    int32_t wh[PD_MAX_LEVELS][2];
+};
+
+// ---- tile shapes ---------------------------------------------------------
+// resize: 64 lanes x 4 pixels wide, 16 rows
+constexpr int RS_TX = 256;   // pixels per tile row
+constexpr int RS_TY = 16;    // rows per tile
+// features: 16x16 cells per workgroup (one cell per lane), blocks 15x15
+constexpr int FT_C = 16;
+constexpr int FT_B = 15;
+// scoring: one wave = 64 window columns x SC_R window rows
+constexpr int SC_R = 16;
+constexpr int SC_W = 64;
+constexpr int SC_WAVES = 4;  // waves (independent tiles) per workgroup
+// compaction: windows per workgroup
+constexpr int CP_N = 256;
+
+__host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+__host__ __device__ inline int resize_tiles_x(int w) { return ceil_div(w, RS_TX); }
+__host__ __device__ inline int resize_tiles_y(int h) { return ceil_div(h, RS_TY); }
+__host__ __device__ inline int feat_tiles_x(int wc) { return wc <= 1 ? 1 : ceil_div(wc - 1, FT_B); }
+__host__ __device__ inline int feat_tiles_y(int hc) { return hc <= 1 ? 1 : ceil_div(hc - 1, FT_B); }
+__host__ __device__ inline int score_tiles_x(int nx) { return ceil_div(nx, SC_W); }
+__host__ __device__ inline int score_tiles_y(int ny) { return ceil_div(ny, SC_R); }
+
+// ---- launchers (each defined next to its kernel) ---------------------------
+hipError_t launch_resize_single(const LevelItem* items, int n_items, hipStream_t s);
+hipError_t launch_resize_table(const LevelItem* items, const Tile* tiles, int n_tiles, hipStream_t s);
+
+hipError_t launch_lbp_codes(const uint8_t* img, int w, int h, int pitch, uint8_t* codes,
+                            int codes_pitch, hipStream_t s);
+hipError_t launch_features_single(const LevelItem& it, int features, float clip, float eps,
+                                  hipStream_t s);
+hipError_t launch_features_table(const LevelItem* items, const Tile* tiles, int n_tiles,
+                                 int features, float clip, float eps, hipStream_t s);
+
+hipError_t launch_score_single(const LevelItem& it, const float* w, const float* bias, int n_models,
+                               int features, hipStream_t s);
+hipError_t launch_score_table(const LevelItem* items, const Tile* tiles, int n_tiles,
+                              const float* w, const float* bias, int n_models, int features,
+                              hipStream_t s);
+
+hipError_t launch_compact_table(const LevelItem* items, const Tile* tiles, int n_tiles, int n_models,
+                                const double* thresholds, int32_t* counters, float* cand_score,
+                                int4* cand_key, hipStream_t s);
+hipError_t launch_nms_table(const NmsGeom* geoms, int n_frames, const int32_t* counters,
+                            const float* cand_score, const int4* cand_key, pd_box* boxes, int cap,
+                            pd_counts* counts, hipStream_t s);
+hipError_t launch_nms_single(const NmsGeom& g, int n, const float* cand_score, const int4* cand_key,
+                             pd_box* boxes, int cap, pd_counts* counts, hipStream_t s);
+hipError_t launch_zero_i32(int32_t* p, int n, hipStream_t s);
+
+}  // namespace pd
