@@ -251,6 +251,31 @@ int pd_nms(const float* cand_score, const int32_t* cand_key, int n,
            const int32_t* level_wh, int n_levels, pd_box* boxes, int cap,
            pd_counts* counts, void* stream);
 
+/* ---- stage timing ---------------------------------------------------------- */
+/* Stages of pd_detect, in launch order. */
+#define PD_STAGE_UPLOAD   0   /* host tables -> workspace copy              */
+#define PD_STAGE_ZERO     1   /* candidate counters cleared                 */
+#define PD_STAGE_RESIZE   2   /* pyramid levels 1..n of every frame         */
+#define PD_STAGE_FEATURES 3   /* HOG + LBP of every level                   */
+#define PD_STAGE_SCORE    4   /* window scores of every level and model     */
+#define PD_STAGE_COMPACT  5   /* threshold + candidate lists                */
+#define PD_STAGE_NMS      6   /* greedy NMS per frame                       */
+#define PD_N_STAGES       7
+
+/*
+ * pd_profile_enable -- when on != 0, every later pd_detect call on this host
+ * thread records a HIP event on its stream before each stage and after the
+ * last one (the only cost is the event records).  on == 0 stops recording.
+ */
+int pd_profile_enable(int on);
+
+/*
+ * pd_profile_read -- waits for the recorded events, then writes to host
+ * ms[PD_N_STAGES] the summed GPU time of each stage over the recorded calls
+ * and to *calls their number; reset != 0 clears the record afterwards.
+ */
+int pd_profile_read(double* ms, int64_t* calls, int reset);
+
 /* ---- diagnostics ----------------------------------------------------------- */
 const char* pd_strerror(int code);
 const char* pd_last_error(void);   /* calling thread's last failure message */

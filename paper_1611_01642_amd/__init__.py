@@ -85,6 +85,8 @@ _SIGS = {
                                  ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
     "pd_nms": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
                               ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
+    "pd_profile_enable": (ctypes.c_int, [ctypes.c_int]),
+    "pd_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]),
     "pd_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "pd_last_error": (ctypes.c_char_p, []),
     "pd_version": (ctypes.c_char_p, []),
@@ -286,6 +288,22 @@ class Detector:
         counts = self.counts.cpu().numpy().view(COUNTS_DTYPE)
         allb = self.boxes.cpu().numpy().view(BOX_DTYPE).reshape(len(self.frames), max(self.cap, 1))
         return [allb[f, :counts[f]["kept"]].copy() for f in range(len(self.frames))], counts
+
+
+STAGES = ("upload", "zero", "resize", "features", "score", "compact", "nms")
+
+
+def profile_enable(on: bool = True) -> None:
+    """Record per-stage HIP events in later pd_detect calls of this thread."""
+    _check(lib().pd_profile_enable(1 if on else 0))
+
+
+def profile_read(reset: bool = True):
+    """({stage: summed ms}, calls) over the recorded pd_detect calls."""
+    ms = (ctypes.c_double * len(STAGES))()
+    calls = ctypes.c_int64(0)
+    _check(lib().pd_profile_read(ms, ctypes.byref(calls), 1 if reset else 0))
+    return dict(zip(STAGES, list(ms))), calls.value
 
 
 def decode_boxes(boxes_u8, counts_u8):

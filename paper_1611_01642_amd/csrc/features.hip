@@ -2,27 +2,32 @@
 // (Section 4.2, Algorithms 1-2) and L2-Hys-normalised HOG block histograms
 // (Section 4.3, Algorithms 4-5) from a single pass over the pixels.
 //
-// Mapping (one workgroup = 256 lanes = a tile of 16 x 16 cells; one lane per
-// 8x8 cell):
-//   1. the tile's pixels plus a one-pixel halo (130 x 130 bytes, clamped at
-//      the image edge) are staged in LDS with coalesced 4-byte loads;
-//   2. each lane walks the 64 pixels of its cell: LBP code -> uniform bin ->
-//      one packed-byte LDS count; gradient -> magnitude and orientation ->
-//      votes into its cell's 3x3 "direction partials" A[dir][bin], where dir
-//      is the neighbouring cell whose centre the vote is weighted towards.
-//      Each pixel votes into 2 cells x 2 cells x 2 bins;
-//   3. a 16x16-pixel block's trilinear histogram (Algorithm 5: every pixel of
-//      the block votes, bilinear in space towards the four cell centres of the
-//      block, linear in orientation) equals, for each of its four cell slots
-//      t, the sum over its four cells s of A[s][t - s].  Votes towards cells
-//      outside the block are exactly the ones this sum leaves out.  So every
-//      pixel is processed once instead of four times (blocks overlap 50 %);
-//   4. L2-Hys per block and planar stores.
-// The 16x16-cell tiles overlap by one cell so that all four cells of every
-// block are inside one tile; a tile owns 15x15 blocks.
+// Mapping: one wave64 owns a strip of 64 cell columns (one lane per 8x8 cell)
+// and walks down FT_CH block rows.  For each cell row, a lane reads its cell's
+// 10x10 pixel neighbourhood straight from global memory (one 8-byte load per
+// pixel row, plus the two halo bytes; neighbouring lanes read neighbouring
+// bytes, so the loads are coalesced) and processes its 64 pixels:
+//   * LBP: 3x3 code -> uniform bin -> +1 on a byte counter in a lane-private
+//     LDS word (plain read-modify-write: no atomics are needed because no other
+//     lane touches these words);
+//   * HOG: gradient -> magnitude and orientation -> votes into the cell's
+//     "direction partials" A[dir][bin] held in registers, where dir is the
+//     neighbouring cell (3x3) whose centre the bilinear spatial weight points
+//     at.  The linear orientation interpolation is evaluated for all nine bins
+//     as a hat function (at most two are non-zero), so every accumulator index
+//     is a compile-time constant.  Spatial weights are separable: a pixel row
+//     first accumulates per target column, then the row is folded into A with
+//     the row's two target weights.
+// A 16x16-pixel block's trilinear histogram (Algorithm 5) equals, for each of
+// its four cell slots t, the sum over its four cells s of A[s][t - s]: votes
+// towards cells outside the block are exactly the terms this sum leaves out,
+// so every pixel is processed once although blocks overlap by 50 %.  The block
+// of row by = cy - 1 is assembled when cell row cy is done, from the previous
+// row's partials (kept in LDS) and the current ones, with one-lane shuffles
+// for the right-hand neighbour; then L2-Hys and planar stores (coalesced).
+// Strips overlap by one cell column, chunks by one cell row.
 //
-// Every LDS accumulator is owned by one lane, so sums run in a fixed order and
-// results are bitwise reproducible.
+// Sums run in a fixed order, so results are bitwise reproducible.
 #include "pd_internal.h"
 
 namespace pd {
@@ -56,7 +61,7 @@ __constant__ LbpTable kLbp = make_lbp_table();
 // ---- atan in units of orientation bins ---------------------------------------
 // atan(r) * 9 / pi for r in [0, 1] as r * P(r^2); coefficients fitted for this
 // library (weighted least squares, see fit_atan.py); max error 4e-7 bins.
-__device__ inline float atan_bins(float r) {
+__device__ __forceinline__ float atan_bins(float r) {
     const float s = r * r;
     float p = -0.011615472845733166f;
     p = fmaf(p, s, 0.0626327395439148f);
@@ -69,21 +74,6 @@ __device__ inline float atan_bins(float r) {
     return p * r;
 }
 
-// ---- tile geometry -----------------------------------------------------------
-constexpr int PX_SIDE = FT_C * PD_CELL;   // 128 pixels of whole cells
-constexpr int PX_ROWS = PX_SIDE + 2;      // + halo row above and below
-constexpr int PX_PITCH = 144;             // LDS column c <-> x = 8*cx0 - 8 + c
-constexpr int PX_WORDS = PX_PITCH / 4;
-constexpr int A_STRIDE = 81;              // 9 directions x 9 bins per cell
-constexpr int L_STRIDE = 15;              // 59 byte counters packed in words
-
-struct FeatSmem {
-    uint8_t px[PX_ROWS * PX_PITCH];
-    uint32_t lut[256];                    // (increment << 7) | word
-    float A[FT_C * FT_C * A_STRIDE];
-    uint32_t cnt[FT_C * FT_C * L_STRIDE];
-};
-
 // Bilinear weight of pixel offset p in [0, 8) of a cell towards the centre of
 // the neighbouring cell d in {-1, 0, 1}: 1 - |p + 0.5 - (8d + 4)| / 8, >= 0.
 __host__ __device__ constexpr float sw(int p, int d) {
@@ -92,211 +82,281 @@ __host__ __device__ constexpr float sw(int p, int d) {
     return w > 0.0f ? w : 0.0f;
 }
 
-template <int FEAT>
-__device__ void features_tile(const uint8_t* __restrict__ img, int w, int h, int pitch,
-                              float* __restrict__ hog, uint8_t* __restrict__ lbp, int ty, int tx,
-                              float clip, float eps) {
-    extern __shared__ __align__(16) uint8_t smem_raw[];
-    FeatSmem& sm = *reinterpret_cast<FeatSmem*>(smem_raw);
-    const int t = threadIdx.x;
+constexpr int LBP_WORDS = 15;  // 59 byte counters packed in words
+constexpr int PREV_VALS = 54;  // partials of dirs dy in {0, 1} of the previous row
+
+struct FeatShared {
+    uint32_t lut[256];                               // (increment << 7) | word
+    uint32_t cnt[FT_WAVES][FT_W * LBP_WORDS];        // lane-private byte counters
+    float prev[FT_WAVES][PREV_VALS][FT_W];           // previous cell row's partials
+};
+
+// One pixel row of a cell's neighbourhood: byte i (0..9) is pixel x0 - 1 + i.
+struct PixRow {
+    uint32_t lo, hi;   // own pixels x0..x0+7
+    uint32_t halo;     // byte 0: pixel x0 - 1, byte 1: pixel x0 + 8 (clamped)
+};
+
+template <bool ALIGNED>
+__device__ __forceinline__ PixRow load_row(const uint8_t* __restrict__ img, int pitch, int w, int y, int x0) {
+    const uint8_t* p = img + (size_t)y * pitch + x0;
+    PixRow r;
+    if (ALIGNED) {
+        const uint2 m = *reinterpret_cast<const uint2*>(p);
+        r.lo = m.x;
+        r.hi = m.y;
+    } else {
+        r.lo = (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16) | ((uint32_t)p[3] << 24);
+        r.hi = (uint32_t)p[4] | ((uint32_t)p[5] << 8) | ((uint32_t)p[6] << 16) | ((uint32_t)p[7] << 24);
+    }
+    const uint32_t left = x0 > 0 ? (uint32_t)p[-1] : (r.lo & 255u);
+    const uint32_t right = x0 + 8 < w ? (uint32_t)p[8] : (r.hi >> 24);
+    r.halo = left | (right << 8);
+    return r;
+}
+
+__device__ __forceinline__ int px_at(const PixRow& r, int i) {  // i in 0..9, compile-time after unrolling
+    if (i == 0) return (int)(r.halo & 255u);
+    if (i == 9) return (int)((r.halo >> 8) & 255u);
+    const int b = i - 1;
+    return (int)(((b < 4 ? r.lo : r.hi) >> (8 * (b & 3))) & 255u);
+}
+
+template <int FEAT, bool ALIGNED>
+__device__ __forceinline__ void features_strip(const uint8_t* __restrict__ img, int w, int h, int pitch, float* __restrict__ hog,
+                               uint8_t* __restrict__ lbp, int ty, int tx, float clip, float eps,
+                               FeatShared& sm, int wave) {
+    constexpr bool DO_HOG = (FEAT & PD_FEAT_HOG) != 0;
+    constexpr bool DO_LBP = (FEAT & PD_FEAT_LBP) != 0;
+    const int lane = threadIdx.x & 63;
     const int hc = h / PD_CELL, wc = w / PD_CELL;
     const int hb = hc - 1, wb = wc - 1;
-    const int cy0 = ty * FT_B, cx0 = tx * FT_B;
-
-    // 1. stage pixels (+ halo, clamped) and the LBP table
-    const int y_org = cy0 * PD_CELL - 1;
-    const int x_org = cx0 * PD_CELL - 8;
-    const bool aligned = (((uintptr_t)img | (uintptr_t)pitch) & 3) == 0;
-    for (int e = t; e < PX_ROWS * PX_WORDS; e += 256) {
-        const int lr = e / PX_WORDS;
-        const int q = e - lr * PX_WORDS;
-        const int y = min(max(y_org + lr, 0), h - 1);
-        const int x = x_org + 4 * q;
-        const uint8_t* row = img + (size_t)y * pitch;
-        uint32_t v;
-        if (aligned && x >= 0 && x + 3 < w) {
-            v = *reinterpret_cast<const uint32_t*>(row + x);
-        } else {
-            v = 0;
+    const int cx0 = tx * FT_BX, cy0 = ty * FT_CH;
+    const int cx = cx0 + lane;
+    const int x0 = PD_CELL * min(cx, wc - 1);  // lanes past the edge read valid pixels
+    const int cy_last = min(cy0 + FT_CH, hc - 1);
+    const bool lbp_col = cx < wc && (lane < FT_BX || cx == wc - 1);
+    const bool blk_col = lane < FT_BX && cx < wb;
+    uint32_t* cnt = &sm.cnt[wave][lane * LBP_WORDS];
+    if (DO_LBP) {
 #pragma unroll
-            for (int b = 0; b < 4; ++b) v |= (uint32_t)row[min(max(x + b, 0), w - 1)] << (8 * b);
+        for (int k = 0; k < LBP_WORDS; ++k) cnt[k] = 0u;
+    }
+
+    // partials of the previous cell row, [value][lane]: value (r*3 + c+1)*9 + k
+    // holds dir (dy = r, dx = c); after the top half of the next row, r = 0
+    // also holds that row's dy = -1 votes (the other term of the same slots)
+    float (*P)[FT_W] = sm.prev[wave];
+    float Aa[3][PD_HOG_BINS], Ab[3][PD_HOG_BINS];  // [dx+1][bin] for two target rows
+
+    // one pixel row: votes into Aa (upper target row) and Ab (lower target row)
+    auto pixel_row = [&](int py, const PixRow& U, const PixRow& C, const PixRow& D, float s0, float s1) {
+        float R[3][PD_HOG_BINS];
+        if (DO_HOG) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int k = 0; k < PD_HOG_BINS; ++k) R[a][k] = 0.0f;
         }
-        *reinterpret_cast<uint32_t*>(&sm.px[lr * PX_PITCH + 4 * q]) = v;
-    }
-    if (FEAT & PD_FEAT_LBP) {
-        const int b = kLbp.bin[t];
-        sm.lut[t] = ((1u << (8 * (b & 3))) << 7) | (uint32_t)(b >> 2);
-    }
-    const int cyl = t >> 4, cxl = t & 15;
-    const int cy = cy0 + cyl, cx = cx0 + cxl;
-    const bool cell_ok = cy < hc && cx < wc;
-    float* Ac = &sm.A[t * A_STRIDE];
-    uint32_t* Lc = &sm.cnt[t * L_STRIDE];
-    if (FEAT & PD_FEAT_HOG) {
-        for (int k = 0; k < A_STRIDE; ++k) Ac[k] = 0.0f;
-    }
-    if (FEAT & PD_FEAT_LBP) {
-        for (int k = 0; k < L_STRIDE; ++k) Lc[k] = 0u;
-    }
-    __syncthreads();
-
-    // 2. per-pixel work of this lane's cell
-    if (cell_ok) {
-        // row r (0..9) of the cell's 10x10 neighbourhood: bytes at LDS columns
-        // 8*cxl + 7 .. 8*cxl + 16
-        auto load_row = [&](int r, int (&v)[10]) {
-            const uint8_t* p = &sm.px[(cyl * PD_CELL + r) * PX_PITCH + cxl * PD_CELL];
-            const uint32_t a = *reinterpret_cast<const uint32_t*>(p + 4);
-            const uint2 m = *reinterpret_cast<const uint2*>(p + 8);
-            const uint32_t c = *reinterpret_cast<const uint32_t*>(p + 16);
-            v[0] = (int)(a >> 24);
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                v[1 + k] = (int)((m.x >> (8 * k)) & 255u);
-                v[5 + k] = (int)((m.y >> (8 * k)) & 255u);
+        for (int px = 0; px < PD_CELL; ++px) {
+            const int c = px_at(C, px + 1);
+            const int L = px_at(C, px), Rt = px_at(C, px + 2);
+            const int T = px_at(U, px + 1), B = px_at(D, px + 1);
+            if (DO_LBP) {
+                const int code = (int)(px_at(U, px) >= c) | ((int)(T >= c) << 1) |
+                                 ((int)(px_at(U, px + 2) >= c) << 2) | ((int)(Rt >= c) << 3) |
+                                 ((int)(px_at(D, px + 2) >= c) << 4) | ((int)(B >= c) << 5) |
+                                 ((int)(px_at(D, px) >= c) << 6) | ((int)(L >= c) << 7);
+                const uint32_t e = sm.lut[code];
+                uint32_t* q = cnt + (e & 127u);
+                *q = *q + (e >> 7);
             }
-            v[9] = (int)(c & 255u);
-        };
-        int ru[10], rm[10], rd[10];
-        load_row(0, ru);
-        load_row(1, rm);
+            if (DO_HOG) {
+                const int dx = L - Rt;  // Algorithm 4
+                const int dy = T - B;
+                const int ax = abs(dx), ay = abs(dy);
+                const int mn = min(ax, ay), mx = max(ax, ay);
+                const float mag = __builtin_amdgcn_sqrtf((float)(dx * dx + dy * dy));
+                const float r = (float)mn * __builtin_amdgcn_rcpf((float)max(mx, 1));
+                float u = atan_bins(r);                           // [0, 2.25] bins
+                u = (ay > ax) ? 4.5f - u : u;                     // first quadrant
+                float t = ((dx * dy < 0) ? 9.0f - u : u) - 0.5f;  // fold, centres 10+20k
+                t = t < 0.0f ? t + 9.0f : t;                      // [0, 9)
+                const float mt = mag * t;
+                float wv[PD_HOG_BINS];                            // magnitude x hat(t - k)
+                wv[0] = fmaxf(0.0f, fmaf(-mag, fminf(t, 9.0f - t), mag));
 #pragma unroll
-        for (int py = 0; py < PD_CELL; ++py) {
-            load_row(py + 2, rd);
+                for (int k = 1; k < PD_HOG_BINS; ++k) wv[k] = fmaxf(0.0f, mag - fabsf(fmaf(-(float)k, mag, mt)));
+                const int dxa = px < 4 ? -1 : 0;
 #pragma unroll
-            for (int px = 0; px < PD_CELL; ++px) {
-                const int c = rm[px + 1];
-                const int L = rm[px], R = rm[px + 2];
-                const int T = ru[px + 1], B = rd[px + 1];
-                if (FEAT & PD_FEAT_LBP) {
-                    const int code = (int)(ru[px] >= c) | ((int)(T >= c) << 1) |
-                                     ((int)(ru[px + 2] >= c) << 2) | ((int)(R >= c) << 3) |
-                                     ((int)(rd[px + 2] >= c) << 4) | ((int)(B >= c) << 5) |
-                                     ((int)(rd[px] >= c) << 6) | ((int)(L >= c) << 7);
-                    const uint32_t e = sm.lut[code];
-                    atomicAdd(&Lc[e & 127u], e >> 7);
-                }
-                if (FEAT & PD_FEAT_HOG) {
-                    const int dx = L - R;       // Algorithm 4
-                    const int dy = T - B;
-                    const int ax = abs(dx), ay = abs(dy);
-                    const int mn = min(ax, ay), mx = max(ax, ay);
-                    const float mag = __builtin_amdgcn_sqrtf((float)(dx * dx + dy * dy));
-                    const float r = (float)mn * __builtin_amdgcn_rcpf((float)max(mx, 1));
-                    float u = atan_bins(r);                 // [0, 2.25] bins
-                    u = (ay > ax) ? 4.5f - u : u;           // first quadrant
-                    const float th = (dx * dy < 0) ? 9.0f - u : u;  // fold to [0, 180)
-                    const float tb = th - 0.5f;             // bin centres at 10 + 20 k
-                    const float fl = floorf(tb);
-                    const float w1 = tb - fl;
-                    int b0 = (int)fl;
-                    b0 = b0 < 0 ? PD_HOG_BINS - 1 : min(b0, PD_HOG_BINS - 1);
-                    const int b1 = b0 == PD_HOG_BINS - 1 ? 0 : b0 + 1;
-                    const float v1 = mag * w1;
-                    const float v0 = mag - v1;
-                    const int dya = py < 4 ? -1 : 0;   // the two cell rows voted to
-                    const int dxa = px < 4 ? -1 : 0;   // the two cell columns
+                for (int q = 0; q < 2; ++q) {
+                    const float sx = sw(px, dxa + q);
 #pragma unroll
-                    for (int qy = 0; qy < 2; ++qy) {
-#pragma unroll
-                        for (int qx = 0; qx < 2; ++qx) {
-                            const int ddy = dya + qy, ddx = dxa + qx;
-                            const float s = sw(py, ddy) * sw(px, ddx);
-                            const int dir = (ddy + 1) * 3 + (ddx + 1);
-                            atomicAdd(&Ac[dir * PD_HOG_BINS + b0], v0 * s);
-                            atomicAdd(&Ac[dir * PD_HOG_BINS + b1], v1 * s);
-                        }
-                    }
+                    for (int k = 0; k < PD_HOG_BINS; ++k) R[dxa + q + 1][k] = fmaf(sx, wv[k], R[dxa + q + 1][k]);
                 }
             }
+        }
+        if (DO_HOG) {
 #pragma unroll
-            for (int k = 0; k < 10; ++k) {
-                ru[k] = rm[k];
-                rm[k] = rd[k];
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int k = 0; k < PD_HOG_BINS; ++k) {
+                    Aa[a][k] = fmaf(s0, R[a][k], Aa[a][k]);
+                    Ab[a][k] = fmaf(s1, R[a][k], Ab[a][k]);
+                }
+        }
+    };
+
+    for (int cy = cy0; cy <= cy_last; ++cy) {
+        const int yb = PD_CELL * cy - 1;  // pixel row of neighbourhood row 0
+        PixRow U = load_row<ALIGNED>(img, pitch, w, max(yb, 0), x0);
+        PixRow C = load_row<ALIGNED>(img, pitch, w, min(yb + 1, h - 1), x0);
+        PixRow D = load_row<ALIGNED>(img, pitch, w, min(yb + 2, h - 1), x0);
+        if (DO_HOG) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int k = 0; k < PD_HOG_BINS; ++k) Aa[a][k] = Ab[a][k] = 0.0f;
+        }
+        // top half: pixel rows 0..3 vote towards cell rows -1 (Aa) and 0 (Ab)
+#pragma unroll 1
+        for (int py = 0; py < 4; ++py) {
+            const PixRow N = load_row<ALIGNED>(img, pitch, w, min(yb + py + 3, h - 1), x0);
+            const float fpy = (float)py;
+            pixel_row(py, U, C, D, (3.5f - fpy) * 0.125f, (4.5f + fpy) * 0.125f);
+            U = C;
+            C = D;
+            D = N;
+        }
+        if (DO_HOG) {
+            if (cy > cy0) {  // fold the dy = -1 votes into the previous row's r = 0 terms
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int k = 0; k < PD_HOG_BINS; ++k) P[a * 9 + k][lane] += Aa[a][k];
             }
-        }
-    }
-    __syncthreads();
-
-    // 3a. LBP histograms of the cells this tile owns
-    if (FEAT & PD_FEAT_LBP) {
-        const int cy_end = (cy0 + FT_C >= hc) ? hc : cy0 + FT_B;
-        const int cx_end = (cx0 + FT_C >= wc) ? wc : cx0 + FT_B;
-        if (cell_ok && cy < cy_end && cx < cx_end) {
-            const size_t plane = (size_t)hc * wc;
-            uint8_t* o = lbp + (size_t)cy * wc + cx;
 #pragma unroll
-            for (int k = 0; k < PD_LBP_BINS; ++k)
-                o[k * plane] = (uint8_t)((Lc[k >> 2] >> (8 * (k & 3))) & 255u);
+            for (int a = 0; a < 3; ++a)
+#pragma unroll
+                for (int k = 0; k < PD_HOG_BINS; ++k) Aa[a][k] = 0.0f;
         }
-    }
+        // bottom half: pixel rows 4..7 vote towards cell rows +1 (Aa) and 0 (Ab)
+#pragma unroll 1
+        for (int py = 4; py < 8; ++py) {
+            const PixRow N = load_row<ALIGNED>(img, pitch, w, min(yb + py + 3, h - 1), x0);
+            const float fpy = (float)py;
+            pixel_row(py, U, C, D, (fpy - 3.5f) * 0.125f, (11.5f - fpy) * 0.125f);
+            U = C;
+            C = D;
+            D = N;
+        }
 
-    // 3b. HOG blocks: slot t of block (by, bx) sums A[s][t - s] over its cells s
-    if (FEAT & PD_FEAT_HOG) {
-        if (t < FT_B * FT_B) {
-            const int byl = t / FT_B, bxl = t - (t / FT_B) * FT_B;
-            const int by = cy0 + byl, bx = cx0 + bxl;
-            if (by < hb && bx < wb) {
+        // LBP histogram of this cell row
+        if (DO_LBP) {
+            const bool own_row = cy < cy0 + FT_CH || cy == hc - 1;
+            if (own_row && lbp_col) {
+                const size_t plane = (size_t)hc * wc;
+                uint8_t* o = lbp + (size_t)cy * wc + cx;
+#pragma unroll 1
+                for (int k = 0; k < PD_LBP_BINS; ++k, o += plane) *o = (uint8_t)((cnt[k >> 2] >> (8 * (k & 3))) & 255u);
+            }
+#pragma unroll
+            for (int k = 0; k < LBP_WORDS; ++k) cnt[k] = 0u;
+        }
+
+        if (DO_HOG) {
+            // blocks of row cy - 1, slots (r, c): (r, 0) = O_r0 + X_r(right lane),
+            // (r, 1) = O_r1 + O_r0(right lane), with O_rc = P(r, c) + cur(r - 1, c)
+            // and X_r = P(r, -1) + cur(r - 1, -1); the r = 0 sums are already in P
+            if (cy > cy0) {
                 float v[PD_HOG_BLOCK];
 #pragma unroll
                 for (int r = 0; r < 2; ++r) {
 #pragma unroll
-                    for (int c = 0; c < 2; ++c) {
-#pragma unroll
-                        for (int k = 0; k < PD_HOG_BINS; ++k) {
-                            float acc = 0.0f;
-#pragma unroll
-                            for (int sy = 0; sy < 2; ++sy) {
-#pragma unroll
-                                for (int sx = 0; sx < 2; ++sx) {
-                                    const int src = (byl + sy) * FT_C + (bxl + sx);
-                                    const int dir = (r - sy + 1) * 3 + (c - sx + 1);
-                                    acc += sm.A[src * A_STRIDE + dir * PD_HOG_BINS + k];
-                                }
-                            }
-                            v[(r * 2 + c) * PD_HOG_BINS + k] = acc;
+                    for (int k = 0; k < PD_HOG_BINS; ++k) {
+                        float xr = P[(r * 3 + 0) * 9 + k][lane];
+                        float o0 = P[(r * 3 + 1) * 9 + k][lane];
+                        float o1 = P[(r * 3 + 2) * 9 + k][lane];
+                        if (r == 1) {
+                            xr += Ab[0][k];
+                            o0 += Ab[1][k];
+                            o1 += Ab[2][k];
                         }
+                        const float o0n = __shfl_down(o0, 1, 64);
+                        const float xrn = __shfl_down(xr, 1, 64);
+                        v[(r * 2 + 0) * 9 + k] = o0 + xrn;
+                        v[(r * 2 + 1) * 9 + k] = o1 + o0n;
                     }
                 }
-                // 4. L2-Hys
-                const float e2 = eps * eps;
-                float ss = 0.0f;
+                if (blk_col) {
+                    const float e2 = eps * eps;
+                    float ss = 0.0f;
 #pragma unroll
-                for (int k = 0; k < PD_HOG_BLOCK; ++k) ss = fmaf(v[k], v[k], ss);
-                float inv = 1.0f / sqrtf(ss + e2);
-                float ss2 = 0.0f;
+                    for (int k = 0; k < PD_HOG_BLOCK; ++k) ss = fmaf(v[k], v[k], ss);
+                    float inv = 1.0f / sqrtf(ss + e2);
+                    float ss2 = 0.0f;
 #pragma unroll
-                for (int k = 0; k < PD_HOG_BLOCK; ++k) {
-                    v[k] = fminf(v[k] * inv, clip);
-                    ss2 = fmaf(v[k], v[k], ss2);
+                    for (int k = 0; k < PD_HOG_BLOCK; ++k) {
+                        v[k] = fminf(v[k] * inv, clip);
+                        ss2 = fmaf(v[k], v[k], ss2);
+                    }
+                    inv = 1.0f / sqrtf(ss2 + e2);
+                    const size_t plane = (size_t)hb * wb;
+                    float* o = hog + (size_t)(cy - 1) * wb + cx;
+#pragma unroll
+                    for (int k = 0; k < PD_HOG_BLOCK; ++k) {
+                        *o = v[k] * inv;
+                        o += plane;
+                    }
                 }
-                inv = 1.0f / sqrtf(ss2 + e2);
-                const size_t plane = (size_t)hb * wb;
-                float* o = hog + (size_t)by * wb + bx;
+            }
+            if (cy < cy_last) {  // this row's dy = 0 and dy = +1 partials become P
 #pragma unroll
-                for (int k = 0; k < PD_HOG_BLOCK; ++k) o[k * plane] = v[k] * inv;
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int k = 0; k < PD_HOG_BINS; ++k) {
+                        P[a * 9 + k][lane] = Ab[a][k];
+                        P[(3 + a) * 9 + k][lane] = Aa[a][k];
+                    }
             }
         }
     }
 }
 
-constexpr size_t kFeatSmem = sizeof(FeatSmem);
-static_assert(kFeatSmem <= 160 * 1024, "feature tile exceeds LDS");
-
-template <int FEAT>
-__global__ void __launch_bounds__(256) features_single_kernel(LevelItem it, float clip, float eps) {
-    const int ntx = feat_tiles_x(it.wc);
-    features_tile<FEAT>(it.pyr, it.w, it.h, it.pitch, it.hog, it.lbp, blockIdx.x / ntx,
-                        blockIdx.x % ntx, clip, eps);
+__device__ inline void init_lut(FeatShared& sm) {
+    const int b = kLbp.bin[threadIdx.x];
+    sm.lut[threadIdx.x] = ((1u << (8 * (b & 3))) << 7) | (uint32_t)(b >> 2);
 }
 
+template <int FEAT, bool ALIGNED>
+__global__ void __launch_bounds__(256) features_single_kernel(LevelItem it, float clip, float eps) {
+    __shared__ FeatShared sm;
+    init_lut(sm);
+    __syncthreads();
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int task = blockIdx.x * FT_WAVES + wave;
+    const int ntx = feat_tiles_x(it.wc);
+    if (task >= ntx * feat_tiles_y(it.hc)) return;
+    features_strip<FEAT, ALIGNED>(it.pyr, it.w, it.h, it.pitch, it.hog, it.lbp, task / ntx, task % ntx, clip, eps,
+                                  sm, wave);
+}
+
+// The table launch requires 8-byte aligned level rows (pd_detect copies
+// misaligned frames into the pyramid buffer).
 template <int FEAT>
 __global__ void __launch_bounds__(256) features_table_kernel(const LevelItem* __restrict__ items,
-                                                             const Tile* __restrict__ tiles,
+                                                             const Tile* __restrict__ tiles, int n_tiles,
                                                              float clip, float eps) {
-    const Tile tl = tiles[blockIdx.x];
+    __shared__ FeatShared sm;
+    init_lut(sm);
+    __syncthreads();
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int task = blockIdx.x * FT_WAVES + wave;
+    if (task >= n_tiles) return;
+    const Tile tl = tiles[task];
     const LevelItem& it = items[tl.item];
-    features_tile<FEAT>(it.pyr, it.w, it.h, it.pitch, it.hog, it.lbp, tl.ty, tl.tx, clip, eps);
+    features_strip<FEAT, true>(it.pyr, it.w, it.h, it.pitch, it.hog, it.lbp, tl.ty, tl.tx, clip, eps, sm, wave);
 }
 
 // Algorithm 1 on its own: one thread per pixel (used to check the codes).
@@ -319,25 +379,23 @@ __global__ void __launch_bounds__(256) lbp_codes_kernel(const uint8_t* __restric
     codes[(size_t)y * codes_pitch + x] = (uint8_t)code;
 }
 
-template <int FEAT>
+template <int FEAT, bool ALIGNED>
 hipError_t feat_single(const LevelItem& it, float clip, float eps, hipStream_t s) {
-    static const hipError_t attr = hipFuncSetAttribute(
-        reinterpret_cast<const void*>(&features_single_kernel<FEAT>),
-        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFeatSmem);
-    if (attr != hipSuccess) return attr;
     const int n = feat_tiles_x(it.wc) * feat_tiles_y(it.hc);
-    features_single_kernel<FEAT><<<n, 256, kFeatSmem, s>>>(it, clip, eps);
+    features_single_kernel<FEAT, ALIGNED><<<ceil_div(n, FT_WAVES), 256, 0, s>>>(it, clip, eps);
     return hipGetLastError();
+}
+
+template <int FEAT>
+hipError_t feat_single_any(const LevelItem& it, float clip, float eps, hipStream_t s) {
+    const bool aligned = (((uintptr_t)it.pyr | (uintptr_t)it.pitch) & 7) == 0;
+    return aligned ? feat_single<FEAT, true>(it, clip, eps, s) : feat_single<FEAT, false>(it, clip, eps, s);
 }
 
 template <int FEAT>
 hipError_t feat_table(const LevelItem* items, const Tile* tiles, int n_tiles, float clip, float eps,
                       hipStream_t s) {
-    static const hipError_t attr = hipFuncSetAttribute(
-        reinterpret_cast<const void*>(&features_table_kernel<FEAT>),
-        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFeatSmem);
-    if (attr != hipSuccess) return attr;
-    features_table_kernel<FEAT><<<n_tiles, 256, kFeatSmem, s>>>(items, tiles, clip, eps);
+    features_table_kernel<FEAT><<<ceil_div(n_tiles, FT_WAVES), 256, 0, s>>>(items, tiles, n_tiles, clip, eps);
     return hipGetLastError();
 }
 
@@ -353,9 +411,9 @@ hipError_t launch_lbp_codes(const uint8_t* img, int w, int h, int pitch, uint8_t
 hipError_t launch_features_single(const LevelItem& it, int features, float clip, float eps, hipStream_t s) {
     if (it.hc <= 0 || it.wc <= 0) return hipSuccess;
     switch (features & (PD_FEAT_HOG | PD_FEAT_LBP)) {
-        case PD_FEAT_HOG: return feat_single<PD_FEAT_HOG>(it, clip, eps, s);
-        case PD_FEAT_LBP: return feat_single<PD_FEAT_LBP>(it, clip, eps, s);
-        case PD_FEAT_HOG | PD_FEAT_LBP: return feat_single<PD_FEAT_HOG | PD_FEAT_LBP>(it, clip, eps, s);
+        case PD_FEAT_HOG: return feat_single_any<PD_FEAT_HOG>(it, clip, eps, s);
+        case PD_FEAT_LBP: return feat_single_any<PD_FEAT_LBP>(it, clip, eps, s);
+        case PD_FEAT_HOG | PD_FEAT_LBP: return feat_single_any<PD_FEAT_HOG | PD_FEAT_LBP>(it, clip, eps, s);
         default: return hipSuccess;
     }
 }

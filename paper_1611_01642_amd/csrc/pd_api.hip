@@ -185,16 +185,17 @@ bool plan_detect(const pd_frame* frames, int n_frames, const pd_params* p, int n
             item_geometry(it, wh[k][0], wh[k][1]);
             L.sizes.push_back(wh[k][0]);
             L.sizes.push_back(wh[k][1]);
-            // level 0 is the frame itself: no pyramid copy
+            // level 0 is read from the frame itself when its rows are 8-byte
+            // aligned, else copied here like the other levels
             L.pyr_off.push_back(data);
-            if (k > 0) data = align_up(data + (int64_t)align_up(it.w, 16) * it.h, kAlign);
+            data = align_up(data + (int64_t)align_up(it.w, 16) * it.h, kAlign);
             L.hog_off.push_back(data);
             data = align_up(data + (int64_t)PD_HOG_BLOCK * it.hb * it.wb * 4, kAlign);
             L.lbp_off.push_back(data);
             data = align_up(data + (int64_t)PD_LBP_BINS * it.hc * it.wc, kAlign);
             L.sc_off.push_back(data);
             data = align_up(data + (int64_t)n_models * it.ny * it.nx * 4, kAlign);
-            L.n_rs += k > 0 ? resize_tiles_x(it.w) * resize_tiles_y(it.h) : 0;
+            L.n_rs += resize_tiles_x(it.w) * resize_tiles_y(it.h);  // upper bound
             L.n_ft += feat_tiles_x(it.wc) * feat_tiles_y(it.hc);
             L.n_sc += score_tiles_x(it.nx) * score_tiles_y(it.ny) * n_models;
             L.n_cp += ceil_div(it.nx * it.ny, CP_N);
@@ -221,9 +222,80 @@ bool plan_detect(const pd_frame* frames, int n_frames, const pd_params* p, int n
 }
 
 
+// Stage events of pd_detect (pd_profile_enable / pd_profile_read).
+struct Profile {
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    std::vector<std::vector<hipEvent_t>> pending;  // PD_N_STAGES + 1 events per call
+    double ms[PD_N_STAGES] = {};
+    int64_t calls = 0;
+    ~Profile() {
+        for (auto& v : pending)
+            for (auto e : v) (void)hipEventDestroy(e);
+        for (auto e : pool) (void)hipEventDestroy(e);
+    }
+};
+thread_local Profile g_prof;
+
+// Records the boundary events of one pd_detect call (or nothing when off).
+struct StageMarks {
+    std::vector<hipEvent_t> ev;
+    explicit StageMarks(bool on) {
+        if (!on) return;
+        for (int k = 0; k <= PD_N_STAGES; ++k) {
+            hipEvent_t e = nullptr;
+            if (!g_prof.pool.empty()) {
+                e = g_prof.pool.back();
+                g_prof.pool.pop_back();
+            } else if (hipEventCreate(&e) != hipSuccess) {
+                e = nullptr;
+            }
+            ev.push_back(e);
+        }
+    }
+    void mark(int k, hipStream_t s) {
+        if (!ev.empty() && ev[k]) (void)hipEventRecord(ev[k], s);
+    }
+    void commit() {
+        if (!ev.empty()) g_prof.pending.push_back(std::move(ev));
+    }
+};
+
 }  // namespace
 
 extern "C" {
+
+int pd_profile_enable(int on) {
+    g_prof.on = on != 0;
+    return PD_OK;
+}
+
+int pd_profile_read(double* ms, int64_t* calls, int reset) {
+    if (!ms || !calls) return fail(PD_E_ARG, "NULL output");
+    for (auto& v : g_prof.pending) {
+        bool ok = true;
+        for (auto e : v) ok = ok && e;
+        if (ok) {
+            if (int rc = hip_status(hipEventSynchronize(v.back()), "profile wait")) return rc;
+            for (int k = 0; k < PD_N_STAGES; ++k) {
+                float t = 0.0f;
+                if (hipEventElapsedTime(&t, v[k], v[k + 1]) == hipSuccess) g_prof.ms[k] += t;
+            }
+            ++g_prof.calls;
+        }
+        for (auto e : v)
+            if (e) g_prof.pool.push_back(e);
+    }
+    g_prof.pending.clear();
+    for (int k = 0; k < PD_N_STAGES; ++k) ms[k] = g_prof.ms[k];
+    *calls = g_prof.calls;
+    if (reset) {
+        for (double& v : g_prof.ms) v = 0.0;
+        g_prof.calls = 0;
+    }
+    return PD_OK;
+}
+
 
 void pd_params_default(pd_params* p) {
     if (!p) return;
@@ -419,7 +491,8 @@ int pd_detect(const pd_frame* frames, int n_frames, const float* weights, const 
             it.src_w = frames[f].w;
             it.src_h = frames[f].h;
             it.src_pitch = frames[f].pitch;
-            if (k == 0) {
+            const bool direct = k == 0 && (((uintptr_t)frames[f].data | (uintptr_t)frames[f].pitch) & 7) == 0;
+            if (direct) {
                 it.pyr = const_cast<uint8_t*>(frames[f].data);
                 it.pitch = frames[f].pitch;
             } else {
@@ -433,7 +506,7 @@ int pd_detect(const pd_frame* frames, int n_frames, const float* weights, const 
             it.level = k;
             geoms[f].wh[k][0] = it.w;
             geoms[f].wh[k][1] = it.h;
-            if (k > 0)
+            if (!direct)
                 for (int ty = 0; ty < resize_tiles_y(it.h); ++ty)
                     for (int tx = 0; tx < resize_tiles_x(it.w); ++tx) t_rs[nrs++] = Tile{q, ty, tx, 0};
             for (int ty = 0; ty < feat_tiles_y(it.hc); ++ty)
@@ -452,27 +525,37 @@ int pd_detect(const pd_frame* frames, int n_frames, const float* weights, const 
     int4* d_ckey = reinterpret_cast<int4*>(ws + L.off_ckey);
 
     int rc;
+    StageMarks marks(g_prof.on);
+    marks.mark(PD_STAGE_UPLOAD, s);
     if ((rc = hip_status(hipMemcpyAsync(ws, stage, (size_t)L.table_bytes, hipMemcpyHostToDevice, s),
                          "table upload")))
         return rc;
     if ((rc = hip_status(hipEventRecord(slot.ev, s), "staging record"))) return rc;
     slot.pending = true;
+    marks.mark(PD_STAGE_ZERO, s);
     if ((rc = hip_status(launch_zero_i32(d_counters, n_frames, s), "zero"))) return rc;
-    if ((rc = hip_status(launch_resize_table(d_items, d_tiles, L.n_rs, s), "resize"))) return rc;
+    marks.mark(PD_STAGE_RESIZE, s);
+    if ((rc = hip_status(launch_resize_table(d_items, d_tiles, nrs, s), "resize"))) return rc;
+    marks.mark(PD_STAGE_FEATURES, s);
     if ((rc = hip_status(launch_features_table(d_items, d_tiles + L.n_rs, L.n_ft, params->features,
                                                params->clip, params->eps, s),
                          "features")))
         return rc;
+    marks.mark(PD_STAGE_SCORE, s);
     if ((rc = hip_status(launch_score_table(d_items, d_tiles + L.n_rs + L.n_ft, L.n_sc, weights, bias, n_models,
                                             params->features, s),
                          "score")))
         return rc;
+    marks.mark(PD_STAGE_COMPACT, s);
     if ((rc = hip_status(launch_compact_table(d_items, d_tiles + L.n_rs + L.n_ft + L.n_sc, L.n_cp, n_models,
                                               thresholds, d_counters, d_cscore, d_ckey, s),
                          "compact")))
         return rc;
-    return hip_status(launch_nms_table(d_geoms, n_frames, d_counters, d_cscore, d_ckey, boxes, cap, counts, s),
-                      "nms");
+    marks.mark(PD_STAGE_NMS, s);
+    rc = hip_status(launch_nms_table(d_geoms, n_frames, d_counters, d_cscore, d_ckey, boxes, cap, counts, s), "nms");
+    marks.mark(PD_N_STAGES, s);
+    marks.commit();
+    return rc;
 }
 
 int pd_nms(const float* cand_score, const int32_t* cand_key, int n, const int32_t* level_wh, int n_levels,

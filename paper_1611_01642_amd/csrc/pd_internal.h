@@ -41,11 +41,14 @@ struct NmsGeom {
 // resize: 64 lanes x 4 pixels wide, 16 rows
 constexpr int RS_TX = 256;   // pixels per tile row
 constexpr int RS_TY = 16;    // rows per tile
-// features: 16x16 cells per workgroup (one cell per lane), blocks 15x15
-constexpr int FT_C = 16;
-constexpr int FT_B = 15;
+// features: one wave = a strip of 64 cell columns (one per lane) walking
+// down FT_CH block rows (+1 overlap cell row); it owns 63 block columns
+constexpr int FT_W = 64;
+constexpr int FT_BX = 63;
+constexpr int FT_CH = 8;
+constexpr int FT_WAVES = 4;  // waves (independent strips) per workgroup
 // scoring: one wave = 64 window columns x SC_R window rows
-constexpr int SC_R = 16;
+constexpr int SC_R = 8;
 constexpr int SC_W = 64;
 constexpr int SC_WAVES = 4;  // waves (independent tiles) per workgroup
 // compaction: windows per workgroup
@@ -55,8 +58,8 @@ __host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; 
 
 __host__ __device__ inline int resize_tiles_x(int w) { return ceil_div(w, RS_TX); }
 __host__ __device__ inline int resize_tiles_y(int h) { return ceil_div(h, RS_TY); }
-__host__ __device__ inline int feat_tiles_x(int wc) { return wc <= 1 ? 1 : ceil_div(wc - 1, FT_B); }
-__host__ __device__ inline int feat_tiles_y(int hc) { return hc <= 1 ? 1 : ceil_div(hc - 1, FT_B); }
+__host__ __device__ inline int feat_tiles_x(int wc) { return wc <= 1 ? 1 : ceil_div(wc - 1, FT_BX); }
+__host__ __device__ inline int feat_tiles_y(int hc) { return hc <= 1 ? 1 : ceil_div(hc - 1, FT_CH); }
 __host__ __device__ inline int score_tiles_x(int nx) { return ceil_div(nx, SC_W); }
 __host__ __device__ inline int score_tiles_y(int ny) { return ceil_div(ny, SC_R); }
 

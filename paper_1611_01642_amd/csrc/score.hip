@@ -3,42 +3,68 @@
 // The score of window (i, j) is a 2-D correlation of the feature planes with
 // the model:  s(i,j) = sum_c sum_a sum_b F_c[i+a][j+b] * W[a][b][c] + bias.
 // Algorithm 6 gives each window a warp that re-reads the window's whole
-// feature vector; here one wave64 owns 64 adjacent window columns (one per
-// lane) and SC_R window rows (registers), so every feature value a lane loads
-// serves up to 15 (HOG) or 16 (LBP) windows of its column, and the loads of a
-// wave are 64 consecutive floats/bytes of one plane row (coalesced).  Weights
-// are wave-uniform (scalar loads).  FP32 products, FP32 sums in a fixed order.
+// feature vector.  Here one wave64 owns a tile of 64 adjacent window columns
+// (one per lane) x SC_R window rows (registers).  For each feature plane c the
+// wave stages the tile's (SC_R + 14 or 15) x (64 + 6 or 7) patch in its own
+// LDS region (coalesced loads of the next plane are in flight while the
+// current one is used), then every patch value a lane reads from LDS serves up
+// to SC_R windows of its column.  Weights are wave-uniform (scalar loads).
+// FP32 products and FP32 sums in a fixed order.
 #include "pd_internal.h"
 
 namespace pd {
 namespace {
 
+constexpr int HOG_PR = SC_R + PD_WIN_BLOCKS_Y - 1;  // patch rows
+constexpr int HOG_PC = SC_W + PD_WIN_BLOCKS_X - 1;  // patch columns
+constexpr int LBP_PR = SC_R + PD_WIN_CELLS_Y - 1;
+constexpr int LBP_PC = SC_W + PD_WIN_CELLS_X - 1;
+constexpr int HOG_PQ = (HOG_PR * HOG_PC + 63) / 64;  // patch values per lane
+constexpr int LBP_PQ = (LBP_PR * LBP_PC + 63) / 64;
+constexpr int PATCH = (HOG_PR * HOG_PC > LBP_PR * LBP_PC ? HOG_PR * HOG_PC : LBP_PR * LBP_PC);
+
 template <int FEAT>
-__device__ void score_tile(const float* __restrict__ hog, const uint8_t* __restrict__ lbp, int wc, int hc,
-                           const float* __restrict__ wt, float bias, float* __restrict__ out, int ty,
-                           int tx, int lane) {
+__device__ __forceinline__ void score_tile(const float* __restrict__ hog, const uint8_t* __restrict__ lbp, int wc,
+                                           int hc, const float* __restrict__ wt, float bias, float* __restrict__ out,
+                                           int ty, int tx, int lane, float* __restrict__ patch) {
     const int hb = hc - 1, wb = wc - 1;
     const int ny = hc - PD_WIN_CELLS_Y + 1, nx = wc - PD_WIN_CELLS_X + 1;
     const int i0 = ty * SC_R;
-    const int j = tx * SC_W + lane;
-    const int jj = min(j, nx - 1);   // lanes past the last column load valid data
+    const int j0 = tx * SC_W;
     float acc[SC_R];
 #pragma unroll
     for (int r = 0; r < SC_R; ++r) acc[r] = 0.0f;
 
     if (FEAT & PD_FEAT_HOG) {
         const size_t plane = (size_t)hb * wb;
+        int off[HOG_PQ];  // clamped plane offsets of this lane's patch values
+#pragma unroll
+        for (int q = 0; q < HOG_PQ; ++q) {
+            const int e = min(lane + 64 * q, HOG_PR * HOG_PC - 1);
+            const int row = e / HOG_PC, col = e - (e / HOG_PC) * HOG_PC;
+            off[q] = min(i0 + row, hb - 1) * wb + min(j0 + col, wb - 1);
+        }
+        float pre[HOG_PQ];
+#pragma unroll
+        for (int q = 0; q < HOG_PQ; ++q) pre[q] = hog[off[q]];
         for (int c = 0; c < PD_HOG_BLOCK; ++c) {
-            const float* fp = hog + c * plane + jj;
+#pragma unroll
+            for (int q = 0; q < HOG_PQ; ++q)
+                if (lane + 64 * q < HOG_PR * HOG_PC) patch[lane + 64 * q] = pre[q];
+            if (c + 1 < PD_HOG_BLOCK) {
+                const float* nxt = hog + (size_t)(c + 1) * plane;
+#pragma unroll
+                for (int q = 0; q < HOG_PQ; ++q) pre[q] = nxt[off[q]];
+            }
+            __builtin_amdgcn_wave_barrier();
             for (int b = 0; b < PD_WIN_BLOCKS_X; ++b) {
                 float wa[PD_WIN_BLOCKS_Y];
 #pragma unroll
-                for (int a = 0; a < PD_WIN_BLOCKS_Y; ++a)
-                    wa[a] = wt[(a * PD_WIN_BLOCKS_X + b) * PD_HOG_BLOCK + c];
+                for (int a = 0; a < PD_WIN_BLOCKS_Y; ++a) wa[a] = wt[(a * PD_WIN_BLOCKS_X + b) * PD_HOG_BLOCK + c];
+                const float* pr = patch + lane + b;
 #pragma unroll
-                for (int y = 0; y < SC_R + PD_WIN_BLOCKS_Y - 1; ++y) {
-                    const int row = min(i0 + y, hb - 1);
-                    const float v = fp[(size_t)row * wb + b];
+                for (int y = 0; y < HOG_PR; ++y) {
+                    const float v = pr[y * HOG_PC];
 #pragma unroll
                     for (int r = 0; r < SC_R; ++r) {
                         const int a = y - r;
@@ -46,22 +72,40 @@ __device__ void score_tile(const float* __restrict__ hog, const uint8_t* __restr
                     }
                 }
             }
+            __builtin_amdgcn_wave_barrier();
         }
     }
     if (FEAT & PD_FEAT_LBP) {
         const size_t plane = (size_t)hc * wc;
         const float* wl = wt + PD_HOG_DIM;
+        int off[LBP_PQ];
+#pragma unroll
+        for (int q = 0; q < LBP_PQ; ++q) {
+            const int e = min(lane + 64 * q, LBP_PR * LBP_PC - 1);
+            const int row = e / LBP_PC, col = e - (e / LBP_PC) * LBP_PC;
+            off[q] = min(i0 + row, hc - 1) * wc + min(j0 + col, wc - 1);
+        }
+        uint32_t pre[LBP_PQ];
+#pragma unroll
+        for (int q = 0; q < LBP_PQ; ++q) pre[q] = lbp[off[q]];
         for (int c = 0; c < PD_LBP_BINS; ++c) {
-            const uint8_t* fp = lbp + c * plane + jj;
+#pragma unroll
+            for (int q = 0; q < LBP_PQ; ++q)
+                if (lane + 64 * q < LBP_PR * LBP_PC) patch[lane + 64 * q] = (float)pre[q];
+            if (c + 1 < PD_LBP_BINS) {
+                const uint8_t* nxt = lbp + (size_t)(c + 1) * plane;
+#pragma unroll
+                for (int q = 0; q < LBP_PQ; ++q) pre[q] = nxt[off[q]];
+            }
+            __builtin_amdgcn_wave_barrier();
             for (int b = 0; b < PD_WIN_CELLS_X; ++b) {
                 float wa[PD_WIN_CELLS_Y];
 #pragma unroll
-                for (int a = 0; a < PD_WIN_CELLS_Y; ++a)
-                    wa[a] = wl[(a * PD_WIN_CELLS_X + b) * PD_LBP_BINS + c];
+                for (int a = 0; a < PD_WIN_CELLS_Y; ++a) wa[a] = wl[(a * PD_WIN_CELLS_X + b) * PD_LBP_BINS + c];
+                const float* pr = patch + lane + b;
 #pragma unroll
-                for (int y = 0; y < SC_R + PD_WIN_CELLS_Y - 1; ++y) {
-                    const int row = min(i0 + y, hc - 1);
-                    const float v = (float)fp[(size_t)row * wc + b];
+                for (int y = 0; y < LBP_PR; ++y) {
+                    const float v = pr[y * LBP_PC];
 #pragma unroll
                     for (int r = 0; r < SC_R; ++r) {
                         const int a = y - r;
@@ -69,8 +113,10 @@ __device__ void score_tile(const float* __restrict__ hog, const uint8_t* __restr
                     }
                 }
             }
+            __builtin_amdgcn_wave_barrier();
         }
     }
+    const int j = j0 + lane;
     if (j < nx) {
 #pragma unroll
         for (int r = 0; r < SC_R; ++r) {
@@ -83,14 +129,16 @@ __device__ void score_tile(const float* __restrict__ hog, const uint8_t* __restr
 template <int FEAT>
 __global__ void __launch_bounds__(256) score_single_kernel(LevelItem it, const float* __restrict__ wt,
                                                            const float* __restrict__ bias, int n_models) {
-    const int wave = blockIdx.x * SC_WAVES + (threadIdx.x >> 6);
+    __shared__ float patches[SC_WAVES][PATCH];
+    const int wave = blockIdx.x * SC_WAVES + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int ntx = score_tiles_x(it.nx), nty = score_tiles_y(it.ny);
     const int per_model = ntx * nty;
     if (wave >= per_model * n_models) return;
     const int m = wave / per_model;
     const int local = wave - m * per_model;
     score_tile<FEAT>(it.hog, it.lbp, it.wc, it.hc, wt + (size_t)m * PD_FEATURE_DIM, bias[m],
-                     it.scores + (size_t)m * it.ny * it.nx, local / ntx, local % ntx, threadIdx.x & 63);
+                     it.scores + (size_t)m * it.ny * it.nx, local / ntx, local % ntx, threadIdx.x & 63,
+                     patches[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)]);
 }
 
 // Tile.pad carries the model index.
@@ -99,13 +147,15 @@ __global__ void __launch_bounds__(256) score_table_kernel(const LevelItem* __res
                                                           const Tile* __restrict__ tiles, int n_tiles,
                                                           const float* __restrict__ wt,
                                                           const float* __restrict__ bias) {
-    const int wave = blockIdx.x * SC_WAVES + (threadIdx.x >> 6);
+    __shared__ float patches[SC_WAVES][PATCH];
+    const int wave = blockIdx.x * SC_WAVES + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (wave >= n_tiles) return;
     const Tile tl = tiles[wave];
     const LevelItem& it = items[tl.item];
     const int m = tl.pad;
     score_tile<FEAT>(it.hog, it.lbp, it.wc, it.hc, wt + (size_t)m * PD_FEATURE_DIM, bias[m],
-                     it.scores + (size_t)m * it.ny * it.nx, tl.ty, tl.tx, threadIdx.x & 63);
+                     it.scores + (size_t)m * it.ny * it.nx, tl.ty, tl.tx, threadIdx.x & 63,
+                     patches[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)]);
 }
 
 template <int FEAT>
