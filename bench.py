@@ -37,12 +37,11 @@ def _gen(seed):
 
 
 def make_frames(n, seed0=1000, workers=16):
-    from multiprocessing import get_context
+    # threads, not processes: profilers preload themselves into child processes
+    from concurrent.futures import ThreadPoolExecutor
     seeds = [seed0 + f for f in range(n)]
-    if n <= 4:
-        return [_gen(s) for s in seeds]
-    with get_context("spawn").Pool(min(workers, n)) as pool:
-        return pool.map(_gen, seeds)
+    with ThreadPoolExecutor(max_workers=min(workers, n)) as ex:
+        return list(ex.map(_gen, seeds))
 
 
 def _oracle_frame(seed):
@@ -84,6 +83,22 @@ def cpu_baseline(frames_per_core=2, max_cores=16):
                       f"mean {1000 * sum(per) / n:.0f} ms per frame per core"}
 
 
+def measured_traffic(kernel, batch):
+    """HBM bytes per launch of `kernel` from the committed counter record, or
+    None when the record is for another batch or the kernel source changed."""
+    import hashlib
+    path = os.path.join(HERE, "profiles", "traffic_road1242x375_b256.json")
+    if batch != 256 or not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get(kernel)
+    if not rec:
+        return None
+    src = os.path.join(HERE, rec["source"])
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["sha256"]:
+        return None
+    return rec["read_bytes"] + rec["write_bytes"]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -92,6 +107,8 @@ def main():
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--no-latency", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="after timing, run one 256 MiB device-to-device copy (scales HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build",
@@ -178,12 +195,14 @@ def main():
         achieved = score_flops / score_s / 1e12
         roof = {"kernel": "score_table_kernel (FP32 window scoring)", "bound": "alu",
                 "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP32_TFLOPS, 4), "traffic": None}
+                "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                "traffic": measured_traffic("score_table_kernel", B)}
     else:
         achieved = feat_bytes / feat_s / 1e9
         roof = {"kernel": "features_table_kernel (HOG+LBP)", "bound": "hbm",
                 "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None}
+                "frac": round(achieved / PEAK_HBM_GBS, 4),
+                "traffic": measured_traffic("features_table_kernel", B)}
 
     value = B * args.steps / elapsed
     out = {
@@ -205,6 +224,12 @@ def main():
         "detections_per_frame": round(float(np.mean([c["kept"] for c in counts])), 2),
         "candidates_per_frame": round(float(np.mean([c["candidates"] for c in counts])), 2),
     }
+    if args.calib_copy:
+        src = torch.ones(64 << 20, dtype=torch.int32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["calib_copy_bytes"] = int(src.numel()) * 4
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline()
