@@ -63,6 +63,14 @@ extern "C" {
 #define PD_FEAT_HOG      1
 #define PD_FEAT_LBP      2
 
+/* scoring precision */
+#define PD_PREC_F32      0    /* FP32 features, FP32 scoring                  */
+#define PD_PREC_BF16     1    /* BF16 HOG, BF16 MFMA scoring (FP32 sums) with
+                                 FP64 rescoring of near-threshold windows     */
+#define PD_MAX_MODELS_BF16 8  /* 8 models x {hi, lo} weight halves = 16 MFMA
+                                 columns                                      */
+#define PD_MAX_NEAR      1024 /* near-threshold windows rescored per frame    */
+
 /* ---- parameters -------------------------------------------------------- */
 typedef struct pd_params {
     int32_t scale_num;   /* pyramid step as the ratio scale_num/scale_den,  */
@@ -71,10 +79,15 @@ typedef struct pd_params {
     float   clip;        /* L2-Hys clip level (0.2)                         */
     float   eps;         /* L2-Hys epsilon (1e-3)                           */
     int32_t features;    /* PD_FEAT_HOG | PD_FEAT_LBP                       */
-    int32_t reserved[4]; /* zero                                           */
+    int32_t precision;   /* PD_PREC_F32 or PD_PREC_BF16                     */
+    float   margin;      /* PD_PREC_BF16: windows whose score is within
+                            margin of the threshold are rescored in FP64
+                            (0.05)                                          */
+    int32_t reserved[2]; /* zero                                           */
 } pd_params;
 
-/* Fills the defaults above: 11/10, all levels, 0.2, 1e-3, HOG|LBP. */
+/* Fills the defaults above: 11/10, all levels, 0.2, 1e-3, HOG|LBP, FP32,
+   margin 0.05. */
 void pd_params_default(pd_params* p);
 
 /* One pyramid level as planned by pd_plan_pyramid (host struct). */
@@ -157,10 +170,13 @@ int pd_hog(const uint8_t* lvl, int w, int h, int pitch, const pd_params* params,
 
 /*
  * pd_features -- pd_hog and pd_lbp of one level in a single pass over the
- * pixels (either output may be NULL when its subset is off).
+ * pixels.  HOG goes to `blocks` (FP32) or to `blocks_bf16` (the same values
+ * rounded to nearest-even BF16, uint16 bit patterns, same [36][Hb][Wb]
+ * layout); at most one of the two may be non-NULL.  Outputs that are NULL
+ * are not computed.
  */
 int pd_features(const uint8_t* lvl, int w, int h, int pitch, const pd_params* params,
-                float* blocks, uint8_t* cell_hist, void* stream);
+                float* blocks, uint16_t* blocks_bf16, uint8_t* cell_hist, void* stream);
 
 /*
  * pd_score_windows -- Section 4.4, Algorithm 6.
@@ -181,6 +197,24 @@ int pd_score_windows(const float* blocks, const uint8_t* cells, int cells_x, int
                      const float* weights, const float* bias, int n_models,
                      float* scores, void* stream);
 
+/*
+ * BF16 scoring (Section 4.4, Algorithm 6 as a GEMM of windows x 11332
+ * features x models on BF16 MFMA with FP32 accumulation).  Each FP32 weight
+ * w is carried as hi = bf16(w) plus lo = bf16(w - hi).
+ *
+ * pd_packed_models_bytes -- bytes of the packed model buffer (any n_models).
+ * pd_pack_models -- packs weights (device float [n_models][11332], layout of
+ *   pd_score_windows, n_models <= PD_MAX_MODELS_BF16) into `packed` (device).
+ * pd_score_windows_bf16 -- scores [n_models][Hc-15][Wc-7] (FP32) from BF16
+ *   HOG planes [36][Hc-1][Wc-1] (uint16 bit patterns), uint8 LBP planes
+ *   [59][Hc][Wc], packed models and bias (device float [n_models]).
+ */
+int64_t pd_packed_models_bytes(void);
+int pd_pack_models(const float* weights, int n_models, uint16_t* packed, void* stream);
+int pd_score_windows_bf16(const uint16_t* blocks_bf16, const uint8_t* cells, int cells_x, int cells_y,
+                          const uint16_t* packed, const float* bias, int n_models, float* scores,
+                          void* stream);
+
 /* ---- whole pipeline ------------------------------------------------------ */
 
 /* One input frame (device image). */
@@ -197,7 +231,8 @@ typedef struct pd_box {
                                 x1 = floor(256*(8j+64)*w0/wk), y likewise
                                 with 128 and the heights                    */
     float   score;           /* window score (max over models)             */
-    double  score64;         /* reserved; NaN                              */
+    double  score64;         /* FP64 rescore (PD_PREC_BF16, windows within
+                                the margin of the threshold), else NaN     */
 } pd_box;
 
 /* Per-frame result counters written by pd_detect. */
@@ -206,7 +241,8 @@ typedef struct pd_counts {
     int32_t kept;        /* boxes written after NMS (<= cap)               */
     int32_t overflow;    /* 1 if candidates > PD_MAX_CANDIDATES or the kept
                             boxes exceeded `cap` (results then incomplete) */
-    int32_t reserved;
+    int32_t rescored;    /* PD_PREC_BF16: windows rescored in FP64 (true
+                            count; at most PD_MAX_NEAR were rescored)      */
 } pd_counts;
 
 /*
@@ -222,9 +258,13 @@ int64_t pd_detect_workspace_bytes(const pd_frame* frames, int n_frames,
  * any sizes (Section 4.1 steps 2-5): pyramid, features, window scores,
  * threshold (a window is a detection iff its score, the max over models,
  * is > thresholds[frame]) and greedy NMS (order by score descending, then
- * level, i, j ascending; a box is suppressed iff its IoU with a kept box is
- * > 0.5, decided exactly as 2*inter > union on the integer boxes).  Every
- * stage is one launch over all frames and levels.
+ * level, i, j ascending).  With params->precision == PD_PREC_BF16 (at most
+ * 8 models) the HOG features are stored in BF16, scores come from BF16 MFMA,
+ * and every window whose score is within params->margin of the threshold is
+ * recomputed from its pixels in FP64; its FP64 score decides.  A box is
+ * suppressed iff its IoU with a kept box is > 0.5, decided exactly as
+ * 2*inter > union on the integer boxes.  Every stage is one launch over all
+ * frames and levels.
  *   frames     : host array of n_frames descriptors (device images)
  *   weights    : device float [n_models][11332], bias: device [n_models]
  *   thresholds : device double [n_frames]
@@ -236,6 +276,19 @@ int pd_detect(const pd_frame* frames, int n_frames, const float* weights,
               const float* bias, int n_models, const pd_params* params,
               const double* thresholds, void* workspace, int64_t workspace_bytes,
               pd_box* boxes, int cap, pd_counts* counts, void* stream);
+
+/*
+ * pd_detect_candidates -- test hook: after pd_detect on the same arguments
+ * (frames, params, n_models, workspace), enqueue copies of frame `frame`'s
+ * candidate list (windows above the threshold, before NMS, in no particular
+ * order; min(pd_counts.candidates, PD_MAX_CANDIDATES) entries):
+ *   cand_score : device float [cap]; cand_key: device int32 [cap][4] =
+ *                (level, i, j, model); cand_s64: device double [cap] or NULL
+ *                (FP64 score for rescored windows, NaN otherwise; PD_PREC_BF16)
+ */
+int pd_detect_candidates(const pd_frame* frames, int n_frames, const pd_params* params, int n_models,
+                         const void* workspace, int64_t workspace_bytes, int frame, float* cand_score,
+                         int32_t* cand_key, double* cand_s64, int cap, void* stream);
 
 /*
  * pd_nms -- greedy NMS of one candidate list (the last stage of pd_detect,

@@ -25,6 +25,9 @@ MAX_LEVELS = 64
 MAX_MODELS = 16
 MAX_CANDIDATES = 4096
 FEAT_HOG, FEAT_LBP = 1, 2
+PREC_F32, PREC_BF16 = 0, 1
+MAX_MODELS_BF16 = 8
+MAX_NEAR = 1024
 
 E_ARG, E_SIZE, E_WORKSPACE, E_HIP = -1, -2, -3, -4
 
@@ -38,7 +41,8 @@ class PdError(RuntimeError):
 class Params(ctypes.Structure):
     _fields_ = [("scale_num", ctypes.c_int32), ("scale_den", ctypes.c_int32),
                 ("max_levels", ctypes.c_int32), ("clip", ctypes.c_float), ("eps", ctypes.c_float),
-                ("features", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+                ("features", ctypes.c_int32), ("precision", ctypes.c_int32), ("margin", ctypes.c_float),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class Level(ctypes.Structure):
@@ -57,7 +61,7 @@ class Frame(ctypes.Structure):
 BOX_DTYPE = np.dtype([("frame", "<i4"), ("level", "<i4"), ("i", "<i4"), ("j", "<i4"), ("model", "<i4"),
                       ("x0", "<i4"), ("y0", "<i4"), ("x1", "<i4"), ("y1", "<i4"),
                       ("score", "<f4"), ("score64", "<f8")])
-COUNTS_DTYPE = np.dtype([("candidates", "<i4"), ("kept", "<i4"), ("overflow", "<i4"), ("reserved", "<i4")])
+COUNTS_DTYPE = np.dtype([("candidates", "<i4"), ("kept", "<i4"), ("overflow", "<i4"), ("rescored", "<i4")])
 assert BOX_DTYPE.itemsize == 48 and COUNTS_DTYPE.itemsize == 16
 
 _lib = None
@@ -75,7 +79,15 @@ _SIGS = {
     "pd_hog": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
                               ctypes.c_void_p, ctypes.c_void_p]),
     "pd_features": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
-                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "pd_packed_models_bytes": (ctypes.c_int64, []),
+    "pd_pack_models": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
+    "pd_score_windows_bf16": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                             ctypes.c_void_p]),
+    "pd_detect_candidates": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
+                                            ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p,
+                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
     "pd_score_windows": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                                         ctypes.c_void_p]),
@@ -116,7 +128,7 @@ def _check(rc: int) -> None:
 
 
 def params(scale=(11, 10), max_levels: int = 0, clip: float = 0.2, eps: float = 1e-3,
-           features: int = FEAT_HOG | FEAT_LBP) -> Params:
+           features: int = FEAT_HOG | FEAT_LBP, precision: int = PREC_F32, margin: float = 0.05) -> Params:
     p = Params()
     lib().pd_params_default(ctypes.byref(p))
     p.scale_num, p.scale_den = scale
@@ -124,6 +136,8 @@ def params(scale=(11, 10), max_levels: int = 0, clip: float = 0.2, eps: float = 
     p.clip = clip
     p.eps = eps
     p.features = features
+    p.precision = precision
+    p.margin = margin
     return p
 
 
@@ -177,19 +191,44 @@ def lbp_codes(img):
     return out
 
 
-def features(img, prm: Params = None, hog: bool = True, lbp: bool = True):
-    """(blocks [36][Hb][Wb] float32 or None, cells [59][Hc][Wc] uint8 or None)."""
+def features(img, prm: Params = None, hog: bool = True, lbp: bool = True, bf16: bool = False):
+    """(blocks [36][Hb][Wb] float32 (bfloat16 if bf16) or None,
+    cells [59][Hc][Wc] uint8 or None)."""
     torch = _torch()
     prm = prm or params()
     p, w, h, pitch = _image_args(img)
     hc, wc = h // CELL, w // CELL
-    blocks = torch.empty((HOG_BLOCK, max(hc - 1, 0), max(wc - 1, 0)), dtype=torch.float32,
-                         device=img.device) if hog else None
+    blocks = torch.empty((HOG_BLOCK, max(hc - 1, 0), max(wc - 1, 0)),
+                         dtype=torch.bfloat16 if bf16 else torch.float32, device=img.device) if hog else None
     cells = torch.empty((LBP_BINS, hc, wc), dtype=torch.uint8, device=img.device) if lbp else None
+    bptr = blocks.data_ptr() if hog else 0
     _check(lib().pd_features(p, w, h, pitch, ctypes.byref(prm),
-                             ctypes.c_void_p(blocks.data_ptr() if hog else 0),
+                             ctypes.c_void_p(bptr if not bf16 else 0), ctypes.c_void_p(bptr if bf16 else 0),
                              ctypes.c_void_p(cells.data_ptr() if lbp else 0), _stream()))
     return blocks, cells
+
+
+def pack_models(weights):
+    """Packed BF16 hi/lo model buffer (uint8 device tensor) for score_windows_bf16."""
+    torch = _torch()
+    weights = weights.contiguous()
+    out = torch.empty(int(lib().pd_packed_models_bytes()), dtype=torch.uint8, device=weights.device)
+    _check(lib().pd_pack_models(ctypes.c_void_p(weights.data_ptr()), int(weights.shape[0]),
+                                ctypes.c_void_p(out.data_ptr()), _stream()))
+    return out
+
+
+def score_windows_bf16(blocks_bf16, cells, packed, bias, n_models: int):
+    """Scores [m][Hc-15][Wc-7] float32 from BF16 HOG planes on BF16 MFMA."""
+    torch = _torch()
+    hc, wc = int(cells.shape[1]), int(cells.shape[2])
+    if blocks_bf16.dtype != torch.bfloat16 or blocks_bf16.shape != (HOG_BLOCK, hc - 1, wc - 1):
+        raise ValueError("blocks must be bfloat16 [36][Hc-1][Wc-1]")
+    out = torch.empty((n_models, max(hc - 15, 0), max(wc - 7, 0)), dtype=torch.float32, device=cells.device)
+    _check(lib().pd_score_windows_bf16(ctypes.c_void_p(blocks_bf16.data_ptr()), ctypes.c_void_p(cells.data_ptr()),
+                                       wc, hc, ctypes.c_void_p(packed.data_ptr()), ctypes.c_void_p(bias.data_ptr()),
+                                       n_models, ctypes.c_void_p(out.data_ptr()), _stream()))
+    return out
 
 
 def hog(img, prm: Params = None):
@@ -282,6 +321,24 @@ class Detector:
                                ctypes.c_void_p(thresholds.data_ptr()), ctypes.c_void_p(self.ws_ptr),
                                self.ws_bytes, ctypes.c_void_p(self.boxes.data_ptr()), self.cap,
                                ctypes.c_void_p(self.counts.data_ptr()), _stream()))
+
+    def candidates(self, frame: int):
+        """(scores float32 [n], keys int32 [n][4], fp64 scores or None) of one
+        frame's pre-NMS candidate list (after run(); n = candidates count)."""
+        torch = _torch()
+        counts = self.counts.cpu().numpy().view(COUNTS_DTYPE)
+        n = int(min(counts[frame]["candidates"], MAX_CANDIDATES))
+        dev = self.frames[0].device
+        cs = torch.empty(max(n, 1), dtype=torch.float32, device=dev)
+        ck = torch.empty((max(n, 1), 4), dtype=torch.int32, device=dev)
+        bf = self.prm.precision == PREC_BF16
+        c64 = torch.empty(max(n, 1), dtype=torch.float64, device=dev) if bf else None
+        _check(lib().pd_detect_candidates(self._frames, len(self.frames), ctypes.byref(self.prm), self.n_models,
+                                          ctypes.c_void_p(self.ws_ptr), self.ws_bytes, frame,
+                                          ctypes.c_void_p(cs.data_ptr()), ctypes.c_void_p(ck.data_ptr()),
+                                          ctypes.c_void_p(c64.data_ptr() if bf else 0), n, _stream()))
+        torch.cuda.synchronize()
+        return (cs[:n].cpu().numpy(), ck[:n].cpu().numpy(), c64[:n].cpu().numpy() if bf else None)
 
     def results(self):
         """(boxes per frame as numpy structured arrays, counts structured array)."""

@@ -124,8 +124,8 @@ __device__ __forceinline__ int px_at(const PixRow& r, int i) {  // i in 0..9, co
 
 template <int FEAT, bool ALIGNED>
 __device__ __forceinline__ void features_strip(const uint8_t* __restrict__ img, int w, int h, int pitch, float* __restrict__ hog,
-                               uint8_t* __restrict__ lbp, int ty, int tx, float clip, float eps,
-                               FeatShared& sm, int wave) {
+                               uint16_t* __restrict__ hog16, uint8_t* __restrict__ lbp, int ty, int tx, float clip,
+                               float eps, FeatShared& sm, int wave) {
     constexpr bool DO_HOG = (FEAT & PD_FEAT_HOG) != 0;
     constexpr bool DO_LBP = (FEAT & PD_FEAT_LBP) != 0;
     const int lane = threadIdx.x & 63;
@@ -303,11 +303,21 @@ __device__ __forceinline__ void features_strip(const uint8_t* __restrict__ img, 
                     }
                     inv = 1.0f / sqrtf(ss2 + e2);
                     const size_t plane = (size_t)hb * wb;
-                    float* o = hog + (size_t)(cy - 1) * wb + cx;
+                    const size_t at = (size_t)(cy - 1) * wb + cx;
+                    if (hog16) {  // BF16 planes (round to nearest even)
+                        uint16_t* o = hog16 + at;
 #pragma unroll
-                    for (int k = 0; k < PD_HOG_BLOCK; ++k) {
-                        *o = v[k] * inv;
-                        o += plane;
+                        for (int k = 0; k < PD_HOG_BLOCK; ++k) {
+                            *o = f32_to_bf16(v[k] * inv);
+                            o += plane;
+                        }
+                    } else {
+                        float* o = hog + at;
+#pragma unroll
+                        for (int k = 0; k < PD_HOG_BLOCK; ++k) {
+                            *o = v[k] * inv;
+                            o += plane;
+                        }
                     }
                 }
             }
@@ -338,8 +348,8 @@ __global__ void __launch_bounds__(256) features_single_kernel(LevelItem it, floa
     const int task = blockIdx.x * FT_WAVES + wave;
     const int ntx = feat_tiles_x(it.wc);
     if (task >= ntx * feat_tiles_y(it.hc)) return;
-    features_strip<FEAT, ALIGNED>(it.pyr, it.w, it.h, it.pitch, it.hog, it.lbp, task / ntx, task % ntx, clip, eps,
-                                  sm, wave);
+    features_strip<FEAT, ALIGNED>(it.pyr, it.w, it.h, it.pitch, it.hog, it.hog16, it.lbp, task / ntx, task % ntx,
+                                  clip, eps, sm, wave);
 }
 
 // The table launch requires 8-byte aligned level rows (pd_detect copies
@@ -356,7 +366,8 @@ __global__ void __launch_bounds__(256) features_table_kernel(const LevelItem* __
     if (task >= n_tiles) return;
     const Tile tl = tiles[task];
     const LevelItem& it = items[tl.item];
-    features_strip<FEAT, true>(it.pyr, it.w, it.h, it.pitch, it.hog, it.lbp, tl.ty, tl.tx, clip, eps, sm, wave);
+    features_strip<FEAT, true>(it.pyr, it.w, it.h, it.pitch, it.hog, it.hog16, it.lbp, tl.ty, tl.tx, clip, eps, sm,
+                               wave);
 }
 
 // Algorithm 1 on its own: one thread per pixel (used to check the codes).

@@ -23,10 +23,12 @@ __global__ void zero_kernel(int32_t* p, int n) {
 
 __global__ void __launch_bounds__(256) compact_kernel(const LevelItem* __restrict__ items,
                                                       const Tile* __restrict__ tiles, int n_models,
-                                                      const double* __restrict__ thresholds,
+                                                      const double* __restrict__ thresholds, float margin,
                                                       int32_t* __restrict__ counters,
                                                       float* __restrict__ cand_score,
-                                                      int4* __restrict__ cand_key) {
+                                                      int4* __restrict__ cand_key, double* __restrict__ cand_s64,
+                                                      int32_t* __restrict__ near_count,
+                                                      int4* __restrict__ near_key) {
     const Tile tl = tiles[blockIdx.x];
     const LevelItem& it = items[tl.item];
     const int n = it.nx * it.ny;
@@ -42,13 +44,19 @@ __global__ void __launch_bounds__(256) compact_kernel(const LevelItem* __restric
             bm = m;
         }
     }
-    if ((double)best > thresholds[it.frame]) {
+    const double thr = thresholds[it.frame];
+    const int i = q / it.nx;
+    if (margin > 0.0f && fabs((double)best - thr) < (double)margin) {
+        // too close to call in this precision: rescored in FP64
+        const int pos = atomicAdd(&near_count[it.frame], 1);
+        if (pos < MAX_NEAR) near_key[(size_t)it.frame * MAX_NEAR + pos] = make_int4(it.level, i, q - i * it.nx, bm);
+    } else if ((double)best > thr) {
         const int pos = atomicAdd(&counters[it.frame], 1);
         if (pos < PD_MAX_CANDIDATES) {
             const size_t o = (size_t)it.frame * PD_MAX_CANDIDATES + pos;
-            const int i = q / it.nx;
             cand_score[o] = best;
             cand_key[o] = make_int4(it.level, i, q - i * it.nx, bm);
+            if (cand_s64) cand_s64[o] = __longlong_as_double(0x7ff8000000000000LL);
         }
     }
 }
@@ -95,8 +103,8 @@ __device__ inline bool overlaps(const int4& a, const int4& b) {
 }
 
 __device__ void nms_frame(const NmsGeom& g, int frame, int raw_count, const float* __restrict__ cs,
-                          const int4* __restrict__ ck, pd_box* __restrict__ boxes, int cap,
-                          pd_counts* __restrict__ counts) {
+                          const int4* __restrict__ ck, const double* __restrict__ c64, int rescored,
+                          pd_box* __restrict__ boxes, int cap, pd_counts* __restrict__ counts) {
     extern __shared__ __align__(16) uint8_t smem_raw[];
     NmsSmem& sm = *reinterpret_cast<NmsSmem*>(smem_raw);
     const int t = threadIdx.x;
@@ -183,7 +191,7 @@ __device__ void nms_frame(const NmsGeom& g, int frame, int raw_count, const floa
         b.x1 = bx.z;
         b.y1 = bx.w;
         b.score = cs[src];
-        b.score64 = __longlong_as_double(0x7ff8000000000000LL);
+        b.score64 = c64 ? c64[src] : __longlong_as_double(0x7ff8000000000000LL);
         boxes[(size_t)frame * cap + q] = b;
     }
     if (t == 0) {
@@ -191,7 +199,7 @@ __device__ void nms_frame(const NmsGeom& g, int frame, int raw_count, const floa
         c.candidates = raw_count;
         c.kept = nout;
         c.overflow = (raw_count > PD_MAX_CANDIDATES || K > cap) ? 1 : 0;
-        c.reserved = 0;
+        c.rescored = rescored;
         counts[frame] = c;
     }
 }
@@ -200,17 +208,20 @@ __global__ void __launch_bounds__(256) nms_table_kernel(const NmsGeom* __restric
                                                         const int32_t* __restrict__ counters,
                                                         const float* __restrict__ cand_score,
                                                         const int4* __restrict__ cand_key,
+                                                        const double* __restrict__ cand_s64,
+                                                        const int32_t* __restrict__ near_count,
                                                         pd_box* __restrict__ boxes, int cap,
                                                         pd_counts* __restrict__ counts) {
     const int f = blockIdx.x;
     const size_t o = (size_t)f * PD_MAX_CANDIDATES;
-    nms_frame(geoms[f], f, counters[f], cand_score + o, cand_key + o, boxes, cap, counts);
+    nms_frame(geoms[f], f, counters[f], cand_score + o, cand_key + o, cand_s64 ? cand_s64 + o : nullptr,
+              near_count ? near_count[f] : 0, boxes, cap, counts);
 }
 
 __global__ void __launch_bounds__(256) nms_single_kernel(NmsGeom g, int n, const float* __restrict__ cs,
                                                          const int4* __restrict__ ck, pd_box* __restrict__ boxes,
                                                          int cap, pd_counts* __restrict__ counts) {
-    nms_frame(g, 0, n, cs, ck, boxes, cap, counts);
+    nms_frame(g, 0, n, cs, ck, nullptr, 0, boxes, cap, counts);
 }
 
 constexpr size_t kNmsSmem = sizeof(NmsSmem);
@@ -224,24 +235,32 @@ hipError_t launch_zero_i32(int32_t* p, int n, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_compact_table(const LevelItem* items, const Tile* tiles, int n_tiles, int n_models,
-                                const double* thresholds, int32_t* counters, float* cand_score,
-                                int4* cand_key, hipStream_t s) {
+hipError_t launch_compact_margin(const LevelItem* items, const Tile* tiles, int n_tiles, int n_models,
+                                 const double* thresholds, float margin, int32_t* counters, float* cand_score,
+                                 int4* cand_key, double* cand_s64, int32_t* near_count, int4* near_key,
+                                 hipStream_t s) {
     if (n_tiles <= 0) return hipSuccess;
-    compact_kernel<<<n_tiles, 256, 0, s>>>(items, tiles, n_models, thresholds, counters, cand_score,
-                                           cand_key);
+    compact_kernel<<<n_tiles, 256, 0, s>>>(items, tiles, n_models, thresholds, margin, counters, cand_score, cand_key,
+                                           cand_s64, near_count, near_key);
     return hipGetLastError();
 }
 
+hipError_t launch_compact_table(const LevelItem* items, const Tile* tiles, int n_tiles, int n_models,
+                                const double* thresholds, int32_t* counters, float* cand_score,
+                                int4* cand_key, hipStream_t s) {
+    return launch_compact_margin(items, tiles, n_tiles, n_models, thresholds, 0.0f, counters, cand_score, cand_key,
+                                 nullptr, nullptr, nullptr, s);
+}
+
 hipError_t launch_nms_table(const NmsGeom* geoms, int n_frames, const int32_t* counters,
-                            const float* cand_score, const int4* cand_key, pd_box* boxes, int cap,
-                            pd_counts* counts, hipStream_t s) {
+                            const float* cand_score, const int4* cand_key, const double* cand_s64,
+                            const int32_t* near_count, pd_box* boxes, int cap, pd_counts* counts, hipStream_t s) {
     if (n_frames <= 0) return hipSuccess;
     static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&nms_table_kernel),
                                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kNmsSmem);
     if (attr != hipSuccess) return attr;
-    nms_table_kernel<<<n_frames, 256, kNmsSmem, s>>>(geoms, counters, cand_score, cand_key, boxes, cap,
-                                                    counts);
+    nms_table_kernel<<<n_frames, 256, kNmsSmem, s>>>(geoms, counters, cand_score, cand_key, cand_s64, near_count,
+                                                    boxes, cap, counts);
     return hipGetLastError();
 }
 

@@ -45,6 +45,9 @@ bool check_params(const pd_params* p) {
         return fail(PD_E_ARG, "clip and eps must be positive"), false;
     if ((p->features & ~(PD_FEAT_HOG | PD_FEAT_LBP)) != 0 || (p->features & (PD_FEAT_HOG | PD_FEAT_LBP)) == 0)
         return fail(PD_E_ARG, "unknown feature flags 0x%x", p->features), false;
+    if (p->precision != PD_PREC_F32 && p->precision != PD_PREC_BF16)
+        return fail(PD_E_ARG, "unknown precision %d", p->precision), false;
+    if (!(p->margin >= 0.0f) || !std::isfinite(p->margin)) return fail(PD_E_ARG, "margin must be >= 0"), false;
     return true;
 }
 
@@ -161,7 +164,9 @@ void item_geometry(LevelItem& it, int w, int h) {
 struct DetectLayout {
     int n_items = 0;
     int n_rs = 0, n_ft = 0, n_sc = 0, n_cp = 0;
-    int64_t off_items = 0, off_tiles = 0, off_geoms = 0, off_counters = 0, off_cscore = 0, off_ckey = 0;
+    bool bf16 = false;
+    int64_t off_items = 0, off_tiles = 0, off_geoms = 0, off_first = 0, off_counters = 0, off_cscore = 0,
+            off_ckey = 0, off_c64 = 0, off_near_count = 0, off_near_key = 0, off_packed = 0;
     int64_t off_data = 0, total = 0;
     int64_t table_bytes = 0;  // bytes uploaded from the host (items .. geoms)
     std::vector<int> level_count;         // per frame
@@ -171,6 +176,7 @@ struct DetectLayout {
 
 bool plan_detect(const pd_frame* frames, int n_frames, const pd_params* p, int n_models, DetectLayout& L) {
     L = DetectLayout();
+    L.bf16 = p->precision == PD_PREC_BF16;
     L.level_count.resize(n_frames);
     int wh[PD_MAX_LEVELS][2];
     int64_t data = 0;
@@ -190,14 +196,15 @@ bool plan_detect(const pd_frame* frames, int n_frames, const pd_params* p, int n
             L.pyr_off.push_back(data);
             data = align_up(data + (int64_t)align_up(it.w, 16) * it.h, kAlign);
             L.hog_off.push_back(data);
-            data = align_up(data + (int64_t)PD_HOG_BLOCK * it.hb * it.wb * 4, kAlign);
+            data = align_up(data + (int64_t)PD_HOG_BLOCK * it.hb * it.wb * (L.bf16 ? 2 : 4), kAlign);
             L.lbp_off.push_back(data);
             data = align_up(data + (int64_t)PD_LBP_BINS * it.hc * it.wc, kAlign);
             L.sc_off.push_back(data);
             data = align_up(data + (int64_t)n_models * it.ny * it.nx * 4, kAlign);
             L.n_rs += resize_tiles_x(it.w) * resize_tiles_y(it.h);  // upper bound
             L.n_ft += feat_tiles_x(it.wc) * feat_tiles_y(it.hc);
-            L.n_sc += score_tiles_x(it.nx) * score_tiles_y(it.ny) * n_models;
+            L.n_sc += L.bf16 ? ceil_div(it.nx, MF_TILE_C) * ceil_div(it.ny, MF_TILE_R)
+                             : score_tiles_x(it.nx) * score_tiles_y(it.ny) * n_models;
             L.n_cp += ceil_div(it.nx * it.ny, CP_N);
             ++L.n_items;
         }
@@ -209,13 +216,25 @@ bool plan_detect(const pd_frame* frames, int n_frames, const pd_params* p, int n
     o = align_up(o + (int64_t)(L.n_rs + L.n_ft + L.n_sc + L.n_cp) * sizeof(Tile), kAlign);
     L.off_geoms = o;
     o = align_up(o + (int64_t)n_frames * sizeof(NmsGeom), kAlign);
+    L.off_first = o;
+    o = align_up(o + (int64_t)n_frames * 4, kAlign);
     L.table_bytes = o;
-    L.off_counters = o;
+    L.off_counters = o;  // candidate counters, then near counters (zeroed together)
+    o = align_up(o + (int64_t)n_frames * 4, kAlign);
+    L.off_near_count = o;
     o = align_up(o + (int64_t)n_frames * 4, kAlign);
     L.off_cscore = o;
     o = align_up(o + (int64_t)n_frames * PD_MAX_CANDIDATES * 4, kAlign);
     L.off_ckey = o;
     o = align_up(o + (int64_t)n_frames * PD_MAX_CANDIDATES * 16, kAlign);
+    if (L.bf16) {
+        L.off_c64 = o;
+        o = align_up(o + (int64_t)n_frames * PD_MAX_CANDIDATES * 8, kAlign);
+        L.off_near_key = o;
+        o = align_up(o + (int64_t)n_frames * MAX_NEAR * 16, kAlign);
+        L.off_packed = o;
+        o = align_up(o + packed_weight_elems() * 2, kAlign);
+    }
     L.off_data = o;
     L.total = o + data;
     return true;
@@ -306,6 +325,8 @@ void pd_params_default(pd_params* p) {
     p->clip = 0.2f;
     p->eps = 1e-3f;
     p->features = PD_FEAT_HOG | PD_FEAT_LBP;
+    p->precision = PD_PREC_F32;
+    p->margin = 0.05f;
 }
 
 const char* pd_strerror(int code) {
@@ -375,18 +396,20 @@ int pd_lbp_codes(const uint8_t* lvl, int w, int h, int pitch, uint8_t* codes, in
 }
 
 int pd_features(const uint8_t* lvl, int w, int h, int pitch, const pd_params* params, float* blocks,
-                uint8_t* cell_hist, void* stream) {
+                uint16_t* blocks_bf16, uint8_t* cell_hist, void* stream) {
     if (int rc = check_image(lvl, w, h, pitch, "level")) return rc;
     if (!check_params(params)) return PD_E_ARG;
+    if (blocks && blocks_bf16) return fail(PD_E_ARG, "give either FP32 or BF16 HOG output, not both");
     int feat = 0;
-    if (blocks) feat |= PD_FEAT_HOG;
+    if (blocks || blocks_bf16) feat |= PD_FEAT_HOG;
     if (cell_hist) feat |= PD_FEAT_LBP;
-    if (!feat) return fail(PD_E_ARG, "both outputs are NULL");
+    if (!feat) return fail(PD_E_ARG, "all outputs are NULL");
     LevelItem it{};
     item_geometry(it, w, h);
     it.pyr = const_cast<uint8_t*>(lvl);
     it.pitch = pitch;
     it.hog = blocks;
+    it.hog16 = blocks_bf16;
     it.lbp = cell_hist;
     if (it.hc < 1 || it.wc < 1) return PD_OK;  // no whole cell: nothing to write
     if ((feat & PD_FEAT_HOG) && (it.hb < 1 || it.wb < 1)) feat &= ~PD_FEAT_HOG;
@@ -399,12 +422,12 @@ int pd_lbp(const uint8_t* lvl, int w, int h, int pitch, uint8_t* cell_hist, void
     if (!cell_hist) return fail(PD_E_ARG, "cell_hist is NULL");
     pd_params p;
     pd_params_default(&p);
-    return pd_features(lvl, w, h, pitch, &p, nullptr, cell_hist, stream);
+    return pd_features(lvl, w, h, pitch, &p, nullptr, nullptr, cell_hist, stream);
 }
 
 int pd_hog(const uint8_t* lvl, int w, int h, int pitch, const pd_params* params, float* blocks, void* stream) {
     if (!blocks) return fail(PD_E_ARG, "blocks is NULL");
-    return pd_features(lvl, w, h, pitch, params, blocks, nullptr, stream);
+    return pd_features(lvl, w, h, pitch, params, blocks, nullptr, nullptr, stream);
 }
 
 int pd_score_windows(const float* blocks, const uint8_t* cells, int cells_x, int cells_y, const float* weights,
@@ -424,10 +447,37 @@ int pd_score_windows(const float* blocks, const uint8_t* cells, int cells_x, int
                       "score launch");
 }
 
+int64_t pd_packed_models_bytes(void) { return packed_weight_elems() * 2; }
+
+int pd_pack_models(const float* weights, int n_models, uint16_t* packed, void* stream) {
+    if (n_models < 1 || n_models > PD_MAX_MODELS_BF16)
+        return fail(PD_E_SIZE, "n_models %d outside [1, %d]", n_models, PD_MAX_MODELS_BF16);
+    if (!weights || !packed) return fail(PD_E_ARG, "NULL pointer argument");
+    return hip_status(launch_pack_weights(weights, n_models, packed, (hipStream_t)stream), "pack launch");
+}
+
+int pd_score_windows_bf16(const uint16_t* blocks_bf16, const uint8_t* cells, int cells_x, int cells_y,
+                          const uint16_t* packed, const float* bias, int n_models, float* scores, void* stream) {
+    if (cells_x < PD_WIN_CELLS_X || cells_y < PD_WIN_CELLS_Y || cells_x > PD_MAX_DIM / PD_CELL ||
+        cells_y > PD_MAX_DIM / PD_CELL)
+        return fail(PD_E_SIZE, "cell grid %dx%d cannot hold a window", cells_x, cells_y);
+    if (n_models < 1 || n_models > PD_MAX_MODELS_BF16)
+        return fail(PD_E_SIZE, "n_models %d outside [1, %d]", n_models, PD_MAX_MODELS_BF16);
+    if (!blocks_bf16 || !cells || !packed || !bias || !scores) return fail(PD_E_ARG, "NULL pointer argument");
+    LevelItem it{};
+    item_geometry(it, cells_x * PD_CELL, cells_y * PD_CELL);
+    it.hog16 = const_cast<uint16_t*>(blocks_bf16);
+    it.lbp = const_cast<uint8_t*>(cells);
+    it.scores = scores;
+    return hip_status(launch_mfma_single(it, packed, bias, n_models, PD_FEAT_HOG | PD_FEAT_LBP, (hipStream_t)stream),
+                      "bf16 score launch");
+}
+
 int64_t pd_detect_workspace_bytes(const pd_frame* frames, int n_frames, const pd_params* params, int n_models) {
     if (!check_params(params)) return PD_E_ARG;
     if (!frames || n_frames < 1) return fail(PD_E_ARG, "frames is NULL or n_frames < 1");
-    if (n_models < 1 || n_models > PD_MAX_MODELS) return fail(PD_E_SIZE, "n_models outside [1, %d]", PD_MAX_MODELS);
+    const int max_m = params->precision == PD_PREC_BF16 ? PD_MAX_MODELS_BF16 : PD_MAX_MODELS;
+    if (n_models < 1 || n_models > max_m) return fail(PD_E_SIZE, "n_models outside [1, %d]", max_m);
     DetectLayout L;
     if (!plan_detect(frames, n_frames, params, n_models, L)) return PD_E_SIZE;
     return L.total;
@@ -438,7 +488,8 @@ int pd_detect(const pd_frame* frames, int n_frames, const float* weights, const 
               pd_box* boxes, int cap, pd_counts* counts, void* stream) {
     if (!check_params(params)) return PD_E_ARG;
     if (!frames || n_frames < 1) return fail(PD_E_ARG, "frames is NULL or n_frames < 1");
-    if (n_models < 1 || n_models > PD_MAX_MODELS) return fail(PD_E_SIZE, "n_models outside [1, %d]", PD_MAX_MODELS);
+    const int max_m = params->precision == PD_PREC_BF16 ? PD_MAX_MODELS_BF16 : PD_MAX_MODELS;
+    if (n_models < 1 || n_models > max_m) return fail(PD_E_SIZE, "n_models outside [1, %d]", max_m);
     if (!weights || !bias || !thresholds || !counts || (cap > 0 && !boxes) || cap < 0)
         return fail(PD_E_ARG, "NULL pointer argument");
     for (int f = 0; f < n_frames; ++f) {
@@ -477,6 +528,7 @@ int pd_detect(const pd_frame* frames, int n_frames, const float* weights, const 
     LevelItem* items = reinterpret_cast<LevelItem*>(stage + L.off_items);
     Tile* tiles = reinterpret_cast<Tile*>(stage + L.off_tiles);
     NmsGeom* geoms = reinterpret_cast<NmsGeom*>(stage + L.off_geoms);
+    int32_t* first = reinterpret_cast<int32_t*>(stage + L.off_first);
     Tile* t_rs = tiles;
     Tile* t_ft = t_rs + L.n_rs;
     Tile* t_sc = t_ft + L.n_ft;
@@ -484,6 +536,7 @@ int pd_detect(const pd_frame* frames, int n_frames, const float* weights, const 
     int q = 0, nrs = 0, nft = 0, nsc = 0, ncp = 0;
     for (int f = 0; f < n_frames; ++f) {
         geoms[f].n_levels = L.level_count[f];
+        first[f] = q;
         for (int k = 0; k < L.level_count[f]; ++k, ++q) {
             LevelItem& it = items[q];
             item_geometry(it, L.sizes[2 * q], L.sizes[2 * q + 1]);
@@ -499,7 +552,8 @@ int pd_detect(const pd_frame* frames, int n_frames, const float* weights, const 
                 it.pyr = data + L.pyr_off[q];
                 it.pitch = (int)align_up(it.w, 16);
             }
-            it.hog = reinterpret_cast<float*>(data + L.hog_off[q]);
+            if (L.bf16) it.hog16 = reinterpret_cast<uint16_t*>(data + L.hog_off[q]);
+            else it.hog = reinterpret_cast<float*>(data + L.hog_off[q]);
             it.lbp = data + L.lbp_off[q];
             it.scores = reinterpret_cast<float*>(data + L.sc_off[q]);
             it.frame = f;
@@ -511,18 +565,28 @@ int pd_detect(const pd_frame* frames, int n_frames, const float* weights, const 
                     for (int tx = 0; tx < resize_tiles_x(it.w); ++tx) t_rs[nrs++] = Tile{q, ty, tx, 0};
             for (int ty = 0; ty < feat_tiles_y(it.hc); ++ty)
                 for (int tx = 0; tx < feat_tiles_x(it.wc); ++tx) t_ft[nft++] = Tile{q, ty, tx, 0};
-            for (int m = 0; m < n_models; ++m)
-                for (int ty = 0; ty < score_tiles_y(it.ny); ++ty)
-                    for (int tx = 0; tx < score_tiles_x(it.nx); ++tx) t_sc[nsc++] = Tile{q, ty, tx, m};
+            if (L.bf16) {
+                for (int ty = 0; ty < ceil_div(it.ny, MF_TILE_R); ++ty)
+                    for (int tx = 0; tx < ceil_div(it.nx, MF_TILE_C); ++tx) t_sc[nsc++] = Tile{q, ty, tx, 0};
+            } else {
+                for (int m = 0; m < n_models; ++m)
+                    for (int ty = 0; ty < score_tiles_y(it.ny); ++ty)
+                        for (int tx = 0; tx < score_tiles_x(it.nx); ++tx) t_sc[nsc++] = Tile{q, ty, tx, m};
+            }
             for (int c = 0; c < ceil_div(it.nx * it.ny, CP_N); ++c) t_cp[ncp++] = Tile{q, 0, c, 0};
         }
     }
     const LevelItem* d_items = reinterpret_cast<const LevelItem*>(ws + L.off_items);
     const Tile* d_tiles = reinterpret_cast<const Tile*>(ws + L.off_tiles);
     const NmsGeom* d_geoms = reinterpret_cast<const NmsGeom*>(ws + L.off_geoms);
+    const int32_t* d_first = reinterpret_cast<const int32_t*>(ws + L.off_first);
     int32_t* d_counters = reinterpret_cast<int32_t*>(ws + L.off_counters);
+    int32_t* d_near_count = reinterpret_cast<int32_t*>(ws + L.off_near_count);
     float* d_cscore = reinterpret_cast<float*>(ws + L.off_cscore);
     int4* d_ckey = reinterpret_cast<int4*>(ws + L.off_ckey);
+    double* d_c64 = L.bf16 ? reinterpret_cast<double*>(ws + L.off_c64) : nullptr;
+    int4* d_near_key = L.bf16 ? reinterpret_cast<int4*>(ws + L.off_near_key) : nullptr;
+    uint16_t* d_packed = L.bf16 ? reinterpret_cast<uint16_t*>(ws + L.off_packed) : nullptr;
 
     int rc;
     StageMarks marks(g_prof.on);
@@ -533,7 +597,10 @@ int pd_detect(const pd_frame* frames, int n_frames, const float* weights, const 
     if ((rc = hip_status(hipEventRecord(slot.ev, s), "staging record"))) return rc;
     slot.pending = true;
     marks.mark(PD_STAGE_ZERO, s);
-    if ((rc = hip_status(launch_zero_i32(d_counters, n_frames, s), "zero"))) return rc;
+    // candidate and near counters are adjacent: one clear
+    if ((rc = hip_status(launch_zero_i32(d_counters, (int)((L.off_cscore - L.off_counters) / 4), s), "zero")))
+        return rc;
+    if (L.bf16 && (rc = hip_status(launch_pack_weights(weights, n_models, d_packed, s), "pack"))) return rc;
     marks.mark(PD_STAGE_RESIZE, s);
     if ((rc = hip_status(launch_resize_table(d_items, d_tiles, nrs, s), "resize"))) return rc;
     marks.mark(PD_STAGE_FEATURES, s);
@@ -542,20 +609,63 @@ int pd_detect(const pd_frame* frames, int n_frames, const float* weights, const 
                          "features")))
         return rc;
     marks.mark(PD_STAGE_SCORE, s);
-    if ((rc = hip_status(launch_score_table(d_items, d_tiles + L.n_rs + L.n_ft, L.n_sc, weights, bias, n_models,
-                                            params->features, s),
-                         "score")))
+    if (L.bf16) {
+        if ((rc = hip_status(launch_mfma_table(d_items, d_tiles + L.n_rs + L.n_ft, L.n_sc, d_packed, bias, n_models,
+                                               params->features, s),
+                             "bf16 score")))
+            return rc;
+    } else if ((rc = hip_status(launch_score_table(d_items, d_tiles + L.n_rs + L.n_ft, L.n_sc, weights, bias,
+                                                   n_models, params->features, s),
+                                "score"))) {
         return rc;
+    }
     marks.mark(PD_STAGE_COMPACT, s);
-    if ((rc = hip_status(launch_compact_table(d_items, d_tiles + L.n_rs + L.n_ft + L.n_sc, L.n_cp, n_models,
-                                              thresholds, d_counters, d_cscore, d_ckey, s),
+    if ((rc = hip_status(launch_compact_margin(d_items, d_tiles + L.n_rs + L.n_ft + L.n_sc, L.n_cp, n_models,
+                                               thresholds, L.bf16 ? params->margin : 0.0f, d_counters, d_cscore,
+                                               d_ckey, d_c64, d_near_count, d_near_key, s),
                          "compact")))
         return rc;
+    if (L.bf16 && (rc = hip_status(launch_rescore64(d_items, d_first, n_frames, d_near_count, d_near_key, weights,
+                                                    bias, n_models, params->clip, params->eps, thresholds,
+                                                    d_counters, d_cscore, d_ckey, d_c64, s),
+                                   "rescore")))
+        return rc;
     marks.mark(PD_STAGE_NMS, s);
-    rc = hip_status(launch_nms_table(d_geoms, n_frames, d_counters, d_cscore, d_ckey, boxes, cap, counts, s), "nms");
+    rc = hip_status(launch_nms_table(d_geoms, n_frames, d_counters, d_cscore, d_ckey, d_c64,
+                                     L.bf16 ? d_near_count : nullptr, boxes, cap, counts, s),
+                    "nms");
     marks.mark(PD_N_STAGES, s);
     marks.commit();
     return rc;
+}
+
+int pd_detect_candidates(const pd_frame* frames, int n_frames, const pd_params* params, int n_models,
+                         const void* workspace, int64_t workspace_bytes, int frame, float* cand_score,
+                         int32_t* cand_key, double* cand_s64, int cap, void* stream) {
+    if (!check_params(params)) return PD_E_ARG;
+    if (!frames || n_frames < 1 || frame < 0 || frame >= n_frames) return fail(PD_E_ARG, "bad frame index");
+    if (cap < 0 || cap > PD_MAX_CANDIDATES) return fail(PD_E_SIZE, "cap outside [0, %d]", PD_MAX_CANDIDATES);
+    if (!workspace || (cap > 0 && (!cand_score || !cand_key))) return fail(PD_E_ARG, "NULL pointer argument");
+    DetectLayout L;
+    if (!plan_detect(frames, n_frames, params, n_models, L)) return PD_E_SIZE;
+    if (workspace_bytes < L.total) return fail(PD_E_WORKSPACE, "workspace smaller than pd_detect's");
+    if (cand_s64 && !L.bf16) return fail(PD_E_ARG, "FP64 scores exist only with PD_PREC_BF16");
+    const uint8_t* ws = static_cast<const uint8_t*>(workspace);
+    hipStream_t s = (hipStream_t)stream;
+    const size_t o = (size_t)frame * PD_MAX_CANDIDATES;
+    int rc;
+    if ((rc = hip_status(hipMemcpyAsync(cand_score, ws + L.off_cscore + o * 4, (size_t)cap * 4,
+                                        hipMemcpyDeviceToDevice, s),
+                         "copy")))
+        return rc;
+    if ((rc = hip_status(hipMemcpyAsync(cand_key, ws + L.off_ckey + o * 16, (size_t)cap * 16,
+                                        hipMemcpyDeviceToDevice, s),
+                         "copy")))
+        return rc;
+    if (cand_s64)
+        return hip_status(hipMemcpyAsync(cand_s64, ws + L.off_c64 + o * 8, (size_t)cap * 8, hipMemcpyDeviceToDevice, s),
+                          "copy");
+    return PD_OK;
 }
 
 int pd_nms(const float* cand_score, const int32_t* cand_key, int n, const int32_t* level_wh, int n_levels,

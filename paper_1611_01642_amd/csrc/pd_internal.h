@@ -14,7 +14,8 @@ namespace pd {
 struct LevelItem {
     const uint8_t* src;   // level-0 image of the frame
     uint8_t* pyr;         // this level inside the pyramid buffer
-    float* hog;           // [36][hb][wb]
+    float* hog;           // [36][hb][wb] FP32, or NULL
+    uint16_t* hog16;      // [36][hb][wb] BF16, or NULL
     uint8_t* lbp;         // [59][hc][wc]
     float* scores;        // [n_models][ny][nx]
     int32_t src_w, src_h, src_pitch;
@@ -53,8 +54,20 @@ constexpr int SC_W = 64;
 constexpr int SC_WAVES = 4;  // waves (independent tiles) per workgroup
 // compaction: windows per workgroup
 constexpr int CP_N = 256;
+// FP64 rescoring: near-threshold windows kept per frame
+constexpr int MAX_NEAR = 1024;
+// MFMA scoring tile: window rows x window columns
+constexpr int MF_TILE_R = 4;
+constexpr int MF_TILE_C = 64;
 
 __host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+// FP32 -> BF16, round to nearest even (finite inputs).
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
 
 __host__ __device__ inline int resize_tiles_x(int w) { return ceil_div(w, RS_TX); }
 __host__ __device__ inline int resize_tiles_y(int h) { return ceil_div(h, RS_TY); }
@@ -80,12 +93,27 @@ hipError_t launch_score_table(const LevelItem* items, const Tile* tiles, int n_t
                               const float* w, const float* bias, int n_models, int features,
                               hipStream_t s);
 
+int64_t packed_weight_elems();
+hipError_t launch_pack_weights(const float* w, int n_models, uint16_t* out, hipStream_t s);
+hipError_t launch_mfma_single(const LevelItem& it, const uint16_t* wpk, const float* bias, int n_models, int features,
+                              hipStream_t s);
+hipError_t launch_mfma_table(const LevelItem* items, const Tile* tiles, int n_tiles, const uint16_t* wpk,
+                             const float* bias, int n_models, int features, hipStream_t s);
+// windows with |score - threshold| < margin go to the near list (margin <= 0: none)
+hipError_t launch_compact_margin(const LevelItem* items, const Tile* tiles, int n_tiles, int n_models,
+                                 const double* thresholds, float margin, int32_t* counters, float* cand_score,
+                                 int4* cand_key, double* cand_s64, int32_t* near_count, int4* near_key,
+                                 hipStream_t s);
+hipError_t launch_rescore64(const LevelItem* items, const int32_t* frame_first_item, int n_frames,
+                            const int32_t* near_count, const int4* near_key, const float* weights,
+                            const float* bias, int n_models, float clip, float eps, const double* thresholds,
+                            int32_t* counters, float* cand_score, int4* cand_key, double* cand_s64, hipStream_t s);
 hipError_t launch_compact_table(const LevelItem* items, const Tile* tiles, int n_tiles, int n_models,
                                 const double* thresholds, int32_t* counters, float* cand_score,
                                 int4* cand_key, hipStream_t s);
 hipError_t launch_nms_table(const NmsGeom* geoms, int n_frames, const int32_t* counters,
-                            const float* cand_score, const int4* cand_key, pd_box* boxes, int cap,
-                            pd_counts* counts, hipStream_t s);
+                            const float* cand_score, const int4* cand_key, const double* cand_s64,
+                            const int32_t* near_count, pd_box* boxes, int cap, pd_counts* counts, hipStream_t s);
 hipError_t launch_nms_single(const NmsGeom& g, int n, const float* cand_score, const int4* cand_key,
                              pd_box* boxes, int cap, pd_counts* counts, hipStream_t s);
 hipError_t launch_zero_i32(int32_t* p, int n, hipStream_t s);

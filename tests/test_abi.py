@@ -78,7 +78,18 @@ def test_argument_errors_enqueue_nothing():
     assert L.pd_lbp(fake, 64, 64, 64, nil, nil) == pd.E_ARG
     assert L.pd_lbp_codes(fake, 20000, 64, 20000, fake, 20000, nil) == pd.E_SIZE
     bad = pd.params(features=4)
-    assert L.pd_features(fake, 64, 64, 64, ctypes.byref(bad), fake, fake, nil) == pd.E_ARG
+    assert L.pd_features(fake, 64, 64, 64, ctypes.byref(bad), fake, nil, fake, nil) == pd.E_ARG
+    ok = pd.params()
+    assert L.pd_features(fake, 64, 64, 64, ctypes.byref(ok), fake, fake, fake, nil) == pd.E_ARG  # FP32 and BF16
+    assert L.pd_features(fake, 64, 64, 64, ctypes.byref(ok), nil, nil, nil, nil) == pd.E_ARG
+    bad = pd.params(precision=7)
+    assert L.pd_features(fake, 64, 64, 64, ctypes.byref(bad), fake, nil, fake, nil) == pd.E_ARG
+    bad = pd.params(margin=-1.0)
+    assert L.pd_features(fake, 64, 64, 64, ctypes.byref(bad), fake, nil, fake, nil) == pd.E_ARG
+    assert L.pd_pack_models(fake, 9, fake, nil) == pd.E_SIZE
+    assert L.pd_score_windows_bf16(fake, fake, 8, 16, fake, fake, 9, fake, nil) == pd.E_SIZE
+    assert L.pd_score_windows_bf16(fake, fake, 7, 16, fake, fake, 1, fake, nil) == pd.E_SIZE
+    assert L.pd_packed_models_bytes() == (15 * 8 + 16 * 15) * 16 * 32 * 2
     assert L.pd_score_windows(fake, fake, 7, 16, fake, fake, 1, fake, nil) == pd.E_SIZE
     assert L.pd_score_windows(fake, fake, 8, 16, fake, fake, 0, fake, nil) == pd.E_SIZE
     assert L.pd_score_windows(fake, fake, 8, 16, fake, fake, 17, fake, nil) == pd.E_SIZE
@@ -87,6 +98,16 @@ def test_argument_errors_enqueue_nothing():
     assert L.pd_nms(fake, fake, 4097, wh, 1, fake, 10, fake, nil) == pd.E_SIZE
     assert L.pd_nms(fake, fake, 10, wh, 0, fake, 10, fake, nil) == pd.E_SIZE
     assert L.pd_build_pyramid(fake, 100, 100, 100, nil, 65, fake, nil) == pd.E_SIZE
+
+
+def test_bf16_workspace_and_model_limit():
+    prm = pd.params(precision=pd.PREC_BF16)
+    assert pd.workspace_bytes([(1242, 375)], 8, prm) > 0
+    L = pd.lib()
+    arr = (pd.Frame * 1)()
+    arr[0].w, arr[0].h = 1242, 375
+    assert L.pd_detect_workspace_bytes(arr, 1, ctypes.byref(prm), 9) == pd.E_SIZE
+    assert L.pd_detect_workspace_bytes(arr, 1, ctypes.byref(pd.params()), 9) > 0
 
 
 def test_detect_workspace_and_errors():
