@@ -99,6 +99,44 @@ def measured_traffic(kernel, batch):
     return rec["read_bytes"] + rec["write_bytes"]
 
 
+def calibrate_threshold(pd, torch, calib, wts, bias, prm):
+    """Midpoint of the 99th-percentile pair of one calibration frame's window
+    scores (max over models), computed on the GPU path before timing."""
+    _, _, views = pd.build_pyramid(calib, prm)
+    bf = prm.precision == pd.PREC_BF16
+    packed = pd.pack_models(wts) if bf else None
+    sc = []
+    for v in views:
+        blk, cel = pd.features(v.contiguous(), prm, bf16=bf)
+        s = pd.score_windows_bf16(blk, cel, packed, bias, int(wts.shape[0])) if bf else \
+            pd.score_windows(blk, cel, wts, bias)
+        sc.append(s.max(dim=0).values.flatten())
+    s = torch.sort(torch.cat(sc).double(), descending=True).values.cpu().numpy()
+    k = math.ceil(0.01 * s.size)
+    return 0.5 * (s[k - 1] + s[k])
+
+
+def time_detect(pd, torch, frames, wts, bias, prm, thr_value, steps, warmup):
+    """(seconds for `steps` pd_detect calls, per-stage ms per call, counts)."""
+    B = len(frames)
+    thr = torch.full((B,), thr_value, dtype=torch.float64, device=frames[0].device)
+    det = pd.Detector(frames, wts, bias, prm, cap=1024)
+    for _ in range(warmup):
+        det.run(thr)
+    torch.cuda.synchronize()
+    pd.profile_enable(True)
+    pd.profile_read(reset=True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        det.run(thr)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    stage_ms, calls = pd.profile_read(reset=True)
+    pd.profile_enable(False)
+    _, counts = det.results()
+    return elapsed, {k: v / max(calls, 1) for k, v in stage_ms.items()}, counts
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -107,6 +145,7 @@ def main():
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--no-latency", action="store_true")
+    ap.add_argument("--no-bf16", action="store_true", help="skip the BF16 MFMA legs")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after timing, run one 256 MiB device-to-device copy (scales HBM byte counters)")
     args = ap.parse_args()
@@ -224,6 +263,24 @@ def main():
         "detections_per_frame": round(float(np.mean([c["kept"] for c in counts])), 2),
         "candidates_per_frame": round(float(np.mean([c["candidates"] for c in counts])), 2),
     }
+    if not args.no_bf16:
+        print("[bench] bf16 legs", file=sys.stderr, flush=True)
+        legs = {}
+        for m in (1, 8):
+            wm = torch.from_numpy(pd_synth.svm_weights(m)).to(dev)
+            bm = torch.from_numpy(pd_synth.svm_bias(m)).to(dev)
+            prm16 = pd.params(precision=pd.PREC_BF16, margin=0.05)
+            t16 = calibrate_threshold(pd, torch, calib, wm, bm, prm16)
+            el, st, cnt = time_detect(pd, torch, frames, wm, bm, prm16, t16, args.steps, args.warmup)
+            sflops = 2.0 * 11332 * windows * B * m
+            legs[f"bf16_{m}model"] = {
+                "value": round(B * args.steps / el, 1), "unit": "frames/s", "ms_per_step": round(1000 * el / args.steps, 4),
+                "stage_ms_per_launch": {k: round(v, 4) for k, v in st.items()},
+                "score_tflops_useful": round(sflops / (st["score"] / 1000) / 1e12, 2),
+                "rescored_per_frame": round(float(np.mean([c["rescored"] for c in cnt])), 2),
+                "candidates_per_frame": round(float(np.mean([c["candidates"] for c in cnt])), 2),
+                "overflow_frames": int(sum(c["overflow"] for c in cnt))}
+        out["bf16"] = legs
     if args.calib_copy:
         src = torch.ones(64 << 20, dtype=torch.int32, device=dev)
         dst = torch.empty_like(src)

@@ -29,6 +29,7 @@ namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int MF_COLS = 64;                       // window columns per tile
 constexpr int MF_ROWS = 4;                        // window rows per tile (one per wave)
@@ -87,23 +88,69 @@ __global__ void pack_weights_kernel(const float* __restrict__ w, int n_models, u
 }
 
 // ---- scoring -----------------------------------------------------------------
-// Stage feature row y (clamped) of the tile into a ring slot, channel-innermost.
+// Feature row y (clamped) of the tile, channel-innermost in a ring slot: the
+// loads are issued into registers first (load_row) and written to LDS after
+// the current step's MFMAs (store_row), so their latency is hidden.
 template <bool HOG>
-__device__ __forceinline__ void stage_row(__bf16* dst, const uint16_t* __restrict__ hog16,
-                                          const uint8_t* __restrict__ lbp, int y, int j0, int hcols, int hrows) {
-    constexpr int SR = HOG ? MF_HOG_SR : MF_LBP_SR;
-    constexpr int NC = HOG ? PD_HOG_BLOCK : PD_LBP_BINS;
-    constexpr int C = HOG ? MF_HOG_C : MF_LBP_C;
+struct RowRegs {
+    static constexpr int SR = HOG ? MF_HOG_SR : MF_LBP_SR;
+    static constexpr int NC = HOG ? PD_HOG_BLOCK : PD_LBP_BINS;
+    static constexpr int N = (SR * NC + 255) / 256;
+    uint16_t v[N];
+};
+
+template <bool HOG>
+__device__ __forceinline__ void load_row(RowRegs<HOG>& r, const uint16_t* __restrict__ hog16,
+                                         const uint8_t* __restrict__ lbp, int y, int j0, int hcols, int hrows) {
+    constexpr int SR = RowRegs<HOG>::SR, NC = RowRegs<HOG>::NC;
     const size_t plane = (size_t)hrows * hcols;
-    const int yy = min(y, hrows - 1);
-    uint16_t* d = reinterpret_cast<uint16_t*>(dst);
-    for (int e = threadIdx.x; e < SR * NC; e += 256) {
+    const size_t row = (size_t)min(y, hrows - 1) * hcols;
+#pragma unroll
+    for (int q = 0; q < RowRegs<HOG>::N; ++q) {  // unconditional loads (clamped index) stay in registers
+        const int e = min((int)threadIdx.x + 256 * q, SR * NC - 1);
         const int c = e / SR, col = e - (e / SR) * SR;
-        const size_t src = c * plane + (size_t)yy * hcols + min(j0 + col, hcols - 1);
-        uint16_t v;
-        if (HOG) v = hog16[src];
-        else v = (uint16_t)(__float_as_uint((float)lbp[src]) >> 16);  // counts <= 64: exact in bf16
-        d[col * C + c] = v;
+        const size_t src = c * plane + row + min(j0 + col, hcols - 1);
+        if (HOG) r.v[q] = hog16[src];
+        else r.v[q] = (uint16_t)(__float_as_uint((float)lbp[src]) >> 16);  // counts <= 64: exact in bf16
+    }
+}
+
+template <bool HOG>
+__device__ __forceinline__ void store_row(const RowRegs<HOG>& r, __bf16* dst) {
+    constexpr int SR = RowRegs<HOG>::SR, NC = RowRegs<HOG>::NC;
+    constexpr int C = HOG ? MF_HOG_C : MF_LBP_C;
+    uint16_t* d = reinterpret_cast<uint16_t*>(dst);
+#pragma unroll
+    for (int q = 0; q < RowRegs<HOG>::N; ++q) {
+        const int e = threadIdx.x + 256 * q;
+        if (e < SR * NC) {
+            const int c = e / SR, col = e - (e / SR) * SR;
+            d[col * C + c] = r.v[q];
+        }
+    }
+}
+
+template <int BSZ>
+struct SliceRegs {
+    static constexpr int N = (BSZ / 8 + 255) / 256;
+    u32x4 v[N];
+};
+
+template <int BSZ>
+__device__ __forceinline__ void load_slice(SliceRegs<BSZ>& r, const uint16_t* __restrict__ src) {
+#pragma unroll
+    for (int q = 0; q < SliceRegs<BSZ>::N; ++q) {
+        const int e = min((int)threadIdx.x + 256 * q, BSZ / 8 - 1);
+        r.v[q] = reinterpret_cast<const u32x4*>(src)[e];
+    }
+}
+
+template <int BSZ>
+__device__ __forceinline__ void store_slice(const SliceRegs<BSZ>& r, __bf16* dst) {
+#pragma unroll
+    for (int q = 0; q < SliceRegs<BSZ>::N; ++q) {
+        const int e = threadIdx.x + 256 * q;
+        if (e < BSZ / 8) reinterpret_cast<u32x4*>(dst)[e] = r.v[q];
     }
 }
 
@@ -125,7 +172,7 @@ __device__ __forceinline__ void mfma_tile(const uint16_t* __restrict__ hog16, co
     for (int e = threadIdx.x; e < (int)(sizeof(MfmaShared) / 4); e += 256) reinterpret_cast<uint32_t*>(&sm)[e] = 0u;
     __syncthreads();
 
-    auto phase = [&](auto hog_tag) {
+    auto phase = [&](auto hog_tag) __attribute__((always_inline)) {
         constexpr bool HOG = decltype(hog_tag)::value;
         constexpr int A = HOG ? PD_WIN_BLOCKS_Y : PD_WIN_CELLS_Y;
         constexpr int T = HOG ? MF_HOG_T : MF_LBP_T;
@@ -134,17 +181,26 @@ __device__ __forceinline__ void mfma_tile(const uint16_t* __restrict__ hog16, co
         const int hrows = HOG ? hb : hc, hcols = HOG ? wb : wc;
         const uint16_t* wsrc = HOG ? wpk : wpk + PD_WIN_BLOCKS_Y * MF_HOG_T * 16 * 32;
         // prologue: rows i0..i0+3 and the slice of offset 0
-        for (int r = 0; r < MF_ROWS; ++r) stage_row<HOG>(sm.ring[r], hog16, lbp, i0 + r, j0, hcols, hrows);
-        for (int e = threadIdx.x; e < BSZ / 8; e += 256)
-            reinterpret_cast<uint4*>(sm.bw[0])[e] = reinterpret_cast<const uint4*>(wsrc)[e];
+        {
+            RowRegs<HOG> rr;
+            for (int r = 0; r < MF_ROWS; ++r) {
+                load_row<HOG>(rr, hog16, lbp, i0 + r, j0, hcols, hrows);
+                store_row<HOG>(rr, sm.ring[r]);
+            }
+            SliceRegs<BSZ> sr;
+            load_slice<BSZ>(sr, wsrc);
+            store_slice<BSZ>(sr, sm.bw[0]);
+        }
         __syncthreads();
         for (int a = 0; a < A; ++a) {
-            // next step's feature row and weight slice (not needed after the last step)
-            if (a + 1 < A) {
-                stage_row<HOG>(sm.ring[(a + MF_ROWS) % MF_RING], hog16, lbp, i0 + a + MF_ROWS, j0, hcols, hrows);
-                const uint4* src = reinterpret_cast<const uint4*>(wsrc + (size_t)(a + 1) * BSZ);
-                uint4* dst = reinterpret_cast<uint4*>(sm.bw[(a + 1) & 1]);
-                for (int e = threadIdx.x; e < BSZ / 8; e += 256) dst[e] = src[e];
+            // loads of the next step's feature row and weight slice are in
+            // flight during this step's MFMAs
+            RowRegs<HOG> nrow;
+            SliceRegs<BSZ> nsl;
+            const bool more = a + 1 < A;
+            if (more) {
+                load_row<HOG>(nrow, hog16, lbp, i0 + a + MF_ROWS, j0, hcols, hrows);
+                load_slice<BSZ>(nsl, wsrc + (size_t)(a + 1) * BSZ);
             }
             const __bf16* row = sm.ring[(a + wave) % MF_RING];
             const __bf16* bw = sm.bw[a & 1];
@@ -156,10 +212,14 @@ __device__ __forceinline__ void mfma_tile(const uint16_t* __restrict__ hog16, co
                     const __bf16* ap = row + (16 * mt + mrow) * C + 32 * t + 8 * kg;
                     const uint2 lo = *reinterpret_cast<const uint2*>(ap);
                     const uint2 hi = *reinterpret_cast<const uint2*>(ap + 4);
-                    const uint4 av = make_uint4(lo.x, lo.y, hi.x, hi.y);
-                    acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(*reinterpret_cast<const bf16x8*>(&av), bf,
-                                                                      acc[mt], 0, 0, 0);
+                    const u32x4 av = {lo.x, lo.y, hi.x, hi.y};
+                    acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av), bf, acc[mt], 0,
+                                                                      0, 0);
                 }
+            }
+            if (more) {  // slots not read in this step (see the ring indexing above)
+                store_row<HOG>(nrow, sm.ring[(a + MF_ROWS) % MF_RING]);
+                store_slice<BSZ>(nsl, sm.bw[(a + 1) & 1]);
             }
             __syncthreads();
         }

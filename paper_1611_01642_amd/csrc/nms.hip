@@ -28,7 +28,7 @@ __global__ void __launch_bounds__(256) compact_kernel(const LevelItem* __restric
                                                       float* __restrict__ cand_score,
                                                       int4* __restrict__ cand_key, double* __restrict__ cand_s64,
                                                       int32_t* __restrict__ near_count,
-                                                      int4* __restrict__ near_key) {
+                                                      int4* __restrict__ near_key, int n_frames) {
     const Tile tl = tiles[blockIdx.x];
     const LevelItem& it = items[tl.item];
     const int n = it.nx * it.ny;
@@ -47,9 +47,14 @@ __global__ void __launch_bounds__(256) compact_kernel(const LevelItem* __restric
     const double thr = thresholds[it.frame];
     const int i = q / it.nx;
     if (margin > 0.0f && fabs((double)best - thr) < (double)margin) {
-        // too close to call in this precision: rescored in FP64
+        // too close to call in this precision: rescored in FP64.  near_count
+        // holds one counter per frame (capped at MAX_NEAR) and, after them,
+        // the length of the dense list of all frames' near windows.
         const int pos = atomicAdd(&near_count[it.frame], 1);
-        if (pos < MAX_NEAR) near_key[(size_t)it.frame * MAX_NEAR + pos] = make_int4(it.level, i, q - i * it.nx, bm);
+        if (pos < MAX_NEAR) {
+            const int g = atomicAdd(&near_count[n_frames], 1);
+            near_key[g] = make_int4(it.frame * PD_MAX_LEVELS + it.level, i, q - i * it.nx, bm);
+        }
     } else if ((double)best > thr) {
         const int pos = atomicAdd(&counters[it.frame], 1);
         if (pos < PD_MAX_CANDIDATES) {
@@ -238,10 +243,10 @@ hipError_t launch_zero_i32(int32_t* p, int n, hipStream_t s) {
 hipError_t launch_compact_margin(const LevelItem* items, const Tile* tiles, int n_tiles, int n_models,
                                  const double* thresholds, float margin, int32_t* counters, float* cand_score,
                                  int4* cand_key, double* cand_s64, int32_t* near_count, int4* near_key,
-                                 hipStream_t s) {
+                                 int n_frames, hipStream_t s) {
     if (n_tiles <= 0) return hipSuccess;
     compact_kernel<<<n_tiles, 256, 0, s>>>(items, tiles, n_models, thresholds, margin, counters, cand_score, cand_key,
-                                           cand_s64, near_count, near_key);
+                                           cand_s64, near_count, near_key, n_frames);
     return hipGetLastError();
 }
 
@@ -249,7 +254,7 @@ hipError_t launch_compact_table(const LevelItem* items, const Tile* tiles, int n
                                 const double* thresholds, int32_t* counters, float* cand_score,
                                 int4* cand_key, hipStream_t s) {
     return launch_compact_margin(items, tiles, n_tiles, n_models, thresholds, 0.0f, counters, cand_score, cand_key,
-                                 nullptr, nullptr, nullptr, s);
+                                 nullptr, nullptr, nullptr, 0, s);
 }
 
 hipError_t launch_nms_table(const NmsGeom* geoms, int n_frames, const int32_t* counters,

@@ -221,8 +221,8 @@ bool plan_detect(const pd_frame* frames, int n_frames, const pd_params* p, int n
     L.table_bytes = o;
     L.off_counters = o;  // candidate counters, then near counters (zeroed together)
     o = align_up(o + (int64_t)n_frames * 4, kAlign);
-    L.off_near_count = o;
-    o = align_up(o + (int64_t)n_frames * 4, kAlign);
+    L.off_near_count = o;  // per-frame near counters + the dense list length
+    o = align_up(o + (int64_t)(n_frames + 1) * 4, kAlign);
     L.off_cscore = o;
     o = align_up(o + (int64_t)n_frames * PD_MAX_CANDIDATES * 4, kAlign);
     L.off_ckey = o;
@@ -622,7 +622,7 @@ int pd_detect(const pd_frame* frames, int n_frames, const float* weights, const 
     marks.mark(PD_STAGE_COMPACT, s);
     if ((rc = hip_status(launch_compact_margin(d_items, d_tiles + L.n_rs + L.n_ft + L.n_sc, L.n_cp, n_models,
                                                thresholds, L.bf16 ? params->margin : 0.0f, d_counters, d_cscore,
-                                               d_ckey, d_c64, d_near_count, d_near_key, s),
+                                               d_ckey, d_c64, d_near_count, d_near_key, n_frames, s),
                          "compact")))
         return rc;
     if (L.bf16 && (rc = hip_status(launch_rescore64(d_items, d_first, n_frames, d_near_count, d_near_key, weights,

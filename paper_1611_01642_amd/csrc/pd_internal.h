@@ -103,7 +103,9 @@ hipError_t launch_mfma_table(const LevelItem* items, const Tile* tiles, int n_ti
 hipError_t launch_compact_margin(const LevelItem* items, const Tile* tiles, int n_tiles, int n_models,
                                  const double* thresholds, float margin, int32_t* counters, float* cand_score,
                                  int4* cand_key, double* cand_s64, int32_t* near_count, int4* near_key,
-                                 hipStream_t s);
+                                 int n_frames, hipStream_t s);
+// near_count[n_frames] is the length of the dense near list near_key
+// (entries: frame * PD_MAX_LEVELS + level, i, j, model)
 hipError_t launch_rescore64(const LevelItem* items, const int32_t* frame_first_item, int n_frames,
                             const int32_t* near_count, const int4* near_key, const float* weights,
                             const float* bias, int n_models, float clip, float eps, const double* thresholds,

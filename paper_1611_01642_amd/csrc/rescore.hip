@@ -46,11 +46,11 @@ __global__ void __launch_bounds__(256) rescore64_kernel(const LevelItem* __restr
                                                         int4* __restrict__ cand_key, double* __restrict__ cand_s64) {
     __shared__ RescoreShared sm;
     const int t = threadIdx.x;
-    for (int q = blockIdx.x; q < n_frames * MAX_NEAR; q += gridDim.x) {
-        const int f = q / MAX_NEAR, idx = q - (q / MAX_NEAR) * MAX_NEAR;
-        if (idx >= min(near_count[f], MAX_NEAR)) continue;  // uniform over the workgroup
+    const int total = near_count[n_frames];  // dense list of every frame's near windows
+    for (int q = blockIdx.x; q < total; q += gridDim.x) {
         const int4 key = near_key[q];
-        const LevelItem& it = items[first_item[f] + key.x];
+        const int f = key.x / PD_MAX_LEVELS, level = key.x - f * PD_MAX_LEVELS;
+        const LevelItem& it = items[first_item[f] + level];
         const int wi = key.y, wj = key.z;
 
         // pixels of the window + one halo pixel, clamped to the level
@@ -161,7 +161,7 @@ __global__ void __launch_bounds__(256) rescore64_kernel(const LevelItem* __restr
                 if (pos < PD_MAX_CANDIDATES) {
                     const size_t o = (size_t)f * PD_MAX_CANDIDATES + pos;
                     cand_score[o] = (float)best;
-                    cand_key[o] = make_int4(key.x, wi, wj, bm);
+                    cand_key[o] = make_int4(level, wi, wj, bm);
                     cand_s64[o] = best;
                 }
             }
@@ -177,7 +177,7 @@ hipError_t launch_rescore64(const LevelItem* items, const int32_t* frame_first_i
                             int n_models, float clip, float eps, const double* thresholds, int32_t* counters,
                             float* cand_score, int4* cand_key, double* cand_s64, hipStream_t s) {
     if (n_frames <= 0) return hipSuccess;
-    const int grid = min(n_frames * MAX_NEAR, 2048);
+    const int grid = min(n_frames * MAX_NEAR, 1024);
     rescore64_kernel<<<grid, 256, 0, s>>>(items, frame_first_item, n_frames, near_count, near_key, weights, bias,
                                          n_models, (double)clip, (double)eps, thresholds, counters, cand_score,
                                          cand_key, cand_s64);
