@@ -198,9 +198,12 @@ int pd_score_windows(const float* blocks, const uint8_t* cells, int cells_x, int
                      float* scores, void* stream);
 
 /*
- * BF16 scoring (Section 4.4, Algorithm 6 as a GEMM of windows x 11332
- * features x models on BF16 MFMA with FP32 accumulation).  Each FP32 weight
- * w is carried as hi = bf16(w) plus lo = bf16(w - hi).
+ * BF16 scoring (Section 4.4, Algorithm 6 as GEMMs on BF16 MFMA with FP32
+ * accumulation).  LBP weights are carried as hi = bf16(w) plus lo =
+ * bf16(w - hi) (LBP counts are exact); HOG weights as hi only (HOG features
+ * are BF16).  One model: per feature row, a GEMM of windows x (b, c) x the
+ * model's row offsets, then diagonal sums; 2..8 models: windows x features x
+ * (models, hi/lo).
  *
  * pd_packed_models_bytes -- bytes of the packed model buffer (any n_models).
  * pd_pack_models -- packs weights (device float [n_models][11332], layout of

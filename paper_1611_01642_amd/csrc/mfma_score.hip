@@ -5,8 +5,9 @@
 // models.  Each model's FP32 weight w is split into two BF16 numbers,
 // hi = bf16(w) and lo = bf16(w - hi), and both become GEMM columns, so the 16
 // columns of one v_mfma_f32_16x16x32_bf16 hold 8 models x {hi, lo}; a model's
-// score is column hi + column lo (the weights then carry ~16 bits).  Features
-// are BF16 (HOG) or exact small integers (LBP counts).
+// score is column hi + column lo.  LBP features are exact small integers, so
+// their weights keep hi + lo (~16 bits); HOG features are BF16, and their
+// weights keep the BF16 part only (the lo column is zero for HOG rows).
 //
 // The K range of a window splits by window row offset a (15 HOG block rows,
 // 16 LBP cell rows).  For a fixed a, window (i, j) reads feature row i + a,
@@ -84,7 +85,9 @@ __global__ void pack_weights_kernel(const float* __restrict__ w, int n_models, u
         }
     }
     const uint16_t hi = f2bf(v);
-    out[e] = n < 8 ? hi : f2bf(v - bf2f(hi));
+    // HOG features are BF16, so the HOG weights carry their BF16 part only;
+    // LBP counts are exact, so LBP weights carry hi + lo
+    out[e] = n < 8 ? hi : (is_hog ? (uint16_t)0 : f2bf(v - bf2f(hi)));
 }
 
 // ---- scoring -----------------------------------------------------------------

@@ -203,8 +203,9 @@ bool plan_detect(const pd_frame* frames, int n_frames, const pd_params* p, int n
             data = align_up(data + (int64_t)n_models * it.ny * it.nx * 4, kAlign);
             L.n_rs += resize_tiles_x(it.w) * resize_tiles_y(it.h);  // upper bound
             L.n_ft += feat_tiles_x(it.wc) * feat_tiles_y(it.hc);
-            L.n_sc += L.bf16 ? ceil_div(it.nx, MF_TILE_C) * ceil_div(it.ny, MF_TILE_R)
-                             : score_tiles_x(it.nx) * score_tiles_y(it.ny) * n_models;
+            L.n_sc += !L.bf16 ? score_tiles_x(it.nx) * score_tiles_y(it.ny) * n_models
+                      : n_models == 1 ? ceil_div(it.nx, RG_TILE_C)
+                                      : ceil_div(it.nx, MF_TILE_C) * ceil_div(it.ny, MF_TILE_R);
             L.n_cp += ceil_div(it.nx * it.ny, CP_N);
             ++L.n_items;
         }
@@ -233,7 +234,7 @@ bool plan_detect(const pd_frame* frames, int n_frames, const pd_params* p, int n
         L.off_near_key = o;
         o = align_up(o + (int64_t)n_frames * MAX_NEAR * 16, kAlign);
         L.off_packed = o;
-        o = align_up(o + packed_weight_elems() * 2, kAlign);
+        o = align_up(o + (packed_weight_elems() + rowgemm_packed_elems()) * 2, kAlign);
     }
     L.off_data = o;
     L.total = o + data;
@@ -447,13 +448,16 @@ int pd_score_windows(const float* blocks, const uint8_t* cells, int cells_x, int
                       "score launch");
 }
 
-int64_t pd_packed_models_bytes(void) { return packed_weight_elems() * 2; }
+int64_t pd_packed_models_bytes(void) { return (packed_weight_elems() + rowgemm_packed_elems()) * 2; }
 
 int pd_pack_models(const float* weights, int n_models, uint16_t* packed, void* stream) {
     if (n_models < 1 || n_models > PD_MAX_MODELS_BF16)
         return fail(PD_E_SIZE, "n_models %d outside [1, %d]", n_models, PD_MAX_MODELS_BF16);
     if (!weights || !packed) return fail(PD_E_ARG, "NULL pointer argument");
-    return hip_status(launch_pack_weights(weights, n_models, packed, (hipStream_t)stream), "pack launch");
+    if (int rc = hip_status(launch_pack_weights(weights, n_models, packed, (hipStream_t)stream), "pack launch"))
+        return rc;
+    return hip_status(launch_pack_rowgemm(weights, packed + packed_weight_elems(), (hipStream_t)stream),
+                      "pack launch");
 }
 
 int pd_score_windows_bf16(const uint16_t* blocks_bf16, const uint8_t* cells, int cells_x, int cells_y,
@@ -469,6 +473,9 @@ int pd_score_windows_bf16(const uint16_t* blocks_bf16, const uint8_t* cells, int
     it.hog16 = const_cast<uint16_t*>(blocks_bf16);
     it.lbp = const_cast<uint8_t*>(cells);
     it.scores = scores;
+    if (n_models == 1)
+        return hip_status(launch_rowgemm_single(it, packed + packed_weight_elems(), bias, (hipStream_t)stream),
+                          "bf16 score launch");
     return hip_status(launch_mfma_single(it, packed, bias, n_models, PD_FEAT_HOG | PD_FEAT_LBP, (hipStream_t)stream),
                       "bf16 score launch");
 }
@@ -565,7 +572,9 @@ int pd_detect(const pd_frame* frames, int n_frames, const float* weights, const 
                     for (int tx = 0; tx < resize_tiles_x(it.w); ++tx) t_rs[nrs++] = Tile{q, ty, tx, 0};
             for (int ty = 0; ty < feat_tiles_y(it.hc); ++ty)
                 for (int tx = 0; tx < feat_tiles_x(it.wc); ++tx) t_ft[nft++] = Tile{q, ty, tx, 0};
-            if (L.bf16) {
+            if (L.bf16 && n_models == 1) {
+                for (int tx = 0; tx < ceil_div(it.nx, RG_TILE_C); ++tx) t_sc[nsc++] = Tile{q, 0, tx, 0};
+            } else if (L.bf16) {
                 for (int ty = 0; ty < ceil_div(it.ny, MF_TILE_R); ++ty)
                     for (int tx = 0; tx < ceil_div(it.nx, MF_TILE_C); ++tx) t_sc[nsc++] = Tile{q, ty, tx, 0};
             } else {
@@ -600,7 +609,10 @@ int pd_detect(const pd_frame* frames, int n_frames, const float* weights, const 
     // candidate and near counters are adjacent: one clear
     if ((rc = hip_status(launch_zero_i32(d_counters, (int)((L.off_cscore - L.off_counters) / 4), s), "zero")))
         return rc;
-    if (L.bf16 && (rc = hip_status(launch_pack_weights(weights, n_models, d_packed, s), "pack"))) return rc;
+    if (L.bf16) {
+        if ((rc = hip_status(launch_pack_weights(weights, n_models, d_packed, s), "pack"))) return rc;
+        if ((rc = hip_status(launch_pack_rowgemm(weights, d_packed + packed_weight_elems(), s), "pack"))) return rc;
+    }
     marks.mark(PD_STAGE_RESIZE, s);
     if ((rc = hip_status(launch_resize_table(d_items, d_tiles, nrs, s), "resize"))) return rc;
     marks.mark(PD_STAGE_FEATURES, s);
@@ -609,7 +621,12 @@ int pd_detect(const pd_frame* frames, int n_frames, const float* weights, const 
                          "features")))
         return rc;
     marks.mark(PD_STAGE_SCORE, s);
-    if (L.bf16) {
+    if (L.bf16 && n_models == 1 && params->features == (PD_FEAT_HOG | PD_FEAT_LBP)) {
+        if ((rc = hip_status(launch_rowgemm_table(d_items, d_tiles + L.n_rs + L.n_ft, L.n_sc,
+                                                  d_packed + packed_weight_elems(), bias, s),
+                             "bf16 score")))
+            return rc;
+    } else if (L.bf16) {
         if ((rc = hip_status(launch_mfma_table(d_items, d_tiles + L.n_rs + L.n_ft, L.n_sc, d_packed, bias, n_models,
                                                params->features, s),
                              "bf16 score")))

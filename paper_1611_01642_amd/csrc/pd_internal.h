@@ -94,6 +94,13 @@ hipError_t launch_score_table(const LevelItem* items, const Tile* tiles, int n_t
                               hipStream_t s);
 
 int64_t packed_weight_elems();
+int64_t rowgemm_packed_elems();
+hipError_t launch_pack_rowgemm(const float* w, uint16_t* out, hipStream_t s);
+hipError_t launch_rowgemm_single(const LevelItem& it, const uint16_t* packed, const float* bias, hipStream_t s);
+hipError_t launch_rowgemm_table(const LevelItem* items, const Tile* tiles, int n_tiles, const uint16_t* packed,
+                                const float* bias, hipStream_t s);
+// row-GEMM scoring (one model): tile = 64 window columns, all rows
+constexpr int RG_TILE_C = 64;
 hipError_t launch_pack_weights(const float* w, int n_models, uint16_t* out, hipStream_t s);
 hipError_t launch_mfma_single(const LevelItem& it, const uint16_t* wpk, const float* bias, int n_models, int features,
                               hipStream_t s);

@@ -1,0 +1,243 @@
+// Window scoring of one linear SVM on BF16 MFMA (Section 4.4, Algorithm 6),
+// with the model's row offsets as the GEMM columns.
+//
+// A window (i, j) scores s = sum_a P[i + a][j][a] with
+//   P[y][j][a] = sum_{b, c} F[y][j + b][c] * W[a][b][c],
+// HOG rows a = 0..14 (b < 7, c < 36) and LBP rows a = 0..15 (b < 8, c < 59).
+// For one feature row y, P is a dense GEMM: rows = 16 windows j, K = the
+// window's (b, c) run of that row (contiguous when the row is staged
+// channel-innermost), columns = the 16 offsets a.  So every staged feature
+// row is multiplied once with the whole model (the window-row formulation
+// re-reads each feature row for every window row it covers), and all 16
+// MFMA columns are useful.  The diagonal sums run in a 16-slot ring of
+// window-row accumulators in LDS: at row y, column a belongs to window row
+// y - a; window row y - 15 is complete after row y.
+//
+// Numerics: HOG features are BF16 and the HOG weights their BF16 part; LBP
+// counts are exact and the LBP weights are hi + lo BF16 halves (two MFMAs into
+// the same FP32 accumulator).  FP32 accumulation; fixed summation order.
+//
+// Tile: a workgroup of 4 waves owns 64 window columns of one level (16 per
+// wave) and streams down all feature rows; the next row's loads are in flight
+// during the current row's MFMAs.
+#include "pd_internal.h"
+
+namespace pd {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int RG_COLS = 64;
+constexpr int RG_HOG_T = 8;    // K chunks of 32 per HOG row: 7 * 36 = 252 -> 256
+constexpr int RG_LBP_T = 15;   // 8 * 60 = 480 (59 bins padded to 60)
+constexpr int RG_HOG_C = PD_HOG_BLOCK;
+constexpr int RG_LBP_C = 60;
+constexpr int RG_HOG_SR = RG_COLS + PD_WIN_BLOCKS_X - 1;  // 70 staged blocks
+constexpr int RG_LBP_SR = RG_COLS + PD_WIN_CELLS_X - 1;   // 71 staged cells
+constexpr int RG_HOG_ROW = (RG_HOG_SR * RG_HOG_C + 8 + 7) / 8 * 8;
+constexpr int RG_LBP_ROW = (RG_LBP_SR * RG_LBP_C + 8 + 7) / 8 * 8;
+
+// packed B fragments: [HOG hi: t 8][LBP hi: t 15][LBP lo: t 15], each
+// [lane 64][8] bf16 (lane: column a = lane % 16, K group lane / 16)
+constexpr int RG_FRAG = 64 * 8;
+constexpr int RG_PACKED = (RG_HOG_T + 2 * RG_LBP_T) * RG_FRAG;
+
+struct RowShared {
+    __bf16 hog[2][RG_HOG_ROW];
+    __bf16 lbp[2][RG_LBP_ROW];
+    __bf16 blbp[2 * RG_LBP_T * RG_FRAG];
+    float ring[4][16][16];  // per wave: window-row slot x window column
+};
+
+__global__ void pack_rowgemm_kernel(const float* __restrict__ w, uint16_t* __restrict__ out) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= RG_PACKED) return;
+    const int f = e / RG_FRAG, r = e - f * RG_FRAG;
+    const int lane = r >> 3, kk = r & 7;
+    const int a = lane & 15;
+    float v = 0.0f;
+    bool lo = false;
+    if (f < RG_HOG_T) {
+        const int k = 32 * f + 8 * (lane >> 4) + kk;
+        const int b = k / RG_HOG_C, c = k % RG_HOG_C;
+        if (a < PD_WIN_BLOCKS_Y && b < PD_WIN_BLOCKS_X) v = w[(a * PD_WIN_BLOCKS_X + b) * PD_HOG_BLOCK + c];
+    } else {
+        const int t = (f - RG_HOG_T) % RG_LBP_T;
+        lo = f >= RG_HOG_T + RG_LBP_T;
+        const int k = 32 * t + 8 * (lane >> 4) + kk;
+        const int b = k / RG_LBP_C, c = k % RG_LBP_C;
+        if (b < PD_WIN_CELLS_X && c < PD_LBP_BINS) v = w[PD_HOG_DIM + (a * PD_WIN_CELLS_X + b) * PD_LBP_BINS + c];
+    }
+    const uint16_t hi = f32_to_bf16(v);
+    out[e] = lo ? f32_to_bf16(v - __uint_as_float((uint32_t)hi << 16)) : hi;
+}
+
+template <bool HOG>
+struct RowRegs {
+    static constexpr int SR = HOG ? RG_HOG_SR : RG_LBP_SR;
+    static constexpr int NC = HOG ? PD_HOG_BLOCK : PD_LBP_BINS;
+    static constexpr int N = (SR * NC + 255) / 256;
+    uint16_t v[N];
+};
+
+template <bool HOG>
+__device__ __forceinline__ void load_row(RowRegs<HOG>& r, const uint16_t* __restrict__ hog16,
+                                         const uint8_t* __restrict__ lbp, int y, int j0, int hcols, int hrows) {
+    constexpr int SR = RowRegs<HOG>::SR, NC = RowRegs<HOG>::NC;
+    const size_t plane = (size_t)hrows * hcols;
+    const size_t row = (size_t)min(y, hrows - 1) * hcols;
+#pragma unroll
+    for (int q = 0; q < RowRegs<HOG>::N; ++q) {
+        const int e = min((int)threadIdx.x + 256 * q, SR * NC - 1);
+        const int c = e / SR, col = e - (e / SR) * SR;
+        const size_t src = c * plane + row + min(j0 + col, hcols - 1);
+        if (HOG) r.v[q] = hog16[src];
+        else r.v[q] = (uint16_t)(__float_as_uint((float)lbp[src]) >> 16);  // counts <= 64: exact in bf16
+    }
+}
+
+template <bool HOG>
+__device__ __forceinline__ void store_row(const RowRegs<HOG>& r, __bf16* dst) {
+    constexpr int SR = RowRegs<HOG>::SR, NC = RowRegs<HOG>::NC;
+    constexpr int C = HOG ? RG_HOG_C : RG_LBP_C;
+    uint16_t* d = reinterpret_cast<uint16_t*>(dst);
+#pragma unroll
+    for (int q = 0; q < RowRegs<HOG>::N; ++q) {
+        const int e = threadIdx.x + 256 * q;
+        if (e < SR * NC) {
+            const int c = e / SR, col = e - (e / SR) * SR;
+            d[col * C + c] = r.v[q];
+        }
+    }
+}
+
+__device__ __forceinline__ bf16x8 a_frag(const __bf16* p) {  // 8-byte aligned run of 8 bf16
+    const uint2 lo = *reinterpret_cast<const uint2*>(p);
+    const uint2 hi = *reinterpret_cast<const uint2*>(p + 4);
+    const u32x4 v = {lo.x, lo.y, hi.x, hi.y};
+    return __builtin_bit_cast(bf16x8, v);
+}
+
+__device__ __forceinline__ void rowgemm_tile(const LevelItem& it, const uint16_t* __restrict__ packed, float bias,
+                                             int tx, RowShared& sm) {
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int hc = it.hc, wc = it.wc, hb = hc - 1, wb = wc - 1;
+    const int ny = it.ny, nx = it.nx;
+    const int j0 = tx * RG_COLS;
+    const int mrow = lane & 15, kg = lane >> 4;
+
+    // B fragments: HOG in registers, LBP hi/lo in LDS (shared by the 4 waves)
+    bf16x8 bh[RG_HOG_T];
+    const u32x4* pk = reinterpret_cast<const u32x4*>(packed);
+#pragma unroll
+    for (int t = 0; t < RG_HOG_T; ++t) bh[t] = __builtin_bit_cast(bf16x8, pk[t * 64 + lane]);
+    for (int e = threadIdx.x; e < 2 * RG_LBP_T * 64; e += 256)
+        reinterpret_cast<u32x4*>(sm.blbp)[e] = pk[RG_HOG_T * 64 + e];
+    for (int e = threadIdx.x; e < 4 * 16 * 16; e += 256) (&sm.ring[0][0][0])[e] = 0.0f;
+    // zero the staged rows once so every value an MFMA reads is finite
+    for (int e = threadIdx.x; e < (int)(sizeof(sm.hog) + sizeof(sm.lbp)) / 4; e += 256)
+        reinterpret_cast<uint32_t*>(&sm.hog[0][0])[e] = 0u;
+    __syncthreads();
+    {
+        RowRegs<true> rh;
+        RowRegs<false> rl;
+        load_row<true>(rh, it.hog16, it.lbp, 0, j0, wb, hb);
+        load_row<false>(rl, it.hog16, it.lbp, 0, j0, wc, hc);
+        store_row<true>(rh, sm.hog[0]);
+        store_row<false>(rl, sm.lbp[0]);
+    }
+    __syncthreads();
+
+    float (*ring)[16] = sm.ring[wave];
+    for (int y = 0; y < hc; ++y) {
+        const int cur = y & 1;
+        const bool more = y + 1 < hc;
+        RowRegs<true> nh;
+        RowRegs<false> nl;
+        if (more) {
+            if (y + 1 < hb) load_row<true>(nh, it.hog16, it.lbp, y + 1, j0, wb, hb);
+            load_row<false>(nl, it.hog16, it.lbp, y + 1, j0, wc, hc);
+        }
+        f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (y < hb) {
+            const __bf16* row = sm.hog[cur] + (16 * wave + mrow) * RG_HOG_C + 8 * kg;
+#pragma unroll
+            for (int t = 0; t < RG_HOG_T; ++t)
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_frag(row + 32 * t), bh[t], acc, 0, 0, 0);
+        }
+        {
+            const __bf16* row = sm.lbp[cur] + (16 * wave + mrow) * RG_LBP_C + 8 * kg;
+            const bf16x8* bl = reinterpret_cast<const bf16x8*>(sm.blbp);
+#pragma unroll
+            for (int t = 0; t < RG_LBP_T; ++t) {
+                const bf16x8 av = a_frag(row + 32 * t);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bl[t * 64 + lane], acc, 0, 0, 0);
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bl[(RG_LBP_T + t) * 64 + lane], acc, 0, 0, 0);
+            }
+        }
+        // acc[r] = P[y][window 4*kg + r][a = mrow] belongs to window row y - a
+        {
+            const int i = y - mrow;
+            if (i >= 0 && i < ny) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) ring[i & 15][4 * kg + r] += acc[r];
+            }
+        }
+        if (y >= PD_WIN_CELLS_Y - 1) {  // window row y - 15 is complete
+            const int i = y - (PD_WIN_CELLS_Y - 1);
+            if (lane < 16) {
+                const float v = ring[i & 15][lane];
+                ring[i & 15][lane] = 0.0f;
+                const int j = j0 + 16 * wave + lane;
+                if (i < ny && j < nx) it.scores[(size_t)i * nx + j] = v + bias;
+            }
+        }
+        if (more) {
+            if (y + 1 < hb) store_row<true>(nh, sm.hog[cur ^ 1]);
+            store_row<false>(nl, sm.lbp[cur ^ 1]);
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(256) rowgemm_single_kernel(LevelItem it, const uint16_t* __restrict__ packed,
+                                                             const float* __restrict__ bias) {
+    __shared__ RowShared sm;
+    rowgemm_tile(it, packed, bias[0], blockIdx.x, sm);
+}
+
+__global__ void __launch_bounds__(256) rowgemm_table_kernel(const LevelItem* __restrict__ items,
+                                                            const Tile* __restrict__ tiles,
+                                                            const uint16_t* __restrict__ packed,
+                                                            const float* __restrict__ bias) {
+    __shared__ RowShared sm;
+    const Tile tl = tiles[blockIdx.x];
+    rowgemm_tile(items[tl.item], packed, bias[0], tl.tx, sm);
+}
+
+}  // namespace
+
+int64_t rowgemm_packed_elems() { return RG_PACKED; }
+
+hipError_t launch_pack_rowgemm(const float* w, uint16_t* out, hipStream_t s) {
+    pack_rowgemm_kernel<<<ceil_div(RG_PACKED, 256), 256, 0, s>>>(w, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_rowgemm_single(const LevelItem& it, const uint16_t* packed, const float* bias, hipStream_t s) {
+    if (it.nx <= 0 || it.ny <= 0) return hipSuccess;
+    rowgemm_single_kernel<<<ceil_div(it.nx, RG_COLS), 256, 0, s>>>(it, packed, bias);
+    return hipGetLastError();
+}
+
+hipError_t launch_rowgemm_table(const LevelItem* items, const Tile* tiles, int n_tiles, const uint16_t* packed,
+                                const float* bias, hipStream_t s) {
+    if (n_tiles <= 0) return hipSuccess;
+    rowgemm_table_kernel<<<n_tiles, 256, 0, s>>>(items, tiles, packed, bias);
+    return hipGetLastError();
+}
+
+}  // namespace pd

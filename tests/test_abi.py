@@ -89,7 +89,7 @@ def test_argument_errors_enqueue_nothing():
     assert L.pd_pack_models(fake, 9, fake, nil) == pd.E_SIZE
     assert L.pd_score_windows_bf16(fake, fake, 8, 16, fake, fake, 9, fake, nil) == pd.E_SIZE
     assert L.pd_score_windows_bf16(fake, fake, 7, 16, fake, fake, 1, fake, nil) == pd.E_SIZE
-    assert L.pd_packed_models_bytes() == (15 * 8 + 16 * 15) * 16 * 32 * 2
+    assert L.pd_packed_models_bytes() == ((15 * 8 + 16 * 15) * 16 * 32 + (8 + 2 * 15) * 64 * 8) * 2
     assert L.pd_score_windows(fake, fake, 7, 16, fake, fake, 1, fake, nil) == pd.E_SIZE
     assert L.pd_score_windows(fake, fake, 8, 16, fake, fake, 0, fake, nil) == pd.E_SIZE
     assert L.pd_score_windows(fake, fake, 8, 16, fake, fake, 17, fake, nil) == pd.E_SIZE

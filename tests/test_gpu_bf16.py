@@ -53,6 +53,7 @@ def test_mfma_scoring_exact_operands(w, h, m):
     bias = np.linspace(-1.0, 1.0, m).astype(np.float32)
     hi = bf16_round(wts)
     lo = bf16_round(wts.astype(np.float64) - hi)
+    lo[:, :O.HOG_DIM] = 0.0          # HOG weights carry their BF16 part only
     packed = pd.pack_models(to_dev(wts))
     got = pd.score_windows_bf16(to_dev(hog16.astype(np.float32).transpose(2, 0, 1)).to(torch.bfloat16),
                                 to_dev(cells.transpose(2, 0, 1)), packed, to_dev(bias), m).cpu().numpy()
@@ -73,13 +74,13 @@ def _oracle_frame(img, m, scale=(11, 10), maxl=0):
     return wts, bias, levels, thr
 
 
-@pytest.mark.parametrize("cfg", ["small8", "road8"])
+@pytest.mark.parametrize("cfg", ["small8", "road8", "road1"])
 def test_detect_bf16_decisions_equal_oracle(cfg):
     if cfg == "small8":
         img, scale, maxl = pd_synth.frame(320, 240, 1000), (6, 5), 3
     else:
         img, scale, maxl = pd_synth.frame(1242, 375, 1000), (11, 10), 0
-    m = 8
+    m = 1 if cfg.endswith("1") else 8
     wts, bias, levels, thr = _oracle_frame(img, m, scale, maxl)
     h0, w0 = img.shape
     prm = pd.params(scale=scale, max_levels=maxl, precision=pd.PREC_BF16, margin=0.05)
@@ -108,9 +109,10 @@ def test_detect_bf16_decisions_equal_oracle(cfg):
         absx = O.window_scores(lv["hog"], lv["cells"], np.abs(wts.astype(np.float64)), np.zeros(m))
         hog_only = O.window_scores(lv["hog"], np.zeros_like(lv["cells"]), np.abs(wts.astype(np.float64)),
                                    np.zeros(m))
-        # rounding HOG to BF16 (2^-9 relative) + its FP32 computation (1e-5), the hi/lo
-        # weights (2^-17), FP32 accumulation of ~2 x 11520 products
-        bound = 2.0 ** -9 * hog_only + 1e-5 * hog_only + 2.0 ** -17 * absx + 2 * 11520 * 2.0 ** -24 * absx
+        # HOG features rounded to BF16 (2^-9 relative) + their FP32 computation (1e-5),
+        # HOG weights rounded to BF16 (2^-9), LBP weights as hi + lo (2^-17), FP32
+        # accumulation of ~2 x 11520 products
+        bound = (2.0 ** -8 + 1e-5) * hog_only + 2.0 ** -17 * absx + 2 * 11520 * 2.0 ** -24 * absx
         err = np.abs(s - ref)
         assert np.all(err <= bound), (k, err.max())
         worst_ratio = max(worst_ratio, float((err / bound).max()))
