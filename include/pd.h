@@ -83,11 +83,19 @@ typedef struct pd_params {
     float   margin;      /* PD_PREC_BF16: windows whose score is within
                             margin of the threshold are rescored in FP64
                             (0.05)                                          */
-    int32_t reserved[2]; /* zero                                           */
+    /* Tile and launch shapes of pd_detect (0 = default).  They change the
+       work partition only, never a result; pd_autotune picks them.        */
+    int32_t tune_feat_rows;  /* block rows per feature strip: 4..32 (8)    */
+    int32_t tune_score_rows; /* PD_PREC_F32 window rows per scoring wave:
+                                8 or 16 (8)                                */
+    int32_t tune_grid;       /* 0: one workgroup per tile group; n > 0:
+                                feature and scoring grids of at most n
+                                workgroups looping over the tiles          */
+    int32_t reserved;        /* zero                                       */
 } pd_params;
 
 /* Fills the defaults above: 11/10, all levels, 0.2, 1e-3, HOG|LBP, FP32,
-   margin 0.05. */
+   margin 0.05, default tile shapes. */
 void pd_params_default(pd_params* p);
 
 /* One pyramid level as planned by pd_plan_pyramid (host struct). */
@@ -279,6 +287,53 @@ int pd_detect(const pd_frame* frames, int n_frames, const float* weights,
               const float* bias, int n_models, const pd_params* params,
               const double* thresholds, void* workspace, int64_t workspace_bytes,
               pd_box* boxes, int cap, pd_counts* counts, void* stream);
+
+/*
+ * pd_graph_create -- the kernel sequence of pd_detect on exactly these
+ * arguments, captured once into a HIP graph for replay by pd_graph_launch
+ * (HIP graph capture in place of per-call launches; the work is that of
+ * Section 4.1 steps 2-5 as in pd_detect).  The call uploads the level and
+ * tile tables into `workspace` now and waits for that copy on `stream`; the
+ * graph holds kernels only (the counters are cleared by a kernel).  Every
+ * pointer argument is baked into the graph: the frames, weights, bias,
+ * thresholds, workspace, boxes and counts must stay allocated until
+ * pd_graph_destroy, and their contents may change between launches (new
+ * pixels in the same frame buffers, new thresholds or weights).  Frame sizes
+ * and params are fixed.  Launches of one graph must not overlap (they share
+ * the workspace).
+ *   out : host pointer receiving the graph handle
+ * Errors: those of pd_detect; PD_E_HIP if capture or instantiation fails.
+ */
+typedef struct pd_graph pd_graph;
+int pd_graph_create(const pd_frame* frames, int n_frames, const float* weights,
+                    const float* bias, int n_models, const pd_params* params,
+                    const double* thresholds, void* workspace, int64_t workspace_bytes,
+                    pd_box* boxes, int cap, pd_counts* counts, void* stream,
+                    pd_graph** out);
+
+/* pd_graph_launch -- enqueue one replay of the captured pipeline on stream. */
+int pd_graph_launch(pd_graph* graph, void* stream);
+
+/* pd_graph_destroy -- release the graph (NULL is accepted); the caller makes
+   sure no launch is still running. */
+int pd_graph_destroy(pd_graph* graph);
+
+/*
+ * pd_autotune -- times pd_detect on these arguments (one untimed call, then
+ * `iters` calls between HIP events, per candidate) over the tuning fields of
+ * pd_params, one field at a time: feature strip rows {4, 6, 8, 12, 16},
+ * FP32 scoring rows {8, 16}, grid cap {0, 256, 512, 1024, 2048}; starting
+ * from params' own values.  Writes params with the fastest fields to *best
+ * (host) and its time per call in ms to *best_ms (host, may be NULL).
+ * Blocks until the timing runs finished; leaves boxes and counts of the
+ * last run.  The workspace size does not depend on the tuning fields.
+ * Errors: those of pd_detect; PD_E_ARG for iters outside [1, 1000].
+ */
+int pd_autotune(const pd_frame* frames, int n_frames, const float* weights,
+                const float* bias, int n_models, const pd_params* params,
+                const double* thresholds, void* workspace, int64_t workspace_bytes,
+                pd_box* boxes, int cap, pd_counts* counts, int iters,
+                pd_params* best, float* best_ms, void* stream);
 
 /*
  * pd_detect_candidates -- test hook: after pd_detect on the same arguments

@@ -42,7 +42,13 @@ class Params(ctypes.Structure):
     _fields_ = [("scale_num", ctypes.c_int32), ("scale_den", ctypes.c_int32),
                 ("max_levels", ctypes.c_int32), ("clip", ctypes.c_float), ("eps", ctypes.c_float),
                 ("features", ctypes.c_int32), ("precision", ctypes.c_int32), ("margin", ctypes.c_float),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("tune_feat_rows", ctypes.c_int32), ("tune_score_rows", ctypes.c_int32),
+                ("tune_grid", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    TUNING = ("tune_feat_rows", "tune_score_rows", "tune_grid")
+
+    def tuning(self) -> dict:
+        return {k: int(getattr(self, k)) for k in self.TUNING}
 
 
 class Level(ctypes.Structure):
@@ -95,6 +101,16 @@ _SIGS = {
     "pd_detect": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                  ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
+    "pd_graph_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_int64, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_void_p]),
+    "pd_graph_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "pd_graph_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "pd_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                   ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                   ctypes.c_void_p, ctypes.c_void_p]),
     "pd_nms": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
                               ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
     "pd_profile_enable": (ctypes.c_int, [ctypes.c_int]),
@@ -128,7 +144,8 @@ def _check(rc: int) -> None:
 
 
 def params(scale=(11, 10), max_levels: int = 0, clip: float = 0.2, eps: float = 1e-3,
-           features: int = FEAT_HOG | FEAT_LBP, precision: int = PREC_F32, margin: float = 0.05) -> Params:
+           features: int = FEAT_HOG | FEAT_LBP, precision: int = PREC_F32, margin: float = 0.05,
+           tune_feat_rows: int = 0, tune_score_rows: int = 0, tune_grid: int = 0) -> Params:
     p = Params()
     lib().pd_params_default(ctypes.byref(p))
     p.scale_num, p.scale_den = scale
@@ -138,6 +155,7 @@ def params(scale=(11, 10), max_levels: int = 0, clip: float = 0.2, eps: float = 
     p.features = features
     p.precision = precision
     p.margin = margin
+    p.tune_feat_rows, p.tune_score_rows, p.tune_grid = tune_feat_rows, tune_score_rows, tune_grid
     return p
 
 
@@ -316,11 +334,50 @@ class Detector:
 
     def run(self, thresholds) -> None:
         """Enqueue the whole pipeline; thresholds: float64 CUDA tensor [n_frames]."""
-        _check(lib().pd_detect(self._frames, len(self.frames), ctypes.c_void_p(self.weights.data_ptr()),
-                               ctypes.c_void_p(self.bias.data_ptr()), self.n_models, ctypes.byref(self.prm),
-                               ctypes.c_void_p(thresholds.data_ptr()), ctypes.c_void_p(self.ws_ptr),
-                               self.ws_bytes, ctypes.c_void_p(self.boxes.data_ptr()), self.cap,
-                               ctypes.c_void_p(self.counts.data_ptr()), _stream()))
+        _check(lib().pd_detect(*self._args(thresholds), _stream()))
+
+    def _args(self, thresholds):
+        return (self._frames, len(self.frames), ctypes.c_void_p(self.weights.data_ptr()),
+                ctypes.c_void_p(self.bias.data_ptr()), self.n_models, ctypes.byref(self.prm),
+                ctypes.c_void_p(thresholds.data_ptr()), ctypes.c_void_p(self.ws_ptr), self.ws_bytes,
+                ctypes.c_void_p(self.boxes.data_ptr()), self.cap, ctypes.c_void_p(self.counts.data_ptr()))
+
+    def capture(self, thresholds) -> None:
+        """Capture the pipeline into a HIP graph (pd_graph_create).  The graph
+        keeps the frame, weight and threshold buffers: refill them in place
+        and call replay()."""
+        self.release()
+        self._thr_keep = thresholds
+        h = ctypes.c_void_p(0)
+        _check(lib().pd_graph_create(*self._args(thresholds), _stream(), ctypes.byref(h)))
+        self._graph = h
+
+    def replay(self) -> None:
+        """Enqueue one launch of the captured graph on the current stream."""
+        if getattr(self, "_graph", None) is None:
+            raise RuntimeError("capture() first")
+        _check(lib().pd_graph_launch(self._graph, _stream()))
+
+    def release(self) -> None:
+        g = getattr(self, "_graph", None)
+        if g is not None:
+            self._graph = None
+            _check(lib().pd_graph_destroy(g))
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
+    def autotune(self, thresholds, iters: int = 3):
+        """Pick the tuning fields of the params by timing (pd_autotune); the
+        detector keeps the result.  Returns (tuning dict, ms per call)."""
+        best = Params()
+        ms = ctypes.c_float(0.0)
+        _check(lib().pd_autotune(*self._args(thresholds), iters, ctypes.byref(best), ctypes.byref(ms), _stream()))
+        self.prm = best
+        return best.tuning(), float(ms.value)
 
     def candidates(self, frame: int):
         """(scores float32 [n], keys int32 [n][4], fp64 scores or None) of one

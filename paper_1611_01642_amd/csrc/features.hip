@@ -3,7 +3,7 @@
 // (Section 4.3, Algorithms 4-5) from a single pass over the pixels.
 //
 // Mapping: one wave64 owns a strip of 64 cell columns (one lane per 8x8 cell)
-// and walks down FT_CH block rows.  For each cell row, a lane reads its cell's
+// and walks down a chunk of block rows.  For each cell row, a lane reads its cell's
 // 10x10 pixel neighbourhood straight from global memory (one 8-byte load per
 // pixel row, plus the two halo bytes; neighbouring lanes read neighbouring
 // bytes, so the loads are coalesced) and processes its 64 pixels:
@@ -124,17 +124,17 @@ __device__ __forceinline__ int px_at(const PixRow& r, int i) {  // i in 0..9, co
 
 template <int FEAT, bool ALIGNED>
 __device__ __forceinline__ void features_strip(const uint8_t* __restrict__ img, int w, int h, int pitch, float* __restrict__ hog,
-                               uint16_t* __restrict__ hog16, uint8_t* __restrict__ lbp, int ty, int tx, float clip,
-                               float eps, FeatShared& sm, int wave) {
+                               uint16_t* __restrict__ hog16, uint8_t* __restrict__ lbp, int ty, int tx, int ch,
+                               float clip, float eps, FeatShared& sm, int wave) {
     constexpr bool DO_HOG = (FEAT & PD_FEAT_HOG) != 0;
     constexpr bool DO_LBP = (FEAT & PD_FEAT_LBP) != 0;
     const int lane = threadIdx.x & 63;
     const int hc = h / PD_CELL, wc = w / PD_CELL;
     const int hb = hc - 1, wb = wc - 1;
-    const int cx0 = tx * FT_BX, cy0 = ty * FT_CH;
+    const int cx0 = tx * FT_BX, cy0 = ty * ch;
     const int cx = cx0 + lane;
     const int x0 = PD_CELL * min(cx, wc - 1);  // lanes past the edge read valid pixels
-    const int cy_last = min(cy0 + FT_CH, hc - 1);
+    const int cy_last = min(cy0 + ch, hc - 1);
     const bool lbp_col = cx < wc && (lane < FT_BX || cx == wc - 1);
     const bool blk_col = lane < FT_BX && cx < wb;
     uint32_t* cnt = &sm.cnt[wave][lane * LBP_WORDS];
@@ -254,7 +254,7 @@ __device__ __forceinline__ void features_strip(const uint8_t* __restrict__ img, 
 
         // LBP histogram of this cell row
         if (DO_LBP) {
-            const bool own_row = cy < cy0 + FT_CH || cy == hc - 1;
+            const bool own_row = cy < cy0 + ch || cy == hc - 1;
             if (own_row && lbp_col) {
                 const size_t plane = (size_t)hc * wc;
                 uint8_t* o = lbp + (size_t)cy * wc + cx;
@@ -349,25 +349,26 @@ __global__ void __launch_bounds__(256) features_single_kernel(LevelItem it, floa
     const int ntx = feat_tiles_x(it.wc);
     if (task >= ntx * feat_tiles_y(it.hc)) return;
     features_strip<FEAT, ALIGNED>(it.pyr, it.w, it.h, it.pitch, it.hog, it.hog16, it.lbp, task / ntx, task % ntx,
-                                  clip, eps, sm, wave);
+                                  FT_CH, clip, eps, sm, wave);
 }
 
 // The table launch requires 8-byte aligned level rows (pd_detect copies
 // misaligned frames into the pyramid buffer).
 template <int FEAT>
 __global__ void __launch_bounds__(256) features_table_kernel(const LevelItem* __restrict__ items,
-                                                             const Tile* __restrict__ tiles, int n_tiles,
+                                                             const Tile* __restrict__ tiles, int n_tiles, int ch,
                                                              float clip, float eps) {
     __shared__ FeatShared sm;
     init_lut(sm);
     __syncthreads();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int task = blockIdx.x * FT_WAVES + wave;
-    if (task >= n_tiles) return;
-    const Tile tl = tiles[task];
-    const LevelItem& it = items[tl.item];
-    features_strip<FEAT, true>(it.pyr, it.w, it.h, it.pitch, it.hog, it.hog16, it.lbp, tl.ty, tl.tx, clip, eps, sm,
-                               wave);
+    // strips are independent per wave; a capped grid loops over them
+    for (int task = blockIdx.x * FT_WAVES + wave; task < n_tiles; task += gridDim.x * FT_WAVES) {
+        const Tile tl = tiles[task];
+        const LevelItem& it = items[tl.item];
+        features_strip<FEAT, true>(it.pyr, it.w, it.h, it.pitch, it.hog, it.hog16, it.lbp, tl.ty, tl.tx, ch, clip,
+                                   eps, sm, wave);
+    }
 }
 
 // Algorithm 1 on its own: one thread per pixel (used to check the codes).
@@ -405,8 +406,10 @@ hipError_t feat_single_any(const LevelItem& it, float clip, float eps, hipStream
 
 template <int FEAT>
 hipError_t feat_table(const LevelItem* items, const Tile* tiles, int n_tiles, float clip, float eps,
-                      hipStream_t s) {
-    features_table_kernel<FEAT><<<ceil_div(n_tiles, FT_WAVES), 256, 0, s>>>(items, tiles, n_tiles, clip, eps);
+                      const Tuning& tu, hipStream_t s) {
+    int blocks = ceil_div(n_tiles, FT_WAVES);
+    if (tu.grid > 0) blocks = min(blocks, tu.grid);
+    features_table_kernel<FEAT><<<blocks, 256, 0, s>>>(items, tiles, n_tiles, tu.feat_rows, clip, eps);
     return hipGetLastError();
 }
 
@@ -430,13 +433,13 @@ hipError_t launch_features_single(const LevelItem& it, int features, float clip,
 }
 
 hipError_t launch_features_table(const LevelItem* items, const Tile* tiles, int n_tiles, int features,
-                                 float clip, float eps, hipStream_t s) {
+                                 float clip, float eps, const Tuning& tu, hipStream_t s) {
     if (n_tiles <= 0) return hipSuccess;
     switch (features & (PD_FEAT_HOG | PD_FEAT_LBP)) {
-        case PD_FEAT_HOG: return feat_table<PD_FEAT_HOG>(items, tiles, n_tiles, clip, eps, s);
-        case PD_FEAT_LBP: return feat_table<PD_FEAT_LBP>(items, tiles, n_tiles, clip, eps, s);
+        case PD_FEAT_HOG: return feat_table<PD_FEAT_HOG>(items, tiles, n_tiles, clip, eps, tu, s);
+        case PD_FEAT_LBP: return feat_table<PD_FEAT_LBP>(items, tiles, n_tiles, clip, eps, tu, s);
         case PD_FEAT_HOG | PD_FEAT_LBP:
-            return feat_table<PD_FEAT_HOG | PD_FEAT_LBP>(items, tiles, n_tiles, clip, eps, s);
+            return feat_table<PD_FEAT_HOG | PD_FEAT_LBP>(items, tiles, n_tiles, clip, eps, tu, s);
         default: return hipSuccess;
     }
 }

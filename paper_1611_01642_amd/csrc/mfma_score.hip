@@ -260,20 +260,33 @@ __global__ void __launch_bounds__(256) mfma_single_kernel(LevelItem it, const ui
         mfma_tile<PD_FEAT_LBP>(it.hog16, it.lbp, it.wc, it.hc, wpk, bias, n_models, it.scores, ty, tx, sm);
 }
 
+// With LOOP a capped grid strides over the tile table; the barrier at the end
+// of each tile keeps the next tile's staging off LDS rows still being read.
+template <bool LOOP>
 __global__ void __launch_bounds__(256) mfma_table_kernel(const LevelItem* __restrict__ items,
-                                                         const Tile* __restrict__ tiles,
+                                                         const Tile* __restrict__ tiles, int n_tiles,
                                                          const uint16_t* __restrict__ wpk,
                                                          const float* __restrict__ bias, int n_models, int feat) {
     __shared__ MfmaShared sm;
-    const Tile tl = tiles[blockIdx.x];
-    const LevelItem& it = items[tl.item];
-    if (feat == (PD_FEAT_HOG | PD_FEAT_LBP))
-        mfma_tile<PD_FEAT_HOG | PD_FEAT_LBP>(it.hog16, it.lbp, it.wc, it.hc, wpk, bias, n_models, it.scores, tl.ty,
-                                             tl.tx, sm);
-    else if (feat == PD_FEAT_HOG)
-        mfma_tile<PD_FEAT_HOG>(it.hog16, it.lbp, it.wc, it.hc, wpk, bias, n_models, it.scores, tl.ty, tl.tx, sm);
-    else
-        mfma_tile<PD_FEAT_LBP>(it.hog16, it.lbp, it.wc, it.hc, wpk, bias, n_models, it.scores, tl.ty, tl.tx, sm);
+    auto one = [&](int t) __attribute__((always_inline)) {
+        const Tile tl = tiles[t];
+        const LevelItem& it = items[tl.item];
+        if (feat == (PD_FEAT_HOG | PD_FEAT_LBP))
+            mfma_tile<PD_FEAT_HOG | PD_FEAT_LBP>(it.hog16, it.lbp, it.wc, it.hc, wpk, bias, n_models, it.scores,
+                                                 tl.ty, tl.tx, sm);
+        else if (feat == PD_FEAT_HOG)
+            mfma_tile<PD_FEAT_HOG>(it.hog16, it.lbp, it.wc, it.hc, wpk, bias, n_models, it.scores, tl.ty, tl.tx, sm);
+        else
+            mfma_tile<PD_FEAT_LBP>(it.hog16, it.lbp, it.wc, it.hc, wpk, bias, n_models, it.scores, tl.ty, tl.tx, sm);
+    };
+    if constexpr (LOOP) {
+        for (int t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+            one(t);
+            __syncthreads();
+        }
+    } else {
+        one(blockIdx.x);
+    }
 }
 
 }  // namespace
@@ -297,9 +310,13 @@ hipError_t launch_mfma_single(const LevelItem& it, const uint16_t* wpk, const fl
 }
 
 hipError_t launch_mfma_table(const LevelItem* items, const Tile* tiles, int n_tiles, const uint16_t* wpk,
-                             const float* bias, int n_models, int features, hipStream_t s) {
+                             const float* bias, int n_models, int features, int grid, hipStream_t s) {
     if (n_tiles <= 0) return hipSuccess;
-    mfma_table_kernel<<<n_tiles, 256, 0, s>>>(items, tiles, wpk, bias, n_models, features & (PD_FEAT_HOG | PD_FEAT_LBP));
+    const int feat = features & (PD_FEAT_HOG | PD_FEAT_LBP);
+    if (grid > 0 && grid < n_tiles)
+        mfma_table_kernel<true><<<grid, 256, 0, s>>>(items, tiles, n_tiles, wpk, bias, n_models, feat);
+    else
+        mfma_table_kernel<false><<<n_tiles, 256, 0, s>>>(items, tiles, n_tiles, wpk, bias, n_models, feat);
     return hipGetLastError();
 }
 

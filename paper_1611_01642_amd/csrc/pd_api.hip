@@ -33,6 +33,7 @@ int hip_status(hipError_t e, const char* what) {
 }
 
 constexpr int64_t kAlign = 256;
+constexpr int FT_MIN_ROWS = 4, FT_MAX_ROWS = 32;  // feature strip heights accepted in tune_feat_rows
 inline int64_t align_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
 bool check_params(const pd_params* p) {
@@ -48,7 +49,22 @@ bool check_params(const pd_params* p) {
     if (p->precision != PD_PREC_F32 && p->precision != PD_PREC_BF16)
         return fail(PD_E_ARG, "unknown precision %d", p->precision), false;
     if (!(p->margin >= 0.0f) || !std::isfinite(p->margin)) return fail(PD_E_ARG, "margin must be >= 0"), false;
+    if (p->tune_feat_rows != 0 && (p->tune_feat_rows < FT_MIN_ROWS || p->tune_feat_rows > FT_MAX_ROWS))
+        return fail(PD_E_ARG, "tune_feat_rows must be 0 or in [%d, %d]", FT_MIN_ROWS, FT_MAX_ROWS), false;
+    if (p->tune_score_rows != 0 && p->tune_score_rows != 8 && p->tune_score_rows != 16)
+        return fail(PD_E_ARG, "tune_score_rows must be 0, 8 or 16"), false;
+    if (p->tune_grid < 0 || p->tune_grid > (1 << 20))
+        return fail(PD_E_ARG, "tune_grid must be in [0, 2^20]"), false;
     return true;
+}
+
+// Tile and launch shapes from the tuning fields (0 selects the default).
+Tuning tuning_of(const pd_params* p) {
+    Tuning t;
+    if (p->tune_feat_rows) t.feat_rows = p->tune_feat_rows;
+    if (p->tune_score_rows) t.score_rows = p->tune_score_rows;
+    t.grid = p->tune_grid;
+    return t;
 }
 
 int check_image(const void* img, int w, int h, int pitch, const char* name) {
@@ -163,7 +179,7 @@ void item_geometry(LevelItem& it, int w, int h) {
 // and by pd_detect.
 struct DetectLayout {
     int n_items = 0;
-    int n_rs = 0, n_ft = 0, n_sc = 0, n_cp = 0;
+    int n_rs = 0, n_ft = 0, n_sc = 0, n_cp = 0;  // tile table capacities
     bool bf16 = false;
     int64_t off_items = 0, off_tiles = 0, off_geoms = 0, off_first = 0, off_counters = 0, off_cscore = 0,
             off_ckey = 0, off_c64 = 0, off_near_count = 0, off_near_key = 0, off_packed = 0;
@@ -202,8 +218,10 @@ bool plan_detect(const pd_frame* frames, int n_frames, const pd_params* p, int n
             L.sc_off.push_back(data);
             data = align_up(data + (int64_t)n_models * it.ny * it.nx * 4, kAlign);
             L.n_rs += resize_tiles_x(it.w) * resize_tiles_y(it.h);  // upper bound
-            L.n_ft += feat_tiles_x(it.wc) * feat_tiles_y(it.hc);
-            L.n_sc += !L.bf16 ? score_tiles_x(it.nx) * score_tiles_y(it.ny) * n_models
+            // table capacity for the finest tile shapes the tuning fields
+            // allow, so the workspace size does not depend on them
+            L.n_ft += feat_tiles_x(it.wc) * feat_tiles_y(it.hc, FT_MIN_ROWS);
+            L.n_sc += !L.bf16 ? score_tiles_x(it.nx) * score_tiles_y(it.ny, SC_R) * n_models
                       : n_models == 1 ? ceil_div(it.nx, RG_TILE_C)
                                       : ceil_div(it.nx, MF_TILE_C) * ceil_div(it.ny, MF_TILE_R);
             L.n_cp += ceil_div(it.nx * it.ny, CP_N);
@@ -280,6 +298,179 @@ struct StageMarks {
         if (!ev.empty()) g_prof.pending.push_back(std::move(ev));
     }
 };
+
+// Argument checks and workspace layout shared by pd_detect, pd_graph_create
+// and pd_autotune.
+int validate_detect(const pd_frame* frames, int n_frames, const float* weights, const float* bias, int n_models,
+                    const pd_params* params, const double* thresholds, const void* workspace,
+                    int64_t workspace_bytes, const pd_box* boxes, int cap, const pd_counts* counts,
+                    DetectLayout& L) {
+    if (!check_params(params)) return PD_E_ARG;
+    if (!frames || n_frames < 1) return fail(PD_E_ARG, "frames is NULL or n_frames < 1");
+    const int max_m = params->precision == PD_PREC_BF16 ? PD_MAX_MODELS_BF16 : PD_MAX_MODELS;
+    if (n_models < 1 || n_models > max_m) return fail(PD_E_SIZE, "n_models outside [1, %d]", max_m);
+    if (!weights || !bias || !thresholds || !counts || (cap > 0 && !boxes) || cap < 0)
+        return fail(PD_E_ARG, "NULL pointer argument");
+    for (int f = 0; f < n_frames; ++f) {
+        if (int rc = check_image(frames[f].data, frames[f].w, frames[f].h, frames[f].pitch, "frame")) return rc;
+    }
+    if (!plan_detect(frames, n_frames, params, n_models, L)) return PD_E_SIZE;
+    if (!workspace || workspace_bytes < L.total)
+        return fail(PD_E_WORKSPACE, "workspace of %lld bytes, need %lld", (long long)workspace_bytes,
+                    (long long)L.total);
+    if ((uintptr_t)workspace & (kAlign - 1)) return fail(PD_E_ARG, "workspace must be 256-byte aligned");
+    return PD_OK;
+}
+
+// Device-side view of one planned pd_detect call.
+struct DetectRun {
+    const LevelItem* items = nullptr;
+    const Tile *t_rs = nullptr, *t_ft = nullptr, *t_sc = nullptr, *t_cp = nullptr;
+    int nrs = 0, nft = 0, nsc = 0, ncp = 0;  // tiles in use
+    const NmsGeom* geoms = nullptr;
+    const int32_t* first = nullptr;
+    int32_t* counters = nullptr;
+    int32_t* near_count = nullptr;
+    float* cscore = nullptr;
+    int4* ckey = nullptr;
+    double* c64 = nullptr;
+    int4* near_key = nullptr;
+    uint16_t* packed = nullptr;
+    int n_zero = 0;  // counters + near counters, cleared together
+};
+
+// Builds the level, tile and NMS tables of one call in host memory `stage`
+// (L.table_bytes), laid out as they are uploaded to the start of `ws`.
+void fill_tables(const pd_frame* frames, int n_frames, int n_models, const Tuning& tu, const DetectLayout& L,
+                 uint8_t* ws, uint8_t* stage, DetectRun& R) {
+    uint8_t* data = ws + L.off_data;
+    std::memset(stage, 0, (size_t)L.table_bytes);
+    LevelItem* items = reinterpret_cast<LevelItem*>(stage + L.off_items);
+    Tile* tiles = reinterpret_cast<Tile*>(stage + L.off_tiles);
+    NmsGeom* geoms = reinterpret_cast<NmsGeom*>(stage + L.off_geoms);
+    int32_t* first = reinterpret_cast<int32_t*>(stage + L.off_first);
+    Tile* t_rs = tiles;
+    Tile* t_ft = t_rs + L.n_rs;
+    Tile* t_sc = t_ft + L.n_ft;
+    Tile* t_cp = t_sc + L.n_sc;
+    int q = 0, nrs = 0, nft = 0, nsc = 0, ncp = 0;
+    for (int f = 0; f < n_frames; ++f) {
+        geoms[f].n_levels = L.level_count[f];
+        first[f] = q;
+        for (int k = 0; k < L.level_count[f]; ++k, ++q) {
+            LevelItem& it = items[q];
+            item_geometry(it, L.sizes[2 * q], L.sizes[2 * q + 1]);
+            it.src = frames[f].data;
+            it.src_w = frames[f].w;
+            it.src_h = frames[f].h;
+            it.src_pitch = frames[f].pitch;
+            const bool direct = k == 0 && (((uintptr_t)frames[f].data | (uintptr_t)frames[f].pitch) & 7) == 0;
+            if (direct) {
+                it.pyr = const_cast<uint8_t*>(frames[f].data);
+                it.pitch = frames[f].pitch;
+            } else {
+                it.pyr = data + L.pyr_off[q];
+                it.pitch = (int)align_up(it.w, 16);
+            }
+            if (L.bf16) it.hog16 = reinterpret_cast<uint16_t*>(data + L.hog_off[q]);
+            else it.hog = reinterpret_cast<float*>(data + L.hog_off[q]);
+            it.lbp = data + L.lbp_off[q];
+            it.scores = reinterpret_cast<float*>(data + L.sc_off[q]);
+            it.frame = f;
+            it.level = k;
+            geoms[f].wh[k][0] = it.w;
+            geoms[f].wh[k][1] = it.h;
+            if (!direct)
+                for (int ty = 0; ty < resize_tiles_y(it.h); ++ty)
+                    for (int tx = 0; tx < resize_tiles_x(it.w); ++tx) t_rs[nrs++] = Tile{q, ty, tx, 0};
+            for (int ty = 0; ty < feat_tiles_y(it.hc, tu.feat_rows); ++ty)
+                for (int tx = 0; tx < feat_tiles_x(it.wc); ++tx) t_ft[nft++] = Tile{q, ty, tx, 0};
+            if (L.bf16 && n_models == 1) {
+                for (int tx = 0; tx < ceil_div(it.nx, RG_TILE_C); ++tx) t_sc[nsc++] = Tile{q, 0, tx, 0};
+            } else if (L.bf16) {
+                for (int ty = 0; ty < ceil_div(it.ny, MF_TILE_R); ++ty)
+                    for (int tx = 0; tx < ceil_div(it.nx, MF_TILE_C); ++tx) t_sc[nsc++] = Tile{q, ty, tx, 0};
+            } else {
+                for (int m = 0; m < n_models; ++m)
+                    for (int ty = 0; ty < score_tiles_y(it.ny, tu.score_rows); ++ty)
+                        for (int tx = 0; tx < score_tiles_x(it.nx); ++tx) t_sc[nsc++] = Tile{q, ty, tx, m};
+            }
+            for (int c = 0; c < ceil_div(it.nx * it.ny, CP_N); ++c) t_cp[ncp++] = Tile{q, 0, c, 0};
+        }
+    }
+    const Tile* d_tiles = reinterpret_cast<const Tile*>(ws + L.off_tiles);
+    R.items = reinterpret_cast<const LevelItem*>(ws + L.off_items);
+    R.t_rs = d_tiles;
+    R.t_ft = d_tiles + L.n_rs;
+    R.t_sc = d_tiles + L.n_rs + L.n_ft;
+    R.t_cp = d_tiles + L.n_rs + L.n_ft + L.n_sc;
+    R.nrs = nrs;
+    R.nft = nft;
+    R.nsc = nsc;
+    R.ncp = ncp;
+    R.geoms = reinterpret_cast<const NmsGeom*>(ws + L.off_geoms);
+    R.first = reinterpret_cast<const int32_t*>(ws + L.off_first);
+    R.counters = reinterpret_cast<int32_t*>(ws + L.off_counters);
+    R.near_count = reinterpret_cast<int32_t*>(ws + L.off_near_count);
+    R.cscore = reinterpret_cast<float*>(ws + L.off_cscore);
+    R.ckey = reinterpret_cast<int4*>(ws + L.off_ckey);
+    R.c64 = L.bf16 ? reinterpret_cast<double*>(ws + L.off_c64) : nullptr;
+    R.near_key = L.bf16 ? reinterpret_cast<int4*>(ws + L.off_near_key) : nullptr;
+    R.packed = L.bf16 ? reinterpret_cast<uint16_t*>(ws + L.off_packed) : nullptr;
+    R.n_zero = (int)((L.off_cscore - L.off_counters) / 4);
+}
+
+// The kernel sequence of one call (tables already uploaded).  Only kernels are
+// enqueued here, so the sequence can be captured into a graph.
+int enqueue_detect(const DetectRun& R, const DetectLayout& L, const Tuning& tu, const float* weights,
+                   const float* bias, int n_models, const pd_params* params, const double* thresholds, int n_frames,
+                   pd_box* boxes, int cap, pd_counts* counts, StageMarks& marks, hipStream_t s) {
+    int rc;
+    marks.mark(PD_STAGE_ZERO, s);
+    if ((rc = hip_status(launch_zero_i32(R.counters, R.n_zero, s), "zero"))) return rc;
+    if (L.bf16) {
+        if ((rc = hip_status(launch_pack_weights(weights, n_models, R.packed, s), "pack"))) return rc;
+        if ((rc = hip_status(launch_pack_rowgemm(weights, R.packed + packed_weight_elems(), s), "pack"))) return rc;
+    }
+    marks.mark(PD_STAGE_RESIZE, s);
+    if ((rc = hip_status(launch_resize_table(R.items, R.t_rs, R.nrs, s), "resize"))) return rc;
+    marks.mark(PD_STAGE_FEATURES, s);
+    if ((rc = hip_status(launch_features_table(R.items, R.t_ft, R.nft, params->features, params->clip, params->eps,
+                                               tu, s),
+                         "features")))
+        return rc;
+    marks.mark(PD_STAGE_SCORE, s);
+    if (L.bf16 && n_models == 1 && params->features == (PD_FEAT_HOG | PD_FEAT_LBP)) {
+        if ((rc = hip_status(launch_rowgemm_table(R.items, R.t_sc, R.nsc, R.packed + packed_weight_elems(), bias,
+                                                  tu.grid, s),
+                             "bf16 score")))
+            return rc;
+    } else if (L.bf16) {
+        if ((rc = hip_status(launch_mfma_table(R.items, R.t_sc, R.nsc, R.packed, bias, n_models, params->features,
+                                               tu.grid, s),
+                             "bf16 score")))
+            return rc;
+    } else if ((rc = hip_status(launch_score_table(R.items, R.t_sc, R.nsc, weights, bias, n_models,
+                                                   params->features, tu, s),
+                                "score"))) {
+        return rc;
+    }
+    marks.mark(PD_STAGE_COMPACT, s);
+    if ((rc = hip_status(launch_compact_margin(R.items, R.t_cp, R.ncp, n_models, thresholds,
+                                               L.bf16 ? params->margin : 0.0f, R.counters, R.cscore, R.ckey, R.c64,
+                                               R.near_count, R.near_key, n_frames, s),
+                         "compact")))
+        return rc;
+    if (L.bf16 && (rc = hip_status(launch_rescore64(R.items, R.first, n_frames, R.near_count, R.near_key, weights,
+                                                    bias, n_models, params->clip, params->eps, thresholds,
+                                                    R.counters, R.cscore, R.ckey, R.c64, s),
+                                   "rescore")))
+        return rc;
+    marks.mark(PD_STAGE_NMS, s);
+    return hip_status(launch_nms_table(R.geoms, n_frames, R.counters, R.cscore, R.ckey, R.c64,
+                                       L.bf16 ? R.near_count : nullptr, boxes, cap, counts, s),
+                      "nms");
+}
 
 }  // namespace
 
@@ -493,23 +684,10 @@ int64_t pd_detect_workspace_bytes(const pd_frame* frames, int n_frames, const pd
 int pd_detect(const pd_frame* frames, int n_frames, const float* weights, const float* bias, int n_models,
               const pd_params* params, const double* thresholds, void* workspace, int64_t workspace_bytes,
               pd_box* boxes, int cap, pd_counts* counts, void* stream) {
-    if (!check_params(params)) return PD_E_ARG;
-    if (!frames || n_frames < 1) return fail(PD_E_ARG, "frames is NULL or n_frames < 1");
-    const int max_m = params->precision == PD_PREC_BF16 ? PD_MAX_MODELS_BF16 : PD_MAX_MODELS;
-    if (n_models < 1 || n_models > max_m) return fail(PD_E_SIZE, "n_models outside [1, %d]", max_m);
-    if (!weights || !bias || !thresholds || !counts || (cap > 0 && !boxes) || cap < 0)
-        return fail(PD_E_ARG, "NULL pointer argument");
-    for (int f = 0; f < n_frames; ++f) {
-        if (int rc = check_image(frames[f].data, frames[f].w, frames[f].h, frames[f].pitch, "frame")) return rc;
-    }
     DetectLayout L;
-    if (!plan_detect(frames, n_frames, params, n_models, L)) return PD_E_SIZE;
-    if (!workspace || workspace_bytes < L.total)
-        return fail(PD_E_WORKSPACE, "workspace of %lld bytes, need %lld", (long long)workspace_bytes,
-                    (long long)L.total);
-    if ((uintptr_t)workspace & (kAlign - 1)) return fail(PD_E_ARG, "workspace must be 256-byte aligned");
-    uint8_t* ws = static_cast<uint8_t*>(workspace);
-    uint8_t* data = ws + L.off_data;
+    if (int rc = validate_detect(frames, n_frames, weights, bias, n_models, params, thresholds, workspace,
+                                 workspace_bytes, boxes, cap, counts, L))
+        return rc;
     hipStream_t s = (hipStream_t)stream;
 
     // host tables, built in a pinned staging slot
@@ -530,130 +708,157 @@ int pd_detect(const pd_frame* frames, int n_frames, const float* weights, const 
         if (int rc = hip_status(hipHostMalloc(&slot.host, want, hipHostMallocDefault), "staging alloc")) return rc;
         slot.size = want;
     }
-    uint8_t* stage = static_cast<uint8_t*>(slot.host);
-    std::memset(stage, 0, (size_t)L.table_bytes);
-    LevelItem* items = reinterpret_cast<LevelItem*>(stage + L.off_items);
-    Tile* tiles = reinterpret_cast<Tile*>(stage + L.off_tiles);
-    NmsGeom* geoms = reinterpret_cast<NmsGeom*>(stage + L.off_geoms);
-    int32_t* first = reinterpret_cast<int32_t*>(stage + L.off_first);
-    Tile* t_rs = tiles;
-    Tile* t_ft = t_rs + L.n_rs;
-    Tile* t_sc = t_ft + L.n_ft;
-    Tile* t_cp = t_sc + L.n_sc;
-    int q = 0, nrs = 0, nft = 0, nsc = 0, ncp = 0;
-    for (int f = 0; f < n_frames; ++f) {
-        geoms[f].n_levels = L.level_count[f];
-        first[f] = q;
-        for (int k = 0; k < L.level_count[f]; ++k, ++q) {
-            LevelItem& it = items[q];
-            item_geometry(it, L.sizes[2 * q], L.sizes[2 * q + 1]);
-            it.src = frames[f].data;
-            it.src_w = frames[f].w;
-            it.src_h = frames[f].h;
-            it.src_pitch = frames[f].pitch;
-            const bool direct = k == 0 && (((uintptr_t)frames[f].data | (uintptr_t)frames[f].pitch) & 7) == 0;
-            if (direct) {
-                it.pyr = const_cast<uint8_t*>(frames[f].data);
-                it.pitch = frames[f].pitch;
-            } else {
-                it.pyr = data + L.pyr_off[q];
-                it.pitch = (int)align_up(it.w, 16);
-            }
-            if (L.bf16) it.hog16 = reinterpret_cast<uint16_t*>(data + L.hog_off[q]);
-            else it.hog = reinterpret_cast<float*>(data + L.hog_off[q]);
-            it.lbp = data + L.lbp_off[q];
-            it.scores = reinterpret_cast<float*>(data + L.sc_off[q]);
-            it.frame = f;
-            it.level = k;
-            geoms[f].wh[k][0] = it.w;
-            geoms[f].wh[k][1] = it.h;
-            if (!direct)
-                for (int ty = 0; ty < resize_tiles_y(it.h); ++ty)
-                    for (int tx = 0; tx < resize_tiles_x(it.w); ++tx) t_rs[nrs++] = Tile{q, ty, tx, 0};
-            for (int ty = 0; ty < feat_tiles_y(it.hc); ++ty)
-                for (int tx = 0; tx < feat_tiles_x(it.wc); ++tx) t_ft[nft++] = Tile{q, ty, tx, 0};
-            if (L.bf16 && n_models == 1) {
-                for (int tx = 0; tx < ceil_div(it.nx, RG_TILE_C); ++tx) t_sc[nsc++] = Tile{q, 0, tx, 0};
-            } else if (L.bf16) {
-                for (int ty = 0; ty < ceil_div(it.ny, MF_TILE_R); ++ty)
-                    for (int tx = 0; tx < ceil_div(it.nx, MF_TILE_C); ++tx) t_sc[nsc++] = Tile{q, ty, tx, 0};
-            } else {
-                for (int m = 0; m < n_models; ++m)
-                    for (int ty = 0; ty < score_tiles_y(it.ny); ++ty)
-                        for (int tx = 0; tx < score_tiles_x(it.nx); ++tx) t_sc[nsc++] = Tile{q, ty, tx, m};
-            }
-            for (int c = 0; c < ceil_div(it.nx * it.ny, CP_N); ++c) t_cp[ncp++] = Tile{q, 0, c, 0};
-        }
-    }
-    const LevelItem* d_items = reinterpret_cast<const LevelItem*>(ws + L.off_items);
-    const Tile* d_tiles = reinterpret_cast<const Tile*>(ws + L.off_tiles);
-    const NmsGeom* d_geoms = reinterpret_cast<const NmsGeom*>(ws + L.off_geoms);
-    const int32_t* d_first = reinterpret_cast<const int32_t*>(ws + L.off_first);
-    int32_t* d_counters = reinterpret_cast<int32_t*>(ws + L.off_counters);
-    int32_t* d_near_count = reinterpret_cast<int32_t*>(ws + L.off_near_count);
-    float* d_cscore = reinterpret_cast<float*>(ws + L.off_cscore);
-    int4* d_ckey = reinterpret_cast<int4*>(ws + L.off_ckey);
-    double* d_c64 = L.bf16 ? reinterpret_cast<double*>(ws + L.off_c64) : nullptr;
-    int4* d_near_key = L.bf16 ? reinterpret_cast<int4*>(ws + L.off_near_key) : nullptr;
-    uint16_t* d_packed = L.bf16 ? reinterpret_cast<uint16_t*>(ws + L.off_packed) : nullptr;
+    DetectRun R;
+    fill_tables(frames, n_frames, n_models, tuning_of(params), L, static_cast<uint8_t*>(workspace),
+                static_cast<uint8_t*>(slot.host), R);
 
     int rc;
     StageMarks marks(g_prof.on);
     marks.mark(PD_STAGE_UPLOAD, s);
-    if ((rc = hip_status(hipMemcpyAsync(ws, stage, (size_t)L.table_bytes, hipMemcpyHostToDevice, s),
+    if ((rc = hip_status(hipMemcpyAsync(workspace, slot.host, (size_t)L.table_bytes, hipMemcpyHostToDevice, s),
                          "table upload")))
         return rc;
     if ((rc = hip_status(hipEventRecord(slot.ev, s), "staging record"))) return rc;
     slot.pending = true;
-    marks.mark(PD_STAGE_ZERO, s);
-    // candidate and near counters are adjacent: one clear
-    if ((rc = hip_status(launch_zero_i32(d_counters, (int)((L.off_cscore - L.off_counters) / 4), s), "zero")))
-        return rc;
-    if (L.bf16) {
-        if ((rc = hip_status(launch_pack_weights(weights, n_models, d_packed, s), "pack"))) return rc;
-        if ((rc = hip_status(launch_pack_rowgemm(weights, d_packed + packed_weight_elems(), s), "pack"))) return rc;
-    }
-    marks.mark(PD_STAGE_RESIZE, s);
-    if ((rc = hip_status(launch_resize_table(d_items, d_tiles, nrs, s), "resize"))) return rc;
-    marks.mark(PD_STAGE_FEATURES, s);
-    if ((rc = hip_status(launch_features_table(d_items, d_tiles + L.n_rs, L.n_ft, params->features,
-                                               params->clip, params->eps, s),
-                         "features")))
-        return rc;
-    marks.mark(PD_STAGE_SCORE, s);
-    if (L.bf16 && n_models == 1 && params->features == (PD_FEAT_HOG | PD_FEAT_LBP)) {
-        if ((rc = hip_status(launch_rowgemm_table(d_items, d_tiles + L.n_rs + L.n_ft, L.n_sc,
-                                                  d_packed + packed_weight_elems(), bias, s),
-                             "bf16 score")))
-            return rc;
-    } else if (L.bf16) {
-        if ((rc = hip_status(launch_mfma_table(d_items, d_tiles + L.n_rs + L.n_ft, L.n_sc, d_packed, bias, n_models,
-                                               params->features, s),
-                             "bf16 score")))
-            return rc;
-    } else if ((rc = hip_status(launch_score_table(d_items, d_tiles + L.n_rs + L.n_ft, L.n_sc, weights, bias,
-                                                   n_models, params->features, s),
-                                "score"))) {
-        return rc;
-    }
-    marks.mark(PD_STAGE_COMPACT, s);
-    if ((rc = hip_status(launch_compact_margin(d_items, d_tiles + L.n_rs + L.n_ft + L.n_sc, L.n_cp, n_models,
-                                               thresholds, L.bf16 ? params->margin : 0.0f, d_counters, d_cscore,
-                                               d_ckey, d_c64, d_near_count, d_near_key, n_frames, s),
-                         "compact")))
-        return rc;
-    if (L.bf16 && (rc = hip_status(launch_rescore64(d_items, d_first, n_frames, d_near_count, d_near_key, weights,
-                                                    bias, n_models, params->clip, params->eps, thresholds,
-                                                    d_counters, d_cscore, d_ckey, d_c64, s),
-                                   "rescore")))
-        return rc;
-    marks.mark(PD_STAGE_NMS, s);
-    rc = hip_status(launch_nms_table(d_geoms, n_frames, d_counters, d_cscore, d_ckey, d_c64,
-                                     L.bf16 ? d_near_count : nullptr, boxes, cap, counts, s),
-                    "nms");
+    rc = enqueue_detect(R, L, tuning_of(params), weights, bias, n_models, params, thresholds, n_frames, boxes, cap,
+                        counts, marks, s);
     marks.mark(PD_N_STAGES, s);
     marks.commit();
     return rc;
+}
+
+struct pd_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+int pd_graph_create(const pd_frame* frames, int n_frames, const float* weights, const float* bias, int n_models,
+                    const pd_params* params, const double* thresholds, void* workspace, int64_t workspace_bytes,
+                    pd_box* boxes, int cap, pd_counts* counts, void* stream, pd_graph** out) {
+    if (!out) return fail(PD_E_ARG, "out is NULL");
+    *out = nullptr;
+    DetectLayout L;
+    if (int rc = validate_detect(frames, n_frames, weights, bias, n_models, params, thresholds, workspace,
+                                 workspace_bytes, boxes, cap, counts, L))
+        return rc;
+    // the tables are uploaded once, now; the graph holds only kernels
+    std::vector<uint8_t> host((size_t)L.table_bytes);
+    DetectRun R;
+    fill_tables(frames, n_frames, n_models, tuning_of(params), L, static_cast<uint8_t*>(workspace), host.data(), R);
+    hipStream_t s = (hipStream_t)stream;
+    int rc;
+    if ((rc = hip_status(hipMemcpyAsync(workspace, host.data(), host.size(), hipMemcpyHostToDevice, s),
+                         "table upload")))
+        return rc;
+    if ((rc = hip_status(hipStreamSynchronize(s), "table upload"))) return rc;
+
+    hipStream_t cs = nullptr;  // capture needs a stream other than the null stream
+    if ((rc = hip_status(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "capture stream"))) return rc;
+    pd_graph* g = new pd_graph();
+    rc = hip_status(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture");
+    if (!rc) {
+        StageMarks none(false);
+        const int rc_enq = enqueue_detect(R, L, tuning_of(params), weights, bias, n_models, params, thresholds,
+                                          n_frames, boxes, cap, counts, none, cs);
+        const int rc_end = hip_status(hipStreamEndCapture(cs, &g->graph), "end capture");
+        rc = rc_enq ? rc_enq : rc_end;
+    }
+    if (!rc) rc = hip_status(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0), "graph instantiate");
+    (void)hipStreamDestroy(cs);
+    if (rc) {
+        if (g->exec) (void)hipGraphExecDestroy(g->exec);
+        if (g->graph) (void)hipGraphDestroy(g->graph);
+        delete g;
+        return rc;
+    }
+    *out = g;
+    return PD_OK;
+}
+
+int pd_graph_launch(pd_graph* g, void* stream) {
+    if (!g || !g->exec) return fail(PD_E_ARG, "graph is NULL");
+    return hip_status(hipGraphLaunch(g->exec, (hipStream_t)stream), "graph launch");
+}
+
+int pd_graph_destroy(pd_graph* g) {
+    if (!g) return PD_OK;
+    int rc = PD_OK;
+    if (g->exec) rc = hip_status(hipGraphExecDestroy(g->exec), "graph exec destroy");
+    if (g->graph) {
+        const int r2 = hip_status(hipGraphDestroy(g->graph), "graph destroy");
+        rc = rc ? rc : r2;
+    }
+    delete g;
+    return rc;
+}
+
+int pd_autotune(const pd_frame* frames, int n_frames, const float* weights, const float* bias, int n_models,
+                const pd_params* params, const double* thresholds, void* workspace, int64_t workspace_bytes,
+                pd_box* boxes, int cap, pd_counts* counts, int iters, pd_params* best, float* best_ms,
+                void* stream) {
+    if (!best) return fail(PD_E_ARG, "best is NULL");
+    if (iters < 1 || iters > 1000) return fail(PD_E_ARG, "iters outside [1, 1000]");
+    {
+        DetectLayout L;
+        if (int rc = validate_detect(frames, n_frames, weights, bias, n_models, params, thresholds, workspace,
+                                     workspace_bytes, boxes, cap, counts, L))
+            return rc;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const bool prof = g_prof.on;
+    g_prof.on = false;  // tuning calls stay out of the stage profile
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = hip_status(hipEventCreate(&e0), "event");
+    if (!rc) rc = hip_status(hipEventCreate(&e1), "event");
+    // one untimed call, then `iters` calls between two events
+    auto time_of = [&](const pd_params& p, float* ms) -> int {
+        int r = pd_detect(frames, n_frames, weights, bias, n_models, &p, thresholds, workspace, workspace_bytes,
+                          boxes, cap, counts, stream);
+        if (!r) r = hip_status(hipEventRecord(e0, s), "event");
+        for (int k = 0; k < iters && !r; ++k)
+            r = pd_detect(frames, n_frames, weights, bias, n_models, &p, thresholds, workspace, workspace_bytes,
+                          boxes, cap, counts, stream);
+        if (!r) r = hip_status(hipEventRecord(e1, s), "event");
+        if (!r) r = hip_status(hipEventSynchronize(e1), "event");
+        if (!r) r = hip_status(hipEventElapsedTime(ms, e0, e1), "event");
+        *ms /= (float)iters;
+        return r;
+    };
+    pd_params cur = *params;
+    const Tuning t0 = tuning_of(params);
+    cur.tune_feat_rows = t0.feat_rows;
+    cur.tune_score_rows = t0.score_rows;
+    float cur_ms = 0.0f;
+    if (!rc) rc = time_of(cur, &cur_ms);
+    // one knob at a time (the stages they shape are independent)
+    const int feat_rows[] = {4, 6, 8, 12, 16};
+    const int score_rows[] = {8, 16};
+    const int grids[] = {0, 256, 512, 1024, 2048};
+    for (int knob = 0; knob < 3 && !rc; ++knob) {
+        const int* vals = knob == 0 ? feat_rows : knob == 1 ? score_rows : grids;
+        const int n = knob == 0 ? 5 : knob == 1 ? 2 : 5;
+        if (knob == 1 && params->precision != PD_PREC_F32) continue;  // FP32 scoring only
+        for (int v = 0; v < n && !rc; ++v) {
+            pd_params c = cur;
+            int& field = knob == 0 ? c.tune_feat_rows : knob == 1 ? c.tune_score_rows : c.tune_grid;
+            const int now = knob == 0 ? cur.tune_feat_rows : knob == 1 ? cur.tune_score_rows : cur.tune_grid;
+            if (vals[v] == now) continue;
+            field = vals[v];
+            float ms = 0.0f;
+            rc = time_of(c, &ms);
+            if (!rc && ms < cur_ms) {
+                cur = c;
+                cur_ms = ms;
+            }
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    g_prof.on = prof;
+    if (rc) return rc;
+    *best = cur;
+    if (best_ms) *best_ms = cur_ms;
+    return PD_OK;
 }
 
 int pd_detect_candidates(const pd_frame* frames, int n_frames, const pd_params* params, int n_models,

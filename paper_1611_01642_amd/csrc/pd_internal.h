@@ -72,9 +72,16 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
 __host__ __device__ inline int resize_tiles_x(int w) { return ceil_div(w, RS_TX); }
 __host__ __device__ inline int resize_tiles_y(int h) { return ceil_div(h, RS_TY); }
 __host__ __device__ inline int feat_tiles_x(int wc) { return wc <= 1 ? 1 : ceil_div(wc - 1, FT_BX); }
-__host__ __device__ inline int feat_tiles_y(int hc) { return hc <= 1 ? 1 : ceil_div(hc - 1, FT_CH); }
+__host__ __device__ inline int feat_tiles_y(int hc, int rows = FT_CH) { return hc <= 1 ? 1 : ceil_div(hc - 1, rows); }
 __host__ __device__ inline int score_tiles_x(int nx) { return ceil_div(nx, SC_W); }
-__host__ __device__ inline int score_tiles_y(int ny) { return ceil_div(ny, SC_R); }
+__host__ __device__ inline int score_tiles_y(int ny, int rows = SC_R) { return ceil_div(ny, rows); }
+
+// Tile shapes and launch shapes chosen at run time (pd_params tuning fields).
+struct Tuning {
+    int feat_rows = FT_CH;   // block rows per feature strip (2..32)
+    int score_rows = SC_R;   // FP32 scoring: window rows per wave (8 or 16)
+    int grid = 0;            // 0: one workgroup per tile group; > 0: at most this many, looping
+};
 
 // ---- launchers (each defined next to its kernel) ---------------------------
 hipError_t launch_resize_single(const LevelItem* items, int n_items, hipStream_t s);
@@ -85,27 +92,27 @@ hipError_t launch_lbp_codes(const uint8_t* img, int w, int h, int pitch, uint8_t
 hipError_t launch_features_single(const LevelItem& it, int features, float clip, float eps,
                                   hipStream_t s);
 hipError_t launch_features_table(const LevelItem* items, const Tile* tiles, int n_tiles,
-                                 int features, float clip, float eps, hipStream_t s);
+                                 int features, float clip, float eps, const Tuning& tu, hipStream_t s);
 
 hipError_t launch_score_single(const LevelItem& it, const float* w, const float* bias, int n_models,
                                int features, hipStream_t s);
 hipError_t launch_score_table(const LevelItem* items, const Tile* tiles, int n_tiles,
                               const float* w, const float* bias, int n_models, int features,
-                              hipStream_t s);
+                              const Tuning& tu, hipStream_t s);
 
 int64_t packed_weight_elems();
 int64_t rowgemm_packed_elems();
 hipError_t launch_pack_rowgemm(const float* w, uint16_t* out, hipStream_t s);
 hipError_t launch_rowgemm_single(const LevelItem& it, const uint16_t* packed, const float* bias, hipStream_t s);
 hipError_t launch_rowgemm_table(const LevelItem* items, const Tile* tiles, int n_tiles, const uint16_t* packed,
-                                const float* bias, hipStream_t s);
+                                const float* bias, int grid, hipStream_t s);
 // row-GEMM scoring (one model): tile = 64 window columns, all rows
 constexpr int RG_TILE_C = 64;
 hipError_t launch_pack_weights(const float* w, int n_models, uint16_t* out, hipStream_t s);
 hipError_t launch_mfma_single(const LevelItem& it, const uint16_t* wpk, const float* bias, int n_models, int features,
                               hipStream_t s);
 hipError_t launch_mfma_table(const LevelItem* items, const Tile* tiles, int n_tiles, const uint16_t* wpk,
-                             const float* bias, int n_models, int features, hipStream_t s);
+                             const float* bias, int n_models, int features, int grid, hipStream_t s);
 // windows with |score - threshold| < margin go to the near list (margin <= 0: none)
 hipError_t launch_compact_margin(const LevelItem* items, const Tile* tiles, int n_tiles, int n_models,
                                  const double* thresholds, float margin, int32_t* counters, float* cand_score,

@@ -209,13 +209,23 @@ __global__ void __launch_bounds__(256) rowgemm_single_kernel(LevelItem it, const
     rowgemm_tile(it, packed, bias[0], blockIdx.x, sm);
 }
 
+// With LOOP a capped grid strides over the tile table (each tile ends on a
+// barrier).
+template <bool LOOP>
 __global__ void __launch_bounds__(256) rowgemm_table_kernel(const LevelItem* __restrict__ items,
-                                                            const Tile* __restrict__ tiles,
+                                                            const Tile* __restrict__ tiles, int n_tiles,
                                                             const uint16_t* __restrict__ packed,
                                                             const float* __restrict__ bias) {
     __shared__ RowShared sm;
-    const Tile tl = tiles[blockIdx.x];
-    rowgemm_tile(items[tl.item], packed, bias[0], tl.tx, sm);
+    if constexpr (LOOP) {
+        for (int t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+            const Tile tl = tiles[t];
+            rowgemm_tile(items[tl.item], packed, bias[0], tl.tx, sm);
+        }
+    } else {
+        const Tile tl = tiles[blockIdx.x];
+        rowgemm_tile(items[tl.item], packed, bias[0], tl.tx, sm);
+    }
 }
 
 }  // namespace
@@ -234,9 +244,12 @@ hipError_t launch_rowgemm_single(const LevelItem& it, const uint16_t* packed, co
 }
 
 hipError_t launch_rowgemm_table(const LevelItem* items, const Tile* tiles, int n_tiles, const uint16_t* packed,
-                                const float* bias, hipStream_t s) {
+                                const float* bias, int grid, hipStream_t s) {
     if (n_tiles <= 0) return hipSuccess;
-    rowgemm_table_kernel<<<n_tiles, 256, 0, s>>>(items, tiles, packed, bias);
+    if (grid > 0 && grid < n_tiles)
+        rowgemm_table_kernel<true><<<grid, 256, 0, s>>>(items, tiles, n_tiles, packed, bias);
+    else
+        rowgemm_table_kernel<false><<<n_tiles, 256, 0, s>>>(items, tiles, n_tiles, packed, bias);
     return hipGetLastError();
 }
 

@@ -4,36 +4,42 @@
 // the model:  s(i,j) = sum_c sum_a sum_b F_c[i+a][j+b] * W[a][b][c] + bias.
 // Algorithm 6 gives each window a warp that re-reads the window's whole
 // feature vector.  Here one wave64 owns a tile of 64 adjacent window columns
-// (one per lane) x SC_R window rows (registers).  For each feature plane c the
-// wave stages the tile's (SC_R + 14 or 15) x (64 + 6 or 7) patch in its own
+// (one per lane) x R window rows (registers; R = 8 or 16).  For each feature plane c the
+// wave stages the tile's (R + 14 or 15) x (64 + 6 or 7) patch in its own
 // LDS region (coalesced loads of the next plane are in flight while the
 // current one is used), then every patch value a lane reads from LDS serves up
-// to SC_R windows of its column.  Weights are wave-uniform (scalar loads).
+// to R windows of its column.  Weights are wave-uniform (scalar loads).
 // FP32 products and FP32 sums in a fixed order.
 #include "pd_internal.h"
 
 namespace pd {
 namespace {
 
-constexpr int HOG_PR = SC_R + PD_WIN_BLOCKS_Y - 1;  // patch rows
-constexpr int HOG_PC = SC_W + PD_WIN_BLOCKS_X - 1;  // patch columns
-constexpr int LBP_PR = SC_R + PD_WIN_CELLS_Y - 1;
-constexpr int LBP_PC = SC_W + PD_WIN_CELLS_X - 1;
-constexpr int HOG_PQ = (HOG_PR * HOG_PC + 63) / 64;  // patch values per lane
-constexpr int LBP_PQ = (LBP_PR * LBP_PC + 63) / 64;
-constexpr int PATCH = (HOG_PR * HOG_PC > LBP_PR * LBP_PC ? HOG_PR * HOG_PC : LBP_PR * LBP_PC);
+// Patch geometry for R window rows per wave.
+template <int R>
+struct Patch {
+    static constexpr int HOG_PR = R + PD_WIN_BLOCKS_Y - 1;  // patch rows
+    static constexpr int HOG_PC = SC_W + PD_WIN_BLOCKS_X - 1;  // patch columns
+    static constexpr int LBP_PR = R + PD_WIN_CELLS_Y - 1;
+    static constexpr int LBP_PC = SC_W + PD_WIN_CELLS_X - 1;
+    static constexpr int HOG_PQ = (HOG_PR * HOG_PC + 63) / 64;  // patch values per lane
+    static constexpr int LBP_PQ = (LBP_PR * LBP_PC + 63) / 64;
+    static constexpr int SIZE = (HOG_PR * HOG_PC > LBP_PR * LBP_PC ? HOG_PR * HOG_PC : LBP_PR * LBP_PC);
+};
 
-template <int FEAT>
+template <int FEAT, int R>
 __device__ __forceinline__ void score_tile(const float* __restrict__ hog, const uint8_t* __restrict__ lbp, int wc,
                                            int hc, const float* __restrict__ wt, float bias, float* __restrict__ out,
                                            int ty, int tx, int lane, float* __restrict__ patch) {
+    constexpr int HOG_PR = Patch<R>::HOG_PR, HOG_PC = Patch<R>::HOG_PC, HOG_PQ = Patch<R>::HOG_PQ;
+    constexpr int LBP_PR = Patch<R>::LBP_PR, LBP_PC = Patch<R>::LBP_PC, LBP_PQ = Patch<R>::LBP_PQ;
     const int hb = hc - 1, wb = wc - 1;
     const int ny = hc - PD_WIN_CELLS_Y + 1, nx = wc - PD_WIN_CELLS_X + 1;
-    const int i0 = ty * SC_R;
+    const int i0 = ty * R;
     const int j0 = tx * SC_W;
-    float acc[SC_R];
+    float acc[R];
 #pragma unroll
-    for (int r = 0; r < SC_R; ++r) acc[r] = 0.0f;
+    for (int r = 0; r < R; ++r) acc[r] = 0.0f;
 
     if (FEAT & PD_FEAT_HOG) {
         const size_t plane = (size_t)hb * wb;
@@ -66,7 +72,7 @@ __device__ __forceinline__ void score_tile(const float* __restrict__ hog, const 
                 for (int y = 0; y < HOG_PR; ++y) {
                     const float v = pr[y * HOG_PC];
 #pragma unroll
-                    for (int r = 0; r < SC_R; ++r) {
+                    for (int r = 0; r < R; ++r) {
                         const int a = y - r;
                         if (a >= 0 && a < PD_WIN_BLOCKS_Y) acc[r] = fmaf(v, wa[a], acc[r]);
                     }
@@ -107,7 +113,7 @@ __device__ __forceinline__ void score_tile(const float* __restrict__ hog, const 
                 for (int y = 0; y < LBP_PR; ++y) {
                     const float v = pr[y * LBP_PC];
 #pragma unroll
-                    for (int r = 0; r < SC_R; ++r) {
+                    for (int r = 0; r < R; ++r) {
                         const int a = y - r;
                         if (a >= 0 && a < PD_WIN_CELLS_Y) acc[r] = fmaf(v, wa[a], acc[r]);
                     }
@@ -119,7 +125,7 @@ __device__ __forceinline__ void score_tile(const float* __restrict__ hog, const 
     const int j = j0 + lane;
     if (j < nx) {
 #pragma unroll
-        for (int r = 0; r < SC_R; ++r) {
+        for (int r = 0; r < R; ++r) {
             const int i = i0 + r;
             if (i < ny) out[(size_t)i * nx + j] = acc[r] + bias;
         }
@@ -129,33 +135,41 @@ __device__ __forceinline__ void score_tile(const float* __restrict__ hog, const 
 template <int FEAT>
 __global__ void __launch_bounds__(256) score_single_kernel(LevelItem it, const float* __restrict__ wt,
                                                            const float* __restrict__ bias, int n_models) {
-    __shared__ float patches[SC_WAVES][PATCH];
+    __shared__ float patches[SC_WAVES][Patch<SC_R>::SIZE];
     const int wave = blockIdx.x * SC_WAVES + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int ntx = score_tiles_x(it.nx), nty = score_tiles_y(it.ny);
     const int per_model = ntx * nty;
     if (wave >= per_model * n_models) return;
     const int m = wave / per_model;
     const int local = wave - m * per_model;
-    score_tile<FEAT>(it.hog, it.lbp, it.wc, it.hc, wt + (size_t)m * PD_FEATURE_DIM, bias[m],
-                     it.scores + (size_t)m * it.ny * it.nx, local / ntx, local % ntx, threadIdx.x & 63,
-                     patches[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)]);
+    score_tile<FEAT, SC_R>(it.hog, it.lbp, it.wc, it.hc, wt + (size_t)m * PD_FEATURE_DIM, bias[m],
+                           it.scores + (size_t)m * it.ny * it.nx, local / ntx, local % ntx, threadIdx.x & 63,
+                           patches[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)]);
 }
 
-// Tile.pad carries the model index.
-template <int FEAT>
+// Tile.pad carries the model index; tiles of R window rows.  Waves are
+// independent; with LOOP a capped grid strides over the table (a separate
+// instantiation: the loop costs registers the one-tile form does not need).
+template <int FEAT, int R, bool LOOP>
 __global__ void __launch_bounds__(256) score_table_kernel(const LevelItem* __restrict__ items,
                                                           const Tile* __restrict__ tiles, int n_tiles,
                                                           const float* __restrict__ wt,
                                                           const float* __restrict__ bias) {
-    __shared__ float patches[SC_WAVES][PATCH];
-    const int wave = blockIdx.x * SC_WAVES + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (wave >= n_tiles) return;
-    const Tile tl = tiles[wave];
-    const LevelItem& it = items[tl.item];
-    const int m = tl.pad;
-    score_tile<FEAT>(it.hog, it.lbp, it.wc, it.hc, wt + (size_t)m * PD_FEATURE_DIM, bias[m],
-                     it.scores + (size_t)m * it.ny * it.nx, tl.ty, tl.tx, threadIdx.x & 63,
-                     patches[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)]);
+    __shared__ float patches[SC_WAVES][Patch<R>::SIZE];
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    auto one = [&](int wave) __attribute__((always_inline)) {
+        const Tile tl = tiles[wave];
+        const LevelItem& it = items[tl.item];
+        const int m = tl.pad;
+        score_tile<FEAT, R>(it.hog, it.lbp, it.wc, it.hc, wt + (size_t)m * PD_FEATURE_DIM, bias[m],
+                            it.scores + (size_t)m * it.ny * it.nx, tl.ty, tl.tx, threadIdx.x & 63, patches[wv]);
+    };
+    if constexpr (LOOP) {
+        for (int wave = blockIdx.x * SC_WAVES + wv; wave < n_tiles; wave += gridDim.x * SC_WAVES) one(wave);
+    } else {
+        const int wave = blockIdx.x * SC_WAVES + wv;
+        if (wave < n_tiles) one(wave);
+    }
 }
 
 template <int FEAT>
@@ -167,8 +181,17 @@ hipError_t score_single(const LevelItem& it, const float* w, const float* b, int
 
 template <int FEAT>
 hipError_t score_table(const LevelItem* items, const Tile* tiles, int n, const float* w, const float* b,
-                       hipStream_t s) {
-    score_table_kernel<FEAT><<<ceil_div(n, SC_WAVES), 256, 0, s>>>(items, tiles, n, w, b);
+                       const Tuning& tu, hipStream_t s) {
+    const int rows = tu.score_rows == 16 ? 16 : SC_R;
+    const int blocks = ceil_div(n, SC_WAVES);
+    if (tu.grid > 0 && tu.grid < blocks) {
+        if (rows == 16) score_table_kernel<FEAT, 16, true><<<tu.grid, 256, 0, s>>>(items, tiles, n, w, b);
+        else score_table_kernel<FEAT, SC_R, true><<<tu.grid, 256, 0, s>>>(items, tiles, n, w, b);
+    } else if (rows == 16) {
+        score_table_kernel<FEAT, 16, false><<<blocks, 256, 0, s>>>(items, tiles, n, w, b);
+    } else {
+        score_table_kernel<FEAT, SC_R, false><<<blocks, 256, 0, s>>>(items, tiles, n, w, b);
+    }
     return hipGetLastError();
 }
 
@@ -185,13 +208,13 @@ hipError_t launch_score_single(const LevelItem& it, const float* w, const float*
 }
 
 hipError_t launch_score_table(const LevelItem* items, const Tile* tiles, int n_tiles, const float* w,
-                              const float* bias, int n_models, int features, hipStream_t s) {
+                              const float* bias, int n_models, int features, const Tuning& tu, hipStream_t s) {
     (void)n_models;
     if (n_tiles <= 0) return hipSuccess;
     switch (features & (PD_FEAT_HOG | PD_FEAT_LBP)) {
-        case PD_FEAT_HOG: return score_table<PD_FEAT_HOG>(items, tiles, n_tiles, w, bias, s);
-        case PD_FEAT_LBP: return score_table<PD_FEAT_LBP>(items, tiles, n_tiles, w, bias, s);
-        default: return score_table<PD_FEAT_HOG | PD_FEAT_LBP>(items, tiles, n_tiles, w, bias, s);
+        case PD_FEAT_HOG: return score_table<PD_FEAT_HOG>(items, tiles, n_tiles, w, bias, tu, s);
+        case PD_FEAT_LBP: return score_table<PD_FEAT_LBP>(items, tiles, n_tiles, w, bias, tu, s);
+        default: return score_table<PD_FEAT_HOG | PD_FEAT_LBP>(items, tiles, n_tiles, w, bias, tu, s);
     }
 }
 

@@ -28,7 +28,7 @@ def test_library_loads_and_exports_every_declared_symbol():
 
 
 def test_struct_sizes_match_header():
-    assert ctypes.sizeof(pd.Params) == 40
+    assert ctypes.sizeof(pd.Params) == 48
     assert ctypes.sizeof(pd.Level) == 48
     assert ctypes.sizeof(pd.Frame) == 24
     assert pd.BOX_DTYPE.itemsize == 48
@@ -98,6 +98,30 @@ def test_argument_errors_enqueue_nothing():
     assert L.pd_nms(fake, fake, 4097, wh, 1, fake, 10, fake, nil) == pd.E_SIZE
     assert L.pd_nms(fake, fake, 10, wh, 0, fake, 10, fake, nil) == pd.E_SIZE
     assert L.pd_build_pyramid(fake, 100, 100, 100, nil, 65, fake, nil) == pd.E_SIZE
+
+
+def test_tuning_field_checks_and_graph_handles():
+    L = pd.lib()
+    fake = ctypes.c_void_p(0x1000)
+    nil = ctypes.c_void_p(0)
+    for kw in (dict(tune_feat_rows=3), dict(tune_feat_rows=33), dict(tune_score_rows=12), dict(tune_grid=-1)):
+        bad = pd.params(**kw)
+        assert L.pd_features(fake, 64, 64, 64, ctypes.byref(bad), fake, nil, fake, nil) == pd.E_ARG, kw
+        assert "tune" in L.pd_last_error().decode()
+    for kw in (dict(tune_feat_rows=4), dict(tune_feat_rows=32), dict(tune_score_rows=16), dict(tune_grid=1)):
+        assert pd.workspace_bytes([(1242, 375)], 2, pd.params(**kw)) == pd.workspace_bytes([(1242, 375)], 2)
+    assert L.pd_graph_destroy(nil) == 0
+    assert L.pd_graph_launch(nil, nil) == pd.E_ARG
+    arr = (pd.Frame * 1)()
+    arr[0].data, arr[0].w, arr[0].h, arr[0].pitch = 0x1000, 100, 100, 100
+    prm = pd.params()
+    assert L.pd_graph_create(arr, 1, fake, fake, 1, ctypes.byref(prm), fake, fake, 16, fake, 10, fake, nil,
+                             nil) == pd.E_ARG
+    best = pd.Params()
+    assert L.pd_autotune(arr, 1, fake, fake, 1, ctypes.byref(prm), fake, fake, 16, fake, 10, fake, 0,
+                         ctypes.byref(best), nil, nil) == pd.E_ARG
+    assert L.pd_autotune(arr, 1, fake, fake, 1, ctypes.byref(prm), fake, fake, 16, fake, 10, fake, 1,
+                         ctypes.byref(best), nil, nil) == pd.E_WORKSPACE
 
 
 def test_bf16_workspace_and_model_limit():
