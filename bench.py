@@ -31,17 +31,59 @@ PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3
 
 
-def _gen(seed):
+def _gen(args):
     import pd_synth
-    return pd_synth.frame(W0, H0, seed)
+    w, h, seed = args
+    return pd_synth.frame(w, h, seed)
 
 
-def make_frames(n, seed0=1000, workers=16):
+def make_frames(n, seed0=1000, workers=16, sizes=None):
     # threads, not processes: profilers preload themselves into child processes
     from concurrent.futures import ThreadPoolExecutor
-    seeds = [seed0 + f for f in range(n)]
-    with ThreadPoolExecutor(max_workers=min(workers, n)) as ex:
-        return list(ex.map(_gen, seeds))
+    sizes = sizes or [(W0, H0)] * n
+    jobs = [(w, h, seed0 + f) for f, (w, h) in enumerate(sizes)]
+    with ThreadPoolExecutor(max_workers=min(workers, len(jobs))) as ex:
+        return list(ex.map(_gen, jobs))
+
+
+MIXED = [(640, 480)] * 24 + [(1242, 375)] * 24 + [(1920, 1080)] * 16
+
+
+def time_calls(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def batched_leg(pd, torch, dev, wts, bias, thr_value, steps, warmup):
+    """64 frames of mixed sizes (24 x 640x480, 24 x 1242x375, 16 x 1920x1080)
+    in one pd_detect: autotuned tile shapes, then eager calls and replays of
+    the captured graph."""
+    host = make_frames(len(MIXED), seed0=2000, sizes=MIXED)
+    frames = [torch.from_numpy(h).to(dev) for h in host]
+    B = len(frames)
+    thr = torch.full((B,), thr_value, dtype=torch.float64, device=dev)
+    det = pd.Detector(frames, wts, bias, pd.params(), cap=1024)
+    tuning, tuned_ms = det.autotune(thr, iters=3)
+    el_eager = time_calls(torch, lambda: det.run(thr), steps, warmup)
+    det.capture(thr)
+    el_graph = time_calls(torch, det.replay, steps, warmup)
+    det.release()
+    _, counts = det.results()
+    px = sum(w * h for w, h in MIXED)
+    return {"workload": "64 synthetic frames of mixed sizes (24 x 640x480, 24 x 1242x375, 16 x 1920x1080), "
+                        "full pyramids at 11/10, FP32, 1 SVM, one pd_detect per step",
+            "tuning": tuning, "autotune_ms_per_call": round(tuned_ms, 4),
+            "eager_frames_per_s": round(B * steps / el_eager, 1),
+            "graph_frames_per_s": round(B * steps / el_graph, 1),
+            "graph_mpx_per_s": round(px * steps / el_graph / 1e6, 1),
+            "ms_per_step_graph": round(1000 * el_graph / steps, 4),
+            "overflow_frames": int(sum(c["overflow"] for c in counts))}
 
 
 def _oracle_frame(seed):
@@ -146,6 +188,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--no-latency", action="store_true")
     ap.add_argument("--no-bf16", action="store_true", help="skip the BF16 MFMA legs")
+    ap.add_argument("--no-batched", action="store_true", help="skip the mixed-size batched leg")
+    ap.add_argument("--no-tune", action="store_true", help="default tile shapes (no autotuning)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after timing, run one 256 MiB device-to-device copy (scales HBM byte counters)")
     args = ap.parse_args()
@@ -188,6 +232,11 @@ def main():
     thr = torch.full((B,), thr_value, dtype=torch.float64, device=dev)
 
     det = pd.Detector(frames, wts, bias, prm, cap=1024)
+    tuning = prm.tuning()
+    if not args.no_tune:
+        print("[bench] autotuning tile shapes", file=sys.stderr, flush=True)
+        tuning, _ = det.autotune(thr, iters=3)
+        prm = det.prm
     print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         det.run(thr)
@@ -206,7 +255,7 @@ def main():
     boxes, counts = det.results()
     per_launch = {k: v / max(calls, 1) for k, v in stage_ms.items()}
 
-    latency_ms = None
+    latency_ms = latency_graph_ms = None
     if not args.no_latency:
         one = pd.Detector(frames[:1], wts, bias, prm, cap=1024)
         for _ in range(10):
@@ -218,6 +267,9 @@ def main():
             one.run(thr[:1])
         torch.cuda.synchronize()
         latency_ms = 1000 * (time.perf_counter() - t1) / n1
+        one.capture(thr[:1])
+        latency_graph_ms = 1000 * time_calls(torch, one.replay, n1, 10) / n1
+        one.release()
 
     # algorithmic work per frame, from the plan
     windows = sum(L.win_x * L.win_y for L in levels)
@@ -259,7 +311,9 @@ def main():
         "score_tflops": round(score_flops / score_s / 1e12, 3),
         "features_gbs": round(feat_bytes / feat_s / 1e9, 1),
         "score_feature_read_gbs": round(score_bytes / score_s / 1e9, 1),
+        "tuning": tuning,
         "latency_ms_1frame": None if latency_ms is None else round(latency_ms, 4),
+        "latency_ms_1frame_graph": None if latency_graph_ms is None else round(latency_graph_ms, 4),
         "detections_per_frame": round(float(np.mean([c["kept"] for c in counts])), 2),
         "candidates_per_frame": round(float(np.mean([c["candidates"] for c in counts])), 2),
     }
@@ -281,6 +335,9 @@ def main():
                 "candidates_per_frame": round(float(np.mean([c["candidates"] for c in cnt])), 2),
                 "overflow_frames": int(sum(c["overflow"] for c in cnt))}
         out["bf16"] = legs
+    if not args.no_batched:
+        print("[bench] batched mixed-size leg", file=sys.stderr, flush=True)
+        out["batched_mixed64"] = batched_leg(pd, torch, dev, wts, bias, thr_value, args.steps, args.warmup)
     if args.calib_copy:
         src = torch.ones(64 << 20, dtype=torch.int32, device=dev)
         dst = torch.empty_like(src)
