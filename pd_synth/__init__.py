@@ -111,3 +111,21 @@ def svm_weights(n_models: int = 1, dim: int = FEATURE_DIM, seed0: int = 7) -> np
 
 def svm_bias(n_models: int = 1) -> np.ndarray:
     return np.zeros(n_models, dtype=np.float32)
+
+
+PRUNER_CHANNELS = (68, 32, 32, 16)
+
+
+def pruner_init(channels=PRUNER_CHANNELS, seed: int = 11) -> np.ndarray:
+    """Initial parameters of the window pruner as one float32 vector, laid out
+    per conv layer as weights [Cout][Cin][3][3] then bias [Cout], then the 1x1
+    head's weights [C] and bias: He-normal weights (std sqrt(2 / (9 Cin)),
+    head std sqrt(1 / C)), zero biases."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for cin, cout in zip(channels[:-1], channels[1:]):
+        parts.append(rng.normal(0.0, np.sqrt(2.0 / (9 * cin)), cout * cin * 9))
+        parts.append(np.zeros(cout))
+    parts.append(rng.normal(0.0, np.sqrt(1.0 / channels[-1]), channels[-1]))
+    parts.append(np.zeros(1))
+    return np.concatenate(parts).astype(np.float32)
