@@ -335,6 +335,86 @@ int pd_autotune(const pd_frame* frames, int n_frames, const float* weights,
                 pd_box* boxes, int cap, pd_counts* counts, int iters,
                 pd_params* best, float* best_ms, void* stream);
 
+/* ---- learned window pruner ------------------------------------------------
+ * Not part of the paper: a small network over per-cell features predicts
+ * which windows the linear SVM (Section 4.4) will score above the threshold,
+ * so that the others need not be scored.
+ *   cell map  : per 8x8 cell, 68 FP32 channels, planar [68][cells_y][cells_x]:
+ *               the cell's 9-bin orientation histogram (Section 4.3, the
+ *               gradients of Algorithm 4 and the votes of Algorithm 5) with
+ *               the full bilinear spatial kernel -- every pixel whose centre
+ *               is within 8 px per axis of the cell centre votes with weight
+ *               (1 - |dy|/8)(1 - |dx|/8) -- divided by sqrt(|h|^2 + eps^2),
+ *               then the 59 uniform-LBP counts (Section 4.2) / 64.
+ *   network   : conv3x3 68->32, ReLU, conv3x3 32->32, ReLU, conv3x3 32->16,
+ *               ReLU, 1x1 16->1; zero padding; one logit per cell; window
+ *               (i, j) takes the logit of cell (i + 7, j + 3).
+ *   parameters: one float vector of PD_PRUNER_PARAMS values: per conv layer
+ *               weights [Cout][Cin][3][3] then bias [Cout]; then the head's
+ *               weights [16] and bias [1].
+ */
+#define PD_PRUNER_CHANNELS 68
+#define PD_PRUNER_PARAMS   33505
+
+/* One map (pyramid level) of a pruner call; every pointer is a device
+   pointer, planar FP32, owned by the caller. */
+typedef struct pd_net_map {
+    const float* cellmap;  /* [68][cells_y][cells_x]                          */
+    float* logits;         /* [cells_y][cells_x], written                     */
+    const float* labels;   /* [cells_y][cells_x] 0/1, pd_pruner_gradient only */
+    const float* mask;     /* [cells_y][cells_x] 0/1, pd_pruner_gradient only */
+    int32_t cells_x, cells_y;
+} pd_net_map;
+
+/*
+ * pd_features_cellmap -- pd_features (FP32 HOG blocks and LBP cell counts)
+ * and, from the same pass over the pixels, the pruner's cell map of the
+ * level.  blocks [36][Hb][Wb], cell_hist [59][Hc][Wc] u8, cellmap
+ * [68][Hc][Wc] FP32 (device, caller-owned).  The HOG normalisation's eps
+ * (params->eps) is also the cell map's.  Errors: PD_E_SIZE if the level has
+ * no 16x16 block.
+ */
+int pd_features_cellmap(const uint8_t* level, int w, int h, int pitch, const pd_params* params,
+                        float* blocks, uint8_t* cell_hist, float* cellmap, void* stream);
+
+/* Workspace (device bytes, 256-byte aligned) of pd_pruner_forward and
+   pd_pruner_gradient for these maps (host array; sizes only are read). */
+int64_t pd_pruner_workspace_bytes(const pd_net_map* maps, int n_maps);
+
+/* pd_pruner_forward -- logits of every map (FP32 throughout). */
+int pd_pruner_forward(const pd_net_map* maps, int n_maps, const float* params,
+                      void* workspace, int64_t workspace_bytes, void* stream);
+
+/*
+ * pd_pruner_gradient -- forward, then the gradient of the class-weighted
+ * binary cross-entropy L = (1/N) sum over masked cells of
+ * -pos_weight*y*log(s) - (1 - y)*log(1 - s), s = sigmoid(logit), N = number
+ * of masked cells over all maps.  grad: device float [PD_PRUNER_PARAMS]
+ * (layout of params); stats: device double [2] = (L, N).  Deterministic:
+ * the same inputs give the same bits.
+ */
+int pd_pruner_gradient(const pd_net_map* maps, int n_maps, const float* params, float pos_weight,
+                       float* grad, double* stats, void* workspace, int64_t workspace_bytes,
+                       void* stream);
+
+/*
+ * pd_adam_step -- one Adam update (Kingma and Ba, bias-corrected) of n
+ * FP32 parameters in place: m = b1 m + (1-b1) g, v = b2 v + (1-b2) g^2,
+ * p -= lr * (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps).
+ * step >= 1 counts updates.  All arrays are device float [n].
+ */
+int pd_adam_step(float* params, const float* grad, float* m, float* v, int n, int step, float lr,
+                 float beta1, float beta2, float eps, void* stream);
+
+/*
+ * pd_window_labels -- training targets of one level: labels[cy][cx] = 1 iff
+ * window (cy - 7, cx - 3) exists and its score (scores [win_y][win_x], e.g.
+ * the max over models) is > *threshold (device double); mask = 1 where the
+ * window exists.  Requires cells = windows + (7, 15) per axis.
+ */
+int pd_window_labels(const float* scores, int win_x, int win_y, int cells_x, int cells_y,
+                     const double* threshold, float* labels, float* mask, void* stream);
+
 /*
  * pd_detect_candidates -- test hook: after pd_detect on the same arguments
  * (frames, params, n_models, workspace), enqueue copies of frame `frame`'s

@@ -28,6 +28,7 @@ FEAT_HOG, FEAT_LBP = 1, 2
 PREC_F32, PREC_BF16 = 0, 1
 MAX_MODELS_BF16 = 8
 MAX_NEAR = 1024
+PRUNER_CHANNELS, PRUNER_PARAMS = 68, 33505
 
 E_ARG, E_SIZE, E_WORKSPACE, E_HIP = -1, -2, -3, -4
 
@@ -57,6 +58,11 @@ class Level(ctypes.Structure):
                 ("blocks_x", ctypes.c_int32), ("blocks_y", ctypes.c_int32),
                 ("win_x", ctypes.c_int32), ("win_y", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("offset", ctypes.c_int64)]
+
+
+class NetMap(ctypes.Structure):
+    _fields_ = [("cellmap", ctypes.c_void_p), ("logits", ctypes.c_void_p), ("labels", ctypes.c_void_p),
+                ("mask", ctypes.c_void_p), ("cells_x", ctypes.c_int32), ("cells_y", ctypes.c_int32)]
 
 
 class Frame(ctypes.Structure):
@@ -111,6 +117,20 @@ _SIGS = {
                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                    ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                                    ctypes.c_void_p, ctypes.c_void_p]),
+    "pd_features_cellmap": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_void_p]),
+    "pd_pruner_workspace_bytes": (ctypes.c_int64, [ctypes.c_void_p, ctypes.c_int]),
+    "pd_pruner_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_int64, ctypes.c_void_p]),
+    "pd_pruner_gradient": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_float,
+                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                          ctypes.c_void_p]),
+    "pd_adam_step": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_int, ctypes.c_int, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                    ctypes.c_float, ctypes.c_void_p]),
+    "pd_window_labels": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "pd_nms": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
                               ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
     "pd_profile_enable": (ctypes.c_int, [ctypes.c_int]),
@@ -270,6 +290,85 @@ def score_windows(blocks, cells, weights, bias):
                                   ctypes.c_void_p(weights.data_ptr()), ctypes.c_void_p(bias.data_ptr()), m,
                                   ctypes.c_void_p(out.data_ptr()), _stream()))
     return out
+
+
+# ------------------------------------------------------------- pruner --
+def features_cellmap(img, prm: Params = None):
+    """(blocks [36][Hb][Wb] float32, cells [59][Hc][Wc] uint8, cell map
+    [68][Hc][Wc] float32) of one level in one pass."""
+    torch = _torch()
+    prm = prm or params()
+    p, w, h, pitch = _image_args(img)
+    hc, wc = h // CELL, w // CELL
+    blocks = torch.empty((HOG_BLOCK, max(hc - 1, 0), max(wc - 1, 0)), dtype=torch.float32, device=img.device)
+    cells = torch.empty((LBP_BINS, hc, wc), dtype=torch.uint8, device=img.device)
+    cmap = torch.empty((PRUNER_CHANNELS, hc, wc), dtype=torch.float32, device=img.device)
+    _check(lib().pd_features_cellmap(p, w, h, pitch, ctypes.byref(prm), ctypes.c_void_p(blocks.data_ptr()),
+                                     ctypes.c_void_p(cells.data_ptr()), ctypes.c_void_p(cmap.data_ptr()),
+                                     _stream()))
+    return blocks, cells, cmap
+
+
+class PrunerBatch:
+    """Device buffers of pd_pruner_forward / pd_pruner_gradient for a fixed
+    list of cell maps ([68][Hc][Wc] float32 tensors) with optional labels and
+    masks ([Hc][Wc] float32)."""
+
+    def __init__(self, cellmaps, labels=None, masks=None):
+        torch = _torch()
+        self.cellmaps = [c.contiguous() for c in cellmaps]
+        dev = self.cellmaps[0].device
+        self.logits = [torch.empty((int(c.shape[1]), int(c.shape[2])), dtype=torch.float32, device=dev)
+                       for c in self.cellmaps]
+        self.labels, self.masks = labels, masks
+        n = len(self.cellmaps)
+        self._maps = (NetMap * n)()
+        for k, c in enumerate(self.cellmaps):
+            m = self._maps[k]
+            m.cellmap, m.logits = c.data_ptr(), self.logits[k].data_ptr()
+            m.labels = labels[k].data_ptr() if labels is not None else 0
+            m.mask = masks[k].data_ptr() if masks is not None else 0
+            m.cells_x, m.cells_y = int(c.shape[2]), int(c.shape[1])
+        nbytes = int(lib().pd_pruner_workspace_bytes(self._maps, n))
+        _check(nbytes if nbytes < 0 else 0)
+        self.ws_bytes = nbytes
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        self.ws_ptr = self.workspace.data_ptr() + (-self.workspace.data_ptr()) % 256
+        self.grad = torch.empty(PRUNER_PARAMS, dtype=torch.float32, device=dev)
+        self.stats = torch.zeros(2, dtype=torch.float64, device=dev)
+
+    def forward(self, weights):
+        _check(lib().pd_pruner_forward(self._maps, len(self.cellmaps), ctypes.c_void_p(weights.data_ptr()),
+                                       ctypes.c_void_p(self.ws_ptr), self.ws_bytes, _stream()))
+        return self.logits
+
+    def gradient(self, weights, pos_weight: float):
+        """Enqueue forward + backward; self.grad and self.stats (loss, N) hold the results."""
+        _check(lib().pd_pruner_gradient(self._maps, len(self.cellmaps), ctypes.c_void_p(weights.data_ptr()),
+                                        float(pos_weight), ctypes.c_void_p(self.grad.data_ptr()),
+                                        ctypes.c_void_p(self.stats.data_ptr()), ctypes.c_void_p(self.ws_ptr),
+                                        self.ws_bytes, _stream()))
+        return self.grad
+
+
+def adam_step(params_, grad, m, v, step: int, lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999,
+              eps: float = 1e-8) -> None:
+    _check(lib().pd_adam_step(ctypes.c_void_p(params_.data_ptr()), ctypes.c_void_p(grad.data_ptr()),
+                              ctypes.c_void_p(m.data_ptr()), ctypes.c_void_p(v.data_ptr()), int(params_.numel()),
+                              int(step), lr, beta1, beta2, eps, _stream()))
+
+
+def window_labels(scores, cells_x: int, cells_y: int, threshold):
+    """(labels, mask) [Hc][Wc] float32 of one level from its window scores
+    [Hc-15][Wc-7] (max over models) and a device float64 threshold [1]."""
+    torch = _torch()
+    scores = scores.contiguous()
+    lab = torch.empty((cells_y, cells_x), dtype=torch.float32, device=scores.device)
+    mask = torch.empty_like(lab)
+    _check(lib().pd_window_labels(ctypes.c_void_p(scores.data_ptr()), int(scores.shape[1]), int(scores.shape[0]),
+                                  cells_x, cells_y, ctypes.c_void_p(threshold.data_ptr()),
+                                  ctypes.c_void_p(lab.data_ptr()), ctypes.c_void_p(mask.data_ptr()), _stream()))
+    return lab, mask
 
 
 def nms(cand_score, cand_key, level_wh, cap: int):

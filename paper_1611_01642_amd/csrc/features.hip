@@ -122,21 +122,54 @@ __device__ __forceinline__ int px_at(const PixRow& r, int i) {  // i in 0..9, co
     return (int)(((b < 4 ? r.lo : r.hi) >> (8 * (b & 3))) & 255u);
 }
 
-template <int FEAT, bool ALIGNED>
+// With CM the strip also emits the pruner's cell map: per cell, the 9-bin
+// histogram with the full bilinear spatial kernel (every vote aimed at the
+// cell: its own pixels' and its 8 neighbours', Sum_d A[c - d][d]), divided by
+// sqrt(|h|^2 + eps^2), then the 59 LBP counts / 64; planar [68][hc][wc].
+// Lanes 1..62 own columns tx*62 .. tx*62 + 61, lanes 0 and 63 are halo, and
+// the strip starts half a cell row early (the downward votes of the row
+// above), so each owned cell sees all of its neighbours' partials.
+template <int FEAT, bool ALIGNED, bool CM = false>
 __device__ __forceinline__ void features_strip(const uint8_t* __restrict__ img, int w, int h, int pitch, float* __restrict__ hog,
-                               uint16_t* __restrict__ hog16, uint8_t* __restrict__ lbp, int ty, int tx, int ch,
-                               float clip, float eps, FeatShared& sm, int wave) {
+                               uint16_t* __restrict__ hog16, uint8_t* __restrict__ lbp, float* __restrict__ cmap,
+                               int ty, int tx, int ch, float clip, float eps, FeatShared& sm, int wave) {
     constexpr bool DO_HOG = (FEAT & PD_FEAT_HOG) != 0;
     constexpr bool DO_LBP = (FEAT & PD_FEAT_LBP) != 0;
+    static_assert(!CM || (DO_HOG && DO_LBP), "the cell map needs HOG and LBP");
     const int lane = threadIdx.x & 63;
     const int hc = h / PD_CELL, wc = w / PD_CELL;
     const int hb = hc - 1, wb = wc - 1;
-    const int cx0 = tx * FT_BX, cy0 = ty * ch;
-    const int cx = cx0 + lane;
-    const int x0 = PD_CELL * min(cx, wc - 1);  // lanes past the edge read valid pixels
+    const int cx0 = CM ? tx * FT_BX_CM : tx * FT_BX, cy0 = ty * ch;
+    const int cx = CM ? cx0 - 1 + lane : cx0 + lane;
+    const int x0 = PD_CELL * min(max(cx, 0), wc - 1);  // lanes past the edges read valid pixels
     const int cy_last = min(cy0 + ch, hc - 1);
-    const bool lbp_col = cx < wc && (lane < FT_BX || cx == wc - 1);
-    const bool blk_col = lane < FT_BX && cx < wb;
+    const int cy_start = (CM && cy0 > 0) ? cy0 - 1 : cy0;
+    const bool own = !CM || (lane >= 1 && lane <= FT_BX_CM && cx < wc);
+    const bool lbp_col = CM ? own : cx < wc && (lane < FT_BX || cx == wc - 1);
+    const bool blk_col = CM ? (own && cx < wb) : (lane < FT_BX && cx < wb);
+    const bool left_real = cx - 1 >= 0 && cx - 1 < wc, right_real = cx + 1 >= 0 && cx + 1 < wc;
+    float down9[PD_HOG_BINS];  // CM: votes from the row above, gathered per target cell
+#pragma unroll
+    for (int k = 0; k < PD_HOG_BINS; ++k) down9[k] = 0.0f;
+    // CM: the 9 votes aimed at this lane's cell from three source columns:
+    // own (dx = 0), the right neighbour's dx = -1 and the left's dx = +1
+    auto gather3 = [&](float l, float o, float r) -> float {
+        const float fr = __shfl_down(l, 1, 64);
+        const float fl = __shfl_up(r, 1, 64);
+        return o + (right_real ? fr : 0.0f) + (left_real ? fl : 0.0f);
+    };
+    auto emit_cell = [&](int row, const float* hist) {
+        float ss = 0.0f;
+#pragma unroll
+        for (int k = 0; k < PD_HOG_BINS; ++k) ss = fmaf(hist[k], hist[k], ss);
+        const float inv = 1.0f / sqrtf(ss + eps * eps);
+        if (own) {
+            const size_t plane = (size_t)hc * wc;
+            float* o = cmap + (size_t)row * wc + cx;
+#pragma unroll
+            for (int k = 0; k < PD_HOG_BINS; ++k) o[k * plane] = hist[k] * inv;
+        }
+    };
     uint32_t* cnt = &sm.cnt[wave][lane * LBP_WORDS];
     if (DO_LBP) {
 #pragma unroll
@@ -150,7 +183,8 @@ __device__ __forceinline__ void features_strip(const uint8_t* __restrict__ img, 
     float Aa[3][PD_HOG_BINS], Ab[3][PD_HOG_BINS];  // [dx+1][bin] for two target rows
 
     // one pixel row: votes into Aa (upper target row) and Ab (lower target row)
-    auto pixel_row = [&](int py, const PixRow& U, const PixRow& C, const PixRow& D, float s0, float s1) {
+    auto pixel_row = [&](int py, const PixRow& U, const PixRow& C, const PixRow& D, float s0, float s1,
+                         bool count_lbp) {
         float R[3][PD_HOG_BINS];
         if (DO_HOG) {
 #pragma unroll
@@ -163,7 +197,7 @@ __device__ __forceinline__ void features_strip(const uint8_t* __restrict__ img, 
             const int c = px_at(C, px + 1);
             const int L = px_at(C, px), Rt = px_at(C, px + 2);
             const int T = px_at(U, px + 1), B = px_at(D, px + 1);
-            if (DO_LBP) {
+            if (DO_LBP && count_lbp) {
                 const int code = (int)(px_at(U, px) >= c) | ((int)(T >= c) << 1) |
                                  ((int)(px_at(U, px + 2) >= c) << 2) | ((int)(Rt >= c) << 3) |
                                  ((int)(px_at(D, px + 2) >= c) << 4) | ((int)(B >= c) << 5) |
@@ -208,11 +242,14 @@ __device__ __forceinline__ void features_strip(const uint8_t* __restrict__ img, 
         }
     };
 
-    for (int cy = cy0; cy <= cy_last; ++cy) {
+    for (int cy = cy_start; cy <= cy_last; ++cy) {
+        // CM's extra row above the strip: only its downward votes are needed
+        const bool extra = CM && cy < cy0;
         const int yb = PD_CELL * cy - 1;  // pixel row of neighbourhood row 0
-        PixRow U = load_row<ALIGNED>(img, pitch, w, max(yb, 0), x0);
-        PixRow C = load_row<ALIGNED>(img, pitch, w, min(yb + 1, h - 1), x0);
-        PixRow D = load_row<ALIGNED>(img, pitch, w, min(yb + 2, h - 1), x0);
+        const int py0 = extra ? 4 : 0;
+        PixRow U = load_row<ALIGNED>(img, pitch, w, max(yb + py0, 0), x0);
+        PixRow C = load_row<ALIGNED>(img, pitch, w, min(yb + py0 + 1, h - 1), x0);
+        PixRow D = load_row<ALIGNED>(img, pitch, w, min(yb + py0 + 2, h - 1), x0);
         if (DO_HOG) {
 #pragma unroll
             for (int a = 0; a < 3; ++a)
@@ -220,21 +257,35 @@ __device__ __forceinline__ void features_strip(const uint8_t* __restrict__ img, 
                 for (int k = 0; k < PD_HOG_BINS; ++k) Aa[a][k] = Ab[a][k] = 0.0f;
         }
         // top half: pixel rows 0..3 vote towards cell rows -1 (Aa) and 0 (Ab)
+        if (!extra) {
 #pragma unroll 1
-        for (int py = 0; py < 4; ++py) {
-            const PixRow N = load_row<ALIGNED>(img, pitch, w, min(yb + py + 3, h - 1), x0);
-            const float fpy = (float)py;
-            pixel_row(py, U, C, D, (3.5f - fpy) * 0.125f, (4.5f + fpy) * 0.125f);
-            U = C;
-            C = D;
-            D = N;
+            for (int py = 0; py < 4; ++py) {
+                const PixRow N = load_row<ALIGNED>(img, pitch, w, min(yb + py + 3, h - 1), x0);
+                const float fpy = (float)py;
+                pixel_row(py, U, C, D, (3.5f - fpy) * 0.125f, (4.5f + fpy) * 0.125f, true);
+                U = C;
+                C = D;
+                D = N;
+            }
         }
         if (DO_HOG) {
-            if (cy > cy0) {  // fold the dy = -1 votes into the previous row's r = 0 terms
+            if (cy > cy_start) {  // fold the dy = -1 votes into the previous row's r = 0 terms
 #pragma unroll
                 for (int a = 0; a < 3; ++a)
 #pragma unroll
                     for (int k = 0; k < PD_HOG_BINS; ++k) P[a * 9 + k][lane] += Aa[a][k];
+                if (CM) {
+                    // cell row cy - 1 is complete: votes from rows cy - 2 (down9),
+                    // cy - 1 and cy (P r = 0); then row cy - 1's downward votes
+                    float hist[PD_HOG_BINS];
+#pragma unroll
+                    for (int k = 0; k < PD_HOG_BINS; ++k)
+                        hist[k] = down9[k] + gather3(P[0 * 9 + k][lane], P[1 * 9 + k][lane], P[2 * 9 + k][lane]);
+                    if (cy - 1 >= cy0) emit_cell(cy - 1, hist);
+#pragma unroll
+                    for (int k = 0; k < PD_HOG_BINS; ++k)
+                        down9[k] = gather3(P[3 * 9 + k][lane], P[4 * 9 + k][lane], P[5 * 9 + k][lane]);
+                }
             }
 #pragma unroll
             for (int a = 0; a < 3; ++a)
@@ -246,7 +297,7 @@ __device__ __forceinline__ void features_strip(const uint8_t* __restrict__ img, 
         for (int py = 4; py < 8; ++py) {
             const PixRow N = load_row<ALIGNED>(img, pitch, w, min(yb + py + 3, h - 1), x0);
             const float fpy = (float)py;
-            pixel_row(py, U, C, D, (fpy - 3.5f) * 0.125f, (11.5f - fpy) * 0.125f);
+            pixel_row(py, U, C, D, (fpy - 3.5f) * 0.125f, (11.5f - fpy) * 0.125f, !extra);
             U = C;
             C = D;
             D = N;
@@ -254,12 +305,18 @@ __device__ __forceinline__ void features_strip(const uint8_t* __restrict__ img, 
 
         // LBP histogram of this cell row
         if (DO_LBP) {
-            const bool own_row = cy < cy0 + ch || cy == hc - 1;
+            const bool own_row = cy >= cy0 && (cy < cy0 + ch || cy == hc - 1);
             if (own_row && lbp_col) {
                 const size_t plane = (size_t)hc * wc;
                 uint8_t* o = lbp + (size_t)cy * wc + cx;
 #pragma unroll 1
                 for (int k = 0; k < PD_LBP_BINS; ++k, o += plane) *o = (uint8_t)((cnt[k >> 2] >> (8 * (k & 3))) & 255u);
+                if (CM) {
+                    float* c = cmap + ((size_t)PD_HOG_BINS * hc + cy) * wc + cx;
+#pragma unroll 1
+                    for (int k = 0; k < PD_LBP_BINS; ++k, c += plane)
+                        *c = (float)((cnt[k >> 2] >> (8 * (k & 3))) & 255u) * (1.0f / 64.0f);
+                }
             }
 #pragma unroll
             for (int k = 0; k < LBP_WORDS; ++k) cnt[k] = 0u;
@@ -332,6 +389,12 @@ __device__ __forceinline__ void features_strip(const uint8_t* __restrict__ img, 
             }
         }
     }
+    if (CM && cy_last == hc - 1) {  // the level's last cell row: no row below it
+        float hist[PD_HOG_BINS];
+#pragma unroll
+        for (int k = 0; k < PD_HOG_BINS; ++k) hist[k] = down9[k] + gather3(Ab[0][k], Ab[1][k], Ab[2][k]);
+        emit_cell(hc - 1, hist);
+    }
 }
 
 __device__ inline void init_lut(FeatShared& sm) {
@@ -348,8 +411,37 @@ __global__ void __launch_bounds__(256) features_single_kernel(LevelItem it, floa
     const int task = blockIdx.x * FT_WAVES + wave;
     const int ntx = feat_tiles_x(it.wc);
     if (task >= ntx * feat_tiles_y(it.hc)) return;
-    features_strip<FEAT, ALIGNED>(it.pyr, it.w, it.h, it.pitch, it.hog, it.hog16, it.lbp, task / ntx, task % ntx,
-                                  FT_CH, clip, eps, sm, wave);
+    features_strip<FEAT, ALIGNED>(it.pyr, it.w, it.h, it.pitch, it.hog, it.hog16, it.lbp, nullptr, task / ntx,
+                                  task % ntx, FT_CH, clip, eps, sm, wave);
+}
+
+template <bool ALIGNED>
+__global__ void __launch_bounds__(256) cellmap_single_kernel(LevelItem it, float clip, float eps) {
+    __shared__ FeatShared sm;
+    init_lut(sm);
+    __syncthreads();
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int task = blockIdx.x * FT_WAVES + wave;
+    const int ntx = feat_tiles_x_cm(it.wc);
+    if (task >= ntx * feat_tiles_y(it.hc)) return;
+    features_strip<PD_FEAT_HOG | PD_FEAT_LBP, ALIGNED, true>(it.pyr, it.w, it.h, it.pitch, it.hog, it.hog16, it.lbp,
+                                                             it.cmap, task / ntx, task % ntx, FT_CH, clip, eps, sm,
+                                                             wave);
+}
+
+__global__ void __launch_bounds__(256) cellmap_table_kernel(const LevelItem* __restrict__ items,
+                                                            const Tile* __restrict__ tiles, int n_tiles, int ch,
+                                                            float clip, float eps) {
+    __shared__ FeatShared sm;
+    init_lut(sm);
+    __syncthreads();
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (int task = blockIdx.x * FT_WAVES + wave; task < n_tiles; task += gridDim.x * FT_WAVES) {
+        const Tile tl = tiles[task];
+        const LevelItem& it = items[tl.item];
+        features_strip<PD_FEAT_HOG | PD_FEAT_LBP, true, true>(it.pyr, it.w, it.h, it.pitch, it.hog, it.hog16, it.lbp,
+                                                              it.cmap, tl.ty, tl.tx, ch, clip, eps, sm, wave);
+    }
 }
 
 // The table launch requires 8-byte aligned level rows (pd_detect copies
@@ -366,8 +458,8 @@ __global__ void __launch_bounds__(256) features_table_kernel(const LevelItem* __
     for (int task = blockIdx.x * FT_WAVES + wave; task < n_tiles; task += gridDim.x * FT_WAVES) {
         const Tile tl = tiles[task];
         const LevelItem& it = items[tl.item];
-        features_strip<FEAT, true>(it.pyr, it.w, it.h, it.pitch, it.hog, it.hog16, it.lbp, tl.ty, tl.tx, ch, clip,
-                                   eps, sm, wave);
+        features_strip<FEAT, true>(it.pyr, it.w, it.h, it.pitch, it.hog, it.hog16, it.lbp, nullptr, tl.ty, tl.tx, ch,
+                                   clip, eps, sm, wave);
     }
 }
 
@@ -414,6 +506,24 @@ hipError_t feat_table(const LevelItem* items, const Tile* tiles, int n_tiles, fl
 }
 
 }  // namespace
+
+hipError_t launch_features_cellmap_single(const LevelItem& it, float clip, float eps, hipStream_t s) {
+    if (it.hc <= 0 || it.wc <= 0) return hipSuccess;
+    const int n = feat_tiles_x_cm(it.wc) * feat_tiles_y(it.hc);
+    const bool aligned = (((uintptr_t)it.pyr | (uintptr_t)it.pitch) & 7) == 0;
+    if (aligned) cellmap_single_kernel<true><<<ceil_div(n, FT_WAVES), 256, 0, s>>>(it, clip, eps);
+    else cellmap_single_kernel<false><<<ceil_div(n, FT_WAVES), 256, 0, s>>>(it, clip, eps);
+    return hipGetLastError();
+}
+
+hipError_t launch_features_cellmap_table(const LevelItem* items, const Tile* tiles, int n_tiles, float clip,
+                                         float eps, const Tuning& tu, hipStream_t s) {
+    if (n_tiles <= 0) return hipSuccess;
+    int blocks = ceil_div(n_tiles, FT_WAVES);
+    if (tu.grid > 0) blocks = min(blocks, tu.grid);
+    cellmap_table_kernel<<<blocks, 256, 0, s>>>(items, tiles, n_tiles, tu.feat_rows, clip, eps);
+    return hipGetLastError();
+}
 
 hipError_t launch_lbp_codes(const uint8_t* img, int w, int h, int pitch, uint8_t* codes, int codes_pitch,
                             hipStream_t s) {

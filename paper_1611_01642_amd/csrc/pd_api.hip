@@ -95,6 +95,111 @@ struct Staging {
 };
 thread_local Staging g_stage;
 
+// Copies `bytes` of host tables to device `dst` through the next pinned
+// staging slot (the slot is reused only after that copy has finished).
+int stage_upload(const void* src, size_t bytes, void* dst, hipStream_t s) {
+    Staging::Slot& slot = g_stage.slot[g_stage.next];
+    g_stage.next = (g_stage.next + 1) % 4;
+    if (slot.pending) {
+        if (int rc = hip_status(hipEventSynchronize(slot.ev), "staging wait")) return rc;
+        slot.pending = false;
+    }
+    if (!slot.ev) {
+        if (int rc = hip_status(hipEventCreateWithFlags(&slot.ev, hipEventDisableTiming), "staging event")) return rc;
+    }
+    if (slot.size < bytes) {
+        if (slot.host) (void)hipHostFree(slot.host);
+        slot.host = nullptr;
+        slot.size = 0;
+        const size_t want = (size_t)align_up((int64_t)bytes, 1 << 16);
+        if (int rc = hip_status(hipHostMalloc(&slot.host, want, hipHostMallocDefault), "staging alloc")) return rc;
+        slot.size = want;
+    }
+    std::memcpy(slot.host, src, bytes);
+    if (int rc = hip_status(hipMemcpyAsync(dst, slot.host, bytes, hipMemcpyHostToDevice, s), "table upload"))
+        return rc;
+    if (int rc = hip_status(hipEventRecord(slot.ev, s), "staging record")) return rc;
+    slot.pending = true;
+    return PD_OK;
+}
+
+// Workspace of the pruner calls: tables, weight copies, partials, then per
+// map its activations (32 + 32 + 16 channels) and two 32-channel gradient
+// buffers.
+struct NetLayout {
+    int n_tiles = 0;
+    int64_t off_items = 0, off_tiles = 0, off_prep = 0, off_partial = 0, off_stats = 0, off_maps = 0, total = 0;
+    std::vector<int64_t> map_off;
+};
+
+bool plan_net(const pd_net_map* maps, int n_maps, NetLayout& L) {
+    L = NetLayout();
+    for (int m = 0; m < n_maps; ++m) {
+        const int wc = maps[m].cells_x, hc = maps[m].cells_y;
+        if (wc < 1 || hc < 1 || wc > PD_MAX_DIM / PD_CELL || hc > PD_MAX_DIM / PD_CELL)
+            return fail(PD_E_SIZE, "map %d size %dx%d outside [1, %d]", m, wc, hc, PD_MAX_DIM / PD_CELL), false;
+        L.n_tiles += hc * ceil_div(wc, 64);
+    }
+    int64_t o = 0;
+    L.off_items = o;
+    o = align_up(o + (int64_t)n_maps * sizeof(NetItem), kAlign);
+    L.off_tiles = o;
+    o = align_up(o + (int64_t)L.n_tiles * sizeof(Tile), kAlign);
+    L.off_prep = o;
+    o = align_up(o + pruner_prep_floats() * 4, kAlign);
+    L.off_partial = o;
+    o = align_up(o + pruner_partial_floats(L.n_tiles) * 4, kAlign);
+    L.off_stats = o;
+    o = align_up(o + 16, kAlign);
+    L.off_maps = o;
+    for (int m = 0; m < n_maps; ++m) {
+        L.map_off.push_back(o);
+        o = align_up(o + (int64_t)(32 + 32 + 16 + 32 + 32) * maps[m].cells_x * maps[m].cells_y * 4, kAlign);
+    }
+    L.total = o;
+    return true;
+}
+
+// Validates the maps and the workspace, uploads the tables.
+int net_setup(const pd_net_map* maps, int n_maps, bool training, void* workspace, int64_t workspace_bytes,
+              hipStream_t s, NetLayout& L) {
+    if (!maps || n_maps < 1) return fail(PD_E_ARG, "maps is NULL or n_maps < 1");
+    for (int m = 0; m < n_maps; ++m) {
+        if (!maps[m].cellmap || !maps[m].logits) return fail(PD_E_ARG, "map %d: NULL cell map or logits", m);
+        if (training && (!maps[m].labels || !maps[m].mask)) return fail(PD_E_ARG, "map %d: NULL labels or mask", m);
+    }
+    if (!plan_net(maps, n_maps, L)) return PD_E_SIZE;
+    if (!workspace || workspace_bytes < L.total)
+        return fail(PD_E_WORKSPACE, "workspace of %lld bytes, need %lld", (long long)workspace_bytes,
+                    (long long)L.total);
+    if ((uintptr_t)workspace & (kAlign - 1)) return fail(PD_E_ARG, "workspace must be 256-byte aligned");
+    uint8_t* ws = static_cast<uint8_t*>(workspace);
+    std::vector<uint8_t> host((size_t)L.off_prep);
+    NetItem* items = reinterpret_cast<NetItem*>(host.data() + L.off_items);
+    Tile* tiles = reinterpret_cast<Tile*>(host.data() + L.off_tiles);
+    int t = 0;
+    for (int m = 0; m < n_maps; ++m) {
+        const int wc = maps[m].cells_x, hc = maps[m].cells_y;
+        const size_t plane = (size_t)wc * hc;
+        NetItem& it = items[m];
+        float* base = reinterpret_cast<float*>(ws + L.map_off[m]);
+        it.buf[NET_X] = const_cast<float*>(maps[m].cellmap);
+        it.buf[NET_A1] = base;
+        it.buf[NET_A2] = base + 32 * plane;
+        it.buf[NET_A3] = base + 64 * plane;
+        it.buf[NET_GA] = base + 80 * plane;
+        it.buf[NET_GB] = base + 112 * plane;
+        it.logit = maps[m].logits;
+        it.label = maps[m].labels;
+        it.mask = maps[m].mask;
+        it.wc = wc;
+        it.hc = hc;
+        for (int p = 0; p < hc; ++p)
+            for (int tx = 0; tx < ceil_div(wc, 64); ++tx) tiles[t++] = Tile{m, p, tx, 0};
+    }
+    return stage_upload(host.data(), host.size(), ws, s);
+}
+
 // Unsigned big integer (32-bit limbs) for exact level sizes.
 struct Big {
     std::vector<uint32_t> d{1};
@@ -608,6 +713,84 @@ int pd_features(const uint8_t* lvl, int w, int h, int pitch, const pd_params* pa
     if (!feat) return PD_OK;
     return hip_status(launch_features_single(it, feat, params->clip, params->eps, (hipStream_t)stream),
                       "features launch");
+}
+
+int pd_features_cellmap(const uint8_t* lvl, int w, int h, int pitch, const pd_params* params, float* blocks,
+                        uint8_t* cell_hist, float* cellmap, void* stream) {
+    if (int rc = check_image(lvl, w, h, pitch, "level")) return rc;
+    if (!check_params(params)) return PD_E_ARG;
+    if (!blocks || !cell_hist || !cellmap) return fail(PD_E_ARG, "NULL output");
+    LevelItem it{};
+    item_geometry(it, w, h);
+    if (it.hb < 1 || it.wb < 1) return fail(PD_E_SIZE, "level %dx%d has no 16x16 block", w, h);
+    it.pyr = const_cast<uint8_t*>(lvl);
+    it.pitch = pitch;
+    it.hog = blocks;
+    it.lbp = cell_hist;
+    it.cmap = cellmap;
+    return hip_status(launch_features_cellmap_single(it, params->clip, params->eps, (hipStream_t)stream),
+                      "cell map launch");
+}
+
+int64_t pd_pruner_workspace_bytes(const pd_net_map* maps, int n_maps) {
+    if (!maps || n_maps < 1) return fail(PD_E_ARG, "maps is NULL or n_maps < 1");
+    NetLayout L;
+    if (!plan_net(maps, n_maps, L)) return PD_E_SIZE;
+    return L.total;
+}
+
+int pd_pruner_forward(const pd_net_map* maps, int n_maps, const float* params, void* workspace,
+                      int64_t workspace_bytes, void* stream) {
+    if (!params) return fail(PD_E_ARG, "params is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    NetLayout L;
+    if (int rc = net_setup(maps, n_maps, false, workspace, workspace_bytes, s, L)) return rc;
+    uint8_t* ws = static_cast<uint8_t*>(workspace);
+    float* prep = reinterpret_cast<float*>(ws + L.off_prep);
+    if (int rc = hip_status(launch_pruner_prep(params, prep, s), "pruner weights")) return rc;
+    return hip_status(launch_pruner_forward(reinterpret_cast<const NetItem*>(ws + L.off_items),
+                                            reinterpret_cast<const Tile*>(ws + L.off_tiles), L.n_tiles, params, prep,
+                                            false, s),
+                      "pruner forward");
+}
+
+int pd_pruner_gradient(const pd_net_map* maps, int n_maps, const float* params, float pos_weight, float* grad,
+                       double* stats, void* workspace, int64_t workspace_bytes, void* stream) {
+    if (!params || !grad || !stats) return fail(PD_E_ARG, "NULL pointer argument");
+    if (!(pos_weight > 0.0f) || !std::isfinite(pos_weight)) return fail(PD_E_ARG, "pos_weight must be > 0");
+    hipStream_t s = (hipStream_t)stream;
+    NetLayout L;
+    if (int rc = net_setup(maps, n_maps, true, workspace, workspace_bytes, s, L)) return rc;
+    uint8_t* ws = static_cast<uint8_t*>(workspace);
+    const NetItem* items = reinterpret_cast<const NetItem*>(ws + L.off_items);
+    const Tile* tiles = reinterpret_cast<const Tile*>(ws + L.off_tiles);
+    float* prep = reinterpret_cast<float*>(ws + L.off_prep);
+    int rc;
+    if ((rc = hip_status(launch_pruner_prep(params, prep, s), "pruner weights"))) return rc;
+    if ((rc = hip_status(launch_pruner_forward(items, tiles, L.n_tiles, params, prep, true, s), "pruner forward")))
+        return rc;
+    return hip_status(launch_pruner_backward(items, tiles, L.n_tiles, params, prep, pos_weight, grad, stats,
+                                             reinterpret_cast<float*>(ws + L.off_partial), s),
+                      "pruner backward");
+}
+
+int pd_adam_step(float* params, const float* grad, float* m, float* v, int n, int step, float lr, float beta1,
+                 float beta2, float eps, void* stream) {
+    if (!params || !grad || !m || !v) return fail(PD_E_ARG, "NULL pointer argument");
+    if (n < 1 || step < 1) return fail(PD_E_SIZE, "n and step must be >= 1");
+    if (!(lr > 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
+        return fail(PD_E_ARG, "lr > 0, beta1 and beta2 in [0, 1), eps > 0 required");
+    return hip_status(launch_adam(params, grad, m, v, n, step, lr, beta1, beta2, eps, (hipStream_t)stream), "adam");
+}
+
+int pd_window_labels(const float* scores, int win_x, int win_y, int cells_x, int cells_y, const double* threshold,
+                     float* labels, float* mask, void* stream) {
+    if (!scores || !threshold || !labels || !mask) return fail(PD_E_ARG, "NULL pointer argument");
+    if (win_x < 1 || win_y < 1 || win_x + PD_WIN_CELLS_X - 1 != cells_x || win_y + PD_WIN_CELLS_Y - 1 != cells_y)
+        return fail(PD_E_SIZE, "window grid %dx%d does not match cells %dx%d", win_x, win_y, cells_x, cells_y);
+    return hip_status(launch_window_labels(scores, win_x, win_y, cells_x, cells_y, threshold, labels, mask,
+                                           (hipStream_t)stream),
+                      "labels");
 }
 
 int pd_lbp(const uint8_t* lvl, int w, int h, int pitch, uint8_t* cell_hist, void* stream) {

@@ -18,10 +18,27 @@ struct LevelItem {
     uint16_t* hog16;      // [36][hb][wb] BF16, or NULL
     uint8_t* lbp;         // [59][hc][wc]
     float* scores;        // [n_models][ny][nx]
+    float* cmap;          // pruner cell map [68][hc][wc] FP32, or NULL
     int32_t src_w, src_h, src_pitch;
     int32_t w, h, pitch;
     int32_t wc, hc, wb, hb, nx, ny;
     int32_t frame, level;
+};
+
+// ---- learned window pruner ----------------------------------------------
+constexpr int PRUNER_CH[4] = {68, 32, 32, 16};  // cell-map channels, conv outputs
+constexpr int PRUNER_WIN_DI = 7, PRUNER_WIN_DJ = 3;  // window (i, j) <-> cell (i + 7, j + 3)
+constexpr int PRUNER_PARAMS = 68 * 32 * 9 + 32 + 32 * 32 * 9 + 32 + 32 * 16 * 9 + 16 + 16 + 1;
+// buffer slots of a NetItem
+enum { NET_X = 0, NET_A1, NET_A2, NET_A3, NET_GA, NET_GB, NET_SLOTS };
+
+// One map (pyramid level) of a pruner launch: planar FP32 buffers.
+struct NetItem {
+    float* buf[NET_SLOTS];  // cell map (68), a1 (32), a2 (32), a3 (16), gradient buffers (32, 32)
+    float* logit;           // [hc][wc]
+    const float* label;     // [hc][wc] (training)
+    const float* mask;      // [hc][wc] (training)
+    int32_t wc, hc;
 };
 
 // One workgroup's share of a batched launch: which item and which tile.
@@ -72,6 +89,10 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
 __host__ __device__ inline int resize_tiles_x(int w) { return ceil_div(w, RS_TX); }
 __host__ __device__ inline int resize_tiles_y(int h) { return ceil_div(h, RS_TY); }
 __host__ __device__ inline int feat_tiles_x(int wc) { return wc <= 1 ? 1 : ceil_div(wc - 1, FT_BX); }
+// Strips that also emit the pruner cell map own 62 columns: every owned cell
+// needs both neighbours in the same wave.
+constexpr int FT_BX_CM = 62;
+__host__ __device__ inline int feat_tiles_x_cm(int wc) { return ceil_div(wc, FT_BX_CM); }
 __host__ __device__ inline int feat_tiles_y(int hc, int rows = FT_CH) { return hc <= 1 ? 1 : ceil_div(hc - 1, rows); }
 __host__ __device__ inline int score_tiles_x(int nx) { return ceil_div(nx, SC_W); }
 __host__ __device__ inline int score_tiles_y(int ny, int rows = SC_R) { return ceil_div(ny, rows); }
@@ -93,6 +114,10 @@ hipError_t launch_features_single(const LevelItem& it, int features, float clip,
                                   hipStream_t s);
 hipError_t launch_features_table(const LevelItem* items, const Tile* tiles, int n_tiles,
                                  int features, float clip, float eps, const Tuning& tu, hipStream_t s);
+// Fused HOG + LBP + pruner cell map (it.cmap), HOG|LBP only.
+hipError_t launch_features_cellmap_single(const LevelItem& it, float clip, float eps, hipStream_t s);
+hipError_t launch_features_cellmap_table(const LevelItem* items, const Tile* tiles, int n_tiles, float clip,
+                                         float eps, const Tuning& tu, hipStream_t s);
 
 hipError_t launch_score_single(const LevelItem& it, const float* w, const float* bias, int n_models,
                                int features, hipStream_t s);
@@ -132,6 +157,20 @@ hipError_t launch_nms_table(const NmsGeom* geoms, int n_frames, const int32_t* c
                             const int32_t* near_count, pd_box* boxes, int cap, pd_counts* counts, hipStream_t s);
 hipError_t launch_nms_single(const NmsGeom& g, int n, const float* cand_score, const int4* cand_key,
                              pd_box* boxes, int cap, pd_counts* counts, hipStream_t s);
+int64_t pruner_prep_floats();
+hipError_t launch_pruner_prep(const float* params, float* prep, hipStream_t s);
+hipError_t launch_pruner_forward(const NetItem* items, const Tile* tiles, int n_tiles, const float* params,
+                                 const float* prep, bool keep_a3, hipStream_t s);
+int pruner_wgrad_blocks(int n_tiles);
+int64_t pruner_partial_floats(int n_tiles);
+hipError_t launch_pruner_backward(const NetItem* items, const Tile* tiles, int n_tiles, const float* params,
+                                  const float* prep, float pos_weight, float* grad, double* stats, float* partial,
+                                  hipStream_t s);
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int n, int step, float lr, float b1, float b2,
+                       float eps, hipStream_t s);
+hipError_t launch_window_labels(const float* scores, int nx, int ny, int wc, int hc, const double* thr,
+                                float* labels, float* mask, hipStream_t s);
+
 hipError_t launch_zero_i32(int32_t* p, int n, hipStream_t s);
 
 }  // namespace pd

@@ -1,0 +1,399 @@
+// The learned window pruner: a 68-32-32-16 conv3x3 network with a 1x1
+// sigmoid head over the per-cell feature map of every pyramid level, trained
+// on the GPU with these kernels.  The network is not part of the paper; it
+// predicts which windows the linear SVM of Section 4.4 will score above the
+// threshold, so the others need not be scored.
+//
+// Layout: every map is planar FP32 [C][hc][wc]; one item per map (a pyramid
+// level of a frame) carries pointers to its cell map, activations, gradient
+// buffers, logits, labels and mask.  Work tiles are 64 consecutive cells of
+// one row; a wave owns a tile, a lane owns a cell.
+//
+//  * conv3x3 (zero padding): per input channel the wave stages the 3 x 66
+//    neighbourhood of its tile in LDS (the next channel's loads in flight),
+//    then each lane accumulates all output channels in registers with
+//    wave-uniform weights (scalar loads, tap-major layout [cin][9][cout]).
+//    The same kernel computes the data gradient with the flipped, transposed
+//    weights and the ReLU mask of the layer below.  The last layer fuses the
+//    1x1 head.
+//  * weight gradients: dW[o][c][u][v] = sum over cells of dZ[o] x X[c] at
+//    offset (u - 1, v - 1): a fixed set of workgroups strides over the tiles
+//    (both operands staged in LDS), each thread owning one output channel and
+//    a group of input channels; per-workgroup partials are then summed in
+//    FP64 in a fixed order, so gradients are bitwise reproducible.
+//  * loss: class-weighted binary cross-entropy over the masked cells; the
+//    gradients are accumulated un-normalised and divided by the number of
+//    masked cells in the final reduction.
+#include <cmath>
+
+#include "pd_internal.h"
+
+namespace pd {
+namespace {
+
+constexpr int NW = 64;  // cells per tile
+constexpr int NWAVES = 4;
+constexpr int HALO_W = NW + 2;
+
+template <int COUT, bool HEAD>
+__global__ void __launch_bounds__(256) conv3x3_kernel(const NetItem* __restrict__ items,
+                                                      const Tile* __restrict__ tiles, int n_tiles, int in_slot,
+                                                      int cin, int out_slot, int mask_slot,
+                                                      const float* __restrict__ wt, const float* __restrict__ bias,
+                                                      int relu, const float* __restrict__ head) {
+    __shared__ float stage[NWAVES][2][3 * HALO_W];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int task = blockIdx.x * NWAVES + wave;
+    if (task >= n_tiles) return;
+    const Tile tl = tiles[task];
+    const NetItem& it = items[tl.item];
+    const int wc = it.wc, hc = it.hc;
+    const int p = tl.ty, q0 = tl.tx * NW, q = q0 + lane;
+    const size_t plane = (size_t)hc * wc;
+    const float* in = it.buf[in_slot];
+
+    float acc[COUT];
+#pragma unroll
+    for (int o = 0; o < COUT; ++o) acc[o] = bias ? bias[o] : 0.0f;
+
+    // staged element e = r * 66 + col holds in[c][p - 1 + r][q0 - 1 + col] (0 outside)
+    int off[4];
+    bool ok[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int e = lane + 64 * k;
+        const int r = e / HALO_W, col = e - (e / HALO_W) * HALO_W;
+        const int y = p - 1 + r, x = q0 - 1 + col;
+        ok[k] = e < 3 * HALO_W && y >= 0 && y < hc && x >= 0 && x < wc;
+        off[k] = ok[k] ? y * wc + x : 0;
+    }
+    float pre[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) pre[k] = ok[k] ? in[off[k]] : 0.0f;
+    for (int c = 0; c < cin; ++c) {
+        float* s = stage[wave][c & 1];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            if (lane + 64 * k < 3 * HALO_W) s[lane + 64 * k] = pre[k];
+        if (c + 1 < cin) {
+            const float* nx = in + (size_t)(c + 1) * plane;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) pre[k] = ok[k] ? nx[off[k]] : 0.0f;
+        }
+        __builtin_amdgcn_wave_barrier();
+        float xv[9];
+#pragma unroll
+        for (int u = 0; u < 3; ++u)
+#pragma unroll
+            for (int v = 0; v < 3; ++v) xv[u * 3 + v] = s[u * HALO_W + lane + v];
+        const float* w = wt + (size_t)c * 9 * COUT;
+#pragma unroll
+        for (int t = 0; t < 9; ++t)
+#pragma unroll
+            for (int o = 0; o < COUT; ++o) acc[o] = fmaf(xv[t], w[t * COUT + o], acc[o]);
+        __builtin_amdgcn_wave_barrier();
+    }
+    if (q >= wc) return;
+    const size_t at = (size_t)p * wc + q;
+    if (relu) {
+#pragma unroll
+        for (int o = 0; o < COUT; ++o) acc[o] = fmaxf(acc[o], 0.0f);
+    }
+    if (mask_slot >= 0) {  // data gradient through the ReLU of the layer below
+        const float* a = it.buf[mask_slot];
+#pragma unroll
+        for (int o = 0; o < COUT; ++o) acc[o] = a[o * plane + at] > 0.0f ? acc[o] : 0.0f;
+    }
+    if (out_slot >= 0) {
+        float* out = it.buf[out_slot];
+#pragma unroll
+        for (int o = 0; o < COUT; ++o) out[o * plane + at] = acc[o];
+    }
+    if (HEAD) {
+        float z = head[COUT];
+#pragma unroll
+        for (int o = 0; o < COUT; ++o) z = fmaf(head[o], acc[o], z);
+        it.logit[at] = z;
+    }
+}
+
+// dW partials of one layer: thread = (output channel o, channel group g).
+template <int CIN, int COUT>
+__global__ void __launch_bounds__(256) wgrad_kernel(const NetItem* __restrict__ items, const Tile* __restrict__ tiles,
+                                                    int n_tiles, int x_slot, int dz_slot,
+                                                    float* __restrict__ partial) {
+    constexpr int G = 256 / COUT;
+    constexpr int CPT = (CIN + G - 1) / G;
+    constexpr int NOUT = COUT * CIN * 9 + COUT;
+    __shared__ float xs[CIN][3][HALO_W];
+    __shared__ float ds[COUT][NW + 1];
+    const int tid = threadIdx.x;
+    const int o = tid % COUT, g = tid / COUT;
+    float acc[CPT][9];
+#pragma unroll
+    for (int j = 0; j < CPT; ++j)
+#pragma unroll
+        for (int t = 0; t < 9; ++t) acc[j][t] = 0.0f;
+    float accb = 0.0f;
+    for (int ti = blockIdx.x; ti < n_tiles; ti += gridDim.x) {
+        const Tile tl = tiles[ti];
+        const NetItem& it = items[tl.item];
+        const int wc = it.wc, hc = it.hc, p = tl.ty, q0 = tl.tx * NW;
+        const size_t plane = (size_t)hc * wc;
+        const float* x = it.buf[x_slot];
+        const float* dz = it.buf[dz_slot];
+        __syncthreads();  // the previous tile's reads are done
+        for (int e = tid; e < CIN * 3 * HALO_W; e += 256) {
+            const int c = e / (3 * HALO_W), rem = e - c * (3 * HALO_W);
+            const int r = rem / HALO_W, col = rem - r * HALO_W;
+            const int y = p - 1 + r, xx = q0 - 1 + col;
+            xs[c][r][col] = (y >= 0 && y < hc && xx >= 0 && xx < wc) ? x[c * plane + (size_t)y * wc + xx] : 0.0f;
+        }
+        for (int e = tid; e < COUT * NW; e += 256) {
+            const int oo = e / NW, qq = e - oo * NW;
+            ds[oo][qq] = q0 + qq < wc ? dz[oo * plane + (size_t)p * wc + q0 + qq] : 0.0f;
+        }
+        __syncthreads();
+        for (int qq = 0; qq < NW; ++qq) {
+            const float d = ds[o][qq];
+            accb += d;
+#pragma unroll
+            for (int j = 0; j < CPT; ++j) {
+                const int c = g + G * j;
+                if (c < CIN) {
+#pragma unroll
+                    for (int u = 0; u < 3; ++u)
+#pragma unroll
+                        for (int v = 0; v < 3; ++v) acc[j][u * 3 + v] = fmaf(d, xs[c][u][qq + v], acc[j][u * 3 + v]);
+                }
+            }
+        }
+    }
+    float* out = partial + (size_t)blockIdx.x * NOUT;
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+        const int c = g + G * j;
+        if (c < CIN) {
+#pragma unroll
+            for (int t = 0; t < 9; ++t) out[(o * CIN + c) * 9 + t] = acc[j][t];
+        }
+    }
+    if (g == 0) out[COUT * CIN * 9 + o] = accb;
+}
+
+// Loss and head: per cell dz = m((1 - y) s - pw y (1 - s)) (un-normalised),
+// dZ3[c] = dz hw[c] [a3[c] > 0]; per-workgroup partials of dhw, dhb, the
+// loss and the number of masked cells (NHEAD = 16 + 3 values).
+constexpr int HEAD_C = 16;
+constexpr int NHEAD = HEAD_C + 3;
+
+__device__ __forceinline__ float softplus(float x) { return fmaxf(x, 0.0f) + log1pf(expf(-fabsf(x))); }
+
+__global__ void __launch_bounds__(256) head_loss_kernel(const NetItem* __restrict__ items,
+                                                        const Tile* __restrict__ tiles, int n_tiles, int a3_slot,
+                                                        int dz_slot, const float* __restrict__ head, float pos_weight,
+                                                        double* __restrict__ partial) {
+    __shared__ double red[256][NHEAD];
+    double mine[NHEAD];
+#pragma unroll
+    for (int k = 0; k < NHEAD; ++k) mine[k] = 0.0;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int task = blockIdx.x * NWAVES + wave;
+    if (task < n_tiles) {
+        const Tile tl = tiles[task];
+        const NetItem& it = items[tl.item];
+        const int q = tl.tx * NW + lane;
+        if (q < it.wc) {
+            const size_t plane = (size_t)it.hc * it.wc;
+            const size_t at = (size_t)tl.ty * it.wc + q;
+            const float z = it.logit[at], y = it.label[at], m = it.mask[at];
+            const float s = 1.0f / (1.0f + expf(-z));
+            const float dz = m * ((1.0f - y) * s - pos_weight * y * (1.0f - s));
+            const float* a3 = it.buf[a3_slot];
+            float* dz3 = it.buf[dz_slot];
+#pragma unroll
+            for (int c = 0; c < HEAD_C; ++c) {
+                const float a = a3[c * plane + at];
+                dz3[c * plane + at] = a > 0.0f ? dz * head[c] : 0.0f;
+                mine[c] = (double)dz * (double)a;
+            }
+            mine[HEAD_C] = dz;
+            mine[HEAD_C + 1] = m != 0.0f ? (double)m * ((double)pos_weight * y * softplus(-z) +
+                                                         (1.0 - (double)y) * softplus(z))
+                                         : 0.0;
+            mine[HEAD_C + 2] = m;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NHEAD; ++k) red[threadIdx.x][k] = mine[k];
+    __syncthreads();
+    for (int stride = 128; stride > 0; stride >>= 1) {
+        if ((int)threadIdx.x < stride)
+            for (int k = 0; k < NHEAD; ++k) red[threadIdx.x][k] += red[threadIdx.x + stride][k];
+        __syncthreads();
+    }
+    if (threadIdx.x < NHEAD) partial[(size_t)blockIdx.x * NHEAD + threadIdx.x] = red[0][threadIdx.x];
+}
+
+// Head partials -> grad of hw and hb (divided by N), loss, N.
+__global__ void head_reduce_kernel(const double* __restrict__ partial, int n_blocks, float* __restrict__ grad_head,
+                                   double* __restrict__ stats) {
+    const int k = threadIdx.x;
+    if (k >= NHEAD) return;
+    double s = 0.0;
+    for (int b = 0; b < n_blocks; ++b) s += partial[(size_t)b * NHEAD + k];
+    __shared__ double sums[NHEAD];
+    sums[k] = s;
+    __syncthreads();
+    const double n = sums[HEAD_C + 2];
+    const double inv = n > 0.0 ? 1.0 / n : 0.0;
+    if (k <= HEAD_C) grad_head[k] = (float)(s * inv);
+    if (k == HEAD_C + 1) stats[0] = s * inv;  // mean loss
+    if (k == HEAD_C + 2) stats[1] = n;        // masked cells
+}
+
+// Layer partials -> gradient slice (divided by N = stats[1]).
+__global__ void __launch_bounds__(256) wgrad_reduce_kernel(const float* __restrict__ partial, int n_blocks, int nout,
+                                                           const double* __restrict__ stats,
+                                                           float* __restrict__ grad) {
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= nout) return;
+    double s = 0.0;
+    for (int b = 0; b < n_blocks; ++b) s += (double)partial[(size_t)b * nout + k];
+    const double n = stats[1];
+    grad[k] = (float)(n > 0.0 ? s / n : 0.0);
+}
+
+// Tap-major copies of the conv weights: forward [cin][9][cout], and the
+// flipped, transposed form [cout][9][cin] used for data gradients.
+__global__ void __launch_bounds__(256) prep_weights_kernel(const float* __restrict__ params, float* __restrict__ fwd,
+                                                           float* __restrict__ bwd, int cin, int cout) {
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= cout * cin * 9) return;
+    const int o = e / (cin * 9), rem = e - o * cin * 9, c = rem / 9, t = rem - c * 9;
+    const float w = params[e];
+    fwd[((size_t)c * 9 + t) * cout + o] = w;
+    if (bwd) bwd[((size_t)o * 9 + (8 - t)) * cin + c] = w;
+}
+
+__global__ void __launch_bounds__(256) adam_kernel(float* __restrict__ p, const float* __restrict__ g,
+                                                   float* __restrict__ m, float* __restrict__ v, int n, float lr,
+                                                   float b1, float b2, float eps, float c1, float c2) {
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= n) return;
+    const float gk = g[k];
+    const float mk = b1 * m[k] + (1.0f - b1) * gk;
+    const float vk = b2 * v[k] + (1.0f - b2) * gk * gk;
+    m[k] = mk;
+    v[k] = vk;
+    p[k] -= lr * (mk * c1) / (sqrtf(vk * c2) + eps);
+}
+
+__global__ void __launch_bounds__(256) window_labels_kernel(const float* __restrict__ scores, int nx, int ny,
+                                                            int wc, int hc, const double* __restrict__ thr,
+                                                            float* __restrict__ labels, float* __restrict__ mask) {
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= wc * hc) return;
+    const int cy = e / wc, cx = e - cy * wc;
+    const int i = cy - PRUNER_WIN_DI, j = cx - PRUNER_WIN_DJ;
+    const bool win = i >= 0 && i < ny && j >= 0 && j < nx;
+    mask[e] = win ? 1.0f : 0.0f;
+    labels[e] = win && (double)scores[(size_t)i * nx + j] > thr[0] ? 1.0f : 0.0f;
+}
+
+}  // namespace
+
+int64_t pruner_prep_floats() {
+    int64_t n = 0;
+    for (int l = 0; l < 3; ++l) n += 2LL * PRUNER_CH[l] * PRUNER_CH[l + 1] * 9;
+    return n;
+}
+
+hipError_t launch_pruner_prep(const float* params, float* prep, hipStream_t s) {
+    const float* src = params;
+    float* dst = prep;
+    for (int l = 0; l < 3; ++l) {
+        const int cin = PRUNER_CH[l], cout = PRUNER_CH[l + 1], n = cin * cout * 9;
+        prep_weights_kernel<<<ceil_div(n, 256), 256, 0, s>>>(src, dst, dst + n, cin, cout);
+        src += n + cout;
+        dst += 2 * n;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_pruner_forward(const NetItem* items, const Tile* tiles, int n_tiles, const float* params,
+                                 const float* prep, bool keep_a3, hipStream_t s) {
+    if (n_tiles <= 0) return hipSuccess;
+    const int grid = ceil_div(n_tiles, NWAVES);
+    const float* b1 = params + 68 * 32 * 9;
+    const float* b2 = b1 + 32 + 32 * 32 * 9;
+    const float* b3 = b2 + 32 + 32 * 16 * 9;
+    const float* head = b3 + 16;
+    const float* w1 = prep;
+    const float* w2 = w1 + 2 * 68 * 32 * 9;
+    const float* w3 = w2 + 2 * 32 * 32 * 9;
+    conv3x3_kernel<32, false><<<grid, 256, 0, s>>>(items, tiles, n_tiles, NET_X, 68, NET_A1, -1, w1, b1, 1, nullptr);
+    conv3x3_kernel<32, false><<<grid, 256, 0, s>>>(items, tiles, n_tiles, NET_A1, 32, NET_A2, -1, w2, b2, 1, nullptr);
+    conv3x3_kernel<16, true><<<grid, 256, 0, s>>>(items, tiles, n_tiles, NET_A2, 32, keep_a3 ? NET_A3 : -1, -1, w3,
+                                                  b3, 1, head);
+    return hipGetLastError();
+}
+
+int pruner_wgrad_blocks(int n_tiles) { return n_tiles < 1 ? 1 : (n_tiles < 512 ? n_tiles : 512); }
+
+int64_t pruner_partial_floats(int n_tiles) {
+    // the largest layer's partials, reused by each layer in turn (+ head, as doubles)
+    const int nb = pruner_wgrad_blocks(n_tiles);
+    return (int64_t)nb * (68 * 32 * 9 + 32) + 2LL * ceil_div(n_tiles, NWAVES) * NHEAD + 4;
+}
+
+hipError_t launch_pruner_backward(const NetItem* items, const Tile* tiles, int n_tiles, const float* params,
+                                  const float* prep, float pos_weight, float* grad, double* stats, float* partial,
+                                  hipStream_t s) {
+    if (n_tiles <= 0) return hipSuccess;
+    const int grid = ceil_div(n_tiles, NWAVES);
+    const int nb = pruner_wgrad_blocks(n_tiles);
+    const int n1 = 68 * 32 * 9, n2 = 32 * 32 * 9, n3 = 32 * 16 * 9;
+    const float* head = params + n1 + 32 + n2 + 32 + n3 + 16;
+    const float* w2b = prep + 2 * n1 + n2;
+    const float* w3b = prep + 2 * n1 + 2 * n2 + n3;
+    float* g1 = grad;
+    float* g2 = g1 + n1 + 32;
+    float* g3 = g2 + n2 + 32;
+    float* gh = g3 + n3 + 16;
+    double* hpart = reinterpret_cast<double*>(partial + (int64_t)nb * (n1 + 32));
+    // head and loss, then the normaliser N
+    head_loss_kernel<<<grid, 256, 0, s>>>(items, tiles, n_tiles, NET_A3, NET_GA, head, pos_weight, hpart);
+    head_reduce_kernel<<<1, 64, 0, s>>>(hpart, grid, gh, stats);
+    // layer 3: dW3 from dZ3 (GA) and a2; dZ2 = conv(dZ3, W3 flipped) [a2 > 0] -> GB
+    wgrad_kernel<32, 16><<<nb, 256, 0, s>>>(items, tiles, n_tiles, NET_A2, NET_GA, partial);
+    wgrad_reduce_kernel<<<ceil_div(n3 + 16, 256), 256, 0, s>>>(partial, nb, n3 + 16, stats, g3);
+    conv3x3_kernel<32, false><<<grid, 256, 0, s>>>(items, tiles, n_tiles, NET_GA, 16, NET_GB, NET_A2, w3b, nullptr, 0,
+                                                   nullptr);
+    // layer 2: dW2 from dZ2 (GB) and a1; dZ1 = conv(dZ2, W2 flipped) [a1 > 0] -> GA
+    wgrad_kernel<32, 32><<<nb, 256, 0, s>>>(items, tiles, n_tiles, NET_A1, NET_GB, partial);
+    wgrad_reduce_kernel<<<ceil_div(n2 + 32, 256), 256, 0, s>>>(partial, nb, n2 + 32, stats, g2);
+    conv3x3_kernel<32, false><<<grid, 256, 0, s>>>(items, tiles, n_tiles, NET_GB, 32, NET_GA, NET_A1, w2b, nullptr, 0,
+                                                   nullptr);
+    // layer 1: dW1 from dZ1 (GA) and the cell map
+    wgrad_kernel<68, 32><<<nb, 256, 0, s>>>(items, tiles, n_tiles, NET_X, NET_GA, partial);
+    wgrad_reduce_kernel<<<ceil_div(n1 + 32, 256), 256, 0, s>>>(partial, nb, n1 + 32, stats, g1);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int n, int step, float lr, float b1, float b2,
+                       float eps, hipStream_t s) {
+    const float c1 = (float)(1.0 / (1.0 - std::pow((double)b1, step)));
+    const float c2 = (float)(1.0 / (1.0 - std::pow((double)b2, step)));
+    adam_kernel<<<ceil_div(n, 256), 256, 0, s>>>(p, g, m, v, n, lr, b1, b2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+hipError_t launch_window_labels(const float* scores, int nx, int ny, int wc, int hc, const double* thr,
+                                float* labels, float* mask, hipStream_t s) {
+    window_labels_kernel<<<ceil_div(wc * hc, 256), 256, 0, s>>>(scores, nx, ny, wc, hc, thr, labels, mask);
+    return hipGetLastError();
+}
+
+}  // namespace pd
