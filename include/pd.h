@@ -416,6 +416,19 @@ int pd_window_labels(const float* scores, int win_x, int win_y, int cells_x, int
                      const double* threshold, float* labels, float* mask, void* stream);
 
 /*
+ * pd_pruner_logits_bf16 -- the inference form of the pruner on one level
+ * (w x h >= 64x128): features and the cell map in one pass (the cell map
+ * stored channels-last in BF16), then the network on BF16 MFMA with FP32
+ * accumulation (bias, ReLU and head in FP32; layer outputs rounded to
+ * BF16).  logits: device float [h/8][w/8].  Workspace (device, 256-byte
+ * aligned) from pd_pruner_logits_bf16_workspace_bytes(w, h).
+ */
+int64_t pd_pruner_logits_bf16_workspace_bytes(int w, int h);
+int pd_pruner_logits_bf16(const uint8_t* level, int w, int h, int pitch, const pd_params* params,
+                          const float* pruner, float* logits, void* workspace, int64_t workspace_bytes,
+                          void* stream);
+
+/*
  * pd_detect_candidates -- test hook: after pd_detect on the same arguments
  * (frames, params, n_models, workspace), enqueue copies of frame `frame`'s
  * candidate list (windows above the threshold, before NMS, in no particular

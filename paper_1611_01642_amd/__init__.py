@@ -131,6 +131,10 @@ _SIGS = {
                                     ctypes.c_float, ctypes.c_void_p]),
     "pd_window_labels": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "pd_pruner_logits_bf16_workspace_bytes": (ctypes.c_int64, [ctypes.c_int, ctypes.c_int]),
+    "pd_pruner_logits_bf16": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_int64, ctypes.c_void_p]),
     "pd_nms": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
                               ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
     "pd_profile_enable": (ctypes.c_int, [ctypes.c_int]),
@@ -349,6 +353,22 @@ class PrunerBatch:
                                         ctypes.c_void_p(self.stats.data_ptr()), ctypes.c_void_p(self.ws_ptr),
                                         self.ws_bytes, _stream()))
         return self.grad
+
+
+def pruner_logits_bf16(img, weights, prm: Params = None):
+    """Logits [Hc][Wc] float32 of one level by the BF16 MFMA inference path."""
+    torch = _torch()
+    prm = prm or params()
+    p, w, h, pitch = _image_args(img)
+    nbytes = int(lib().pd_pruner_logits_bf16_workspace_bytes(w, h))
+    _check(nbytes if nbytes < 0 else 0)
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=img.device)
+    ptr = ws.data_ptr() + (-ws.data_ptr()) % 256
+    out = torch.empty((h // CELL, w // CELL), dtype=torch.float32, device=img.device)
+    _check(lib().pd_pruner_logits_bf16(p, w, h, pitch, ctypes.byref(prm), ctypes.c_void_p(weights.data_ptr()),
+                                       ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(ptr), nbytes, _stream()))
+    out._workspace = ws  # keep alive until the stream is done
+    return out
 
 
 def adam_step(params_, grad, m, v, step: int, lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999,

@@ -125,14 +125,16 @@ __device__ __forceinline__ int px_at(const PixRow& r, int i) {  // i in 0..9, co
 // With CM the strip also emits the pruner's cell map: per cell, the 9-bin
 // histogram with the full bilinear spatial kernel (every vote aimed at the
 // cell: its own pixels' and its 8 neighbours', Sum_d A[c - d][d]), divided by
-// sqrt(|h|^2 + eps^2), then the 59 LBP counts / 64; planar [68][hc][wc].
+// sqrt(|h|^2 + eps^2), then the 59 LBP counts / 64: FP32 planar
+// [68][hc][wc] (cmap) and/or BF16 channels-last [hc][wc][72] (cmap16).
 // Lanes 1..62 own columns tx*62 .. tx*62 + 61, lanes 0 and 63 are halo, and
 // the strip starts half a cell row early (the downward votes of the row
 // above), so each owned cell sees all of its neighbours' partials.
 template <int FEAT, bool ALIGNED, bool CM = false>
 __device__ __forceinline__ void features_strip(const uint8_t* __restrict__ img, int w, int h, int pitch, float* __restrict__ hog,
                                uint16_t* __restrict__ hog16, uint8_t* __restrict__ lbp, float* __restrict__ cmap,
-                               int ty, int tx, int ch, float clip, float eps, FeatShared& sm, int wave) {
+                               uint16_t* __restrict__ cmap16, int ty, int tx, int ch, float clip, float eps,
+                               FeatShared& sm, int wave) {
     constexpr bool DO_HOG = (FEAT & PD_FEAT_HOG) != 0;
     constexpr bool DO_LBP = (FEAT & PD_FEAT_LBP) != 0;
     static_assert(!CM || (DO_HOG && DO_LBP), "the cell map needs HOG and LBP");
@@ -164,10 +166,17 @@ __device__ __forceinline__ void features_strip(const uint8_t* __restrict__ img, 
         for (int k = 0; k < PD_HOG_BINS; ++k) ss = fmaf(hist[k], hist[k], ss);
         const float inv = 1.0f / sqrtf(ss + eps * eps);
         if (own) {
-            const size_t plane = (size_t)hc * wc;
-            float* o = cmap + (size_t)row * wc + cx;
+            if (cmap) {
+                const size_t plane = (size_t)hc * wc;
+                float* o = cmap + (size_t)row * wc + cx;
 #pragma unroll
-            for (int k = 0; k < PD_HOG_BINS; ++k) o[k * plane] = hist[k] * inv;
+                for (int k = 0; k < PD_HOG_BINS; ++k) o[k * plane] = hist[k] * inv;
+            }
+            if (cmap16) {
+                uint16_t* o = cmap16 + ((size_t)row * wc + cx) * PR_CP1;
+#pragma unroll
+                for (int k = 0; k < PD_HOG_BINS; ++k) o[k] = f32_to_bf16(hist[k] * inv);
+            }
         }
     };
     uint32_t* cnt = &sm.cnt[wave][lane * LBP_WORDS];
@@ -311,11 +320,19 @@ __device__ __forceinline__ void features_strip(const uint8_t* __restrict__ img, 
                 uint8_t* o = lbp + (size_t)cy * wc + cx;
 #pragma unroll 1
                 for (int k = 0; k < PD_LBP_BINS; ++k, o += plane) *o = (uint8_t)((cnt[k >> 2] >> (8 * (k & 3))) & 255u);
-                if (CM) {
+                if (CM && cmap) {
                     float* c = cmap + ((size_t)PD_HOG_BINS * hc + cy) * wc + cx;
 #pragma unroll 1
                     for (int k = 0; k < PD_LBP_BINS; ++k, c += plane)
                         *c = (float)((cnt[k >> 2] >> (8 * (k & 3))) & 255u) * (1.0f / 64.0f);
+                }
+                if (CM && cmap16) {  // counts / 64 are exact in BF16; channels 68..71 zero
+                    uint16_t* c = cmap16 + ((size_t)cy * wc + cx) * PR_CP1 + PD_HOG_BINS;
+#pragma unroll 1
+                    for (int k = 0; k < PD_LBP_BINS; ++k)
+                        c[k] = f32_to_bf16((float)((cnt[k >> 2] >> (8 * (k & 3))) & 255u) * (1.0f / 64.0f));
+#pragma unroll
+                    for (int k = PD_LBP_BINS; k < PR_CP1 - PD_HOG_BINS; ++k) c[k] = 0;
                 }
             }
 #pragma unroll
@@ -411,8 +428,8 @@ __global__ void __launch_bounds__(256) features_single_kernel(LevelItem it, floa
     const int task = blockIdx.x * FT_WAVES + wave;
     const int ntx = feat_tiles_x(it.wc);
     if (task >= ntx * feat_tiles_y(it.hc)) return;
-    features_strip<FEAT, ALIGNED>(it.pyr, it.w, it.h, it.pitch, it.hog, it.hog16, it.lbp, nullptr, task / ntx,
-                                  task % ntx, FT_CH, clip, eps, sm, wave);
+    features_strip<FEAT, ALIGNED>(it.pyr, it.w, it.h, it.pitch, it.hog, it.hog16, it.lbp, nullptr, nullptr,
+                                  task / ntx, task % ntx, FT_CH, clip, eps, sm, wave);
 }
 
 template <bool ALIGNED>
@@ -425,8 +442,8 @@ __global__ void __launch_bounds__(256) cellmap_single_kernel(LevelItem it, float
     const int ntx = feat_tiles_x_cm(it.wc);
     if (task >= ntx * feat_tiles_y(it.hc)) return;
     features_strip<PD_FEAT_HOG | PD_FEAT_LBP, ALIGNED, true>(it.pyr, it.w, it.h, it.pitch, it.hog, it.hog16, it.lbp,
-                                                             it.cmap, task / ntx, task % ntx, FT_CH, clip, eps, sm,
-                                                             wave);
+                                                             it.cmap, it.cmap16, task / ntx, task % ntx, FT_CH, clip,
+                                                             eps, sm, wave);
 }
 
 __global__ void __launch_bounds__(256) cellmap_table_kernel(const LevelItem* __restrict__ items,
@@ -440,7 +457,8 @@ __global__ void __launch_bounds__(256) cellmap_table_kernel(const LevelItem* __r
         const Tile tl = tiles[task];
         const LevelItem& it = items[tl.item];
         features_strip<PD_FEAT_HOG | PD_FEAT_LBP, true, true>(it.pyr, it.w, it.h, it.pitch, it.hog, it.hog16, it.lbp,
-                                                              it.cmap, tl.ty, tl.tx, ch, clip, eps, sm, wave);
+                                                              it.cmap, it.cmap16, tl.ty, tl.tx, ch, clip, eps, sm,
+                                                              wave);
     }
 }
 
@@ -458,8 +476,8 @@ __global__ void __launch_bounds__(256) features_table_kernel(const LevelItem* __
     for (int task = blockIdx.x * FT_WAVES + wave; task < n_tiles; task += gridDim.x * FT_WAVES) {
         const Tile tl = tiles[task];
         const LevelItem& it = items[tl.item];
-        features_strip<FEAT, true>(it.pyr, it.w, it.h, it.pitch, it.hog, it.hog16, it.lbp, nullptr, tl.ty, tl.tx, ch,
-                                   clip, eps, sm, wave);
+        features_strip<FEAT, true>(it.pyr, it.w, it.h, it.pitch, it.hog, it.hog16, it.lbp, nullptr, nullptr, tl.ty,
+                                   tl.tx, ch, clip, eps, sm, wave);
     }
 }
 

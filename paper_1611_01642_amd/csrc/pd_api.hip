@@ -793,6 +793,86 @@ int pd_window_labels(const float* scores, int win_x, int win_y, int cells_x, int
                       "labels");
 }
 
+// Workspace of pd_pruner_logits_bf16 for one w x h level.
+struct LogitsLayout {
+    int n_tiles = 0;
+    int64_t off_item = 0, off_tiles = 0, off_packed = 0, off_hog = 0, off_lbp = 0, off_cmap = 0, off_a1 = 0,
+            off_a2 = 0, total = 0;
+};
+
+LogitsLayout plan_logits(int w, int h) {
+    LogitsLayout L;
+    LevelItem it{};
+    item_geometry(it, w, h);
+    L.n_tiles = pruner_mfma_tiles_y(it.hc) * ceil_div(it.wc, 64);
+    const int64_t cells = (int64_t)it.hc * it.wc;
+    int64_t o = 0;
+    L.off_item = o;
+    o = align_up(o + (int64_t)sizeof(LevelItem), kAlign);
+    L.off_tiles = o;
+    o = align_up(o + (int64_t)L.n_tiles * sizeof(Tile), kAlign);
+    L.off_packed = o;
+    o = align_up(o + pruner_packed_bf16_elems() * 2, kAlign);
+    L.off_hog = o;
+    o = align_up(o + (int64_t)PD_HOG_BLOCK * std::max(it.hb, 0) * std::max(it.wb, 0) * 4, kAlign);
+    L.off_lbp = o;
+    o = align_up(o + (int64_t)PD_LBP_BINS * cells, kAlign);
+    L.off_cmap = o;
+    o = align_up(o + cells * PR_CP1 * 2, kAlign);
+    L.off_a1 = o;
+    o = align_up(o + cells * 32 * 2, kAlign);
+    L.off_a2 = o;
+    o = align_up(o + cells * 32 * 2, kAlign);
+    L.total = o;
+    return L;
+}
+
+int64_t pd_pruner_logits_bf16_workspace_bytes(int w, int h) {
+    if (w < PD_WIN_W || h < PD_WIN_H || w > PD_MAX_DIM || h > PD_MAX_DIM)
+        return fail(PD_E_SIZE, "level %dx%d outside [64x128, %d]", w, h, PD_MAX_DIM);
+    return plan_logits(w, h).total;
+}
+
+int pd_pruner_logits_bf16(const uint8_t* lvl, int w, int h, int pitch, const pd_params* params,
+                          const float* pruner, float* logits, void* workspace, int64_t workspace_bytes,
+                          void* stream) {
+    if (int rc = check_image(lvl, w, h, pitch, "level")) return rc;
+    if (!check_params(params)) return PD_E_ARG;
+    if (w < PD_WIN_W || h < PD_WIN_H) return fail(PD_E_SIZE, "level %dx%d smaller than a window", w, h);
+    if (!pruner || !logits) return fail(PD_E_ARG, "NULL pointer argument");
+    const LogitsLayout L = plan_logits(w, h);
+    if (!workspace || workspace_bytes < L.total)
+        return fail(PD_E_WORKSPACE, "workspace of %lld bytes, need %lld", (long long)workspace_bytes,
+                    (long long)L.total);
+    if ((uintptr_t)workspace & (kAlign - 1)) return fail(PD_E_ARG, "workspace must be 256-byte aligned");
+    uint8_t* ws = static_cast<uint8_t*>(workspace);
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<uint8_t> host((size_t)L.off_packed);
+    LevelItem& it = *reinterpret_cast<LevelItem*>(host.data() + L.off_item);
+    item_geometry(it, w, h);
+    it.pyr = const_cast<uint8_t*>(lvl);
+    it.pitch = pitch;
+    it.hog = reinterpret_cast<float*>(ws + L.off_hog);
+    it.lbp = ws + L.off_lbp;
+    it.cmap16 = reinterpret_cast<uint16_t*>(ws + L.off_cmap);
+    it.act1 = reinterpret_cast<uint16_t*>(ws + L.off_a1);
+    it.act2 = reinterpret_cast<uint16_t*>(ws + L.off_a2);
+    it.logit = logits;
+    Tile* tiles = reinterpret_cast<Tile*>(host.data() + L.off_tiles);
+    int t = 0;
+    for (int ty = 0; ty < pruner_mfma_tiles_y(it.hc); ++ty)
+        for (int tx = 0; tx < ceil_div(it.wc, 64); ++tx) tiles[t++] = Tile{0, ty, tx, 0};
+    int rc;
+    if ((rc = stage_upload(host.data(), host.size(), ws, s))) return rc;
+    uint16_t* packed = reinterpret_cast<uint16_t*>(ws + L.off_packed);
+    if ((rc = hip_status(launch_pruner_pack_bf16(pruner, packed, s), "pruner pack"))) return rc;
+    if ((rc = hip_status(launch_features_cellmap_single(it, params->clip, params->eps, s), "cell map"))) return rc;
+    return hip_status(launch_pruner_mfma(reinterpret_cast<const LevelItem*>(ws + L.off_item),
+                                         reinterpret_cast<const Tile*>(ws + L.off_tiles), L.n_tiles, pruner, packed,
+                                         s),
+                      "pruner mfma");
+}
+
 int pd_lbp(const uint8_t* lvl, int w, int h, int pitch, uint8_t* cell_hist, void* stream) {
     if (!cell_hist) return fail(PD_E_ARG, "cell_hist is NULL");
     pd_params p;

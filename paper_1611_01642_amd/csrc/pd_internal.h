@@ -19,6 +19,10 @@ struct LevelItem {
     uint8_t* lbp;         // [59][hc][wc]
     float* scores;        // [n_models][ny][nx]
     float* cmap;          // pruner cell map [68][hc][wc] FP32, or NULL
+    uint16_t* cmap16;     // pruner cell map [hc][wc][72] BF16 (channels 68..71 zero), or NULL
+    uint16_t* act1;       // pruner layer outputs [hc][wc][32] BF16
+    uint16_t* act2;
+    float* logit;         // pruner logits [hc][wc]
     int32_t src_w, src_h, src_pitch;
     int32_t w, h, pitch;
     int32_t wc, hc, wb, hb, nx, ny;
@@ -157,6 +161,13 @@ hipError_t launch_nms_table(const NmsGeom* geoms, int n_frames, const int32_t* c
                             const int32_t* near_count, pd_box* boxes, int cap, pd_counts* counts, hipStream_t s);
 hipError_t launch_nms_single(const NmsGeom& g, int n, const float* cand_score, const int4* cand_key,
                              pd_box* boxes, int cap, pd_counts* counts, hipStream_t s);
+// BF16 MFMA inference of the pruner network (channels-last BF16 maps).
+constexpr int PR_CP1 = 72;  // layer-1 input channel stride
+int64_t pruner_packed_bf16_elems();
+hipError_t launch_pruner_pack_bf16(const float* params, uint16_t* packed, hipStream_t s);
+int pruner_mfma_tiles_y(int hc);  // row pairs
+hipError_t launch_pruner_mfma(const LevelItem* items, const Tile* tiles, int n_tiles, const float* params,
+                              const uint16_t* packed, hipStream_t s);
 int64_t pruner_prep_floats();
 hipError_t launch_pruner_prep(const float* params, float* prep, hipStream_t s);
 hipError_t launch_pruner_forward(const NetItem* items, const Tile* tiles, int n_tiles, const float* params,

@@ -302,6 +302,156 @@ __global__ void __launch_bounds__(256) window_labels_kernel(const float* __restr
     labels[e] = win && (double)scores[(size_t)i * nx + j] > thr[0] ? 1.0f : 0.0f;
 }
 
+// ---- BF16 MFMA inference ------------------------------------------------------
+// Implicit GEMM per layer on v_mfma_f32_16x16x32_bf16: M = 16 cells of a row,
+// N = 16 output channels, K = (tap, input channel) with the channel vector of
+// each neighbour cell contiguous (channels-last maps).  A workgroup computes
+// 2 rows x 64 cells: it stages the 4 x 66 input cells and the layer's packed
+// weights (fragment order) in LDS; each wave owns 32 cells (2 M-tiles) of one
+// row and all output channels.  FP32 accumulation; bias and ReLU in FP32,
+// outputs rounded to BF16; the last layer applies the 1x1 head (cross-lane
+// sum over the 16 channels) and writes FP32 logits.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <int L>
+struct Layer;
+template <>
+struct Layer<1> {
+    static constexpr int CIN = 68, CP = PR_CP1, XS = PR_CP1, COUT = 32;
+};
+template <>
+struct Layer<2> {
+    static constexpr int CIN = 32, CP = 32, XS = 40, COUT = 32;
+};
+template <>
+struct Layer<3> {
+    static constexpr int CIN = 32, CP = 32, XS = 40, COUT = 16;
+};
+template <int L>
+struct LayerDims : Layer<L> {
+    static constexpr int KCH = (9 * Layer<L>::CP + 31) / 32;  // K chunks of 32
+    static constexpr int NT = Layer<L>::COUT / 16;            // N tiles
+    static constexpr int PACKED = KCH * NT * 64 * 8;          // bf16 values
+    static constexpr int PARAMS = Layer<L>::COUT * Layer<L>::CIN * 9;
+};
+
+constexpr int MR = 2;           // output rows per workgroup
+constexpr int MC = 64;          // output cells per row
+constexpr int XR = MR + 2, XC = MC + 2;
+
+template <int L>
+__global__ void __launch_bounds__(256) pack_bf16_kernel(const float* __restrict__ w, uint16_t* __restrict__ out) {
+    using D = LayerDims<L>;
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= D::PACKED) return;
+    const int t = e / (D::NT * 512), n = (e / 512) % D::NT, l = (e / 8) % 64, j = e % 8;
+    const int k = 32 * t + 8 * (l >> 4) + j, och = 16 * n + (l & 15);
+    const int tap = k / D::CP, c = k - tap * D::CP;
+    const float v = (tap < 9 && c < D::CIN) ? w[((size_t)och * D::CIN + c) * 9 + tap] : 0.0f;
+    out[e] = f32_to_bf16(v);
+}
+
+template <int L>
+__global__ void __launch_bounds__(256) conv_mfma_kernel(const LevelItem* __restrict__ items,
+                                                        const Tile* __restrict__ tiles,
+                                                        const uint16_t* __restrict__ packed,
+                                                        const float* __restrict__ bias,
+                                                        const float* __restrict__ head) {
+    using D = LayerDims<L>;
+    constexpr int CP = D::CP, XS = D::XS, KCH = D::KCH, NT = D::NT;
+    __shared__ __attribute__((aligned(16))) uint16_t xs[XR * XC * XS];
+    __shared__ __attribute__((aligned(16))) uint16_t wsm[D::PACKED];
+    const Tile tl = tiles[blockIdx.x];
+    const LevelItem& it = items[tl.item];
+    const int wc = it.wc, hc = it.hc;
+    const int p0 = tl.ty * MR, q0 = tl.tx * MC;
+    const uint16_t* in = L == 1 ? it.cmap16 : (L == 2 ? it.act1 : it.act2);
+    const int tid = threadIdx.x;
+
+    // stage weights and the (MR + 2) x (MC + 2) input cells, zero outside the map
+    {
+        const u32x4* src = reinterpret_cast<const u32x4*>(packed);
+        u32x4* dst = reinterpret_cast<u32x4*>(wsm);
+        for (int e = tid; e < D::PACKED / 8; e += 256) dst[e] = src[e];
+        constexpr int PARTS = CP / 8;
+        for (int e = tid; e < XR * XC * PARTS; e += 256) {
+            const int cell = e / PARTS, part = e - cell * PARTS;
+            const int r = cell / XC, col = cell - r * XC;
+            const int y = p0 - 1 + r, x = q0 - 1 + col;
+            u32x4 v = {0u, 0u, 0u, 0u};
+            if (y >= 0 && y < hc && x >= 0 && x < wc)
+                v = *reinterpret_cast<const u32x4*>(in + ((size_t)y * wc + x) * CP + 8 * part);
+            *reinterpret_cast<u32x4*>(xs + cell * XS + 8 * part) = v;
+        }
+    }
+    __syncthreads();
+
+    const int wave = tid >> 6, lane = tid & 63;
+    const int prow = wave >> 1;               // output row within the pair
+    const int cbase = (wave & 1) * 32;        // first cell of the wave within the tile
+    f32x4 acc[2][NT];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int n = 0; n < NT; ++n) acc[mt][n] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int t = 0; t < KCH; ++t) {
+        const int k0 = 32 * t + 8 * (lane >> 4);
+        const int tap = k0 / CP, c0 = k0 - tap * CP;
+        const int u = tap / 3, v = tap - 3 * (tap / 3);
+        bf16x8 a[2];
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) {
+            const int col = cbase + 16 * mt + (lane & 15);
+            u32x4 av = {0u, 0u, 0u, 0u};
+            if (tap < 9) av = *reinterpret_cast<const u32x4*>(xs + ((prow + u) * XC + col + v) * XS + c0);
+            a[mt] = __builtin_bit_cast(bf16x8, av);
+        }
+#pragma unroll
+        for (int n = 0; n < NT; ++n) {
+            const bf16x8 b =
+                __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(wsm + ((t * NT + n) * 64 + lane) * 8));
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt) acc[mt][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], b, acc[mt][n], 0, 0, 0);
+        }
+    }
+
+    // lane holds D[cell 4 * (lane / 16) + r][channel lane % 16] of each tile
+    const int p = p0 + prow;
+    if (L < 3) {
+        uint16_t* out = L == 1 ? it.act1 : it.act2;
+#pragma unroll
+        for (int n = 0; n < NT; ++n) {
+            const int och = 16 * n + (lane & 15);
+            const float b = bias[och];
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int q = q0 + cbase + 16 * mt + 4 * (lane >> 4) + r;
+                    if (p < hc && q < wc) out[((size_t)p * wc + q) * 32 + och] = f32_to_bf16(fmaxf(acc[mt][n][r] + b, 0.0f));
+                }
+        }
+    } else {
+        const int och = lane & 15;
+        const float b = bias[och], hw = head[och], hb = head[16];
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                float z = hw * fmaxf(acc[mt][0][r] + b, 0.0f);
+                z += __shfl_xor(z, 8, 16);
+                z += __shfl_xor(z, 4, 16);
+                z += __shfl_xor(z, 2, 16);
+                z += __shfl_xor(z, 1, 16);
+                const int q = q0 + cbase + 16 * mt + 4 * (lane >> 4) + r;
+                if (och == 0 && p < hc && q < wc) it.logit[(size_t)p * wc + q] = z + hb;
+            }
+    }
+}
+
 }  // namespace
 
 int64_t pruner_prep_floats() {
@@ -393,6 +543,37 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, int n, int 
 hipError_t launch_window_labels(const float* scores, int nx, int ny, int wc, int hc, const double* thr,
                                 float* labels, float* mask, hipStream_t s) {
     window_labels_kernel<<<ceil_div(wc * hc, 256), 256, 0, s>>>(scores, nx, ny, wc, hc, thr, labels, mask);
+    return hipGetLastError();
+}
+
+int64_t pruner_packed_bf16_elems() {
+    return (int64_t)LayerDims<1>::PACKED + LayerDims<2>::PACKED + LayerDims<3>::PACKED;
+}
+
+hipError_t launch_pruner_pack_bf16(const float* params, uint16_t* packed, hipStream_t s) {
+    const float* w1 = params;
+    const float* w2 = w1 + LayerDims<1>::PARAMS + 32;
+    const float* w3 = w2 + LayerDims<2>::PARAMS + 32;
+    pack_bf16_kernel<1><<<ceil_div(LayerDims<1>::PACKED, 256), 256, 0, s>>>(w1, packed);
+    pack_bf16_kernel<2><<<ceil_div(LayerDims<2>::PACKED, 256), 256, 0, s>>>(w2, packed + LayerDims<1>::PACKED);
+    pack_bf16_kernel<3><<<ceil_div(LayerDims<3>::PACKED, 256), 256, 0, s>>>(
+        w3, packed + LayerDims<1>::PACKED + LayerDims<2>::PACKED);
+    return hipGetLastError();
+}
+
+int pruner_mfma_tiles_y(int hc) { return ceil_div(hc, MR); }
+
+hipError_t launch_pruner_mfma(const LevelItem* items, const Tile* tiles, int n_tiles, const float* params,
+                              const uint16_t* packed, hipStream_t s) {
+    if (n_tiles <= 0) return hipSuccess;
+    const float* b1 = params + LayerDims<1>::PARAMS;
+    const float* b2 = b1 + 32 + LayerDims<2>::PARAMS;
+    const float* b3 = b2 + 32 + LayerDims<3>::PARAMS;
+    const float* head = b3 + 16;
+    conv_mfma_kernel<1><<<n_tiles, 256, 0, s>>>(items, tiles, packed, b1, nullptr);
+    conv_mfma_kernel<2><<<n_tiles, 256, 0, s>>>(items, tiles, packed + LayerDims<1>::PACKED, b2, nullptr);
+    conv_mfma_kernel<3><<<n_tiles, 256, 0, s>>>(items, tiles, packed + LayerDims<1>::PACKED + LayerDims<2>::PACKED,
+                                                b3, head);
     return hipGetLastError();
 }
 

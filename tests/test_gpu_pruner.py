@@ -131,3 +131,19 @@ def test_window_labels_match_oracle():
     torch.cuda.synchronize()
     el, em = P.window_labels(hc, wc, scores.astype(np.float64), 0.8)
     assert np.array_equal(lab.cpu().numpy(), el) and np.array_equal(mask.cpu().numpy(), em)
+
+
+@pytest.mark.parametrize("w,h,seed", [(64, 128, 21), (640, 480, 22), (1242, 375, 23), (333, 200, 24)])
+def test_bf16_inference_logits_match_oracle(w, h, seed):
+    """Cell map (BF16, channels-last) and the network on BF16 MFMA against the
+    FP64 oracle: BF16 rounding of the inputs, weights and two layer outputs
+    bounds the error at a few 1e-3 of the logit scale."""
+    img = pd_synth.frame(w, h, seed)
+    params = pd_synth.pruner_init(seed=seed)
+    print(f"\n[bf16 logits] {w}x{h}", flush=True)
+    got = pd.pruner_logits_bf16(to_dev(img), to_dev(params)).cpu().numpy().astype(np.float64)
+    exp, _ = P.forward(P.cellmap(img), params.astype(np.float64))
+    scale = np.abs(exp).max()
+    err = np.abs(got - exp).max()
+    print(f"[bf16 logits] max |err| {err:.3g}, max |z| {scale:.3g}", flush=True)
+    assert err <= 2e-2 * scale
