@@ -91,11 +91,18 @@ typedef struct pd_params {
     int32_t tune_grid;       /* 0: one workgroup per tile group; n > 0:
                                 feature and scoring grids of at most n
                                 workgroups looping over the tiles          */
-    int32_t reserved;        /* zero                                       */
+    /* Learned window pruning (pd_detect; see the pruner section below):
+       with prune_keep = K > 0 the network `pruner` (device float
+       [PD_PRUNER_PARAMS]) runs on every level (BF16 MFMA) and, per frame,
+       only windows whose logit is >= the K-th largest window logit of the
+       frame (ties kept) can be detections; score tiles holding none of them
+       are not scored.  0 = off (pruner ignored).                          */
+    int32_t prune_keep;
+    const float* pruner;
 } pd_params;
 
 /* Fills the defaults above: 11/10, all levels, 0.2, 1e-3, HOG|LBP, FP32,
-   margin 0.05, default tile shapes. */
+   margin 0.05, default tile shapes, no pruning. */
 void pd_params_default(pd_params* p);
 
 /* One pyramid level as planned by pd_plan_pyramid (host struct). */

@@ -44,7 +44,7 @@ class Params(ctypes.Structure):
                 ("max_levels", ctypes.c_int32), ("clip", ctypes.c_float), ("eps", ctypes.c_float),
                 ("features", ctypes.c_int32), ("precision", ctypes.c_int32), ("margin", ctypes.c_float),
                 ("tune_feat_rows", ctypes.c_int32), ("tune_score_rows", ctypes.c_int32),
-                ("tune_grid", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("tune_grid", ctypes.c_int32), ("prune_keep", ctypes.c_int32), ("pruner", ctypes.c_void_p)]
 
     TUNING = ("tune_feat_rows", "tune_score_rows", "tune_grid")
 
@@ -169,7 +169,10 @@ def _check(rc: int) -> None:
 
 def params(scale=(11, 10), max_levels: int = 0, clip: float = 0.2, eps: float = 1e-3,
            features: int = FEAT_HOG | FEAT_LBP, precision: int = PREC_F32, margin: float = 0.05,
-           tune_feat_rows: int = 0, tune_score_rows: int = 0, tune_grid: int = 0) -> Params:
+           tune_feat_rows: int = 0, tune_score_rows: int = 0, tune_grid: int = 0, prune_keep: int = 0,
+           pruner=None) -> Params:
+    """pd_params; `pruner` is a device float32 tensor of PRUNER_PARAMS values
+    (the caller keeps it alive while the params are in use)."""
     p = Params()
     lib().pd_params_default(ctypes.byref(p))
     p.scale_num, p.scale_den = scale
@@ -180,6 +183,8 @@ def params(scale=(11, 10), max_levels: int = 0, clip: float = 0.2, eps: float = 
     p.precision = precision
     p.margin = margin
     p.tune_feat_rows, p.tune_score_rows, p.tune_grid = tune_feat_rows, tune_score_rows, tune_grid
+    p.prune_keep = prune_keep
+    p.pruner = pruner.data_ptr() if pruner is not None else None
     return p
 
 

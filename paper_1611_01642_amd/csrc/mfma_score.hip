@@ -266,8 +266,10 @@ template <bool LOOP>
 __global__ void __launch_bounds__(256) mfma_table_kernel(const LevelItem* __restrict__ items,
                                                          const Tile* __restrict__ tiles, int n_tiles,
                                                          const uint16_t* __restrict__ wpk,
-                                                         const float* __restrict__ bias, int n_models, int feat) {
+                                                         const float* __restrict__ bias, int n_models, int feat,
+                                                         const int* __restrict__ n_dev) {
     __shared__ MfmaShared sm;
+    if (n_dev) n_tiles = min(n_tiles, *n_dev);
     auto one = [&](int t) __attribute__((always_inline)) {
         const Tile tl = tiles[t];
         const LevelItem& it = items[tl.item];
@@ -284,7 +286,7 @@ __global__ void __launch_bounds__(256) mfma_table_kernel(const LevelItem* __rest
             one(t);
             __syncthreads();
         }
-    } else {
+    } else if ((int)blockIdx.x < n_tiles) {
         one(blockIdx.x);
     }
 }
@@ -310,13 +312,14 @@ hipError_t launch_mfma_single(const LevelItem& it, const uint16_t* wpk, const fl
 }
 
 hipError_t launch_mfma_table(const LevelItem* items, const Tile* tiles, int n_tiles, const uint16_t* wpk,
-                             const float* bias, int n_models, int features, int grid, hipStream_t s) {
+                             const float* bias, int n_models, int features, int grid, hipStream_t s,
+                             const int* n_dev) {
     if (n_tiles <= 0) return hipSuccess;
     const int feat = features & (PD_FEAT_HOG | PD_FEAT_LBP);
     if (grid > 0 && grid < n_tiles)
-        mfma_table_kernel<true><<<grid, 256, 0, s>>>(items, tiles, n_tiles, wpk, bias, n_models, feat);
+        mfma_table_kernel<true><<<grid, 256, 0, s>>>(items, tiles, n_tiles, wpk, bias, n_models, feat, n_dev);
     else
-        mfma_table_kernel<false><<<n_tiles, 256, 0, s>>>(items, tiles, n_tiles, wpk, bias, n_models, feat);
+        mfma_table_kernel<false><<<n_tiles, 256, 0, s>>>(items, tiles, n_tiles, wpk, bias, n_models, feat, n_dev);
     return hipGetLastError();
 }
 

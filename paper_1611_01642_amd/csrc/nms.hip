@@ -28,12 +28,17 @@ __global__ void __launch_bounds__(256) compact_kernel(const LevelItem* __restric
                                                       float* __restrict__ cand_score,
                                                       int4* __restrict__ cand_key, double* __restrict__ cand_s64,
                                                       int32_t* __restrict__ near_count,
-                                                      int4* __restrict__ near_key, int n_frames) {
+                                                      int4* __restrict__ near_key, int n_frames,
+                                                      const float* __restrict__ kth) {
     const Tile tl = tiles[blockIdx.x];
     const LevelItem& it = items[tl.item];
     const int n = it.nx * it.ny;
     const int q = tl.tx * CP_N + threadIdx.x;
     if (q >= n) return;
+    if (kth) {  // pruned: only windows the network keeps can be detections
+        const int wi = q / it.nx, wj = q - wi * it.nx;
+        if (!(it.logit[(size_t)(wi + PRUNER_WIN_DI) * it.wc + wj + PRUNER_WIN_DJ] >= kth[it.frame])) return;
+    }
     const float* s = it.scores + q;
     float best = s[0];
     int bm = 0;
@@ -246,7 +251,17 @@ hipError_t launch_compact_margin(const LevelItem* items, const Tile* tiles, int 
                                  int n_frames, hipStream_t s) {
     if (n_tiles <= 0) return hipSuccess;
     compact_kernel<<<n_tiles, 256, 0, s>>>(items, tiles, n_models, thresholds, margin, counters, cand_score, cand_key,
-                                           cand_s64, near_count, near_key, n_frames);
+                                           cand_s64, near_count, near_key, n_frames, nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_compact_margin_pruned(const LevelItem* items, const Tile* tiles, int n_tiles, int n_models,
+                                       const double* thresholds, float margin, int32_t* counters, float* cand_score,
+                                       int4* cand_key, double* cand_s64, int32_t* near_count, int4* near_key,
+                                       int n_frames, const float* kth, hipStream_t s) {
+    if (n_tiles <= 0) return hipSuccess;
+    compact_kernel<<<n_tiles, 256, 0, s>>>(items, tiles, n_models, thresholds, margin, counters, cand_score, cand_key,
+                                           cand_s64, near_count, near_key, n_frames, kth);
     return hipGetLastError();
 }
 

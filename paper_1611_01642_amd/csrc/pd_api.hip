@@ -55,6 +55,10 @@ bool check_params(const pd_params* p) {
         return fail(PD_E_ARG, "tune_score_rows must be 0, 8 or 16"), false;
     if (p->tune_grid < 0 || p->tune_grid > (1 << 20))
         return fail(PD_E_ARG, "tune_grid must be in [0, 2^20]"), false;
+    if (p->prune_keep < 0) return fail(PD_E_ARG, "prune_keep must be >= 0"), false;
+    if (p->prune_keep > 0 && !p->pruner) return fail(PD_E_ARG, "prune_keep > 0 needs the pruner weights"), false;
+    if (p->prune_keep > 0 && p->features != (PD_FEAT_HOG | PD_FEAT_LBP))
+        return fail(PD_E_ARG, "pruning needs HOG and LBP features"), false;
     return true;
 }
 
@@ -284,8 +288,11 @@ void item_geometry(LevelItem& it, int w, int h) {
 // and by pd_detect.
 struct DetectLayout {
     int n_items = 0;
-    int n_rs = 0, n_ft = 0, n_sc = 0, n_cp = 0;  // tile table capacities
+    int n_rs = 0, n_ft = 0, n_sc = 0, n_cp = 0, n_pr = 0;  // tile table capacities
     bool bf16 = false;
+    bool prune = false;  // learned pruning: cell maps, network, top-K, tile filter
+    int64_t off_kth = 0, off_kept = 0, off_prpack = 0;
+    std::vector<int64_t> cm_off, a1_off, a2_off, lg_off;  // per item (pruning)
     int64_t off_items = 0, off_tiles = 0, off_geoms = 0, off_first = 0, off_counters = 0, off_cscore = 0,
             off_ckey = 0, off_c64 = 0, off_near_count = 0, off_near_key = 0, off_packed = 0;
     int64_t off_data = 0, total = 0;
@@ -298,6 +305,7 @@ struct DetectLayout {
 bool plan_detect(const pd_frame* frames, int n_frames, const pd_params* p, int n_models, DetectLayout& L) {
     L = DetectLayout();
     L.bf16 = p->precision == PD_PREC_BF16;
+    L.prune = p->prune_keep > 0;
     L.level_count.resize(n_frames);
     int wh[PD_MAX_LEVELS][2];
     int64_t data = 0;
@@ -322,13 +330,25 @@ bool plan_detect(const pd_frame* frames, int n_frames, const pd_params* p, int n
             data = align_up(data + (int64_t)PD_LBP_BINS * it.hc * it.wc, kAlign);
             L.sc_off.push_back(data);
             data = align_up(data + (int64_t)n_models * it.ny * it.nx * 4, kAlign);
+            if (L.prune) {
+                const int64_t cells = (int64_t)it.hc * it.wc;
+                L.cm_off.push_back(data);
+                data = align_up(data + cells * PR_CP1 * 2, kAlign);
+                L.a1_off.push_back(data);
+                data = align_up(data + cells * 32 * 2, kAlign);
+                L.a2_off.push_back(data);
+                data = align_up(data + cells * 32 * 2, kAlign);
+                L.lg_off.push_back(data);
+                data = align_up(data + cells * 4, kAlign);
+                L.n_pr += pruner_mfma_tiles_y(it.hc) * ceil_div(it.wc, 64);
+            }
             L.n_rs += resize_tiles_x(it.w) * resize_tiles_y(it.h);  // upper bound
             // table capacity for the finest tile shapes the tuning fields
             // allow, so the workspace size does not depend on them
-            L.n_ft += feat_tiles_x(it.wc) * feat_tiles_y(it.hc, FT_MIN_ROWS);
+            L.n_ft += (L.prune ? feat_tiles_x_cm(it.wc) : feat_tiles_x(it.wc)) * feat_tiles_y(it.hc, FT_MIN_ROWS);
             L.n_sc += !L.bf16 ? score_tiles_x(it.nx) * score_tiles_y(it.ny, SC_R) * n_models
-                      : n_models == 1 ? ceil_div(it.nx, RG_TILE_C)
-                                      : ceil_div(it.nx, MF_TILE_C) * ceil_div(it.ny, MF_TILE_R);
+                      : (n_models == 1 && !L.prune) ? ceil_div(it.nx, RG_TILE_C)
+                                                    : ceil_div(it.nx, MF_TILE_C) * ceil_div(it.ny, MF_TILE_R);
             L.n_cp += ceil_div(it.nx * it.ny, CP_N);
             ++L.n_items;
         }
@@ -337,7 +357,7 @@ bool plan_detect(const pd_frame* frames, int n_frames, const pd_params* p, int n
     L.off_items = o;
     o = align_up(o + (int64_t)L.n_items * sizeof(LevelItem), kAlign);
     L.off_tiles = o;
-    o = align_up(o + (int64_t)(L.n_rs + L.n_ft + L.n_sc + L.n_cp) * sizeof(Tile), kAlign);
+    o = align_up(o + (int64_t)(L.n_rs + L.n_ft + L.n_sc + L.n_cp + L.n_pr) * sizeof(Tile), kAlign);
     L.off_geoms = o;
     o = align_up(o + (int64_t)n_frames * sizeof(NmsGeom), kAlign);
     L.off_first = o;
@@ -345,8 +365,8 @@ bool plan_detect(const pd_frame* frames, int n_frames, const pd_params* p, int n
     L.table_bytes = o;
     L.off_counters = o;  // candidate counters, then near counters (zeroed together)
     o = align_up(o + (int64_t)n_frames * 4, kAlign);
-    L.off_near_count = o;  // per-frame near counters + the dense list length
-    o = align_up(o + (int64_t)(n_frames + 1) * 4, kAlign);
+    L.off_near_count = o;  // per-frame near counters + the dense list length (+ kept tiles)
+    o = align_up(o + (int64_t)(n_frames + 2) * 4, kAlign);
     L.off_cscore = o;
     o = align_up(o + (int64_t)n_frames * PD_MAX_CANDIDATES * 4, kAlign);
     L.off_ckey = o;
@@ -358,6 +378,14 @@ bool plan_detect(const pd_frame* frames, int n_frames, const pd_params* p, int n
         o = align_up(o + (int64_t)n_frames * MAX_NEAR * 16, kAlign);
         L.off_packed = o;
         o = align_up(o + (packed_weight_elems() + rowgemm_packed_elems()) * 2, kAlign);
+    }
+    if (L.prune) {
+        L.off_kth = o;
+        o = align_up(o + (int64_t)n_frames * 4, kAlign);
+        L.off_kept = o;
+        o = align_up(o + (int64_t)L.n_sc * sizeof(Tile), kAlign);
+        L.off_prpack = o;
+        o = align_up(o + pruner_packed_bf16_elems() * 2, kAlign);
     }
     L.off_data = o;
     L.total = o + data;
@@ -441,7 +469,13 @@ struct DetectRun {
     double* c64 = nullptr;
     int4* near_key = nullptr;
     uint16_t* packed = nullptr;
-    int n_zero = 0;  // counters + near counters, cleared together
+    int n_zero = 0;  // counters + near counters (+ kept-tile count), cleared together
+    const Tile* t_pr = nullptr;  // pruner conv tiles
+    int npr = 0;
+    float* kth = nullptr;        // per frame: K-th largest window logit
+    Tile* kept = nullptr;        // score tiles that hold a kept window
+    int32_t* kept_count = nullptr;
+    uint16_t* prpack = nullptr;  // BF16 fragment-packed pruner weights
 };
 
 // Builds the level, tile and NMS tables of one call in host memory `stage`
@@ -458,7 +492,8 @@ void fill_tables(const pd_frame* frames, int n_frames, int n_models, const Tunin
     Tile* t_ft = t_rs + L.n_rs;
     Tile* t_sc = t_ft + L.n_ft;
     Tile* t_cp = t_sc + L.n_sc;
-    int q = 0, nrs = 0, nft = 0, nsc = 0, ncp = 0;
+    Tile* t_pr = t_cp + L.n_cp;
+    int q = 0, nrs = 0, nft = 0, nsc = 0, ncp = 0, npr = 0;
     for (int f = 0; f < n_frames; ++f) {
         geoms[f].n_levels = L.level_count[f];
         first[f] = q;
@@ -488,9 +523,18 @@ void fill_tables(const pd_frame* frames, int n_frames, int n_models, const Tunin
             if (!direct)
                 for (int ty = 0; ty < resize_tiles_y(it.h); ++ty)
                     for (int tx = 0; tx < resize_tiles_x(it.w); ++tx) t_rs[nrs++] = Tile{q, ty, tx, 0};
+            const int ftx = L.prune ? feat_tiles_x_cm(it.wc) : feat_tiles_x(it.wc);
             for (int ty = 0; ty < feat_tiles_y(it.hc, tu.feat_rows); ++ty)
-                for (int tx = 0; tx < feat_tiles_x(it.wc); ++tx) t_ft[nft++] = Tile{q, ty, tx, 0};
-            if (L.bf16 && n_models == 1) {
+                for (int tx = 0; tx < ftx; ++tx) t_ft[nft++] = Tile{q, ty, tx, 0};
+            if (L.prune) {
+                it.cmap16 = reinterpret_cast<uint16_t*>(data + L.cm_off[q]);
+                it.act1 = reinterpret_cast<uint16_t*>(data + L.a1_off[q]);
+                it.act2 = reinterpret_cast<uint16_t*>(data + L.a2_off[q]);
+                it.logit = reinterpret_cast<float*>(data + L.lg_off[q]);
+                for (int ty = 0; ty < pruner_mfma_tiles_y(it.hc); ++ty)
+                    for (int tx = 0; tx < ceil_div(it.wc, 64); ++tx) t_pr[npr++] = Tile{q, ty, tx, 0};
+            }
+            if (L.bf16 && n_models == 1 && !L.prune) {
                 for (int tx = 0; tx < ceil_div(it.nx, RG_TILE_C); ++tx) t_sc[nsc++] = Tile{q, 0, tx, 0};
             } else if (L.bf16) {
                 for (int ty = 0; ty < ceil_div(it.ny, MF_TILE_R); ++ty)
@@ -523,6 +567,14 @@ void fill_tables(const pd_frame* frames, int n_frames, int n_models, const Tunin
     R.near_key = L.bf16 ? reinterpret_cast<int4*>(ws + L.off_near_key) : nullptr;
     R.packed = L.bf16 ? reinterpret_cast<uint16_t*>(ws + L.off_packed) : nullptr;
     R.n_zero = (int)((L.off_cscore - L.off_counters) / 4);
+    if (L.prune) {
+        R.t_pr = d_tiles + L.n_rs + L.n_ft + L.n_sc + L.n_cp;
+        R.npr = npr;
+        R.kth = reinterpret_cast<float*>(ws + L.off_kth);
+        R.kept = reinterpret_cast<Tile*>(ws + L.off_kept);
+        R.kept_count = reinterpret_cast<int32_t*>(ws + L.off_near_count) + n_frames + 1;
+        R.prpack = reinterpret_cast<uint16_t*>(ws + L.off_prpack);
+    }
 }
 
 // The kernel sequence of one call (tables already uploaded).  Only kernels are
@@ -537,9 +589,49 @@ int enqueue_detect(const DetectRun& R, const DetectLayout& L, const Tuning& tu, 
         if ((rc = hip_status(launch_pack_weights(weights, n_models, R.packed, s), "pack"))) return rc;
         if ((rc = hip_status(launch_pack_rowgemm(weights, R.packed + packed_weight_elems(), s), "pack"))) return rc;
     }
+    if (L.prune && (rc = hip_status(launch_pruner_pack_bf16(params->pruner, R.prpack, s), "pruner pack")))
+        return rc;
     marks.mark(PD_STAGE_RESIZE, s);
     if ((rc = hip_status(launch_resize_table(R.items, R.t_rs, R.nrs, s), "resize"))) return rc;
     marks.mark(PD_STAGE_FEATURES, s);
+    if (L.prune) {
+        if ((rc = hip_status(launch_features_cellmap_table(R.items, R.t_ft, R.nft, params->clip, params->eps, tu, s),
+                             "features + cell map")))
+            return rc;
+        marks.mark(PD_STAGE_SCORE, s);
+        if ((rc = hip_status(launch_pruner_mfma(R.items, R.t_pr, R.npr, params->pruner, R.prpack, s), "pruner")))
+            return rc;
+        if ((rc = hip_status(launch_topk(R.items, R.first, R.geoms, n_frames, params->prune_keep, R.kth, s), "top-k")))
+            return rc;
+        const int rows = L.bf16 ? MF_TILE_R : tu.score_rows, cols = L.bf16 ? MF_TILE_C : SC_W;
+        if ((rc = hip_status(launch_tile_filter(R.items, R.t_sc, R.nsc, rows, cols, R.kth, R.kept, R.kept_count, s),
+                             "tile filter")))
+            return rc;
+        if (L.bf16)
+            rc = hip_status(launch_mfma_table(R.items, R.kept, R.nsc, R.packed, bias, n_models, params->features,
+                                              tu.grid, s, R.kept_count),
+                            "bf16 score");
+        else
+            rc = hip_status(launch_score_table(R.items, R.kept, R.nsc, weights, bias, n_models, params->features, tu,
+                                               s, R.kept_count),
+                            "score");
+        if (rc) return rc;
+        marks.mark(PD_STAGE_COMPACT, s);
+        if ((rc = hip_status(launch_compact_margin_pruned(R.items, R.t_cp, R.ncp, n_models, thresholds,
+                                                          L.bf16 ? params->margin : 0.0f, R.counters, R.cscore,
+                                                          R.ckey, R.c64, R.near_count, R.near_key, n_frames, R.kth, s),
+                             "compact")))
+            return rc;
+        if (L.bf16 && (rc = hip_status(launch_rescore64(R.items, R.first, n_frames, R.near_count, R.near_key,
+                                                        weights, bias, n_models, params->clip, params->eps,
+                                                        thresholds, R.counters, R.cscore, R.ckey, R.c64, s),
+                                       "rescore")))
+            return rc;
+        marks.mark(PD_STAGE_NMS, s);
+        return hip_status(launch_nms_table(R.geoms, n_frames, R.counters, R.cscore, R.ckey, R.c64,
+                                           L.bf16 ? R.near_count : nullptr, boxes, cap, counts, s),
+                          "nms");
+    }
     if ((rc = hip_status(launch_features_table(R.items, R.t_ft, R.nft, params->features, params->clip, params->eps,
                                                tu, s),
                          "features")))

@@ -125,9 +125,10 @@ hipError_t launch_features_cellmap_table(const LevelItem* items, const Tile* til
 
 hipError_t launch_score_single(const LevelItem& it, const float* w, const float* bias, int n_models,
                                int features, hipStream_t s);
+// n_dev (optional): the tile count is read from device memory (at most n_tiles)
 hipError_t launch_score_table(const LevelItem* items, const Tile* tiles, int n_tiles,
                               const float* w, const float* bias, int n_models, int features,
-                              const Tuning& tu, hipStream_t s);
+                              const Tuning& tu, hipStream_t s, const int* n_dev = nullptr);
 
 int64_t packed_weight_elems();
 int64_t rowgemm_packed_elems();
@@ -141,8 +142,13 @@ hipError_t launch_pack_weights(const float* w, int n_models, uint16_t* out, hipS
 hipError_t launch_mfma_single(const LevelItem& it, const uint16_t* wpk, const float* bias, int n_models, int features,
                               hipStream_t s);
 hipError_t launch_mfma_table(const LevelItem* items, const Tile* tiles, int n_tiles, const uint16_t* wpk,
-                             const float* bias, int n_models, int features, int grid, hipStream_t s);
+                             const float* bias, int n_models, int features, int grid, hipStream_t s,
+                             const int* n_dev = nullptr);
 // windows with |score - threshold| < margin go to the near list (margin <= 0: none)
+hipError_t launch_compact_margin_pruned(const LevelItem* items, const Tile* tiles, int n_tiles, int n_models,
+                                       const double* thresholds, float margin, int32_t* counters, float* cand_score,
+                                       int4* cand_key, double* cand_s64, int32_t* near_count, int4* near_key,
+                                       int n_frames, const float* kth, hipStream_t s);
 hipError_t launch_compact_margin(const LevelItem* items, const Tile* tiles, int n_tiles, int n_models,
                                  const double* thresholds, float margin, int32_t* counters, float* cand_score,
                                  int4* cand_key, double* cand_s64, int32_t* near_count, int4* near_key,
@@ -166,6 +172,12 @@ constexpr int PR_CP1 = 72;  // layer-1 input channel stride
 int64_t pruner_packed_bf16_elems();
 hipError_t launch_pruner_pack_bf16(const float* params, uint16_t* packed, hipStream_t s);
 int pruner_mfma_tiles_y(int hc);  // row pairs
+// Per frame, the K-th largest window logit (-inf when K >= windows).
+hipError_t launch_topk(const LevelItem* items, const int32_t* first_item, const NmsGeom* geoms, int n_frames,
+                       int keep_k, float* kth, hipStream_t s);
+// Appends the score tiles (rows x cols windows) that hold a kept window.
+hipError_t launch_tile_filter(const LevelItem* items, const Tile* tiles, int n_tiles, int rows, int cols,
+                              const float* kth, Tile* kept, int32_t* kept_count, hipStream_t s);
 hipError_t launch_pruner_mfma(const LevelItem* items, const Tile* tiles, int n_tiles, const float* params,
                               const uint16_t* packed, hipStream_t s);
 int64_t pruner_prep_floats();

@@ -577,4 +577,108 @@ hipError_t launch_pruner_mfma(const LevelItem* items, const Tile* tiles, int n_t
     return hipGetLastError();
 }
 
+namespace {
+
+// Order-preserving map of a float to an unsigned key (larger float, larger key).
+__device__ __forceinline__ uint32_t fkey(float z) {
+    const uint32_t u = __float_as_uint(z + 0.0f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+// One workgroup per frame: radix selection (8 bits per pass, most significant
+// first) of the K-th largest logit over the frame's windows, every level.
+__global__ void __launch_bounds__(256) topk_kernel(const LevelItem* __restrict__ items,
+                                                   const int32_t* __restrict__ first_item,
+                                                   const NmsGeom* __restrict__ geoms, int keep_k,
+                                                   float* __restrict__ kth) {
+    __shared__ uint32_t hist[256];
+    __shared__ uint32_t sel[2];  // prefix, remaining rank
+    __shared__ int total_s;
+    const int f = blockIdx.x, tid = threadIdx.x;
+    const int i0 = first_item[f], nl = geoms[f].n_levels;
+    if (tid == 0) {
+        int n = 0;
+        for (int l = 0; l < nl; ++l) n += items[i0 + l].nx * items[i0 + l].ny;
+        total_s = n;
+        sel[0] = 0u;
+        sel[1] = (uint32_t)keep_k;
+    }
+    __syncthreads();
+    if (keep_k >= total_s) {  // every window is kept
+        if (tid == 0) kth[f] = -INFINITY;
+        return;
+    }
+    uint32_t mask = 0u;
+    for (int shift = 24; shift >= 0; shift -= 8) {
+        hist[tid] = 0u;
+        __syncthreads();
+        const uint32_t prefix = sel[0];
+        for (int l = 0; l < nl; ++l) {
+            const LevelItem& it = items[i0 + l];
+            const int n = it.nx * it.ny;
+            for (int q = tid; q < n; q += 256) {
+                const int wi = q / it.nx, wj = q - wi * it.nx;
+                const uint32_t k = fkey(it.logit[(size_t)(wi + PRUNER_WIN_DI) * it.wc + wj + PRUNER_WIN_DJ]);
+                if ((k & mask) == prefix) atomicAdd(&hist[(k >> shift) & 255u], 1u);
+            }
+        }
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t rank = sel[1], d = 255u;
+            for (;; --d) {
+                if (hist[d] >= rank || d == 0u) break;
+                rank -= hist[d];
+            }
+            sel[0] = prefix | (d << shift);
+            sel[1] = rank;
+        }
+        mask |= 255u << shift;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const uint32_t k = sel[0];
+        kth[f] = __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
+    }
+}
+
+// One wave per score tile: does any of its windows have logit >= kth?
+__global__ void __launch_bounds__(256) tile_filter_kernel(const LevelItem* __restrict__ items,
+                                                          const Tile* __restrict__ tiles, int n_tiles, int rows,
+                                                          int cols, const float* __restrict__ kth,
+                                                          Tile* __restrict__ kept, int32_t* __restrict__ kept_count) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int t = blockIdx.x * 4 + wave;
+    if (t >= n_tiles) return;
+    const Tile tl = tiles[t];
+    const LevelItem& it = items[tl.item];
+    const float thr = kth[it.frame];
+    bool any = false;
+    for (int c = lane; c < cols; c += 64) {
+        const int j = tl.tx * cols + c;
+        if (j >= it.nx) break;
+        for (int r = 0; r < rows; ++r) {
+            const int i = tl.ty * rows + r;
+            if (i >= it.ny) break;
+            any = any || it.logit[(size_t)(i + PRUNER_WIN_DI) * it.wc + j + PRUNER_WIN_DJ] >= thr;
+        }
+    }
+    if (__any(any) && lane == 0) kept[atomicAdd(kept_count, 1)] = tl;
+}
+
+}  // namespace
+
+hipError_t launch_topk(const LevelItem* items, const int32_t* first_item, const NmsGeom* geoms, int n_frames,
+                       int keep_k, float* kth, hipStream_t s) {
+    if (n_frames <= 0) return hipSuccess;
+    topk_kernel<<<n_frames, 256, 0, s>>>(items, first_item, geoms, keep_k, kth);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_filter(const LevelItem* items, const Tile* tiles, int n_tiles, int rows, int cols,
+                              const float* kth, Tile* kept, int32_t* kept_count, hipStream_t s) {
+    if (n_tiles <= 0) return hipSuccess;
+    tile_filter_kernel<<<ceil_div(n_tiles, 4), 256, 0, s>>>(items, tiles, n_tiles, rows, cols, kth, kept, kept_count);
+    return hipGetLastError();
+}
+
 }  // namespace pd

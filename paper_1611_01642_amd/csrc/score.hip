@@ -154,9 +154,11 @@ template <int FEAT, int R, bool LOOP>
 __global__ void __launch_bounds__(256) score_table_kernel(const LevelItem* __restrict__ items,
                                                           const Tile* __restrict__ tiles, int n_tiles,
                                                           const float* __restrict__ wt,
-                                                          const float* __restrict__ bias) {
+                                                          const float* __restrict__ bias,
+                                                          const int* __restrict__ n_dev) {
     __shared__ float patches[SC_WAVES][Patch<R>::SIZE];
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (n_dev) n_tiles = min(n_tiles, *n_dev);
     auto one = [&](int wave) __attribute__((always_inline)) {
         const Tile tl = tiles[wave];
         const LevelItem& it = items[tl.item];
@@ -181,16 +183,16 @@ hipError_t score_single(const LevelItem& it, const float* w, const float* b, int
 
 template <int FEAT>
 hipError_t score_table(const LevelItem* items, const Tile* tiles, int n, const float* w, const float* b,
-                       const Tuning& tu, hipStream_t s) {
+                       const Tuning& tu, hipStream_t s, const int* nd) {
     const int rows = tu.score_rows == 16 ? 16 : SC_R;
     const int blocks = ceil_div(n, SC_WAVES);
     if (tu.grid > 0 && tu.grid < blocks) {
-        if (rows == 16) score_table_kernel<FEAT, 16, true><<<tu.grid, 256, 0, s>>>(items, tiles, n, w, b);
-        else score_table_kernel<FEAT, SC_R, true><<<tu.grid, 256, 0, s>>>(items, tiles, n, w, b);
+        if (rows == 16) score_table_kernel<FEAT, 16, true><<<tu.grid, 256, 0, s>>>(items, tiles, n, w, b, nd);
+        else score_table_kernel<FEAT, SC_R, true><<<tu.grid, 256, 0, s>>>(items, tiles, n, w, b, nd);
     } else if (rows == 16) {
-        score_table_kernel<FEAT, 16, false><<<blocks, 256, 0, s>>>(items, tiles, n, w, b);
+        score_table_kernel<FEAT, 16, false><<<blocks, 256, 0, s>>>(items, tiles, n, w, b, nd);
     } else {
-        score_table_kernel<FEAT, SC_R, false><<<blocks, 256, 0, s>>>(items, tiles, n, w, b);
+        score_table_kernel<FEAT, SC_R, false><<<blocks, 256, 0, s>>>(items, tiles, n, w, b, nd);
     }
     return hipGetLastError();
 }
@@ -208,13 +210,14 @@ hipError_t launch_score_single(const LevelItem& it, const float* w, const float*
 }
 
 hipError_t launch_score_table(const LevelItem* items, const Tile* tiles, int n_tiles, const float* w,
-                              const float* bias, int n_models, int features, const Tuning& tu, hipStream_t s) {
+                              const float* bias, int n_models, int features, const Tuning& tu, hipStream_t s,
+                              const int* n_dev) {
     (void)n_models;
     if (n_tiles <= 0) return hipSuccess;
     switch (features & (PD_FEAT_HOG | PD_FEAT_LBP)) {
-        case PD_FEAT_HOG: return score_table<PD_FEAT_HOG>(items, tiles, n_tiles, w, bias, tu, s);
-        case PD_FEAT_LBP: return score_table<PD_FEAT_LBP>(items, tiles, n_tiles, w, bias, tu, s);
-        default: return score_table<PD_FEAT_HOG | PD_FEAT_LBP>(items, tiles, n_tiles, w, bias, tu, s);
+        case PD_FEAT_HOG: return score_table<PD_FEAT_HOG>(items, tiles, n_tiles, w, bias, tu, s, n_dev);
+        case PD_FEAT_LBP: return score_table<PD_FEAT_LBP>(items, tiles, n_tiles, w, bias, tu, s, n_dev);
+        default: return score_table<PD_FEAT_HOG | PD_FEAT_LBP>(items, tiles, n_tiles, w, bias, tu, s, n_dev);
     }
 }
 

@@ -28,7 +28,7 @@ def test_library_loads_and_exports_every_declared_symbol():
 
 
 def test_struct_sizes_match_header():
-    assert ctypes.sizeof(pd.Params) == 48
+    assert ctypes.sizeof(pd.Params) == 56
     assert ctypes.sizeof(pd.Level) == 48
     assert ctypes.sizeof(pd.Frame) == 24
     assert pd.BOX_DTYPE.itemsize == 48
