@@ -323,7 +323,7 @@ class PrunerBatch:
     list of cell maps ([68][Hc][Wc] float32 tensors) with optional labels and
     masks ([Hc][Wc] float32)."""
 
-    def __init__(self, cellmaps, labels=None, masks=None):
+    def __init__(self, cellmaps, labels=None, masks=None, workspace=None):
         torch = _torch()
         self.cellmaps = [c.contiguous() for c in cellmaps]
         dev = self.cellmaps[0].device
@@ -341,7 +341,10 @@ class PrunerBatch:
         nbytes = int(lib().pd_pruner_workspace_bytes(self._maps, n))
         _check(nbytes if nbytes < 0 else 0)
         self.ws_bytes = nbytes
-        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        if workspace is not None and workspace.numel() >= nbytes + 256:
+            self.workspace = workspace  # shared by batches that run one after another
+        else:
+            self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
         self.ws_ptr = self.workspace.data_ptr() + (-self.workspace.data_ptr()) % 256
         self.grad = torch.empty(PRUNER_PARAMS, dtype=torch.float32, device=dev)
         self.stats = torch.zeros(2, dtype=torch.float64, device=dev)
