@@ -347,8 +347,8 @@ bool plan_detect(const pd_frame* frames, int n_frames, const pd_params* p, int n
             // allow, so the workspace size does not depend on them
             L.n_ft += (L.prune ? feat_tiles_x_cm(it.wc) : feat_tiles_x(it.wc)) * feat_tiles_y(it.hc, FT_MIN_ROWS);
             L.n_sc += !L.bf16 ? score_tiles_x(it.nx) * score_tiles_y(it.ny, SC_R) * n_models
-                      : (n_models == 1 && !L.prune) ? ceil_div(it.nx, RG_TILE_C)
-                                                    : ceil_div(it.nx, MF_TILE_C) * ceil_div(it.ny, MF_TILE_R);
+                      : n_models == 1 ? ceil_div(it.nx, RG_TILE_C)
+                                      : ceil_div(it.nx, MF_TILE_C) * ceil_div(it.ny, MF_TILE_R);
             L.n_cp += ceil_div(it.nx * it.ny, CP_N);
             ++L.n_items;
         }
@@ -534,7 +534,7 @@ void fill_tables(const pd_frame* frames, int n_frames, int n_models, const Tunin
                 for (int ty = 0; ty < pruner_mfma_tiles_y(it.hc); ++ty)
                     for (int tx = 0; tx < ceil_div(it.wc, 64); ++tx) t_pr[npr++] = Tile{q, ty, tx, 0};
             }
-            if (L.bf16 && n_models == 1 && !L.prune) {
+            if (L.bf16 && n_models == 1) {
                 for (int tx = 0; tx < ceil_div(it.nx, RG_TILE_C); ++tx) t_sc[nsc++] = Tile{q, 0, tx, 0};
             } else if (L.bf16) {
                 for (int ty = 0; ty < ceil_div(it.ny, MF_TILE_R); ++ty)
@@ -604,17 +604,24 @@ int enqueue_detect(const DetectRun& R, const DetectLayout& L, const Tuning& tu, 
         if ((rc = hip_status(launch_topk(R.items, R.first, R.geoms, n_frames, params->prune_keep, R.kth, s), "top-k")))
             return rc;
         const int rows = L.bf16 ? MF_TILE_R : tu.score_rows, cols = L.bf16 ? MF_TILE_C : SC_W;
-        if ((rc = hip_status(launch_tile_filter(R.items, R.t_sc, R.nsc, rows, cols, R.kth, R.kept, R.kept_count, s),
-                             "tile filter")))
-            return rc;
-        if (L.bf16)
-            rc = hip_status(launch_mfma_table(R.items, R.kept, R.nsc, R.packed, bias, n_models, params->features,
-                                              tu.grid, s, R.kept_count),
+        if (L.bf16 && n_models == 1) {
+            // one model: the row-GEMM kernel scores whole 64-column strips, which
+            // nearly always hold a kept window; the keep set acts in compaction
+            rc = hip_status(launch_rowgemm_table(R.items, R.t_sc, R.nsc, R.packed + packed_weight_elems(), bias,
+                                                 tu.grid, s),
                             "bf16 score");
-        else
-            rc = hip_status(launch_score_table(R.items, R.kept, R.nsc, weights, bias, n_models, params->features, tu,
-                                               s, R.kept_count),
-                            "score");
+        } else {
+            rc = hip_status(launch_tile_filter(R.items, R.t_sc, R.nsc, rows, cols, R.kth, R.kept, R.kept_count, s),
+                            "tile filter");
+            if (!rc && L.bf16)
+                rc = hip_status(launch_mfma_table(R.items, R.kept, R.nsc, R.packed, bias, n_models, params->features,
+                                                  tu.grid, s, R.kept_count),
+                                "bf16 score");
+            else if (!rc)
+                rc = hip_status(launch_score_table(R.items, R.kept, R.nsc, weights, bias, n_models, params->features,
+                                                   tu, s, R.kept_count),
+                                "score");
+        }
         if (rc) return rc;
         marks.mark(PD_STAGE_COMPACT, s);
         if ((rc = hip_status(launch_compact_margin_pruned(R.items, R.t_cp, R.ncp, n_models, thresholds,

@@ -370,20 +370,40 @@ __global__ void __launch_bounds__(256) conv_mfma_kernel(const LevelItem* __restr
     const uint16_t* in = L == 1 ? it.cmap16 : (L == 2 ? it.act1 : it.act2);
     const int tid = threadIdx.x;
 
-    // stage weights and the (MR + 2) x (MC + 2) input cells, zero outside the map
+    // stage weights and the (MR + 2) x (MC + 2) input cells, zero outside the
+    // map: every load of a thread is issued before its first LDS store
     {
-        const u32x4* src = reinterpret_cast<const u32x4*>(packed);
-        u32x4* dst = reinterpret_cast<u32x4*>(wsm);
-        for (int e = tid; e < D::PACKED / 8; e += 256) dst[e] = src[e];
+        constexpr int NWQ = (D::PACKED / 8 + 255) / 256;
         constexpr int PARTS = CP / 8;
-        for (int e = tid; e < XR * XC * PARTS; e += 256) {
+        constexpr int NXQ = (XR * XC * PARTS + 255) / 256;
+        const u32x4* src = reinterpret_cast<const u32x4*>(packed);
+        u32x4 wv[NWQ], xv[NXQ];
+#pragma unroll
+        for (int k = 0; k < NWQ; ++k) {
+            const int e = tid + 256 * k;
+            wv[k] = e < D::PACKED / 8 ? src[e] : u32x4{0u, 0u, 0u, 0u};
+        }
+#pragma unroll
+        for (int k = 0; k < NXQ; ++k) {
+            const int e = tid + 256 * k;
             const int cell = e / PARTS, part = e - cell * PARTS;
             const int r = cell / XC, col = cell - r * XC;
             const int y = p0 - 1 + r, x = q0 - 1 + col;
-            u32x4 v = {0u, 0u, 0u, 0u};
-            if (y >= 0 && y < hc && x >= 0 && x < wc)
-                v = *reinterpret_cast<const u32x4*>(in + ((size_t)y * wc + x) * CP + 8 * part);
-            *reinterpret_cast<u32x4*>(xs + cell * XS + 8 * part) = v;
+            xv[k] = u32x4{0u, 0u, 0u, 0u};
+            if (e < XR * XC * PARTS && y >= 0 && y < hc && x >= 0 && x < wc)
+                xv[k] = *reinterpret_cast<const u32x4*>(in + ((size_t)y * wc + x) * CP + 8 * part);
+        }
+        u32x4* dst = reinterpret_cast<u32x4*>(wsm);
+#pragma unroll
+        for (int k = 0; k < NWQ; ++k)
+            if (tid + 256 * k < D::PACKED / 8) dst[tid + 256 * k] = wv[k];
+#pragma unroll
+        for (int k = 0; k < NXQ; ++k) {
+            const int e = tid + 256 * k;
+            if (e < XR * XC * PARTS) {
+                const int cell = e / PARTS, part = e - cell * PARTS;
+                *reinterpret_cast<u32x4*>(xs + cell * XS + 8 * part) = xv[k];
+            }
         }
     }
     __syncthreads();

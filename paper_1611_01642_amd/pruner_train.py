@@ -121,12 +121,14 @@ def recall_at(frames, weights, bias, thresholds, pruner, keep: int, plain_boxes,
     return (hit / total if total else 1.0), boxes
 
 
-def calibrate_keep(frames, weights, bias, thresholds, pruner, target: float = 0.99, prm_kw=None):
+def calibrate_keep(frames, weights, bias, thresholds, pruner, target: float = 0.99, prm_kw=None, plain_kw=None):
     """Smallest K (binary search over [1, windows per frame]) whose recall
     over `frames` reaches `target`; returns (K, recall, plain boxes, windows
-    per frame)."""
+    per frame).  prm_kw: params of the pruned detector; plain_kw: of the
+    plain detector it is measured against (default: the same)."""
     prm_kw = dict(prm_kw or {})
-    det = Detector(frames, weights, bias, make_params(**prm_kw), cap=1024)
+    plain_kw = dict(prm_kw if plain_kw is None else plain_kw)
+    det = Detector(frames, weights, bias, make_params(**plain_kw), cap=1024)
     det.run(thresholds)
     _torch().cuda.synchronize()
     plain, _ = det.results()
