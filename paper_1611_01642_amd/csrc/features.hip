@@ -134,21 +134,27 @@ template <int FEAT, bool ALIGNED, bool CM = false>
 __device__ __forceinline__ void features_strip(const uint8_t* __restrict__ img, int w, int h, int pitch, float* __restrict__ hog,
                                uint16_t* __restrict__ hog16, uint8_t* __restrict__ lbp, float* __restrict__ cmap,
                                uint16_t* __restrict__ cmap16, int ty, int tx, int ch, float clip, float eps,
-                               FeatShared& sm, int wave) {
+                               FeatShared& sm, int wave, int group = 64) {
     constexpr bool DO_HOG = (FEAT & PD_FEAT_HOG) != 0;
     constexpr bool DO_LBP = (FEAT & PD_FEAT_LBP) != 0;
     static_assert(!CM || (DO_HOG && DO_LBP), "the cell map needs HOG and LBP");
     const int lane = threadIdx.x & 63;
     const int hc = h / PD_CELL, wc = w / PD_CELL;
     const int hb = hc - 1, wb = wc - 1;
-    const int cx0 = CM ? tx * FT_BX_CM : tx * FT_BX, cy0 = ty * ch;
-    const int cx = CM ? cx0 - 1 + lane : cx0 + lane;
+    // lane groups (non-CM): a wave of `group`-lane groups, all on the same
+    // columns, group g walking row chunk ty + g (narrow tail strips of a
+    // level keep the wave's lanes busy); group = 64 is one strip
+    const int li = CM ? lane : (lane & (group - 1));
+    const int g = CM ? 0 : lane / group;
+    const int cx0 = CM ? tx * FT_BX_CM : tx * FT_BX, cy0 = (ty + g) * ch;
+    const int cx = CM ? cx0 - 1 + lane : cx0 + li;
     const int x0 = PD_CELL * min(max(cx, 0), wc - 1);  // lanes past the edges read valid pixels
-    const int cy_last = min(cy0 + ch, hc - 1);
+    // a group past the level's last row chunk does nothing (empty row range)
+    const int cy_last = cy0 <= max(hc - 2, 0) || cy0 == 0 ? min(cy0 + ch, hc - 1) : cy0 - 1;
     const int cy_start = (CM && cy0 > 0) ? cy0 - 1 : cy0;
     const bool own = !CM || (lane >= 1 && lane <= FT_BX_CM && cx < wc);
-    const bool lbp_col = CM ? own : cx < wc && (lane < FT_BX || cx == wc - 1);
-    const bool blk_col = CM ? (own && cx < wb) : (lane < FT_BX && cx < wb);
+    const bool lbp_col = CM ? own : cx < wc && (li < group - 1 || cx == wc - 1);
+    const bool blk_col = CM ? (own && cx < wb) : (li < group - 1 && cx < wb);
     const bool left_real = cx - 1 >= 0 && cx - 1 < wc, right_real = cx + 1 >= 0 && cx + 1 < wc;
     float down9[PD_HOG_BINS];  // CM: votes from the row above, gathered per target cell
 #pragma unroll
@@ -477,7 +483,7 @@ __global__ void __launch_bounds__(256) features_table_kernel(const LevelItem* __
         const Tile tl = tiles[task];
         const LevelItem& it = items[tl.item];
         features_strip<FEAT, true>(it.pyr, it.w, it.h, it.pitch, it.hog, it.hog16, it.lbp, nullptr, nullptr, tl.ty,
-                                   tl.tx, ch, clip, eps, sm, wave);
+                                   tl.tx, ch, clip, eps, sm, wave, tl.pad);
     }
 }
 

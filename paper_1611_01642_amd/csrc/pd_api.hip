@@ -523,9 +523,25 @@ void fill_tables(const pd_frame* frames, int n_frames, int n_models, const Tunin
             if (!direct)
                 for (int ty = 0; ty < resize_tiles_y(it.h); ++ty)
                     for (int tx = 0; tx < resize_tiles_x(it.w); ++tx) t_rs[nrs++] = Tile{q, ty, tx, 0};
-            const int ftx = L.prune ? feat_tiles_x_cm(it.wc) : feat_tiles_x(it.wc);
-            for (int ty = 0; ty < feat_tiles_y(it.hc, tu.feat_rows); ++ty)
-                for (int tx = 0; tx < ftx; ++tx) t_ft[nft++] = Tile{q, ty, tx, 0};
+            const int fty = feat_tiles_y(it.hc, tu.feat_rows);
+            if (L.prune) {
+                for (int ty = 0; ty < fty; ++ty)
+                    for (int tx = 0; tx < feat_tiles_x_cm(it.wc); ++tx) t_ft[nft++] = Tile{q, ty, tx, 0};
+            } else {
+                // full 64-lane strips of 63 block columns; the remaining columns
+                // in narrower lane groups (pad = group width), each wave taking
+                // 64 / width row chunks
+                const int wb = it.wc - 1;
+                const int full = wb > 0 ? wb / FT_BX : 0;
+                const int tail = wb > 0 ? wb - full * FT_BX : 0;
+                for (int ty = 0; ty < fty; ++ty)
+                    for (int tx = 0; tx < full; ++tx) t_ft[nft++] = Tile{q, ty, tx, 64};
+                if (tail > 0 || full == 0) {
+                    int width = 2;
+                    while (width - 1 < std::max(tail, 1)) width *= 2;
+                    for (int ty = 0; ty < fty; ty += 64 / width) t_ft[nft++] = Tile{q, ty, full, width};
+                }
+            }
             if (L.prune) {
                 it.cmap16 = reinterpret_cast<uint16_t*>(data + L.cm_off[q]);
                 it.act1 = reinterpret_cast<uint16_t*>(data + L.a1_off[q]);

@@ -3,7 +3,10 @@
 // Q8 fixed point, rounded half up.  All arithmetic is integer, so results are
 // exact.  One workgroup writes a 256 x 16 pixel tile of one level; the Q8
 // coordinates of the tile's columns and rows are computed once per tile in
-// LDS (they need a 64-bit division).
+// LDS (they need a 64-bit division), and the source rectangle the tile reads
+// is staged in LDS with coalesced word loads, so the four taps of every
+// output pixel are LDS reads (tiles whose rectangle does not fit read the
+// taps from global memory instead).
 #include "pd_internal.h"
 
 namespace pd {
@@ -17,16 +20,58 @@ __device__ inline uint32_t q8_coord(int x, int n0, int nk) {
     return (uint32_t)s;  // index = s >> 8, fraction = s & 255
 }
 
+constexpr int RS_LDS = 36 * 1024;  // staged source bytes per workgroup (scale factors up to ~2.9)
+constexpr int RS_BATCH = 8;        // loads in flight per thread while staging
+
+__device__ __forceinline__ uint32_t blend(int p00, int p01, int p10, int p11, int fx, int fy) {
+    const int acc = (256 - fx) * (256 - fy) * p00 + fx * (256 - fy) * p01 + (256 - fx) * fy * p10 + fx * fy * p11 +
+                    (1 << 15);
+    return (uint32_t)(acc >> 16);
+}
+
 __device__ void resize_tile(const uint8_t* __restrict__ src, int sw, int sh, int spitch,
                             uint8_t* __restrict__ dst, int w, int h, int pitch, int ty, int tx) {
     __shared__ uint32_t xs[RS_TX];
     __shared__ uint32_t ys[RS_TY];
+    __shared__ __attribute__((aligned(16))) uint8_t stage[RS_LDS];
     const int t = threadIdx.x;
     const int x_base = tx * RS_TX;
     const int y_base = ty * RS_TY;
     if (x_base + t < w) xs[t] = q8_coord(x_base + t, sw, w);
     if (t < RS_TY && y_base + t < h) ys[t] = q8_coord(y_base + t, sh, h);
     __syncthreads();
+
+    // source rectangle of the tile: rows sy0..sy1, columns sx0..sx1
+    const int xe = min(x_base + RS_TX, w) - 1 - x_base, ye = min(y_base + RS_TY, h) - 1 - y_base;
+    const int sx0 = (int)(xs[0] >> 8), sx1 = min((int)(xs[xe] >> 8) + 1, sw - 1);
+    const int sy0 = (int)(ys[0] >> 8), sy1 = min((int)(ys[ye] >> 8) + 1, sh - 1);
+    const int nrow = sy1 - sy0 + 1;
+    const int span_w = (sx1 - sx0 + 7) / 4;  // aligned words per row, whatever the row's alignment
+    const bool staged = nrow * span_w * 4 <= RS_LDS;  // uniform over the workgroup
+    if (staged) {
+        // coalesced aligned words; a word is loaded only if it holds a byte of
+        // the rectangle (so it never leaves the pages of the image)
+        const int n = nrow * span_w;
+        for (int base = 0; base < n; base += 256 * RS_BATCH) {
+            uint32_t v[RS_BATCH];
+#pragma unroll
+            for (int k = 0; k < RS_BATCH; ++k) {
+                const int e = base + t + 256 * k;
+                const int r = e / span_w, wd = e - r * span_w;
+                const uintptr_t a0 = reinterpret_cast<uintptr_t>(src + (size_t)(sy0 + r) * spitch + sx0);
+                const uintptr_t al = a0 & ~(uintptr_t)3;
+                v[k] = 0u;
+                if (e < n && 4 * (uintptr_t)wd <= (a0 - al) + (uintptr_t)(sx1 - sx0))
+                    v[k] = *reinterpret_cast<const uint32_t*>(al + 4 * wd);
+            }
+#pragma unroll
+            for (int k = 0; k < RS_BATCH; ++k) {
+                const int e = base + t + 256 * k;
+                if (e < n) *reinterpret_cast<uint32_t*>(stage + 4 * e) = v[k];
+            }
+        }
+        __syncthreads();
+    }
 
     const int lane = t & 63;
     const int wave = t >> 6;
@@ -39,24 +84,35 @@ __device__ void resize_tile(const uint8_t* __restrict__ src, int sw, int sh, int
         const int ya = (int)(sy >> 8);
         const int fy = (int)(sy & 255);
         const int yb = min(ya + 1, sh - 1);
-        const uint8_t* ra = src + (size_t)ya * spitch;
-        const uint8_t* rb = src + (size_t)yb * spitch;
         uint32_t packed = 0;
+        if (staged) {
+            const int oa = (int)(reinterpret_cast<uintptr_t>(src + (size_t)ya * spitch + sx0) & 3);
+            const int ob = (int)(reinterpret_cast<uintptr_t>(src + (size_t)yb * spitch + sx0) & 3);
+            const uint8_t* ra = stage + (ya - sy0) * span_w * 4 + oa - sx0;
+            const uint8_t* rb = stage + (yb - sy0) * span_w * 4 + ob - sx0;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int x = x0 + q;
-            uint32_t v = 0;
-            if (x < w) {
-                const uint32_t sx = xs[4 * lane + q];
-                const int xa = (int)(sx >> 8);
-                const int fx = (int)(sx & 255);
-                const int xb = min(xa + 1, sw - 1);
-                const int p00 = ra[xa], p01 = ra[xb], p10 = rb[xa], p11 = rb[xb];
-                const int acc = (256 - fx) * (256 - fy) * p00 + fx * (256 - fy) * p01 +
-                                (256 - fx) * fy * p10 + fx * fy * p11 + (1 << 15);
-                v = (uint32_t)(acc >> 16);
+            for (int q = 0; q < 4; ++q) {
+                const int x = x0 + q;
+                if (x < w) {
+                    const uint32_t sx = xs[4 * lane + q];
+                    const int xa = (int)(sx >> 8), fx = (int)(sx & 255);
+                    const int xb = min(xa + 1, sw - 1);
+                    packed |= blend(ra[xa], ra[xb], rb[xa], rb[xb], fx, fy) << (8 * q);
+                }
             }
-            packed |= v << (8 * q);
+        } else {
+            const uint8_t* ra = src + (size_t)ya * spitch;
+            const uint8_t* rb = src + (size_t)yb * spitch;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int x = x0 + q;
+                if (x < w) {
+                    const uint32_t sx = xs[4 * lane + q];
+                    const int xa = (int)(sx >> 8), fx = (int)(sx & 255);
+                    const int xb = min(xa + 1, sw - 1);
+                    packed |= blend(ra[xa], ra[xb], rb[xa], rb[xb], fx, fy) << (8 * q);
+                }
+            }
         }
         // pitch is a multiple of 16 >= w, so the 4-byte store stays in the row
         *reinterpret_cast<uint32_t*>(dst + (size_t)y * pitch + x0) = packed;
