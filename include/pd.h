@@ -86,8 +86,8 @@ typedef struct pd_params {
     /* Tile and launch shapes of pd_detect (0 = default).  They change the
        work partition only, never a result; pd_autotune picks them.        */
     int32_t tune_feat_rows;  /* block rows per feature strip: 4..32 (8)    */
-    int32_t tune_score_rows; /* PD_PREC_F32 window rows per scoring wave:
-                                8 or 16 (8)                                */
+    int32_t tune_score_rows; /* PD_PREC_F32 window rows per scoring lane:
+                                4, 8 or 16 (8)                             */
     int32_t tune_grid;       /* 0: one workgroup per tile group; n > 0:
                                 feature and scoring grids of at most n
                                 workgroups looping over the tiles          */
@@ -329,7 +329,7 @@ int pd_graph_destroy(pd_graph* graph);
  * pd_autotune -- times pd_detect on these arguments (one untimed call, then
  * `iters` calls between HIP events, per candidate) over the tuning fields of
  * pd_params, one field at a time: feature strip rows {4, 6, 8, 12, 16},
- * FP32 scoring rows {8, 16}, grid cap {0, 256, 512, 1024, 2048}; starting
+ * FP32 scoring rows {4, 8, 16}, grid cap {0, 256, 512, 1024, 2048}; starting
  * from params' own values.  Writes params with the fastest fields to *best
  * (host) and its time per call in ms to *best_ms (host, may be NULL).
  * Blocks until the timing runs finished; leaves boxes and counts of the

@@ -51,8 +51,8 @@ bool check_params(const pd_params* p) {
     if (!(p->margin >= 0.0f) || !std::isfinite(p->margin)) return fail(PD_E_ARG, "margin must be >= 0"), false;
     if (p->tune_feat_rows != 0 && (p->tune_feat_rows < FT_MIN_ROWS || p->tune_feat_rows > FT_MAX_ROWS))
         return fail(PD_E_ARG, "tune_feat_rows must be 0 or in [%d, %d]", FT_MIN_ROWS, FT_MAX_ROWS), false;
-    if (p->tune_score_rows != 0 && p->tune_score_rows != 8 && p->tune_score_rows != 16)
-        return fail(PD_E_ARG, "tune_score_rows must be 0, 8 or 16"), false;
+    if (p->tune_score_rows != 0 && p->tune_score_rows != 4 && p->tune_score_rows != 8 && p->tune_score_rows != 16)
+        return fail(PD_E_ARG, "tune_score_rows must be 0, 4, 8 or 16"), false;
     if (p->tune_grid < 0 || p->tune_grid > (1 << 20))
         return fail(PD_E_ARG, "tune_grid must be in [0, 2^20]"), false;
     if (p->prune_keep < 0) return fail(PD_E_ARG, "prune_keep must be >= 0"), false;
@@ -346,7 +346,7 @@ bool plan_detect(const pd_frame* frames, int n_frames, const pd_params* p, int n
             // table capacity for the finest tile shapes the tuning fields
             // allow, so the workspace size does not depend on them
             L.n_ft += (L.prune ? feat_tiles_x_cm(it.wc) : feat_tiles_x(it.wc)) * feat_tiles_y(it.hc, FT_MIN_ROWS);
-            L.n_sc += !L.bf16 ? score_tiles_x(it.nx) * score_tiles_y(it.ny, SC_R) * n_models
+            L.n_sc += !L.bf16 ? score_tiles_x(it.nx) * score_tiles_y(it.ny, 4) * n_models
                       : n_models == 1 ? ceil_div(it.nx, RG_TILE_C)
                                       : ceil_div(it.nx, MF_TILE_C) * ceil_div(it.ny, MF_TILE_R);
             L.n_cp += ceil_div(it.nx * it.ny, CP_N);
@@ -556,9 +556,18 @@ void fill_tables(const pd_frame* frames, int n_frames, int n_models, const Tunin
                 for (int ty = 0; ty < ceil_div(it.ny, MF_TILE_R); ++ty)
                     for (int tx = 0; tx < ceil_div(it.nx, MF_TILE_C); ++tx) t_sc[nsc++] = Tile{q, ty, tx, 0};
             } else {
-                for (int m = 0; m < n_models; ++m)
-                    for (int ty = 0; ty < score_tiles_y(it.ny, tu.score_rows); ++ty)
-                        for (int tx = 0; tx < score_tiles_x(it.nx); ++tx) t_sc[nsc++] = Tile{q, ty, tx, m};
+                // full 64-column tiles; the last columns in 32- or 16-lane
+                // groups, each on its own row chunk
+                const int nty = score_tiles_y(it.ny, tu.score_rows);
+                const int full = it.nx / SC_W, tail = it.nx - full * SC_W;
+                const int width = tail > 32 ? 64 : (tail > 16 ? 32 : 16);
+                for (int m = 0; m < n_models; ++m) {
+                    for (int ty = 0; ty < nty; ++ty)
+                        for (int tx = 0; tx < full; ++tx) t_sc[nsc++] = Tile{q, ty, tx, score_pad(m, 64)};
+                    if (tail > 0)
+                        for (int ty = 0; ty < nty; ty += SC_W / width)
+                            t_sc[nsc++] = Tile{q, ty, full, score_pad(m, width)};
+                }
             }
             for (int c = 0; c < ceil_div(it.nx * it.ny, CP_N); ++c) t_cp[ncp++] = Tile{q, 0, c, 0};
         }
@@ -1210,11 +1219,11 @@ int pd_autotune(const pd_frame* frames, int n_frames, const float* weights, cons
     if (!rc) rc = time_of(cur, &cur_ms);
     // one knob at a time (the stages they shape are independent)
     const int feat_rows[] = {4, 6, 8, 12, 16};
-    const int score_rows[] = {8, 16};
+    const int score_rows[] = {4, 8, 16};
     const int grids[] = {0, 256, 512, 1024, 2048};
     for (int knob = 0; knob < 3 && !rc; ++knob) {
         const int* vals = knob == 0 ? feat_rows : knob == 1 ? score_rows : grids;
-        const int n = knob == 0 ? 5 : knob == 1 ? 2 : 5;
+        const int n = knob == 0 ? 5 : knob == 1 ? 3 : 5;
         if (knob == 1 && params->precision != PD_PREC_F32) continue;  // FP32 scoring only
         for (int v = 0; v < n && !rc; ++v) {
             pd_params c = cur;

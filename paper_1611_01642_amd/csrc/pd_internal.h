@@ -46,11 +46,19 @@ struct NetItem {
 };
 
 // One workgroup's share of a batched launch: which item and which tile.
+// FP32 scoring tiles keep the model in pad's low 16 bits and the lane-group
+// width (64, 32 or 16 window columns) in its high bits.
 struct Tile {
     int32_t item;
     int32_t ty, tx;
     int32_t pad;
 };
+__host__ __device__ inline int tile_model(const Tile& t) { return t.pad & 0xffff; }
+__host__ __device__ inline int tile_width(const Tile& t) {
+    const int w = t.pad >> 16;
+    return w ? w : 64;
+}
+__host__ __device__ inline int32_t score_pad(int model, int width) { return model | ((width == 64 ? 0 : width) << 16); }
 
 // Greedy-NMS geometry of one frame: sizes of its levels, level 0 first.
 struct NmsGeom {
@@ -104,7 +112,7 @@ __host__ __device__ inline int score_tiles_y(int ny, int rows = SC_R) { return c
 // Tile shapes and launch shapes chosen at run time (pd_params tuning fields).
 struct Tuning {
     int feat_rows = FT_CH;   // block rows per feature strip (2..32)
-    int score_rows = SC_R;   // FP32 scoring: window rows per wave (8 or 16)
+    int score_rows = SC_R;   // FP32 scoring: window rows per lane (4, 8 or 16)
     int grid = 0;            // 0: one workgroup per tile group; > 0: at most this many, looping
 };
 

@@ -672,12 +672,15 @@ __global__ void __launch_bounds__(256) tile_filter_kernel(const LevelItem* __res
     const Tile tl = tiles[t];
     const LevelItem& it = items[tl.item];
     const float thr = kth[it.frame];
+    // a tile of width w < cols (FP32 lane groups) covers cols / w row chunks
+    const int w = cols == SC_W ? tile_width(tl) : cols;
+    const int r0 = tl.ty * rows, nr = rows * (cols / w);
     bool any = false;
-    for (int c = lane; c < cols; c += 64) {
+    for (int c = lane; c < w; c += 64) {
         const int j = tl.tx * cols + c;
         if (j >= it.nx) break;
-        for (int r = 0; r < rows; ++r) {
-            const int i = tl.ty * rows + r;
+        for (int r = 0; r < nr; ++r) {
+            const int i = r0 + r;
             if (i >= it.ny) break;
             any = any || it.logit[(size_t)(i + PRUNER_WIN_DI) * it.wc + j + PRUNER_WIN_DJ] >= thr;
         }

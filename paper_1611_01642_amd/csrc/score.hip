@@ -15,27 +15,36 @@
 namespace pd {
 namespace {
 
-// Patch geometry for R window rows per wave.
-template <int R>
+// Patch geometry for R window rows per lane group of L lanes (64 / L groups
+// per wave, each on its own row chunk, all on the same L window columns).
+template <int R, int L = SC_W>
 struct Patch {
-    static constexpr int HOG_PR = R + PD_WIN_BLOCKS_Y - 1;  // patch rows
-    static constexpr int HOG_PC = SC_W + PD_WIN_BLOCKS_X - 1;  // patch columns
+    static constexpr int G = SC_W / L;
+    static constexpr int HOG_PR = R + PD_WIN_BLOCKS_Y - 1;  // patch rows per group
+    static constexpr int HOG_PC = L + PD_WIN_BLOCKS_X - 1;  // patch columns
     static constexpr int LBP_PR = R + PD_WIN_CELLS_Y - 1;
-    static constexpr int LBP_PC = SC_W + PD_WIN_CELLS_X - 1;
-    static constexpr int HOG_PQ = (HOG_PR * HOG_PC + 63) / 64;  // patch values per lane
-    static constexpr int LBP_PQ = (LBP_PR * LBP_PC + 63) / 64;
-    static constexpr int SIZE = (HOG_PR * HOG_PC > LBP_PR * LBP_PC ? HOG_PR * HOG_PC : LBP_PR * LBP_PC);
+    static constexpr int LBP_PC = L + PD_WIN_CELLS_X - 1;
+    static constexpr int HOG_N = G * HOG_PR * HOG_PC, LBP_N = G * LBP_PR * LBP_PC;
+    static constexpr int HOG_PQ = (HOG_N + 63) / 64;  // patch values per lane
+    static constexpr int LBP_PQ = (LBP_N + 63) / 64;
+    static constexpr int SIZE = HOG_N > LBP_N ? HOG_N : LBP_N;
 };
+template <int R>
+constexpr int patch_floats() {
+    constexpr int a = Patch<R, 64>::SIZE, b = Patch<R, 32>::SIZE, c = Patch<R, 16>::SIZE;
+    return a > b ? (a > c ? a : c) : (b > c ? b : c);
+}
 
-template <int FEAT, int R>
+template <int FEAT, int R, int L = SC_W>
 __device__ __forceinline__ void score_tile(const float* __restrict__ hog, const uint8_t* __restrict__ lbp, int wc,
                                            int hc, const float* __restrict__ wt, float bias, float* __restrict__ out,
                                            int ty, int tx, int lane, float* __restrict__ patch) {
-    constexpr int HOG_PR = Patch<R>::HOG_PR, HOG_PC = Patch<R>::HOG_PC, HOG_PQ = Patch<R>::HOG_PQ;
-    constexpr int LBP_PR = Patch<R>::LBP_PR, LBP_PC = Patch<R>::LBP_PC, LBP_PQ = Patch<R>::LBP_PQ;
+    using PG = Patch<R, L>;
+    constexpr int HOG_PR = PG::HOG_PR, HOG_PC = PG::HOG_PC, HOG_PQ = PG::HOG_PQ, HOG_N = PG::HOG_N;
+    constexpr int LBP_PR = PG::LBP_PR, LBP_PC = PG::LBP_PC, LBP_PQ = PG::LBP_PQ, LBP_N = PG::LBP_N;
     const int hb = hc - 1, wb = wc - 1;
     const int ny = hc - PD_WIN_CELLS_Y + 1, nx = wc - PD_WIN_CELLS_X + 1;
-    const int i0 = ty * R;
+    const int g = lane / L, li = lane % L;  // group and column within it
     const int j0 = tx * SC_W;
     float acc[R];
 #pragma unroll
@@ -46,9 +55,10 @@ __device__ __forceinline__ void score_tile(const float* __restrict__ hog, const 
         int off[HOG_PQ];  // clamped plane offsets of this lane's patch values
 #pragma unroll
         for (int q = 0; q < HOG_PQ; ++q) {
-            const int e = min(lane + 64 * q, HOG_PR * HOG_PC - 1);
-            const int row = e / HOG_PC, col = e - (e / HOG_PC) * HOG_PC;
-            off[q] = min(i0 + row, hb - 1) * wb + min(j0 + col, wb - 1);
+            const int e = min(lane + 64 * q, HOG_N - 1);
+            const int gq = e / (HOG_PR * HOG_PC), rem = e - gq * (HOG_PR * HOG_PC);
+            const int row = rem / HOG_PC, col = rem - (rem / HOG_PC) * HOG_PC;
+            off[q] = min((ty + gq) * R + row, hb - 1) * wb + min(j0 + col, wb - 1);
         }
         float pre[HOG_PQ];
 #pragma unroll
@@ -56,7 +66,7 @@ __device__ __forceinline__ void score_tile(const float* __restrict__ hog, const 
         for (int c = 0; c < PD_HOG_BLOCK; ++c) {
 #pragma unroll
             for (int q = 0; q < HOG_PQ; ++q)
-                if (lane + 64 * q < HOG_PR * HOG_PC) patch[lane + 64 * q] = pre[q];
+                if (lane + 64 * q < HOG_N) patch[lane + 64 * q] = pre[q];
             if (c + 1 < PD_HOG_BLOCK) {
                 const float* nxt = hog + (size_t)(c + 1) * plane;
 #pragma unroll
@@ -67,7 +77,7 @@ __device__ __forceinline__ void score_tile(const float* __restrict__ hog, const 
                 float wa[PD_WIN_BLOCKS_Y];
 #pragma unroll
                 for (int a = 0; a < PD_WIN_BLOCKS_Y; ++a) wa[a] = wt[(a * PD_WIN_BLOCKS_X + b) * PD_HOG_BLOCK + c];
-                const float* pr = patch + lane + b;
+                const float* pr = patch + g * (HOG_PR * HOG_PC) + li + b;
 #pragma unroll
                 for (int y = 0; y < HOG_PR; ++y) {
                     const float v = pr[y * HOG_PC];
@@ -87,9 +97,10 @@ __device__ __forceinline__ void score_tile(const float* __restrict__ hog, const 
         int off[LBP_PQ];
 #pragma unroll
         for (int q = 0; q < LBP_PQ; ++q) {
-            const int e = min(lane + 64 * q, LBP_PR * LBP_PC - 1);
-            const int row = e / LBP_PC, col = e - (e / LBP_PC) * LBP_PC;
-            off[q] = min(i0 + row, hc - 1) * wc + min(j0 + col, wc - 1);
+            const int e = min(lane + 64 * q, LBP_N - 1);
+            const int gq = e / (LBP_PR * LBP_PC), rem = e - gq * (LBP_PR * LBP_PC);
+            const int row = rem / LBP_PC, col = rem - (rem / LBP_PC) * LBP_PC;
+            off[q] = min((ty + gq) * R + row, hc - 1) * wc + min(j0 + col, wc - 1);
         }
         uint32_t pre[LBP_PQ];
 #pragma unroll
@@ -97,7 +108,7 @@ __device__ __forceinline__ void score_tile(const float* __restrict__ hog, const 
         for (int c = 0; c < PD_LBP_BINS; ++c) {
 #pragma unroll
             for (int q = 0; q < LBP_PQ; ++q)
-                if (lane + 64 * q < LBP_PR * LBP_PC) patch[lane + 64 * q] = (float)pre[q];
+                if (lane + 64 * q < LBP_N) patch[lane + 64 * q] = (float)pre[q];
             if (c + 1 < PD_LBP_BINS) {
                 const uint8_t* nxt = lbp + (size_t)(c + 1) * plane;
 #pragma unroll
@@ -108,7 +119,7 @@ __device__ __forceinline__ void score_tile(const float* __restrict__ hog, const 
                 float wa[PD_WIN_CELLS_Y];
 #pragma unroll
                 for (int a = 0; a < PD_WIN_CELLS_Y; ++a) wa[a] = wl[(a * PD_WIN_CELLS_X + b) * PD_LBP_BINS + c];
-                const float* pr = patch + lane + b;
+                const float* pr = patch + g * (LBP_PR * LBP_PC) + li + b;
 #pragma unroll
                 for (int y = 0; y < LBP_PR; ++y) {
                     const float v = pr[y * LBP_PC];
@@ -122,7 +133,8 @@ __device__ __forceinline__ void score_tile(const float* __restrict__ hog, const 
             __builtin_amdgcn_wave_barrier();
         }
     }
-    const int j = j0 + lane;
+    const int i0 = (ty + g) * R;
+    const int j = j0 + li;
     if (j < nx) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -147,7 +159,7 @@ __global__ void __launch_bounds__(256) score_single_kernel(LevelItem it, const f
                            patches[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)]);
 }
 
-// Tile.pad carries the model index; tiles of R window rows.  Waves are
+// Tiles of R window rows (pad: model and lane-group width).  Waves are
 // independent; with LOOP a capped grid strides over the table (a separate
 // instantiation: the loop costs registers the one-tile form does not need).
 template <int FEAT, int R, bool LOOP>
@@ -156,15 +168,22 @@ __global__ void __launch_bounds__(256) score_table_kernel(const LevelItem* __res
                                                           const float* __restrict__ wt,
                                                           const float* __restrict__ bias,
                                                           const int* __restrict__ n_dev) {
-    __shared__ float patches[SC_WAVES][Patch<R>::SIZE];
+    __shared__ float patches[SC_WAVES][patch_floats<R>()];
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (n_dev) n_tiles = min(n_tiles, *n_dev);
     auto one = [&](int wave) __attribute__((always_inline)) {
         const Tile tl = tiles[wave];
         const LevelItem& it = items[tl.item];
-        const int m = tl.pad;
-        score_tile<FEAT, R>(it.hog, it.lbp, it.wc, it.hc, wt + (size_t)m * PD_FEATURE_DIM, bias[m],
-                            it.scores + (size_t)m * it.ny * it.nx, tl.ty, tl.tx, threadIdx.x & 63, patches[wv]);
+        const int m = tile_model(tl), width = tile_width(tl);
+        const float* w = wt + (size_t)m * PD_FEATURE_DIM;
+        float* o = it.scores + (size_t)m * it.ny * it.nx;
+        const int lane = threadIdx.x & 63;
+        if (width == 64)
+            score_tile<FEAT, R, 64>(it.hog, it.lbp, it.wc, it.hc, w, bias[m], o, tl.ty, tl.tx, lane, patches[wv]);
+        else if (width == 32)
+            score_tile<FEAT, R, 32>(it.hog, it.lbp, it.wc, it.hc, w, bias[m], o, tl.ty, tl.tx, lane, patches[wv]);
+        else
+            score_tile<FEAT, R, 16>(it.hog, it.lbp, it.wc, it.hc, w, bias[m], o, tl.ty, tl.tx, lane, patches[wv]);
     };
     if constexpr (LOOP) {
         for (int wave = blockIdx.x * SC_WAVES + wv; wave < n_tiles; wave += gridDim.x * SC_WAVES) one(wave);
@@ -181,19 +200,23 @@ hipError_t score_single(const LevelItem& it, const float* w, const float* b, int
     return hipGetLastError();
 }
 
+template <int FEAT, int R>
+void launch_rows(bool loop, int grid, const LevelItem* items, const Tile* tiles, int n, const float* w,
+                 const float* b, const int* nd, hipStream_t s) {
+    if (loop) score_table_kernel<FEAT, R, true><<<grid, 256, 0, s>>>(items, tiles, n, w, b, nd);
+    else score_table_kernel<FEAT, R, false><<<grid, 256, 0, s>>>(items, tiles, n, w, b, nd);
+}
+
 template <int FEAT>
 hipError_t score_table(const LevelItem* items, const Tile* tiles, int n, const float* w, const float* b,
                        const Tuning& tu, hipStream_t s, const int* nd) {
-    const int rows = tu.score_rows == 16 ? 16 : SC_R;
+    const int rows = tu.score_rows;
     const int blocks = ceil_div(n, SC_WAVES);
-    if (tu.grid > 0 && tu.grid < blocks) {
-        if (rows == 16) score_table_kernel<FEAT, 16, true><<<tu.grid, 256, 0, s>>>(items, tiles, n, w, b, nd);
-        else score_table_kernel<FEAT, SC_R, true><<<tu.grid, 256, 0, s>>>(items, tiles, n, w, b, nd);
-    } else if (rows == 16) {
-        score_table_kernel<FEAT, 16, false><<<blocks, 256, 0, s>>>(items, tiles, n, w, b, nd);
-    } else {
-        score_table_kernel<FEAT, SC_R, false><<<blocks, 256, 0, s>>>(items, tiles, n, w, b, nd);
-    }
+    const bool loop = tu.grid > 0 && tu.grid < blocks;
+    const int grid = loop ? tu.grid : blocks;
+    if (rows == 16) launch_rows<FEAT, 16>(loop, grid, items, tiles, n, w, b, nd, s);
+    else if (rows == 4) launch_rows<FEAT, 4>(loop, grid, items, tiles, n, w, b, nd, s);
+    else launch_rows<FEAT, SC_R>(loop, grid, items, tiles, n, w, b, nd, s);
     return hipGetLastError();
 }
 

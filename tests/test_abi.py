@@ -104,7 +104,8 @@ def test_tuning_field_checks_and_graph_handles():
     L = pd.lib()
     fake = ctypes.c_void_p(0x1000)
     nil = ctypes.c_void_p(0)
-    for kw in (dict(tune_feat_rows=3), dict(tune_feat_rows=33), dict(tune_score_rows=12), dict(tune_grid=-1)):
+    for kw in (dict(tune_feat_rows=3), dict(tune_feat_rows=33), dict(tune_score_rows=12), dict(tune_score_rows=2),
+               dict(tune_grid=-1)):
         bad = pd.params(**kw)
         assert L.pd_features(fake, 64, 64, 64, ctypes.byref(bad), fake, nil, fake, nil) == pd.E_ARG, kw
         assert "tune" in L.pd_last_error().decode()

@@ -55,7 +55,8 @@ def test_tuning_fields_keep_results(prec, m):
     shapes = [dict(tune_feat_rows=4), dict(tune_feat_rows=6), dict(tune_feat_rows=13), dict(tune_feat_rows=32),
               dict(tune_grid=7), dict(tune_grid=300), dict(tune_feat_rows=12, tune_grid=1)]
     if prec == pd.PREC_F32:
-        shapes += [dict(tune_score_rows=16), dict(tune_score_rows=16, tune_grid=5)]
+        shapes += [dict(tune_score_rows=16), dict(tune_score_rows=16, tune_grid=5), dict(tune_score_rows=4),
+                   dict(tune_score_rows=4, tune_grid=3)]
     for kw in shapes:
         print(f"\n[tuning] prec {prec} models {m} {kw}", flush=True)
         _same(ref, _run(frames, wts, bias, pd.params(precision=prec, **kw), thr))
@@ -105,7 +106,7 @@ def test_autotune_gives_valid_fields_and_same_results():
     tuning, ms = det.autotune(thr, iters=2)
     print(f"\n[autotune] {tuning} {ms:.3f} ms", flush=True)
     assert tuning["tune_feat_rows"] in (4, 6, 8, 12, 16)
-    assert tuning["tune_score_rows"] in (8, 16)
+    assert tuning["tune_score_rows"] in (4, 8, 16)
     assert tuning["tune_grid"] in (0, 256, 512, 1024, 2048)
     assert 0.0 < ms < 1000.0
     det.run(thr)
