@@ -10,10 +10,19 @@
 // in FP64 with the FP32 weights.  A window whose FP64 score (max over models)
 // exceeds the threshold is appended to the frame's candidate list.
 //
-// One workgroup per near window: lanes 0..127 own the window's 16x8 cells
-// (pixel work and per-cell partials in LDS, no atomics); then lanes 0..104
-// assemble the 15x7 blocks and lanes 128..255 take the 16x8 LBP cells; the
-// per-lane partial dot products are reduced in a fixed order.
+// One workgroup per near window:
+//  * pixels: the window's 130 x 66 pixels (with halo) in LDS;
+//  * votes: lane pair (l, l + 32) of each wave owns one of the 128 cells, the
+//    first lane its top four pixel rows, the second its bottom four; a lane
+//    sums its 32 pixels' votes in registers (the linear orientation vote as a
+//    hat over the 9 bins, towards the 2 x 3 target cells its rows can reach),
+//    the two halves meet through one cross-lane exchange and the cell's 81
+//    direction partials are stored once (no read-modify-write in LDS);
+//  * blocks: lanes 0..104 sum the partials aimed at each block slot
+//    (exactly Algorithm 5's votes), L2-Hys, and store the window's 3780 HOG
+//    values (over the partials, after a barrier);
+//  * dot products: all 256 lanes stride over the 11332 features (coalesced
+//    FP32 weights, LBP counts from the planes), then a fixed-order reduction.
 #include "pd_internal.h"
 
 namespace pd {
@@ -25,12 +34,15 @@ constexpr int RS_CELLS = PD_WIN_CELLS_Y * PD_WIN_CELLS_X;  // 128
 
 struct RescoreShared {
     uint8_t px[RS_PY][RS_PX + 2];
-    double A[RS_CELLS][81];            // per cell: 3x3 target cells x 9 bins
-    double part[256][8];               // per lane, per model
-    int take;
+    union {
+        double A[RS_CELLS][81];      // per cell: 3x3 target cells x 9 bins
+        double hog[PD_HOG_DIM];      // the window's normalised HOG values
+    } u;
+    double part[4][8];               // per wave, per model
 };
 
-__device__ double spatial_w(int p, int d) {  // pixel offset p in its cell towards cell d in {-1,0,1}
+// Bilinear weight of pixel offset p in [0, 8) of a cell towards cell d in {-1, 0, 1}.
+__device__ __forceinline__ double spatial_w(int p, int d) {
     const double w = 1.0 - fabs((double)p + 0.5 - (8.0 * d + 4.0)) / 8.0;
     return w > 0.0 ? w : 0.0;
 }
@@ -46,6 +58,7 @@ __global__ void __launch_bounds__(256) rescore64_kernel(const LevelItem* __restr
                                                         int4* __restrict__ cand_key, double* __restrict__ cand_s64) {
     __shared__ RescoreShared sm;
     const int t = threadIdx.x;
+    const int wave = t >> 6, lane = t & 63;
     const int total = near_count[n_frames];  // dense list of every frame's near windows
     for (int q = blockIdx.x; q < total; q += gridDim.x) {
         const int4 key = near_key[q];
@@ -62,11 +75,22 @@ __global__ void __launch_bounds__(256) rescore64_kernel(const LevelItem* __restr
         }
         __syncthreads();
 
-        if (t < RS_CELLS) {
-            double* A = sm.A[t];
-            for (int k = 0; k < 81; ++k) A[k] = 0.0;
-            const int cy = t / PD_WIN_CELLS_X, cx = t - (t / PD_WIN_CELLS_X) * PD_WIN_CELLS_X;
-            for (int py = 0; py < PD_CELL; ++py) {
+        {
+            const int half = lane >> 5;                       // 0: pixel rows 0..3, 1: rows 4..7
+            const int cell = wave * 32 + (lane & 31);
+            const int cy = cell / PD_WIN_CELLS_X, cx = cell - (cell / PD_WIN_CELLS_X) * PD_WIN_CELLS_X;
+            // acc[dy index][dx + 1][bin]; dy index 0/1 = dy -1/0 (top) or 0/+1 (bottom)
+            double acc[2][3][PD_HOG_BINS];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 3; ++b)
+#pragma unroll
+                    for (int k = 0; k < PD_HOG_BINS; ++k) acc[a][b][k] = 0.0;
+            for (int pr = 0; pr < 4; ++pr) {
+                const int py = 4 * half + pr;
+                const double wy0 = spatial_w(py, half - 1), wy1 = spatial_w(py, half);
+#pragma unroll
                 for (int px = 0; px < PD_CELL; ++px) {
                     const int r = PD_CELL * cy + py + 1, c = PD_CELL * cx + px + 1;
                     const int dx = (int)sm.px[r][c - 1] - (int)sm.px[r][c + 1];   // Algorithm 4
@@ -75,83 +99,100 @@ __global__ void __launch_bounds__(256) rescore64_kernel(const LevelItem* __restr
                     double ang = atan2((double)dy, (double)dx) * 57.295779513082320876798154814105;
                     if (ang < 0.0) ang += 180.0;
                     if (ang >= 180.0) ang -= 180.0;
-                    const double tb = ang / 20.0 - 0.5;
-                    const double fl = floor(tb);
-                    int b0 = (int)fl % PD_HOG_BINS;
-                    if (b0 < 0) b0 += PD_HOG_BINS;
-                    const int b1 = (b0 + 1) % PD_HOG_BINS;
-                    const double w1 = tb - fl, w0 = 1.0 - w1;
-                    for (int ddy = -1; ddy <= 1; ++ddy) {
-                        const double wy = spatial_w(py, ddy);
-                        if (wy == 0.0) continue;
-                        for (int ddx = -1; ddx <= 1; ++ddx) {
-                            const double wx = spatial_w(px, ddx);
-                            if (wx == 0.0) continue;
-                            const int dir = (ddy + 1) * 3 + (ddx + 1);
-                            A[dir * PD_HOG_BINS + b0] += mag * wy * wx * w0;
-                            A[dir * PD_HOG_BINS + b1] += mag * wy * wx * w1;
-                        }
+                    const double tb = ang / 20.0 - 0.5;            // [-0.5, 8.5)
+                    double h[PD_HOG_BINS];                         // linear vote per bin (wrap-around)
+                    h[0] = fmax(0.0, 1.0 - fmin(fabs(tb), fabs(tb - 9.0)));
+#pragma unroll
+                    for (int k = 1; k < PD_HOG_BINS - 1; ++k) h[k] = fmax(0.0, 1.0 - fabs(tb - (double)k));
+                    h[8] = fmax(0.0, 1.0 - fmin(fabs(tb - 8.0), fabs(tb + 1.0)));
+                    const int q0 = px < 4 ? 0 : 1;                 // target columns q0 - 1 and q0 (as dx)
+                    const double wx0 = spatial_w(px, q0 - 1), wx1 = spatial_w(px, q0);
+                    const double m0 = mag * wy0, m1 = mag * wy1;
+#pragma unroll
+                    for (int k = 0; k < PD_HOG_BINS; ++k) {
+                        acc[0][q0][k] = fma(m0 * wx0, h[k], acc[0][q0][k]);
+                        acc[0][q0 + 1][k] = fma(m0 * wx1, h[k], acc[0][q0 + 1][k]);
+                        acc[1][q0][k] = fma(m1 * wx0, h[k], acc[1][q0][k]);
+                        acc[1][q0 + 1][k] = fma(m1 * wx1, h[k], acc[1][q0 + 1][k]);
                     }
                 }
             }
+            // dy = 0 gets the top half's acc[1] and the bottom half's acc[0]
+            double* A = sm.u.A[cell];
+#pragma unroll
+            for (int b = 0; b < 3; ++b)
+#pragma unroll
+                for (int k = 0; k < PD_HOG_BINS; ++k) {
+                    const double other = __shfl_xor(acc[0][b][k], 32, 64);
+                    if (half == 0) {
+                        A[(0 * 3 + b) * PD_HOG_BINS + k] = acc[0][b][k];           // dy = -1
+                        A[(1 * 3 + b) * PD_HOG_BINS + k] = acc[1][b][k] + other;   // dy = 0
+                    } else {
+                        A[(2 * 3 + b) * PD_HOG_BINS + k] = acc[1][b][k];           // dy = +1
+                    }
+                }
         }
         __syncthreads();
 
-        double part[8];
-        for (int m = 0; m < 8; ++m) part[m] = 0.0;
-        if (t < PD_WIN_BLOCKS_Y * PD_WIN_BLOCKS_X) {
+        // blocks: slot (r, c) of block (by, bx) sums the partials its 4 cells aim at it
+        double v[PD_HOG_BLOCK];
+        double inv = 0.0;
+        const bool blk = t < PD_WIN_BLOCKS_Y * PD_WIN_BLOCKS_X;
+        if (blk) {
             const int by = t / PD_WIN_BLOCKS_X, bx = t - (t / PD_WIN_BLOCKS_X) * PD_WIN_BLOCKS_X;
-            double v[PD_HOG_BLOCK];
             for (int r = 0; r < 2; ++r)
                 for (int c = 0; c < 2; ++c)
                     for (int k = 0; k < PD_HOG_BINS; ++k) {
                         double s = 0.0;
                         for (int sy = 0; sy < 2; ++sy)
                             for (int sx = 0; sx < 2; ++sx)
-                                s += sm.A[(by + sy) * PD_WIN_CELLS_X + (bx + sx)][((r - sy + 1) * 3 + (c - sx + 1)) *
-                                                                                   PD_HOG_BINS + k];
+                                s += sm.u.A[(by + sy) * PD_WIN_CELLS_X + (bx + sx)][((r - sy + 1) * 3 + (c - sx + 1)) *
+                                                                                     PD_HOG_BINS + k];
                         v[(r * 2 + c) * PD_HOG_BINS + k] = s;
                     }
             double ss = 0.0;
             for (int k = 0; k < PD_HOG_BLOCK; ++k) ss += v[k] * v[k];
-            double inv = 1.0 / sqrt(ss + eps * eps);
+            inv = 1.0 / sqrt(ss + eps * eps);
             double ss2 = 0.0;
             for (int k = 0; k < PD_HOG_BLOCK; ++k) {
                 v[k] = fmin(v[k] * inv, clip);
                 ss2 += v[k] * v[k];
             }
             inv = 1.0 / sqrt(ss2 + eps * eps);
-            for (int m = 0; m < n_models; ++m) {
-                const float* w = weights + (size_t)m * PD_FEATURE_DIM + (by * PD_WIN_BLOCKS_X + bx) * PD_HOG_BLOCK;
-                double s = 0.0;
-                for (int k = 0; k < PD_HOG_BLOCK; ++k) s += (v[k] * inv) * (double)w[k];
-                part[m] = s;
-            }
-        } else if (t >= 128) {
-            const int u = t - 128;
-            const int a = u / PD_WIN_CELLS_X, b = u - (u / PD_WIN_CELLS_X) * PD_WIN_CELLS_X;
-            const size_t plane = (size_t)it.hc * it.wc;
-            const uint8_t* cnt = it.lbp + (size_t)(wi + a) * it.wc + (wj + b);
-            for (int m = 0; m < n_models; ++m) {
-                const float* w = weights + (size_t)m * PD_FEATURE_DIM + PD_HOG_DIM + (a * PD_WIN_CELLS_X + b) * PD_LBP_BINS;
-                double s = 0.0;
-                for (int c = 0; c < PD_LBP_BINS; ++c) s += (double)cnt[c * plane] * (double)w[c];
-                part[m] = s;
-            }
         }
-        for (int m = 0; m < 8; ++m) sm.part[t][m] = part[m];
+        __syncthreads();  // every partial is read before the HOG values overwrite them
+        if (blk)
+            for (int k = 0; k < PD_HOG_BLOCK; ++k) sm.u.hog[t * PD_HOG_BLOCK + k] = v[k] * inv;
         __syncthreads();
-        for (int stride = 128; stride > 0; stride >>= 1) {
-            if (t < stride)
-                for (int m = 0; m < 8; ++m) sm.part[t][m] += sm.part[t + stride][m];
-            __syncthreads();
+
+        // dot products over the 11332 features, all lanes, coalesced weights
+        double part[8];
+        for (int m = 0; m < 8; ++m) part[m] = 0.0;
+        const size_t plane = (size_t)it.hc * it.wc;
+        for (int k = t; k < PD_FEATURE_DIM; k += 256) {
+            double x;
+            if (k < PD_HOG_DIM) {
+                x = sm.u.hog[k];
+            } else {
+                const int e = k - PD_HOG_DIM;
+                const int cell = e / PD_LBP_BINS, bin = e - cell * PD_LBP_BINS;
+                const int a = cell / PD_WIN_CELLS_X, b = cell - a * PD_WIN_CELLS_X;
+                x = (double)it.lbp[bin * plane + (size_t)(wi + a) * it.wc + (wj + b)];
+            }
+            for (int m = 0; m < n_models; ++m) part[m] = fma(x, (double)weights[(size_t)m * PD_FEATURE_DIM + k], part[m]);
         }
+        for (int m = 0; m < 8; ++m) {
+            double s = part[m];
+            for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+            if (lane == 0) sm.part[wave][m] = s;
+        }
+        __syncthreads();
         if (t == 0) {
-            double best = sm.part[0][0] + (double)bias[0];
+            double best = 0.0;
             int bm = 0;
-            for (int m = 1; m < n_models; ++m) {
-                const double s = sm.part[0][m] + (double)bias[m];
-                if (s > best) {
+            for (int m = 0; m < n_models; ++m) {
+                const double s = ((sm.part[0][m] + sm.part[1][m]) + (sm.part[2][m] + sm.part[3][m])) + (double)bias[m];
+                if (m == 0 || s > best) {
                     best = s;
                     bm = m;
                 }
