@@ -8,8 +8,9 @@
 //   level, i, j ascending) with a bitonic sort in LDS; the greedy pass walks
 //   them in chunks of 64: a candidate is suppressed if it overlaps (IoU > 0.5,
 //   decided exactly as 2*inter > union on integer boxes) a box kept in an
-//   earlier chunk (tested in parallel) or an earlier kept box of its own chunk
-//   (a 64x64 overlap mask resolved by one lane).  This is exactly the serial
+//   earlier chunk (tested in parallel; per-candidate flags, no atomics) or an
+//   earlier kept box of its own chunk (a 64x64 overlap mask resolved by one
+//   lane).  This is exactly the serial
 //   greedy algorithm, and needs no n x n mask in memory.
 #include "pd_internal.h"
 
@@ -78,7 +79,7 @@ struct NmsSmem {
     int4 kbox[PD_MAX_CANDIDATES];
     int4 cbox[64];
     unsigned long long cmask[64];
-    uint32_t sup[2];
+    uint32_t supf[64];  // candidate of the chunk overlaps an earlier kept box (every writer stores 1)
     int nkept;
 };
 
@@ -153,12 +154,12 @@ __device__ void nms_frame(const NmsGeom& g, int frame, int raw_count, const floa
             const int4 k = ck[sm.sidx[c0 + t]];
             sm.cbox[t] = window_box(g, k.x, k.y, k.z);
         }
-        if (t < 2) sm.sup[t] = 0u;
+        if (t < 64) sm.supf[t] = 0u;
         __syncthreads();
         const int K = sm.nkept;
         for (int e = t; e < cn * K; e += 256) {
             const int q = e % cn, kk = e / cn;
-            if (overlaps(sm.cbox[q], sm.kbox[kk])) atomicOr(&sm.sup[q >> 5], 1u << (q & 31));
+            if (overlaps(sm.cbox[q], sm.kbox[kk])) sm.supf[q] = 1u;
         }
         if (t < cn) {
             unsigned long long m = 0;
@@ -167,19 +168,22 @@ __device__ void nms_frame(const NmsGeom& g, int frame, int raw_count, const floa
             sm.cmask[t] = m;
         }
         __syncthreads();
-        if (t == 0) {
-            unsigned long long alive = (cn == 64) ? ~0ull : ((1ull << cn) - 1);
-            alive &= ~(((unsigned long long)sm.sup[1] << 32) | sm.sup[0]);
-            int nk = sm.nkept;
-            for (int q = 0; q < cn; ++q) {
-                if ((alive >> q) & 1ull) {
-                    sm.kbox[nk] = sm.cbox[q];
-                    sm.kpos[nk] = (uint16_t)(c0 + q);
-                    ++nk;
-                    alive &= ~sm.cmask[q];
+        if (t < 64) {  // wave 0: the chunk's surviving candidates as a bit mask
+            const unsigned long long sup = __ballot(t < cn && sm.supf[t] != 0u);
+            if (t == 0) {
+                unsigned long long alive = (cn == 64) ? ~0ull : ((1ull << cn) - 1);
+                alive &= ~sup;
+                int nk = sm.nkept;
+                for (int q = 0; q < cn; ++q) {
+                    if ((alive >> q) & 1ull) {
+                        sm.kbox[nk] = sm.cbox[q];
+                        sm.kpos[nk] = (uint16_t)(c0 + q);
+                        ++nk;
+                        alive &= ~sm.cmask[q];
+                    }
                 }
+                sm.nkept = nk;
             }
-            sm.nkept = nk;
         }
         __syncthreads();
     }

@@ -21,8 +21,9 @@
 //  * blocks: lanes 0..104 sum the partials aimed at each block slot
 //    (exactly Algorithm 5's votes), L2-Hys, and store the window's 3780 HOG
 //    values (over the partials, after a barrier);
-//  * dot products: all 256 lanes stride over the 11332 features (coalesced
-//    FP32 weights, LBP counts from the planes), then a fixed-order reduction.
+//  * dot products: the window's LBP counts are staged in LDS beside the HOG
+//    values; all 256 lanes stride over the 11332 features (coalesced FP32
+//    weights, four features in flight), then a fixed-order reduction.
 #include "pd_internal.h"
 
 namespace pd {
@@ -36,7 +37,10 @@ struct RescoreShared {
     uint8_t px[RS_PY][RS_PX + 2];
     union {
         double A[RS_CELLS][81];      // per cell: 3x3 target cells x 9 bins
-        double hog[PD_HOG_DIM];      // the window's normalised HOG values
+        struct {
+            double hog[PD_HOG_DIM];  // the window's normalised HOG values
+            uint8_t lbp[PD_LBP_DIM]; // its LBP counts, feature order (cell, bin)
+        } x;
     } u;
     double part[4][8];               // per wave, per model
 };
@@ -162,25 +166,46 @@ __global__ void __launch_bounds__(256) rescore64_kernel(const LevelItem* __restr
         }
         __syncthreads();  // every partial is read before the HOG values overwrite them
         if (blk)
-            for (int k = 0; k < PD_HOG_BLOCK; ++k) sm.u.hog[t * PD_HOG_BLOCK + k] = v[k] * inv;
+            for (int k = 0; k < PD_HOG_BLOCK; ++k) sm.u.x.hog[t * PD_HOG_BLOCK + k] = v[k] * inv;
+        {
+            // LBP counts of the window's 16 x 8 cells: 8 contiguous bytes per
+            // plane row, stored in feature order
+            const size_t plane = (size_t)it.hc * it.wc;
+            for (int e = t; e < PD_LBP_DIM; e += 256) {
+                const int bin = e / (PD_WIN_CELLS_Y * PD_WIN_CELLS_X), cell = e - bin * (PD_WIN_CELLS_Y * PD_WIN_CELLS_X);
+                const int a = cell / PD_WIN_CELLS_X, b = cell - a * PD_WIN_CELLS_X;
+                sm.u.x.lbp[cell * PD_LBP_BINS + bin] = it.lbp[bin * plane + (size_t)(wi + a) * it.wc + (wj + b)];
+            }
+        }
         __syncthreads();
 
         // dot products over the 11332 features, all lanes, coalesced weights
+        // (models unrolled to 8 with guards, four features per step, so a
+        // thread's weight loads are in flight together; features from LDS)
         double part[8];
+#pragma unroll
         for (int m = 0; m < 8; ++m) part[m] = 0.0;
-        const size_t plane = (size_t)it.hc * it.wc;
-        for (int k = t; k < PD_FEATURE_DIM; k += 256) {
-            double x;
-            if (k < PD_HOG_DIM) {
-                x = sm.u.hog[k];
-            } else {
-                const int e = k - PD_HOG_DIM;
-                const int cell = e / PD_LBP_BINS, bin = e - cell * PD_LBP_BINS;
-                const int a = cell / PD_WIN_CELLS_X, b = cell - a * PD_WIN_CELLS_X;
-                x = (double)it.lbp[bin * plane + (size_t)(wi + a) * it.wc + (wj + b)];
+        for (int k0 = t; k0 < PD_FEATURE_DIM; k0 += 1024) {
+            // unconditional loads at clamped indices (no branch per load):
+            // past the last feature x is 0; models past n_models repeat the
+            // last one and their sums are never read
+            float w[4][8];
+            double x[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int k = k0 + 256 * u;
+                const int kc = min(k, PD_FEATURE_DIM - 1);
+#pragma unroll
+                for (int m = 0; m < 8; ++m) w[u][m] = weights[(size_t)min(m, n_models - 1) * PD_FEATURE_DIM + kc];
+                const double xv = kc < PD_HOG_DIM ? sm.u.x.hog[kc] : (double)sm.u.x.lbp[kc - PD_HOG_DIM];
+                x[u] = k < PD_FEATURE_DIM ? xv : 0.0;
             }
-            for (int m = 0; m < n_models; ++m) part[m] = fma(x, (double)weights[(size_t)m * PD_FEATURE_DIM + k], part[m]);
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int m = 0; m < 8; ++m) part[m] = fma(x[u], (double)w[u][m], part[m]);
         }
+#pragma unroll
         for (int m = 0; m < 8; ++m) {
             double s = part[m];
             for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
