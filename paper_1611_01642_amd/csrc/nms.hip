@@ -79,6 +79,7 @@ struct NmsSmem {
     int4 kbox[PD_MAX_CANDIDATES];
     int4 cbox[64];
     unsigned long long cmask[64];
+    uint16_t cpart[4][64];  // in-chunk overlap bits, 16 columns per part
     uint32_t supf[64];  // candidate of the chunk overlaps an earlier kept box (every writer stores 1)
     int nkept;
 };
@@ -104,13 +105,15 @@ __device__ inline int4 window_box(const NmsGeom& g, int level, int i, int j) {
     return b;
 }
 
+// 2 * inter > union on the integer Q8 boxes.  Sides are below 2^23, so
+// every product and sum here is an integer below 2^53: exact in FP64.
 __device__ inline bool overlaps(const int4& a, const int4& b) {
-    const int64_t iw = (int64_t)min(a.z, b.z) - max(a.x, b.x);
-    const int64_t ih = (int64_t)min(a.w, b.w) - max(a.y, b.y);
+    const int iw = min(a.z, b.z) - max(a.x, b.x);
+    const int ih = min(a.w, b.w) - max(a.y, b.y);
     if (iw <= 0 || ih <= 0) return false;
-    const int64_t inter = iw * ih;
-    const int64_t uni = (int64_t)(a.z - a.x) * (a.w - a.y) + (int64_t)(b.z - b.x) * (b.w - b.y) - inter;
-    return 2 * inter > uni;
+    const double inter = (double)iw * (double)ih;
+    const double uni = (double)(a.z - a.x) * (double)(a.w - a.y) + (double)(b.z - b.x) * (double)(b.w - b.y) - inter;
+    return 2.0 * inter > uni;
 }
 
 __device__ void nms_frame(const NmsGeom& g, int frame, int raw_count, const float* __restrict__ cs,
@@ -161,12 +164,20 @@ __device__ void nms_frame(const NmsGeom& g, int frame, int raw_count, const floa
             const int q = e % cn, kk = e / cn;
             if (overlaps(sm.cbox[q], sm.kbox[kk])) sm.supf[q] = 1u;
         }
-        if (t < cn) {
-            unsigned long long m = 0;
-            for (int r = t + 1; r < cn; ++r)
-                if (overlaps(sm.cbox[t], sm.cbox[r])) m |= 1ull << r;
-            sm.cmask[t] = m;
+        {
+            // in-chunk overlaps: candidate q against the later ones, 16
+            // columns per thread (4 threads per candidate)
+            const int q = t & 63, part = t >> 6;
+            uint32_t m = 0;
+            if (q < cn)
+                for (int r = max(q + 1, 16 * part); r < min(cn, 16 * part + 16); ++r)
+                    if (overlaps(sm.cbox[q], sm.cbox[r])) m |= 1u << (r - 16 * part);
+            sm.cpart[part][q] = (uint16_t)m;
         }
+        __syncthreads();
+        if (t < 64)
+            sm.cmask[t] = (unsigned long long)sm.cpart[0][t] | ((unsigned long long)sm.cpart[1][t] << 16) |
+                          ((unsigned long long)sm.cpart[2][t] << 32) | ((unsigned long long)sm.cpart[3][t] << 48);
         __syncthreads();
         if (t < 64) {  // wave 0: the chunk's surviving candidates as a bit mask
             const unsigned long long sup = __ballot(t < cn && sm.supf[t] != 0u);
