@@ -93,8 +93,10 @@ struct FeatShared {
 
 // One pixel row of a cell's neighbourhood: byte i (0..9) is pixel x0 - 1 + i.
 struct PixRow {
-    uint32_t lo, hi;   // own pixels x0..x0+7
+    uint32_t lo, hi;   // own pixels x0..x0+7 (bytes 1..8)
     uint32_t halo;     // byte 0: pixel x0 - 1, byte 1: pixel x0 + 8 (clamped)
+    uint32_t l0, l1;   // bytes 0..3 and 4..7: the left neighbours of lo, hi
+    uint32_t r0, r1;   // bytes 2..5 and 6..9: the right neighbours of lo, hi
 };
 
 template <bool ALIGNED>
@@ -112,7 +114,33 @@ __device__ __forceinline__ PixRow load_row(const uint8_t* __restrict__ img, int 
     const uint32_t left = x0 > 0 ? (uint32_t)p[-1] : (r.lo & 255u);
     const uint32_t right = x0 + 8 < w ? (uint32_t)p[8] : (r.hi >> 24);
     r.halo = left | (right << 8);
+    r.l0 = __builtin_amdgcn_perm(r.lo, r.halo, 0x06050400u);
+    r.l1 = __builtin_amdgcn_alignbyte(r.hi, r.lo, 3);
+    r.r0 = __builtin_amdgcn_alignbyte(r.hi, r.lo, 1);
+    r.r1 = __builtin_amdgcn_perm(r.halo, r.hi, 0x05030201u);
     return r;
+}
+
+// Per byte of four packed pixels, n >= c in bit 7 (the other bits are
+// don't-care): the low seven bits are compared with the byte's top bit as a
+// guard against borrows between bytes, and the top bits decide where they
+// differ.
+__device__ __forceinline__ uint32_t ge_bytes(uint32_t n, uint32_t c, uint32_t c_low) {
+    const uint32_t d = (n | 0x80808080u) - c_low;
+    // (n & ~c) | (~(n ^ c) & d) as one three-input bit operation
+    return __builtin_amdgcn_bitop3_b32(n, c, d, 0xB2);
+}
+
+// Merges the eight comparison words (answer in bit 7 of each byte) into one
+// LBP code per byte, neighbour k in bit 7 - k: the bit-reversed order of the
+// code Algorithm 1 defines, which the lookup table below is built for.
+__device__ __forceinline__ uint32_t lbp_codes4(const uint32_t (&r)[8]) {
+    // (a & m) | (b & ~m) as one three-input bit operation
+    auto sel = [](uint32_t m, uint32_t a, uint32_t b) { return __builtin_amdgcn_bitop3_b32(m, a, b, 0xCA); };
+    const uint32_t t01 = sel(0x80808080u, r[0], r[1] >> 1), t23 = sel(0x80808080u, r[2], r[3] >> 1);
+    const uint32_t t45 = sel(0x80808080u, r[4], r[5] >> 1), t67 = sel(0x80808080u, r[6], r[7] >> 1);
+    const uint32_t q0 = sel(0xC0C0C0C0u, t01, t23 >> 2), q1 = sel(0xC0C0C0C0u, t45, t67 >> 2);
+    return sel(0xF0F0F0F0u, q0, q1 >> 4);
 }
 
 __device__ __forceinline__ int px_at(const PixRow& r, int i) {  // i in 0..9, compile-time after unrolling
@@ -201,6 +229,23 @@ __device__ __forceinline__ void features_strip(const uint8_t* __restrict__ img, 
     auto pixel_row = [&](int py, const PixRow& U, const PixRow& C, const PixRow& D, float s0, float s1,
                          bool count_lbp) {
         float R[3][PD_HOG_BINS];
+        // LBP codes of the row's 8 pixels, four per word (Algorithm 1's
+        // neighbours in its bit order: up-left, up, up-right, right,
+        // down-right, down, down-left, left)
+        uint32_t code4[2] = {0u, 0u};
+        if (DO_LBP && count_lbp) {
+            const uint32_t cw[2] = {C.lo, C.hi};
+            const uint32_t nb[2][8] = {{U.l0, U.lo, U.r0, C.r0, D.r0, D.lo, D.l0, C.l0},
+                                       {U.l1, U.hi, U.r1, C.r1, D.r1, D.hi, D.l1, C.l1}};
+#pragma unroll
+            for (int hw = 0; hw < 2; ++hw) {
+                const uint32_t c_low = cw[hw] & 0x7f7f7f7fu;
+                uint32_t r[8];
+#pragma unroll
+                for (int k = 0; k < 8; ++k) r[k] = ge_bytes(nb[hw][k], cw[hw], c_low);
+                code4[hw] = lbp_codes4(r);
+            }
+        }
         if (DO_HOG) {
 #pragma unroll
             for (int a = 0; a < 3; ++a)
@@ -209,15 +254,10 @@ __device__ __forceinline__ void features_strip(const uint8_t* __restrict__ img, 
         }
 #pragma unroll
         for (int px = 0; px < PD_CELL; ++px) {
-            const int c = px_at(C, px + 1);
             const int L = px_at(C, px), Rt = px_at(C, px + 2);
             const int T = px_at(U, px + 1), B = px_at(D, px + 1);
             if (DO_LBP && count_lbp) {
-                const int code = (int)(px_at(U, px) >= c) | ((int)(T >= c) << 1) |
-                                 ((int)(px_at(U, px + 2) >= c) << 2) | ((int)(Rt >= c) << 3) |
-                                 ((int)(px_at(D, px + 2) >= c) << 4) | ((int)(B >= c) << 5) |
-                                 ((int)(px_at(D, px) >= c) << 6) | ((int)(L >= c) << 7);
-                const uint32_t e = sm.lut[code];
+                const uint32_t e = sm.lut[(code4[px >> 2] >> (8 * (px & 3))) & 255u];
                 uint32_t* q = cnt + (e & 127u);
                 *q = *q + (e >> 7);
             }
@@ -232,11 +272,18 @@ __device__ __forceinline__ void features_strip(const uint8_t* __restrict__ img, 
                 u = (ay > ax) ? 4.5f - u : u;                     // first quadrant
                 float t = ((dx * dy < 0) ? 9.0f - u : u) - 0.5f;  // fold, centres 10+20k
                 t = t < 0.0f ? t + 9.0f : t;                      // [0, 9)
+                // magnitude x hat(t - k): with c_j = mag (j - t), the hat of bin
+                // k is the median of 0, c_{k+1} and -c_{k-1}; bin 0 also takes
+                // the wrapped side, max(0, c_1, -c_8)
                 const float mt = mag * t;
-                float wv[PD_HOG_BINS];                            // magnitude x hat(t - k)
-                wv[0] = fmaxf(0.0f, fmaf(-mag, fminf(t, 9.0f - t), mag));
+                float c[PD_HOG_BINS + 1];
+                c[0] = -mt;
 #pragma unroll
-                for (int k = 1; k < PD_HOG_BINS; ++k) wv[k] = fmaxf(0.0f, mag - fabsf(fmaf(-(float)k, mag, mt)));
+                for (int j = 1; j <= PD_HOG_BINS; ++j) c[j] = fmaf((float)j, mag, -mt);
+                float wv[PD_HOG_BINS];
+                wv[0] = fmaxf(fmaxf(c[1], -c[8]), 0.0f);
+#pragma unroll
+                for (int k = 1; k < PD_HOG_BINS; ++k) wv[k] = __builtin_amdgcn_fmed3f(0.0f, c[k + 1], -c[k - 1]);
                 const int dxa = px < 4 ? -1 : 0;
 #pragma unroll
                 for (int q = 0; q < 2; ++q) {
@@ -420,8 +467,9 @@ __device__ __forceinline__ void features_strip(const uint8_t* __restrict__ img, 
     }
 }
 
+// Indexed by the bit-reversed code that lbp_codes4 produces.
 __device__ inline void init_lut(FeatShared& sm) {
-    const int b = kLbp.bin[threadIdx.x];
+    const int b = kLbp.bin[__brev(threadIdx.x) >> 24];
     sm.lut[threadIdx.x] = ((1u << (8 * (b & 3))) << 7) | (uint32_t)(b >> 2);
 }
 
