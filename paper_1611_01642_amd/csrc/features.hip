@@ -83,12 +83,17 @@ __host__ __device__ constexpr float sw(int p, int d) {
 }
 
 constexpr int LBP_WORDS = 15;  // 59 byte counters packed in words
-constexpr int PREV_VALS = 54;  // partials of dirs dy in {0, 1} of the previous row
 
+// Per lane, what the previous cell row leaves for the next: with the cell map,
+// its partials of dirs dy in {0, 1} (54 values); without it, the four block
+// slot sums they feed (36 values), which keeps a workgroup's LDS small enough
+// for three workgroups per CU.
+template <bool CM>
 struct FeatShared {
+    static constexpr int PREV_VALS = CM ? 6 * PD_HOG_BINS : 4 * PD_HOG_BINS;
     uint32_t lut[256];                               // (increment << 7) | word
     uint32_t cnt[FT_WAVES][FT_W * LBP_WORDS];        // lane-private byte counters
-    float prev[FT_WAVES][PREV_VALS][FT_W];           // previous cell row's partials
+    float prev[FT_WAVES][PREV_VALS][FT_W];           // previous cell row's partials or slot sums
 };
 
 // One pixel row of a cell's neighbourhood: byte i (0..9) is pixel x0 - 1 + i.
@@ -162,7 +167,7 @@ template <int FEAT, bool ALIGNED, bool CM = false>
 __device__ __forceinline__ void features_strip(const uint8_t* __restrict__ img, int w, int h, int pitch, float* __restrict__ hog,
                                uint16_t* __restrict__ hog16, uint8_t* __restrict__ lbp, float* __restrict__ cmap,
                                uint16_t* __restrict__ cmap16, int ty, int tx, int ch, float clip, float eps,
-                               FeatShared& sm, int wave, int group = 64) {
+                               FeatShared<CM>& sm, int wave, int group = 64) {
     constexpr bool DO_HOG = (FEAT & PD_FEAT_HOG) != 0;
     constexpr bool DO_LBP = (FEAT & PD_FEAT_LBP) != 0;
     static_assert(!CM || (DO_HOG && DO_LBP), "the cell map needs HOG and LBP");
@@ -213,16 +218,58 @@ __device__ __forceinline__ void features_strip(const uint8_t* __restrict__ img, 
             }
         }
     };
+    // L2-Hys of one block (slots (r, c) in order (0,0), (0,1), (1,0), (1,1)),
+    // stored into the planes at block row `row`, column cx
+    auto store_block = [&](float (&v)[PD_HOG_BLOCK], int row) {
+        const float e2 = eps * eps;
+        float ss = 0.0f;
+#pragma unroll
+        for (int k = 0; k < PD_HOG_BLOCK; ++k) ss = fmaf(v[k], v[k], ss);
+        float inv = 1.0f / sqrtf(ss + e2);
+        float ss2 = 0.0f;
+#pragma unroll
+        for (int k = 0; k < PD_HOG_BLOCK; ++k) {
+            v[k] = fminf(v[k] * inv, clip);
+            ss2 = fmaf(v[k], v[k], ss2);
+        }
+        inv = 1.0f / sqrtf(ss2 + e2);
+        const size_t plane = (size_t)hb * wb;
+        const size_t at = (size_t)row * wb + cx;
+        if (hog16) {  // BF16 planes (round to nearest even)
+            uint16_t* o = hog16 + at;
+#pragma unroll
+            for (int k = 0; k < PD_HOG_BLOCK; ++k) {
+                *o = f32_to_bf16(v[k] * inv);
+                o += plane;
+            }
+        } else {
+            float* o = hog + at;
+#pragma unroll
+            for (int k = 0; k < PD_HOG_BLOCK; ++k) {
+                *o = v[k] * inv;
+                o += plane;
+            }
+        }
+    };
     uint32_t* cnt = &sm.cnt[wave][lane * LBP_WORDS];
     if (DO_LBP) {
 #pragma unroll
         for (int k = 0; k < LBP_WORDS; ++k) cnt[k] = 0u;
     }
 
-    // partials of the previous cell row, [value][lane]: value (r*3 + c+1)*9 + k
-    // holds dir (dy = r, dx = c); after the top half of the next row, r = 0
-    // also holds that row's dy = -1 votes (the other term of the same slots)
+    // [value][lane].  With CM, value (r*3 + c+1)*9 + k is the previous cell
+    // row's partial of dir (dy = r, dx = c); after the top half of the next
+    // row, r = 0 also holds that row's dy = -1 votes (the other term of the
+    // same slots).  Without CM, value (r*2 + c)*9 + k is the sum aimed at slot
+    // (r, c) of the block whose top-left cell is this lane's in the previous
+    // row, from that row's two cells (and, after the top half of the next row,
+    // from the next row's dy = -1 votes).
     float (*P)[FT_W] = sm.prev[wave];
+    // the two terms one cell row gives slot (r, c), c in {0, 1}, of the block
+    // starting at this lane's column: own dx = c and the right lane's dx = c - 1
+    auto pair = [&](const float (&X)[3][PD_HOG_BINS], int c, int k) -> float {
+        return X[1 + c][k] + __shfl_down(X[c][k], 1, 64);
+    };
     float Aa[3][PD_HOG_BINS], Ab[3][PD_HOG_BINS];  // [dx+1][bin] for two target rows
 
     // one pixel row: votes into Aa (upper target row) and Ab (lower target row)
@@ -312,6 +359,7 @@ __device__ __forceinline__ void features_strip(const uint8_t* __restrict__ img, 
         PixRow U = load_row<ALIGNED>(img, pitch, w, max(yb + py0, 0), x0);
         PixRow C = load_row<ALIGNED>(img, pitch, w, min(yb + py0 + 1, h - 1), x0);
         PixRow D = load_row<ALIGNED>(img, pitch, w, min(yb + py0 + 2, h - 1), x0);
+        float top[2][PD_HOG_BINS];  // CM: top slots of the blocks of row cy - 1
         if (DO_HOG) {
 #pragma unroll
             for (int a = 0; a < 3; ++a)
@@ -331,12 +379,25 @@ __device__ __forceinline__ void features_strip(const uint8_t* __restrict__ img, 
             }
         }
         if (DO_HOG) {
-            if (cy > cy_start) {  // fold the dy = -1 votes into the previous row's r = 0 terms
+            if (cy > cy_start && !CM) {  // fold the dy = -1 votes into the top slots
+#pragma unroll
+                for (int k = 0; k < PD_HOG_BINS; ++k) {
+                    P[0 * 9 + k][lane] += pair(Aa, 0, k);
+                    P[1 * 9 + k][lane] += pair(Aa, 1, k);
+                }
+            }
+            if (cy > cy_start && CM) {  // fold the dy = -1 votes into the previous row's r = 0 terms
+                // the blocks' top slots first, summed as without CM
+#pragma unroll
+                for (int k = 0; k < PD_HOG_BINS; ++k) {
+                    top[0][k] = (P[1 * 9 + k][lane] + __shfl_down(P[0 * 9 + k][lane], 1, 64)) + pair(Aa, 0, k);
+                    top[1][k] = (P[2 * 9 + k][lane] + __shfl_down(P[1 * 9 + k][lane], 1, 64)) + pair(Aa, 1, k);
+                }
 #pragma unroll
                 for (int a = 0; a < 3; ++a)
 #pragma unroll
                     for (int k = 0; k < PD_HOG_BINS; ++k) P[a * 9 + k][lane] += Aa[a][k];
-                if (CM) {
+                {
                     // cell row cy - 1 is complete: votes from rows cy - 2 (down9),
                     // cy - 1 and cy (P r = 0); then row cy - 1's downward votes
                     float hist[PD_HOG_BINS];
@@ -393,62 +454,47 @@ __device__ __forceinline__ void features_strip(const uint8_t* __restrict__ img, 
         }
 
         if (DO_HOG) {
-            // blocks of row cy - 1, slots (r, c): (r, 0) = O_r0 + X_r(right lane),
-            // (r, 1) = O_r1 + O_r0(right lane), with O_rc = P(r, c) + cur(r - 1, c)
-            // and X_r = P(r, -1) + cur(r - 1, -1); the r = 0 sums are already in P
-            if (cy > cy0) {
+            // blocks of row cy - 1: top slots from P (CM: top), bottom slots the
+            // previous row's terms + this row's terms S (which are also the next
+            // row's top slots); both forms add the same terms in the same order
+            float S[2][PD_HOG_BINS];
+#pragma unroll
+            for (int k = 0; k < PD_HOG_BINS; ++k) {
+                S[0][k] = pair(Ab, 0, k);
+                S[1][k] = pair(Ab, 1, k);
+            }
+            if (cy > cy0 && !CM) {
                 float v[PD_HOG_BLOCK];
 #pragma unroll
-                for (int r = 0; r < 2; ++r) {
-#pragma unroll
-                    for (int k = 0; k < PD_HOG_BINS; ++k) {
-                        float xr = P[(r * 3 + 0) * 9 + k][lane];
-                        float o0 = P[(r * 3 + 1) * 9 + k][lane];
-                        float o1 = P[(r * 3 + 2) * 9 + k][lane];
-                        if (r == 1) {
-                            xr += Ab[0][k];
-                            o0 += Ab[1][k];
-                            o1 += Ab[2][k];
-                        }
-                        const float o0n = __shfl_down(o0, 1, 64);
-                        const float xrn = __shfl_down(xr, 1, 64);
-                        v[(r * 2 + 0) * 9 + k] = o0 + xrn;
-                        v[(r * 2 + 1) * 9 + k] = o1 + o0n;
-                    }
+                for (int k = 0; k < PD_HOG_BINS; ++k) {
+                    v[0 * 9 + k] = P[0 * 9 + k][lane];
+                    v[1 * 9 + k] = P[1 * 9 + k][lane];
+                    v[2 * 9 + k] = P[2 * 9 + k][lane] + S[0][k];
+                    v[3 * 9 + k] = P[3 * 9 + k][lane] + S[1][k];
                 }
-                if (blk_col) {
-                    const float e2 = eps * eps;
-                    float ss = 0.0f;
+                if (blk_col) store_block(v, cy - 1);
+            }
+            if (cy > cy0 && CM) {
+                float v[PD_HOG_BLOCK];
 #pragma unroll
-                    for (int k = 0; k < PD_HOG_BLOCK; ++k) ss = fmaf(v[k], v[k], ss);
-                    float inv = 1.0f / sqrtf(ss + e2);
-                    float ss2 = 0.0f;
+                for (int k = 0; k < PD_HOG_BINS; ++k) {
+                    v[0 * 9 + k] = top[0][k];
+                    v[1 * 9 + k] = top[1][k];
+                    v[2 * 9 + k] = (P[4 * 9 + k][lane] + __shfl_down(P[3 * 9 + k][lane], 1, 64)) + S[0][k];
+                    v[3 * 9 + k] = (P[5 * 9 + k][lane] + __shfl_down(P[4 * 9 + k][lane], 1, 64)) + S[1][k];
+                }
+                if (blk_col) store_block(v, cy - 1);
+            }
+            if (cy < cy_last && !CM) {  // this row's slot sums for the next row's blocks
 #pragma unroll
-                    for (int k = 0; k < PD_HOG_BLOCK; ++k) {
-                        v[k] = fminf(v[k] * inv, clip);
-                        ss2 = fmaf(v[k], v[k], ss2);
-                    }
-                    inv = 1.0f / sqrtf(ss2 + e2);
-                    const size_t plane = (size_t)hb * wb;
-                    const size_t at = (size_t)(cy - 1) * wb + cx;
-                    if (hog16) {  // BF16 planes (round to nearest even)
-                        uint16_t* o = hog16 + at;
-#pragma unroll
-                        for (int k = 0; k < PD_HOG_BLOCK; ++k) {
-                            *o = f32_to_bf16(v[k] * inv);
-                            o += plane;
-                        }
-                    } else {
-                        float* o = hog + at;
-#pragma unroll
-                        for (int k = 0; k < PD_HOG_BLOCK; ++k) {
-                            *o = v[k] * inv;
-                            o += plane;
-                        }
-                    }
+                for (int k = 0; k < PD_HOG_BINS; ++k) {
+                    P[0 * 9 + k][lane] = S[0][k];
+                    P[1 * 9 + k][lane] = S[1][k];
+                    P[2 * 9 + k][lane] = pair(Aa, 0, k);
+                    P[3 * 9 + k][lane] = pair(Aa, 1, k);
                 }
             }
-            if (cy < cy_last) {  // this row's dy = 0 and dy = +1 partials become P
+            if (cy < cy_last && CM) {  // this row's dy = 0 and dy = +1 partials become P
 #pragma unroll
                 for (int a = 0; a < 3; ++a)
 #pragma unroll
@@ -468,14 +514,15 @@ __device__ __forceinline__ void features_strip(const uint8_t* __restrict__ img, 
 }
 
 // Indexed by the bit-reversed code that lbp_codes4 produces.
-__device__ inline void init_lut(FeatShared& sm) {
+template <bool CM>
+__device__ inline void init_lut(FeatShared<CM>& sm) {
     const int b = kLbp.bin[__brev(threadIdx.x) >> 24];
     sm.lut[threadIdx.x] = ((1u << (8 * (b & 3))) << 7) | (uint32_t)(b >> 2);
 }
 
 template <int FEAT, bool ALIGNED>
 __global__ void __launch_bounds__(256) features_single_kernel(LevelItem it, float clip, float eps) {
-    __shared__ FeatShared sm;
+    __shared__ FeatShared<false> sm;
     init_lut(sm);
     __syncthreads();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -488,7 +535,7 @@ __global__ void __launch_bounds__(256) features_single_kernel(LevelItem it, floa
 
 template <bool ALIGNED>
 __global__ void __launch_bounds__(256) cellmap_single_kernel(LevelItem it, float clip, float eps) {
-    __shared__ FeatShared sm;
+    __shared__ FeatShared<true> sm;
     init_lut(sm);
     __syncthreads();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -503,7 +550,7 @@ __global__ void __launch_bounds__(256) cellmap_single_kernel(LevelItem it, float
 __global__ void __launch_bounds__(256) cellmap_table_kernel(const LevelItem* __restrict__ items,
                                                             const Tile* __restrict__ tiles, int n_tiles, int ch,
                                                             float clip, float eps) {
-    __shared__ FeatShared sm;
+    __shared__ FeatShared<true> sm;
     init_lut(sm);
     __syncthreads();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -522,7 +569,7 @@ template <int FEAT>
 __global__ void __launch_bounds__(256) features_table_kernel(const LevelItem* __restrict__ items,
                                                              const Tile* __restrict__ tiles, int n_tiles, int ch,
                                                              float clip, float eps) {
-    __shared__ FeatShared sm;
+    __shared__ FeatShared<false> sm;
     init_lut(sm);
     __syncthreads();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
