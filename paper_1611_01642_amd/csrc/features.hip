@@ -105,13 +105,13 @@ struct PixRow {
 };
 
 template <bool ALIGNED>
-__device__ __forceinline__ PixRow load_row(const uint8_t* __restrict__ img, int pitch, int w, int y, int x0) {
-    const uint8_t* p = img + (size_t)y * pitch + x0;
+__device__ __forceinline__ PixRow load_row(gptr<const uint8_t> __restrict__ img, int pitch, int w, int y, int x0) {
+    const auto p = img + (size_t)y * pitch + x0;
     PixRow r;
     if (ALIGNED) {
-        const uint2 m = *reinterpret_cast<const uint2*>(p);
-        r.lo = m.x;
-        r.hi = m.y;
+        const uint64_t m = *reinterpret_cast<gptr<const uint64_t>>(p);
+        r.lo = (uint32_t)m;
+        r.hi = (uint32_t)(m >> 32);
     } else {
         r.lo = (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16) | ((uint32_t)p[3] << 24);
         r.hi = (uint32_t)p[4] | ((uint32_t)p[5] << 8) | ((uint32_t)p[6] << 16) | ((uint32_t)p[7] << 24);
@@ -164,10 +164,11 @@ __device__ __forceinline__ int px_at(const PixRow& r, int i) {  // i in 0..9, co
 // the strip starts half a cell row early (the downward votes of the row
 // above), so each owned cell sees all of its neighbours' partials.
 template <int FEAT, bool ALIGNED, bool CM = false>
-__device__ __forceinline__ void features_strip(const uint8_t* __restrict__ img, int w, int h, int pitch, float* __restrict__ hog,
-                               uint16_t* __restrict__ hog16, uint8_t* __restrict__ lbp, float* __restrict__ cmap,
-                               uint16_t* __restrict__ cmap16, int ty, int tx, int ch, float clip, float eps,
-                               FeatShared<CM>& sm, int wave, int group = 64) {
+__device__ __forceinline__ void features_strip(gptr<const uint8_t> __restrict__ img, int w, int h, int pitch,
+                                               gptr<float> __restrict__ hog, gptr<uint16_t> __restrict__ hog16,
+                                               gptr<uint8_t> __restrict__ lbp, gptr<float> __restrict__ cmap,
+                                               gptr<uint16_t> __restrict__ cmap16, int ty, int tx, int ch, float clip,
+                                               float eps, FeatShared<CM>& sm, int wave, int group = 64) {
     constexpr bool DO_HOG = (FEAT & PD_FEAT_HOG) != 0;
     constexpr bool DO_LBP = (FEAT & PD_FEAT_LBP) != 0;
     static_assert(!CM || (DO_HOG && DO_LBP), "the cell map needs HOG and LBP");
@@ -207,12 +208,12 @@ __device__ __forceinline__ void features_strip(const uint8_t* __restrict__ img, 
         if (own) {
             if (cmap) {
                 const size_t plane = (size_t)hc * wc;
-                float* o = cmap + (size_t)row * wc + cx;
+                const auto o = cmap + (size_t)row * wc + cx;
 #pragma unroll
                 for (int k = 0; k < PD_HOG_BINS; ++k) o[k * plane] = hist[k] * inv;
             }
             if (cmap16) {
-                uint16_t* o = cmap16 + ((size_t)row * wc + cx) * PR_CP1;
+                const auto o = cmap16 + ((size_t)row * wc + cx) * PR_CP1;
 #pragma unroll
                 for (int k = 0; k < PD_HOG_BINS; ++k) o[k] = f32_to_bf16(hist[k] * inv);
             }
@@ -236,14 +237,14 @@ __device__ __forceinline__ void features_strip(const uint8_t* __restrict__ img, 
         const size_t plane = (size_t)hb * wb;
         const size_t at = (size_t)row * wb + cx;
         if (hog16) {  // BF16 planes (round to nearest even)
-            uint16_t* o = hog16 + at;
+            auto o = hog16 + at;
 #pragma unroll
             for (int k = 0; k < PD_HOG_BLOCK; ++k) {
                 *o = f32_to_bf16(v[k] * inv);
                 o += plane;
             }
         } else {
-            float* o = hog + at;
+            auto o = hog + at;
 #pragma unroll
             for (int k = 0; k < PD_HOG_BLOCK; ++k) {
                 *o = v[k] * inv;
@@ -431,17 +432,17 @@ __device__ __forceinline__ void features_strip(const uint8_t* __restrict__ img, 
             const bool own_row = cy >= cy0 && (cy < cy0 + ch || cy == hc - 1);
             if (own_row && lbp_col) {
                 const size_t plane = (size_t)hc * wc;
-                uint8_t* o = lbp + (size_t)cy * wc + cx;
+                auto o = lbp + (size_t)cy * wc + cx;
 #pragma unroll 1
                 for (int k = 0; k < PD_LBP_BINS; ++k, o += plane) *o = (uint8_t)((cnt[k >> 2] >> (8 * (k & 3))) & 255u);
                 if (CM && cmap) {
-                    float* c = cmap + ((size_t)PD_HOG_BINS * hc + cy) * wc + cx;
+                    auto c = cmap + ((size_t)PD_HOG_BINS * hc + cy) * wc + cx;
 #pragma unroll 1
                     for (int k = 0; k < PD_LBP_BINS; ++k, c += plane)
                         *c = (float)((cnt[k >> 2] >> (8 * (k & 3))) & 255u) * (1.0f / 64.0f);
                 }
                 if (CM && cmap16) {  // counts / 64 are exact in BF16; channels 68..71 zero
-                    uint16_t* c = cmap16 + ((size_t)cy * wc + cx) * PR_CP1 + PD_HOG_BINS;
+                    const auto c = cmap16 + ((size_t)cy * wc + cx) * PR_CP1 + PD_HOG_BINS;
 #pragma unroll 1
                     for (int k = 0; k < PD_LBP_BINS; ++k)
                         c[k] = f32_to_bf16((float)((cnt[k >> 2] >> (8 * (k & 3))) & 255u) * (1.0f / 64.0f));
@@ -529,8 +530,8 @@ __global__ void __launch_bounds__(256) features_single_kernel(LevelItem it, floa
     const int task = blockIdx.x * FT_WAVES + wave;
     const int ntx = feat_tiles_x(it.wc);
     if (task >= ntx * feat_tiles_y(it.hc)) return;
-    features_strip<FEAT, ALIGNED>(it.pyr, it.w, it.h, it.pitch, it.hog, it.hog16, it.lbp, nullptr, nullptr,
-                                  task / ntx, task % ntx, FT_CH, clip, eps, sm, wave);
+    features_strip<FEAT, ALIGNED>(gmem(it.pyr), it.w, it.h, it.pitch, gmem(it.hog), gmem(it.hog16), gmem(it.lbp),
+                                  nullptr, nullptr, task / ntx, task % ntx, FT_CH, clip, eps, sm, wave);
 }
 
 template <bool ALIGNED>
@@ -542,9 +543,9 @@ __global__ void __launch_bounds__(256) cellmap_single_kernel(LevelItem it, float
     const int task = blockIdx.x * FT_WAVES + wave;
     const int ntx = feat_tiles_x_cm(it.wc);
     if (task >= ntx * feat_tiles_y(it.hc)) return;
-    features_strip<PD_FEAT_HOG | PD_FEAT_LBP, ALIGNED, true>(it.pyr, it.w, it.h, it.pitch, it.hog, it.hog16, it.lbp,
-                                                             it.cmap, it.cmap16, task / ntx, task % ntx, FT_CH, clip,
-                                                             eps, sm, wave);
+    features_strip<PD_FEAT_HOG | PD_FEAT_LBP, ALIGNED, true>(
+        gmem(it.pyr), it.w, it.h, it.pitch, gmem(it.hog), gmem(it.hog16), gmem(it.lbp), gmem(it.cmap),
+        gmem(it.cmap16), task / ntx, task % ntx, FT_CH, clip, eps, sm, wave);
 }
 
 __global__ void __launch_bounds__(256) cellmap_table_kernel(const LevelItem* __restrict__ items,
@@ -557,9 +558,9 @@ __global__ void __launch_bounds__(256) cellmap_table_kernel(const LevelItem* __r
     for (int task = blockIdx.x * FT_WAVES + wave; task < n_tiles; task += gridDim.x * FT_WAVES) {
         const Tile tl = tiles[task];
         const LevelItem& it = items[tl.item];
-        features_strip<PD_FEAT_HOG | PD_FEAT_LBP, true, true>(it.pyr, it.w, it.h, it.pitch, it.hog, it.hog16, it.lbp,
-                                                              it.cmap, it.cmap16, tl.ty, tl.tx, ch, clip, eps, sm,
-                                                              wave);
+        features_strip<PD_FEAT_HOG | PD_FEAT_LBP, true, true>(gmem(it.pyr), it.w, it.h, it.pitch, gmem(it.hog),
+                                                              gmem(it.hog16), gmem(it.lbp), gmem(it.cmap),
+                                                              gmem(it.cmap16), tl.ty, tl.tx, ch, clip, eps, sm, wave);
     }
 }
 
@@ -577,8 +578,8 @@ __global__ void __launch_bounds__(256) features_table_kernel(const LevelItem* __
     for (int task = blockIdx.x * FT_WAVES + wave; task < n_tiles; task += gridDim.x * FT_WAVES) {
         const Tile tl = tiles[task];
         const LevelItem& it = items[tl.item];
-        features_strip<FEAT, true>(it.pyr, it.w, it.h, it.pitch, it.hog, it.hog16, it.lbp, nullptr, nullptr, tl.ty,
-                                   tl.tx, ch, clip, eps, sm, wave, tl.pad);
+        features_strip<FEAT, true>(gmem(it.pyr), it.w, it.h, it.pitch, gmem(it.hog), gmem(it.hog16), gmem(it.lbp),
+                                   nullptr, nullptr, tl.ty, tl.tx, ch, clip, eps, sm, wave, tl.pad);
     }
 }
 

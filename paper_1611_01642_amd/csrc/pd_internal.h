@@ -91,6 +91,23 @@ constexpr int MF_TILE_C = 64;
 
 __host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
+// Device buffers reached through tables in memory (LevelItem and the like)
+// are typed as global memory inside kernels: the compiler cannot infer the
+// address space of such pointers and would emit FLAT accesses, which also
+// count against the LDS wait counter and so stall LDS reads behind prefetches.
+// (The host pass of the same source sees plain pointers.)
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+#else
+template <typename T>
+using gptr = T*;
+#endif
+template <typename T>
+__device__ __forceinline__ gptr<T> gmem(T* p) {
+    return (gptr<T>)p;
+}
+
 // FP32 -> BF16, round to nearest even (finite inputs).
 __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
     uint32_t u = __float_as_uint(f);

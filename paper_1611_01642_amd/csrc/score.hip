@@ -36,8 +36,9 @@ constexpr int patch_floats() {
 }
 
 template <int FEAT, int R, int L = SC_W>
-__device__ __forceinline__ void score_tile(const float* __restrict__ hog, const uint8_t* __restrict__ lbp, int wc,
-                                           int hc, const float* __restrict__ wt, float bias, float* __restrict__ out,
+__device__ __forceinline__ void score_tile(gptr<const float> __restrict__ hog, gptr<const uint8_t> __restrict__ lbp,
+                                           int wc, int hc, const float* __restrict__ wt, float bias,
+                                           gptr<float> __restrict__ out,
                                            int ty, int tx, int lane, float* __restrict__ patch) {
     using PG = Patch<R, L>;
     constexpr int HOG_PR = PG::HOG_PR, HOG_PC = PG::HOG_PC, HOG_PQ = PG::HOG_PQ, HOG_N = PG::HOG_N;
@@ -68,7 +69,7 @@ __device__ __forceinline__ void score_tile(const float* __restrict__ hog, const 
             for (int q = 0; q < HOG_PQ; ++q)
                 if (lane + 64 * q < HOG_N) patch[lane + 64 * q] = pre[q];
             if (c + 1 < PD_HOG_BLOCK) {
-                const float* nxt = hog + (size_t)(c + 1) * plane;
+                const auto nxt = hog + (size_t)(c + 1) * plane;
 #pragma unroll
                 for (int q = 0; q < HOG_PQ; ++q) pre[q] = nxt[off[q]];
             }
@@ -110,7 +111,7 @@ __device__ __forceinline__ void score_tile(const float* __restrict__ hog, const 
             for (int q = 0; q < LBP_PQ; ++q)
                 if (lane + 64 * q < LBP_N) patch[lane + 64 * q] = (float)pre[q];
             if (c + 1 < PD_LBP_BINS) {
-                const uint8_t* nxt = lbp + (size_t)(c + 1) * plane;
+                const auto nxt = lbp + (size_t)(c + 1) * plane;
 #pragma unroll
                 for (int q = 0; q < LBP_PQ; ++q) pre[q] = nxt[off[q]];
             }
@@ -154,8 +155,8 @@ __global__ void __launch_bounds__(256) score_single_kernel(LevelItem it, const f
     if (wave >= per_model * n_models) return;
     const int m = wave / per_model;
     const int local = wave - m * per_model;
-    score_tile<FEAT, SC_R>(it.hog, it.lbp, it.wc, it.hc, wt + (size_t)m * PD_FEATURE_DIM, bias[m],
-                           it.scores + (size_t)m * it.ny * it.nx, local / ntx, local % ntx, threadIdx.x & 63,
+    score_tile<FEAT, SC_R>(gmem(it.hog), gmem(it.lbp), it.wc, it.hc, wt + (size_t)m * PD_FEATURE_DIM, bias[m],
+                           gmem(it.scores) + (size_t)m * it.ny * it.nx, local / ntx, local % ntx, threadIdx.x & 63,
                            patches[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)]);
 }
 
@@ -176,14 +177,16 @@ __global__ void __launch_bounds__(256) score_table_kernel(const LevelItem* __res
         const LevelItem& it = items[tl.item];
         const int m = tile_model(tl), width = tile_width(tl);
         const float* w = wt + (size_t)m * PD_FEATURE_DIM;
-        float* o = it.scores + (size_t)m * it.ny * it.nx;
+        const auto o = gmem(it.scores) + (size_t)m * it.ny * it.nx;
+        const auto hog = gmem(it.hog);
+        const auto lbp = gmem(it.lbp);
         const int lane = threadIdx.x & 63;
         if (width == 64)
-            score_tile<FEAT, R, 64>(it.hog, it.lbp, it.wc, it.hc, w, bias[m], o, tl.ty, tl.tx, lane, patches[wv]);
+            score_tile<FEAT, R, 64>(hog, lbp, it.wc, it.hc, w, bias[m], o, tl.ty, tl.tx, lane, patches[wv]);
         else if (width == 32)
-            score_tile<FEAT, R, 32>(it.hog, it.lbp, it.wc, it.hc, w, bias[m], o, tl.ty, tl.tx, lane, patches[wv]);
+            score_tile<FEAT, R, 32>(hog, lbp, it.wc, it.hc, w, bias[m], o, tl.ty, tl.tx, lane, patches[wv]);
         else
-            score_tile<FEAT, R, 16>(it.hog, it.lbp, it.wc, it.hc, w, bias[m], o, tl.ty, tl.tx, lane, patches[wv]);
+            score_tile<FEAT, R, 16>(hog, lbp, it.wc, it.hc, w, bias[m], o, tl.ty, tl.tx, lane, patches[wv]);
     };
     if constexpr (LOOP) {
         for (int wave = blockIdx.x * SC_WAVES + wv; wave < n_tiles; wave += gridDim.x * SC_WAVES) one(wave);
