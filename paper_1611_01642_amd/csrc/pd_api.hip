@@ -520,9 +520,11 @@ void fill_tables(const pd_frame* frames, int n_frames, int n_models, const Tunin
             it.level = k;
             geoms[f].wh[k][0] = it.w;
             geoms[f].wh[k][1] = it.h;
-            if (!direct)
-                for (int ty = 0; ty < resize_tiles_y(it.h); ++ty)
-                    for (int tx = 0; tx < resize_tiles_x(it.w); ++tx) t_rs[nrs++] = Tile{q, ty, tx, 0};
+            if (!direct) {  // tiles of `rows` rows (at least RS_TY: within the capacity counted above)
+                const int rows = resize_rows(it.w, it.h, it.src_w, it.src_h);
+                for (int y = 0; y < it.h; y += rows)
+                    for (int tx = 0; tx < resize_tiles_x(it.w); ++tx) t_rs[nrs++] = Tile{q, y, tx, rows};
+            }
             const int fty = feat_tiles_y(it.hc, tu.feat_rows);
             if (L.prune) {
                 for (int ty = 0; ty < fty; ++ty)

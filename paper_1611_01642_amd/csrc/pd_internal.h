@@ -69,8 +69,10 @@ struct NmsGeom {
 
 // ---- tile shapes ---------------------------------------------------------
 // resize: 64 lanes x 4 pixels wide, 16 rows
-constexpr int RS_TX = 256;   // pixels per tile row
-constexpr int RS_TY = 16;    // rows per tile
+constexpr int RS_TX = 256;      // pixels per tile row
+constexpr int RS_TY = 16;       // rows per tile (single-image launches; the least in tables)
+constexpr int RS_TY_MAX = 128;  // rows per tile in tables
+constexpr int RS_LDS = 36 * 1024;  // staged source bytes per resize workgroup
 // features: one wave = a strip of 64 cell columns (one per lane) walking
 // down FT_CH block rows (+1 overlap cell row); it owns 63 block columns
 constexpr int FT_W = 64;
@@ -117,6 +119,17 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
 
 __host__ __device__ inline int resize_tiles_x(int w) { return ceil_div(w, RS_TX); }
 __host__ __device__ inline int resize_tiles_y(int h) { return ceil_div(h, RS_TY); }
+// Rows per resize tile of a w x h level sampled from a sw x sh image: as many
+// (a multiple of 4, RS_TY..RS_TY_MAX) as keep the tile's source rectangle
+// within the staging buffer, so that levels near full scale run few, tall tiles.
+inline int resize_rows(int w, int h, int sw, int sh) {
+    const double sx = (double)sw / w, sy = (double)sh / h;
+    const double row_bytes = (RS_TX - 1) * sx + 12.0;  // source span of a tile row + alignment slack
+    const double src_rows = RS_LDS / row_bytes - 3.0;
+    int rows = (int)(src_rows / sy) + 1;
+    rows = rows / 4 * 4;
+    return rows < RS_TY ? RS_TY : (rows > RS_TY_MAX ? RS_TY_MAX : rows);
+}
 __host__ __device__ inline int feat_tiles_x(int wc) { return wc <= 1 ? 1 : ceil_div(wc - 1, FT_BX); }
 // Strips that also emit the pruner cell map own 62 columns: every owned cell
 // needs both neighbours in the same wave.

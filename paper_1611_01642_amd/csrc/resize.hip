@@ -20,29 +20,23 @@ __device__ inline uint32_t q8_coord(int x, int n0, int nk) {
     return (uint32_t)s;  // index = s >> 8, fraction = s & 255
 }
 
-constexpr int RS_LDS = 36 * 1024;  // staged source bytes per workgroup (scale factors up to ~2.9)
-constexpr int RS_BATCH = 8;        // loads in flight per thread while staging
+constexpr int RS_BATCH = 16;  // loads in flight per thread while staging
 
-__device__ __forceinline__ uint32_t blend(int p00, int p01, int p10, int p11, int fx, int fy) {
-    const int acc = (256 - fx) * (256 - fy) * p00 + fx * (256 - fy) * p01 + (256 - fx) * fy * p10 + fx * fy * p11 +
-                    (1 << 15);
-    return (uint32_t)(acc >> 16);
-}
-
-__device__ void resize_tile(const uint8_t* __restrict__ src, int sw, int sh, int spitch,
-                            uint8_t* __restrict__ dst, int w, int h, int pitch, int ty, int tx) {
+// Output rows y_base .. y_base + rows - 1 (rows <= RS_TY_MAX), columns
+// tx * RS_TX .. + RS_TX - 1.
+__device__ void resize_tile(gptr<const uint8_t> __restrict__ src, int sw, int sh, int spitch,
+                            gptr<uint8_t> __restrict__ dst, int w, int h, int pitch, int y_base, int rows, int tx) {
     __shared__ uint32_t xs[RS_TX];
-    __shared__ uint32_t ys[RS_TY];
+    __shared__ uint32_t ys[RS_TY_MAX];
     __shared__ __attribute__((aligned(16))) uint8_t stage[RS_LDS];
     const int t = threadIdx.x;
     const int x_base = tx * RS_TX;
-    const int y_base = ty * RS_TY;
     if (x_base + t < w) xs[t] = q8_coord(x_base + t, sw, w);
-    if (t < RS_TY && y_base + t < h) ys[t] = q8_coord(y_base + t, sh, h);
+    if (t < rows && y_base + t < h) ys[t] = q8_coord(y_base + t, sh, h);
     __syncthreads();
 
     // source rectangle of the tile: rows sy0..sy1, columns sx0..sx1
-    const int xe = min(x_base + RS_TX, w) - 1 - x_base, ye = min(y_base + RS_TY, h) - 1 - y_base;
+    const int xe = min(x_base + RS_TX, w) - 1 - x_base, ye = min(y_base + rows, h) - 1 - y_base;
     const int sx0 = (int)(xs[0] >> 8), sx1 = min((int)(xs[xe] >> 8) + 1, sw - 1);
     const int sy0 = (int)(ys[0] >> 8), sy1 = min((int)(ys[ye] >> 8) + 1, sh - 1);
     const int nrow = sy1 - sy0 + 1;
@@ -58,11 +52,11 @@ __device__ void resize_tile(const uint8_t* __restrict__ src, int sw, int sh, int
             for (int k = 0; k < RS_BATCH; ++k) {
                 const int e = base + t + 256 * k;
                 const int r = e / span_w, wd = e - r * span_w;
-                const uintptr_t a0 = reinterpret_cast<uintptr_t>(src + (size_t)(sy0 + r) * spitch + sx0);
-                const uintptr_t al = a0 & ~(uintptr_t)3;
+                const auto p0 = src + (size_t)(sy0 + r) * spitch + sx0;
+                const int mis = (int)(reinterpret_cast<uintptr_t>(p0) & 3);
                 v[k] = 0u;
-                if (e < n && 4 * (uintptr_t)wd <= (a0 - al) + (uintptr_t)(sx1 - sx0))
-                    v[k] = *reinterpret_cast<const uint32_t*>(al + 4 * wd);
+                if (e < n && 4 * wd <= mis + (sx1 - sx0))
+                    v[k] = *reinterpret_cast<gptr<const uint32_t>>(p0 - mis + 4 * wd);
             }
 #pragma unroll
             for (int k = 0; k < RS_BATCH; ++k) {
@@ -77,45 +71,47 @@ __device__ void resize_tile(const uint8_t* __restrict__ src, int sw, int sh, int
     const int wave = t >> 6;
     const int x0 = x_base + 4 * lane;
     if (x0 >= w) return;
-    for (int r = wave; r < RS_TY; r += 4) {
+    // this lane's four columns, once per tile: taps and weights (a column past
+    // the edge repeats the last one; its byte is masked off)
+    int xa[4], xb[4], wx[4];
+    uint32_t keep = 0u;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const uint32_t sx = xs[min(x0 + q, w - 1) - x_base];
+        xa[q] = (int)(sx >> 8);
+        wx[q] = (int)(sx & 255);
+        xb[q] = min(xa[q] + 1, sw - 1);
+        if (x0 + q < w) keep |= 255u << (8 * q);
+    }
+    // (256-fx)(256-fy) p00 + fx (256-fy) p01 + (256-fx) fy p10 + fx fy p11,
+    // + 2^15, >> 16, grouped by row (the same integer)
+    auto pack4 = [&](auto ra, auto rb, int fy) -> uint32_t {
+        uint32_t packed = 0u;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int top = (256 - wx[q]) * (int)ra[xa[q]] + wx[q] * (int)ra[xb[q]];
+            const int bot = (256 - wx[q]) * (int)rb[xa[q]] + wx[q] * (int)rb[xb[q]];
+            packed |= (uint32_t)(((256 - fy) * top + fy * bot + (1 << 15)) >> 16) << (8 * q);
+        }
+        return packed & keep;
+    };
+    for (int r = wave; r < rows; r += 4) {
         const int y = y_base + r;
         if (y >= h) break;
         const uint32_t sy = ys[r];
         const int ya = (int)(sy >> 8);
         const int fy = (int)(sy & 255);
         const int yb = min(ya + 1, sh - 1);
-        uint32_t packed = 0;
+        uint32_t packed;
         if (staged) {
             const int oa = (int)(reinterpret_cast<uintptr_t>(src + (size_t)ya * spitch + sx0) & 3);
             const int ob = (int)(reinterpret_cast<uintptr_t>(src + (size_t)yb * spitch + sx0) & 3);
-            const uint8_t* ra = stage + (ya - sy0) * span_w * 4 + oa - sx0;
-            const uint8_t* rb = stage + (yb - sy0) * span_w * 4 + ob - sx0;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int x = x0 + q;
-                if (x < w) {
-                    const uint32_t sx = xs[4 * lane + q];
-                    const int xa = (int)(sx >> 8), fx = (int)(sx & 255);
-                    const int xb = min(xa + 1, sw - 1);
-                    packed |= blend(ra[xa], ra[xb], rb[xa], rb[xb], fx, fy) << (8 * q);
-                }
-            }
+            packed = pack4(stage + (ya - sy0) * span_w * 4 + oa - sx0, stage + (yb - sy0) * span_w * 4 + ob - sx0, fy);
         } else {
-            const uint8_t* ra = src + (size_t)ya * spitch;
-            const uint8_t* rb = src + (size_t)yb * spitch;
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int x = x0 + q;
-                if (x < w) {
-                    const uint32_t sx = xs[4 * lane + q];
-                    const int xa = (int)(sx >> 8), fx = (int)(sx & 255);
-                    const int xb = min(xa + 1, sw - 1);
-                    packed |= blend(ra[xa], ra[xb], rb[xa], rb[xb], fx, fy) << (8 * q);
-                }
-            }
+            packed = pack4(src + (size_t)ya * spitch, src + (size_t)yb * spitch, fy);
         }
         // pitch is a multiple of 16 >= w, so the 4-byte store stays in the row
-        *reinterpret_cast<uint32_t*>(dst + (size_t)y * pitch + x0) = packed;
+        *reinterpret_cast<gptr<uint32_t>>(dst + (size_t)y * pitch + x0) = packed;
     }
 }
 
@@ -134,15 +130,17 @@ __global__ void __launch_bounds__(256) resize_single_kernel(ResizeArgs a) {
     while (k + 1 < a.n && a.prefix[k + 1] <= b) ++k;
     const int local = b - a.prefix[k];
     const int ntx = (a.w[k] + RS_TX - 1) / RS_TX;
-    resize_tile(a.src, a.sw, a.sh, a.spitch, a.dst + a.off[k], a.w[k], a.h[k], a.pitch[k],
-                local / ntx, local % ntx);
+    resize_tile(gmem(a.src), a.sw, a.sh, a.spitch, gmem(a.dst) + a.off[k], a.w[k], a.h[k], a.pitch[k],
+                (local / ntx) * RS_TY, RS_TY, local % ntx);
 }
 
 __global__ void __launch_bounds__(256) resize_table_kernel(const LevelItem* __restrict__ items,
                                                            const Tile* __restrict__ tiles) {
     const Tile tl = tiles[blockIdx.x];
     const LevelItem& it = items[tl.item];
-    resize_tile(it.src, it.src_w, it.src_h, it.src_pitch, it.pyr, it.w, it.h, it.pitch, tl.ty, tl.tx);
+    // tile: first row in ty, row count in pad
+    resize_tile(gmem(it.src), it.src_w, it.src_h, it.src_pitch, gmem(it.pyr), it.w, it.h, it.pitch, tl.ty, tl.pad,
+                tl.tx);
 }
 
 }  // namespace
