@@ -460,6 +460,7 @@ struct DetectRun {
     const LevelItem* items = nullptr;
     const Tile *t_rs = nullptr, *t_ft = nullptr, *t_sc = nullptr, *t_cp = nullptr;
     int nrs = 0, nft = 0, nsc = 0, ncp = 0;  // tiles in use
+    int nsc_half = 0;  // FP32 score tiles of half height, stored after the nsc others
     const NmsGeom* geoms = nullptr;
     const int32_t* first = nullptr;
     int32_t* counters = nullptr;
@@ -494,6 +495,7 @@ void fill_tables(const pd_frame* frames, int n_frames, int n_models, const Tunin
     Tile* t_cp = t_sc + L.n_sc;
     Tile* t_pr = t_cp + L.n_cp;
     int q = 0, nrs = 0, nft = 0, nsc = 0, ncp = 0, npr = 0;
+    std::vector<Tile> half;  // FP32 score tiles of half height, appended after the others
     for (int f = 0; f < n_frames; ++f) {
         geoms[f].n_levels = L.level_count[f];
         first[f] = q;
@@ -563,17 +565,28 @@ void fill_tables(const pd_frame* frames, int n_frames, int n_models, const Tunin
                 const int nty = score_tiles_y(it.ny, tu.score_rows);
                 const int full = it.nx / SC_W, tail = it.nx - full * SC_W;
                 const int width = tail > 32 ? 64 : (tail > 16 ? 32 : 16);
+                // a tile covering only the level's last row chunk, with at most
+                // half of its rows valid, goes to the half-height list (not
+                // with pruning: the kept list is scored by one launch)
+                const int sr = tu.score_rows;
+                auto add = [&](const Tile& t, int groups) {
+                    const bool single = std::min(t.ty + groups, nty) - 1 == t.ty;
+                    if (!L.prune && sr > 4 && single && it.ny - t.ty * sr <= sr / 2) half.push_back(t);
+                    else t_sc[nsc++] = t;
+                };
                 for (int m = 0; m < n_models; ++m) {
                     for (int ty = 0; ty < nty; ++ty)
-                        for (int tx = 0; tx < full; ++tx) t_sc[nsc++] = Tile{q, ty, tx, score_pad(m, 64)};
+                        for (int tx = 0; tx < full; ++tx) add(Tile{q, ty, tx, score_pad(m, 64)}, 1);
                     if (tail > 0)
                         for (int ty = 0; ty < nty; ty += SC_W / width)
-                            t_sc[nsc++] = Tile{q, ty, full, score_pad(m, width)};
+                            add(Tile{q, ty, full, score_pad(m, width)}, SC_W / width);
                 }
             }
             for (int c = 0; c < ceil_div(it.nx * it.ny, CP_N); ++c) t_cp[ncp++] = Tile{q, 0, c, 0};
         }
     }
+    R.nsc_half = (int)half.size();  // within capacity: one tile each, as without the split
+    for (int k = 0; k < R.nsc_half; ++k) t_sc[nsc + k] = half[k];
     const Tile* d_tiles = reinterpret_cast<const Tile*>(ws + L.off_tiles);
     R.items = reinterpret_cast<const LevelItem*>(ws + L.off_items);
     R.t_rs = d_tiles;
@@ -682,7 +695,7 @@ int enqueue_detect(const DetectRun& R, const DetectLayout& L, const Tuning& tu, 
                              "bf16 score")))
             return rc;
     } else if ((rc = hip_status(launch_score_table(R.items, R.t_sc, R.nsc, weights, bias, n_models,
-                                                   params->features, tu, s),
+                                                   params->features, tu, s, nullptr, R.nsc_half),
                                 "score"))) {
         return rc;
     }

@@ -163,10 +163,12 @@ hipError_t launch_features_cellmap_table(const LevelItem* items, const Tile* til
 
 hipError_t launch_score_single(const LevelItem& it, const float* w, const float* bias, int n_models,
                                int features, hipStream_t s);
-// n_dev (optional): the tile count is read from device memory (at most n_tiles)
+// n_dev (optional): the tile count is read from device memory (at most n_tiles).
+// n_half tiles after the n_tiles (rows 8 or 16 only) have at most half the
+// rows valid and compute only those.
 hipError_t launch_score_table(const LevelItem* items, const Tile* tiles, int n_tiles,
                               const float* w, const float* bias, int n_models, int features,
-                              const Tuning& tu, hipStream_t s, const int* n_dev = nullptr);
+                              const Tuning& tu, hipStream_t s, const int* n_dev = nullptr, int n_half = 0);
 
 int64_t packed_weight_elems();
 int64_t rowgemm_packed_elems();

@@ -35,7 +35,9 @@ constexpr int patch_floats() {
     return a > b ? (a > c ? a : c) : (b > c ? b : c);
 }
 
-template <int FEAT, int R, int L = SC_W>
+// R window rows per lane from row (ty + group) * STEP: a tile laid out on a
+// grid of STEP rows whose valid rows fit in R < STEP computes only those.
+template <int FEAT, int R, int L = SC_W, int STEP = R>
 __device__ __forceinline__ void score_tile(gptr<const float> __restrict__ hog, gptr<const uint8_t> __restrict__ lbp,
                                            int wc, int hc, const float* __restrict__ wt, float bias,
                                            gptr<float> __restrict__ out,
@@ -59,7 +61,7 @@ __device__ __forceinline__ void score_tile(gptr<const float> __restrict__ hog, g
             const int e = min(lane + 64 * q, HOG_N - 1);
             const int gq = e / (HOG_PR * HOG_PC), rem = e - gq * (HOG_PR * HOG_PC);
             const int row = rem / HOG_PC, col = rem - (rem / HOG_PC) * HOG_PC;
-            off[q] = min((ty + gq) * R + row, hb - 1) * wb + min(j0 + col, wb - 1);
+            off[q] = min((ty + gq) * STEP + row, hb - 1) * wb + min(j0 + col, wb - 1);
         }
         float pre[HOG_PQ];
 #pragma unroll
@@ -74,6 +76,7 @@ __device__ __forceinline__ void score_tile(gptr<const float> __restrict__ hog, g
                 for (int q = 0; q < HOG_PQ; ++q) pre[q] = nxt[off[q]];
             }
             __builtin_amdgcn_wave_barrier();
+#pragma unroll 1
             for (int b = 0; b < PD_WIN_BLOCKS_X; ++b) {
                 float wa[PD_WIN_BLOCKS_Y];
 #pragma unroll
@@ -101,7 +104,7 @@ __device__ __forceinline__ void score_tile(gptr<const float> __restrict__ hog, g
             const int e = min(lane + 64 * q, LBP_N - 1);
             const int gq = e / (LBP_PR * LBP_PC), rem = e - gq * (LBP_PR * LBP_PC);
             const int row = rem / LBP_PC, col = rem - (rem / LBP_PC) * LBP_PC;
-            off[q] = min((ty + gq) * R + row, hc - 1) * wc + min(j0 + col, wc - 1);
+            off[q] = min((ty + gq) * STEP + row, hc - 1) * wc + min(j0 + col, wc - 1);
         }
         uint32_t pre[LBP_PQ];
 #pragma unroll
@@ -116,6 +119,7 @@ __device__ __forceinline__ void score_tile(gptr<const float> __restrict__ hog, g
                 for (int q = 0; q < LBP_PQ; ++q) pre[q] = nxt[off[q]];
             }
             __builtin_amdgcn_wave_barrier();
+#pragma unroll 1
             for (int b = 0; b < PD_WIN_CELLS_X; ++b) {
                 float wa[PD_WIN_CELLS_Y];
 #pragma unroll
@@ -134,7 +138,7 @@ __device__ __forceinline__ void score_tile(gptr<const float> __restrict__ hog, g
             __builtin_amdgcn_wave_barrier();
         }
     }
-    const int i0 = (ty + g) * R;
+    const int i0 = (ty + g) * STEP;
     const int j = j0 + li;
     if (j < nx) {
 #pragma unroll
@@ -163,16 +167,20 @@ __global__ void __launch_bounds__(256) score_single_kernel(LevelItem it, const f
 // Tiles of R window rows (pad: model and lane-group width).  Waves are
 // independent; with LOOP a capped grid strides over the table (a separate
 // instantiation: the loop costs registers the one-tile form does not need).
+// Without LOOP, the n_half tiles stored after the n_tiles have at most R / 2
+// valid rows: the blocks past those of the n_tiles compute only R / 2 rows
+// for them (LOOP computes all R rows of every tile: also correct, since rows
+// past the level are not stored).
 template <int FEAT, int R, bool LOOP>
 __global__ void __launch_bounds__(256) score_table_kernel(const LevelItem* __restrict__ items,
                                                           const Tile* __restrict__ tiles, int n_tiles,
                                                           const float* __restrict__ wt,
                                                           const float* __restrict__ bias,
-                                                          const int* __restrict__ n_dev) {
+                                                          const int* __restrict__ n_dev, int n_half) {
     __shared__ float patches[SC_WAVES][patch_floats<R>()];
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (n_dev) n_tiles = min(n_tiles, *n_dev);
-    auto one = [&](int wave) __attribute__((always_inline)) {
+    auto one = [&](int wave, auto r_tag) __attribute__((always_inline)) {
+        constexpr int RR = decltype(r_tag)::value;
         const Tile tl = tiles[wave];
         const LevelItem& it = items[tl.item];
         const int m = tile_model(tl), width = tile_width(tl);
@@ -182,17 +190,28 @@ __global__ void __launch_bounds__(256) score_table_kernel(const LevelItem* __res
         const auto lbp = gmem(it.lbp);
         const int lane = threadIdx.x & 63;
         if (width == 64)
-            score_tile<FEAT, R, 64>(hog, lbp, it.wc, it.hc, w, bias[m], o, tl.ty, tl.tx, lane, patches[wv]);
+            score_tile<FEAT, RR, 64, R>(hog, lbp, it.wc, it.hc, w, bias[m], o, tl.ty, tl.tx, lane, patches[wv]);
         else if (width == 32)
-            score_tile<FEAT, R, 32>(hog, lbp, it.wc, it.hc, w, bias[m], o, tl.ty, tl.tx, lane, patches[wv]);
+            score_tile<FEAT, RR, 32, R>(hog, lbp, it.wc, it.hc, w, bias[m], o, tl.ty, tl.tx, lane, patches[wv]);
         else
-            score_tile<FEAT, R, 16>(hog, lbp, it.wc, it.hc, w, bias[m], o, tl.ty, tl.tx, lane, patches[wv]);
+            score_tile<FEAT, RR, 16, R>(hog, lbp, it.wc, it.hc, w, bias[m], o, tl.ty, tl.tx, lane, patches[wv]);
     };
     if constexpr (LOOP) {
-        for (int wave = blockIdx.x * SC_WAVES + wv; wave < n_tiles; wave += gridDim.x * SC_WAVES) one(wave);
+        const int n = (n_dev ? min(n_tiles, *n_dev) : n_tiles) + n_half;
+        for (int wave = blockIdx.x * SC_WAVES + wv; wave < n; wave += gridDim.x * SC_WAVES)
+            one(wave, std::integral_constant<int, R>());
     } else {
+        const int main_blocks = ceil_div(n_tiles, SC_WAVES);  // before the device count applies
+        if constexpr (R > 4) {
+            if ((int)blockIdx.x >= main_blocks) {
+                const int t = ((int)blockIdx.x - main_blocks) * SC_WAVES + wv;
+                if (t < n_half) one(n_tiles + t, std::integral_constant<int, R / 2>());
+                return;
+            }
+        }
+        if (n_dev) n_tiles = min(n_tiles, *n_dev);
         const int wave = blockIdx.x * SC_WAVES + wv;
-        if (wave < n_tiles) one(wave);
+        if (wave < n_tiles) one(wave, std::integral_constant<int, R>());
     }
 }
 
@@ -205,21 +224,22 @@ hipError_t score_single(const LevelItem& it, const float* w, const float* b, int
 
 template <int FEAT, int R>
 void launch_rows(bool loop, int grid, const LevelItem* items, const Tile* tiles, int n, const float* w,
-                 const float* b, const int* nd, hipStream_t s) {
-    if (loop) score_table_kernel<FEAT, R, true><<<grid, 256, 0, s>>>(items, tiles, n, w, b, nd);
-    else score_table_kernel<FEAT, R, false><<<grid, 256, 0, s>>>(items, tiles, n, w, b, nd);
+                 const float* b, const int* nd, int n_half, hipStream_t s) {
+    if (loop) score_table_kernel<FEAT, R, true><<<grid, 256, 0, s>>>(items, tiles, n, w, b, nd, n_half);
+    else score_table_kernel<FEAT, R, false><<<grid, 256, 0, s>>>(items, tiles, n, w, b, nd, n_half);
 }
 
 template <int FEAT>
 hipError_t score_table(const LevelItem* items, const Tile* tiles, int n, const float* w, const float* b,
-                       const Tuning& tu, hipStream_t s, const int* nd) {
+                       const Tuning& tu, hipStream_t s, const int* nd, int n_half) {
     const int rows = tu.score_rows;
-    const int blocks = ceil_div(n, SC_WAVES);
+    if (rows == 4) n_half = 0;  // none are made for 4 rows
+    const int blocks = ceil_div(n, SC_WAVES) + ceil_div(n_half, SC_WAVES);
     const bool loop = tu.grid > 0 && tu.grid < blocks;
     const int grid = loop ? tu.grid : blocks;
-    if (rows == 16) launch_rows<FEAT, 16>(loop, grid, items, tiles, n, w, b, nd, s);
-    else if (rows == 4) launch_rows<FEAT, 4>(loop, grid, items, tiles, n, w, b, nd, s);
-    else launch_rows<FEAT, SC_R>(loop, grid, items, tiles, n, w, b, nd, s);
+    if (rows == 16) launch_rows<FEAT, 16>(loop, grid, items, tiles, n, w, b, nd, n_half, s);
+    else if (rows == 4) launch_rows<FEAT, 4>(loop, grid, items, tiles, n, w, b, nd, 0, s);
+    else launch_rows<FEAT, SC_R>(loop, grid, items, tiles, n, w, b, nd, n_half, s);
     return hipGetLastError();
 }
 
@@ -237,13 +257,13 @@ hipError_t launch_score_single(const LevelItem& it, const float* w, const float*
 
 hipError_t launch_score_table(const LevelItem* items, const Tile* tiles, int n_tiles, const float* w,
                               const float* bias, int n_models, int features, const Tuning& tu, hipStream_t s,
-                              const int* n_dev) {
+                              const int* n_dev, int n_half) {
     (void)n_models;
-    if (n_tiles <= 0) return hipSuccess;
+    if (n_tiles <= 0 && n_half <= 0) return hipSuccess;
     switch (features & (PD_FEAT_HOG | PD_FEAT_LBP)) {
-        case PD_FEAT_HOG: return score_table<PD_FEAT_HOG>(items, tiles, n_tiles, w, bias, tu, s, n_dev);
-        case PD_FEAT_LBP: return score_table<PD_FEAT_LBP>(items, tiles, n_tiles, w, bias, tu, s, n_dev);
-        default: return score_table<PD_FEAT_HOG | PD_FEAT_LBP>(items, tiles, n_tiles, w, bias, tu, s, n_dev);
+        case PD_FEAT_HOG: return score_table<PD_FEAT_HOG>(items, tiles, n_tiles, w, bias, tu, s, n_dev, n_half);
+        case PD_FEAT_LBP: return score_table<PD_FEAT_LBP>(items, tiles, n_tiles, w, bias, tu, s, n_dev, n_half);
+        default: return score_table<PD_FEAT_HOG | PD_FEAT_LBP>(items, tiles, n_tiles, w, bias, tu, s, n_dev, n_half);
     }
 }
 
