@@ -67,12 +67,15 @@ struct NmsGeom {
     int32_t wh[PD_MAX_LEVELS][2];
 };
 
+// XCDs (chiplets with their own L2) that workgroups are dealt to, round-robin
+constexpr int N_XCD = 8;
+
 // ---- tile shapes ---------------------------------------------------------
 // resize: 64 lanes x 4 pixels wide, 16 rows
 constexpr int RS_TX = 256;      // pixels per tile row
 constexpr int RS_TY = 16;       // rows per tile (single-image launches; the least in tables)
 constexpr int RS_TY_MAX = 128;  // rows per tile in tables
-constexpr int RS_LDS = 36 * 1024;  // staged source bytes per resize workgroup
+constexpr int RS_LDS = 20 * 1024;  // staged source bytes per resize workgroup (7 workgroups per CU)
 // features: one wave = a strip of 64 cell columns (one per lane) walking
 // down FT_CH block rows (+1 overlap cell row); it owns 63 block columns
 constexpr int FT_W = 64;

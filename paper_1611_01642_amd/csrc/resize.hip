@@ -1,10 +1,10 @@
 // Pyramid resize (Section 4.1 step 2, Section 4.4): every level is resampled
 // from the level-0 image with pixel-centre-aligned bilinear interpolation in
 // Q8 fixed point, rounded half up.  All arithmetic is integer, so results are
-// exact.  One workgroup writes a 256 x 16 pixel tile of one level; the Q8
-// coordinates of the tile's columns and rows are computed once per tile in
-// LDS (they need a 64-bit division), and the source rectangle the tile reads
-// is staged in LDS with coalesced word loads, so the four taps of every
+// exact.  One workgroup writes a tile of 256 columns x 16..128 rows of one
+// level; the Q8 coordinates of the tile's columns and rows are computed once
+// per tile in LDS, and the source rectangle the tile reads is staged in LDS
+// with coalesced word loads, whole rows per pass, so the four taps of every
 // output pixel are LDS reads (tiles whose rectangle does not fit read the
 // taps from global memory instead).
 #include "pd_internal.h"
@@ -13,18 +13,22 @@ namespace pd {
 namespace {
 
 // Q8 source coordinate of output sample `x` along an axis of n0 -> nk
-// samples: ((2x + 1) n0 - nk) * 128 / nk, split into index and fraction.
+// samples: ((2x + 1) n0 - nk) * 128 / nk, the integer quotient truncated,
+// split into index (s >> 8) and fraction (s & 255).  Taken in double: the
+// numerator (|num| < 2^39) and divisor convert exactly, and a quotient that is
+// not an integer lies at least 1 / nk from one, far more than the rounding of
+// the division (below |num / nk| 2^-53), so truncating the rounded quotient
+// gives the integer quotient.
 __device__ inline uint32_t q8_coord(int x, int n0, int nk) {
-    int64_t num = (int64_t)(2 * x + 1) * n0 - nk;
-    int64_t s = (num * 128) / nk;
-    return (uint32_t)s;  // index = s >> 8, fraction = s & 255
+    const int64_t num = ((int64_t)(2 * x + 1) * n0 - nk) * 128;
+    return (uint32_t)(int64_t)__builtin_trunc((double)num / (double)nk);
 }
 
-constexpr int RS_BATCH = 16;  // loads in flight per thread while staging
+constexpr int RS_BATCH = 8;  // loads in flight per thread while staging
 
 // Output rows y_base .. y_base + rows - 1 (rows <= RS_TY_MAX), columns
 // tx * RS_TX .. + RS_TX - 1.
-__device__ void resize_tile(gptr<const uint8_t> __restrict__ src, int sw, int sh, int spitch,
+__device__ __forceinline__ void resize_tile(gptr<const uint8_t> __restrict__ src, int sw, int sh, int spitch,
                             gptr<uint8_t> __restrict__ dst, int w, int h, int pitch, int y_base, int rows, int tx) {
     __shared__ uint32_t xs[RS_TX];
     __shared__ uint32_t ys[RS_TY_MAX];
@@ -41,27 +45,30 @@ __device__ void resize_tile(gptr<const uint8_t> __restrict__ src, int sw, int sh
     const int sy0 = (int)(ys[0] >> 8), sy1 = min((int)(ys[ye] >> 8) + 1, sh - 1);
     const int nrow = sy1 - sy0 + 1;
     const int span_w = (sx1 - sx0 + 7) / 4;  // aligned words per row, whatever the row's alignment
-    const bool staged = nrow * span_w * 4 <= RS_LDS;  // uniform over the workgroup
+    const bool staged = span_w <= 256 && nrow * span_w * 4 <= RS_LDS;  // uniform over the workgroup
     if (staged) {
-        // coalesced aligned words; a word is loaded only if it holds a byte of
-        // the rectangle (so it never leaves the pages of the image)
-        const int n = nrow * span_w;
-        for (int base = 0; base < n; base += 256 * RS_BATCH) {
-            uint32_t v[RS_BATCH];
+        // coalesced aligned words, K whole rows per pass: thread t takes word
+        // wd of rows r0, r0 + K, ...; a word is loaded only if it holds a byte
+        // of the rectangle (so it never leaves the pages of the image)
+        const int K = 256 / span_w;
+        const int r0 = t / span_w, wd = t - r0 * span_w;
+        if (r0 < K) {
+            for (int rb = r0; rb < nrow; rb += K * RS_BATCH) {
+                uint32_t v[RS_BATCH];
 #pragma unroll
-            for (int k = 0; k < RS_BATCH; ++k) {
-                const int e = base + t + 256 * k;
-                const int r = e / span_w, wd = e - r * span_w;
-                const auto p0 = src + (size_t)(sy0 + r) * spitch + sx0;
-                const int mis = (int)(reinterpret_cast<uintptr_t>(p0) & 3);
-                v[k] = 0u;
-                if (e < n && 4 * wd <= mis + (sx1 - sx0))
-                    v[k] = *reinterpret_cast<gptr<const uint32_t>>(p0 - mis + 4 * wd);
-            }
+                for (int k = 0; k < RS_BATCH; ++k) {
+                    const int r = rb + K * k;
+                    const auto p0 = src + (size_t)(sy0 + min(r, nrow - 1)) * spitch + sx0;
+                    const int mis = (int)(reinterpret_cast<uintptr_t>(p0) & 3);
+                    v[k] = 0u;
+                    if (r < nrow && 4 * wd <= mis + (sx1 - sx0))
+                        v[k] = *reinterpret_cast<gptr<const uint32_t>>(p0 - mis + 4 * wd);
+                }
 #pragma unroll
-            for (int k = 0; k < RS_BATCH; ++k) {
-                const int e = base + t + 256 * k;
-                if (e < n) *reinterpret_cast<uint32_t*>(stage + 4 * e) = v[k];
+                for (int k = 0; k < RS_BATCH; ++k) {
+                    const int r = rb + K * k;
+                    if (r < nrow) *reinterpret_cast<uint32_t*>(stage + 4 * (r * span_w + wd)) = v[k];
+                }
             }
         }
         __syncthreads();
@@ -134,9 +141,15 @@ __global__ void __launch_bounds__(256) resize_single_kernel(ResizeArgs a) {
                 (local / ntx) * RS_TY, RS_TY, local % ntx);
 }
 
+// Workgroups are dealt to the XCDs round-robin; each XCD takes a contiguous
+// run of the table instead, so the levels of a frame, which all read the same
+// source image, mostly share one XCD's L2.
 __global__ void __launch_bounds__(256) resize_table_kernel(const LevelItem* __restrict__ items,
-                                                           const Tile* __restrict__ tiles) {
-    const Tile tl = tiles[blockIdx.x];
+                                                           const Tile* __restrict__ tiles, int n_tiles) {
+    const int run = (n_tiles + N_XCD - 1) / N_XCD;
+    const int t = (int)(blockIdx.x % N_XCD) * run + (int)(blockIdx.x / N_XCD);
+    if (t >= n_tiles) return;
+    const Tile tl = tiles[t];
     const LevelItem& it = items[tl.item];
     // tile: first row in ty, row count in pad
     resize_tile(gmem(it.src), it.src_w, it.src_h, it.src_pitch, gmem(it.pyr), it.w, it.h, it.pitch, tl.ty, tl.pad,
@@ -170,7 +183,7 @@ hipError_t launch_resize_single(const LevelItem* items, int n_items, hipStream_t
 
 hipError_t launch_resize_table(const LevelItem* items, const Tile* tiles, int n_tiles, hipStream_t s) {
     if (n_tiles <= 0) return hipSuccess;
-    resize_table_kernel<<<n_tiles, 256, 0, s>>>(items, tiles);
+    resize_table_kernel<<<N_XCD * ((n_tiles + N_XCD - 1) / N_XCD), 256, 0, s>>>(items, tiles, n_tiles);
     return hipGetLastError();
 }
 
