@@ -517,12 +517,14 @@ __device__ __forceinline__ void features_strip(gptr<const uint8_t> __restrict__ 
 // Indexed by the bit-reversed code that lbp_codes4 produces.
 template <bool CM>
 __device__ inline void init_lut(FeatShared<CM>& sm) {
-    const int b = kLbp.bin[__brev(threadIdx.x) >> 24];
-    sm.lut[threadIdx.x] = ((1u << (8 * (b & 3))) << 7) | (uint32_t)(b >> 2);
+    for (int c = threadIdx.x; c < 256; c += FT_WAVES * 64) {
+        const int b = kLbp.bin[__brev(c) >> 24];
+        sm.lut[c] = ((1u << (8 * (b & 3))) << 7) | (uint32_t)(b >> 2);
+    }
 }
 
 template <int FEAT, bool ALIGNED>
-__global__ void __launch_bounds__(256) features_single_kernel(LevelItem it, float clip, float eps) {
+__global__ void __launch_bounds__(FT_WAVES * 64) features_single_kernel(LevelItem it, float clip, float eps) {
     __shared__ FeatShared<false> sm;
     init_lut(sm);
     __syncthreads();
@@ -535,7 +537,7 @@ __global__ void __launch_bounds__(256) features_single_kernel(LevelItem it, floa
 }
 
 template <bool ALIGNED>
-__global__ void __launch_bounds__(256) cellmap_single_kernel(LevelItem it, float clip, float eps) {
+__global__ void __launch_bounds__(FT_WAVES * 64) cellmap_single_kernel(LevelItem it, float clip, float eps) {
     __shared__ FeatShared<true> sm;
     init_lut(sm);
     __syncthreads();
@@ -548,7 +550,7 @@ __global__ void __launch_bounds__(256) cellmap_single_kernel(LevelItem it, float
         gmem(it.cmap16), task / ntx, task % ntx, FT_CH, clip, eps, sm, wave);
 }
 
-__global__ void __launch_bounds__(256) cellmap_table_kernel(const LevelItem* __restrict__ items,
+__global__ void __launch_bounds__(FT_WAVES * 64) cellmap_table_kernel(const LevelItem* __restrict__ items,
                                                             const Tile* __restrict__ tiles, int n_tiles, int ch,
                                                             float clip, float eps) {
     __shared__ FeatShared<true> sm;
@@ -567,7 +569,7 @@ __global__ void __launch_bounds__(256) cellmap_table_kernel(const LevelItem* __r
 // The table launch requires 8-byte aligned level rows (pd_detect copies
 // misaligned frames into the pyramid buffer).
 template <int FEAT>
-__global__ void __launch_bounds__(256) features_table_kernel(const LevelItem* __restrict__ items,
+__global__ void __launch_bounds__(FT_WAVES * 64) features_table_kernel(const LevelItem* __restrict__ items,
                                                              const Tile* __restrict__ tiles, int n_tiles, int ch,
                                                              float clip, float eps) {
     __shared__ FeatShared<false> sm;
@@ -606,7 +608,7 @@ __global__ void __launch_bounds__(256) lbp_codes_kernel(const uint8_t* __restric
 template <int FEAT, bool ALIGNED>
 hipError_t feat_single(const LevelItem& it, float clip, float eps, hipStream_t s) {
     const int n = feat_tiles_x(it.wc) * feat_tiles_y(it.hc);
-    features_single_kernel<FEAT, ALIGNED><<<ceil_div(n, FT_WAVES), 256, 0, s>>>(it, clip, eps);
+    features_single_kernel<FEAT, ALIGNED><<<ceil_div(n, FT_WAVES), FT_WAVES * 64, 0, s>>>(it, clip, eps);
     return hipGetLastError();
 }
 
@@ -621,7 +623,7 @@ hipError_t feat_table(const LevelItem* items, const Tile* tiles, int n_tiles, fl
                       const Tuning& tu, hipStream_t s) {
     int blocks = ceil_div(n_tiles, FT_WAVES);
     if (tu.grid > 0) blocks = min(blocks, tu.grid);
-    features_table_kernel<FEAT><<<blocks, 256, 0, s>>>(items, tiles, n_tiles, tu.feat_rows, clip, eps);
+    features_table_kernel<FEAT><<<blocks, FT_WAVES * 64, 0, s>>>(items, tiles, n_tiles, tu.feat_rows, clip, eps);
     return hipGetLastError();
 }
 
@@ -631,8 +633,8 @@ hipError_t launch_features_cellmap_single(const LevelItem& it, float clip, float
     if (it.hc <= 0 || it.wc <= 0) return hipSuccess;
     const int n = feat_tiles_x_cm(it.wc) * feat_tiles_y(it.hc);
     const bool aligned = (((uintptr_t)it.pyr | (uintptr_t)it.pitch) & 7) == 0;
-    if (aligned) cellmap_single_kernel<true><<<ceil_div(n, FT_WAVES), 256, 0, s>>>(it, clip, eps);
-    else cellmap_single_kernel<false><<<ceil_div(n, FT_WAVES), 256, 0, s>>>(it, clip, eps);
+    if (aligned) cellmap_single_kernel<true><<<ceil_div(n, FT_WAVES), FT_WAVES * 64, 0, s>>>(it, clip, eps);
+    else cellmap_single_kernel<false><<<ceil_div(n, FT_WAVES), FT_WAVES * 64, 0, s>>>(it, clip, eps);
     return hipGetLastError();
 }
 
@@ -641,7 +643,7 @@ hipError_t launch_features_cellmap_table(const LevelItem* items, const Tile* til
     if (n_tiles <= 0) return hipSuccess;
     int blocks = ceil_div(n_tiles, FT_WAVES);
     if (tu.grid > 0) blocks = min(blocks, tu.grid);
-    cellmap_table_kernel<<<blocks, 256, 0, s>>>(items, tiles, n_tiles, tu.feat_rows, clip, eps);
+    cellmap_table_kernel<<<blocks, FT_WAVES * 64, 0, s>>>(items, tiles, n_tiles, tu.feat_rows, clip, eps);
     return hipGetLastError();
 }
 

@@ -585,6 +585,25 @@ void fill_tables(const pd_frame* frames, int n_frames, int n_models, const Tunin
             for (int c = 0; c < ceil_div(it.nx * it.ny, CP_N); ++c) t_cp[ncp++] = Tile{q, 0, c, 0};
         }
     }
+    if (nft > 1) {
+        // feature strips longest first (cell rows walked; with the cell map,
+        // one more above all but the first), so that the launch ends on its
+        // shortest strips: a counting sort, stable within a length
+        const int ch = tu.feat_rows;
+        auto rows_of = [&](const Tile& t) {
+            const int c0 = t.ty * ch;
+            return std::max(0, std::min(c0 + ch, items[t.item].hc - 1) - c0 + 1);
+        };
+        std::vector<int> start(ch + 2, 0);
+        for (int i = 0; i < nft; ++i) ++start[rows_of(t_ft[i])];
+        for (int r = ch + 1, acc = 0; r >= 0; --r) {
+            const int c = start[r];
+            start[r] = acc;
+            acc += c;
+        }
+        const std::vector<Tile> by_item(t_ft, t_ft + nft);
+        for (const Tile& t : by_item) t_ft[start[rows_of(t)]++] = t;
+    }
     R.nsc_half = (int)half.size();  // within capacity: one tile each, as without the split
     for (int k = 0; k < R.nsc_half; ++k) t_sc[nsc + k] = half[k];
     const Tile* d_tiles = reinterpret_cast<const Tile*>(ws + L.off_tiles);
