@@ -302,9 +302,12 @@ def main():
     boxes, counts = det.results()
     per_launch = {k: v / max(calls, 1) for k, v in stage_ms.items()}
 
-    latency_ms = latency_graph_ms = None
+    latency_ms = latency_graph_ms = latency_tuning = None
     if not args.no_latency:
-        one = pd.Detector(frames[:1], wts, bias, prm, cap=1024)
+        one = pd.Detector(frames[:1], wts, bias, pd.params(), cap=1024)
+        latency_tuning = one.prm.tuning()
+        if not args.no_tune:  # tile shapes for one frame (the batch's leave it few waves)
+            latency_tuning, _ = one.autotune(thr[:1], iters=3)
         for _ in range(10):
             one.run(thr[:1])
         torch.cuda.synchronize()
@@ -361,6 +364,7 @@ def main():
         "tuning": tuning,
         "latency_ms_1frame": None if latency_ms is None else round(latency_ms, 4),
         "latency_ms_1frame_graph": None if latency_graph_ms is None else round(latency_graph_ms, 4),
+        "latency_tuning": latency_tuning,
         "detections_per_frame": round(float(np.mean([c["kept"] for c in counts])), 2),
         "candidates_per_frame": round(float(np.mean([c["candidates"] for c in counts])), 2),
     }
