@@ -31,6 +31,7 @@ METRIC = "frames/sec at 1242x375 full pyramid (plain vs pruned+BF16) at >=99% re
 W0, H0 = 1242, 375
 PEAK_HBM_GBS = 8000.0
 PEAK_FP32_TFLOPS = 157.3
+HOG_DIM = 15 * 7 * 36  # HOG part of a window's feature vector (the LBP part follows)
 
 
 def _gen(args):
@@ -160,11 +161,14 @@ def calibrate_threshold(pd, torch, calib, wts, bias, prm):
     return 0.5 * (s[k - 1] + s[k])
 
 
-def time_detect(pd, torch, frames, wts, bias, prm, thr_value, steps, warmup):
-    """(seconds for `steps` pd_detect calls, per-stage ms per call, counts)."""
+def time_detect(pd, torch, frames, wts, bias, prm, thr_value, steps, warmup, tune=False):
+    """(seconds for `steps` pd_detect calls, per-stage ms per call, counts);
+    with `tune`, after the autotuner has picked the tile shapes."""
     B = len(frames)
     thr = torch.full((B,), thr_value, dtype=torch.float64, device=frames[0].device)
     det = pd.Detector(frames, wts, bias, prm, cap=1024)
+    if tune:
+        det.autotune(thr, iters=3)
     for _ in range(warmup):
         det.run(thr)
     torch.cuda.synchronize()
@@ -231,6 +235,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--no-latency", action="store_true")
     ap.add_argument("--no-bf16", action="store_true", help="skip the BF16 MFMA legs")
+    ap.add_argument("--no-subsets", action="store_true", help="skip the HOG-SVM and LBP-SVM legs")
     ap.add_argument("--no-batched", action="store_true", help="skip the mixed-size batched leg")
     ap.add_argument("--no-tune", action="store_true", help="default tile shapes (no autotuning)")
     ap.add_argument("--no-pruned", action="store_true", help="skip the learned-pruning leg")
@@ -376,7 +381,8 @@ def main():
             bm = torch.from_numpy(pd_synth.svm_bias(m)).to(dev)
             prm16 = pd.params(precision=pd.PREC_BF16, margin=0.05)
             t16 = calibrate_threshold(pd, torch, calib, wm, bm, prm16)
-            el, st, cnt = time_detect(pd, torch, frames, wm, bm, prm16, t16, args.steps, args.warmup)
+            el, st, cnt = time_detect(pd, torch, frames, wm, bm, prm16, t16, args.steps, args.warmup,
+                                      tune=not args.no_tune)
             sflops = 2.0 * 11332 * windows * B * m
             legs[f"bf16_{m}model"] = {
                 "value": round(B * args.steps / el, 1), "unit": "frames/s", "ms_per_step": round(1000 * el / args.steps, 4),
@@ -386,6 +392,25 @@ def main():
                 "candidates_per_frame": round(float(np.mean([c["candidates"] for c in cnt])), 2),
                 "overflow_frames": int(sum(c["overflow"] for c in cnt))}
         out["bf16"] = legs
+    if not args.no_subsets:
+        # the paper's single-family pipelines: the same kernels on HOG or LBP
+        # only; the threshold comes from the full path with the other
+        # family's weights at zero (the same linear model)
+        print("[bench] HOG-SVM and LBP-SVM legs", file=sys.stderr, flush=True)
+        legs = {}
+        for name, feat, dims in (("hog_svm", pd.FEAT_HOG, slice(HOG_DIM, None)),
+                                 ("lbp_svm", pd.FEAT_LBP, slice(0, HOG_DIM))):
+            wz = wts.clone()
+            wz[:, dims] = 0
+            ts = calibrate_threshold(pd, torch, calib, wz, bias, pd.params())
+            el, st, cnt = time_detect(pd, torch, frames, wz, bias, pd.params(features=feat), ts, args.steps,
+                                      args.warmup, tune=not args.no_tune)
+            legs[name] = {
+                "value": round(B * args.steps / el, 1), "unit": "frames/s", "ms_per_step": round(1000 * el / args.steps, 4),
+                "stage_ms_per_launch": {k: round(v, 4) for k, v in st.items()},
+                "detections_per_frame": round(float(np.mean([c["kept"] for c in cnt])), 2),
+                "candidates_per_frame": round(float(np.mean([c["candidates"] for c in cnt])), 2)}
+        out["feature_subsets"] = legs
     if not args.no_pruned:
         print("[bench] pruned + BF16 leg (training the pruner)", file=sys.stderr, flush=True)
         out["chosen"] = pruned_leg(pd, torch, dev, frames, boxes, wts, bias, thr_value, args.steps, args.warmup,
