@@ -50,6 +50,10 @@ Readings of points the paper leaves open (each also listed in the design doc):
      (2 * inter > union in integers).
   R11 several models: window score = max over models, lowest model index on
      ties.
+  R19 LBP block histograms (Algorithm 3): the raw sum of the 2x2 cell
+     histograms of each 16x16 block (50 % overlap, no normalisation); a
+     block-level window vector is the 15x7 HOG blocks then the 15x7 LBP
+     blocks, row-major, channel innermost (3780 + 6195 = 9975 values).
 """
 from __future__ import annotations
 
@@ -66,6 +70,8 @@ WIN_CELLS_Y, WIN_CELLS_X = 16, 8     # LBP cells per window
 HOG_DIM = WIN_BLOCKS_Y * WIN_BLOCKS_X * 4 * HOG_BINS   # 3780
 LBP_DIM = WIN_CELLS_Y * WIN_CELLS_X * LBP_BINS         # 7552
 FEATURE_DIM = HOG_DIM + LBP_DIM                        # 11332
+LBP_BLOCK_DIM = WIN_BLOCKS_Y * WIN_BLOCKS_X * LBP_BINS # 6195
+BLOCK_MODEL_DIM = HOG_DIM + LBP_BLOCK_DIM              # 9975
 
 
 # ---------------------------------------------------------------------------
@@ -303,6 +309,65 @@ def window_scores(hog: np.ndarray, cells: np.ndarray, weights: np.ndarray,
 
 def level_features(level: np.ndarray, clip: float = 0.2, eps: float = 1e-3):
     return hog_features(level, clip, eps), lbp_cell_histograms(level)
+
+
+# ---------------------------------------------------------------------------
+# LBP block histograms (Section 4.2, Algorithm 3; reading R19) and the
+# cell-level model with the same scores
+# ---------------------------------------------------------------------------
+
+def lbp_block_histograms(cells: np.ndarray) -> np.ndarray:
+    """[Hb][Wb][59]: each 16x16 block's histogram is the sum of its four
+    8x8 cell histograms (the histogram reduction of Algorithm 3)."""
+    cells = np.asarray(cells, dtype=np.int64)
+    return cells[:-1, :-1] + cells[:-1, 1:] + cells[1:, :-1] + cells[1:, 1:]
+
+
+def window_vector_blocks(hog: np.ndarray, lbp_blocks: np.ndarray, i: int, j: int) -> np.ndarray:
+    """Block-level feature vector of the window anchored at cell (i, j)."""
+    h = hog[i:i + WIN_BLOCKS_Y, j:j + WIN_BLOCKS_X, :]
+    l = lbp_blocks[i:i + WIN_BLOCKS_Y, j:j + WIN_BLOCKS_X, :]
+    assert h.shape == (WIN_BLOCKS_Y, WIN_BLOCKS_X, 4 * HOG_BINS)
+    assert l.shape == (WIN_BLOCKS_Y, WIN_BLOCKS_X, LBP_BINS)
+    return np.concatenate([h.reshape(-1), l.reshape(-1).astype(np.float64)])
+
+
+def window_scores_blocks(hog: np.ndarray, lbp_blocks: np.ndarray, weights: np.ndarray,
+                         bias: np.ndarray) -> np.ndarray:
+    """Scores [m][Y][X] of block-level models [m][9975] by explicit
+    extraction of every window's block-level vector (brute force)."""
+    weights = np.atleast_2d(np.asarray(weights, dtype=np.float64))
+    bias = np.asarray(bias, dtype=np.float64).reshape(-1)
+    ny = max(0, lbp_blocks.shape[0] - WIN_BLOCKS_Y + 1)
+    nx = max(0, lbp_blocks.shape[1] - WIN_BLOCKS_X + 1)
+    out = np.zeros((weights.shape[0], ny, nx))
+    for i in range(ny):
+        x = np.stack([window_vector_blocks(hog, lbp_blocks, i, j) for j in range(nx)]) if nx else None
+        if nx:
+            out[:, i, :] = (x @ weights.T + bias[None, :]).T
+    return out
+
+
+def fold_lbp_block_weights(weights: np.ndarray) -> np.ndarray:
+    """The cell-level model [m][11332] that scores every window as the
+    block-level model [m][9975] does: HOG weights copied; since a block
+    histogram is the plain sum of its cells, the weight of window cell
+    (a, b) is the sum of the weights of the window blocks that contain it,
+    (a', b') with a' in {a-1, a} and b' in {b-1, b}."""
+    weights = np.atleast_2d(np.asarray(weights, dtype=np.float64))
+    m = weights.shape[0]
+    out = np.zeros((m, FEATURE_DIM))
+    out[:, :HOG_DIM] = weights[:, :HOG_DIM]
+    wb = weights[:, HOG_DIM:].reshape(m, WIN_BLOCKS_Y, WIN_BLOCKS_X, LBP_BINS)
+    wc = np.zeros((m, WIN_CELLS_Y, WIN_CELLS_X, LBP_BINS))
+    for a in range(WIN_CELLS_Y):
+        for b in range(WIN_CELLS_X):
+            for a2 in (a - 1, a):
+                for b2 in (b - 1, b):
+                    if 0 <= a2 < WIN_BLOCKS_Y and 0 <= b2 < WIN_BLOCKS_X:
+                        wc[:, a, b, :] += wb[:, a2, b2, :]
+    out[:, HOG_DIM:] = wc.reshape(m, -1)
+    return out
 
 
 # ---------------------------------------------------------------------------
