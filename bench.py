@@ -185,6 +185,42 @@ def time_detect(pd, torch, frames, wts, bias, prm, thr_value, steps, warmup, tun
     return elapsed, {k: v / max(calls, 1) for k, v in stage_ms.items()}, counts
 
 
+def lbp_block_leg(pd, torch, frames, calib, prm, steps, warmup):
+    """The paper's LBP block histograms (Algorithm 3): the reduction kernel on
+    the level-0 cell histograms of the batch (HIP events), the weight fold,
+    and detection with a block-level model through its folded cell-level
+    model (the same kernels as the plain leg)."""
+    B = len(frames)
+    cells = torch.stack([pd.lbp(f) for f in frames]).contiguous()
+    n, _, hc, wc = (int(x) for x in cells.shape)
+    for _ in range(3):
+        pd.lbp_blocks(cells)
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(20):
+        pd.lbp_blocks(cells)
+    e1.record(s)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 20
+    nbytes = n * 59 * (hc * wc + 2 * (hc - 1) * (wc - 1))
+    rng = np.random.default_rng(11)
+    wb = torch.from_numpy(rng.normal(0.0, 0.01, size=(1, pd.BLOCK_MODEL_DIM)).astype(np.float32)).to(frames[0].device)
+    bias = torch.zeros(1, device=frames[0].device)
+    e0.record(s)
+    wc_model = pd.fold_lbp_weights(wb)
+    e1.record(s)
+    torch.cuda.synchronize()
+    fold_ms = e0.elapsed_time(e1)
+    thr = calibrate_threshold(pd, torch, calib, wc_model, bias, pd.params())
+    el, st, cnt = time_detect(pd, torch, frames, wc_model, bias, prm, thr, steps, warmup)
+    return {"alg3_blocks_ms": round(ms, 4), "alg3_blocks_gbs": round(nbytes / (ms / 1000) / 1e9, 1),
+            "alg3_blocks_workload": f"{n} x 59 x {hc}x{wc} cell counts (level 0 of the batch) -> uint16 blocks",
+            "fold_ms": round(fold_ms, 4), "value": round(B * steps / el, 1), "unit": "frames/s",
+            "stage_ms_per_launch": {k: round(v, 4) for k, v in st.items()},
+            "candidates_per_frame": round(float(np.mean([c["candidates"] for c in cnt])), 2)}
+
+
 def pruned_leg(pd, torch, dev, frames, plain_boxes, wts, bias, thr_value, steps, warmup, n_train, n_cal, epochs):
     """The chosen form: learned pruning + BF16 MFMA scoring with FP64 rescoring.
     The pruner is trained here (n_train synthetic frames, the project's own
@@ -411,6 +447,8 @@ def main():
                 "detections_per_frame": round(float(np.mean([c["kept"] for c in cnt])), 2),
                 "candidates_per_frame": round(float(np.mean([c["candidates"] for c in cnt])), 2)}
         out["feature_subsets"] = legs
+    if not args.no_subsets:
+        out["lbp_block_model"] = lbp_block_leg(pd, torch, frames, calib, prm, args.steps, args.warmup)
     if not args.no_pruned:
         print("[bench] pruned + BF16 leg (training the pruner)", file=sys.stderr, flush=True)
         out["chosen"] = pruned_leg(pd, torch, dev, frames, boxes, wts, bias, thr_value, args.steps, args.warmup,

@@ -54,6 +54,9 @@ extern "C" {
 #define PD_HOG_DIM       3780   /* 15 * 7 * 36                             */
 #define PD_LBP_DIM       7552   /* 16 * 8 * 59                             */
 #define PD_FEATURE_DIM   11332  /* PD_HOG_DIM + PD_LBP_DIM                 */
+#define PD_LBP_BLOCK_DIM 6195   /* 15 * 7 * 59: LBP block histograms of a
+                                   window (Algorithm 3)                     */
+#define PD_BLOCK_MODEL_DIM 9975 /* PD_HOG_DIM + PD_LBP_BLOCK_DIM          */
 #define PD_MAX_LEVELS    64
 #define PD_MAX_DIM       16384  /* largest accepted image side             */
 #define PD_MAX_MODELS    16
@@ -192,6 +195,34 @@ int pd_hog(const uint8_t* lvl, int w, int h, int pitch, const pd_params* params,
  */
 int pd_features(const uint8_t* lvl, int w, int h, int pitch, const pd_params* params,
                 float* blocks, uint16_t* blocks_bf16, uint8_t* cell_hist, void* stream);
+
+/*
+ * pd_lbp_blocks -- Section 4.2, Algorithm 3 (the histogram reduction).
+ * The 59-bin histogram of each 16x16-pixel block (blocks overlap by one
+ * cell) as the sum of its four 8x8 cell histograms, for n images at once.
+ *   cells   : device uint8 [n][59][hc][wc] (pd_lbp layout per image)
+ *   blocks  : device uint16 [n][59][hc-1][wc-1] (a block counts 256 pixels)
+ * Errors: PD_E_SIZE unless n >= 1, hc, wc >= 2 and the sides are within
+ * PD_MAX_DIM / 8; PD_E_ARG on a NULL pointer.
+ */
+int pd_lbp_blocks(const uint8_t* cells, int n, int hc, int wc, uint16_t* blocks, void* stream);
+
+/*
+ * pd_fold_lbp_weights -- a linear model over HOG blocks and LBP block
+ * histograms (Algorithm 3) as the cell-level model with the same window
+ * scores.  Block-model layout per model: the 3780 HOG weights, then
+ * [15][7][59] LBP block weights (window block row, column, bin).  Since a
+ * block histogram is the plain sum of its four cells, the output's LBP weight
+ * of window cell (a, b) is the sum of the weights of the window blocks
+ * (a', b'), a' in {a-1, a}, b' in {b-1, b}, that contain it (FP32 sums in a
+ * fixed order); HOG weights are copied.  pd_detect and pd_score_windows with
+ * the folded weights then score with the block-level model.
+ *   wb : device float [n_models][PD_BLOCK_MODEL_DIM]
+ *   w  : device float [n_models][PD_FEATURE_DIM]
+ * Errors: PD_E_SIZE when n_models is outside [1, PD_MAX_MODELS]; PD_E_ARG on
+ * a NULL pointer.
+ */
+int pd_fold_lbp_weights(const float* wb, int n_models, float* w, void* stream);
 
 /*
  * pd_score_windows -- Section 4.4, Algorithm 6.

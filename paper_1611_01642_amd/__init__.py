@@ -21,6 +21,7 @@ WIN_W, WIN_H = 64, 128
 HOG_BLOCK = 36
 LBP_BINS = 59
 HOG_DIM, LBP_DIM, FEATURE_DIM = 3780, 7552, 11332
+LBP_BLOCK_DIM, BLOCK_MODEL_DIM = 6195, 9975
 MAX_LEVELS = 64
 MAX_MODELS = 16
 MAX_CANDIDATES = 4096
@@ -100,6 +101,9 @@ _SIGS = {
     "pd_detect_candidates": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
                                             ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p,
                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p]),
+    "pd_lbp_blocks": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                     ctypes.c_void_p]),
+    "pd_fold_lbp_weights": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
     "pd_score_windows": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                                         ctypes.c_void_p]),
@@ -284,6 +288,35 @@ def hog(img, prm: Params = None):
 
 def lbp(img):
     return features(img, None, hog=False, lbp=True)[1]
+
+
+def lbp_blocks(cells):
+    """LBP block histograms (pd_lbp_blocks) of cell histograms uint8
+    [59][Hc][Wc] or [n][59][Hc][Wc]: int16 [..][59][Hc-1][Wc-1] (counts up to
+    256, held in int16 storage)."""
+    torch = _torch()
+    if cells.dtype != torch.uint8 or cells.dim() not in (3, 4) or not cells.is_contiguous():
+        raise ValueError("cells must be contiguous uint8 [59][Hc][Wc] or [n][59][Hc][Wc]")
+    c4 = cells if cells.dim() == 4 else cells.unsqueeze(0)
+    n, _, hc, wc = (int(x) for x in c4.shape)
+    out = torch.empty((n, LBP_BINS, max(hc - 1, 0), max(wc - 1, 0)), dtype=torch.int16, device=cells.device)
+    _check(lib().pd_lbp_blocks(ctypes.c_void_p(c4.data_ptr()), n, hc, wc, ctypes.c_void_p(out.data_ptr()),
+                               _stream()))
+    return out if cells.dim() == 4 else out[0]
+
+
+def fold_lbp_weights(wb):
+    """The cell-level models [m][11332] (pd_fold_lbp_weights) with the same
+    window scores as block-level models wb [m][9975] (HOG, then LBP block
+    histograms)."""
+    torch = _torch()
+    wb = wb.contiguous()
+    if wb.dtype != torch.float32 or wb.dim() != 2 or int(wb.shape[1]) != BLOCK_MODEL_DIM:
+        raise ValueError("wb must be float32 [m][9975]")
+    m = int(wb.shape[0])
+    out = torch.empty((m, FEATURE_DIM), dtype=torch.float32, device=wb.device)
+    _check(lib().pd_fold_lbp_weights(ctypes.c_void_p(wb.data_ptr()), m, ctypes.c_void_p(out.data_ptr()), _stream()))
+    return out
 
 
 def score_windows(blocks, cells, weights, bias):

@@ -1060,6 +1060,20 @@ int pd_score_windows(const float* blocks, const uint8_t* cells, int cells_x, int
                       "score launch");
 }
 
+int pd_lbp_blocks(const uint8_t* cells, int n, int hc, int wc, uint16_t* blocks, void* stream) {
+    if (n < 1 || hc < 2 || wc < 2 || hc > PD_MAX_DIM / PD_CELL || wc > PD_MAX_DIM / PD_CELL ||
+        (int64_t)n * PD_LBP_BINS * hc > INT32_MAX)
+        return fail(PD_E_SIZE, "cell grid %dx%d x %d images has no block", wc, hc, n);
+    if (!cells || !blocks) return fail(PD_E_ARG, "NULL pointer argument");
+    return hip_status(launch_lbp_blocks(cells, n, hc, wc, blocks, (hipStream_t)stream), "lbp blocks launch");
+}
+
+int pd_fold_lbp_weights(const float* wb, int n_models, float* w, void* stream) {
+    if (n_models < 1 || n_models > PD_MAX_MODELS) return fail(PD_E_SIZE, "n_models %d outside [1, %d]", n_models, PD_MAX_MODELS);
+    if (!wb || !w) return fail(PD_E_ARG, "NULL pointer argument");
+    return hip_status(launch_fold_lbp_weights(wb, n_models, w, (hipStream_t)stream), "fold launch");
+}
+
 int64_t pd_packed_models_bytes(void) { return (packed_weight_elems() + rowgemm_packed_elems()) * 2; }
 
 int pd_pack_models(const float* weights, int n_models, uint16_t* packed, void* stream) {

@@ -173,6 +173,9 @@ hipError_t launch_score_table(const LevelItem* items, const Tile* tiles, int n_t
                               const float* w, const float* bias, int n_models, int features,
                               const Tuning& tu, hipStream_t s, const int* n_dev = nullptr, int n_half = 0);
 
+hipError_t launch_lbp_blocks(const uint8_t* cells, int n, int hc, int wc, uint16_t* blocks, hipStream_t s);
+hipError_t launch_fold_lbp_weights(const float* wb, int n_models, float* w, hipStream_t s);
+
 int64_t packed_weight_elems();
 int64_t rowgemm_packed_elems();
 hipError_t launch_pack_rowgemm(const float* w, uint16_t* out, hipStream_t s);

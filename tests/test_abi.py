@@ -98,6 +98,13 @@ def test_argument_errors_enqueue_nothing():
     assert L.pd_nms(fake, fake, 4097, wh, 1, fake, 10, fake, nil) == pd.E_SIZE
     assert L.pd_nms(fake, fake, 10, wh, 0, fake, 10, fake, nil) == pd.E_SIZE
     assert L.pd_build_pyramid(fake, 100, 100, 100, nil, 65, fake, nil) == pd.E_SIZE
+    assert L.pd_lbp_blocks(fake, 1, 1, 8, fake, nil) == pd.E_SIZE      # no block in one cell row
+    assert L.pd_lbp_blocks(fake, 0, 16, 8, fake, nil) == pd.E_SIZE
+    assert L.pd_lbp_blocks(fake, 1, 16, 2049, fake, nil) == pd.E_SIZE  # wider than PD_MAX_DIM
+    assert L.pd_lbp_blocks(nil, 1, 16, 8, fake, nil) == pd.E_ARG
+    assert L.pd_fold_lbp_weights(fake, 0, fake, nil) == pd.E_SIZE
+    assert L.pd_fold_lbp_weights(fake, 17, fake, nil) == pd.E_SIZE
+    assert L.pd_fold_lbp_weights(fake, 1, nil, nil) == pd.E_ARG
 
 
 def test_tuning_field_checks_and_graph_handles():
