@@ -221,6 +221,50 @@ def lbp_block_leg(pd, torch, frames, calib, prm, steps, warmup):
             "candidates_per_frame": round(float(np.mean([c["candidates"] for c in cnt])), 2)}
 
 
+def streaming_leg(pd, torch, host, wts, bias, thr_value, prm, n_free=300, n_paced=60, depth=3):
+    """Streaming mode (pd_video, Section 4.1 steps 1 and 5 around the GPU
+    steps): 1242x375 frames pushed from pinned-free host memory (a plain
+    numpy array each), uploaded, detected and their boxes downloaded on three
+    streams.  Back to back with `depth` frames in flight: frames/s including
+    both copies.  Paced at 30 and 60 frames/s (each frame pushed at its
+    arrival time, then popped): per-frame latency, on the GPU (upload start to
+    download end) and on the host (push to boxes in hand)."""
+    v = pd.Video(W0, H0, wts, bias, prm, cap=1024, depth=depth)
+    frames = [np.ascontiguousarray(f) for f in host[:64]]
+    for k in range(10):
+        v.push(frames[k % len(frames)], thr_value)
+        v.pop()
+    pushed, popped, dev_ms = 0, 0, []
+    t0 = time.perf_counter()
+    while popped < n_free:
+        while pushed < n_free and pushed - popped < depth:
+            v.push(frames[pushed % len(frames)], thr_value)
+            pushed += 1
+        dev_ms.append(v.pop()[2])
+        popped += 1
+    free_s = time.perf_counter() - t0
+    out = {"frames_per_s_back_to_back": round(n_free / free_s, 1), "depth": depth,
+           "device_ms_mean_back_to_back": round(float(np.mean(dev_ms)), 4)}
+    for fps in (30, 60):
+        host_ms, dev = [], []
+        t_start = time.perf_counter() + 0.01
+        for k in range(n_paced):
+            t_arrive = t_start + k / fps
+            while time.perf_counter() < t_arrive:
+                time.sleep(min(0.002, max(0.0, t_arrive - time.perf_counter())))
+            t_push = time.perf_counter()
+            v.push(frames[k % len(frames)], thr_value)
+            _, _, ms = v.pop()
+            host_ms.append(1000 * (time.perf_counter() - t_push))
+            dev.append(ms)
+        out[f"latency_ms_at_{fps}fps"] = {"host_mean": round(float(np.mean(host_ms)), 4),
+                                          "host_p99": round(float(np.percentile(host_ms, 99)), 4),
+                                          "device_mean": round(float(np.mean(dev)), 4),
+                                          "device_p99": round(float(np.percentile(dev, 99)), 4)}
+    v.close()
+    return out
+
+
 def pruned_leg(pd, torch, dev, frames, plain_boxes, wts, bias, thr_value, steps, warmup, n_train, n_cal, epochs):
     """The chosen form: learned pruning + BF16 MFMA scoring with FP64 rescoring.
     The pruner is trained here (n_train synthetic frames, the project's own
@@ -272,6 +316,7 @@ def main():
     ap.add_argument("--no-latency", action="store_true")
     ap.add_argument("--no-bf16", action="store_true", help="skip the BF16 MFMA legs")
     ap.add_argument("--no-subsets", action="store_true", help="skip the HOG-SVM and LBP-SVM legs")
+    ap.add_argument("--no-streaming", action="store_true", help="skip the streaming video leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the mixed-size batched leg")
     ap.add_argument("--no-tune", action="store_true", help="default tile shapes (no autotuning)")
     ap.add_argument("--no-pruned", action="store_true", help="skip the learned-pruning leg")
@@ -409,6 +454,10 @@ def main():
         "detections_per_frame": round(float(np.mean([c["kept"] for c in counts])), 2),
         "candidates_per_frame": round(float(np.mean([c["candidates"] for c in counts])), 2),
     }
+    if not args.no_streaming:
+        print("[bench] streaming leg", file=sys.stderr, flush=True)
+        sprm = one.prm if not args.no_latency else pd.params()
+        out["streaming"] = streaming_leg(pd, torch, host, wts, bias, thr_value, sprm)
     if not args.no_bf16:
         print("[bench] bf16 legs", file=sys.stderr, flush=True)
         legs = {}

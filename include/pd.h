@@ -356,6 +356,57 @@ int pd_graph_launch(pd_graph* graph, void* stream);
    sure no launch is still running. */
 int pd_graph_destroy(pd_graph* graph);
 
+/* ---- streaming video (Section 4.1 steps 1 and 5 around steps 2-4) ------- */
+/*
+ * A video stream of frames of one size that arrive one at a time in host
+ * memory.  Each push copies the frame to the GPU (step 1), runs pd_detect's
+ * kernels on it (steps 2-4 and NMS, as a graph captured at creation) and
+ * copies the counts and boxes back (step 5), on three streams ordered by
+ * events, so the copies of one frame overlap the detection of its
+ * neighbours.  Up to `depth` frames are in flight; results come back in push
+ * order.  This object owns its buffers: pd_video_create allocates device
+ * memory (frames, workspaces, results) and pinned host memory for `depth`
+ * slots, and pd_video_destroy frees them; push and pop allocate nothing.
+ * One video must not be used from two threads at once.
+ */
+#define PD_VIDEO_MAX_DEPTH 16
+typedef struct pd_video pd_video;
+
+/*
+ * pd_video_create -- frames of w x h pixels, detected with `params` (tuning
+ * fields included) and the models (device weights [n_models][11332], bias
+ * [n_models], kept alive by the caller until pd_video_destroy); up to `cap`
+ * boxes per frame; `depth` in [1, PD_VIDEO_MAX_DEPTH] frames in flight.
+ * Blocks until the set-up finished.
+ *   out : host pointer receiving the handle
+ * Errors: those of pd_detect_workspace_bytes; PD_E_SIZE for depth, cap or the
+ * frame size; PD_E_HIP when an allocation or the capture fails.
+ */
+int pd_video_create(int w, int h, const pd_params* params, const float* weights,
+                    const float* bias, int n_models, int cap, int depth, pd_video** out);
+
+/*
+ * pd_video_push -- queue one frame (host memory, `pitch` bytes per row,
+ * copied before the call returns) with its detection threshold.  Returns
+ * without waiting for the GPU.
+ * Errors: PD_E_SIZE when `depth` frames are already in flight (pop first);
+ * PD_E_ARG on a NULL frame or pitch < w.
+ */
+int pd_video_push(pd_video* v, const uint8_t* frame, int pitch, double threshold);
+
+/*
+ * pd_video_pop -- wait for the oldest frame in flight and copy its counts and
+ * up to `cap` boxes (host buffers, NMS order, frame index 0) to the caller.
+ * `device_ms` (host, may be NULL) receives the GPU time from the start of its
+ * upload to the end of its download, queueing behind earlier frames included.
+ * Errors: PD_E_ARG when no frame is in flight or on a NULL pointer.
+ */
+int pd_video_pop(pd_video* v, pd_box* boxes, int cap, pd_counts* counts, float* device_ms);
+
+/* pd_video_destroy -- wait for work in flight and free the video's buffers
+   (NULL is accepted). */
+int pd_video_destroy(pd_video* v);
+
 /*
  * pd_autotune -- times pd_detect on these arguments (one untimed call, then
  * `iters` calls between HIP events, per candidate) over the tuning fields of

@@ -116,6 +116,12 @@ _SIGS = {
                                        ctypes.c_int64, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                                        ctypes.c_void_p, ctypes.c_void_p]),
     "pd_graph_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "pd_video_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]),
+    "pd_video_push": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_double]),
+    "pd_video_pop": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                    ctypes.c_void_p]),
+    "pd_video_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "pd_graph_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "pd_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
@@ -562,6 +568,50 @@ class Detector:
         counts = self.counts.cpu().numpy().view(COUNTS_DTYPE)
         allb = self.boxes.cpu().numpy().view(BOX_DTYPE).reshape(len(self.frames), max(self.cap, 1))
         return [allb[f, :counts[f]["kept"]].copy() for f in range(len(self.frames))], counts
+
+
+class Video:
+    """Streaming detection of host frames of one size (pd_video_*): push()
+    queues a host uint8 frame with its threshold, pop() returns the oldest
+    frame's (boxes, counts, device ms).  Up to `depth` frames in flight.
+    The device weights and bias must outlive the video."""
+
+    def __init__(self, w: int, h: int, weights, bias, prm: Params = None, cap: int = 1024, depth: int = 3):
+        self.prm = prm or params()
+        self.weights, self.bias = weights.contiguous(), bias.contiguous()
+        self.w, self.h, self.cap = w, h, cap
+        self.handle = ctypes.c_void_p(0)
+        _check(lib().pd_video_create(w, h, ctypes.byref(self.prm), ctypes.c_void_p(self.weights.data_ptr()),
+                                     ctypes.c_void_p(self.bias.data_ptr()), int(self.weights.shape[0]), cap, depth,
+                                     ctypes.byref(self.handle)))
+        self._boxes = np.zeros(cap, BOX_DTYPE)
+        self._counts = np.zeros(1, COUNTS_DTYPE)
+
+    def push(self, frame: np.ndarray, threshold: float) -> None:
+        if frame.dtype != np.uint8 or frame.ndim != 2 or frame.shape[1] < self.w or frame.shape[0] < self.h:
+            raise ValueError("frame must be a uint8 [h][>= w] host array")
+        if frame.strides[1] != 1:
+            raise ValueError("frame rows must be contiguous")
+        _check(lib().pd_video_push(self.handle, ctypes.c_void_p(frame.ctypes.data), int(frame.strides[0]),
+                                   float(threshold)))
+
+    def pop(self):
+        ms = ctypes.c_float(0.0)
+        _check(lib().pd_video_pop(self.handle, ctypes.c_void_p(self._boxes.ctypes.data), self.cap,
+                                  ctypes.c_void_p(self._counts.ctypes.data), ctypes.byref(ms)))
+        n = int(min(self._counts[0]["kept"], self.cap))
+        return self._boxes[:n].copy(), self._counts[0].copy(), float(ms.value)
+
+    def close(self) -> None:
+        if self.handle:
+            _check(lib().pd_video_destroy(self.handle))
+            self.handle = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 STAGES = ("upload", "zero", "resize", "features", "score", "compact", "nms")

@@ -14,10 +14,10 @@
 using namespace pd;
 
 namespace {
-
 thread_local std::string g_last_error;
+}  // namespace
 
-int fail(int code, const char* fmt, ...) {
+int pd::fail(int code, const char* fmt, ...) {
     char buf[512];
     va_list ap;
     va_start(ap, fmt);
@@ -27,10 +27,12 @@ int fail(int code, const char* fmt, ...) {
     return code;
 }
 
-int hip_status(hipError_t e, const char* what) {
+int pd::hip_status(hipError_t e, const char* what) {
     if (e == hipSuccess) return PD_OK;
     return fail(PD_E_HIP, "%s: %s", what, hipGetErrorString(e));
 }
+
+namespace {
 
 constexpr int64_t kAlign = 256;
 constexpr int FT_MIN_ROWS = 4, FT_MAX_ROWS = 32;  // feature strip heights accepted in tune_feat_rows

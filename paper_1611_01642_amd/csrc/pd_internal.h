@@ -173,6 +173,11 @@ hipError_t launch_score_table(const LevelItem* items, const Tile* tiles, int n_t
                               const float* w, const float* bias, int n_models, int features,
                               const Tuning& tu, hipStream_t s, const int* n_dev = nullptr, int n_half = 0);
 
+// Error reporting of the C ABI: sets the calling thread's message and
+// returns `code` (fail) or maps a HIP status (hip_status: PD_OK or PD_E_HIP).
+int fail(int code, const char* fmt, ...);
+int hip_status(hipError_t e, const char* what);
+
 hipError_t launch_lbp_blocks(const uint8_t* cells, int n, int hc, int wc, uint16_t* blocks, hipStream_t s);
 hipError_t launch_fold_lbp_weights(const float* wb, int n_models, float* w, hipStream_t s);
 

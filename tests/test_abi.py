@@ -105,6 +105,17 @@ def test_argument_errors_enqueue_nothing():
     assert L.pd_fold_lbp_weights(fake, 0, fake, nil) == pd.E_SIZE
     assert L.pd_fold_lbp_weights(fake, 17, fake, nil) == pd.E_SIZE
     assert L.pd_fold_lbp_weights(fake, 1, nil, nil) == pd.E_ARG
+    out = ctypes.c_void_p(0)
+    prm = pd.params()
+    assert L.pd_video_create(640, 480, ctypes.byref(prm), fake, fake, 1, 16, 0, ctypes.byref(out)) == pd.E_SIZE
+    assert L.pd_video_create(640, 480, ctypes.byref(prm), fake, fake, 1, 16, 17, ctypes.byref(out)) == pd.E_SIZE
+    assert L.pd_video_create(640, 480, ctypes.byref(prm), fake, fake, 1, 0, 2, ctypes.byref(out)) == pd.E_SIZE
+    assert L.pd_video_create(640, 480, ctypes.byref(prm), nil, fake, 1, 16, 2, ctypes.byref(out)) == pd.E_ARG
+    assert L.pd_video_create(640, 480, ctypes.byref(prm), fake, fake, 1, 16, 2, nil) == pd.E_ARG
+    assert not out.value
+    assert L.pd_video_push(nil, fake, 640, 0.0) == pd.E_ARG
+    assert L.pd_video_pop(nil, fake, 1, fake, nil) == pd.E_ARG
+    assert L.pd_video_destroy(nil) == 0
 
 
 def test_tuning_field_checks_and_graph_handles():
