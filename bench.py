@@ -265,6 +265,40 @@ def streaming_leg(pd, torch, host, wts, bias, thr_value, prm, n_free=300, n_pace
     return out
 
 
+SWEEP_SIZES = [(320, 240), (640, 480), (1242, 375), (1280, 720), (1920, 1080), (2560, 1440), (3840, 2160)]
+
+
+def sweep_leg(pd, torch, dev, wts, bias, reps=20):
+    """px/ns per algorithm against image size, one image per call (the
+    paper's per-algorithm measurement): LBP, HOG, both in one pass, and SVM
+    scoring of the image's windows; HIP events around `reps` back-to-back
+    calls, so small images include the launch cost."""
+    import pd_synth
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        for _ in range(3):
+            fn()
+        e0.record(s)
+        for _ in range(reps):
+            fn()
+        e1.record(s)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    out = {}
+    for w, h in SWEEP_SIZES:
+        img = torch.from_numpy(pd_synth.frame(w, h, 3000 + w)).to(dev)
+        ms = {"lbp": timed(lambda: pd.features(img, None, hog=False, lbp=True)),
+              "hog": timed(lambda: pd.features(img, None, hog=True, lbp=False)),
+              "hog_lbp": timed(lambda: pd.features(img))}
+        blk, cel = pd.features(img)
+        ms["svm"] = timed(lambda: pd.score_windows(blk, cel, wts, bias))
+        out[f"{w}x{h}"] = {k: round(w * h / (v * 1e6), 3) for k, v in ms.items()}
+    return {"unit": "px/ns", "per_call": "one image, level 0 only", **out}
+
+
 def pruned_leg(pd, torch, dev, frames, plain_boxes, wts, bias, thr_value, steps, warmup, n_train, n_cal, epochs):
     """The chosen form: learned pruning + BF16 MFMA scoring with FP64 rescoring.
     The pruner is trained here (n_train synthetic frames, the project's own
@@ -317,6 +351,7 @@ def main():
     ap.add_argument("--no-bf16", action="store_true", help="skip the BF16 MFMA legs")
     ap.add_argument("--no-subsets", action="store_true", help="skip the HOG-SVM and LBP-SVM legs")
     ap.add_argument("--no-streaming", action="store_true", help="skip the streaming video leg")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the px/ns sweep over image sizes")
     ap.add_argument("--no-batched", action="store_true", help="skip the mixed-size batched leg")
     ap.add_argument("--no-tune", action="store_true", help="default tile shapes (no autotuning)")
     ap.add_argument("--no-pruned", action="store_true", help="skip the learned-pruning leg")
@@ -454,6 +489,13 @@ def main():
         "detections_per_frame": round(float(np.mean([c["kept"] for c in counts])), 2),
         "candidates_per_frame": round(float(np.mean([c["candidates"] for c in counts])), 2),
     }
+    if not args.no_sweep:
+        print("[bench] px/ns sweep", file=sys.stderr, flush=True)
+        out["px_per_ns_sweep"] = sweep_leg(pd, torch, dev, wts, bias)
+        pyr_px = B * sum(L.w * L.h for L in levels)  # the timed leg: 256 frames, full pyramids, one launch per stage
+        out["px_per_ns_sweep"]["batched_1242x375_b256_pyramid"] = {
+            "hog_lbp": round(pyr_px / (per_launch["features"] * 1e6), 3),
+            "svm": round(pyr_px / (per_launch["score"] * 1e6), 3)}
     if not args.no_streaming:
         print("[bench] streaming leg", file=sys.stderr, flush=True)
         sprm = one.prm if not args.no_latency else pd.params()
