@@ -492,10 +492,10 @@ def main():
     if not args.no_sweep:
         print("[bench] px/ns sweep", file=sys.stderr, flush=True)
         out["px_per_ns_sweep"] = sweep_leg(pd, torch, dev, wts, bias)
-        pyr_px = B * sum(L.w * L.h for L in levels)  # the timed leg: 256 frames, full pyramids, one launch per stage
+        batch_px = B * sum(L.w * L.h for L in levels)  # the timed leg: 256 frames, full pyramids, one launch per stage
         out["px_per_ns_sweep"]["batched_1242x375_b256_pyramid"] = {
-            "hog_lbp": round(pyr_px / (per_launch["features"] * 1e6), 3),
-            "svm": round(pyr_px / (per_launch["score"] * 1e6), 3)}
+            "hog_lbp": round(batch_px / (per_launch["features"] * 1e6), 3),
+            "svm": round(batch_px / (per_launch["score"] * 1e6), 3)}
     if not args.no_streaming:
         print("[bench] streaming leg", file=sys.stderr, flush=True)
         sprm = one.prm if not args.no_latency else pd.params()
