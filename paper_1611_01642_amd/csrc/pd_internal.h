@@ -113,6 +113,16 @@ __device__ __forceinline__ gptr<T> gmem(T* p) {
     return (gptr<T>)p;
 }
 
+// Raw buffer view of `bytes` bytes at `base` (a level's feature planes, at
+// most 4 GiB): loads take a 32-bit lane offset and a wave-uniform byte offset
+// in a scalar register, with no per-value address arithmetic; a read past
+// `bytes` returns 0 instead of faulting.  Word 3 is the gfx9 raw-buffer format.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t planes_rsrc(const void* base, uint64_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0,
+                                             (int)(uint32_t)(bytes < 0xffffffffull ? bytes : 0xffffffffull),
+                                             0x00020000);
+}
+
 // FP32 -> BF16, round to nearest even (finite inputs).
 __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
     uint32_t u = __float_as_uint(f);

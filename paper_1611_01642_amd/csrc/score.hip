@@ -55,25 +55,31 @@ __device__ __forceinline__ void score_tile(gptr<const float> __restrict__ hog, g
 
     if (FEAT & PD_FEAT_HOG) {
         const size_t plane = (size_t)hb * wb;
-        int off[HOG_PQ];  // clamped plane offsets of this lane's patch values
+        // clamped byte offsets in a plane of this lane's patch values; the
+        // loads are raw buffer loads with the plane's byte offset as a scalar,
+        // so no address arithmetic is done per value
+        const auto rsrc = planes_rsrc(hog, (uint64_t)PD_HOG_BLOCK * plane * 4);
+        uint32_t off[HOG_PQ];
 #pragma unroll
         for (int q = 0; q < HOG_PQ; ++q) {
             const int e = min(lane + 64 * q, HOG_N - 1);
             const int gq = e / (HOG_PR * HOG_PC), rem = e - gq * (HOG_PR * HOG_PC);
             const int row = rem / HOG_PC, col = rem - (rem / HOG_PC) * HOG_PC;
-            off[q] = min((ty + gq) * STEP + row, hb - 1) * wb + min(j0 + col, wb - 1);
+            off[q] = 4u * (uint32_t)(min((ty + gq) * STEP + row, hb - 1) * wb + min(j0 + col, wb - 1));
         }
         float pre[HOG_PQ];
 #pragma unroll
-        for (int q = 0; q < HOG_PQ; ++q) pre[q] = hog[off[q]];
+        for (int q = 0; q < HOG_PQ; ++q)
+            pre[q] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rsrc, off[q], 0, 0));
         for (int c = 0; c < PD_HOG_BLOCK; ++c) {
 #pragma unroll
             for (int q = 0; q < HOG_PQ; ++q)
                 if (lane + 64 * q < HOG_N) patch[lane + 64 * q] = pre[q];
             if (c + 1 < PD_HOG_BLOCK) {
-                const auto nxt = hog + (size_t)(c + 1) * plane;
+                const uint32_t pofs = (uint32_t)((c + 1) * plane * 4);
 #pragma unroll
-                for (int q = 0; q < HOG_PQ; ++q) pre[q] = nxt[off[q]];
+                for (int q = 0; q < HOG_PQ; ++q)
+                    pre[q] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rsrc, off[q], pofs, 0));
             }
             __builtin_amdgcn_wave_barrier();
 #pragma unroll 1
@@ -98,25 +104,26 @@ __device__ __forceinline__ void score_tile(gptr<const float> __restrict__ hog, g
     if (FEAT & PD_FEAT_LBP) {
         const size_t plane = (size_t)hc * wc;
         const float* wl = wt + PD_HOG_DIM;
-        int off[LBP_PQ];
+        const auto rsrc = planes_rsrc(lbp, (uint64_t)PD_LBP_BINS * plane);
+        uint32_t off[LBP_PQ];  // clamped byte offsets in a plane (as for HOG)
 #pragma unroll
         for (int q = 0; q < LBP_PQ; ++q) {
             const int e = min(lane + 64 * q, LBP_N - 1);
             const int gq = e / (LBP_PR * LBP_PC), rem = e - gq * (LBP_PR * LBP_PC);
             const int row = rem / LBP_PC, col = rem - (rem / LBP_PC) * LBP_PC;
-            off[q] = min((ty + gq) * STEP + row, hc - 1) * wc + min(j0 + col, wc - 1);
+            off[q] = (uint32_t)(min((ty + gq) * STEP + row, hc - 1) * wc + min(j0 + col, wc - 1));
         }
         uint32_t pre[LBP_PQ];
 #pragma unroll
-        for (int q = 0; q < LBP_PQ; ++q) pre[q] = lbp[off[q]];
+        for (int q = 0; q < LBP_PQ; ++q) pre[q] = __builtin_amdgcn_raw_buffer_load_b8(rsrc, off[q], 0, 0);
         for (int c = 0; c < PD_LBP_BINS; ++c) {
 #pragma unroll
             for (int q = 0; q < LBP_PQ; ++q)
                 if (lane + 64 * q < LBP_N) patch[lane + 64 * q] = (float)pre[q];
             if (c + 1 < PD_LBP_BINS) {
-                const auto nxt = lbp + (size_t)(c + 1) * plane;
+                const uint32_t pofs = (uint32_t)((c + 1) * plane);
 #pragma unroll
-                for (int q = 0; q < LBP_PQ; ++q) pre[q] = nxt[off[q]];
+                for (int q = 0; q < LBP_PQ; ++q) pre[q] = __builtin_amdgcn_raw_buffer_load_b8(rsrc, off[q], pofs, 0);
             }
             __builtin_amdgcn_wave_barrier();
 #pragma unroll 1
