@@ -573,7 +573,7 @@ void fill_tables(const pd_frame* frames, int n_frames, int n_models, const Tunin
                 const int sr = tu.score_rows;
                 auto add = [&](const Tile& t, int groups) {
                     const bool single = std::min(t.ty + groups, nty) - 1 == t.ty;
-                    if (!L.prune && sr > 4 && single && it.ny - t.ty * sr <= sr / 2) half.push_back(t);
+                    if (!L.prune && sr >= 4 && single && it.ny - t.ty * sr <= sr / 2) half.push_back(t);
                     else t_sc[nsc++] = t;
                 };
                 for (int m = 0; m < n_models; ++m) {

@@ -177,7 +177,7 @@ hipError_t launch_features_cellmap_table(const LevelItem* items, const Tile* til
 hipError_t launch_score_single(const LevelItem& it, const float* w, const float* bias, int n_models,
                                int features, hipStream_t s);
 // n_dev (optional): the tile count is read from device memory (at most n_tiles).
-// n_half tiles after the n_tiles (rows 8 or 16 only) have at most half the
+// n_half tiles after the n_tiles have at most half the
 // rows valid and compute only those.
 hipError_t launch_score_table(const LevelItem* items, const Tile* tiles, int n_tiles,
                               const float* w, const float* bias, int n_models, int features,

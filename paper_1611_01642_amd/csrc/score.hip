@@ -209,7 +209,7 @@ __global__ void __launch_bounds__(256) score_table_kernel(const LevelItem* __res
             one(wave, std::integral_constant<int, R>());
     } else {
         const int main_blocks = ceil_div(n_tiles, SC_WAVES);  // before the device count applies
-        if constexpr (R > 4) {
+        if constexpr (R >= 4) {
             if ((int)blockIdx.x >= main_blocks) {
                 const int t = ((int)blockIdx.x - main_blocks) * SC_WAVES + wv;
                 if (t < n_half) one(n_tiles + t, std::integral_constant<int, R / 2>());
@@ -240,12 +240,11 @@ template <int FEAT>
 hipError_t score_table(const LevelItem* items, const Tile* tiles, int n, const float* w, const float* b,
                        const Tuning& tu, hipStream_t s, const int* nd, int n_half) {
     const int rows = tu.score_rows;
-    if (rows == 4) n_half = 0;  // none are made for 4 rows
     const int blocks = ceil_div(n, SC_WAVES) + ceil_div(n_half, SC_WAVES);
     const bool loop = tu.grid > 0 && tu.grid < blocks;
     const int grid = loop ? tu.grid : blocks;
     if (rows == 16) launch_rows<FEAT, 16>(loop, grid, items, tiles, n, w, b, nd, n_half, s);
-    else if (rows == 4) launch_rows<FEAT, 4>(loop, grid, items, tiles, n, w, b, nd, 0, s);
+    else if (rows == 4) launch_rows<FEAT, 4>(loop, grid, items, tiles, n, w, b, nd, n_half, s);
     else launch_rows<FEAT, SC_R>(loop, grid, items, tiles, n, w, b, nd, n_half, s);
     return hipGetLastError();
 }
