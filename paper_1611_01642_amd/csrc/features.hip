@@ -213,9 +213,15 @@ __device__ __forceinline__ void features_strip(gptr<const uint8_t> __restrict__ 
                 for (int k = 0; k < PD_HOG_BINS; ++k) o[k * plane] = hist[k] * inv;
             }
             if (cmap16) {
+                // a cell's 72 channels are 144 bytes, 16-byte aligned: channels
+                // 0..7 in one 16-byte store, channel 8 in a 2-byte one
                 const auto o = cmap16 + ((size_t)row * wc + cx) * PR_CP1;
+                uint32_t h2[4];
 #pragma unroll
-                for (int k = 0; k < PD_HOG_BINS; ++k) o[k] = f32_to_bf16(hist[k] * inv);
+                for (int k = 0; k < 4; ++k)
+                    h2[k] = (uint32_t)f32_to_bf16(hist[2 * k] * inv) | ((uint32_t)f32_to_bf16(hist[2 * k + 1] * inv) << 16);
+                *reinterpret_cast<gptr<uint4>>(o) = make_uint4(h2[0], h2[1], h2[2], h2[3]);
+                o[8] = f32_to_bf16(hist[8] * inv);
             }
         }
     };
@@ -441,13 +447,25 @@ __device__ __forceinline__ void features_strip(gptr<const uint8_t> __restrict__ 
                     for (int k = 0; k < PD_LBP_BINS; ++k, c += plane)
                         *c = (float)((cnt[k >> 2] >> (8 * (k & 3))) & 255u) * (1.0f / 64.0f);
                 }
-                if (CM && cmap16) {  // counts / 64 are exact in BF16; channels 68..71 zero
-                    const auto c = cmap16 + ((size_t)cy * wc + cx) * PR_CP1 + PD_HOG_BINS;
+                if (CM && cmap16) {
+                    // channels 9..71: counts / 64 (exact in BF16), then 4 zeros.
+                    // Bytes 18..143 of the cell's 16-byte aligned record: a
+                    // 2-, a 4- and an 8-byte store up to byte 32, then 7
+                    // 16-byte stores
+                    const auto cell = cmap16 + ((size_t)cy * wc + cx) * PR_CP1;
+                    auto ch = [&](int c) -> uint32_t {  // BF16 bits of channel c (9..71)
+                        const int k = c - PD_HOG_BINS;
+                        return k < PD_LBP_BINS
+                                   ? (uint32_t)f32_to_bf16((float)((cnt[k >> 2] >> (8 * (k & 3))) & 255u) * (1.0f / 64.0f))
+                                   : 0u;
+                    };
+                    auto two = [&](int c) { return ch(c) | (ch(c + 1) << 16); };
+                    cell[9] = (uint16_t)ch(9);
+                    *reinterpret_cast<gptr<uint32_t>>(cell + 10) = two(10);
+                    *reinterpret_cast<gptr<uint2>>(cell + 12) = make_uint2(two(12), two(14));
 #pragma unroll 1
-                    for (int k = 0; k < PD_LBP_BINS; ++k)
-                        c[k] = f32_to_bf16((float)((cnt[k >> 2] >> (8 * (k & 3))) & 255u) * (1.0f / 64.0f));
-#pragma unroll
-                    for (int k = PD_LBP_BINS; k < PR_CP1 - PD_HOG_BINS; ++k) c[k] = 0;
+                    for (int c = 16; c < PR_CP1; c += 8)
+                        *reinterpret_cast<gptr<uint4>>(cell + c) = make_uint4(two(c), two(c + 2), two(c + 4), two(c + 6));
                 }
             }
 #pragma unroll
