@@ -26,6 +26,8 @@
 //    masked cells in the final reduction.
 #include <cmath>
 
+#include <algorithm>
+
 #include "pd_internal.h"
 
 namespace pd {
@@ -305,12 +307,14 @@ __global__ void __launch_bounds__(256) window_labels_kernel(const float* __restr
 // ---- BF16 MFMA inference ------------------------------------------------------
 // Implicit GEMM per layer on v_mfma_f32_16x16x32_bf16: M = 16 cells of a row,
 // N = 16 output channels, K = (tap, input channel) with the channel vector of
-// each neighbour cell contiguous (channels-last maps).  A workgroup computes
-// 2 rows x 64 cells: it stages the 4 x 66 input cells and the layer's packed
-// weights (fragment order) in LDS; each wave owns 32 cells (2 M-tiles) of one
-// row and all output channels.  FP32 accumulation; bias and ReLU in FP32,
-// outputs rounded to BF16; the last layer applies the 1x1 head (cross-lane
-// sum over the 16 channels) and writes FP32 logits.
+// each neighbour cell contiguous (channels-last maps).  Persistent workgroups:
+// each wave loads the packed weight fragments of its output-channel tile into
+// registers once, then the workgroup loops over tiles of 2 rows x 64 cells,
+// staging the 4 x 66 input cells in LDS per tile; the waves sharing an
+// output-channel tile split its 8 M-tiles.  FP32 accumulation over K in
+// ascending order; bias and ReLU in FP32, outputs rounded to BF16; the last
+// layer applies the 1x1 head (cross-lane sum over its 16 channels) and writes
+// FP32 logits.
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
@@ -355,120 +359,106 @@ __global__ void __launch_bounds__(256) pack_bf16_kernel(const float* __restrict_
 
 template <int L>
 __global__ void __launch_bounds__(256) conv_mfma_kernel(const LevelItem* __restrict__ items,
-                                                        const Tile* __restrict__ tiles,
+                                                        const Tile* __restrict__ tiles, int n_tiles,
                                                         const uint16_t* __restrict__ packed,
                                                         const float* __restrict__ bias,
                                                         const float* __restrict__ head) {
     using D = LayerDims<L>;
     constexpr int CP = D::CP, XS = D::XS, KCH = D::KCH, NT = D::NT;
+    constexpr int WPN = 4 / NT;                  // waves per output-channel tile
+    constexpr int MT = (MR * MC / 16) / WPN;     // M-tiles per wave
+    static_assert(MT * WPN * 16 == MR * MC && (MC / 16) % MT == 0, "a wave's M-tiles lie in one row");
     __shared__ __attribute__((aligned(16))) uint16_t xs[XR * XC * XS];
-    __shared__ __attribute__((aligned(16))) uint16_t wsm[D::PACKED];
-    const Tile tl = tiles[blockIdx.x];
-    const LevelItem& it = items[tl.item];
-    const int wc = it.wc, hc = it.hc;
-    const int p0 = tl.ty * MR, q0 = tl.tx * MC;
-    const uint16_t* in = L == 1 ? it.cmap16 : (L == 2 ? it.act1 : it.act2);
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int nw = wave % NT;                    // this wave's output-channel tile
+    const int m0 = (wave / NT) * MT;             // its first M-tile (row-major over MR x MC / 16)
+    const int prow = m0 / (MC / 16), cbase = (m0 % (MC / 16)) * 16;
 
-    // stage weights and the (MR + 2) x (MC + 2) input cells, zero outside the
-    // map: every load of a thread is issued before its first LDS store
-    {
-        constexpr int NWQ = (D::PACKED / 8 + 255) / 256;
-        constexpr int PARTS = CP / 8;
-        constexpr int NXQ = (XR * XC * PARTS + 255) / 256;
-        const u32x4* src = reinterpret_cast<const u32x4*>(packed);
-        u32x4 wv[NWQ], xv[NXQ];
+    // this wave's B fragments, fragment order (K chunk t, N tile nw, lane)
+    u32x4 bw[KCH];
 #pragma unroll
-        for (int k = 0; k < NWQ; ++k) {
-            const int e = tid + 256 * k;
-            wv[k] = e < D::PACKED / 8 ? src[e] : u32x4{0u, 0u, 0u, 0u};
-        }
+    for (int t = 0; t < KCH; ++t) bw[t] = reinterpret_cast<const u32x4*>(packed)[(t * NT + nw) * 64 + lane];
+
+    for (int ti = blockIdx.x; ti < n_tiles; ti += gridDim.x) {
+        const Tile tl = tiles[ti];
+        const LevelItem& it = items[tl.item];
+        const int wc = it.wc, hc = it.hc;
+        const int p0 = tl.ty * MR, q0 = tl.tx * MC;
+        const uint16_t* in = L == 1 ? it.cmap16 : (L == 2 ? it.act1 : it.act2);
+        // stage the (MR + 2) x (MC + 2) input cells, zero outside the map:
+        // every load of a thread is issued before its first LDS store
+        {
+            constexpr int PARTS = CP / 8;
+            constexpr int NXQ = (XR * XC * PARTS + 255) / 256;
+            u32x4 xv[NXQ];
 #pragma unroll
-        for (int k = 0; k < NXQ; ++k) {
-            const int e = tid + 256 * k;
-            const int cell = e / PARTS, part = e - cell * PARTS;
-            const int r = cell / XC, col = cell - r * XC;
-            const int y = p0 - 1 + r, x = q0 - 1 + col;
-            xv[k] = u32x4{0u, 0u, 0u, 0u};
-            if (e < XR * XC * PARTS && y >= 0 && y < hc && x >= 0 && x < wc)
-                xv[k] = *reinterpret_cast<const u32x4*>(in + ((size_t)y * wc + x) * CP + 8 * part);
-        }
-        u32x4* dst = reinterpret_cast<u32x4*>(wsm);
-#pragma unroll
-        for (int k = 0; k < NWQ; ++k)
-            if (tid + 256 * k < D::PACKED / 8) dst[tid + 256 * k] = wv[k];
-#pragma unroll
-        for (int k = 0; k < NXQ; ++k) {
-            const int e = tid + 256 * k;
-            if (e < XR * XC * PARTS) {
+            for (int k = 0; k < NXQ; ++k) {
+                const int e = tid + 256 * k;
                 const int cell = e / PARTS, part = e - cell * PARTS;
-                *reinterpret_cast<u32x4*>(xs + cell * XS + 8 * part) = xv[k];
+                const int r = cell / XC, col = cell - r * XC;
+                const int y = p0 - 1 + r, x = q0 - 1 + col;
+                xv[k] = u32x4{0u, 0u, 0u, 0u};
+                if (e < XR * XC * PARTS && y >= 0 && y < hc && x >= 0 && x < wc)
+                    xv[k] = *reinterpret_cast<const u32x4*>(in + ((size_t)y * wc + x) * CP + 8 * part);
+            }
+            __syncthreads();  // the previous tile's reads of xs are done
+#pragma unroll
+            for (int k = 0; k < NXQ; ++k) {
+                const int e = tid + 256 * k;
+                if (e < XR * XC * PARTS) {
+                    const int cell = e / PARTS, part = e - cell * PARTS;
+                    *reinterpret_cast<u32x4*>(xs + cell * XS + 8 * part) = xv[k];
+                }
             }
         }
-    }
-    __syncthreads();
+        __syncthreads();
 
-    const int wave = tid >> 6, lane = tid & 63;
-    const int prow = wave >> 1;               // output row within the pair
-    const int cbase = (wave & 1) * 32;        // first cell of the wave within the tile
-    f32x4 acc[2][NT];
+        f32x4 acc[MT];
 #pragma unroll
-    for (int mt = 0; mt < 2; ++mt)
+        for (int mt = 0; mt < MT; ++mt) acc[mt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-        for (int n = 0; n < NT; ++n) acc[mt][n] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int t = 0; t < KCH; ++t) {
+            const int k0 = 32 * t + 8 * (lane >> 4);
+            const int tap = k0 / CP, c0 = k0 - tap * CP;
+            const int u = tap / 3, v = tap - 3 * (tap / 3);
+            const bf16x8 b = __builtin_bit_cast(bf16x8, bw[t]);
 #pragma unroll
-    for (int t = 0; t < KCH; ++t) {
-        const int k0 = 32 * t + 8 * (lane >> 4);
-        const int tap = k0 / CP, c0 = k0 - tap * CP;
-        const int u = tap / 3, v = tap - 3 * (tap / 3);
-        bf16x8 a[2];
-#pragma unroll
-        for (int mt = 0; mt < 2; ++mt) {
-            const int col = cbase + 16 * mt + (lane & 15);
-            u32x4 av = {0u, 0u, 0u, 0u};
-            if (tap < 9) av = *reinterpret_cast<const u32x4*>(xs + ((prow + u) * XC + col + v) * XS + c0);
-            a[mt] = __builtin_bit_cast(bf16x8, av);
+            for (int mt = 0; mt < MT; ++mt) {
+                const int col = cbase + 16 * mt + (lane & 15);
+                u32x4 av = {0u, 0u, 0u, 0u};
+                if (tap < 9) av = *reinterpret_cast<const u32x4*>(xs + ((prow + u) * XC + col + v) * XS + c0);
+                acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av), b, acc[mt], 0, 0, 0);
+            }
         }
-#pragma unroll
-        for (int n = 0; n < NT; ++n) {
-            const bf16x8 b =
-                __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(wsm + ((t * NT + n) * 64 + lane) * 8));
-#pragma unroll
-            for (int mt = 0; mt < 2; ++mt) acc[mt][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], b, acc[mt][n], 0, 0, 0);
-        }
-    }
 
-    // lane holds D[cell 4 * (lane / 16) + r][channel lane % 16] of each tile
-    const int p = p0 + prow;
-    if (L < 3) {
-        uint16_t* out = L == 1 ? it.act1 : it.act2;
+        // lane holds D[cell 4 * (lane / 16) + r][channel lane % 16] of each tile
+        const int p = p0 + prow;
+        const int och = 16 * nw + (lane & 15);
+        if (L < 3) {
+            uint16_t* out = L == 1 ? it.act1 : it.act2;
+            const float bo = bias[och];
 #pragma unroll
-        for (int n = 0; n < NT; ++n) {
-            const int och = 16 * n + (lane & 15);
-            const float b = bias[och];
-#pragma unroll
-            for (int mt = 0; mt < 2; ++mt)
+            for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int q = q0 + cbase + 16 * mt + 4 * (lane >> 4) + r;
-                    if (p < hc && q < wc) out[((size_t)p * wc + q) * 32 + och] = f32_to_bf16(fmaxf(acc[mt][n][r] + b, 0.0f));
+                    if (p < hc && q < wc) out[((size_t)p * wc + q) * 32 + och] = f32_to_bf16(fmaxf(acc[mt][r] + bo, 0.0f));
+                }
+        } else {
+            const float bo = bias[och], hw = head[och], hb = head[16];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    float z = hw * fmaxf(acc[mt][r] + bo, 0.0f);
+                    z += __shfl_xor(z, 8, 16);
+                    z += __shfl_xor(z, 4, 16);
+                    z += __shfl_xor(z, 2, 16);
+                    z += __shfl_xor(z, 1, 16);
+                    const int q = q0 + cbase + 16 * mt + 4 * (lane >> 4) + r;
+                    if ((lane & 15) == 0 && p < hc && q < wc) it.logit[(size_t)p * wc + q] = z + hb;
                 }
         }
-    } else {
-        const int och = lane & 15;
-        const float b = bias[och], hw = head[och], hb = head[16];
-#pragma unroll
-        for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                float z = hw * fmaxf(acc[mt][0][r] + b, 0.0f);
-                z += __shfl_xor(z, 8, 16);
-                z += __shfl_xor(z, 4, 16);
-                z += __shfl_xor(z, 2, 16);
-                z += __shfl_xor(z, 1, 16);
-                const int q = q0 + cbase + 16 * mt + 4 * (lane >> 4) + r;
-                if (och == 0 && p < hc && q < wc) it.logit[(size_t)p * wc + q] = z + hb;
-            }
     }
 }
 
@@ -590,10 +580,12 @@ hipError_t launch_pruner_mfma(const LevelItem* items, const Tile* tiles, int n_t
     const float* b2 = b1 + 32 + LayerDims<2>::PARAMS;
     const float* b3 = b2 + 32 + LayerDims<3>::PARAMS;
     const float* head = b3 + 16;
-    conv_mfma_kernel<1><<<n_tiles, 256, 0, s>>>(items, tiles, packed, b1, nullptr);
-    conv_mfma_kernel<2><<<n_tiles, 256, 0, s>>>(items, tiles, packed + LayerDims<1>::PACKED, b2, nullptr);
-    conv_mfma_kernel<3><<<n_tiles, 256, 0, s>>>(items, tiles, packed + LayerDims<1>::PACKED + LayerDims<2>::PACKED,
-                                                b3, head);
+    // persistent workgroups: a few per CU, each looping over the tiles
+    const int grid = std::min(n_tiles, 4 * 256);
+    conv_mfma_kernel<1><<<grid, 256, 0, s>>>(items, tiles, n_tiles, packed, b1, nullptr);
+    conv_mfma_kernel<2><<<grid, 256, 0, s>>>(items, tiles, n_tiles, packed + LayerDims<1>::PACKED, b2, nullptr);
+    conv_mfma_kernel<3><<<grid, 256, 0, s>>>(items, tiles, n_tiles,
+                                             packed + LayerDims<1>::PACKED + LayerDims<2>::PACKED, b3, head);
     return hipGetLastError();
 }
 
