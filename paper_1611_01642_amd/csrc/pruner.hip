@@ -310,7 +310,8 @@ __global__ void __launch_bounds__(256) window_labels_kernel(const float* __restr
 // each neighbour cell contiguous (channels-last maps).  Persistent workgroups:
 // each wave loads the packed weight fragments of its output-channel tile into
 // registers once, then the workgroup loops over tiles of 2 rows x 64 cells,
-// staging the 4 x 66 input cells in LDS per tile; the waves sharing an
+// staging the 4 x 66 input cells in LDS per tile (a contiguous run of the
+// table per workgroup); the waves sharing an
 // output-channel tile split its 8 M-tiles.  FP32 accumulation over K in
 // ascending order; bias and ReLU in FP32, outputs rounded to BF16; the last
 // layer applies the 1x1 head (cross-lane sum over its 16 channels) and writes
@@ -379,7 +380,12 @@ __global__ void __launch_bounds__(256) conv_mfma_kernel(const LevelItem* __restr
 #pragma unroll
     for (int t = 0; t < KCH; ++t) bw[t] = reinterpret_cast<const u32x4*>(packed)[(t * NT + nw) * 64 + lane];
 
-    for (int ti = blockIdx.x; ti < n_tiles; ti += gridDim.x) {
+    // a contiguous run of the (row-major) tile table per workgroup, so the
+    // input rows a tile shares with the previous row pair are still in this
+    // XCD's L2
+    const int run = (n_tiles + gridDim.x - 1) / gridDim.x;
+    const int t_end = min(n_tiles, ((int)blockIdx.x + 1) * run);
+    for (int ti = blockIdx.x * run; ti < t_end; ++ti) {
         const Tile tl = tiles[ti];
         const LevelItem& it = items[tl.item];
         const int wc = it.wc, hc = it.hc;
