@@ -299,12 +299,15 @@ def sweep_leg(pd, torch, dev, wts, bias, reps=20):
     return {"unit": "px/ns", "per_call": "one image, level 0 only", **out}
 
 
-def pruned_leg(pd, torch, dev, frames, plain_boxes, wts, bias, thr_value, steps, warmup, n_train, n_cal, epochs):
+def pruned_leg(pd, torch, dev, frames, plain_boxes, wts, bias, thr_value, steps, warmup, n_train, n_cal, epochs,
+               tune=False, cal_target=0.995):
     """The chosen form: learned pruning + BF16 MFMA scoring with FP64 rescoring.
     The pruner is trained here (n_train synthetic frames, the project's own
-    forward/backward kernels), K is calibrated for 99 % recall of the plain
-    FP32 detector's boxes on n_cal held-out frames, then the bench batch is
-    timed; recall on the bench batch itself is reported beside it."""
+    forward/backward kernels), K is calibrated for cal_target recall of the
+    plain FP32 detector's boxes on n_cal held-out frames (above the 99 % goal,
+    so that frames the calibration has not seen still reach it), then the
+    bench batch is timed; recall on the bench batch itself is reported beside
+    it."""
     import pd_synth
     from paper_1611_01642_amd import pruner_train as T
     t0 = time.perf_counter()
@@ -321,16 +324,17 @@ def pruned_leg(pd, torch, dev, frames, plain_boxes, wts, bias, thr_value, steps,
     cal_f = [torch.from_numpy(h).to(dev) for h in make_frames(n_cal, seed0=30000)]
     thr_cal = torch.full((n_cal,), thr_value, dtype=torch.float64, device=dev)
     bf = {"precision": pd.PREC_BF16}
-    k, r_cal, _, n_win = T.calibrate_keep(cal_f, wts, bias, thr_cal, pr, 0.99, prm_kw=bf, plain_kw={})
+    k, r_cal, _, n_win = T.calibrate_keep(cal_f, wts, bias, thr_cal, pr, cal_target, prm_kw=bf, plain_kw={})
     t3 = time.perf_counter()
     prm = pd.params(precision=pd.PREC_BF16, prune_keep=k, pruner=pr)
-    el, st, cnt = time_detect(pd, torch, frames, wts, bias, prm, thr_value, steps, warmup)
+    el, st, cnt = time_detect(pd, torch, frames, wts, bias, prm, thr_value, steps, warmup, tune=tune)
     B = len(frames)
     thr = torch.full((B,), thr_value, dtype=torch.float64, device=dev)
     r_bench, _ = T.recall_at(frames, wts, bias, thr, pr, k, plain_boxes, bf)
     return {"form": "learned pruning (top-K windows per frame) + BF16 MFMA scoring + FP64 rescore, 1 SVM",
             "value": round(B * steps / el, 1), "unit": "frames/s", "ms_per_step": round(1000 * el / steps, 4),
-            "keep_k": k, "keep_fraction": round(k / n_win, 4), "recall_calibration": round(r_cal, 4),
+            "keep_k": k, "keep_fraction": round(k / n_win, 4), "recall_target_calibration": cal_target,
+            "recall_calibration": round(r_cal, 4),
             "recall_bench_batch": round(r_bench, 4),
             "stage_ms_per_launch": {q: round(v, 4) for q, v in st.items()},
             "rescored_per_frame": round(float(np.mean([c["rescored"] for c in cnt])), 2),
@@ -358,6 +362,8 @@ def main():
     ap.add_argument("--train-frames", type=int, default=2000)
     ap.add_argument("--cal-frames", type=int, default=200)
     ap.add_argument("--epochs", type=int, default=4)
+    ap.add_argument("--cal-target", type=float, default=0.995,
+                    help="recall the pruner's K is calibrated for on held-out frames")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after timing, run one 256 MiB device-to-device copy (scales HBM byte counters)")
     args = ap.parse_args()
@@ -543,7 +549,8 @@ def main():
     if not args.no_pruned:
         print("[bench] pruned + BF16 leg (training the pruner)", file=sys.stderr, flush=True)
         out["chosen"] = pruned_leg(pd, torch, dev, frames, boxes, wts, bias, thr_value, args.steps, args.warmup,
-                                   args.train_frames, args.cal_frames, args.epochs)
+                                   args.train_frames, args.cal_frames, args.epochs, tune=not args.no_tune,
+                                   cal_target=args.cal_target)
         print(f"[bench] chosen: {out['chosen']['value']} frames/s at K {out['chosen']['keep_k']}",
               file=sys.stderr, flush=True)
     if not args.no_batched:

@@ -408,8 +408,9 @@ int pd_video_pop(pd_video* v, pd_box* boxes, int cap, pd_counts* counts, float* 
 int pd_video_destroy(pd_video* v);
 
 /*
- * pd_autotune -- times pd_detect on these arguments (one untimed call, then
- * `iters` calls between HIP events, per candidate) over the tuning fields of
+ * pd_autotune -- times pd_detect on these arguments (per candidate: one
+ * untimed call, then the least of three timings of `iters` calls between HIP
+ * events) over the tuning fields of
  * pd_params, one field at a time: feature strip rows {4, 6, 8, 12, 16},
  * FP32 scoring rows {4, 8, 16}, grid cap {0, 256, 512, 1024, 2048}; starting
  * from params' own values.  Writes params with the fastest fields to *best

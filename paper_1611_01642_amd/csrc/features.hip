@@ -452,15 +452,19 @@ __device__ __forceinline__ void features_strip(gptr<const uint8_t> __restrict__ 
                     // Bytes 18..143 of the cell's 16-byte aligned record: a
                     // 2-, a 4- and an 8-byte store up to byte 32, then 7
                     // 16-byte stores
+                    // A count is at most 64, so count / 64 has at most seven
+                    // significant bits: exact in BF16, whose bits are then the
+                    // FP32 value's upper half (no rounding step needed).
                     const auto cell = cmap16 + ((size_t)cy * wc + cx) * PR_CP1;
-                    auto ch = [&](int c) -> uint32_t {  // BF16 bits of channel c (9..71)
+                    auto ch = [&](int c) -> float {  // channel c (9..71) as FP32
                         const int k = c - PD_HOG_BINS;
-                        return k < PD_LBP_BINS
-                                   ? (uint32_t)f32_to_bf16((float)((cnt[k >> 2] >> (8 * (k & 3))) & 255u) * (1.0f / 64.0f))
-                                   : 0u;
+                        return k < PD_LBP_BINS ? (float)((cnt[k >> 2] >> (8 * (k & 3))) & 255u) * (1.0f / 64.0f)
+                                               : 0.0f;
                     };
-                    auto two = [&](int c) { return ch(c) | (ch(c + 1) << 16); };
-                    cell[9] = (uint16_t)ch(9);
+                    auto two = [&](int c) {  // BF16 bits of channels c, c + 1
+                        return __builtin_amdgcn_perm(__float_as_uint(ch(c + 1)), __float_as_uint(ch(c)), 0x07060302u);
+                    };
+                    cell[9] = (uint16_t)(__float_as_uint(ch(9)) >> 16);
                     *reinterpret_cast<gptr<uint32_t>>(cell + 10) = two(10);
                     *reinterpret_cast<gptr<uint2>>(cell + 12) = make_uint2(two(12), two(14));
 #pragma unroll 1

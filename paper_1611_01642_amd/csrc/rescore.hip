@@ -23,7 +23,10 @@
 //    values (over the partials, after a barrier);
 //  * dot products: the window's LBP counts are staged in LDS beside the HOG
 //    values; all 256 lanes stride over the 11332 features (coalesced FP32
-//    weights, four features in flight), then a fixed-order reduction.
+//    weights, 16 features in flight for one model, 6 x 8 for eight), then a
+//    fixed-order reduction.
+//  * gathers: a thread issues all of its pixel (and LBP count) loads before
+//    it stores any of them in LDS, so each gather costs one memory latency.
 #include "pd_internal.h"
 
 namespace pd {
@@ -44,6 +47,46 @@ struct RescoreShared {
     } u;
     double part[4][8];               // per wave, per model
 };
+
+constexpr int RS_PX_PER_T = (RS_PY * RS_PX + 255) / 256;   // pixel bytes gathered per thread
+constexpr int RS_LBP_PER_T = (PD_LBP_DIM + 255) / 256;     // LBP counts gathered per thread
+
+// Per-model partial dot products of the window's features (LDS) with the
+// weights, M = 1 or 8 models unrolled (models past n_models repeat the last
+// one; their sums are never read).  Thread t takes features t + 256 u; U
+// features per step, so a thread's M * U weight loads are in flight together.
+// Past the last feature x is 0 and the weight index is clamped.
+template <int M>
+__device__ __forceinline__ void dot_models(RescoreShared& sm, const float* __restrict__ weights, int n_models,
+                                           int t, int wave, int lane) {
+    constexpr int U = M == 1 ? 16 : 6;
+    double part[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) part[m] = 0.0;
+    for (int k0 = t; k0 < PD_FEATURE_DIM; k0 += 256 * U) {
+        float w[U][M];
+        double x[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int k = k0 + 256 * u;
+            const int kc = min(k, PD_FEATURE_DIM - 1);
+#pragma unroll
+            for (int m = 0; m < M; ++m) w[u][m] = weights[(size_t)min(m, n_models - 1) * PD_FEATURE_DIM + kc];
+            const double xv = kc < PD_HOG_DIM ? sm.u.x.hog[kc] : (double)sm.u.x.lbp[kc - PD_HOG_DIM];
+            x[u] = k < PD_FEATURE_DIM ? xv : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int m = 0; m < M; ++m) part[m] = fma(x[u], (double)w[u][m], part[m]);
+    }
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        double s = part[m];
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+        if (lane == 0) sm.part[wave][m] = s;
+    }
+}
 
 // Bilinear weight of pixel offset p in [0, 8) of a cell towards cell d in {-1, 0, 1}.
 __device__ __forceinline__ double spatial_w(int p, int d) {
@@ -70,12 +113,31 @@ __global__ void __launch_bounds__(256) rescore64_kernel(const LevelItem* __restr
         const LevelItem& it = items[first_item[f] + level];
         const int wi = key.y, wj = key.z;
 
-        // pixels of the window + one halo pixel, clamped to the level
-        for (int e = t; e < RS_PY * RS_PX; e += 256) {
-            const int r = e / RS_PX, c = e - (e / RS_PX) * RS_PX;
-            const int y = min(max(PD_CELL * wi - 1 + r, 0), it.h - 1);
-            const int x = min(max(PD_CELL * wj - 1 + c, 0), it.w - 1);
-            sm.px[r][c] = it.pyr[(size_t)y * it.pitch + x];
+        // the thread index as a value opaque to the compiler, so the gathers'
+        // index arithmetic stays in the loop instead of being held in
+        // registers across windows
+        int tt = t;
+        asm volatile("" : "+v"(tt));
+        // pixels of the window + one halo pixel, clamped to the level: every
+        // load of a thread in flight together, then the LDS stores
+        {
+            uint32_t v[RS_PX_PER_T];
+#pragma unroll
+            for (int k = 0; k < RS_PX_PER_T; ++k) {
+                const int e = min(tt + 256 * k, RS_PY * RS_PX - 1);
+                const int r = e / RS_PX, c = e - (e / RS_PX) * RS_PX;
+                const int y = min(max(PD_CELL * wi - 1 + r, 0), it.h - 1);
+                const int x = min(max(PD_CELL * wj - 1 + c, 0), it.w - 1);
+                v[k] = it.pyr[(size_t)y * it.pitch + x];
+            }
+#pragma unroll
+            for (int k = 0; k < RS_PX_PER_T; ++k) {
+                const int e = tt + 256 * k;
+                if (e < RS_PY * RS_PX) {
+                    const int r = e / RS_PX, c = e - (e / RS_PX) * RS_PX;
+                    sm.px[r][c] = (uint8_t)v[k];
+                }
+            }
         }
         __syncthreads();
 
@@ -171,46 +233,29 @@ __global__ void __launch_bounds__(256) rescore64_kernel(const LevelItem* __restr
             // LBP counts of the window's 16 x 8 cells: 8 contiguous bytes per
             // plane row, stored in feature order
             const size_t plane = (size_t)it.hc * it.wc;
-            for (int e = t; e < PD_LBP_DIM; e += 256) {
-                const int bin = e / (PD_WIN_CELLS_Y * PD_WIN_CELLS_X), cell = e - bin * (PD_WIN_CELLS_Y * PD_WIN_CELLS_X);
+            uint32_t v[RS_LBP_PER_T];
+#pragma unroll
+            for (int k = 0; k < RS_LBP_PER_T; ++k) {
+                const int e = min(tt + 256 * k, PD_LBP_DIM - 1);
+                const int bin = e / RS_CELLS, cell = e - bin * RS_CELLS;
                 const int a = cell / PD_WIN_CELLS_X, b = cell - a * PD_WIN_CELLS_X;
-                sm.u.x.lbp[cell * PD_LBP_BINS + bin] = it.lbp[bin * plane + (size_t)(wi + a) * it.wc + (wj + b)];
+                v[k] = it.lbp[bin * plane + (size_t)(wi + a) * it.wc + (wj + b)];
+            }
+#pragma unroll
+            for (int k = 0; k < RS_LBP_PER_T; ++k) {
+                const int e = tt + 256 * k;
+                if (e < PD_LBP_DIM) {
+                    const int bin = e / RS_CELLS, cell = e - bin * RS_CELLS;
+                    sm.u.x.lbp[cell * PD_LBP_BINS + bin] = (uint8_t)v[k];
+                }
             }
         }
         __syncthreads();
 
         // dot products over the 11332 features, all lanes, coalesced weights
-        // (models unrolled to 8 with guards, four features per step, so a
-        // thread's weight loads are in flight together; features from LDS)
-        double part[8];
-#pragma unroll
-        for (int m = 0; m < 8; ++m) part[m] = 0.0;
-        for (int k0 = t; k0 < PD_FEATURE_DIM; k0 += 1024) {
-            // unconditional loads at clamped indices (no branch per load):
-            // past the last feature x is 0; models past n_models repeat the
-            // last one and their sums are never read
-            float w[4][8];
-            double x[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int k = k0 + 256 * u;
-                const int kc = min(k, PD_FEATURE_DIM - 1);
-#pragma unroll
-                for (int m = 0; m < 8; ++m) w[u][m] = weights[(size_t)min(m, n_models - 1) * PD_FEATURE_DIM + kc];
-                const double xv = kc < PD_HOG_DIM ? sm.u.x.hog[kc] : (double)sm.u.x.lbp[kc - PD_HOG_DIM];
-                x[u] = k < PD_FEATURE_DIM ? xv : 0.0;
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int m = 0; m < 8; ++m) part[m] = fma(x[u], (double)w[u][m], part[m]);
-        }
-#pragma unroll
-        for (int m = 0; m < 8; ++m) {
-            double s = part[m];
-            for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-            if (lane == 0) sm.part[wave][m] = s;
-        }
+        // from the L2, a fixed-order reduction
+        if (n_models == 1) dot_models<1>(sm, weights, 1, t, wave, lane);
+        else dot_models<8>(sm, weights, n_models, t, wave, lane);
         __syncthreads();
         if (t == 0) {
             double best = 0.0;

@@ -35,6 +35,29 @@ __device__ __forceinline__ void resize_tile(gptr<const uint8_t> __restrict__ src
     __shared__ __attribute__((aligned(16))) uint8_t stage[RS_LDS];
     const int t = threadIdx.x;
     const int x_base = tx * RS_TX;
+    if (w == sw && h == sh) {
+        // the level is the image itself (every Q8 coordinate is the pixel's
+        // own index, fraction 0): a copy.  Lane: 4 output bytes from the two
+        // aligned source words that hold them; the second word is loaded only
+        // if it holds one of those bytes inside the row, so no load leaves the
+        // image's pages.
+        const int x0 = x_base + 4 * (t & 63);
+        if (x0 >= w) return;
+        const uint32_t keep = w - x0 >= 4 ? 0xffffffffu : (1u << (8 * (w - x0))) - 1u;
+        for (int r = t >> 6; r < rows; r += 4) {
+            const int y = y_base + r;
+            if (y >= h) break;
+            const auto a = src + (size_t)y * spitch + x0;
+            const int mis = (int)(reinterpret_cast<uintptr_t>(a) & 3);
+            const auto wp = reinterpret_cast<gptr<const uint32_t>>(a - mis);
+            const uint32_t w0 = wp[0];
+            const uint32_t w1 = mis > 0 && x0 + 4 - mis < w ? wp[1] : 0u;
+            const uint32_t v = __builtin_amdgcn_alignbyte(w1, w0, (uint32_t)mis);
+            // pitch is a multiple of 16 >= w, so the 4-byte store stays in the row
+            *reinterpret_cast<gptr<uint32_t>>(dst + (size_t)y * pitch + x0) = v & keep;
+        }
+        return;
+    }
     if (x_base + t < w) xs[t] = q8_coord(x_base + t, sw, w);
     if (t < rows && y_base + t < h) ys[t] = q8_coord(y_base + t, sh, h);
     __syncthreads();
