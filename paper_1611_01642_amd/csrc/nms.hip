@@ -4,14 +4,14 @@
 // compact: one thread per window; the window's score is the max over the
 //   models (lowest model index on ties); windows with score > threshold are
 //   appended to their frame's candidate list with an atomic counter.
-// nms: one workgroup per frame.  Candidates are sorted by (score descending,
+// nms: one workgroup (16 waves) per frame.  Candidates are sorted by (score descending,
 //   level, i, j ascending) with a bitonic sort in LDS; the greedy pass walks
 //   them in chunks of 64: a candidate is suppressed if it overlaps (IoU > 0.5,
 //   decided exactly as 2*inter > union on integer boxes) a box kept in an
 //   earlier chunk (tested in parallel; per-candidate flags, no atomics) or an
-//   earlier kept box of its own chunk (a 64x64 overlap mask resolved by one
-//   lane).  This is exactly the serial
-//   greedy algorithm, and needs no n x n mask in memory.
+//   earlier kept box of its own chunk (a 64x64 overlap mask, one row per lane,
+//   walked in order on the scalar unit).  This is exactly the serial greedy
+//   algorithm, and needs no n x n mask in memory.
 #include "pd_internal.h"
 
 namespace pd {
@@ -72,14 +72,19 @@ __global__ void __launch_bounds__(256) compact_kernel(const LevelItem* __restric
     }
 }
 
+// One workgroup of 16 waves per frame: the frame's LDS scratch allows one
+// workgroup per compute unit, and the overlap tests and the sort are
+// latency-bound, so the workgroup brings its own waves to hide the latency.
+constexpr int NMS_WAVES = 16;
+constexpr int NMS_THREADS = NMS_WAVES * 64;
+
 struct NmsSmem {
     unsigned long long key[PD_MAX_CANDIDATES];
     uint16_t sidx[PD_MAX_CANDIDATES];
     uint16_t kpos[PD_MAX_CANDIDATES];
     int4 kbox[PD_MAX_CANDIDATES];
     int4 cbox[64];
-    unsigned long long cmask[64];
-    uint16_t cpart[4][64];  // in-chunk overlap bits, 16 columns per part
+    unsigned long long cmask[64];  // in-chunk overlap bits: candidate q's later overlaps
     uint32_t supf[64];  // candidate of the chunk overlaps an earlier kept box (every writer stores 1)
     int nkept;
 };
@@ -125,7 +130,7 @@ __device__ void nms_frame(const NmsGeom& g, int frame, int raw_count, const floa
     const int n = min(raw_count, PD_MAX_CANDIDATES);
     int np2 = 64;
     while (np2 < n) np2 <<= 1;
-    for (int q = t; q < np2; q += 256) {
+    for (int q = t; q < np2; q += NMS_THREADS) {
         sm.key[q] = q < n ? sort_key(cs[q], ck[q]) : ~0ull;
         sm.sidx[q] = (uint16_t)q;
     }
@@ -133,7 +138,7 @@ __device__ void nms_frame(const NmsGeom& g, int frame, int raw_count, const floa
     __syncthreads();
     for (int k = 2; k <= np2; k <<= 1) {
         for (int jj = k >> 1; jj > 0; jj >>= 1) {
-            for (int q = t; q < np2; q += 256) {
+            for (int q = t; q < np2; q += NMS_THREADS) {
                 const int p = q ^ jj;
                 if (p > q) {
                     const unsigned long long a = sm.key[q], b = sm.key[p];
@@ -157,51 +162,70 @@ __device__ void nms_frame(const NmsGeom& g, int frame, int raw_count, const floa
             const int4 k = ck[sm.sidx[c0 + t]];
             sm.cbox[t] = window_box(g, k.x, k.y, k.z);
         }
-        if (t < 64) sm.supf[t] = 0u;
+        if (t < 64) {
+            sm.supf[t] = 0u;
+            sm.cmask[t] = 0ull;
+        }
         __syncthreads();
         const int K = sm.nkept;
-        for (int e = t; e < cn * K; e += 256) {
-            const int q = e % cn, kk = e / cn;
-            if (overlaps(sm.cbox[q], sm.kbox[kk])) sm.supf[q] = 1u;
-        }
-        {
-            // in-chunk overlaps: candidate q against the later ones, 16
-            // columns per thread (4 threads per candidate)
-            const int q = t & 63, part = t >> 6;
-            uint32_t m = 0;
-            if (q < cn)
-                for (int r = max(q + 1, 16 * part); r < min(cn, 16 * part + 16); ++r)
-                    if (overlaps(sm.cbox[q], sm.cbox[r])) m |= 1u << (r - 16 * part);
-            sm.cpart[part][q] = (uint16_t)m;
-        }
-        __syncthreads();
-        if (t < 64)
-            sm.cmask[t] = (unsigned long long)sm.cpart[0][t] | ((unsigned long long)sm.cpart[1][t] << 16) |
-                          ((unsigned long long)sm.cpart[2][t] << 32) | ((unsigned long long)sm.cpart[3][t] << 48);
-        __syncthreads();
-        if (t < 64) {  // wave 0: the chunk's surviving candidates as a bit mask
-            const unsigned long long sup = __ballot(t < cn && sm.supf[t] != 0u);
-            if (t == 0) {
-                unsigned long long alive = (cn == 64) ? ~0ull : ((1ull << cn) - 1);
-                alive &= ~sup;
-                int nk = sm.nkept;
-                for (int q = 0; q < cn; ++q) {
-                    if ((alive >> q) & 1ull) {
-                        sm.kbox[nk] = sm.cbox[q];
-                        sm.kpos[nk] = (uint16_t)(c0 + q);
-                        ++nk;
-                        alive &= ~sm.cmask[q];
-                    }
-                }
-                sm.nkept = nk;
+        const int q = t & 63, part = t >> 6;
+        if (q < cn) {
+            // against the boxes kept in earlier chunks: lane q of every wave
+            // takes candidate q, the NMS_WAVES waves split the kept list, two
+            // boxes per step
+            const int4 cb = sm.cbox[q];
+            bool hit = false;
+            for (int kk = part; kk < K && !hit; kk += 2 * NMS_WAVES) {
+                const int k2 = min(kk + NMS_WAVES, K - 1);
+                const int4 a = sm.kbox[kk], b = sm.kbox[k2];
+                hit = overlaps(cb, a) || overlaps(cb, b);
             }
+            if (hit) sm.supf[q] = 1u;
+            // in-chunk overlaps: candidate q against the later ones, four
+            // columns per wave, merged into the candidate's mask by LDS OR
+            unsigned long long m = 0;
+#pragma unroll
+            for (int u = 0; u < 64 / NMS_WAVES; ++u) {
+                const int r = (64 / NMS_WAVES) * part + u;
+                if (r > q && r < cn && overlaps(cb, sm.cbox[r])) m |= 1ull << r;
+            }
+            if (m) atomicOr(&sm.cmask[q], m);
+        }
+        __syncthreads();
+        if (t < 64) {
+            // wave 0 resolves the chunk: lane q holds candidate q's overlap mask;
+            // the greedy walk over the chunk runs on the scalar unit with each
+            // mask read from its lane, then the kept boxes are appended in
+            // candidate order, one lane each
+            const unsigned long long cm = q < cn ? sm.cmask[q] : 0ull;
+            const unsigned long long sup = __ballot(q < cn && sm.supf[q] != 0u);
+            unsigned long long alive = (cn == 64) ? ~0ull : ((1ull << cn) - 1);
+            alive &= ~sup;
+            const uint32_t cm_lo = (uint32_t)cm, cm_hi = (uint32_t)(cm >> 32);
+            // the lowest alive candidate not yet visited is kept; it removes
+            // the later ones it overlaps (its mask has only higher bits set)
+            unsigned long long todo = alive;
+            while (todo) {
+                const int r = __builtin_ctzll(todo);
+                const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane(cm_lo, r);
+                const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane(cm_hi, r);
+                const unsigned long long mr = (unsigned long long)lo | ((unsigned long long)hi << 32);
+                alive &= ~mr;
+                todo &= alive & ~(1ull << r);
+            }
+            if ((alive >> q) & 1ull) {
+                const int at = K + __popcll(alive & ((1ull << q) - 1ull));
+                sm.kbox[at] = sm.cbox[q];
+                sm.kpos[at] = (uint16_t)(c0 + q);
+            }
+            if (q == 0) sm.nkept = K + __popcll(alive);
         }
         __syncthreads();
     }
 
     const int K = sm.nkept;
     const int nout = min(K, cap);
-    for (int q = t; q < nout; q += 256) {
+    for (int q = t; q < nout; q += NMS_THREADS) {
         const int src = sm.sidx[sm.kpos[q]];
         const int4 k = ck[src];
         pd_box b;
@@ -229,7 +253,7 @@ __device__ void nms_frame(const NmsGeom& g, int frame, int raw_count, const floa
     }
 }
 
-__global__ void __launch_bounds__(256) nms_table_kernel(const NmsGeom* __restrict__ geoms,
+__global__ void __launch_bounds__(NMS_THREADS) nms_table_kernel(const NmsGeom* __restrict__ geoms,
                                                         const int32_t* __restrict__ counters,
                                                         const float* __restrict__ cand_score,
                                                         const int4* __restrict__ cand_key,
@@ -243,7 +267,7 @@ __global__ void __launch_bounds__(256) nms_table_kernel(const NmsGeom* __restric
               near_count ? near_count[f] : 0, boxes, cap, counts);
 }
 
-__global__ void __launch_bounds__(256) nms_single_kernel(NmsGeom g, int n, const float* __restrict__ cs,
+__global__ void __launch_bounds__(NMS_THREADS) nms_single_kernel(NmsGeom g, int n, const float* __restrict__ cs,
                                                          const int4* __restrict__ ck, pd_box* __restrict__ boxes,
                                                          int cap, pd_counts* __restrict__ counts) {
     nms_frame(g, 0, n, cs, ck, nullptr, 0, boxes, cap, counts);
@@ -294,7 +318,7 @@ hipError_t launch_nms_table(const NmsGeom* geoms, int n_frames, const int32_t* c
     static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&nms_table_kernel),
                                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kNmsSmem);
     if (attr != hipSuccess) return attr;
-    nms_table_kernel<<<n_frames, 256, kNmsSmem, s>>>(geoms, counters, cand_score, cand_key, cand_s64, near_count,
+    nms_table_kernel<<<n_frames, NMS_THREADS, kNmsSmem, s>>>(geoms, counters, cand_score, cand_key, cand_s64, near_count,
                                                     boxes, cap, counts);
     return hipGetLastError();
 }
@@ -304,7 +328,7 @@ hipError_t launch_nms_single(const NmsGeom& g, int n, const float* cand_score, c
     static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&nms_single_kernel),
                                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kNmsSmem);
     if (attr != hipSuccess) return attr;
-    nms_single_kernel<<<1, 256, kNmsSmem, s>>>(g, n, cand_score, cand_key, boxes, cap, counts);
+    nms_single_kernel<<<1, NMS_THREADS, kNmsSmem, s>>>(g, n, cand_score, cand_key, boxes, cap, counts);
     return hipGetLastError();
 }
 
