@@ -161,28 +161,49 @@ def calibrate_threshold(pd, torch, calib, wts, bias, prm):
     return 0.5 * (s[k - 1] + s[k])
 
 
+def timed_runs(pd, torch, det, thr, steps, warmup):
+    """The timed region: `steps` HIP-graph replays of the pipeline, back to
+    back after `warmup` untimed ones.  Each timed step replays its own
+    capture (level and tile tables uploaded once at capture; every replay
+    recomputes each stage from the frame buffers), and each capture holds HIP
+    events at the stage boundaries, so the stage times are those of exactly
+    the timed replays.  Then the same number of eager pd_detect calls, for
+    the eager rate.  Returns (graph s, eager s, mean stage ms per replay)."""
+    pd.profile_enable(True)
+    det.capture_steps(thr, steps)
+    pd.profile_enable(False)
+    for k in range(warmup):
+        det.replay_step(k % steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        det.replay_step(k)
+    torch.cuda.synchronize()
+    graph_s = time.perf_counter() - t0
+    per = [det.step_stage_ms(k) for k in range(steps)]
+    stages = {q: sum(p[q] for p in per) / steps for q in per[0]}
+    det.release()
+    det.run(thr)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        det.run(thr)
+    torch.cuda.synchronize()
+    eager_s = time.perf_counter() - t0
+    return graph_s, eager_s, stages
+
+
 def time_detect(pd, torch, frames, wts, bias, prm, thr_value, steps, warmup, tune=False):
-    """(seconds for `steps` pd_detect calls, per-stage ms per call, counts);
-    with `tune`, after the autotuner has picked the tile shapes."""
+    """(graph seconds for `steps` calls, per-stage ms per call, counts, eager
+    seconds); with `tune`, after the autotuner has picked the tile shapes."""
     B = len(frames)
     thr = torch.full((B,), thr_value, dtype=torch.float64, device=frames[0].device)
     det = pd.Detector(frames, wts, bias, prm, cap=1024)
     if tune:
         det.autotune(thr, iters=3)
-    for _ in range(warmup):
-        det.run(thr)
-    torch.cuda.synchronize()
-    pd.profile_enable(True)
-    pd.profile_read(reset=True)
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        det.run(thr)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    stage_ms, calls = pd.profile_read(reset=True)
-    pd.profile_enable(False)
+    graph_s, eager_s, stages = timed_runs(pd, torch, det, thr, steps, warmup)
     _, counts = det.results()
-    return elapsed, {k: v / max(calls, 1) for k, v in stage_ms.items()}, counts
+    return graph_s, stages, counts, eager_s
 
 
 def lbp_block_leg(pd, torch, frames, calib, prm, steps, warmup):
@@ -213,7 +234,7 @@ def lbp_block_leg(pd, torch, frames, calib, prm, steps, warmup):
     torch.cuda.synchronize()
     fold_ms = e0.elapsed_time(e1)
     thr = calibrate_threshold(pd, torch, calib, wc_model, bias, pd.params())
-    el, st, cnt = time_detect(pd, torch, frames, wc_model, bias, prm, thr, steps, warmup)
+    el, st, cnt, _ = time_detect(pd, torch, frames, wc_model, bias, prm, thr, steps, warmup)
     return {"alg3_blocks_ms": round(ms, 4), "alg3_blocks_gbs": round(nbytes / (ms / 1000) / 1e9, 1),
             "alg3_blocks_workload": f"{n} x 59 x {hc}x{wc} cell counts (level 0 of the batch) -> uint16 blocks",
             "fold_ms": round(fold_ms, 4), "value": round(B * steps / el, 1), "unit": "frames/s",
@@ -327,13 +348,13 @@ def pruned_leg(pd, torch, dev, frames, plain_boxes, wts, bias, thr_value, steps,
     k, r_cal, _, n_win = T.calibrate_keep(cal_f, wts, bias, thr_cal, pr, cal_target, prm_kw=bf, plain_kw={})
     t3 = time.perf_counter()
     prm = pd.params(precision=pd.PREC_BF16, prune_keep=k, pruner=pr)
-    el, st, cnt = time_detect(pd, torch, frames, wts, bias, prm, thr_value, steps, warmup, tune=tune)
+    el, st, cnt, el_eager = time_detect(pd, torch, frames, wts, bias, prm, thr_value, steps, warmup, tune=tune)
     B = len(frames)
     thr = torch.full((B,), thr_value, dtype=torch.float64, device=dev)
     r_bench, _ = T.recall_at(frames, wts, bias, thr, pr, k, plain_boxes, bf)
     return {"form": "learned pruning (top-K windows per frame) + BF16 MFMA scoring + FP64 rescore, 1 SVM",
             "value": round(B * steps / el, 1), "unit": "frames/s", "ms_per_step": round(1000 * el / steps, 4),
-            "keep_k": k, "keep_fraction": round(k / n_win, 4), "recall_target_calibration": cal_target,
+            "eager_frames_per_s": round(B * steps / el_eager, 1), "keep_k": k, "keep_fraction": round(k / n_win, 4), "recall_target_calibration": cal_target,
             "recall_calibration": round(r_cal, 4),
             "recall_bench_batch": round(r_bench, 4),
             "stage_ms_per_launch": {q: round(v, 4) for q, v in st.items()},
@@ -411,23 +432,10 @@ def main():
         print("[bench] autotuning tile shapes", file=sys.stderr, flush=True)
         tuning, _ = det.autotune(thr, iters=3)
         prm = det.prm
-    print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
-        det.run(thr)
-    torch.cuda.synchronize()
-    pd.profile_enable(True)
-    pd.profile_read(reset=True)
-    print(f"[bench] timing {args.steps} steps of {B} frames", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        det.run(thr)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    stage_ms, calls = pd.profile_read(reset=True)
-    pd.profile_enable(False)
+    print(f"[bench] capture, warmup {args.warmup}, timing {args.steps} graph replays of {B} frames, then "
+          f"{args.steps} eager calls with stage events", file=sys.stderr, flush=True)
+    elapsed, eager_elapsed, per_launch = timed_runs(pd, torch, det, thr, args.steps, args.warmup)
     boxes, counts = det.results()
-    per_launch = {k: v / max(calls, 1) for k, v in stage_ms.items()}
 
     latency_ms = latency_graph_ms = latency_tuning = None
     if not args.no_latency:
@@ -483,6 +491,11 @@ def main():
                                "1 linear SVM, stride 8, threshold at the 99th percentile, greedy NMS IoU 0.5",
                    "global_batch": B, "frame": "1242x375", "levels": len(levels),
                    "windows_per_frame": windows, "parallelism": "single GPU"},
+        "timing": "HIP-graph replays of the captured pipeline, back to back (level and tile tables uploaded "
+                  "once at capture; each replay recomputes every stage from the frame buffers); stage times "
+                  "from HIP events captured in each timed replay; eager_frames_per_s: the same steps as "
+                  "pd_detect calls",
+        "eager_frames_per_s": round(B * args.steps / eager_elapsed, 1),
         "roofline": roof,
         "stage_ms_per_launch": {k: round(v, 4) for k, v in per_launch.items()},
         "score_tflops": round(score_flops / score_s / 1e12, 3),
@@ -514,11 +527,12 @@ def main():
             bm = torch.from_numpy(pd_synth.svm_bias(m)).to(dev)
             prm16 = pd.params(precision=pd.PREC_BF16, margin=0.05)
             t16 = calibrate_threshold(pd, torch, calib, wm, bm, prm16)
-            el, st, cnt = time_detect(pd, torch, frames, wm, bm, prm16, t16, args.steps, args.warmup,
-                                      tune=not args.no_tune)
+            el, st, cnt, el_eager = time_detect(pd, torch, frames, wm, bm, prm16, t16, args.steps, args.warmup,
+                                                tune=not args.no_tune)
             sflops = 2.0 * 11332 * windows * B * m
             legs[f"bf16_{m}model"] = {
                 "value": round(B * args.steps / el, 1), "unit": "frames/s", "ms_per_step": round(1000 * el / args.steps, 4),
+                "eager_frames_per_s": round(B * args.steps / el_eager, 1),
                 "stage_ms_per_launch": {k: round(v, 4) for k, v in st.items()},
                 "score_tflops_useful": round(sflops / (st["score"] / 1000) / 1e12, 2),
                 "rescored_per_frame": round(float(np.mean([c["rescored"] for c in cnt])), 2),
@@ -536,10 +550,11 @@ def main():
             wz = wts.clone()
             wz[:, dims] = 0
             ts = calibrate_threshold(pd, torch, calib, wz, bias, pd.params())
-            el, st, cnt = time_detect(pd, torch, frames, wz, bias, pd.params(features=feat), ts, args.steps,
-                                      args.warmup, tune=not args.no_tune)
+            el, st, cnt, el_eager = time_detect(pd, torch, frames, wz, bias, pd.params(features=feat), ts,
+                                                args.steps, args.warmup, tune=not args.no_tune)
             legs[name] = {
                 "value": round(B * args.steps / el, 1), "unit": "frames/s", "ms_per_step": round(1000 * el / args.steps, 4),
+                "eager_frames_per_s": round(B * args.steps / el_eager, 1),
                 "stage_ms_per_launch": {k: round(v, 4) for k, v in st.items()},
                 "detections_per_frame": round(float(np.mean([c["kept"] for c in cnt])), 2),
                 "candidates_per_frame": round(float(np.mean([c["candidates"] for c in cnt])), 2)}

@@ -356,6 +356,19 @@ int pd_graph_launch(pd_graph* graph, void* stream);
    sure no launch is still running. */
 int pd_graph_destroy(pd_graph* graph);
 
+/*
+ * pd_graph_stage_ms -- for a graph created while pd_profile_enable was on
+ * (the capture then holds, before each stage and after the last one, a
+ * one-wave kernel that writes the device's constant-rate clock into a slot
+ * the graph owns): waits for the device to go idle and writes to host
+ * ms[PD_N_STAGES] the most recent launch's time per stage (the upload stage
+ * is ~0: a graph holds no copy).  Before the first launch the values are
+ * meaningless.
+ * Errors: PD_E_ARG if graph is NULL or was captured without stage stamps;
+ * PD_E_HIP from the device queries.
+ */
+int pd_graph_stage_ms(pd_graph* graph, double* ms);
+
 /* ---- streaming video (Section 4.1 steps 1 and 5 around steps 2-4) ------- */
 /*
  * A video stream of frames of one size that arrive one at a time in host

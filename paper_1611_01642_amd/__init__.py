@@ -123,6 +123,7 @@ _SIGS = {
                                     ctypes.c_void_p]),
     "pd_video_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "pd_graph_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "pd_graph_stage_ms": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "pd_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                    ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                    ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
@@ -529,6 +530,30 @@ class Detector:
         if g is not None:
             self._graph = None
             _check(lib().pd_graph_destroy(g))
+        for h in getattr(self, "_steps", []):
+            _check(lib().pd_graph_destroy(h))
+        self._steps = []
+
+    def capture_steps(self, thresholds, n: int) -> None:
+        """n separate captures of the pipeline (replay_step(k)); captured
+        while profile_enable(True) is on, each holds its own stage events,
+        so step_stage_ms(k) gives replay k's stage times even when the n
+        replays run back to back."""
+        self.release()
+        self._thr_keep = thresholds
+        for _ in range(n):
+            h = ctypes.c_void_p(0)
+            _check(lib().pd_graph_create(*self._args(thresholds), _stream(), ctypes.byref(h)))
+            self._steps.append(h)
+
+    def replay_step(self, k: int) -> None:
+        _check(lib().pd_graph_launch(self._steps[k], _stream()))
+
+    def step_stage_ms(self, k: int) -> dict:
+        """Per-stage GPU ms of the most recent replay of capture k."""
+        ms = (ctypes.c_double * len(STAGES))()
+        _check(lib().pd_graph_stage_ms(self._steps[k], ms))
+        return dict(zip(STAGES, list(ms)))
 
     def __del__(self):
         try:

@@ -410,9 +410,17 @@ struct Profile {
 };
 thread_local Profile g_prof;
 
-// Records the boundary events of one pd_detect call (or nothing when off).
+// The device's constant-rate clock into *slot (a stage boundary of a captured
+// graph: a kernel node, ordered after the previous stage's kernels).
+__global__ void stamp_kernel(unsigned long long* slot) {
+    if (threadIdx.x == 0) *slot = __builtin_amdgcn_s_memrealtime();
+}
+
+// Records the boundary events of one pd_detect call (or nothing when off);
+// with `stamps` set (graph captures), clock stamps instead of events.
 struct StageMarks {
     std::vector<hipEvent_t> ev;
+    unsigned long long* stamps = nullptr;
     explicit StageMarks(bool on) {
         if (!on) return;
         for (int k = 0; k <= PD_N_STAGES; ++k) {
@@ -427,6 +435,7 @@ struct StageMarks {
         }
     }
     void mark(int k, hipStream_t s) {
+        if (stamps) stamp_kernel<<<1, 64, 0, s>>>(stamps + k);
         if (!ev.empty() && ev[k]) (void)hipEventRecord(ev[k], s);
     }
     void commit() {
@@ -1167,6 +1176,7 @@ int pd_detect(const pd_frame* frames, int n_frames, const float* weights, const 
 struct pd_graph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    unsigned long long* stamps = nullptr;  // stage boundary clock stamps (captured with profiling on)
 };
 
 int pd_graph_create(const pd_frame* frames, int n_frames, const float* weights, const float* bias, int n_models,
@@ -1192,11 +1202,17 @@ int pd_graph_create(const pd_frame* frames, int n_frames, const float* weights, 
     hipStream_t cs = nullptr;  // capture needs a stream other than the null stream
     if ((rc = hip_status(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "capture stream"))) return rc;
     pd_graph* g = new pd_graph();
-    rc = hip_status(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture");
+    StageMarks marks(false);
+    if (g_prof.on) {  // the graph's own stamp slots
+        rc = hip_status(hipMalloc(&g->stamps, (PD_N_STAGES + 1) * sizeof(unsigned long long)), "stage stamps");
+        marks.stamps = g->stamps;
+    }
+    if (!rc) rc = hip_status(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture");
     if (!rc) {
-        StageMarks none(false);
+        marks.mark(PD_STAGE_UPLOAD, cs);
         const int rc_enq = enqueue_detect(R, L, tuning_of(params), weights, bias, n_models, params, thresholds,
-                                          n_frames, boxes, cap, counts, none, cs);
+                                          n_frames, boxes, cap, counts, marks, cs);
+        marks.mark(PD_N_STAGES, cs);
         const int rc_end = hip_status(hipStreamEndCapture(cs, &g->graph), "end capture");
         rc = rc_enq ? rc_enq : rc_end;
     }
@@ -1205,6 +1221,7 @@ int pd_graph_create(const pd_frame* frames, int n_frames, const float* weights, 
     if (rc) {
         if (g->exec) (void)hipGraphExecDestroy(g->exec);
         if (g->graph) (void)hipGraphDestroy(g->graph);
+        if (g->stamps) (void)hipFree(g->stamps);
         delete g;
         return rc;
     }
@@ -1225,8 +1242,27 @@ int pd_graph_destroy(pd_graph* g) {
         const int r2 = hip_status(hipGraphDestroy(g->graph), "graph destroy");
         rc = rc ? rc : r2;
     }
+    if (g->stamps) {
+        const int r3 = hip_status(hipFree(g->stamps), "stage stamps");
+        rc = rc ? rc : r3;
+    }
     delete g;
     return rc;
+}
+
+int pd_graph_stage_ms(pd_graph* g, double* ms) {
+    if (!g || !ms) return fail(PD_E_ARG, "graph or ms is NULL");
+    if (!g->stamps) return fail(PD_E_ARG, "graph was captured without stage stamps");
+    int dev = 0, khz = 0;
+    int rc = hip_status(hipDeviceSynchronize(), "stage stamps");
+    if (!rc) rc = hip_status(hipGetDevice(&dev), "stage stamps");
+    if (!rc) rc = hip_status(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev), "clock rate");
+    unsigned long long t[PD_N_STAGES + 1] = {};
+    if (!rc) rc = hip_status(hipMemcpy(t, g->stamps, sizeof(t), hipMemcpyDeviceToHost), "stage stamps");
+    if (rc) return rc;
+    if (khz <= 0) return fail(PD_E_HIP, "device reports no constant clock rate");
+    for (int k = 0; k < PD_N_STAGES; ++k) ms[k] = (double)(int64_t)(t[k + 1] - t[k]) / (double)khz;
+    return PD_OK;
 }
 
 int pd_autotune(const pd_frame* frames, int n_frames, const float* weights, const float* bias, int n_models,

@@ -131,6 +131,8 @@ def test_tuning_field_checks_and_graph_handles():
         assert pd.workspace_bytes([(1242, 375)], 2, pd.params(**kw)) == pd.workspace_bytes([(1242, 375)], 2)
     assert L.pd_graph_destroy(nil) == 0
     assert L.pd_graph_launch(nil, nil) == pd.E_ARG
+    ms = (ctypes.c_double * len(pd.STAGES))()
+    assert L.pd_graph_stage_ms(nil, ms) == pd.E_ARG
     arr = (pd.Frame * 1)()
     arr[0].data, arr[0].w, arr[0].h, arr[0].pitch = 0x1000, 100, 100, 100
     prm = pd.params()

@@ -6,6 +6,8 @@ A captured graph is replayed several times with new pixels written into the
 same frame buffers and new thresholds, with other eager work in between;
 every replay must equal an eager pd_detect on the same inputs.
 """
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -94,6 +96,42 @@ def test_graph_replays_equal_eager(prec, m):
         _same(exp, got)
         assert sum(int(c["kept"]) for c in got[1]) > 0
     g.release()
+
+
+def test_graph_stage_events_per_capture():
+    """Captures taken while stage profiling is on carry their own stage clock
+    stamps: replayed back to back, each reports its own stage times (upload
+    about 0: a graph copies nothing; the others positive), and the replays'
+    result equals eager pd_detect."""
+    frames = _frames(8000)
+    wts = to_dev(pd_synth.svm_weights(1))
+    bias = to_dev(np.zeros(1, np.float32))
+    thr = to_dev(np.full(3, 2.5))
+    prm = pd.params()
+    det = pd.Detector(frames, wts, bias, prm, cap=1024)
+    pd.profile_enable(True)
+    try:
+        det.capture_steps(thr, 3)
+    finally:
+        pd.profile_enable(False)
+    exp = _run(frames, wts, bias, prm, thr)
+    for k in range(3):
+        print(f"\n[graph stages] replay {k}", flush=True)
+        det.replay_step(k)
+    torch.cuda.synchronize()
+    for k in range(3):
+        st = det.step_stage_ms(k)
+        print(f"[graph stages] capture {k}: {st}", flush=True)
+        assert 0.0 <= st["upload"] < 0.05
+        assert all(st[q] > 0.0 for q in ("resize", "features", "score", "compact", "nms"))
+        assert sum(st.values()) < 1000.0
+    _same(exp, det.results())
+    det.release()
+    # a capture without profiling has no stage stamps
+    det.capture(thr)
+    with pytest.raises(pd.PdError):
+        pd._check(pd.lib().pd_graph_stage_ms(det._graph, (ctypes.c_double * len(pd.STAGES))()))
+    det.release()
 
 
 def test_autotune_gives_valid_fields_and_same_results():
