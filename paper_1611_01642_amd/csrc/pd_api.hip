@@ -296,7 +296,7 @@ struct DetectLayout {
     int64_t off_kth = 0, off_kept = 0, off_prpack = 0;
     std::vector<int64_t> cm_off, a1_off, a2_off, lg_off;  // per item (pruning)
     int64_t off_items = 0, off_tiles = 0, off_geoms = 0, off_first = 0, off_counters = 0, off_cscore = 0,
-            off_ckey = 0, off_c64 = 0, off_near_count = 0, off_near_key = 0, off_packed = 0;
+            off_ckey = 0, off_c64 = 0, off_near_count = 0, off_near_key = 0, off_packed = 0, off_orient = 0;
     int64_t off_data = 0, total = 0;
     int64_t table_bytes = 0;  // bytes uploaded from the host (items .. geoms)
     std::vector<int> level_count;         // per frame
@@ -380,6 +380,8 @@ bool plan_detect(const pd_frame* frames, int n_frames, const pd_params* p, int n
         o = align_up(o + (int64_t)n_frames * MAX_NEAR * 16, kAlign);
         L.off_packed = o;
         o = align_up(o + (packed_weight_elems() + rowgemm_packed_elems()) * 2, kAlign);
+        L.off_orient = o;
+        o = align_up(o + ORIENT_BYTES, kAlign);
     }
     if (L.prune) {
         L.off_kth = o;
@@ -481,6 +483,7 @@ struct DetectRun {
     double* c64 = nullptr;
     int4* near_key = nullptr;
     uint16_t* packed = nullptr;
+    double2* orient = nullptr;  // FP64 rescore's gradient table (BF16 precision)
     int n_zero = 0;  // counters + near counters (+ kept-tile count), cleared together
     const Tile* t_pr = nullptr;  // pruner conv tiles
     int npr = 0;
@@ -636,6 +639,7 @@ void fill_tables(const pd_frame* frames, int n_frames, int n_models, const Tunin
     R.c64 = L.bf16 ? reinterpret_cast<double*>(ws + L.off_c64) : nullptr;
     R.near_key = L.bf16 ? reinterpret_cast<int4*>(ws + L.off_near_key) : nullptr;
     R.packed = L.bf16 ? reinterpret_cast<uint16_t*>(ws + L.off_packed) : nullptr;
+    R.orient = L.bf16 ? reinterpret_cast<double2*>(ws + L.off_orient) : nullptr;
     R.n_zero = (int)((L.off_cscore - L.off_counters) / 4);
     if (L.prune) {
         R.t_pr = d_tiles + L.n_rs + L.n_ft + L.n_sc + L.n_cp;
@@ -656,6 +660,7 @@ int enqueue_detect(const DetectRun& R, const DetectLayout& L, const Tuning& tu, 
     marks.mark(PD_STAGE_ZERO, s);
     if ((rc = hip_status(launch_zero_i32(R.counters, R.n_zero, s), "zero"))) return rc;
     if (L.bf16) {
+        if ((rc = hip_status(launch_orient_table(R.orient, s), "gradient table"))) return rc;
         if ((rc = hip_status(launch_pack_weights(weights, n_models, R.packed, s), "pack"))) return rc;
         if ((rc = hip_status(launch_pack_rowgemm(weights, R.packed + packed_weight_elems(), s), "pack"))) return rc;
     }
@@ -701,7 +706,8 @@ int enqueue_detect(const DetectRun& R, const DetectLayout& L, const Tuning& tu, 
             return rc;
         if (L.bf16 && (rc = hip_status(launch_rescore64(R.items, R.first, n_frames, R.near_count, R.near_key,
                                                         weights, bias, n_models, params->clip, params->eps,
-                                                        thresholds, R.counters, R.cscore, R.ckey, R.c64, s),
+                                                        thresholds, R.counters, R.cscore, R.ckey, R.c64, R.orient,
+                                                        s),
                                        "rescore")))
             return rc;
         marks.mark(PD_STAGE_NMS, s);
@@ -737,7 +743,7 @@ int enqueue_detect(const DetectRun& R, const DetectLayout& L, const Tuning& tu, 
         return rc;
     if (L.bf16 && (rc = hip_status(launch_rescore64(R.items, R.first, n_frames, R.near_count, R.near_key, weights,
                                                     bias, n_models, params->clip, params->eps, thresholds,
-                                                    R.counters, R.cscore, R.ckey, R.c64, s),
+                                                    R.counters, R.cscore, R.ckey, R.c64, R.orient, s),
                                    "rescore")))
         return rc;
     marks.mark(PD_STAGE_NMS, s);

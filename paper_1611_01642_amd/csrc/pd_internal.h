@@ -216,10 +216,16 @@ hipError_t launch_compact_margin(const LevelItem* items, const Tile* tiles, int 
                                  int n_frames, hipStream_t s);
 // near_count[n_frames] is the length of the dense near list near_key
 // (entries: frame * PD_MAX_LEVELS + level, i, j, model)
+// Gradient table of the FP64 rescore: entry dy * ORIENT_W + dx + 255 (dy in
+// 0..255, dx in -255..255) holds (orientation bin coordinate, magnitude).
+constexpr int ORIENT_W = 511, ORIENT_H = 256;
+constexpr int64_t ORIENT_BYTES = (int64_t)ORIENT_W * ORIENT_H * 16;
+hipError_t launch_orient_table(double2* table, hipStream_t s);
 hipError_t launch_rescore64(const LevelItem* items, const int32_t* frame_first_item, int n_frames,
                             const int32_t* near_count, const int4* near_key, const float* weights,
                             const float* bias, int n_models, float clip, float eps, const double* thresholds,
-                            int32_t* counters, float* cand_score, int4* cand_key, double* cand_s64, hipStream_t s);
+                            int32_t* counters, float* cand_score, int4* cand_key, double* cand_s64,
+                            const double2* orient, hipStream_t s);
 hipError_t launch_compact_table(const LevelItem* items, const Tile* tiles, int n_tiles, int n_models,
                                 const double* thresholds, int32_t* counters, float* cand_score,
                                 int4* cand_key, hipStream_t s);

@@ -4,7 +4,8 @@
 // frame's threshold cannot be classified safely (Section 4.4: positive iff
 // the distance to the hyper-plane exceeds the threshold).  This kernel
 // recomputes such a window's features from the pixels of its pyramid level in
-// FP64 -- gradients (Algorithm 4) with the device's double atan2, trilinear
+// FP64 -- gradients (Algorithm 4; orientation and magnitude from a table of
+// every integer gradient, built in FP64 with the device's double atan2), trilinear
 // HOG votes (Algorithm 5) as per-cell direction partials, L2-Hys -- takes its
 // LBP counts (exact integers) from the feature planes, and scores every model
 // in FP64 with the FP32 weights.  A window whose FP64 score (max over models)
@@ -88,6 +89,23 @@ __device__ __forceinline__ void dot_models(RescoreShared& sm, const float* __res
     }
 }
 
+// The gradient table: for dy in 0..255 and dx in -255..255, the
+// orientation's bin coordinate t = angle / 20 - 0.5 in [-0.5, 8.5) (angle in
+// degrees, folded into [0, 180): Algorithm 4 with the device's double atan2)
+// and the magnitude sqrt(dx^2 + dy^2), both FP64.  A gradient with dy < 0
+// looks up (-dx, -dy): the same magnitude and, mathematically, the same
+// folded angle (its FP64 value may differ in the last bits).
+__global__ void orient_table_kernel(double2* __restrict__ table) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= ORIENT_W * ORIENT_H) return;
+    const int dy = e / ORIENT_W, dx = e - dy * ORIENT_W - 255;
+    const double mag = sqrt((double)(dx * dx + dy * dy));
+    double ang = atan2((double)dy, (double)dx) * 57.295779513082320876798154814105;
+    if (ang < 0.0) ang += 180.0;
+    if (ang >= 180.0) ang -= 180.0;
+    table[e] = make_double2(ang / 20.0 - 0.5, mag);
+}
+
 // Bilinear weight of pixel offset p in [0, 8) of a cell towards cell d in {-1, 0, 1}.
 __device__ __forceinline__ double spatial_w(int p, int d) {
     const double w = 1.0 - fabs((double)p + 0.5 - (8.0 * d + 4.0)) / 8.0;
@@ -102,7 +120,8 @@ __global__ void __launch_bounds__(256) rescore64_kernel(const LevelItem* __restr
                                                         const float* __restrict__ bias, int n_models, double clip,
                                                         double eps, const double* __restrict__ thresholds,
                                                         int32_t* __restrict__ counters, float* __restrict__ cand_score,
-                                                        int4* __restrict__ cand_key, double* __restrict__ cand_s64) {
+                                                        int4* __restrict__ cand_key, double* __restrict__ cand_s64,
+                                                        const double2* __restrict__ orient) {
     __shared__ RescoreShared sm;
     const int t = threadIdx.x;
     const int wave = t >> 6, lane = t & 63;
@@ -156,16 +175,19 @@ __global__ void __launch_bounds__(256) rescore64_kernel(const LevelItem* __restr
             for (int pr = 0; pr < 4; ++pr) {
                 const int py = 4 * half + pr;
                 const double wy0 = spatial_w(py, half - 1), wy1 = spatial_w(py, half);
+                // the row's eight table entries in flight together
+                double2 g[PD_CELL];
 #pragma unroll
                 for (int px = 0; px < PD_CELL; ++px) {
                     const int r = PD_CELL * cy + py + 1, c = PD_CELL * cx + px + 1;
                     const int dx = (int)sm.px[r][c - 1] - (int)sm.px[r][c + 1];   // Algorithm 4
                     const int dy = (int)sm.px[r - 1][c] - (int)sm.px[r + 1][c];
-                    const double mag = sqrt((double)(dx * dx + dy * dy));
-                    double ang = atan2((double)dy, (double)dx) * 57.295779513082320876798154814105;
-                    if (ang < 0.0) ang += 180.0;
-                    if (ang >= 180.0) ang -= 180.0;
-                    const double tb = ang / 20.0 - 0.5;            // [-0.5, 8.5)
+                    const int s = dy < 0 ? -1 : 1;
+                    g[px] = orient[(s * dy) * ORIENT_W + s * dx + 255];
+                }
+#pragma unroll
+                for (int px = 0; px < PD_CELL; ++px) {
+                    const double tb = g[px].x, mag = g[px].y;
                     double h[PD_HOG_BINS];                         // linear vote per bin (wrap-around)
                     h[0] = fmax(0.0, 1.0 - fmin(fabs(tb), fabs(tb - 9.0)));
 #pragma unroll
@@ -283,15 +305,21 @@ __global__ void __launch_bounds__(256) rescore64_kernel(const LevelItem* __restr
 
 }  // namespace
 
+hipError_t launch_orient_table(double2* table, hipStream_t s) {
+    orient_table_kernel<<<ceil_div(ORIENT_W * ORIENT_H, 256), 256, 0, s>>>(table);
+    return hipGetLastError();
+}
+
 hipError_t launch_rescore64(const LevelItem* items, const int32_t* frame_first_item, int n_frames,
                             const int32_t* near_count, const int4* near_key, const float* weights, const float* bias,
                             int n_models, float clip, float eps, const double* thresholds, int32_t* counters,
-                            float* cand_score, int4* cand_key, double* cand_s64, hipStream_t s) {
+                            float* cand_score, int4* cand_key, double* cand_s64, const double2* orient,
+                            hipStream_t s) {
     if (n_frames <= 0) return hipSuccess;
     const int grid = min(n_frames * MAX_NEAR, 1024);
     rescore64_kernel<<<grid, 256, 0, s>>>(items, frame_first_item, n_frames, near_count, near_key, weights, bias,
                                          n_models, (double)clip, (double)eps, thresholds, counters, cand_score,
-                                         cand_key, cand_s64);
+                                         cand_key, cand_s64, orient);
     return hipGetLastError();
 }
 
