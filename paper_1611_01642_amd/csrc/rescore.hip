@@ -24,10 +24,13 @@
 //    values (over the partials, after a barrier);
 //  * dot products: the window's LBP counts are staged in LDS beside the HOG
 //    values; all 256 lanes stride over the 11332 features (coalesced FP32
-//    weights, 16 features in flight for one model, 6 x 8 for eight), then a
-//    fixed-order reduction.
+//    weights; one model: 16 features in flight per lane; several: four
+//    consecutive features per lane and step, one 16-byte weight load per
+//    model, 8 x 8 in flight), then a fixed-order reduction;
 //  * gathers: a thread issues all of its pixel (and LBP count) loads before
-//    it stores any of them in LDS, so each gather costs one memory latency.
+//    it stores any of them in LDS, so each gather costs one memory latency;
+//    pixel rows and LBP runs are read as aligned 4-byte words where the
+//    window allows it.
 #include "pd_internal.h"
 
 namespace pd {
@@ -37,8 +40,15 @@ constexpr int RS_PY = PD_WIN_H + 2;  // 130 pixel rows incl. halo
 constexpr int RS_PX = PD_WIN_W + 2;  // 66 pixel columns incl. halo
 constexpr int RS_CELLS = PD_WIN_CELLS_Y * PD_WIN_CELLS_X;  // 128
 
+// LDS pixel rows: byte RS_PX0 + c holds window column c - 1 (c = 0 .. 65),
+// so that a row's source bytes from an aligned word boundary land on aligned
+// LDS words
+constexpr int RS_PX0 = 3;
+constexpr int RS_ROW = 72;                 // 18 words per row
+constexpr int RS_ROW_WORDS = RS_ROW / 4;
+
 struct RescoreShared {
-    uint8_t px[RS_PY][RS_PX + 2];
+    uint8_t px[RS_PY][RS_ROW];
     union {
         double A[RS_CELLS][81];      // per cell: 3x3 target cells x 9 bins
         struct {
@@ -49,8 +59,10 @@ struct RescoreShared {
     double part[4][8];               // per wave, per model
 };
 
-constexpr int RS_PX_PER_T = (RS_PY * RS_PX + 255) / 256;   // pixel bytes gathered per thread
-constexpr int RS_LBP_PER_T = (PD_LBP_DIM + 255) / 256;     // LBP counts gathered per thread
+constexpr int RS_PX_PER_T = (RS_PY * RS_PX + 255) / 256;   // pixel bytes gathered per thread (border windows)
+constexpr int RS_PXW_PER_T = (RS_PY * RS_ROW_WORDS + 255) / 256;  // pixel words per thread (inner windows)
+constexpr int RS_LBP_RUNS = PD_LBP_BINS * PD_WIN_CELLS_Y;  // 8-byte runs: one plane row of the window
+constexpr int RS_RUNS_PER_T = (RS_LBP_RUNS + 255) / 256;
 
 // Per-model partial dot products of the window's features (LDS) with the
 // weights, M = 1 or 8 models unrolled (models past n_models repeat the last
@@ -80,6 +92,59 @@ __device__ __forceinline__ void dot_models(RescoreShared& sm, const float* __res
         for (int u = 0; u < U; ++u)
 #pragma unroll
             for (int m = 0; m < M; ++m) part[m] = fma(x[u], (double)w[u][m], part[m]);
+    }
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        double s = part[m];
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+        if (lane == 0) sm.part[wave][m] = s;
+    }
+}
+
+// The same with each thread taking four consecutive features per step
+// (groups g = t + 256 u of 4: one 16-byte weight load per model; 3780 and
+// 11332 are multiples of 4, so a group is all HOG or all LBP).  Needs 16-byte
+// aligned weights.
+template <int M>
+__device__ __forceinline__ void dot_models4(RescoreShared& sm, const float4* __restrict__ w4, int n_models, int t,
+                                            int wave, int lane) {
+    constexpr int G = PD_FEATURE_DIM / 4;
+    constexpr int U = M == 1 ? 4 : 2;
+    double part[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) part[m] = 0.0;
+    for (int g0 = t; g0 < G; g0 += 256 * U) {
+        float4 w[U][M];
+        double x[U][4];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int g = g0 + 256 * u;
+            const int gc = min(g, G - 1);
+#pragma unroll
+            for (int m = 0; m < M; ++m) w[u][m] = w4[(size_t)min(m, n_models - 1) * G + gc];
+            const int k = 4 * gc;
+            if (k < PD_HOG_DIM) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) x[u][j] = sm.u.x.hog[k + j];
+            } else {
+                const uint32_t b = *reinterpret_cast<const uint32_t*>(&sm.u.x.lbp[k - PD_HOG_DIM]);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) x[u][j] = (double)((b >> (8 * j)) & 255u);
+            }
+            if (g >= G) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) x[u][j] = 0.0;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int m = 0; m < M; ++m) {
+                part[m] = fma(x[u][0], (double)w[u][m].x, part[m]);
+                part[m] = fma(x[u][1], (double)w[u][m].y, part[m]);
+                part[m] = fma(x[u][2], (double)w[u][m].z, part[m]);
+                part[m] = fma(x[u][3], (double)w[u][m].w, part[m]);
+            }
     }
 #pragma unroll
     for (int m = 0; m < M; ++m) {
@@ -121,7 +186,7 @@ __global__ void __launch_bounds__(256) rescore64_kernel(const LevelItem* __restr
                                                         double eps, const double* __restrict__ thresholds,
                                                         int32_t* __restrict__ counters, float* __restrict__ cand_score,
                                                         int4* __restrict__ cand_key, double* __restrict__ cand_s64,
-                                                        const double2* __restrict__ orient) {
+                                                        const double2* __restrict__ orient, bool vec_w) {
     __shared__ RescoreShared sm;
     const int t = threadIdx.x;
     const int wave = t >> 6, lane = t & 63;
@@ -137,9 +202,28 @@ __global__ void __launch_bounds__(256) rescore64_kernel(const LevelItem* __restr
         // registers across windows
         int tt = t;
         asm volatile("" : "+v"(tt));
-        // pixels of the window + one halo pixel, clamped to the level: every
-        // load of a thread in flight together, then the LDS stores
-        {
+        // pixels of the window + one halo pixel: every load of a thread in
+        // flight together, then the LDS stores.  A window whose halo lies
+        // inside the level reads aligned words (its rows start 1 byte before
+        // an 8-byte boundary of a 4-byte aligned row; the last word holds the
+        // halo column, so no word leaves the row); others read bytes,
+        // clamped to the level.
+        const bool inner = wi > 0 && wj > 0 && PD_CELL * wi + PD_WIN_H < it.h && PD_CELL * wj + PD_WIN_W < it.w;
+        if (inner) {
+            const auto base = it.pyr + (size_t)(PD_CELL * wi - 1) * it.pitch + (PD_CELL * wj - 4);
+            uint32_t v[RS_PXW_PER_T];
+#pragma unroll
+            for (int k = 0; k < RS_PXW_PER_T; ++k) {
+                const int e = min(tt + 256 * k, RS_PY * RS_ROW_WORDS - 1);
+                const int r = e / RS_ROW_WORDS, d = e - r * RS_ROW_WORDS;
+                v[k] = *reinterpret_cast<const uint32_t*>(base + (size_t)r * it.pitch + 4 * d);
+            }
+#pragma unroll
+            for (int k = 0; k < RS_PXW_PER_T; ++k) {
+                const int e = tt + 256 * k;
+                if (e < RS_PY * RS_ROW_WORDS) reinterpret_cast<uint32_t*>(&sm.px[0][0])[e] = v[k];
+            }
+        } else {
             uint32_t v[RS_PX_PER_T];
 #pragma unroll
             for (int k = 0; k < RS_PX_PER_T; ++k) {
@@ -154,7 +238,7 @@ __global__ void __launch_bounds__(256) rescore64_kernel(const LevelItem* __restr
                 const int e = tt + 256 * k;
                 if (e < RS_PY * RS_PX) {
                     const int r = e / RS_PX, c = e - (e / RS_PX) * RS_PX;
-                    sm.px[r][c] = (uint8_t)v[k];
+                    sm.px[r][RS_PX0 + c] = (uint8_t)v[k];
                 }
             }
         }
@@ -180,8 +264,8 @@ __global__ void __launch_bounds__(256) rescore64_kernel(const LevelItem* __restr
 #pragma unroll
                 for (int px = 0; px < PD_CELL; ++px) {
                     const int r = PD_CELL * cy + py + 1, c = PD_CELL * cx + px + 1;
-                    const int dx = (int)sm.px[r][c - 1] - (int)sm.px[r][c + 1];   // Algorithm 4
-                    const int dy = (int)sm.px[r - 1][c] - (int)sm.px[r + 1][c];
+                    const int dx = (int)sm.px[r][RS_PX0 + c - 1] - (int)sm.px[r][RS_PX0 + c + 1];  // Algorithm 4
+                    const int dy = (int)sm.px[r - 1][RS_PX0 + c] - (int)sm.px[r + 1][RS_PX0 + c];
                     const int s = dy < 0 ? -1 : 1;
                     g[px] = orient[(s * dy) * ORIENT_W + s * dx + 255];
                 }
@@ -222,6 +306,27 @@ __global__ void __launch_bounds__(256) rescore64_kernel(const LevelItem* __restr
         }
         __syncthreads();
 
+        // LBP counts of the window's 16 x 8 cells: one run of 8 bytes per
+        // plane row, read as the aligned words that hold it (each holds a
+        // byte of the run, so none leaves the planes); issued here so that
+        // they arrive during the block sums, stored in feature order after
+        // them (their LDS space is the partials')
+        uint32_t lw[RS_RUNS_PER_T][3];
+        uint32_t loff[RS_RUNS_PER_T];
+        {
+            const size_t plane = (size_t)it.hc * it.wc;
+#pragma unroll
+            for (int k = 0; k < RS_RUNS_PER_T; ++k) {
+                const int e = min(tt + 256 * k, RS_LBP_RUNS - 1);
+                const int bin = e / PD_WIN_CELLS_Y, a = e - bin * PD_WIN_CELLS_Y;
+                const uint8_t* p = it.lbp + bin * plane + (size_t)(wi + a) * it.wc + wj;
+                loff[k] = (uint32_t)(reinterpret_cast<uintptr_t>(p) & 3);
+                const uint32_t* q = reinterpret_cast<const uint32_t*>(p - loff[k]);
+                lw[k][0] = q[0];
+                lw[k][1] = q[1];
+                lw[k][2] = loff[k] ? q[2] : 0u;
+            }
+        }
         // blocks: slot (r, c) of block (by, bx) sums the partials its 4 cells aim at it
         double v[PD_HOG_BLOCK];
         double inv = 0.0;
@@ -252,23 +357,19 @@ __global__ void __launch_bounds__(256) rescore64_kernel(const LevelItem* __restr
         if (blk)
             for (int k = 0; k < PD_HOG_BLOCK; ++k) sm.u.x.hog[t * PD_HOG_BLOCK + k] = v[k] * inv;
         {
-            // LBP counts of the window's 16 x 8 cells: 8 contiguous bytes per
-            // plane row, stored in feature order
-            const size_t plane = (size_t)it.hc * it.wc;
-            uint32_t v[RS_LBP_PER_T];
 #pragma unroll
-            for (int k = 0; k < RS_LBP_PER_T; ++k) {
-                const int e = min(tt + 256 * k, PD_LBP_DIM - 1);
-                const int bin = e / RS_CELLS, cell = e - bin * RS_CELLS;
-                const int a = cell / PD_WIN_CELLS_X, b = cell - a * PD_WIN_CELLS_X;
-                v[k] = it.lbp[bin * plane + (size_t)(wi + a) * it.wc + (wj + b)];
-            }
-#pragma unroll
-            for (int k = 0; k < RS_LBP_PER_T; ++k) {
+            for (int k = 0; k < RS_RUNS_PER_T; ++k) {
                 const int e = tt + 256 * k;
-                if (e < PD_LBP_DIM) {
-                    const int bin = e / RS_CELLS, cell = e - bin * RS_CELLS;
-                    sm.u.x.lbp[cell * PD_LBP_BINS + bin] = (uint8_t)v[k];
+                if (e < RS_LBP_RUNS) {
+                    const int bin = e / PD_WIN_CELLS_Y, a = e - bin * PD_WIN_CELLS_Y;
+                    const uint32_t lo = __builtin_amdgcn_alignbyte(lw[k][1], lw[k][0], loff[k]);
+                    const uint32_t hi = __builtin_amdgcn_alignbyte(lw[k][2], lw[k][1], loff[k]);
+                    uint8_t* dst = &sm.u.x.lbp[(a * PD_WIN_CELLS_X) * PD_LBP_BINS + bin];
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) {
+                        dst[b * PD_LBP_BINS] = (uint8_t)(lo >> (8 * b));
+                        dst[(b + 4) * PD_LBP_BINS] = (uint8_t)(hi >> (8 * b));
+                    }
                 }
             }
         }
@@ -276,8 +377,13 @@ __global__ void __launch_bounds__(256) rescore64_kernel(const LevelItem* __restr
 
         // dot products over the 11332 features, all lanes, coalesced weights
         // from the L2, a fixed-order reduction
-        if (n_models == 1) dot_models<1>(sm, weights, 1, t, wave, lane);
-        else dot_models<8>(sm, weights, n_models, t, wave, lane);
+        if (vec_w && n_models > 1) {
+            dot_models4<8>(sm, reinterpret_cast<const float4*>(weights), n_models, t, wave, lane);
+        } else if (n_models == 1) {
+            dot_models<1>(sm, weights, 1, t, wave, lane);
+        } else {
+            dot_models<8>(sm, weights, n_models, t, wave, lane);
+        }
         __syncthreads();
         if (t == 0) {
             double best = 0.0;
@@ -319,7 +425,7 @@ hipError_t launch_rescore64(const LevelItem* items, const int32_t* frame_first_i
     const int grid = min(n_frames * MAX_NEAR, 1024);
     rescore64_kernel<<<grid, 256, 0, s>>>(items, frame_first_item, n_frames, near_count, near_key, weights, bias,
                                          n_models, (double)clip, (double)eps, thresholds, counters, cand_score,
-                                         cand_key, cand_s64, orient);
+                                         cand_key, cand_s64, orient, ((uintptr_t)weights & 15) == 0);
     return hipGetLastError();
 }
 
