@@ -128,15 +128,18 @@ def cpu_baseline(frames_per_core=2, max_cores=16):
                       f"mean {1000 * sum(per) / n:.0f} ms per frame per core"}
 
 
-def measured_traffic(kernel, batch):
+def measured_traffic(kernel, batch, tuning):
     """HBM bytes per launch of `kernel` from the committed counter record, or
-    None when the record is for another batch or the kernel source changed."""
+    None when the record is for another batch, another tile shape of that
+    kernel, or the kernel source changed."""
     import hashlib
     path = os.path.join(HERE, "profiles", "traffic_road1242x375_b256.json")
     if batch != 256 or not os.path.exists(path):
         return None
     rec = json.load(open(path)).get(kernel)
     if not rec:
+        return None
+    if any(tuning.get(k) != v for k, v in rec.get("tuning", {}).items()):
         return None
     src = os.path.join(HERE, rec["source"])
     if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["sha256"]:
@@ -379,6 +382,9 @@ def main():
     ap.add_argument("--no-sweep", action="store_true", help="skip the px/ns sweep over image sizes")
     ap.add_argument("--no-batched", action="store_true", help="skip the mixed-size batched leg")
     ap.add_argument("--no-tune", action="store_true", help="default tile shapes (no autotuning)")
+    ap.add_argument("--tuning", type=str, default=None,
+                    help="FEAT_ROWS,SCORE_ROWS,GRID: fixed tile shapes of the plain leg instead of the autotuner "
+                         "(the counter passes use them, so both passes see the same kernels)")
     ap.add_argument("--no-pruned", action="store_true", help="skip the learned-pruning leg")
     ap.add_argument("--train-frames", type=int, default=2000)
     ap.add_argument("--cal-frames", type=int, default=200)
@@ -426,9 +432,12 @@ def main():
     thr_value = 0.5 * (s[k - 1] + s[k])
     thr = torch.full((B,), thr_value, dtype=torch.float64, device=dev)
 
+    if args.tuning:
+        fr, sr, gr = (int(x) for x in args.tuning.split(","))
+        prm = pd.params(tune_feat_rows=fr, tune_score_rows=sr, tune_grid=gr)
     det = pd.Detector(frames, wts, bias, prm, cap=1024)
     tuning = prm.tuning()
-    if not args.no_tune:
+    if not args.no_tune and not args.tuning:
         print("[bench] autotuning tile shapes", file=sys.stderr, flush=True)
         tuning, _ = det.autotune(thr, iters=3)
         prm = det.prm
@@ -472,13 +481,13 @@ def main():
         roof = {"kernel": "score_table_kernel (FP32 window scoring)", "bound": "alu",
                 "achieved": round(achieved, 3), "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-                "traffic": measured_traffic("score_table_kernel", B)}
+                "traffic": measured_traffic("score_table_kernel", B, tuning)}
     else:
         achieved = feat_bytes / feat_s / 1e9
         roof = {"kernel": "features_table_kernel (HOG+LBP)", "bound": "hbm",
                 "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": round(achieved / PEAK_HBM_GBS, 4),
-                "traffic": measured_traffic("features_table_kernel", B)}
+                "traffic": measured_traffic("features_table_kernel", B, tuning)}
 
     value = B * args.steps / elapsed
     out = {
