@@ -385,39 +385,46 @@ __global__ void __launch_bounds__(256) conv_mfma_kernel(const LevelItem* __restr
     // XCD's L2
     const int run = (n_tiles + gridDim.x - 1) / gridDim.x;
     const int t_end = min(n_tiles, ((int)blockIdx.x + 1) * run);
-    for (int ti = blockIdx.x * run; ti < t_end; ++ti) {
+    // the (MR + 2) x (MC + 2) input cells of a tile, zero outside the map, into
+    // registers; the next tile's loads are issued before this tile's MFMAs
+    // (software pipeline: the loads are in flight while the matrix cores run)
+    constexpr int PARTS = CP / 8;
+    constexpr int NXQ = (XR * XC * PARTS + 255) / 256;
+    u32x4 xv[NXQ];
+    auto load_tile = [&](int ti) __attribute__((always_inline)) {
         const Tile tl = tiles[ti];
         const LevelItem& it = items[tl.item];
         const int wc = it.wc, hc = it.hc;
         const int p0 = tl.ty * MR, q0 = tl.tx * MC;
         const uint16_t* in = L == 1 ? it.cmap16 : (L == 2 ? it.act1 : it.act2);
-        // stage the (MR + 2) x (MC + 2) input cells, zero outside the map:
-        // every load of a thread is issued before its first LDS store
-        {
-            constexpr int PARTS = CP / 8;
-            constexpr int NXQ = (XR * XC * PARTS + 255) / 256;
-            u32x4 xv[NXQ];
 #pragma unroll
-            for (int k = 0; k < NXQ; ++k) {
-                const int e = tid + 256 * k;
+        for (int k = 0; k < NXQ; ++k) {
+            const int e = tid + 256 * k;
+            const int cell = e / PARTS, part = e - cell * PARTS;
+            const int r = cell / XC, col = cell - r * XC;
+            const int y = p0 - 1 + r, x = q0 - 1 + col;
+            xv[k] = u32x4{0u, 0u, 0u, 0u};
+            if (e < XR * XC * PARTS && y >= 0 && y < hc && x >= 0 && x < wc)
+                xv[k] = *reinterpret_cast<const u32x4*>(in + ((size_t)y * wc + x) * CP + 8 * part);
+        }
+    };
+    if ((int)blockIdx.x * run < t_end) load_tile(blockIdx.x * run);
+    for (int ti = blockIdx.x * run; ti < t_end; ++ti) {
+        const Tile tl = tiles[ti];
+        const LevelItem& it = items[tl.item];
+        const int wc = it.wc, hc = it.hc;
+        const int p0 = tl.ty * MR, q0 = tl.tx * MC;
+        __syncthreads();  // the previous tile's reads of xs are done
+#pragma unroll
+        for (int k = 0; k < NXQ; ++k) {
+            const int e = tid + 256 * k;
+            if (e < XR * XC * PARTS) {
                 const int cell = e / PARTS, part = e - cell * PARTS;
-                const int r = cell / XC, col = cell - r * XC;
-                const int y = p0 - 1 + r, x = q0 - 1 + col;
-                xv[k] = u32x4{0u, 0u, 0u, 0u};
-                if (e < XR * XC * PARTS && y >= 0 && y < hc && x >= 0 && x < wc)
-                    xv[k] = *reinterpret_cast<const u32x4*>(in + ((size_t)y * wc + x) * CP + 8 * part);
-            }
-            __syncthreads();  // the previous tile's reads of xs are done
-#pragma unroll
-            for (int k = 0; k < NXQ; ++k) {
-                const int e = tid + 256 * k;
-                if (e < XR * XC * PARTS) {
-                    const int cell = e / PARTS, part = e - cell * PARTS;
-                    *reinterpret_cast<u32x4*>(xs + cell * XS + 8 * part) = xv[k];
-                }
+                *reinterpret_cast<u32x4*>(xs + cell * XS + 8 * part) = xv[k];
             }
         }
         __syncthreads();
+        if (ti + 1 < t_end) load_tile(ti + 1);
 
         f32x4 acc[MT];
 #pragma unroll
