@@ -612,6 +612,8 @@ __device__ __forceinline__ uint32_t fkey(float z) {
 
 // One workgroup per frame: radix selection (8 bits per pass, most significant
 // first) of the K-th largest logit over the frame's windows, every level.
+constexpr int TOPK_BATCH = 8;
+
 __global__ void __launch_bounds__(256) topk_kernel(const LevelItem* __restrict__ items,
                                                    const int32_t* __restrict__ first_item,
                                                    const NmsGeom* __restrict__ geoms, int keep_k,
@@ -641,10 +643,18 @@ __global__ void __launch_bounds__(256) topk_kernel(const LevelItem* __restrict__
         for (int l = 0; l < nl; ++l) {
             const LevelItem& it = items[i0 + l];
             const int n = it.nx * it.ny;
-            for (int q = tid; q < n; q += 256) {
-                const int wi = q / it.nx, wj = q - wi * it.nx;
-                const uint32_t k = fkey(it.logit[(size_t)(wi + PRUNER_WIN_DI) * it.wc + wj + PRUNER_WIN_DJ]);
-                if ((k & mask) == prefix) atomicAdd(&hist[(k >> shift) & 255u], 1u);
+            // eight logit loads of a thread in flight together
+            for (int q0 = tid; q0 < n; q0 += 256 * TOPK_BATCH) {
+                uint32_t k[TOPK_BATCH];
+#pragma unroll
+                for (int u = 0; u < TOPK_BATCH; ++u) {
+                    const int q = min(q0 + 256 * u, n - 1);
+                    const int wi = q / it.nx, wj = q - wi * it.nx;
+                    k[u] = fkey(it.logit[(size_t)(wi + PRUNER_WIN_DI) * it.wc + wj + PRUNER_WIN_DJ]);
+                }
+#pragma unroll
+                for (int u = 0; u < TOPK_BATCH; ++u)
+                    if (q0 + 256 * u < n && (k[u] & mask) == prefix) atomicAdd(&hist[(k[u] >> shift) & 255u], 1u);
             }
         }
         __syncthreads();
