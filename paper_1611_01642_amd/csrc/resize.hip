@@ -71,27 +71,35 @@ __device__ __forceinline__ void resize_tile(gptr<const uint8_t> __restrict__ src
     const bool staged = span_w <= 256 && nrow * span_w * 4 <= RS_LDS;  // uniform over the workgroup
     if (staged) {
         // coalesced aligned words, K whole rows per pass: thread t takes word
-        // wd of rows r0, r0 + K, ...; a word is loaded only if it holds a byte
-        // of the rectangle (so it never leaves the pages of the image)
+        // wd of rows r0, r0 + K, ...  Raw buffer loads from the image's first
+        // aligned word, bounded by the aligned word that holds its last byte
+        // (so no load leaves the image's pages); a word's offset steps from
+        // row to row by one add, and past the bound a load returns 0 (those
+        // words are past the rectangle and never read)
         const int K = 256 / span_w;
         const int r0 = t / span_w, wd = t - r0 * span_w;
+        const uint8_t* s8 = (const uint8_t*)src;
+        const uint32_t sa = (uint32_t)(reinterpret_cast<uintptr_t>(s8) & 3);
+        const uint64_t img_bytes = (uint64_t)sa + (uint64_t)(sh - 1) * spitch + sw;
+        const auto rsrc = planes_rsrc(s8 - sa, (img_bytes + 3) & ~3ull);
         if (r0 < K) {
+            // unaligned byte offset (from the aligned base) of the rectangle's
+            // first byte in row r, for r = rb + K k
+            uint32_t u = sa + (uint32_t)(sy0 + r0) * (uint32_t)spitch + (uint32_t)sx0;
+            const uint32_t du = (uint32_t)K * (uint32_t)spitch;
+            uint32_t* st = reinterpret_cast<uint32_t*>(stage) + r0 * span_w + wd;
+            const int dst = K * span_w;
             for (int rb = r0; rb < nrow; rb += K * RS_BATCH) {
                 uint32_t v[RS_BATCH];
 #pragma unroll
                 for (int k = 0; k < RS_BATCH; ++k) {
-                    const int r = rb + K * k;
-                    const auto p0 = src + (size_t)(sy0 + min(r, nrow - 1)) * spitch + sx0;
-                    const int mis = (int)(reinterpret_cast<uintptr_t>(p0) & 3);
-                    v[k] = 0u;
-                    if (r < nrow && 4 * wd <= mis + (sx1 - sx0))
-                        v[k] = *reinterpret_cast<gptr<const uint32_t>>(p0 - mis + 4 * wd);
+                    v[k] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, (u & ~3u) + 4u * (uint32_t)wd, 0, 0);
+                    u += du;
                 }
 #pragma unroll
-                for (int k = 0; k < RS_BATCH; ++k) {
-                    const int r = rb + K * k;
-                    if (r < nrow) *reinterpret_cast<uint32_t*>(stage + 4 * (r * span_w + wd)) = v[k];
-                }
+                for (int k = 0; k < RS_BATCH; ++k)
+                    if (rb + K * k < nrow) st[k * dst] = v[k];
+                st += RS_BATCH * dst;
             }
         }
         __syncthreads();
