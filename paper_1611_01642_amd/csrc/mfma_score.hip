@@ -20,7 +20,8 @@
 // the 4 waves need feature rows i0+a .. i0+a+3, so rows pass through a 5-slot
 // LDS ring (each row is loaded from HBM and converted once); the weight slice
 // of offset a (packed B fragments) is staged once and shared by the 4 waves.
-// The loads for step a+1 are issued before the MFMAs of step a.
+// A feature row's loads are issued two steps before it is stored (HBM
+// latency spans two steps of MFMAs), a weight slice's one step before.
 #include <type_traits>
 
 #include "pd_internal.h"
@@ -133,6 +134,51 @@ __device__ __forceinline__ void store_row(const RowRegs<HOG>& r, __bf16* dst) {
     }
 }
 
+// The same with the per-thread offsets taken once per tile: goff[q], the
+// element's byte offset in the planes without the row (raw buffer loads add
+// the row's byte offset as a scalar), and soff[q], its byte offset in a ring
+// slot.  Clamped elements repeat the last one (same value, same slot).
+template <bool HOG>
+struct RowOffsets {
+    uint32_t goff[RowRegs<HOG>::N], soff[RowRegs<HOG>::N];
+};
+
+template <bool HOG>
+__device__ __forceinline__ void row_offsets(RowOffsets<HOG>& o, int j0, int hcols, int hrows) {
+    constexpr int SR = RowRegs<HOG>::SR, NC = RowRegs<HOG>::NC;
+    constexpr int C = HOG ? MF_HOG_C : MF_LBP_C;
+    const uint32_t plane = (uint32_t)hrows * (uint32_t)hcols;
+#pragma unroll
+    for (int q = 0; q < RowRegs<HOG>::N; ++q) {
+        const int e = min((int)threadIdx.x + 256 * q, SR * NC - 1);
+        const int c = e / SR, col = e - (e / SR) * SR;
+        o.goff[q] = ((uint32_t)c * plane + (uint32_t)min(j0 + col, hcols - 1)) * (HOG ? 2u : 1u);
+        o.soff[q] = (uint32_t)(col * C + c) * 2u;
+    }
+}
+
+template <bool HOG>
+__device__ __forceinline__ void load_row_fast(RowRegs<HOG>& r, const RowOffsets<HOG>& o, __amdgpu_buffer_rsrc_t rsrc,
+                                              int y, int hcols, int hrows) {
+    const uint32_t roff = (uint32_t)min(y, hrows - 1) * (uint32_t)hcols * (HOG ? 2u : 1u);
+#pragma unroll
+    for (int q = 0; q < RowRegs<HOG>::N; ++q) {
+        if (HOG) {
+            r.v[q] = __builtin_amdgcn_raw_buffer_load_b16(rsrc, o.goff[q], roff, 0);
+        } else {  // counts <= 64: exact in bf16
+            const uint32_t b = __builtin_amdgcn_raw_buffer_load_b8(rsrc, o.goff[q], roff, 0);
+            r.v[q] = (uint16_t)(__float_as_uint((float)b) >> 16);
+        }
+    }
+}
+
+template <bool HOG>
+__device__ __forceinline__ void store_row_fast(const RowRegs<HOG>& r, const RowOffsets<HOG>& o, __bf16* dst) {
+    uint8_t* d = reinterpret_cast<uint8_t*>(dst);
+#pragma unroll
+    for (int q = 0; q < RowRegs<HOG>::N; ++q) *reinterpret_cast<uint16_t*>(d + o.soff[q]) = r.v[q];
+}
+
 template <int BSZ>
 struct SliceRegs {
     static constexpr int N = (BSZ / 8 + 255) / 256;
@@ -183,28 +229,34 @@ __device__ __forceinline__ void mfma_tile(const uint16_t* __restrict__ hog16, co
         constexpr int BSZ = T * 16 * 32;  // bf16 per offset slice
         const int hrows = HOG ? hb : hc, hcols = HOG ? wb : wc;
         const uint16_t* wsrc = HOG ? wpk : wpk + PD_WIN_BLOCKS_Y * MF_HOG_T * 16 * 32;
-        // prologue: rows i0..i0+3 and the slice of offset 0
+        // prologue: rows i0..i0+3 and the slice of offset 0 into LDS; row
+        // i0+4 (stored after step 0) into registers
+        RowOffsets<HOG> ro;
+        row_offsets<HOG>(ro, j0, hcols, hrows);
+        const auto rsrc = planes_rsrc(HOG ? (const void*)hog16 : (const void*)lbp,
+                                      (uint64_t)RowRegs<HOG>::NC * hrows * hcols * (HOG ? 2 : 1));
+        RowRegs<HOG> rows2[2];
         {
-            RowRegs<HOG> rr;
             for (int r = 0; r < MF_ROWS; ++r) {
-                load_row<HOG>(rr, hog16, lbp, i0 + r, j0, hcols, hrows);
-                store_row<HOG>(rr, sm.ring[r]);
+                load_row_fast<HOG>(rows2[0], ro, rsrc, i0 + r, hcols, hrows);
+                store_row_fast<HOG>(rows2[0], ro, sm.ring[r]);
             }
             SliceRegs<BSZ> sr;
             load_slice<BSZ>(sr, wsrc);
             store_slice<BSZ>(sr, sm.bw[0]);
+            if (A > 1) load_row_fast<HOG>(rows2[0], ro, rsrc, i0 + MF_ROWS, hcols, hrows);
         }
         __syncthreads();
-        for (int a = 0; a < A; ++a) {
-            // loads of the next step's feature row and weight slice are in
-            // flight during this step's MFMAs
-            RowRegs<HOG> nrow;
+        // Step a: MFMAs on rows i0+a .. i0+a+3 with the slice of offset a.
+        // The feature row it stores at its end (i0+a+4) was loaded one step
+        // earlier, and it issues the load of row i0+a+5 for the next step: a
+        // row's load has two steps of MFMAs to arrive.  The weight slice
+        // (L2-resident) is loaded one step ahead.
+        auto step = [&](int a, RowRegs<HOG>& cur, RowRegs<HOG>& nxt) __attribute__((always_inline)) {
             SliceRegs<BSZ> nsl;
             const bool more = a + 1 < A;
-            if (more) {
-                load_row<HOG>(nrow, hog16, lbp, i0 + a + MF_ROWS, j0, hcols, hrows);
-                load_slice<BSZ>(nsl, wsrc + (size_t)(a + 1) * BSZ);
-            }
+            if (a + 2 < A) load_row_fast<HOG>(nxt, ro, rsrc, i0 + a + MF_ROWS + 1, hcols, hrows);
+            if (more) load_slice<BSZ>(nsl, wsrc + (size_t)(a + 1) * BSZ);
             const __bf16* row = sm.ring[(a + wave) % MF_RING];
             const __bf16* bw = sm.bw[a & 1];
 #pragma unroll
@@ -221,10 +273,16 @@ __device__ __forceinline__ void mfma_tile(const uint16_t* __restrict__ hog16, co
                 }
             }
             if (more) {  // slots not read in this step (see the ring indexing above)
-                store_row<HOG>(nrow, sm.ring[(a + MF_ROWS) % MF_RING]);
+                store_row_fast<HOG>(cur, ro, sm.ring[(a + MF_ROWS) % MF_RING]);
                 store_slice<BSZ>(nsl, sm.bw[(a + 1) & 1]);
             }
             __syncthreads();
+        };
+        // two register sets for rows in flight, alternating (unrolled by two
+        // so that each is a fixed set of registers)
+        for (int a = 0; a < A; a += 2) {
+            step(a, rows2[0], rows2[1]);
+            if (a + 1 < A) step(a + 1, rows2[1], rows2[0]);
         }
     };
     if (FEAT & PD_FEAT_HOG) phase(std::integral_constant<bool, true>());
