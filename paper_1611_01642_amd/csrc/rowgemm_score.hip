@@ -113,6 +113,51 @@ __device__ __forceinline__ void store_row(const RowRegs<HOG>& r, __bf16* dst) {
     }
 }
 
+// The same with the per-thread offsets taken once per tile: goff[q], the
+// element's byte offset in the planes without the row (raw buffer loads add
+// the row's byte offset as a scalar), and soff[q], its byte offset in the
+// staged row.  Clamped elements repeat the last one (same value, same place).
+template <bool HOG>
+struct RowOffsets {
+    uint32_t goff[RowRegs<HOG>::N], soff[RowRegs<HOG>::N];
+};
+
+template <bool HOG>
+__device__ __forceinline__ void row_offsets(RowOffsets<HOG>& o, int j0, int hcols, int hrows) {
+    constexpr int SR = RowRegs<HOG>::SR, NC = RowRegs<HOG>::NC;
+    constexpr int C = HOG ? RG_HOG_C : RG_LBP_C;
+    const uint32_t plane = (uint32_t)hrows * (uint32_t)hcols;
+#pragma unroll
+    for (int q = 0; q < RowRegs<HOG>::N; ++q) {
+        const int e = min((int)threadIdx.x + 256 * q, SR * NC - 1);
+        const int c = e / SR, col = e - (e / SR) * SR;
+        o.goff[q] = ((uint32_t)c * plane + (uint32_t)min(j0 + col, hcols - 1)) * (HOG ? 2u : 1u);
+        o.soff[q] = (uint32_t)(col * C + c) * 2u;
+    }
+}
+
+template <bool HOG>
+__device__ __forceinline__ void load_row_fast(RowRegs<HOG>& r, const RowOffsets<HOG>& o, __amdgpu_buffer_rsrc_t rsrc,
+                                              int y, int hcols, int hrows) {
+    const uint32_t roff = (uint32_t)min(y, hrows - 1) * (uint32_t)hcols * (HOG ? 2u : 1u);
+#pragma unroll
+    for (int q = 0; q < RowRegs<HOG>::N; ++q) {
+        if (HOG) {
+            r.v[q] = __builtin_amdgcn_raw_buffer_load_b16(rsrc, o.goff[q], roff, 0);
+        } else {  // counts <= 64: exact in bf16
+            const uint32_t b = __builtin_amdgcn_raw_buffer_load_b8(rsrc, o.goff[q], roff, 0);
+            r.v[q] = (uint16_t)(__float_as_uint((float)b) >> 16);
+        }
+    }
+}
+
+template <bool HOG>
+__device__ __forceinline__ void store_row_fast(const RowRegs<HOG>& r, const RowOffsets<HOG>& o, __bf16* dst) {
+    uint8_t* d = reinterpret_cast<uint8_t*>(dst);
+#pragma unroll
+    for (int q = 0; q < RowRegs<HOG>::N; ++q) *reinterpret_cast<uint16_t*>(d + o.soff[q]) = r.v[q];
+}
+
 __device__ __forceinline__ bf16x8 a_frag(const __bf16* p) {  // 8-byte aligned run of 8 bf16
     const uint2 lo = *reinterpret_cast<const uint2*>(p);
     const uint2 hi = *reinterpret_cast<const uint2*>(p + 4);
@@ -141,13 +186,19 @@ __device__ __forceinline__ void rowgemm_tile(const LevelItem& it, const uint16_t
     for (int e = threadIdx.x; e < (int)(sizeof(sm.hog) + sizeof(sm.lbp)) / 4; e += 256)
         reinterpret_cast<uint32_t*>(&sm.hog[0][0])[e] = 0u;
     __syncthreads();
+    RowOffsets<true> oh;
+    RowOffsets<false> ol;
+    row_offsets<true>(oh, j0, wb, hb);
+    row_offsets<false>(ol, j0, wc, hc);
+    const auto rh_src = planes_rsrc(it.hog16, (uint64_t)PD_HOG_BLOCK * hb * wb * 2);
+    const auto rl_src = planes_rsrc(it.lbp, (uint64_t)PD_LBP_BINS * hc * wc);
     {
         RowRegs<true> rh;
         RowRegs<false> rl;
-        load_row<true>(rh, it.hog16, it.lbp, 0, j0, wb, hb);
-        load_row<false>(rl, it.hog16, it.lbp, 0, j0, wc, hc);
-        store_row<true>(rh, sm.hog[0]);
-        store_row<false>(rl, sm.lbp[0]);
+        load_row_fast<true>(rh, oh, rh_src, 0, wb, hb);
+        load_row_fast<false>(rl, ol, rl_src, 0, wc, hc);
+        store_row_fast<true>(rh, oh, sm.hog[0]);
+        store_row_fast<false>(rl, ol, sm.lbp[0]);
     }
     __syncthreads();
 
@@ -158,8 +209,8 @@ __device__ __forceinline__ void rowgemm_tile(const LevelItem& it, const uint16_t
         RowRegs<true> nh;
         RowRegs<false> nl;
         if (more) {
-            if (y + 1 < hb) load_row<true>(nh, it.hog16, it.lbp, y + 1, j0, wb, hb);
-            load_row<false>(nl, it.hog16, it.lbp, y + 1, j0, wc, hc);
+            if (y + 1 < hb) load_row_fast<true>(nh, oh, rh_src, y + 1, wb, hb);
+            load_row_fast<false>(nl, ol, rl_src, y + 1, wc, hc);
         }
         f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
         if (y < hb) {
@@ -196,8 +247,8 @@ __device__ __forceinline__ void rowgemm_tile(const LevelItem& it, const uint16_t
             }
         }
         if (more) {
-            if (y + 1 < hb) store_row<true>(nh, sm.hog[cur ^ 1]);
-            store_row<false>(nl, sm.lbp[cur ^ 1]);
+            if (y + 1 < hb) store_row_fast<true>(nh, oh, sm.hog[cur ^ 1]);
+            store_row_fast<false>(nl, ol, sm.lbp[cur ^ 1]);
         }
         __syncthreads();
     }
