@@ -421,15 +421,18 @@ int pd_video_pop(pd_video* v, pd_box* boxes, int cap, pd_counts* counts, float* 
 int pd_video_destroy(pd_video* v);
 
 /*
- * pd_autotune -- times pd_detect on these arguments (per candidate: one
- * untimed call, then the least of three timings of `iters` calls between HIP
- * events) over the tuning fields of
- * pd_params, one field at a time: feature strip rows {4, 6, 8, 12, 16},
- * FP32 scoring rows {4, 8, 16}, grid cap {0, 256, 512, 1024, 2048}; starting
- * from params' own values.  Writes params with the fastest fields to *best
- * (host) and its time per call in ms to *best_ms (host, may be NULL).
- * Blocks until the timing runs finished; leaves boxes and counts of the
- * last run.  The workspace size does not depend on the tuning fields.
+ * pd_autotune -- times pd_detect's kernel sequence on these arguments, as
+ * captured graphs (the device's time, without the host's table build and
+ * upload), over the tuning fields of pd_params: per candidate, against the
+ * current choice, three rounds of (capture, one untimed launch, `iters`
+ * launches between HIP events) for each in turn, the least time of each
+ * compared.  Fields tried one at a time: feature strip rows {4, 6, 8, 12,
+ * 16}, FP32 scoring rows {4, 8, 16}, grid cap {0, 256, 512, 1024, 2048};
+ * starting from params' own values.  Writes params with the fastest fields to
+ * *best (host) and its device time per call in ms to *best_ms (host, may be
+ * NULL).  Blocks until the timing runs finished; leaves boxes and counts of
+ * the last run.  The workspace size does not depend on the tuning fields;
+ * the next pd_detect call uploads its own tables as always.
  * Errors: those of pd_detect; PD_E_ARG for iters outside [1, 1000].
  */
 int pd_autotune(const pd_frame* frames, int n_frames, const float* weights,

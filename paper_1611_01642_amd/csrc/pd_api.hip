@@ -1289,25 +1289,45 @@ int pd_autotune(const pd_frame* frames, int n_frames, const float* weights, cons
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int rc = hip_status(hipEventCreate(&e0), "event");
     if (!rc) rc = hip_status(hipEventCreate(&e1), "event");
-    // one untimed call, then the least of three timings of `iters` calls
-    // between two events (one timing alone is at the mercy of clock and
-    // cache transients)
-    auto time_of = [&](const pd_params& p, float* ms) -> int {
-        int r = pd_detect(frames, n_frames, weights, bias, n_models, &p, thresholds, workspace, workspace_bytes,
-                          boxes, cap, counts, stream);
-        *ms = 0.0f;
-        for (int rep = 0; rep < 3 && !r; ++rep) {
-            if (!r) r = hip_status(hipEventRecord(e0, s), "event");
-            for (int k = 0; k < iters && !r; ++k)
-                r = pd_detect(frames, n_frames, weights, bias, n_models, &p, thresholds, workspace,
-                              workspace_bytes, boxes, cap, counts, stream);
-            if (!r) r = hip_status(hipEventRecord(e1, s), "event");
-            if (!r) r = hip_status(hipEventSynchronize(e1), "event");
-            float t = 0.0f;
-            if (!r) r = hip_status(hipEventElapsedTime(&t, e0, e1), "event");
-            if (!r && (rep == 0 || t < *ms)) *ms = t;
-        }
+    // `iters` launches of a captured graph between two events: the device's
+    // time alone (an eager call also builds and uploads its tables on the
+    // host, which would favour shapes with fewer tiles, not faster kernels)
+    auto time_run = [&](pd_graph* g, float* ms) -> int {
+        int r = hip_status(hipEventRecord(e0, s), "event");
+        for (int k = 0; k < iters && !r; ++k) r = pd_graph_launch(g, stream);
+        if (!r) r = hip_status(hipEventRecord(e1, s), "event");
+        if (!r) r = hip_status(hipEventSynchronize(e1), "event");
+        if (!r) r = hip_status(hipEventElapsedTime(ms, e0, e1), "event");
         *ms /= (float)iters;
+        return r;
+    };
+    // one round for one shape: capture (its tables go into the shared
+    // workspace), one untimed launch, `iters` timed ones
+    auto time_shape = [&](const pd_params& p, float* ms) -> int {
+        pd_graph* g = nullptr;
+        int r = pd_graph_create(frames, n_frames, weights, bias, n_models, &p, thresholds, workspace,
+                                workspace_bytes, boxes, cap, counts, stream, &g);
+        if (!r) r = pd_graph_launch(g, stream);
+        if (!r) r = time_run(g, ms);
+        if (g) {
+            const int r2 = hip_status(hipStreamSynchronize(s), "tuning");
+            const int r3 = pd_graph_destroy(g);
+            r = r ? r : (r2 ? r2 : r3);
+        }
+        return r;
+    };
+    // a candidate against the current choice: three rounds timing both in
+    // turn; each keeps its least time (clock and cache drift hits both alike,
+    // and one timing alone is at its mercy)
+    auto time_pair = [&](const pd_params& a, const pd_params& b, float* ms_a, float* ms_b) -> int {
+        int r = PD_OK;
+        for (int rep = 0; rep < 3 && !r; ++rep) {
+            float ta = 0.0f, tb = 0.0f;
+            r = time_shape(a, &ta);
+            if (!r) r = time_shape(b, &tb);
+            if (!r && (rep == 0 || ta < *ms_a)) *ms_a = ta;
+            if (!r && (rep == 0 || tb < *ms_b)) *ms_b = tb;
+        }
         return r;
     };
     pd_params cur = *params;
@@ -1315,7 +1335,6 @@ int pd_autotune(const pd_frame* frames, int n_frames, const float* weights, cons
     cur.tune_feat_rows = t0.feat_rows;
     cur.tune_score_rows = t0.score_rows;
     float cur_ms = 0.0f;
-    if (!rc) rc = time_of(cur, &cur_ms);
     // one knob at a time (the stages they shape are independent)
     const int feat_rows[] = {4, 6, 8, 12, 16};
     const int score_rows[] = {4, 8, 16};
@@ -1330,9 +1349,10 @@ int pd_autotune(const pd_frame* frames, int n_frames, const float* weights, cons
             const int now = knob == 0 ? cur.tune_feat_rows : knob == 1 ? cur.tune_score_rows : cur.tune_grid;
             if (vals[v] == now) continue;
             field = vals[v];
-            float ms = 0.0f;
-            rc = time_of(c, &ms);
-            if (!rc && ms < cur_ms) {
+            float ms_cur = 0.0f, ms = 0.0f;
+            rc = time_pair(cur, c, &ms_cur, &ms);
+            if (!rc) cur_ms = ms_cur;
+            if (!rc && ms < ms_cur) {
                 cur = c;
                 cur_ms = ms;
             }
