@@ -100,6 +100,22 @@ def _oracle_frame(seed):
     return time.perf_counter() - t0
 
 
+def copy_bandwidth(torch, dev):
+    """GB/s of a 1 GiB device-to-device copy (read + write), mean of 10."""
+    src = torch.ones(256 << 20, dtype=torch.int32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(10):
+        dst.copy_(src)
+    e1.record(s)
+    torch.cuda.synchronize()
+    return round(2 * src.numel() * 4 * 10 / (e0.elapsed_time(e1) / 1000) / 1e9, 1)
+
+
 def cpu_baseline(frames_per_core=2, max_cores=16):
     """The FP64 oracle as it stands, one process per host core, on a bounded
     sample of the same workload."""
@@ -122,10 +138,19 @@ def cpu_baseline(frames_per_core=2, max_cores=16):
                 os.environ.pop(k, None)
             else:
                 os.environ[k] = v
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": n / wall, "unit": "frames/s", "cores": cores, "kind": "oracle",
             "sample": f"{n} frames of 1242x375 (full pyramid, HOG+LBP, 1 SVM, NMS), "
                       f"{frames_per_core} per process, FP64 NumPy, 1 thread per process; "
-                      f"mean {1000 * sum(per) / n:.0f} ms per frame per core"}
+                      f"mean {1000 * sum(per) / n:.0f} ms per frame per core",
+            "one_core_frames_per_s": round(n / sum(per), 3), "cpu_model": model}
 
 
 def measured_traffic(kernel, batch, tuning):
@@ -586,6 +611,11 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         out["calib_copy_bytes"] = int(src.numel()) * 4
+    # the HBM bandwidth a plain device copy reaches here (1 GiB read + 1 GiB
+    # written per copy), beside the published 8 TB/s (not in the counter
+    # passes, whose calibration is the 256 MiB copy above)
+    if not args.calib_copy:
+        out["hbm_copy_gbs"] = copy_bandwidth(torch, dev)
     if not args.no_cpu:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline()

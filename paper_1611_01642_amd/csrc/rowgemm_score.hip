@@ -82,38 +82,7 @@ struct RowRegs {
     uint16_t v[N];
 };
 
-template <bool HOG>
-__device__ __forceinline__ void load_row(RowRegs<HOG>& r, const uint16_t* __restrict__ hog16,
-                                         const uint8_t* __restrict__ lbp, int y, int j0, int hcols, int hrows) {
-    constexpr int SR = RowRegs<HOG>::SR, NC = RowRegs<HOG>::NC;
-    const size_t plane = (size_t)hrows * hcols;
-    const size_t row = (size_t)min(y, hrows - 1) * hcols;
-#pragma unroll
-    for (int q = 0; q < RowRegs<HOG>::N; ++q) {
-        const int e = min((int)threadIdx.x + 256 * q, SR * NC - 1);
-        const int c = e / SR, col = e - (e / SR) * SR;
-        const size_t src = c * plane + row + min(j0 + col, hcols - 1);
-        if (HOG) r.v[q] = hog16[src];
-        else r.v[q] = (uint16_t)(__float_as_uint((float)lbp[src]) >> 16);  // counts <= 64: exact in bf16
-    }
-}
-
-template <bool HOG>
-__device__ __forceinline__ void store_row(const RowRegs<HOG>& r, __bf16* dst) {
-    constexpr int SR = RowRegs<HOG>::SR, NC = RowRegs<HOG>::NC;
-    constexpr int C = HOG ? RG_HOG_C : RG_LBP_C;
-    uint16_t* d = reinterpret_cast<uint16_t*>(dst);
-#pragma unroll
-    for (int q = 0; q < RowRegs<HOG>::N; ++q) {
-        const int e = threadIdx.x + 256 * q;
-        if (e < SR * NC) {
-            const int c = e / SR, col = e - (e / SR) * SR;
-            d[col * C + c] = r.v[q];
-        }
-    }
-}
-
-// The same with the per-thread offsets taken once per tile: goff[q], the
+// The per-thread offsets are taken once per tile: goff[q], the
 // element's byte offset in the planes without the row (raw buffer loads add
 // the row's byte offset as a scalar), and soff[q], its byte offset in the
 // staged row.  Clamped elements repeat the last one (same value, same place).
