@@ -67,9 +67,15 @@ def test_mfma_scoring_exact_operands(w, h, m):
     assert err.max() <= 1e-5 * max(1.0, absx.max()), (err.max(), absx.max())
 
 
+# The library takes L2-Hys clip and eps as FP32 parameters (pd_params), so its
+# FP64 rescore works with their FP32 values widened exactly; the oracle gets
+# the same values wherever FP64 scores are compared at 1e-9.
+CLIP32, EPS32 = float(np.float32(0.2)), float(np.float32(1e-3))
+
+
 def _oracle_frame(img, m, scale=(11, 10), maxl=0):
     wts, bias = pd_synth.svm_weights(m), np.zeros(m, np.float32)
-    levels = O.frame_scores(img, wts, bias, scale[0], scale[1], maxl)
+    levels = O.frame_scores(img, wts, bias, scale[0], scale[1], maxl, clip=CLIP32, eps=EPS32)
     thr = O.frame_threshold(levels)
     return wts, bias, levels, thr
 
@@ -167,3 +173,35 @@ def test_detect_bf16_batch_deterministic():
     b = dets[0][0][1].copy()
     b["frame"] = 0
     assert b.tobytes() == b1[0].tobytes()
+
+
+@pytest.mark.parametrize("w,h,m", [(166, 203, 8), (201, 150, 1)])
+def test_rescore_every_window(w, h, m):
+    """A margin that makes every window near the threshold: all windows of a
+    small frame (border windows, whose pixels are clamped, and inner ones,
+    read as aligned words) go through the FP64 rescore; every candidate
+    carries the oracle's FP64 score and model, and the candidate set is the
+    oracle's exactly (the threshold lies midway between two oracle scores)."""
+    img = pd_synth.frame(w, h, 4321 + w)
+    wts, bias = pd_synth.svm_weights(m), np.zeros(m, np.float32)
+    levels = O.frame_scores(img, wts, bias.astype(np.float64), clip=CLIP32, eps=EPS32)
+    allmax = np.sort(np.concatenate([O.max_over_models(lv["scores"])[0].ravel() for lv in levels]))
+    n_win = allmax.size
+    assert 0 < n_win <= 1024  # every window fits the per-frame rescore cap
+    k = n_win // 3
+    thr = 0.5 * (allmax[n_win - k - 1] + allmax[n_win - k])
+    prm = pd.params(precision=pd.PREC_BF16, margin=1.0e6)
+    det = pd.Detector([to_dev(img)], to_dev(wts), to_dev(bias), prm, cap=1024)
+    det.run(to_dev(np.array([thr])))
+    torch.cuda.synchronize()
+    _, counts = det.results()
+    assert counts[0]["rescored"] == n_win and counts[0]["overflow"] == 0
+    cs, ck, c64 = det.candidates(0)
+    exp = {(c["level"], c["i"], c["j"]): c for c in O.candidates(levels, w, h, thr)}
+    got = {(int(q[0]), int(q[1]), int(q[2])): (float(s), int(q[3])) for q, s in zip(ck, c64)}
+    assert set(got) == set(exp)
+    for key, (s64, model) in got.items():
+        ref = exp[key]["score"]
+        assert abs(s64 - ref) <= 1e-9 * max(1.0, abs(ref)), (key, s64, ref)
+        assert model == exp[key]["model"]
+    print(f"\n[rescore all] {w}x{h} m {m}: windows {n_win}, candidates {len(exp)}", flush=True)
