@@ -426,8 +426,9 @@ int pd_video_destroy(pd_video* v);
  * upload), over the tuning fields of pd_params: per candidate, against the
  * current choice, three rounds of (capture, one untimed launch, `iters`
  * launches between HIP events) for each in turn, the least time of each
- * compared.  Fields tried one at a time: feature strip rows {4, 6, 8, 12,
- * 16}, FP32 scoring rows {4, 8, 16}, grid cap {0, 256, 512, 1024, 2048};
+ * compared.  Fields tried one at a time: feature strip rows {4, 6, 8, 10,
+ * 12, 14, 16}, FP32 scoring rows {4, 8, 16}, grid cap {0, 256, 512, 1024,
+ * 2048};
  * starting from params' own values.  Writes params with the fastest fields to
  * *best (host) and its device time per call in ms to *best_ms (host, may be
  * NULL).  Blocks until the timing runs finished; leaves boxes and counts of

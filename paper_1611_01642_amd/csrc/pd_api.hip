@@ -1336,12 +1336,12 @@ int pd_autotune(const pd_frame* frames, int n_frames, const float* weights, cons
     cur.tune_score_rows = t0.score_rows;
     float cur_ms = 0.0f;
     // one knob at a time (the stages they shape are independent)
-    const int feat_rows[] = {4, 6, 8, 12, 16};
+    const int feat_rows[] = {4, 6, 8, 10, 12, 14, 16};
     const int score_rows[] = {4, 8, 16};
     const int grids[] = {0, 256, 512, 1024, 2048};
     for (int knob = 0; knob < 3 && !rc; ++knob) {
         const int* vals = knob == 0 ? feat_rows : knob == 1 ? score_rows : grids;
-        const int n = knob == 0 ? 5 : knob == 1 ? 3 : 5;
+        const int n = knob == 0 ? 7 : knob == 1 ? 3 : 5;
         if (knob == 1 && params->precision != PD_PREC_F32) continue;  // FP32 scoring only
         for (int v = 0; v < n && !rc; ++v) {
             pd_params c = cur;
