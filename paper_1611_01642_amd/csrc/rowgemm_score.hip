@@ -18,8 +18,8 @@
 // the same FP32 accumulator).  FP32 accumulation; fixed summation order.
 //
 // Tile: a workgroup of 4 waves owns 64 window columns of one level (16 per
-// wave) and streams down all feature rows; the next row's loads are in flight
-// during the current row's MFMAs.
+// wave) and streams down all feature rows; a row's loads are issued two rows
+// ahead, so they are in flight during two rows of MFMAs.
 #include "pd_internal.h"
 
 namespace pd {
@@ -161,25 +161,29 @@ __device__ __forceinline__ void rowgemm_tile(const LevelItem& it, const uint16_t
     row_offsets<false>(ol, j0, wc, hc);
     const auto rh_src = planes_rsrc(it.hog16, (uint64_t)PD_HOG_BLOCK * hb * wb * 2);
     const auto rl_src = planes_rsrc(it.lbp, (uint64_t)PD_LBP_BINS * hc * wc);
-    {
-        RowRegs<true> rh;
-        RowRegs<false> rl;
-        load_row_fast<true>(rh, oh, rh_src, 0, wb, hb);
-        load_row_fast<false>(rl, ol, rl_src, 0, wc, hc);
-        store_row_fast<true>(rh, oh, sm.hog[0]);
-        store_row_fast<false>(rl, ol, sm.lbp[0]);
+    // row 0 into LDS; row 1 (stored after step 0) into registers
+    RowRegs<true> rh2[2];
+    RowRegs<false> rl2[2];
+    load_row_fast<true>(rh2[0], oh, rh_src, 0, wb, hb);
+    load_row_fast<false>(rl2[0], ol, rl_src, 0, wc, hc);
+    store_row_fast<true>(rh2[0], oh, sm.hog[0]);
+    store_row_fast<false>(rl2[0], ol, sm.lbp[0]);
+    if (1 < hc) {
+        if (1 < hb) load_row_fast<true>(rh2[0], oh, rh_src, 1, wb, hb);
+        load_row_fast<false>(rl2[0], ol, rl_src, 1, wc, hc);
     }
     __syncthreads();
 
     float (*ring)[16] = sm.ring[wave];
-    for (int y = 0; y < hc; ++y) {
+    // Step y: MFMAs on staged row y.  The row it stores at its end (y + 1)
+    // was loaded one step earlier, and it issues the loads of row y + 2: a
+    // row's loads have two steps of MFMAs to arrive.
+    auto step = [&](int y, RowRegs<true>& ch, RowRegs<false>& cl, RowRegs<true>& nh, RowRegs<false>& nl)
+                    __attribute__((always_inline)) {
         const int cur = y & 1;
-        const bool more = y + 1 < hc;
-        RowRegs<true> nh;
-        RowRegs<false> nl;
-        if (more) {
-            if (y + 1 < hb) load_row_fast<true>(nh, oh, rh_src, y + 1, wb, hb);
-            load_row_fast<false>(nl, ol, rl_src, y + 1, wc, hc);
+        if (y + 2 < hc) {
+            if (y + 2 < hb) load_row_fast<true>(nh, oh, rh_src, y + 2, wb, hb);
+            load_row_fast<false>(nl, ol, rl_src, y + 2, wc, hc);
         }
         f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
         if (y < hb) {
@@ -215,11 +219,17 @@ __device__ __forceinline__ void rowgemm_tile(const LevelItem& it, const uint16_t
                 if (i < ny && j < nx) it.scores[(size_t)i * nx + j] = v + bias;
             }
         }
-        if (more) {
-            if (y + 1 < hb) store_row_fast<true>(nh, oh, sm.hog[cur ^ 1]);
-            store_row_fast<false>(nl, ol, sm.lbp[cur ^ 1]);
+        if (y + 1 < hc) {
+            if (y + 1 < hb) store_row_fast<true>(ch, oh, sm.hog[cur ^ 1]);
+            store_row_fast<false>(cl, ol, sm.lbp[cur ^ 1]);
         }
         __syncthreads();
+    };
+    // two register sets for rows in flight, alternating (unrolled by two so
+    // that each is a fixed set of registers)
+    for (int y = 0; y < hc; y += 2) {
+        step(y, rh2[0], rl2[0], rh2[1], rl2[1]);
+        if (y + 1 < hc) step(y + 1, rh2[1], rl2[1], rh2[0], rl2[0]);
     }
 }
 
