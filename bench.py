@@ -527,7 +527,7 @@ def main():
                    "windows_per_frame": windows, "parallelism": "single GPU"},
         "timing": "HIP-graph replays of the captured pipeline, back to back (level and tile tables uploaded "
                   "once at capture; each replay recomputes every stage from the frame buffers); stage times "
-                  "from HIP events captured in each timed replay; eager_frames_per_s: the same steps as "
+                  "from device clock stamps written by each timed replay; eager_frames_per_s: the same steps as "
                   "pd_detect calls",
         "eager_frames_per_s": round(B * args.steps / eager_elapsed, 1),
         "roofline": roof,

@@ -536,7 +536,7 @@ class Detector:
 
     def capture_steps(self, thresholds, n: int) -> None:
         """n separate captures of the pipeline (replay_step(k)); captured
-        while profile_enable(True) is on, each holds its own stage events,
+        while profile_enable(True) is on, each holds its own stage clock stamps,
         so step_stage_ms(k) gives replay k's stage times even when the n
         replays run back to back."""
         self.release()
