@@ -23,6 +23,8 @@ torch = pytest.importorskip("torch")
 import paper_1611_01642_amd as pd  # noqa: E402
 
 CELL = 8
+# the library's L2-Hys parameters are FP32; FP64 rescores are compared with the oracle run on their values
+CLIP32, EPS32 = float(np.float32(0.2)), float(np.float32(1e-3))
 
 
 def test_longest_sides_match_oracle():
@@ -118,3 +120,37 @@ def test_largest_frame_sampled_candidates():
     print(f"[maxsize] candidates {int(c['candidates'])}, kept {int(c['kept'])}; {len(pick)} sampled scores "
           f"({len(l0)} level-0 candidates, anchors to row {int(ck[l0, 1].max()) if len(l0) else -1}, "
           f"column {int(ck[l0, 2].max()) if len(l0) else -1}) equal the oracle's", flush=True)
+
+
+@pytest.mark.parametrize("m", [1, 8])
+def test_bf16_longest_sides_decisions(m):
+    """BF16 MFMA scoring with FP64 rescoring at the largest side: the
+    candidate sets equal the oracle's, rescored windows carry its FP64 score
+    within 1e-9 (clip and eps as their FP32 values, which the library uses)
+    and the others are within the rescoring margin."""
+    sizes = [(16384, 136), (72, 16384), (16384, 128), (64, 16384)]
+    frames = [pd_synth.frame(w, h, 7200 + k) for k, (w, h) in enumerate(sizes)]
+    wts, bias = pd_synth.svm_weights(m), np.zeros(m, np.float32)
+    levels = [O.frame_scores(f, wts, bias, clip=CLIP32, eps=EPS32) for f in frames]
+    thr = [O.frame_threshold(lv) for lv in levels[:2]] + [-1e30, -1e30]
+    prm = pd.params(precision=pd.PREC_BF16, margin=0.05, tune_feat_rows=12, tune_grid=0)
+    (boxes, counts), det = run_graph(frames, wts, bias, thr, prm)
+    for f, (w, h) in enumerate(sizes):
+        assert counts[f]["overflow"] == 0
+        check_valid_nms(boxes[f])
+        exp = {(c["level"], c["i"], c["j"]): c for c in O.candidates(levels[f], w, h, thr[f])}
+        cs, ck, c64 = det.candidates(f)
+        got = {(int(k[0]), int(k[1]), int(k[2])): (float(s), int(k[3]), float(s64))
+               for s, k, s64 in zip(cs, ck, c64)}
+        assert set(got) == set(exp)
+        n_res = 0
+        for key, (s, model, s64) in got.items():
+            ref = exp[key]["score"]
+            if not np.isnan(s64):
+                n_res += 1
+                assert abs(s64 - ref) <= 1e-9 * max(1.0, abs(ref)), (key, s64, ref)
+                assert model == exp[key]["model"]
+            else:
+                assert abs(s - ref) < 0.05, (key, s, ref)
+        print(f"\n[maxsize bf16] {w}x{h}, {m} models: candidates {len(exp)} equal the oracle's, {n_res} rescored",
+              flush=True)
