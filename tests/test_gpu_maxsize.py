@@ -15,7 +15,9 @@ import pytest
 
 import pd_synth
 from oracle import pd_oracle as O
+from oracle import pruner_oracle as P
 from test_gpu_fullsize import BENCH_TUNING, check_valid_nms, compare_frame, run_graph
+from test_gpu_pruned_detect import gpu_keep
 
 pytestmark = pytest.mark.gpu
 
@@ -154,3 +156,41 @@ def test_bf16_longest_sides_decisions(m):
                 assert abs(s - ref) < 0.05, (key, s, ref)
         print(f"\n[maxsize bf16] {w}x{h}, {m} models: candidates {len(exp)} equal the oracle's, {n_res} rescored",
               flush=True)
+
+
+def test_pruned_longest_sides():
+    """The pruner at the largest side: BF16 logits against the FP64 network
+    on the oracle's cell map, and pruned detection (keep set from the device's
+    logits and the top-K rule, as in the pruned-detection tests) equal to the
+    oracle's detections restricted to the kept windows."""
+    sizes = [(16384, 136), (72, 16384)]
+    frames = [pd_synth.frame(w, h, 7300 + k) for k, (w, h) in enumerate(sizes)]
+    params = pd_synth.pruner_init(seed=7301)
+    pr = torch.from_numpy(params).to("cuda:0")
+    wts, bias = pd_synth.svm_weights(1), np.zeros(1, np.float32)
+    for f, (w, h) in enumerate(sizes):
+        img = frames[f]
+        got = pd.pruner_logits_bf16(torch.from_numpy(img).to("cuda:0"), pr).cpu().numpy().astype(np.float64)
+        exp, _ = P.forward(P.cellmap(img), params.astype(np.float64))
+        scale = np.abs(exp).max()
+        assert got.shape == exp.shape and np.abs(got - exp).max() <= 2e-2 * scale
+        levels = O.frame_scores(img, wts, bias)
+        thr = O.frame_threshold(levels)
+        n_win = sum(lv["scores"][0].size for lv in levels)
+        k = n_win // 2
+        prm = pd.params(prune_keep=k, pruner=pr)
+        keep, _ = gpu_keep(img, pr, k, prm)
+        assert sum(int(x.sum()) for x in keep) >= k
+        exp_c = [c for c in O.candidates(levels, w, h, thr) if keep[c["level"]][c["i"], c["j"]]]
+        det = pd.Detector([torch.from_numpy(img).to("cuda:0")], torch.from_numpy(wts).to("cuda:0"),
+                          torch.from_numpy(bias).to("cuda:0"), prm, cap=1024)
+        det.run(torch.tensor([thr], dtype=torch.float64, device="cuda:0"))
+        torch.cuda.synchronize()
+        boxes, counts = det.results()
+        _, ck, _ = det.candidates(0)
+        assert counts[0]["overflow"] == 0
+        assert {(int(a[0]), int(a[1]), int(a[2])) for a in ck} == {(c["level"], c["i"], c["j"]) for c in exp_c}
+        assert [(int(b["level"]), int(b["i"]), int(b["j"])) for b in boxes[0]] == \
+            [(c["level"], c["i"], c["j"]) for c in O.nms(exp_c)]
+        print(f"\n[maxsize pruned] {w}x{h}: logits within {np.abs(got - exp).max() / scale:.2g} of the scale; "
+              f"K {k} of {n_win}, candidates {len(exp_c)} equal the oracle's", flush=True)
