@@ -28,7 +28,7 @@ def block_model(m, seed):
     return rng.normal(0.0, 0.01, size=(m, O.BLOCK_MODEL_DIM)).astype(np.float32)
 
 
-@pytest.mark.parametrize("w,h", [(16, 16), (83, 57), (333, 257), (1242, 375)])
+@pytest.mark.parametrize("w,h", [(16, 16), (83, 57), (333, 257), (1242, 375), (16384, 24), (24, 16384)])
 def test_block_histograms_bit_exact(w, h):
     print(f"lbp blocks {w}x{h}", flush=True)
     imgs = [pd_synth.frame(w, h, 40 + k) for k in range(3)]
