@@ -320,6 +320,12 @@ int64_t pd_detect_workspace_bytes(const pd_frame* frames, int n_frames,
  *   workspace  : device, >= pd_detect_workspace_bytes(...) bytes
  *   boxes      : device pd_box [n_frames][cap], kept boxes in NMS order
  *   counts     : device pd_counts [n_frames]
+ * Errors, found on the host before any GPU work: PD_E_ARG on bad params, a
+ * NULL pointer, a frame pitch below its width, cap < 0, n_frames < 1 (an
+ * empty batch is an error, not a no-op) or a workspace not 256-byte aligned; PD_E_SIZE when n_models is
+ * outside [1, PD_MAX_MODELS] ([1, PD_MAX_MODELS_BF16] in BF16) or a frame's
+ * sides are outside [1, PD_MAX_DIM]; PD_E_WORKSPACE when workspace_bytes is
+ * below pd_detect_workspace_bytes.
  */
 int pd_detect(const pd_frame* frames, int n_frames, const float* weights,
               const float* bias, int n_models, const pd_params* params,

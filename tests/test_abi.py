@@ -179,3 +179,15 @@ def test_detect_workspace_and_errors():
     arr[0].data = 0
     rc = L.pd_detect(arr, 1, fake, fake, 1, ctypes.byref(prm), fake, fake, 1 << 30, fake, 10, fake, ctypes.c_void_p(0))
     assert rc == pd.E_ARG
+    # every error below is found on the host before any GPU work
+    arr[0].data = 0x1000
+
+    def detect(n=1, cap=10):
+        return L.pd_detect(arr, n, fake, fake, 1, ctypes.byref(prm), fake, fake, 1 << 30, fake, cap, fake,
+                           ctypes.c_void_p(0))
+    assert detect(n=0) == pd.E_ARG        # an empty batch
+    assert detect(cap=-1) == pd.E_ARG
+    arr[0].w, arr[0].h, arr[0].pitch = 16385, 100, 16400
+    assert detect() == pd.E_SIZE          # wider than PD_MAX_DIM
+    arr[0].w, arr[0].h, arr[0].pitch = 100, 100, 99
+    assert detect() == pd.E_ARG           # pitch below the width
