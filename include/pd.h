@@ -289,7 +289,10 @@ typedef struct pd_counts {
     int32_t candidates;  /* windows with score > threshold (true count)    */
     int32_t kept;        /* boxes written after NMS (<= cap)               */
     int32_t overflow;    /* 1 if candidates > PD_MAX_CANDIDATES or the kept
-                            boxes exceeded `cap` (results then incomplete) */
+                            boxes exceeded `cap` (results then incomplete:
+                            past PD_MAX_CANDIDATES the list holds the
+                            windows compacted first, which may differ from
+                            run to run; past `cap`, the first `cap` kept) */
     int32_t rescored;    /* PD_PREC_BF16: windows rescored in FP64 (true
                             count; at most PD_MAX_NEAR were rescored)      */
 } pd_counts;

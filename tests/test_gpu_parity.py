@@ -197,6 +197,13 @@ def run_detect(frames, wts, bias, thr, prm, cap=1024):
     return det.results()
 
 
+def run_detect_views(views, wts, bias, thr, prm, cap=1024):
+    det = pd.Detector(views, to_dev(wts), to_dev(bias), prm, cap=cap)
+    det.run(to_dev(np.asarray(thr, np.float64)))
+    torch.cuda.synchronize()
+    return det.results()
+
+
 def kept_keys(boxes):
     return [(int(b["level"]), int(b["i"]), int(b["j"])) for b in boxes]
 
@@ -298,3 +305,31 @@ def test_nms_cap_reports_overflow():
     got, cnt = pd.decode_boxes(boxes, counts)
     assert cnt["kept"] == 10 and cnt["overflow"] == 1
     assert [int(b["j"]) for b in got] == [8 * q for q in range(n - 1, n - 11, -1)]
+
+
+@pytest.mark.parametrize("prec", [pd.PREC_F32, pd.PREC_BF16])
+def test_detect_pitched_misaligned_frames_equal_contiguous(prec):
+    """Frames given as views into wider buffers, starting 1-3 bytes past an
+    aligned address with pitches that are not multiples of 4: the same boxes
+    and counts, bytewise, as the contiguous frames."""
+    sizes = [(1242, 375), (640, 480), (333, 257)]
+    frames = pd_synth.frame_batch(sizes, 2100)
+    wts, bias = pd_synth.svm_weights(1), pd_synth.svm_bias(1)
+    thr = [3.0, 3.0, 3.0]  # lists within capacity (an overflowing list holds whichever windows came first)
+    prm = pd.params(precision=prec, margin=0.05) if prec == pd.PREC_BF16 else pd.params()
+    views, bufs = [], []
+    for k, img in enumerate(frames):
+        h, w = img.shape
+        off, pitch = 1 + k, w + 7 + 2 * k
+        buf = torch.zeros(h * pitch + 64, dtype=torch.uint8, device=DEV)
+        v = buf[off:off + h * pitch].view(h, pitch)[:, :w]
+        v.copy_(to_dev(img))
+        assert v.data_ptr() % 4 == off % 4 and v.stride(0) == pitch
+        views.append(v)
+        bufs.append(buf)
+    got_b, got_c = run_detect_views(views, wts, bias, thr, prm)
+    exp_b, exp_c = run_detect(frames, wts, bias, thr, prm)
+    assert np.all(exp_c["overflow"] == 0) and np.all(exp_c["kept"] > 0)
+    assert got_c.tobytes() == exp_c.tobytes()
+    for f in range(len(frames)):
+        assert got_b[f].tobytes() == exp_b[f].tobytes(), f"frame {f}"
