@@ -296,6 +296,32 @@ def test_nms_matches_oracle_random():
         assert [tuple(int(b[k]) for k in ("x0", "y0", "x1", "y1")) for b in got] == [c["box"] for c in exp]
 
 
+def test_nms_full_list_with_ties():
+    """A list of PD_MAX_CANDIDATES distinct windows over three levels, scores
+    from a small set (many exact ties, +0 and -0 among them, which tie):
+    the kept list, in order, equals the oracle's greedy NMS."""
+    rng = np.random.default_rng(44)
+    wh = [(1242, 375), (1129, 340), (1026, 309)]
+    allw = [(k, i, j) for k, (w, h) in enumerate(wh) for i in range(O.window_grid(w, h)[0])
+            for j in range(O.window_grid(w, h)[1])]
+    pick = rng.choice(len(allw), size=pd.MAX_CANDIDATES, replace=False)
+    values = np.array([-0.0, 0.0, 1.25, -2.5, 3.0, 0.5], np.float32)
+    cands = []
+    for q, p in enumerate(pick):
+        k, i, j = allw[int(p)]
+        s = float(values[q % len(values)]) if q % 3 else float(np.float32(rng.normal()))
+        cands.append({"score": s, "level": k, "i": i, "j": j, "model": 0,
+                      "box": O.window_box_q8(1242, 375, wh[k][0], wh[k][1], i, j)})
+    n = len(cands)
+    cs = to_dev(np.array([c["score"] for c in cands], np.float32))
+    ck = to_dev(np.array([[c["level"], c["i"], c["j"], 0] for c in cands], np.int32))
+    boxes, counts = pd.nms(cs, ck, wh, cap=n)
+    got, cnt = pd.decode_boxes(boxes, counts)
+    exp = O.nms(cands)
+    assert cnt["candidates"] == n and cnt["overflow"] == 0 and cnt["kept"] == len(exp)
+    assert [(int(b["level"]), int(b["i"]), int(b["j"])) for b in got] == [(c["level"], c["i"], c["j"]) for c in exp]
+
+
 def test_nms_cap_reports_overflow():
     wh = [(1242, 375)]
     n = 40
