@@ -26,11 +26,18 @@ def reference(frames, wts, bias, thr):
     return out
 
 
-@pytest.mark.parametrize("w,h,depth", [(640, 480, 3), (1242, 375, 2), (333, 257, 1)])
-def test_video_equals_per_frame_detect(w, h, depth):
+@pytest.mark.parametrize("w,h,depth,n", [(640, 480, 3, 7), (1242, 375, 2, 7), (333, 257, 1, 7), (640, 480, 16, 21),
+                                         (65, 129, 4, 9)])
+def test_video_equals_per_frame_detect(w, h, depth, n):
+    """Depth 16 is the largest ring; a 65x129 frame has exactly one window,
+    which every frame reports (threshold below any score)."""
     print(f"video {w}x{h} depth {depth}", flush=True)
-    frames = [pd_synth.frame(w, h, 1500 + k) for k in range(7)]
-    thr = [4.0 + 0.4 * (k % 3) for k in range(7)]  # a few hundred candidates, below the list cap
+    frames = [pd_synth.frame(w, h, 1500 + k) for k in range(n)]
+    one_window = (w // 8 - 7) * (h // 8 - 15) == 1
+    if one_window:
+        thr = [-1e30] * n
+    else:
+        thr = [4.0 + 0.4 * (k % 3) for k in range(n)]  # a few hundred candidates, below the list cap
     wts = torch.from_numpy(pd_synth.svm_weights(1)).to(DEV)
     bias = torch.from_numpy(pd_synth.svm_bias(1)).to(DEV)
     ref = reference(frames, wts, bias, thr)
@@ -45,6 +52,8 @@ def test_video_equals_per_frame_detect(w, h, depth):
     assert len(got) == len(frames)
     for (gb, gc, ms), (rb, rc) in zip(got, ref):
         assert rc["overflow"] == 0 and rc["kept"] > 0
+        if one_window:
+            assert rc["candidates"] == 1 and rc["kept"] == 1
         assert gb.tobytes() == rb.tobytes()
         assert gc.tobytes() == rc.tobytes()
         assert ms > 0.0
