@@ -39,6 +39,11 @@ extern "C" {
 #define PD_E_SIZE       (-2)  /* non-positive or over-limit dimensions       */
 #define PD_E_WORKSPACE  (-3)  /* workspace missing or too small              */
 #define PD_E_HIP        (-4)  /* a HIP launch or copy reported an error      */
+#define PD_E_OVERFLOW   (-5)  /* results complete but truncated: more
+                                 candidates or kept boxes than capacity (the
+                                 highest-scoring were kept, the true counts
+                                 reported); returned only by calls that wait
+                                 for their results (pd_video_pop)            */
 
 /* ---- fixed geometry ---------------------------------------------------- */
 #define PD_CELL          8
@@ -60,7 +65,8 @@ extern "C" {
 #define PD_MAX_LEVELS    64
 #define PD_MAX_DIM       16384  /* largest accepted image side             */
 #define PD_MAX_MODELS    16
-#define PD_MAX_CANDIDATES 4096  /* windows above threshold kept per frame  */
+#define PD_MAX_CANDIDATES 4096  /* candidates per frame that NMS takes: the
+                                   highest-scoring ones when a frame has more */
 
 /* feature subsets (Section 4.1: LBP-SVM, HOG-SVM, HOGLBP-SVM) */
 #define PD_FEAT_HOG      1
@@ -72,7 +78,6 @@ extern "C" {
                                  FP64 rescoring of near-threshold windows     */
 #define PD_MAX_MODELS_BF16 8  /* 8 models x {hi, lo} weight halves = 16 MFMA
                                  columns                                      */
-#define PD_MAX_NEAR      1024 /* near-threshold windows rescored per frame    */
 
 /* ---- parameters -------------------------------------------------------- */
 typedef struct pd_params {
@@ -286,15 +291,19 @@ typedef struct pd_box {
 
 /* Per-frame result counters written by pd_detect. */
 typedef struct pd_counts {
-    int32_t candidates;  /* windows with score > threshold (true count)    */
+    int32_t candidates;  /* windows with score > threshold (true count; every
+                            one is in the frame's candidate list)          */
     int32_t kept;        /* boxes written after NMS (<= cap)               */
     int32_t overflow;    /* 1 if candidates > PD_MAX_CANDIDATES or the kept
-                            boxes exceeded `cap` (results then incomplete:
-                            past PD_MAX_CANDIDATES the list holds the
-                            windows compacted first, which may differ from
-                            run to run; past `cap`, the first `cap` kept) */
-    int32_t rescored;    /* PD_PREC_BF16: windows rescored in FP64 (true
-                            count; at most PD_MAX_NEAR were rescored)      */
+                            boxes exceeded `cap`.  Past PD_MAX_CANDIDATES,
+                            NMS runs on the PD_MAX_CANDIDATES highest-scoring
+                            candidates (score descending, then level, i, j
+                            ascending: a strict order, so the same inputs
+                            always give the same boxes); past `cap`, the
+                            first `cap` kept boxes (the highest-scoring)
+                            are written                                    */
+    int32_t rescored;    /* PD_PREC_BF16: windows rescored in FP64 (every
+                            window within the margin of the threshold)     */
 } pd_counts;
 
 /*
@@ -313,10 +322,15 @@ int64_t pd_detect_workspace_bytes(const pd_frame* frames, int n_frames,
  * level, i, j ascending).  With params->precision == PD_PREC_BF16 (at most
  * 8 models) the HOG features are stored in BF16, scores come from BF16 MFMA,
  * and every window whose score is within params->margin of the threshold is
- * recomputed from its pixels in FP64; its FP64 score decides.  A box is
- * suppressed iff its IoU with a kept box is > 0.5, decided exactly as
- * 2*inter > union on the integer boxes.  Every stage is one launch over all
- * frames and levels.
+ * recomputed from its pixels in FP64 (no matter how many: the near list has
+ * room for every window of the batch); its FP64 score decides.  With a
+ * feature subset (params->features), BF16 scoring and the FP64 rescore read
+ * only that family's features and weights.  Every candidate (window above
+ * the threshold) of a frame is kept in a list sized by the frame's window
+ * count; NMS runs on at most PD_MAX_CANDIDATES of them, the highest-scoring
+ * (see pd_counts).  A box is suppressed iff its IoU with a kept box is >
+ * 0.5, decided exactly as 2*inter > union on the integer boxes.  Every stage
+ * is one launch over all frames and levels.
  *   frames     : host array of n_frames descriptors (device images)
  *   weights    : device float [n_models][11332], bias: device [n_models]
  *   thresholds : device double [n_frames]
@@ -339,10 +353,13 @@ int pd_detect(const pd_frame* frames, int n_frames, const float* weights,
  * pd_graph_create -- the kernel sequence of pd_detect on exactly these
  * arguments, captured once into a HIP graph for replay by pd_graph_launch
  * (HIP graph capture in place of per-call launches; the work is that of
- * Section 4.1 steps 2-5 as in pd_detect).  The call uploads the level and
- * tile tables into `workspace` now and waits for that copy on `stream`; the
- * graph holds kernels only (the counters are cleared by a kernel).  Every
- * pointer argument is baked into the graph: the frames, weights, bias,
+ * Section 4.1 steps 2-5 as in pd_detect).  The call allocates device memory
+ * for the graph's own copy of the level and tile tables (freed by
+ * pd_graph_destroy), uploads them now and waits for that copy on `stream`;
+ * the graph holds kernels only (the counters are cleared by a kernel).  So
+ * pd_detect, pd_autotune or other graphs may use the same workspace between
+ * launches (one at a time: they share its feature and candidate buffers).
+ * Every pointer argument is baked into the graph: the frames, weights, bias,
  * thresholds, workspace, boxes and counts must stay allocated until
  * pd_graph_destroy, and their contents may change between launches (new
  * pixels in the same frame buffers, new thresholds or weights).  Frame sizes
@@ -421,7 +438,9 @@ int pd_video_push(pd_video* v, const uint8_t* frame, int pitch, double threshold
  * up to `cap` boxes (host buffers, NMS order, frame index 0) to the caller.
  * `device_ms` (host, may be NULL) receives the GPU time from the start of its
  * upload to the end of its download, queueing behind earlier frames included.
- * Errors: PD_E_ARG when no frame is in flight or on a NULL pointer.
+ * Errors: PD_E_ARG when no frame is in flight or on a NULL pointer;
+ * PD_E_OVERFLOW (the frame is popped and its counts and boxes written) when
+ * its counts report an overflow or it kept more boxes than `cap`.
  */
 int pd_video_pop(pd_video* v, pd_box* boxes, int cap, pd_counts* counts, float* device_ms);
 
@@ -546,9 +565,10 @@ int pd_pruner_logits_bf16(const uint8_t* level, int w, int h, int pitch, const p
 
 /*
  * pd_detect_candidates -- test hook: after pd_detect on the same arguments
- * (frames, params, n_models, workspace), enqueue copies of frame `frame`'s
- * candidate list (windows above the threshold, before NMS, in no particular
- * order; min(pd_counts.candidates, PD_MAX_CANDIDATES) entries):
+ * (frames, params, n_models, workspace), enqueue copies of the first `cap`
+ * entries of frame `frame`'s candidate list (windows above the threshold,
+ * before NMS, in no particular order; the list holds
+ * pd_counts.candidates entries, every candidate of the frame):
  *   cand_score : device float [cap]; cand_key: device int32 [cap][4] =
  *                (level, i, j, model); cand_s64: device double [cap] or NULL
  *                (FP64 score for rescored windows, NaN otherwise; PD_PREC_BF16)
@@ -556,6 +576,7 @@ int pd_pruner_logits_bf16(const uint8_t* level, int w, int h, int pitch, const p
 int pd_detect_candidates(const pd_frame* frames, int n_frames, const pd_params* params, int n_models,
                          const void* workspace, int64_t workspace_bytes, int frame, float* cand_score,
                          int32_t* cand_key, double* cand_s64, int cap, void* stream);
+/* Errors: PD_E_SIZE when cap exceeds the frame's window count. */
 
 /*
  * pd_nms -- greedy NMS of one candidate list (the last stage of pd_detect,

@@ -424,6 +424,14 @@ def nms(cands: list) -> list:
     return kept
 
 
+def select_top(cands: list, limit: int) -> list:
+    """The `limit` first candidates in the NMS order (score descending, then
+    level, i, j ascending): the ones NMS takes when a frame has more than it
+    holds (the candidate list is not refined past that many; a reading, the
+    paper fixes no such limit)."""
+    return sorted(cands, key=lambda c: (-c["score"], c["level"], c["i"], c["j"]))[:limit]
+
+
 def max_over_models(scores: np.ndarray):
     """(max score, argmax model with lowest index on ties) over axis 0."""
     scores = np.asarray(scores, dtype=np.float64)

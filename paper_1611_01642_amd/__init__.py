@@ -28,10 +28,9 @@ MAX_CANDIDATES = 4096
 FEAT_HOG, FEAT_LBP = 1, 2
 PREC_F32, PREC_BF16 = 0, 1
 MAX_MODELS_BF16 = 8
-MAX_NEAR = 1024
 PRUNER_CHANNELS, PRUNER_PARAMS = 68, 33505
 
-E_ARG, E_SIZE, E_WORKSPACE, E_HIP = -1, -2, -3, -4
+E_ARG, E_SIZE, E_WORKSPACE, E_HIP, E_OVERFLOW = -1, -2, -3, -4, -5
 
 
 class PdError(RuntimeError):
@@ -575,7 +574,7 @@ class Detector:
         frame's pre-NMS candidate list (after run(); n = candidates count)."""
         torch = _torch()
         counts = self.counts.cpu().numpy().view(COUNTS_DTYPE)
-        n = int(min(counts[frame]["candidates"], MAX_CANDIDATES))
+        n = int(counts[frame]["candidates"])
         dev = self.frames[0].device
         cs = torch.empty(max(n, 1), dtype=torch.float32, device=dev)
         ck = torch.empty((max(n, 1), 4), dtype=torch.int32, device=dev)
@@ -622,8 +621,10 @@ class Video:
 
     def pop(self):
         ms = ctypes.c_float(0.0)
-        _check(lib().pd_video_pop(self.handle, ctypes.c_void_p(self._boxes.ctypes.data), self.cap,
-                                  ctypes.c_void_p(self._counts.ctypes.data), ctypes.byref(ms)))
+        rc = lib().pd_video_pop(self.handle, ctypes.c_void_p(self._boxes.ctypes.data), self.cap,
+                                ctypes.c_void_p(self._counts.ctypes.data), ctypes.byref(ms))
+        if rc != E_OVERFLOW:  # a truncated frame is still a result: counts["overflow"] says so
+            _check(rc)
         n = int(min(self._counts[0]["kept"], self.cap))
         return self._boxes[:n].copy(), self._counts[0].copy(), float(ms.value)
 

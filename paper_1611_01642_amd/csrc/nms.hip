@@ -3,7 +3,13 @@
 //
 // compact: one thread per window; the window's score is the max over the
 //   models (lowest model index on ties); windows with score > threshold are
-//   appended to their frame's candidate list with an atomic counter.
+//   appended to their frame's candidate list with an atomic counter.  A
+//   frame's list has room for every one of its windows, so none is dropped.
+// select: for a frame with more than PD_MAX_CANDIDATES candidates, the
+//   PD_MAX_CANDIDATES highest-scoring ones (score descending, then level, i,
+//   j ascending: a strict order, keys are distinct) by a radix select over
+//   the 64-bit NMS sort key; the selected set does not depend on the order
+//   in which compaction appended the list.
 // nms: one workgroup (16 waves) per frame.  Candidates are sorted by (score descending,
 //   level, i, j ascending) with a bitonic sort in LDS; the greedy pass walks
 //   them in chunks of 64: a candidate is suppressed if it overlaps (IoU > 0.5,
@@ -29,7 +35,7 @@ __global__ void __launch_bounds__(256) compact_kernel(const LevelItem* __restric
                                                       float* __restrict__ cand_score,
                                                       int4* __restrict__ cand_key, double* __restrict__ cand_s64,
                                                       int32_t* __restrict__ near_count,
-                                                      int4* __restrict__ near_key, int n_frames,
+                                                      int4* __restrict__ near_key, int64_t near_cap, int n_frames,
                                                       const float* __restrict__ kth) {
     const Tile tl = tiles[blockIdx.x];
     const LevelItem& it = items[tl.item];
@@ -54,17 +60,16 @@ __global__ void __launch_bounds__(256) compact_kernel(const LevelItem* __restric
     const int i = q / it.nx;
     if (margin > 0.0f && fabs((double)best - thr) < (double)margin) {
         // too close to call in this precision: rescored in FP64.  near_count
-        // holds one counter per frame (capped at MAX_NEAR) and, after them,
-        // the length of the dense list of all frames' near windows.
-        const int pos = atomicAdd(&near_count[it.frame], 1);
-        if (pos < MAX_NEAR) {
-            const int g = atomicAdd(&near_count[n_frames], 1);
-            near_key[g] = make_int4(it.frame * PD_MAX_LEVELS + it.level, i, q - i * it.nx, bm);
-        }
+        // holds one counter per frame and, after them, the length of the
+        // dense list of all frames' near windows (room for every window of
+        // the batch: the bound is never reached)
+        atomicAdd(&near_count[it.frame], 1);
+        const int g = atomicAdd(&near_count[n_frames], 1);
+        if (g < near_cap) near_key[g] = make_int4(it.frame * PD_MAX_LEVELS + it.level, i, q - i * it.nx, bm);
     } else if ((double)best > thr) {
         const int pos = atomicAdd(&counters[it.frame], 1);
-        if (pos < PD_MAX_CANDIDATES) {
-            const size_t o = (size_t)it.frame * PD_MAX_CANDIDATES + pos;
+        if (pos < it.cand_cap) {  // always: a window is appended once at most
+            const size_t o = (size_t)it.cand_off + pos;
             cand_score[o] = best;
             cand_key[o] = make_int4(it.level, i, q - i * it.nx, bm);
             if (cand_s64) cand_s64[o] = __longlong_as_double(0x7ff8000000000000LL);
@@ -119,6 +124,70 @@ __device__ inline bool overlaps(const int4& a, const int4& b) {
     const double inter = (double)iw * (double)ih;
     const double uni = (double)(a.z - a.x) * (double)(a.w - a.y) + (double)(b.z - b.x) * (double)(b.w - b.y) - inter;
     return 2.0 * inter > uni;
+}
+
+// One workgroup per frame.  Finds the PD_MAX_CANDIDATES-th smallest key of
+// the frame's list, one byte per pass from the top (LDS histogram of the
+// keys that share the bytes found so far), then copies every entry whose key
+// is at most that one: exactly PD_MAX_CANDIDATES entries, the keys being
+// distinct.  Their order in the output is immaterial (NMS sorts by key).
+constexpr int SEL_THREADS = 1024;
+
+__global__ void __launch_bounds__(SEL_THREADS) cand_select_kernel(const NmsGeom* __restrict__ geoms,
+                                                                  const int32_t* __restrict__ counters,
+                                                                  const float* __restrict__ cand_score,
+                                                                  const int4* __restrict__ cand_key,
+                                                                  const double* __restrict__ cand_s64,
+                                                                  float* __restrict__ sel_score,
+                                                                  int4* __restrict__ sel_key,
+                                                                  double* __restrict__ sel_s64) {
+    const int f = blockIdx.x, t = threadIdx.x;
+    const int n = min(counters[f], geoms[f].cand_cap);
+    if (n <= PD_MAX_CANDIDATES) return;
+    const size_t base = (size_t)geoms[f].cand_off;
+    const float* cs = cand_score + base;
+    const int4* ck = cand_key + base;
+    __shared__ uint32_t hist[256];
+    __shared__ unsigned long long s_prefix;
+    __shared__ int s_rank, s_out;
+    unsigned long long prefix = 0ull, mask = 0ull;
+    int rank = PD_MAX_CANDIDATES;  // 1-based rank sought among the keys matching prefix
+    for (int shift = 56; shift >= 0; shift -= 8) {
+        if (t < 256) hist[t] = 0u;
+        __syncthreads();
+        for (int q = t; q < n; q += SEL_THREADS) {
+            const unsigned long long key = sort_key(cs[q], ck[q]);
+            if ((key & mask) == prefix) atomicAdd(&hist[(uint32_t)(key >> shift) & 255u], 1u);
+        }
+        __syncthreads();
+        if (t == 0) {
+            int acc = 0, d = 0;
+            for (; d < 255; ++d) {
+                if (acc + (int)hist[d] >= rank) break;
+                acc += (int)hist[d];
+            }
+            s_rank = rank - acc;
+            s_prefix = prefix | ((unsigned long long)d << shift);
+        }
+        __syncthreads();
+        rank = s_rank;
+        prefix = s_prefix;
+        mask |= 255ull << shift;
+        __syncthreads();  // s_rank / s_prefix are rewritten by the next pass
+    }
+    if (t == 0) s_out = 0;
+    __syncthreads();
+    const size_t o = (size_t)f * PD_MAX_CANDIDATES;
+    for (int q = t; q < n; q += SEL_THREADS) {
+        if (sort_key(cs[q], ck[q]) <= prefix) {
+            const int pos = atomicAdd(&s_out, 1);
+            if (pos < PD_MAX_CANDIDATES) {
+                sel_score[o + pos] = cs[q];
+                sel_key[o + pos] = ck[q];
+                if (sel_s64) sel_s64[o + pos] = cand_s64[base + q];
+            }
+        }
+    }
 }
 
 __device__ void nms_frame(const NmsGeom& g, int frame, int raw_count, const float* __restrict__ cs,
@@ -258,13 +327,29 @@ __global__ void __launch_bounds__(NMS_THREADS) nms_table_kernel(const NmsGeom* _
                                                         const float* __restrict__ cand_score,
                                                         const int4* __restrict__ cand_key,
                                                         const double* __restrict__ cand_s64,
+                                                        const float* __restrict__ sel_score,
+                                                        const int4* __restrict__ sel_key,
+                                                        const double* __restrict__ sel_s64,
                                                         const int32_t* __restrict__ near_count,
                                                         pd_box* __restrict__ boxes, int cap,
                                                         pd_counts* __restrict__ counts) {
     const int f = blockIdx.x;
-    const size_t o = (size_t)f * PD_MAX_CANDIDATES;
-    nms_frame(geoms[f], f, counters[f], cand_score + o, cand_key + o, cand_s64 ? cand_s64 + o : nullptr,
-              near_count ? near_count[f] : 0, boxes, cap, counts);
+    const int n = counters[f];
+    const float* cs;
+    const int4* ck;
+    const double* c64;
+    if (n > PD_MAX_CANDIDATES) {  // the selected highest-scoring candidates
+        const size_t o = (size_t)f * PD_MAX_CANDIDATES;
+        cs = sel_score + o;
+        ck = sel_key + o;
+        c64 = sel_s64 ? sel_s64 + o : nullptr;
+    } else {
+        const size_t o = (size_t)geoms[f].cand_off;
+        cs = cand_score + o;
+        ck = cand_key + o;
+        c64 = cand_s64 ? cand_s64 + o : nullptr;
+    }
+    nms_frame(geoms[f], f, n, cs, ck, c64, near_count ? near_count[f] : 0, boxes, cap, counts);
 }
 
 __global__ void __launch_bounds__(NMS_THREADS) nms_single_kernel(NmsGeom g, int n, const float* __restrict__ cs,
@@ -284,42 +369,36 @@ hipError_t launch_zero_i32(int32_t* p, int n, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_compact_margin(const LevelItem* items, const Tile* tiles, int n_tiles, int n_models,
-                                 const double* thresholds, float margin, int32_t* counters, float* cand_score,
-                                 int4* cand_key, double* cand_s64, int32_t* near_count, int4* near_key,
-                                 int n_frames, hipStream_t s) {
+hipError_t launch_compact(const LevelItem* items, const Tile* tiles, int n_tiles, int n_models,
+                          const double* thresholds, float margin, int32_t* counters, float* cand_score,
+                          int4* cand_key, double* cand_s64, int32_t* near_count, int4* near_key, int64_t near_cap,
+                          int n_frames, const float* kth, hipStream_t s) {
     if (n_tiles <= 0) return hipSuccess;
     compact_kernel<<<n_tiles, 256, 0, s>>>(items, tiles, n_models, thresholds, margin, counters, cand_score, cand_key,
-                                           cand_s64, near_count, near_key, n_frames, nullptr);
+                                           cand_s64, near_count, near_key, near_cap, n_frames, kth);
     return hipGetLastError();
 }
 
-hipError_t launch_compact_margin_pruned(const LevelItem* items, const Tile* tiles, int n_tiles, int n_models,
-                                       const double* thresholds, float margin, int32_t* counters, float* cand_score,
-                                       int4* cand_key, double* cand_s64, int32_t* near_count, int4* near_key,
-                                       int n_frames, const float* kth, hipStream_t s) {
-    if (n_tiles <= 0) return hipSuccess;
-    compact_kernel<<<n_tiles, 256, 0, s>>>(items, tiles, n_models, thresholds, margin, counters, cand_score, cand_key,
-                                           cand_s64, near_count, near_key, n_frames, kth);
+hipError_t launch_cand_select(const NmsGeom* geoms, int n_frames, const int32_t* counters, const float* cand_score,
+                              const int4* cand_key, const double* cand_s64, float* sel_score, int4* sel_key,
+                              double* sel_s64, hipStream_t s) {
+    if (n_frames <= 0) return hipSuccess;
+    cand_select_kernel<<<n_frames, SEL_THREADS, 0, s>>>(geoms, counters, cand_score, cand_key, cand_s64, sel_score,
+                                                        sel_key, sel_s64);
     return hipGetLastError();
-}
-
-hipError_t launch_compact_table(const LevelItem* items, const Tile* tiles, int n_tiles, int n_models,
-                                const double* thresholds, int32_t* counters, float* cand_score,
-                                int4* cand_key, hipStream_t s) {
-    return launch_compact_margin(items, tiles, n_tiles, n_models, thresholds, 0.0f, counters, cand_score, cand_key,
-                                 nullptr, nullptr, nullptr, 0, s);
 }
 
 hipError_t launch_nms_table(const NmsGeom* geoms, int n_frames, const int32_t* counters,
                             const float* cand_score, const int4* cand_key, const double* cand_s64,
+                            const float* sel_score, const int4* sel_key, const double* sel_s64,
                             const int32_t* near_count, pd_box* boxes, int cap, pd_counts* counts, hipStream_t s) {
     if (n_frames <= 0) return hipSuccess;
     static const hipError_t attr = hipFuncSetAttribute(reinterpret_cast<const void*>(&nms_table_kernel),
                                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)kNmsSmem);
     if (attr != hipSuccess) return attr;
-    nms_table_kernel<<<n_frames, NMS_THREADS, kNmsSmem, s>>>(geoms, counters, cand_score, cand_key, cand_s64, near_count,
-                                                    boxes, cap, counts);
+    nms_table_kernel<<<n_frames, NMS_THREADS, kNmsSmem, s>>>(geoms, counters, cand_score, cand_key, cand_s64,
+                                                             sel_score, sel_key, sel_s64, near_count, boxes, cap,
+                                                             counts);
     return hipGetLastError();
 }
 

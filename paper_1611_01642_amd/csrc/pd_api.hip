@@ -292,13 +292,18 @@ struct DetectLayout {
     int n_items = 0;
     int n_rs = 0, n_ft = 0, n_sc = 0, n_cp = 0, n_pr = 0;  // tile table capacities
     bool bf16 = false;
+    bool rowgemm = false;  // BF16, one model, HOG and LBP: the row-GEMM scoring kernel and its strip tiles
     bool prune = false;  // learned pruning: cell maps, network, top-K, tile filter
     int64_t off_kth = 0, off_kept = 0, off_prpack = 0;
     std::vector<int64_t> cm_off, a1_off, a2_off, lg_off;  // per item (pruning)
     int64_t off_items = 0, off_tiles = 0, off_geoms = 0, off_first = 0, off_counters = 0, off_cscore = 0,
             off_ckey = 0, off_c64 = 0, off_near_count = 0, off_near_key = 0, off_packed = 0, off_orient = 0;
+    int64_t off_sel_score = 0, off_sel_key = 0, off_sel_64 = 0;  // per frame, the top PD_MAX_CANDIDATES
     int64_t off_data = 0, total = 0;
     int64_t table_bytes = 0;  // bytes uploaded from the host (items .. geoms)
+    int64_t n_windows = 0;    // windows of the batch: the candidate lists' and the near list's capacity
+    std::vector<int64_t> cand_off;        // per frame: first entry of its candidate list
+    std::vector<int> cand_cap;            // per frame: its window count
     std::vector<int> level_count;         // per frame
     std::vector<int> sizes;               // per item: w, h
     std::vector<int64_t> pyr_off, hog_off, lbp_off, sc_off;  // per item, from off_data
@@ -307,6 +312,7 @@ struct DetectLayout {
 bool plan_detect(const pd_frame* frames, int n_frames, const pd_params* p, int n_models, DetectLayout& L) {
     L = DetectLayout();
     L.bf16 = p->precision == PD_PREC_BF16;
+    L.rowgemm = L.bf16 && n_models == 1 && p->features == (PD_FEAT_HOG | PD_FEAT_LBP);
     L.prune = p->prune_keep > 0;
     L.level_count.resize(n_frames);
     int wh[PD_MAX_LEVELS][2];
@@ -317,9 +323,12 @@ bool plan_detect(const pd_frame* frames, int n_frames, const pd_params* p, int n
             return fail(PD_E_SIZE, "frame %d size %dx%d outside [1, %d]", f, w, h, PD_MAX_DIM), false;
         const int n = plan_sizes(w, h, p, wh);
         L.level_count[f] = n;
+        L.cand_off.push_back(L.n_windows);
+        int64_t frame_windows = 0;
         for (int k = 0; k < n; ++k) {
             LevelItem it{};
             item_geometry(it, wh[k][0], wh[k][1]);
+            frame_windows += (int64_t)it.nx * it.ny;
             L.sizes.push_back(wh[k][0]);
             L.sizes.push_back(wh[k][1]);
             // level 0 is read from the frame itself when its rows are 8-byte
@@ -348,12 +357,14 @@ bool plan_detect(const pd_frame* frames, int n_frames, const pd_params* p, int n
             // table capacity for the finest tile shapes the tuning fields
             // allow, so the workspace size does not depend on them
             L.n_ft += (L.prune ? feat_tiles_x_cm(it.wc) : feat_tiles_x(it.wc)) * feat_tiles_y(it.hc, FT_MIN_ROWS);
-            L.n_sc += !L.bf16 ? score_tiles_x(it.nx) * score_tiles_y(it.ny, 4) * n_models
-                      : n_models == 1 ? ceil_div(it.nx, RG_TILE_C)
-                                      : ceil_div(it.nx, MF_TILE_C) * ceil_div(it.ny, MF_TILE_R);
+            L.n_sc += !L.bf16    ? score_tiles_x(it.nx) * score_tiles_y(it.ny, 4) * n_models
+                      : L.rowgemm ? ceil_div(it.nx, RG_TILE_C)
+                                  : ceil_div(it.nx, MF_TILE_C) * ceil_div(it.ny, MF_TILE_R);
             L.n_cp += ceil_div(it.nx * it.ny, CP_N);
             ++L.n_items;
         }
+        L.cand_cap.push_back((int)frame_windows);  // at most 2041 x 2033 x 51 levels < 2^31
+        L.n_windows += frame_windows;
     }
     int64_t o = 0;
     L.off_items = o;
@@ -369,15 +380,22 @@ bool plan_detect(const pd_frame* frames, int n_frames, const pd_params* p, int n
     o = align_up(o + (int64_t)n_frames * 4, kAlign);
     L.off_near_count = o;  // per-frame near counters + the dense list length (+ kept tiles)
     o = align_up(o + (int64_t)(n_frames + 2) * 4, kAlign);
+    // candidate lists: room for every window of every frame
     L.off_cscore = o;
-    o = align_up(o + (int64_t)n_frames * PD_MAX_CANDIDATES * 4, kAlign);
+    o = align_up(o + L.n_windows * 4, kAlign);
     L.off_ckey = o;
+    o = align_up(o + L.n_windows * 16, kAlign);
+    L.off_sel_score = o;
+    o = align_up(o + (int64_t)n_frames * PD_MAX_CANDIDATES * 4, kAlign);
+    L.off_sel_key = o;
     o = align_up(o + (int64_t)n_frames * PD_MAX_CANDIDATES * 16, kAlign);
     if (L.bf16) {
         L.off_c64 = o;
+        o = align_up(o + L.n_windows * 8, kAlign);
+        L.off_sel_64 = o;
         o = align_up(o + (int64_t)n_frames * PD_MAX_CANDIDATES * 8, kAlign);
-        L.off_near_key = o;
-        o = align_up(o + (int64_t)n_frames * MAX_NEAR * 16, kAlign);
+        L.off_near_key = o;  // every window of the batch may be near
+        o = align_up(o + L.n_windows * 16, kAlign);
         L.off_packed = o;
         o = align_up(o + (packed_weight_elems() + rowgemm_packed_elems()) * 2, kAlign);
         L.off_orient = o;
@@ -481,7 +499,11 @@ struct DetectRun {
     float* cscore = nullptr;
     int4* ckey = nullptr;
     double* c64 = nullptr;
+    float* sel_score = nullptr;  // per frame, its PD_MAX_CANDIDATES highest-scoring candidates
+    int4* sel_key = nullptr;
+    double* sel_64 = nullptr;
     int4* near_key = nullptr;
+    int64_t near_cap = 0;
     uint16_t* packed = nullptr;
     double2* orient = nullptr;  // FP64 rescore's gradient table (BF16 precision)
     int n_zero = 0;  // counters + near counters (+ kept-tile count), cleared together
@@ -494,9 +516,11 @@ struct DetectRun {
 };
 
 // Builds the level, tile and NMS tables of one call in host memory `stage`
-// (L.table_bytes), laid out as they are uploaded to the start of `ws`.
+// (L.table_bytes), laid out as they are uploaded to device memory `tbl`: the
+// start of the workspace `ws` for pd_detect, a graph's own buffer for a
+// captured graph.  Every other buffer is in `ws`.
 void fill_tables(const pd_frame* frames, int n_frames, int n_models, const Tuning& tu, const DetectLayout& L,
-                 uint8_t* ws, uint8_t* stage, DetectRun& R) {
+                 uint8_t* ws, uint8_t* tbl, uint8_t* stage, DetectRun& R) {
     uint8_t* data = ws + L.off_data;
     std::memset(stage, 0, (size_t)L.table_bytes);
     LevelItem* items = reinterpret_cast<LevelItem*>(stage + L.off_items);
@@ -512,6 +536,8 @@ void fill_tables(const pd_frame* frames, int n_frames, int n_models, const Tunin
     std::vector<Tile> half;  // FP32 score tiles of half height, appended after the others
     for (int f = 0; f < n_frames; ++f) {
         geoms[f].n_levels = L.level_count[f];
+        geoms[f].cand_off = L.cand_off[f];
+        geoms[f].cand_cap = L.cand_cap[f];
         first[f] = q;
         for (int k = 0; k < L.level_count[f]; ++k, ++q) {
             LevelItem& it = items[q];
@@ -534,6 +560,8 @@ void fill_tables(const pd_frame* frames, int n_frames, int n_models, const Tunin
             it.scores = reinterpret_cast<float*>(data + L.sc_off[q]);
             it.frame = f;
             it.level = k;
+            it.cand_off = L.cand_off[f];
+            it.cand_cap = L.cand_cap[f];
             geoms[f].wh[k][0] = it.w;
             geoms[f].wh[k][1] = it.h;
             if (!direct) {  // tiles of `rows` rows (at least RS_TY: within the capacity counted above)
@@ -568,7 +596,7 @@ void fill_tables(const pd_frame* frames, int n_frames, int n_models, const Tunin
                 for (int ty = 0; ty < pruner_mfma_tiles_y(it.hc); ++ty)
                     for (int tx = 0; tx < ceil_div(it.wc, 64); ++tx) t_pr[npr++] = Tile{q, ty, tx, 0};
             }
-            if (L.bf16 && n_models == 1) {
+            if (L.rowgemm) {
                 for (int tx = 0; tx < ceil_div(it.nx, RG_TILE_C); ++tx) t_sc[nsc++] = Tile{q, 0, tx, 0};
             } else if (L.bf16) {
                 for (int ty = 0; ty < ceil_div(it.ny, MF_TILE_R); ++ty)
@@ -620,8 +648,8 @@ void fill_tables(const pd_frame* frames, int n_frames, int n_models, const Tunin
     }
     R.nsc_half = (int)half.size();  // within capacity: one tile each, as without the split
     for (int k = 0; k < R.nsc_half; ++k) t_sc[nsc + k] = half[k];
-    const Tile* d_tiles = reinterpret_cast<const Tile*>(ws + L.off_tiles);
-    R.items = reinterpret_cast<const LevelItem*>(ws + L.off_items);
+    const Tile* d_tiles = reinterpret_cast<const Tile*>(tbl + L.off_tiles);
+    R.items = reinterpret_cast<const LevelItem*>(tbl + L.off_items);
     R.t_rs = d_tiles;
     R.t_ft = d_tiles + L.n_rs;
     R.t_sc = d_tiles + L.n_rs + L.n_ft;
@@ -630,14 +658,18 @@ void fill_tables(const pd_frame* frames, int n_frames, int n_models, const Tunin
     R.nft = nft;
     R.nsc = nsc;
     R.ncp = ncp;
-    R.geoms = reinterpret_cast<const NmsGeom*>(ws + L.off_geoms);
-    R.first = reinterpret_cast<const int32_t*>(ws + L.off_first);
+    R.geoms = reinterpret_cast<const NmsGeom*>(tbl + L.off_geoms);
+    R.first = reinterpret_cast<const int32_t*>(tbl + L.off_first);
     R.counters = reinterpret_cast<int32_t*>(ws + L.off_counters);
     R.near_count = reinterpret_cast<int32_t*>(ws + L.off_near_count);
     R.cscore = reinterpret_cast<float*>(ws + L.off_cscore);
     R.ckey = reinterpret_cast<int4*>(ws + L.off_ckey);
     R.c64 = L.bf16 ? reinterpret_cast<double*>(ws + L.off_c64) : nullptr;
+    R.sel_score = reinterpret_cast<float*>(ws + L.off_sel_score);
+    R.sel_key = reinterpret_cast<int4*>(ws + L.off_sel_key);
+    R.sel_64 = L.bf16 ? reinterpret_cast<double*>(ws + L.off_sel_64) : nullptr;
     R.near_key = L.bf16 ? reinterpret_cast<int4*>(ws + L.off_near_key) : nullptr;
+    R.near_cap = L.bf16 ? L.n_windows : 0;
     R.packed = L.bf16 ? reinterpret_cast<uint16_t*>(ws + L.off_packed) : nullptr;
     R.orient = L.bf16 ? reinterpret_cast<double2*>(ws + L.off_orient) : nullptr;
     R.n_zero = (int)((L.off_cscore - L.off_counters) / 4);
@@ -649,6 +681,34 @@ void fill_tables(const pd_frame* frames, int n_frames, int n_models, const Tunin
         R.kept_count = reinterpret_cast<int32_t*>(ws + L.off_near_count) + n_frames + 1;
         R.prpack = reinterpret_cast<uint16_t*>(ws + L.off_prpack);
     }
+}
+
+// The decision stages of one call, after the scores: threshold and
+// compaction (kth: pruned keep set, or NULL), FP64 rescoring of the windows
+// within the margin (BF16), the selection of the highest-scoring candidates
+// of an overlong list, NMS.
+int enqueue_decide(const DetectRun& R, const DetectLayout& L, const float* weights, const float* bias, int n_models,
+                   const pd_params* params, const double* thresholds, int n_frames, pd_box* boxes, int cap,
+                   pd_counts* counts, StageMarks& marks, const float* kth, hipStream_t s) {
+    int rc;
+    if ((rc = hip_status(launch_compact(R.items, R.t_cp, R.ncp, n_models, thresholds, L.bf16 ? params->margin : 0.0f,
+                                        R.counters, R.cscore, R.ckey, R.c64, R.near_count, R.near_key, R.near_cap,
+                                        n_frames, kth, s),
+                         "compact")))
+        return rc;
+    if (L.bf16 && (rc = hip_status(launch_rescore64(R.items, R.first, n_frames, R.near_count, R.near_key, weights,
+                                                    bias, n_models, params->features, params->clip, params->eps,
+                                                    thresholds, R.counters, R.cscore, R.ckey, R.c64, R.orient, s),
+                                   "rescore")))
+        return rc;
+    if ((rc = hip_status(launch_cand_select(R.geoms, n_frames, R.counters, R.cscore, R.ckey, R.c64, R.sel_score,
+                                            R.sel_key, R.sel_64, s),
+                         "candidate select")))
+        return rc;
+    marks.mark(PD_STAGE_NMS, s);
+    return hip_status(launch_nms_table(R.geoms, n_frames, R.counters, R.cscore, R.ckey, R.c64, R.sel_score, R.sel_key,
+                                       R.sel_64, L.bf16 ? R.near_count : nullptr, boxes, cap, counts, s),
+                      "nms");
 }
 
 // The kernel sequence of one call (tables already uploaded).  Only kernels are
@@ -679,7 +739,7 @@ int enqueue_detect(const DetectRun& R, const DetectLayout& L, const Tuning& tu, 
         if ((rc = hip_status(launch_topk(R.items, R.first, R.geoms, n_frames, params->prune_keep, R.kth, s), "top-k")))
             return rc;
         const int rows = L.bf16 ? MF_TILE_R : tu.score_rows, cols = L.bf16 ? MF_TILE_C : SC_W;
-        if (L.bf16 && n_models == 1) {
+        if (L.rowgemm) {
             // one model: the row-GEMM kernel scores whole 64-column strips, which
             // nearly always hold a kept window; the keep set acts in compaction
             rc = hip_status(launch_rowgemm_table(R.items, R.t_sc, R.nsc, R.packed + packed_weight_elems(), bias,
@@ -699,28 +759,15 @@ int enqueue_detect(const DetectRun& R, const DetectLayout& L, const Tuning& tu, 
         }
         if (rc) return rc;
         marks.mark(PD_STAGE_COMPACT, s);
-        if ((rc = hip_status(launch_compact_margin_pruned(R.items, R.t_cp, R.ncp, n_models, thresholds,
-                                                          L.bf16 ? params->margin : 0.0f, R.counters, R.cscore,
-                                                          R.ckey, R.c64, R.near_count, R.near_key, n_frames, R.kth, s),
-                             "compact")))
-            return rc;
-        if (L.bf16 && (rc = hip_status(launch_rescore64(R.items, R.first, n_frames, R.near_count, R.near_key,
-                                                        weights, bias, n_models, params->clip, params->eps,
-                                                        thresholds, R.counters, R.cscore, R.ckey, R.c64, R.orient,
-                                                        s),
-                                       "rescore")))
-            return rc;
-        marks.mark(PD_STAGE_NMS, s);
-        return hip_status(launch_nms_table(R.geoms, n_frames, R.counters, R.cscore, R.ckey, R.c64,
-                                           L.bf16 ? R.near_count : nullptr, boxes, cap, counts, s),
-                          "nms");
+        return enqueue_decide(R, L, weights, bias, n_models, params, thresholds, n_frames, boxes, cap, counts, marks,
+                              R.kth, s);
     }
     if ((rc = hip_status(launch_features_table(R.items, R.t_ft, R.nft, params->features, params->clip, params->eps,
                                                tu, s),
                          "features")))
         return rc;
     marks.mark(PD_STAGE_SCORE, s);
-    if (L.bf16 && n_models == 1 && params->features == (PD_FEAT_HOG | PD_FEAT_LBP)) {
+    if (L.rowgemm) {
         if ((rc = hip_status(launch_rowgemm_table(R.items, R.t_sc, R.nsc, R.packed + packed_weight_elems(), bias,
                                                   tu.grid, s),
                              "bf16 score")))
@@ -736,20 +783,8 @@ int enqueue_detect(const DetectRun& R, const DetectLayout& L, const Tuning& tu, 
         return rc;
     }
     marks.mark(PD_STAGE_COMPACT, s);
-    if ((rc = hip_status(launch_compact_margin(R.items, R.t_cp, R.ncp, n_models, thresholds,
-                                               L.bf16 ? params->margin : 0.0f, R.counters, R.cscore, R.ckey, R.c64,
-                                               R.near_count, R.near_key, n_frames, s),
-                         "compact")))
-        return rc;
-    if (L.bf16 && (rc = hip_status(launch_rescore64(R.items, R.first, n_frames, R.near_count, R.near_key, weights,
-                                                    bias, n_models, params->clip, params->eps, thresholds,
-                                                    R.counters, R.cscore, R.ckey, R.c64, R.orient, s),
-                                   "rescore")))
-        return rc;
-    marks.mark(PD_STAGE_NMS, s);
-    return hip_status(launch_nms_table(R.geoms, n_frames, R.counters, R.cscore, R.ckey, R.c64,
-                                       L.bf16 ? R.near_count : nullptr, boxes, cap, counts, s),
-                      "nms");
+    return enqueue_decide(R, L, weights, bias, n_models, params, thresholds, n_frames, boxes, cap, counts, marks,
+                          nullptr, s);
 }
 
 }  // namespace
@@ -1162,7 +1197,7 @@ int pd_detect(const pd_frame* frames, int n_frames, const float* weights, const 
     }
     DetectRun R;
     fill_tables(frames, n_frames, n_models, tuning_of(params), L, static_cast<uint8_t*>(workspace),
-                static_cast<uint8_t*>(slot.host), R);
+                static_cast<uint8_t*>(workspace), static_cast<uint8_t*>(slot.host), R);
 
     int rc;
     StageMarks marks(g_prof.on);
@@ -1183,6 +1218,7 @@ struct pd_graph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     unsigned long long* stamps = nullptr;  // stage boundary clock stamps (captured with profiling on)
+    void* tables = nullptr;                // the graph's own level, tile and NMS tables
 };
 
 int pd_graph_create(const pd_frame* frames, int n_frames, const float* weights, const float* bias, int n_models,
@@ -1194,20 +1230,34 @@ int pd_graph_create(const pd_frame* frames, int n_frames, const float* weights, 
     if (int rc = validate_detect(frames, n_frames, weights, bias, n_models, params, thresholds, workspace,
                                  workspace_bytes, boxes, cap, counts, L))
         return rc;
-    // the tables are uploaded once, now; the graph holds only kernels
+    // the tables are uploaded once, now, into memory the graph owns (so a
+    // later pd_detect, capture or tuning run on the same workspace leaves
+    // them alone); the graph holds only kernels
     std::vector<uint8_t> host((size_t)L.table_bytes);
-    DetectRun R;
-    fill_tables(frames, n_frames, n_models, tuning_of(params), L, static_cast<uint8_t*>(workspace), host.data(), R);
+    pd_graph* g = new pd_graph();
     hipStream_t s = (hipStream_t)stream;
-    int rc;
-    if ((rc = hip_status(hipMemcpyAsync(workspace, host.data(), host.size(), hipMemcpyHostToDevice, s),
-                         "table upload")))
+    int rc = hip_status(hipMalloc(&g->tables, host.size()), "graph tables");
+    if (rc) {
+        delete g;
         return rc;
-    if ((rc = hip_status(hipStreamSynchronize(s), "table upload"))) return rc;
+    }
+    DetectRun R;
+    fill_tables(frames, n_frames, n_models, tuning_of(params), L, static_cast<uint8_t*>(workspace),
+                static_cast<uint8_t*>(g->tables), host.data(), R);
+    rc = hip_status(hipMemcpyAsync(g->tables, host.data(), host.size(), hipMemcpyHostToDevice, s), "table upload");
+    if (!rc) rc = hip_status(hipStreamSynchronize(s), "table upload");
+    if (rc) {
+        (void)hipFree(g->tables);
+        delete g;
+        return rc;
+    }
 
     hipStream_t cs = nullptr;  // capture needs a stream other than the null stream
-    if ((rc = hip_status(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "capture stream"))) return rc;
-    pd_graph* g = new pd_graph();
+    if ((rc = hip_status(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "capture stream"))) {
+        (void)hipFree(g->tables);
+        delete g;
+        return rc;
+    }
     StageMarks marks(false);
     if (g_prof.on) {  // the graph's own stamp slots
         rc = hip_status(hipMalloc(&g->stamps, (PD_N_STAGES + 1) * sizeof(unsigned long long)), "stage stamps");
@@ -1228,6 +1278,7 @@ int pd_graph_create(const pd_frame* frames, int n_frames, const float* weights, 
         if (g->exec) (void)hipGraphExecDestroy(g->exec);
         if (g->graph) (void)hipGraphDestroy(g->graph);
         if (g->stamps) (void)hipFree(g->stamps);
+        if (g->tables) (void)hipFree(g->tables);
         delete g;
         return rc;
     }
@@ -1251,6 +1302,10 @@ int pd_graph_destroy(pd_graph* g) {
     if (g->stamps) {
         const int r3 = hip_status(hipFree(g->stamps), "stage stamps");
         rc = rc ? rc : r3;
+    }
+    if (g->tables) {
+        const int r4 = hip_status(hipFree(g->tables), "graph tables");
+        rc = rc ? rc : r4;
     }
     delete g;
     return rc;
@@ -1372,15 +1427,16 @@ int pd_detect_candidates(const pd_frame* frames, int n_frames, const pd_params* 
                          int32_t* cand_key, double* cand_s64, int cap, void* stream) {
     if (!check_params(params)) return PD_E_ARG;
     if (!frames || n_frames < 1 || frame < 0 || frame >= n_frames) return fail(PD_E_ARG, "bad frame index");
-    if (cap < 0 || cap > PD_MAX_CANDIDATES) return fail(PD_E_SIZE, "cap outside [0, %d]", PD_MAX_CANDIDATES);
     if (!workspace || (cap > 0 && (!cand_score || !cand_key))) return fail(PD_E_ARG, "NULL pointer argument");
     DetectLayout L;
     if (!plan_detect(frames, n_frames, params, n_models, L)) return PD_E_SIZE;
     if (workspace_bytes < L.total) return fail(PD_E_WORKSPACE, "workspace smaller than pd_detect's");
     if (cand_s64 && !L.bf16) return fail(PD_E_ARG, "FP64 scores exist only with PD_PREC_BF16");
+    if (cap < 0 || cap > L.cand_cap[frame])
+        return fail(PD_E_SIZE, "cap outside [0, %d] (the frame's windows)", L.cand_cap[frame]);
     const uint8_t* ws = static_cast<const uint8_t*>(workspace);
     hipStream_t s = (hipStream_t)stream;
-    const size_t o = (size_t)frame * PD_MAX_CANDIDATES;
+    const size_t o = (size_t)L.cand_off[frame];
     int rc;
     if ((rc = hip_status(hipMemcpyAsync(cand_score, ws + L.off_cscore + o * 4, (size_t)cap * 4,
                                         hipMemcpyDeviceToDevice, s),

@@ -23,6 +23,8 @@ struct LevelItem {
     uint16_t* act1;       // pruner layer outputs [hc][wc][32] BF16
     uint16_t* act2;
     float* logit;         // pruner logits [hc][wc]
+    int64_t cand_off;     // the frame's first entry in the candidate lists
+    int32_t cand_cap;     // entries the frame owns there: its window count
     int32_t src_w, src_h, src_pitch;
     int32_t w, h, pitch;
     int32_t wc, hc, wb, hb, nx, ny;
@@ -60,10 +62,14 @@ __host__ __device__ inline int tile_width(const Tile& t) {
 }
 __host__ __device__ inline int32_t score_pad(int model, int width) { return model | ((width == 64 ? 0 : width) << 16); }
 
-// Greedy-NMS geometry of one frame: sizes of its levels, level 0 first.
+// Greedy-NMS geometry of one frame: sizes of its levels, level 0 first, and
+// where its candidate list lives.  A frame's candidate list holds one entry
+// per window at most, so it is sized by the frame's window count and never
+// drops a candidate; NMS takes the PD_MAX_CANDIDATES highest-scoring ones.
 struct NmsGeom {
     int32_t n_levels;
-    int32_t pad;
+    int32_t cand_cap;  // the frame's window count
+    int64_t cand_off;  // first entry of the frame's candidate list
     int32_t wh[PD_MAX_LEVELS][2];
 };
 
@@ -88,8 +94,6 @@ constexpr int SC_W = 64;
 constexpr int SC_WAVES = 4;  // waves (independent tiles) per workgroup
 // compaction: windows per workgroup
 constexpr int CP_N = 256;
-// FP64 rescoring: near-threshold windows kept per frame
-constexpr int MAX_NEAR = 1024;
 // MFMA scoring tile: window rows x window columns
 constexpr int MF_TILE_R = 4;
 constexpr int MF_TILE_C = 64;
@@ -205,15 +209,14 @@ hipError_t launch_mfma_single(const LevelItem& it, const uint16_t* wpk, const fl
 hipError_t launch_mfma_table(const LevelItem* items, const Tile* tiles, int n_tiles, const uint16_t* wpk,
                              const float* bias, int n_models, int features, int grid, hipStream_t s,
                              const int* n_dev = nullptr);
-// windows with |score - threshold| < margin go to the near list (margin <= 0: none)
-hipError_t launch_compact_margin_pruned(const LevelItem* items, const Tile* tiles, int n_tiles, int n_models,
-                                       const double* thresholds, float margin, int32_t* counters, float* cand_score,
-                                       int4* cand_key, double* cand_s64, int32_t* near_count, int4* near_key,
-                                       int n_frames, const float* kth, hipStream_t s);
-hipError_t launch_compact_margin(const LevelItem* items, const Tile* tiles, int n_tiles, int n_models,
-                                 const double* thresholds, float margin, int32_t* counters, float* cand_score,
-                                 int4* cand_key, double* cand_s64, int32_t* near_count, int4* near_key,
-                                 int n_frames, hipStream_t s);
+// Windows with |score - threshold| < margin go to the near list (margin <= 0:
+// none), whose capacity near_cap is the batch's window count, so no near
+// window is ever dropped.  kth (optional): per frame, the K-th largest window
+// logit of the pruner; only windows whose logit reaches it can be candidates.
+hipError_t launch_compact(const LevelItem* items, const Tile* tiles, int n_tiles, int n_models,
+                          const double* thresholds, float margin, int32_t* counters, float* cand_score,
+                          int4* cand_key, double* cand_s64, int32_t* near_count, int4* near_key, int64_t near_cap,
+                          int n_frames, const float* kth, hipStream_t s);
 // near_count[n_frames] is the length of the dense near list near_key
 // (entries: frame * PD_MAX_LEVELS + level, i, j, model)
 // Gradient table of the FP64 rescore: entry dy * ORIENT_W + dx + 255 (dy in
@@ -221,16 +224,25 @@ hipError_t launch_compact_margin(const LevelItem* items, const Tile* tiles, int 
 constexpr int ORIENT_W = 511, ORIENT_H = 256;
 constexpr int64_t ORIENT_BYTES = (int64_t)ORIENT_W * ORIENT_H * 16;
 hipError_t launch_orient_table(double2* table, hipStream_t s);
+// features: PD_FEAT_HOG | PD_FEAT_LBP subset; the dot products run over
+// that family's features only (the other family's weights are not read).
 hipError_t launch_rescore64(const LevelItem* items, const int32_t* frame_first_item, int n_frames,
                             const int32_t* near_count, const int4* near_key, const float* weights,
-                            const float* bias, int n_models, float clip, float eps, const double* thresholds,
-                            int32_t* counters, float* cand_score, int4* cand_key, double* cand_s64,
-                            const double2* orient, hipStream_t s);
-hipError_t launch_compact_table(const LevelItem* items, const Tile* tiles, int n_tiles, int n_models,
-                                const double* thresholds, int32_t* counters, float* cand_score,
-                                int4* cand_key, hipStream_t s);
+                            const float* bias, int n_models, int features, float clip, float eps,
+                            const double* thresholds, int32_t* counters, float* cand_score, int4* cand_key,
+                            double* cand_s64, const double2* orient, hipStream_t s);
+// Per frame whose candidate list is longer than PD_MAX_CANDIDATES: the
+// PD_MAX_CANDIDATES entries with the smallest NMS sort keys (score
+// descending, then level, i, j ascending) copied to the frame's slot of the
+// sel_* arrays ([n_frames][PD_MAX_CANDIDATES]).  Other frames are left alone.
+hipError_t launch_cand_select(const NmsGeom* geoms, int n_frames, const int32_t* counters, const float* cand_score,
+                              const int4* cand_key, const double* cand_s64, float* sel_score, int4* sel_key,
+                              double* sel_s64, hipStream_t s);
+// NMS per frame over its candidate list, or over its sel_* slot when the
+// list is longer than PD_MAX_CANDIDATES.
 hipError_t launch_nms_table(const NmsGeom* geoms, int n_frames, const int32_t* counters,
                             const float* cand_score, const int4* cand_key, const double* cand_s64,
+                            const float* sel_score, const int4* sel_key, const double* sel_s64,
                             const int32_t* near_count, pd_box* boxes, int cap, pd_counts* counts, hipStream_t s);
 hipError_t launch_nms_single(const NmsGeom& g, int n, const float* cand_score, const int4* cand_key,
                              pd_box* boxes, int cap, pd_counts* counts, hipStream_t s);

@@ -65,28 +65,29 @@ constexpr int RS_LBP_RUNS = PD_LBP_BINS * PD_WIN_CELLS_Y;  // 8-byte runs: one p
 constexpr int RS_RUNS_PER_T = (RS_LBP_RUNS + 255) / 256;
 
 // Per-model partial dot products of the window's features (LDS) with the
-// weights, M = 1 or 8 models unrolled (models past n_models repeat the last
-// one; their sums are never read).  Thread t takes features t + 256 u; U
-// features per step, so a thread's M * U weight loads are in flight together.
-// Past the last feature x is 0 and the weight index is clamped.
+// weights over features [k_begin, k_end) (the whole vector, or one feature
+// family), M = 1 or 8 models unrolled (models past n_models repeat the last
+// one; their sums are never read).  Thread t takes features k_begin + t +
+// 256 u; U features per step, so a thread's M * U weight loads are in flight
+// together.  Past k_end x is 0 and the weight index is clamped.
 template <int M>
 __device__ __forceinline__ void dot_models(RescoreShared& sm, const float* __restrict__ weights, int n_models,
-                                           int t, int wave, int lane) {
+                                           int k_begin, int k_end, int t, int wave, int lane) {
     constexpr int U = M == 1 ? 16 : 6;
     double part[M];
 #pragma unroll
     for (int m = 0; m < M; ++m) part[m] = 0.0;
-    for (int k0 = t; k0 < PD_FEATURE_DIM; k0 += 256 * U) {
+    for (int k0 = k_begin + t; k0 < k_end; k0 += 256 * U) {
         float w[U][M];
         double x[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int k = k0 + 256 * u;
-            const int kc = min(k, PD_FEATURE_DIM - 1);
+            const int kc = min(k, k_end - 1);
 #pragma unroll
             for (int m = 0; m < M; ++m) w[u][m] = weights[(size_t)min(m, n_models - 1) * PD_FEATURE_DIM + kc];
             const double xv = kc < PD_HOG_DIM ? sm.u.x.hog[kc] : (double)sm.u.x.lbp[kc - PD_HOG_DIM];
-            x[u] = k < PD_FEATURE_DIM ? xv : 0.0;
+            x[u] = k < k_end ? xv : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
@@ -102,24 +103,24 @@ __device__ __forceinline__ void dot_models(RescoreShared& sm, const float* __res
 }
 
 // The same with each thread taking four consecutive features per step
-// (groups g = t + 256 u of 4: one 16-byte weight load per model; 3780 and
-// 11332 are multiples of 4, so a group is all HOG or all LBP).  Needs 16-byte
-// aligned weights.
+// (groups g = g_begin + t + 256 u of 4: one 16-byte weight load per model;
+// 3780 and 11332 are multiples of 4, so a group is all HOG or all LBP).
+// Needs 16-byte aligned weights.
 template <int M>
-__device__ __forceinline__ void dot_models4(RescoreShared& sm, const float4* __restrict__ w4, int n_models, int t,
-                                            int wave, int lane) {
+__device__ __forceinline__ void dot_models4(RescoreShared& sm, const float4* __restrict__ w4, int n_models,
+                                            int g_begin, int g_end, int t, int wave, int lane) {
     constexpr int G = PD_FEATURE_DIM / 4;
     constexpr int U = M == 1 ? 4 : 2;
     double part[M];
 #pragma unroll
     for (int m = 0; m < M; ++m) part[m] = 0.0;
-    for (int g0 = t; g0 < G; g0 += 256 * U) {
+    for (int g0 = g_begin + t; g0 < g_end; g0 += 256 * U) {
         float4 w[U][M];
         double x[U][4];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int g = g0 + 256 * u;
-            const int gc = min(g, G - 1);
+            const int gc = min(g, g_end - 1);
 #pragma unroll
             for (int m = 0; m < M; ++m) w[u][m] = w4[(size_t)min(m, n_models - 1) * G + gc];
             const int k = 4 * gc;
@@ -131,7 +132,7 @@ __device__ __forceinline__ void dot_models4(RescoreShared& sm, const float4* __r
 #pragma unroll
                 for (int j = 0; j < 4; ++j) x[u][j] = (double)((b >> (8 * j)) & 255u);
             }
-            if (g >= G) {
+            if (g >= g_end) {
 #pragma unroll
                 for (int j = 0; j < 4; ++j) x[u][j] = 0.0;
             }
@@ -182,8 +183,9 @@ __global__ void __launch_bounds__(256) rescore64_kernel(const LevelItem* __restr
                                                         const int32_t* __restrict__ near_count,
                                                         const int4* __restrict__ near_key,
                                                         const float* __restrict__ weights,
-                                                        const float* __restrict__ bias, int n_models, double clip,
-                                                        double eps, const double* __restrict__ thresholds,
+                                                        const float* __restrict__ bias, int n_models, int features,
+                                                        double clip, double eps,
+                                                        const double* __restrict__ thresholds,
                                                         int32_t* __restrict__ counters, float* __restrict__ cand_score,
                                                         int4* __restrict__ cand_key, double* __restrict__ cand_s64,
                                                         const double2* __restrict__ orient, bool vec_w) {
@@ -375,14 +377,18 @@ __global__ void __launch_bounds__(256) rescore64_kernel(const LevelItem* __restr
         }
         __syncthreads();
 
-        // dot products over the 11332 features, all lanes, coalesced weights
-        // from the L2, a fixed-order reduction
+        // dot products over the 11332 features (or the one family of an
+        // HOG-only / LBP-only detector), all lanes, coalesced weights from the
+        // L2, a fixed-order reduction
+        const int k_begin = (features & PD_FEAT_HOG) ? 0 : PD_HOG_DIM;
+        const int k_end = (features & PD_FEAT_LBP) ? PD_FEATURE_DIM : PD_HOG_DIM;
         if (vec_w && n_models > 1) {
-            dot_models4<8>(sm, reinterpret_cast<const float4*>(weights), n_models, t, wave, lane);
+            dot_models4<8>(sm, reinterpret_cast<const float4*>(weights), n_models, k_begin / 4, k_end / 4, t, wave,
+                           lane);
         } else if (n_models == 1) {
-            dot_models<1>(sm, weights, 1, t, wave, lane);
+            dot_models<1>(sm, weights, 1, k_begin, k_end, t, wave, lane);
         } else {
-            dot_models<8>(sm, weights, n_models, t, wave, lane);
+            dot_models<8>(sm, weights, n_models, k_begin, k_end, t, wave, lane);
         }
         __syncthreads();
         if (t == 0) {
@@ -397,8 +403,8 @@ __global__ void __launch_bounds__(256) rescore64_kernel(const LevelItem* __restr
             }
             if (best > thresholds[f]) {
                 const int pos = atomicAdd(&counters[f], 1);
-                if (pos < PD_MAX_CANDIDATES) {
-                    const size_t o = (size_t)f * PD_MAX_CANDIDATES + pos;
+                if (pos < it.cand_cap) {  // always: a window is appended once at most
+                    const size_t o = (size_t)it.cand_off + pos;
                     cand_score[o] = (float)best;
                     cand_key[o] = make_int4(level, wi, wj, bm);
                     cand_s64[o] = best;
@@ -418,14 +424,16 @@ hipError_t launch_orient_table(double2* table, hipStream_t s) {
 
 hipError_t launch_rescore64(const LevelItem* items, const int32_t* frame_first_item, int n_frames,
                             const int32_t* near_count, const int4* near_key, const float* weights, const float* bias,
-                            int n_models, float clip, float eps, const double* thresholds, int32_t* counters,
-                            float* cand_score, int4* cand_key, double* cand_s64, const double2* orient,
-                            hipStream_t s) {
+                            int n_models, int features, float clip, float eps, const double* thresholds,
+                            int32_t* counters, float* cand_score, int4* cand_key, double* cand_s64,
+                            const double2* orient, hipStream_t s) {
     if (n_frames <= 0) return hipSuccess;
-    const int grid = min(n_frames * MAX_NEAR, 1024);
+    // persistent workgroups (one per CU fits the LDS) over the dense near list,
+    // whose length is read on the device
+    const int grid = 1024;
     rescore64_kernel<<<grid, 256, 0, s>>>(items, frame_first_item, n_frames, near_count, near_key, weights, bias,
-                                         n_models, (double)clip, (double)eps, thresholds, counters, cand_score,
-                                         cand_key, cand_s64, orient, ((uintptr_t)weights & 15) == 0);
+                                         n_models, features, (double)clip, (double)eps, thresholds, counters,
+                                         cand_score, cand_key, cand_s64, orient, ((uintptr_t)weights & 15) == 0);
     return hipGetLastError();
 }
 

@@ -161,6 +161,9 @@ int pd_video_pop(pd_video* v, pd_box* boxes, int cap, pd_counts* counts, float* 
     if (n > 0) std::memcpy(boxes, s.h_boxes, sizeof(pd_box) * n);
     v->head = (v->head + 1) % v->depth;
     --v->n_busy;
+    if (s.h_counts->overflow || s.h_counts->kept > cap)
+        return fail(PD_E_OVERFLOW, "frame results truncated: %d candidates, %d kept, %d boxes room",
+                    s.h_counts->candidates, s.h_counts->kept, cap);
     return PD_OK;
 }
 

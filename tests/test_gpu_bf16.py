@@ -153,9 +153,8 @@ def test_detect_bf16_batch_deterministic():
     wts = pd_synth.svm_weights(8)
     bias = np.zeros(8, np.float32)
     prm = pd.params(precision=pd.PREC_BF16)
-    # thresholds near the 95th percentile of the 8-model max score keep the
-    # candidate lists below capacity (an overflowing list is truncated in
-    # atomic order and flagged)
+    # thresholds near the 95th percentile of the 8-model max score: every
+    # candidate list within what NMS takes whole
     thr = to_dev(np.array([6.3, 6.3, 6.3]))
     dets = []
     for _ in range(2):
@@ -187,7 +186,7 @@ def test_rescore_every_window(w, h, m):
     levels = O.frame_scores(img, wts, bias.astype(np.float64), clip=CLIP32, eps=EPS32)
     allmax = np.sort(np.concatenate([O.max_over_models(lv["scores"])[0].ravel() for lv in levels]))
     n_win = allmax.size
-    assert 0 < n_win <= 1024  # every window fits the per-frame rescore cap
+    assert n_win > 0
     k = n_win // 3
     thr = 0.5 * (allmax[n_win - k - 1] + allmax[n_win - k])
     prm = pd.params(precision=pd.PREC_BF16, margin=1.0e6)

@@ -49,8 +49,7 @@ def test_tuning_fields_keep_results(prec, m):
     frames = _frames(5000)
     wts = to_dev(pd_synth.svm_weights(m))
     bias = to_dev(np.zeros(m, np.float32))
-    # thresholds that keep every candidate list below capacity (an overflowing
-    # list is truncated in atomic order)
+    # thresholds that keep every frame's candidates within what NMS takes whole
     thr = to_dev(np.full(3, {1: 2.5, 2: 4.0, 4: 8.0}[m]))
     ref = _run(frames, wts, bias, pd.params(precision=prec), thr)
     assert all(c["candidates"] > 0 and c["overflow"] == 0 for c in ref[1])

@@ -341,7 +341,7 @@ def test_detect_pitched_misaligned_frames_equal_contiguous(prec):
     sizes = [(1242, 375), (640, 480), (333, 257)]
     frames = pd_synth.frame_batch(sizes, 2100)
     wts, bias = pd_synth.svm_weights(1), pd_synth.svm_bias(1)
-    thr = [3.0, 3.0, 3.0]  # lists within capacity (an overflowing list holds whichever windows came first)
+    thr = [3.0, 3.0, 3.0]  # every frame's candidates within what NMS takes whole
     prm = pd.params(precision=prec, margin=0.05) if prec == pd.PREC_BF16 else pd.params()
     views, bufs = [], []
     for k, img in enumerate(frames):

@@ -412,6 +412,30 @@ def test_nms_hand_cases(case):
     assert [c["id"] for c in O.nms(cands)] == kept
 
 
+def test_select_top_hand_case():
+    c = [{"score": 1.0, "level": 0, "i": 5, "j": 0}, {"score": 2.0, "level": 1, "i": 0, "j": 0},
+         {"score": 1.0, "level": 0, "i": 2, "j": 9}, {"score": 1.0, "level": 1, "i": 0, "j": 0},
+         {"score": 0.5, "level": 0, "i": 0, "j": 0}]
+    got = [(d["score"], d["level"], d["i"], d["j"]) for d in O.select_top(c, 3)]
+    assert got == [(2.0, 1, 0, 0), (1.0, 0, 2, 9), (1.0, 0, 5, 0)]
+    assert O.select_top(c, 10) == O.select_top(c, 5) and len(O.select_top(c, 0)) == 0
+
+
+def test_select_top_by_rank_counting():
+    """A candidate is selected iff fewer than `limit` others precede it in the
+    strict NMS order (counted pairwise, no sort)."""
+    rng = np.random.default_rng(11)
+    for n, limit in ((30, 7), (64, 64), (50, 1)):
+        c = [{"score": float(rng.integers(0, 5)), "level": int(rng.integers(0, 3)), "i": int(q), "j": int(rng.integers(0, 4))}
+             for q in range(n)]
+
+        def before(a, b):
+            return a["score"] > b["score"] or (a["score"] == b["score"] and
+                                               (a["level"], a["i"], a["j"]) < (b["level"], b["i"], b["j"]))
+        exp = {id(d) for d in c if sum(before(e, d) for e in c) < limit}
+        assert {id(d) for d in O.select_top(c, limit)} == exp
+
+
 def test_max_over_models_ties_lowest():
     s = np.array([[[1.0, 2.0]], [[1.0, 3.0]]])
     v, m = O.max_over_models(s)
