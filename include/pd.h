@@ -350,6 +350,28 @@ int pd_detect(const pd_frame* frames, int n_frames, const float* weights,
               pd_box* boxes, int cap, pd_counts* counts, void* stream);
 
 /*
+ * pd_detect_noalloc -- pd_detect for callers that cannot allocate memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, results and errors as pd_detect, but no
+ * workspace: it uses a static device array of PD_NOALLOC_SCRATCH_BYTES that
+ * the library holds on every GPU it runs on until the process ends, and it
+ * passes its tables to the device as kernel arguments, so it calls no
+ * hipMalloc, hipFree, hipHostMalloc or other device or pinned allocator.
+ * Every call on a GPU shares that GPU's array: calls that overlap on one GPU
+ * (on different streams, or from different threads) race.  Consecutive calls
+ * on one stream are safe: each clears its counters before use.
+ * Errors: those of pd_detect; PD_E_WORKSPACE, before any GPU work, when the
+ * batch needs more than PD_NOALLOC_SCRATCH_BYTES of workspace
+ * (pd_detect_workspace_bytes: a 1242x375 frame needs about 10 MiB, a
+ * 1920x1080 frame about 50 MiB).
+ */
+#define PD_NOALLOC_SCRATCH_BYTES (64ll << 20)
+int pd_detect_noalloc(const pd_frame* frames, int n_frames, const float* weights,
+                      const float* bias, int n_models, const pd_params* params,
+                      const double* thresholds, pd_box* boxes, int cap,
+                      pd_counts* counts, void* stream);
+
+/*
  * pd_graph_create -- the kernel sequence of pd_detect on exactly these
  * arguments, captured once into a HIP graph for replay by pd_graph_launch
  * (HIP graph capture in place of per-call launches; the work is that of

@@ -29,6 +29,7 @@ FEAT_HOG, FEAT_LBP = 1, 2
 PREC_F32, PREC_BF16 = 0, 1
 MAX_MODELS_BF16 = 8
 PRUNER_CHANNELS, PRUNER_PARAMS = 68, 33505
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 E_ARG, E_SIZE, E_WORKSPACE, E_HIP, E_OVERFLOW = -1, -2, -3, -4, -5
 
@@ -110,6 +111,9 @@ _SIGS = {
     "pd_detect": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                                  ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                  ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
+    "pd_detect_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
     "pd_graph_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_int64, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
@@ -472,6 +476,18 @@ def workspace_bytes(sizes, n_models: int = 1, prm: Params = None) -> int:
     if v < 0:
         _check(int(v))
     return int(v)
+
+
+def detect_noalloc(frames, weights, bias, prm: Params, thresholds, boxes, counts, cap: int) -> None:
+    """pd_detect_noalloc: the pipeline on the library's static scratch array
+    (no workspace).  frames: uint8 CUDA tensors; boxes / counts: uint8 CUDA
+    tensors of at least n * cap * 48 and n * 16 bytes."""
+    arr = _frames_array(frames)
+    weights = weights.contiguous()
+    _check(lib().pd_detect_noalloc(arr, len(frames), ctypes.c_void_p(weights.data_ptr()),
+                                   ctypes.c_void_p(bias.data_ptr()), int(weights.shape[0]), ctypes.byref(prm),
+                                   ctypes.c_void_p(thresholds.data_ptr()), ctypes.c_void_p(boxes.data_ptr()), cap,
+                                   ctypes.c_void_p(counts.data_ptr()), _stream()))
 
 
 @dataclass

@@ -1471,3 +1471,40 @@ int pd_nms(const float* cand_score, const int32_t* cand_key, int n, const int32_
 }
 
 }  // extern "C"
+
+// pd_detect on a workspace the caller names, with the tables' upload left to
+// `upload` (given the host tables and the byte ranges of them in use, as
+// (offset, size) pairs relative to the workspace start): for entry points
+// that must not touch the staging ring's pinned memory.  No stage events.
+#include "detect_workspace.h"
+
+int pd::detect_on_workspace(const pd_frame* frames, int n_frames, const float* weights, const float* bias,
+                            int n_models, const pd_params* params, const double* thresholds, void* workspace,
+                            int64_t workspace_bytes, pd_box* boxes, int cap, pd_counts* counts, hipStream_t s,
+                            TableUpload upload) {
+    DetectLayout L;
+    if (int rc = validate_detect(frames, n_frames, weights, bias, n_models, params, thresholds, workspace,
+                                 workspace_bytes, boxes, cap, counts, L))
+        return rc;
+    std::vector<uint8_t> host((size_t)L.table_bytes);
+    DetectRun R;
+    uint8_t* ws = static_cast<uint8_t*>(workspace);
+    fill_tables(frames, n_frames, n_models, tuning_of(params), L, ws, ws, host.data(), R);
+    // only the entries in use: the items, each tile list's used prefix (FP32
+    // half-height score tiles follow the others), the NMS geometry and the
+    // per-frame item index
+    const int64_t tsz = (int64_t)sizeof(Tile), t0 = L.off_tiles;
+    const int64_t ranges[7][2] = {
+        {L.off_items, (int64_t)L.n_items * (int64_t)sizeof(LevelItem)},
+        {t0, R.nrs * tsz},
+        {t0 + L.n_rs * tsz, R.nft * tsz},
+        {t0 + (L.n_rs + L.n_ft) * tsz, (int64_t)(R.nsc + R.nsc_half) * tsz},
+        {t0 + (L.n_rs + L.n_ft + L.n_sc) * tsz, R.ncp * tsz},
+        {t0 + (L.n_rs + L.n_ft + L.n_sc + L.n_cp) * tsz, R.npr * tsz},
+        {L.off_geoms, L.table_bytes - L.off_geoms},
+    };
+    if (int rc = upload(host.data(), ws, &ranges[0][0], 7, s)) return rc;
+    StageMarks marks(false);
+    return enqueue_detect(R, L, tuning_of(params), weights, bias, n_models, params, thresholds, n_frames, boxes, cap,
+                          counts, marks, s);
+}

@@ -191,3 +191,18 @@ def test_detect_workspace_and_errors():
     assert detect() == pd.E_SIZE          # wider than PD_MAX_DIM
     arr[0].w, arr[0].h, arr[0].pitch = 100, 100, 99
     assert detect() == pd.E_ARG           # pitch below the width
+
+
+def test_noalloc_rejects_batches_beyond_its_scratch_before_any_gpu_work():
+    """pd_detect_noalloc checks the batch's workspace against the static
+    scratch (PD_NOALLOC_SCRATCH_BYTES) on the host, before any HIP call."""
+    L = pd.lib()
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced
+    frames = (pd.Frame * 2)()
+    for f in frames:
+        f.data, f.w, f.h, f.pitch = 0x1000, 1920, 1080, 1920
+    assert pd.workspace_bytes([(1920, 1080)] * 2) > pd.NOALLOC_SCRATCH_BYTES
+    rc = L.pd_detect_noalloc(frames, 2, fake, fake, 1, ctypes.byref(pd.params()), fake, fake, 16, fake, None)
+    assert rc == pd.E_WORKSPACE and "static scratch" in L.pd_last_error().decode()
+    assert L.pd_detect_noalloc(frames, 0, fake, fake, 1, ctypes.byref(pd.params()), fake, fake, 16, fake,
+                               None) == pd.E_ARG
