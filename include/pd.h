@@ -44,6 +44,8 @@ extern "C" {
                                  highest-scoring were kept, the true counts
                                  reported); returned only by calls that wait
                                  for their results (pd_video_pop)            */
+#define PD_E_IO         (-6)  /* a file could not be read or written, or is
+                                 not of the expected kind                    */
 
 /* ---- fixed geometry ---------------------------------------------------- */
 #define PD_CELL          8
@@ -404,6 +406,76 @@ int pd_graph_launch(pd_graph* graph, void* stream);
    sure no launch is still running. */
 int pd_graph_destroy(pd_graph* graph);
 
+/* ---- detection context: tuning table and graph cache ---------------------- */
+/*
+ * A context keeps, across calls:
+ *   - a tuning table: the tile and grid shapes chosen for a batch shape (the
+ *     sequence of frame sizes, n_models, and the params that shape the work:
+ *     scale, max_levels, features, precision, pruning on/off), filled by
+ *     pd_ctx_autotune or pd_ctx_set_tuning, saved and loaded as text;
+ *   - a graph cache: pd_ctx_detect captures a call's kernel sequence once
+ *     (as pd_graph_create) and replays it for every later call with the same
+ *     arguments (same buffers, sizes and params; buffer contents may change),
+ *     so repeated calls skip the host's table build and upload.  At most 8
+ *     graphs are kept; the least recently used is released once its last
+ *     launch has finished.
+ * A context is used by one thread at a time.  pd_ctx_create and
+ * pd_ctx_detect allocate host memory, and the first pd_ctx_detect on a new
+ * set of arguments allocates the graph's table memory and waits for its
+ * upload (as pd_graph_create); later calls on those arguments allocate
+ * nothing.
+ */
+typedef struct pd_ctx pd_ctx;
+int pd_ctx_create(pd_ctx** out);
+/* Waits for the cached graphs' last launches, then releases everything. */
+int pd_ctx_destroy(pd_ctx* ctx);
+/*
+ * pd_ctx_detect -- pd_detect (Section 4.1 steps 2-5) through the context:
+ * when params leave every tuning field at 0 and the table has an entry for
+ * this batch shape, that entry's fields are used; the call is then replayed
+ * from the graph cache (captured first if these arguments are new).  With
+ * pd_profile_enable on, it runs as an eager pd_detect (stage events).
+ * Arguments, results and errors: those of pd_detect and pd_graph_create.
+ */
+int pd_ctx_detect(pd_ctx* ctx, const pd_frame* frames, int n_frames, const float* weights,
+                  const float* bias, int n_models, const pd_params* params,
+                  const double* thresholds, void* workspace, int64_t workspace_bytes,
+                  pd_box* boxes, int cap, pd_counts* counts, void* stream);
+/*
+ * pd_ctx_autotune -- pd_autotune, remembered: when the table already holds
+ * this batch shape, *best is params with its fields (and *best_ms the time
+ * stored with them) and nothing runs; otherwise pd_autotune runs and its
+ * choice is stored.  Arguments and errors: those of pd_autotune.
+ */
+int pd_ctx_autotune(pd_ctx* ctx, const pd_frame* frames, int n_frames, const float* weights,
+                    const float* bias, int n_models, const pd_params* params,
+                    const double* thresholds, void* workspace, int64_t workspace_bytes,
+                    pd_box* boxes, int cap, pd_counts* counts, int iters, pd_params* best,
+                    float* best_ms, void* stream);
+/*
+ * pd_ctx_tuning -- host only: *out = params with the table's tuning fields
+ * for this batch shape.  Returns 1 if the table had an entry, 0 if not (then
+ * *out = params), or a negative PD_E_* code (frames, params or n_models
+ * invalid, as for pd_detect_workspace_bytes).  Only w and h of the frames are
+ * read.
+ */
+int pd_ctx_tuning(const pd_ctx* ctx, const pd_frame* frames, int n_frames, const pd_params* params,
+                  int n_models, pd_params* out);
+/* pd_ctx_set_tuning -- host only: stores params' tuning fields (and `ms`)
+   as the entry of this batch shape.  Errors as pd_ctx_tuning. */
+int pd_ctx_set_tuning(pd_ctx* ctx, const pd_frame* frames, int n_frames, const pd_params* params,
+                      int n_models, float ms);
+/*
+ * pd_ctx_save / pd_ctx_load -- the tuning table as a text file: a first
+ * line "pd-tuning 1", then one line per entry, "<shape>\t<feat_rows>
+ * <score_rows> <grid> <ms>".  Loading adds the file's entries (replacing
+ * those with the same shape) only if the whole file is valid.
+ * Errors: PD_E_IO when the file cannot be opened, read or written, or a line
+ * is malformed or out of range; PD_E_ARG on NULL arguments.
+ */
+int pd_ctx_save(const pd_ctx* ctx, const char* path);
+int pd_ctx_load(pd_ctx* ctx, const char* path);
+
 /*
  * pd_graph_stage_ms -- for a graph created while pd_profile_enable was on
  * (the capture then holds, before each stage and after the last one, a
@@ -571,6 +643,25 @@ int pd_adam_step(float* params, const float* grad, float* m, float* v, int n, in
  */
 int pd_window_labels(const float* scores, int win_x, int win_y, int cells_x, int cells_y,
                      const double* threshold, float* labels, float* mask, void* stream);
+
+/*
+ * pd_pruner_save / pd_pruner_load -- training checkpoints of the pruner: its
+ * parameters and Adam's first and second moments (device float
+ * [PD_PRUNER_PARAMS] each), the number of Adam steps taken and the seed of
+ * the training order, in a binary file `path` (host string): magic
+ * "PDPRUNE1", version, parameter count, step, seed, the three vectors as
+ * little-endian float32, an FNV-1a 64-bit checksum.  Save writes a sibling
+ * file and renames it over `path`.  Both copy through host memory on
+ * `stream` and synchronise it before returning.  Load may take NULL moment
+ * pointers (inference only).
+ * Errors: PD_E_ARG on NULL arguments or a negative step; PD_E_IO when the
+ * file cannot be written or read, or is not a valid checkpoint (size, magic,
+ * version, checksum); PD_E_HIP from the copies.
+ */
+int pd_pruner_save(const char* path, const float* params, const float* adam_m, const float* adam_v,
+                   int64_t step, uint64_t seed, void* stream);
+int pd_pruner_load(const char* path, float* params, float* adam_m, float* adam_v, int64_t* step,
+                   uint64_t* seed, void* stream);
 
 /*
  * pd_pruner_logits_bf16 -- the inference form of the pruner on one level

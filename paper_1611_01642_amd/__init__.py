@@ -31,7 +31,7 @@ MAX_MODELS_BF16 = 8
 PRUNER_CHANNELS, PRUNER_PARAMS = 68, 33505
 NOALLOC_SCRATCH_BYTES = 64 << 20
 
-E_ARG, E_SIZE, E_WORKSPACE, E_HIP, E_OVERFLOW = -1, -2, -3, -4, -5
+E_ARG, E_SIZE, E_WORKSPACE, E_HIP, E_OVERFLOW, E_IO = -1, -2, -3, -4, -5, -6
 
 
 class PdError(RuntimeError):
@@ -119,6 +119,27 @@ _SIGS = {
                                        ctypes.c_int64, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                                        ctypes.c_void_p, ctypes.c_void_p]),
     "pd_graph_launch": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "pd_ctx_create": (ctypes.c_int, [ctypes.c_void_p]),
+    "pd_ctx_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "pd_ctx_detect": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int,
+                                     ctypes.c_void_p, ctypes.c_void_p]),
+    "pd_ctx_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int,
+                                       ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_void_p]),
+    "pd_ctx_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                     ctypes.c_int, ctypes.c_void_p]),
+    "pd_ctx_set_tuning": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                         ctypes.c_int, ctypes.c_float]),
+    "pd_ctx_save": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p]),
+    "pd_ctx_load": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p]),
+    "pd_pruner_save": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_int64, ctypes.c_uint64, ctypes.c_void_p]),
+    "pd_pruner_load": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "pd_video_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p]),
     "pd_video_push": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_double]),
@@ -429,6 +450,24 @@ def adam_step(params_, grad, m, v, step: int, lr: float = 1e-3, beta1: float = 0
                               int(step), lr, beta1, beta2, eps, _stream()))
 
 
+def pruner_save(path: str, params_, m, v, step: int, seed: int) -> None:
+    """Checkpoint (pd_pruner_save): device float32 [PRUNER_PARAMS] parameters
+    and Adam moments, the Adam step count and the training-order seed."""
+    _check(lib().pd_pruner_save(os.fsencode(path), ctypes.c_void_p(params_.data_ptr()), ctypes.c_void_p(m.data_ptr()),
+                                ctypes.c_void_p(v.data_ptr()), int(step), int(seed), _stream()))
+
+
+def pruner_load(path: str, params_, m=None, v=None):
+    """Fills the device tensors from a checkpoint (pd_pruner_load); returns
+    (step, seed)."""
+    step, seed = ctypes.c_int64(0), ctypes.c_uint64(0)
+    _check(lib().pd_pruner_load(os.fsencode(path), ctypes.c_void_p(params_.data_ptr()),
+                                ctypes.c_void_p(m.data_ptr() if m is not None else 0),
+                                ctypes.c_void_p(v.data_ptr() if v is not None else 0), ctypes.byref(step),
+                                ctypes.byref(seed), _stream()))
+    return int(step.value), int(seed.value)
+
+
 def window_labels(scores, cells_x: int, cells_y: int, threshold):
     """(labels, mask) [Hc][Wc] float32 of one level from its window scores
     [Hc-15][Wc-7] (max over models) and a device float64 threshold [1]."""
@@ -490,14 +529,62 @@ def detect_noalloc(frames, weights, bias, prm: Params, thresholds, boxes, counts
                                    ctypes.c_void_p(counts.data_ptr()), _stream()))
 
 
+class Context:
+    """A pd_ctx: the tuning table (per batch shape) and the graph cache of
+    pd_ctx_detect.  Give it to Detectors (Detector(..., ctx=...)) so their
+    run() and autotune() go through it."""
+
+    def __init__(self):
+        self.handle = ctypes.c_void_p(0)
+        _check(lib().pd_ctx_create(ctypes.byref(self.handle)))
+
+    def tuning(self, sizes, n_models: int, prm: Params):
+        """params with the table's tuning fields for frames of these (w, h)
+        sizes, or None when the table has no entry."""
+        arr = (Frame * len(sizes))()
+        for f, (w, h) in enumerate(sizes):
+            arr[f].w, arr[f].h = w, h
+        out = Params()
+        rc = lib().pd_ctx_tuning(self.handle, arr, len(sizes), ctypes.byref(prm), n_models, ctypes.byref(out))
+        if rc < 0:
+            _check(rc)
+        return out if rc == 1 else None
+
+    def set_tuning(self, sizes, n_models: int, prm: Params, ms: float = 0.0) -> None:
+        arr = (Frame * len(sizes))()
+        for f, (w, h) in enumerate(sizes):
+            arr[f].w, arr[f].h = w, h
+        _check(lib().pd_ctx_set_tuning(self.handle, arr, len(sizes), ctypes.byref(prm), n_models, float(ms)))
+
+    def save(self, path: str) -> None:
+        _check(lib().pd_ctx_save(self.handle, os.fsencode(path)))
+
+    def load(self, path: str) -> None:
+        _check(lib().pd_ctx_load(self.handle, os.fsencode(path)))
+
+    def close(self) -> None:
+        if self.handle:
+            h, self.handle = self.handle, ctypes.c_void_p(0)
+            _check(lib().pd_ctx_destroy(h))
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 @dataclass
 class Detector:
-    """Holds the device buffers of pd_detect for one batch shape."""
+    """Holds the device buffers of pd_detect for one batch shape; with a
+    Context, run() and autotune() go through it (pd_ctx_detect,
+    pd_ctx_autotune)."""
     frames: list
     weights: object
     bias: object
     prm: Params
     cap: int = 1024
+    ctx: Context = None
 
     def __post_init__(self):
         torch = _torch()
@@ -516,7 +603,11 @@ class Detector:
 
     def run(self, thresholds) -> None:
         """Enqueue the whole pipeline; thresholds: float64 CUDA tensor [n_frames]."""
-        _check(lib().pd_detect(*self._args(thresholds), _stream()))
+        if self.ctx is not None:
+            self._thr_ctx = thresholds  # a cached graph keeps reading this buffer
+            _check(lib().pd_ctx_detect(self.ctx.handle, *self._args(thresholds), _stream()))
+        else:
+            _check(lib().pd_detect(*self._args(thresholds), _stream()))
 
     def _args(self, thresholds):
         return (self._frames, len(self.frames), ctypes.c_void_p(self.weights.data_ptr()),
@@ -581,7 +672,12 @@ class Detector:
         detector keeps the result.  Returns (tuning dict, ms per call)."""
         best = Params()
         ms = ctypes.c_float(0.0)
-        _check(lib().pd_autotune(*self._args(thresholds), iters, ctypes.byref(best), ctypes.byref(ms), _stream()))
+        if self.ctx is not None:
+            _check(lib().pd_ctx_autotune(self.ctx.handle, *self._args(thresholds), iters, ctypes.byref(best),
+                                         ctypes.byref(ms), _stream()))
+        else:
+            _check(lib().pd_autotune(*self._args(thresholds), iters, ctypes.byref(best), ctypes.byref(ms),
+                                     _stream()))
         self.prm = best
         return best.tuning(), float(ms.value)
 

@@ -789,6 +789,8 @@ int enqueue_detect(const DetectRun& R, const DetectLayout& L, const Tuning& tu, 
 
 }  // namespace
 
+bool pd::profiling_on() { return g_prof.on; }
+
 extern "C" {
 
 int pd_profile_enable(int on) {
@@ -843,6 +845,8 @@ const char* pd_strerror(int code) {
         case PD_E_SIZE: return "invalid size";
         case PD_E_WORKSPACE: return "workspace missing or too small";
         case PD_E_HIP: return "HIP error";
+        case PD_E_OVERFLOW: return "results truncated";
+        case PD_E_IO: return "file error";
         default: return "unknown error";
     }
 }

@@ -191,6 +191,8 @@ hipError_t launch_score_table(const LevelItem* items, const Tile* tiles, int n_t
 // returns `code` (fail) or maps a HIP status (hip_status: PD_OK or PD_E_HIP).
 int fail(int code, const char* fmt, ...);
 int hip_status(hipError_t e, const char* what);
+// Whether pd_profile_enable is on for the calling thread.
+bool profiling_on();
 
 hipError_t launch_lbp_blocks(const uint8_t* cells, int n, int hc, int wc, uint16_t* blocks, hipStream_t s);
 hipError_t launch_fold_lbp_weights(const float* wb, int n_models, float* w, hipStream_t s);

@@ -9,7 +9,9 @@ provides device memory and a few scalar reductions for bookkeeping.
   (max over models) against the detection threshold (pd_window_labels);
 * training: class-weighted BCE (positive weight = negatives / positives over
   the training set), Adam with FP32 master weights, a fixed number of frames
-  per step, steps in a seeded random order per epoch;
+  per step, steps in a seeded random order per epoch (epoch e's order depends
+  on (seed, e) only); a checkpoint (parameters, Adam moments, step, seed) can
+  be written after every epoch and training resumed from it bitwise;
 * calibration: the smallest per-frame K at which the pruned detector's
   post-NMS boxes recall at least the target fraction of the plain detector's
   (one-to-one matching at IoU >= 0.5, greedy in the plain NMS order) over a
@@ -20,7 +22,7 @@ from __future__ import annotations
 import numpy as np
 
 from . import (Detector, PrunerBatch, adam_step, build_pyramid, features_cellmap, params as make_params,
-               score_windows, window_labels, PRUNER_PARAMS)
+               pruner_load, pruner_save, score_windows, window_labels, PRUNER_PARAMS)
 
 
 def _torch():
@@ -49,9 +51,14 @@ def training_set(frames, weights, bias, threshold: float, prm=None):
 
 
 def train(data, init_params, epochs: int = 4, frames_per_step: int = 8, lr: float = 1e-3, seed: int = 0,
-          log=None):
-    """Trains from `init_params` (device float32 [PRUNER_PARAMS]); returns
-    (params, per-epoch mean loss list, positive weight)."""
+          log=None, checkpoint: str = None, resume: str = None):
+    """Trains from `init_params` (device float32 [PRUNER_PARAMS]) for
+    `epochs` epochs; returns (params, per-epoch mean loss list, positive
+    weight).  checkpoint: a file written (pd_pruner_save) after every epoch.
+    resume: a checkpoint of this training (same data, steps per epoch and
+    learning rate) to continue from: its parameters, moments, step and seed
+    replace init_params and `seed`, and only the epochs after it run (the
+    returned losses are theirs)."""
     torch = _torch()
     dev = init_params.device
     n_pos = sum(float(lab.sum()) for frame in data for _, lab, _ in frame)
@@ -61,6 +68,9 @@ def train(data, init_params, epochs: int = 4, frames_per_step: int = 8, lr: floa
     assert p.numel() == PRUNER_PARAMS
     m = torch.zeros_like(p)
     v = torch.zeros_like(p)
+    t = 0
+    if resume is not None:
+        t, seed = pruner_load(resume, p, m, v)
     steps = [data[i:i + frames_per_step] for i in range(0, len(data), frames_per_step)]
     batches, ws = [], None
     for group in steps:
@@ -68,17 +78,20 @@ def train(data, init_params, epochs: int = 4, frames_per_step: int = 8, lr: floa
         b = PrunerBatch([c for c, _, _ in maps], [l for _, l, _ in maps], [k for _, _, k in maps], workspace=ws)
         ws = b.workspace if ws is None or b.workspace.numel() > ws.numel() else ws
         batches.append(b)
-    rng = np.random.default_rng(seed)
-    history, t = [], 0
-    for ep in range(epochs):
+    if t % len(batches):
+        raise ValueError(f"checkpoint step {t} is not a whole number of {len(batches)}-step epochs")
+    history = []
+    for ep in range(t // len(batches), epochs):
         loss = torch.zeros((), dtype=torch.float64, device=dev)
-        for k in rng.permutation(len(batches)):
+        for k in np.random.default_rng([seed, ep]).permutation(len(batches)):
             b = batches[k]
             b.gradient(p, pos_weight)
             t += 1
             adam_step(p, b.grad, m, v, t, lr=lr)
             loss += b.stats[0]
         history.append(float(loss) / len(batches))
+        if checkpoint is not None:
+            pruner_save(checkpoint, p, m, v, t, seed)
         if log:
             log(f"epoch {ep}: mean loss {history[-1]:.4f}")
     return p, history, pos_weight

@@ -206,3 +206,56 @@ def test_noalloc_rejects_batches_beyond_its_scratch_before_any_gpu_work():
     assert rc == pd.E_WORKSPACE and "static scratch" in L.pd_last_error().decode()
     assert L.pd_detect_noalloc(frames, 0, fake, fake, 1, ctypes.byref(pd.params()), fake, fake, 16, fake,
                                None) == pd.E_ARG
+
+
+def test_pruner_load_rejects_bad_files_before_any_gpu_work(tmp_path):
+    """pd_pruner_load validates size, magic and checksum on the host before
+    any copy: a missing, truncated or corrupted file is PD_E_IO."""
+    L = pd.lib()
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced
+    step, seed = ctypes.c_int64(0), ctypes.c_uint64(0)
+
+    def load(path):
+        return L.pd_pruner_load(os.fsencode(str(path)), fake, fake, fake, ctypes.byref(step), ctypes.byref(seed),
+                                None)
+    assert load(tmp_path / "missing") == pd.E_IO
+    n = 32 + 3 * 4 * pd.PRUNER_PARAMS + 8
+    good_size = bytearray(b"PDPRUNE1") + bytearray(n - 8)
+    (tmp_path / "short").write_bytes(bytes(good_size[:-1]))
+    assert load(tmp_path / "short") == pd.E_IO and "size" in L.pd_last_error().decode()
+    bad = bytearray(good_size)
+    bad[0:8] = b"NOTPRUNE"
+    (tmp_path / "magic").write_bytes(bytes(bad))
+    assert load(tmp_path / "magic") == pd.E_IO and "magic" in L.pd_last_error().decode()
+    ok = bytearray(good_size)
+    ok[8:12] = (1).to_bytes(4, "little")
+    ok[12:16] = pd.PRUNER_PARAMS.to_bytes(4, "little")
+    (tmp_path / "sum").write_bytes(bytes(ok))  # checksum left at zero
+    assert load(tmp_path / "sum") == pd.E_IO and "checksum" in L.pd_last_error().decode()
+    assert L.pd_pruner_load(None, fake, fake, fake, ctypes.byref(step), ctypes.byref(seed), None) == pd.E_ARG
+
+
+def test_tuning_table_round_trip(tmp_path):
+    ctx = pd.Context()
+    sizes = [(1242, 375)] * 4 + [(640, 480)]
+    assert ctx.tuning(sizes, 1, pd.params()) is None
+    ctx.set_tuning(sizes, 1, pd.params(tune_feat_rows=12, tune_score_rows=4, tune_grid=512), 3.25)
+    ctx.set_tuning(sizes, 8, pd.params(precision=pd.PREC_BF16, tune_feat_rows=10), 7.0)
+    got = ctx.tuning(sizes, 1, pd.params())
+    assert got.tuning() == {"tune_feat_rows": 12, "tune_score_rows": 4, "tune_grid": 512}
+    assert ctx.tuning(sizes[:4], 1, pd.params()) is None            # another batch shape
+    assert ctx.tuning(sizes, 1, pd.params(features=pd.FEAT_HOG)) is None
+    path = str(tmp_path / "tuning.txt")
+    ctx.save(path)
+    other = pd.Context()
+    other.load(path)
+    assert other.tuning(sizes, 1, pd.params()).tuning() == got.tuning()
+    assert other.tuning(sizes, 8, pd.params(precision=pd.PREC_BF16)).tune_feat_rows == 10
+    text = open(path).read().splitlines()
+    assert text[0] == "pd-tuning 1" and len(text) == 3
+    (tmp_path / "bad.txt").write_text("pd-tuning 1\nshape\t99 4 0 1.0\n")
+    with pytest.raises(pd.PdError) as e:
+        other.load(str(tmp_path / "bad.txt"))
+    assert e.value.code == pd.E_IO
+    with pytest.raises(pd.PdError):
+        other.tuning([(0, 10)], 1, pd.params())
