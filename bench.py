@@ -317,35 +317,59 @@ def streaming_leg(pd, torch, host, wts, bias, thr_value, prm, n_free=300, n_pace
 SWEEP_SIZES = [(320, 240), (640, 480), (1242, 375), (1280, 720), (1920, 1080), (2560, 1440), (3840, 2160)]
 
 
-def sweep_leg(pd, torch, dev, wts, bias, reps=20):
+def sweep_leg(pd, torch, dev, wts, bias, reps=20, budget_ms=150.0):
     """px/ns per algorithm against image size, one image per call (the
-    paper's per-algorithm measurement): LBP, HOG, both in one pass, and SVM
-    scoring of the image's windows; HIP events around `reps` back-to-back
-    calls, so small images include the launch cost."""
+    paper's per-algorithm measurement, Section 5.3): this library's kernels
+    (LBP, HOG, both in one pass, SVM scoring of the image's windows) beside
+    the paper's own mappings on the same GPU -- LBP Naive (LBP map, then a
+    thread per cell) and Scalable (LBP map, then global atomics, Algorithm 2),
+    HOG Global (gradients through global memory, a thread per block), SVM
+    Naive (a thread per window) and warp-level (a wave per window, Algorithm
+    6).  HIP events around back-to-back calls (as many as fit `budget_ms`, at
+    most `reps`), so small images include the launch cost."""
     import pd_synth
     s = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
     def timed(fn):
-        for _ in range(3):
-            fn()
+        fn()
         e0.record(s)
-        for _ in range(reps):
+        fn()
+        e1.record(s)
+        torch.cuda.synchronize()
+        n = max(1, min(reps, int(budget_ms / max(e0.elapsed_time(e1), 1e-3))))
+        e0.record(s)
+        for _ in range(n):
             fn()
         e1.record(s)
         torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / reps
+        return e0.elapsed_time(e1) / n
 
     out = {}
     for w, h in SWEEP_SIZES:
         img = torch.from_numpy(pd_synth.frame(w, h, 3000 + w)).to(dev)
+        grad = torch.empty(2 * w * h, dtype=torch.float32, device=dev)
         ms = {"lbp": timed(lambda: pd.features(img, None, hog=False, lbp=True)),
               "hog": timed(lambda: pd.features(img, None, hog=True, lbp=False)),
-              "hog_lbp": timed(lambda: pd.features(img))}
+              "hog_lbp": timed(lambda: pd.features(img)),
+              "paper_lbp_naive": timed(lambda: pd.lbp_naive(pd.lbp_codes(img))),
+              "paper_lbp_scalable": timed(lambda: pd.lbp_scatter(pd.lbp_codes(img))),
+              "paper_hog_global": timed(lambda: pd.hog_global(img, None, grad))}
         blk, cel = pd.features(img)
         ms["svm"] = timed(lambda: pd.score_windows(blk, cel, wts, bias))
-        out[f"{w}x{h}"] = {k: round(w * h / (v * 1e6), 3) for k, v in ms.items()}
-    return {"unit": "px/ns", "per_call": "one image, level 0 only", **out}
+        ms["paper_svm_naive"] = timed(lambda: pd.score_windows_naive(blk, cel, wts, bias))
+        ms["paper_svm_warp"] = timed(lambda: pd.score_windows_wave(blk, cel, wts, bias))
+        r = {k: round(w * h / (v * 1e6), 3) for k, v in ms.items()}
+        r["speedup"] = {"lbp_scalable_over_naive": round(ms["paper_lbp_naive"] / ms["paper_lbp_scalable"], 2),
+                        "svm_warp_over_naive": round(ms["paper_svm_naive"] / ms["paper_svm_warp"], 2),
+                        "lbp_library_over_paper_best": round(min(ms["paper_lbp_naive"], ms["paper_lbp_scalable"])
+                                                             / ms["lbp"], 2),
+                        "hog_library_over_global": round(ms["paper_hog_global"] / ms["hog"], 2),
+                        "svm_library_over_paper_best": round(min(ms["paper_svm_naive"], ms["paper_svm_warp"])
+                                                             / ms["svm"], 2)}
+        out[f"{w}x{h}"] = r
+    return {"unit": "px/ns", "per_call": "one image, level 0 only",
+            "paper_kernels": "the paper's Section 4 mappings built for this GPU (ablation baselines)", **out}
 
 
 def pruned_leg(pd, torch, dev, frames, plain_boxes, wts, bias, thr_value, steps, warmup, n_train, n_cal, epochs,

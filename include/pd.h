@@ -271,6 +271,44 @@ int pd_score_windows_bf16(const uint16_t* blocks_bf16, const uint8_t* cells, int
                           const uint16_t* packed, const float* bias, int n_models, float* scores,
                           void* stream);
 
+/* ---- the paper's own kernel mappings (ablation baselines) ------------------
+ * The mappings the paper designs and measures (Section 4; px/ns comparisons
+ * of Section 5.3), kept so that they can be timed beside this library's
+ * kernels on the same GPU.  They compute the same results (up to FP32
+ * rounding order); pd_detect does not use them.
+ *
+ * pd_lbp_naive -- Section 4.2, Naive scheme: a thread per 8x8 cell counts
+ *   the cell's 64 codes of an LBP map (pd_lbp_codes output, [h][codes_pitch]
+ *   bytes) in a private array.
+ * pd_lbp_scatter -- Section 4.2, Scalable scheme (Algorithm 2): a thread per
+ *   pixel adds 1 to its cell's bin with a global atomic (the histogram is
+ *   cleared first).
+ *   cell_hist: device uint32 [h/8][w/8][59] (the paper's cell-major layout;
+ *   the uniform bins of pd_lbp).
+ * pd_hog_global -- Section 4.3, Algorithms 4 and 5, the Global variant: a
+ *   thread per pixel writes magnitude and orientation (degrees, [0, 180)) to
+ *   grad (device float [2][h][w], caller-owned scratch); then a thread per
+ *   16x16 block accumulates the block's trilinear histogram directly in
+ *   `blocks` (global memory) and applies L2-Hys.  Same definition and layout
+ *   as pd_hog: blocks float [36][Hb][Wb].
+ * pd_score_windows_naive -- Section 4.4, Naive scheme: a thread per window.
+ * pd_score_windows_wave -- Section 4.4, Algorithm 6 (warp-level): a wave per
+ *   window, lanes striding over the 11332 features, shuffle-tree reduction.
+ *   Both: the arguments, layouts and results of pd_score_windows.
+ * Errors: PD_E_ARG on NULL pointers or a pitch below the width, PD_E_SIZE on
+ * sizes outside the limits of the corresponding library call.
+ */
+int pd_lbp_naive(const uint8_t* codes, int w, int h, int codes_pitch, uint32_t* cell_hist, void* stream);
+int pd_lbp_scatter(const uint8_t* codes, int w, int h, int codes_pitch, uint32_t* cell_hist, void* stream);
+int pd_hog_global(const uint8_t* lvl, int w, int h, int pitch, const pd_params* params, float* grad,
+                  float* blocks, void* stream);
+int pd_score_windows_naive(const float* blocks, const uint8_t* cells, int cells_x, int cells_y,
+                           const float* weights, const float* bias, int n_models, float* scores,
+                           void* stream);
+int pd_score_windows_wave(const float* blocks, const uint8_t* cells, int cells_x, int cells_y,
+                          const float* weights, const float* bias, int n_models, float* scores,
+                          void* stream);
+
 /* ---- whole pipeline ------------------------------------------------------ */
 
 /* One input frame (device image). */

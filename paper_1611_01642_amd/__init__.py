@@ -104,6 +104,18 @@ _SIGS = {
     "pd_lbp_blocks": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
                                      ctypes.c_void_p]),
     "pd_fold_lbp_weights": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
+    "pd_lbp_naive": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                    ctypes.c_void_p]),
+    "pd_lbp_scatter": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                      ctypes.c_void_p]),
+    "pd_hog_global": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "pd_score_windows_naive": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                              ctypes.c_void_p]),
+    "pd_score_windows_wave": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                                             ctypes.c_void_p]),
     "pd_score_windows": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
                                         ctypes.c_void_p]),
@@ -363,6 +375,65 @@ def score_windows(blocks, cells, weights, bias):
                                   ctypes.c_void_p(weights.data_ptr()), ctypes.c_void_p(bias.data_ptr()), m,
                                   ctypes.c_void_p(out.data_ptr()), _stream()))
     return out
+
+
+# ------------------------------------------- the paper's own mappings --
+def lbp_naive(codes):
+    """pd_lbp_naive: uint32 [Hc][Wc][59] cell histograms from an LBP map
+    (uint8 [h][w] CUDA tensor, e.g. lbp_codes(img)), a thread per cell."""
+    torch = _torch()
+    p, w, h, pitch = _image_args(codes)
+    out = torch.empty((h // CELL, w // CELL, LBP_BINS), dtype=torch.int32, device=codes.device)
+    _check(lib().pd_lbp_naive(p, w, h, pitch, ctypes.c_void_p(out.data_ptr()), _stream()))
+    return out
+
+
+def lbp_scatter(codes):
+    """pd_lbp_scatter: the same histograms by global atomics (Algorithm 2)."""
+    torch = _torch()
+    p, w, h, pitch = _image_args(codes)
+    out = torch.empty((h // CELL, w // CELL, LBP_BINS), dtype=torch.int32, device=codes.device)
+    _check(lib().pd_lbp_scatter(p, w, h, pitch, ctypes.c_void_p(out.data_ptr()), _stream()))
+    return out
+
+
+def hog_global(img, prm: Params = None, grad=None):
+    """pd_hog_global: blocks [36][Hb][Wb] float32 by the paper's Global
+    variant (gradients through global memory, a thread per block)."""
+    torch = _torch()
+    prm = prm or params()
+    p, w, h, pitch = _image_args(img)
+    if grad is None or grad.numel() < 2 * w * h:
+        grad = torch.empty(2 * w * h, dtype=torch.float32, device=img.device)
+    out = torch.empty((HOG_BLOCK, max(h // CELL - 1, 0), max(w // CELL - 1, 0)), dtype=torch.float32,
+                      device=img.device)
+    _check(lib().pd_hog_global(p, w, h, pitch, ctypes.byref(prm), ctypes.c_void_p(grad.data_ptr()),
+                               ctypes.c_void_p(out.data_ptr()), _stream()))
+    return out
+
+
+def _score_baseline(fn, blocks, cells, weights, bias):
+    torch = _torch()
+    hc, wc = int(cells.shape[1]), int(cells.shape[2])
+    if blocks.shape != (HOG_BLOCK, hc - 1, wc - 1) or not blocks.is_contiguous() or not cells.is_contiguous():
+        raise ValueError("blocks must be [36][Hc-1][Wc-1] and cells [59][Hc][Wc], contiguous")
+    weights = weights.contiguous()
+    m = int(weights.shape[0])
+    out = torch.empty((m, max(hc - 15, 0), max(wc - 7, 0)), dtype=torch.float32, device=cells.device)
+    _check(fn(ctypes.c_void_p(blocks.data_ptr()), ctypes.c_void_p(cells.data_ptr()), wc, hc,
+              ctypes.c_void_p(weights.data_ptr()), ctypes.c_void_p(bias.data_ptr()), m,
+              ctypes.c_void_p(out.data_ptr()), _stream()))
+    return out
+
+
+def score_windows_naive(blocks, cells, weights, bias):
+    """pd_score_windows_naive: a thread per window."""
+    return _score_baseline(lib().pd_score_windows_naive, blocks, cells, weights, bias)
+
+
+def score_windows_wave(blocks, cells, weights, bias):
+    """pd_score_windows_wave: a wave per window (Algorithm 6)."""
+    return _score_baseline(lib().pd_score_windows_wave, blocks, cells, weights, bias)
 
 
 # ------------------------------------------------------------- pruner --

@@ -33,29 +33,6 @@
 namespace pd {
 namespace {
 
-// ---- uniform LBP table -------------------------------------------------------
-// Codes with at most two circular 0/1 transitions take bins 0..57 in ascending
-// code order; all others share bin 58.
-struct LbpTable {
-    uint8_t bin[256];
-};
-
-constexpr int popcount8(int v) {
-    int n = 0;
-    for (int k = 0; k < 8; ++k) n += (v >> k) & 1;
-    return n;
-}
-
-constexpr LbpTable make_lbp_table() {
-    LbpTable t{};
-    int next = 0;
-    for (int c = 0; c < 256; ++c) {
-        const int rot = ((c >> 1) | (c << 7)) & 255;  // rotate right by one bit
-        t.bin[c] = (uint8_t)(popcount8(c ^ rot) <= 2 ? next++ : 58);
-    }
-    return t;
-}
-
 __constant__ LbpTable kLbp = make_lbp_table();
 
 // ---- atan in units of orientation bins ---------------------------------------

@@ -1116,6 +1116,57 @@ int pd_score_windows(const float* blocks, const uint8_t* cells, int cells_x, int
                       "score launch");
 }
 
+int pd_lbp_naive(const uint8_t* codes, int w, int h, int codes_pitch, uint32_t* cell_hist, void* stream) {
+    if (int rc = check_image(codes, w, h, codes_pitch, "codes")) return rc;
+    if (!cell_hist) return fail(PD_E_ARG, "cell_hist is NULL");
+    return hip_status(launch_lbp_naive(codes, codes_pitch, w / PD_CELL, h / PD_CELL, cell_hist, (hipStream_t)stream),
+                      "lbp naive launch");
+}
+
+int pd_lbp_scatter(const uint8_t* codes, int w, int h, int codes_pitch, uint32_t* cell_hist, void* stream) {
+    if (int rc = check_image(codes, w, h, codes_pitch, "codes")) return rc;
+    if (!cell_hist) return fail(PD_E_ARG, "cell_hist is NULL");
+    return hip_status(launch_lbp_scatter(codes, codes_pitch, w / PD_CELL, h / PD_CELL, cell_hist, (hipStream_t)stream),
+                      "lbp scatter launch");
+}
+
+int pd_hog_global(const uint8_t* lvl, int w, int h, int pitch, const pd_params* params, float* grad, float* blocks,
+                  void* stream) {
+    if (int rc = check_image(lvl, w, h, pitch, "level")) return rc;
+    if (!check_params(params)) return PD_E_ARG;
+    if (!grad || !blocks) return fail(PD_E_ARG, "grad or blocks is NULL");
+    return hip_status(launch_hog_global(lvl, w, h, pitch, params->clip, params->eps, grad, blocks, (hipStream_t)stream),
+                      "hog global launch");
+}
+
+// Shared checks of the two baseline scoring entry points.
+static int check_score_args(const float* blocks, const uint8_t* cells, int cells_x, int cells_y, const float* weights,
+                            const float* bias, int n_models, const float* scores) {
+    if (cells_x < PD_WIN_CELLS_X || cells_y < PD_WIN_CELLS_Y || cells_x > PD_MAX_DIM / PD_CELL ||
+        cells_y > PD_MAX_DIM / PD_CELL)
+        return fail(PD_E_SIZE, "cell grid %dx%d cannot hold a window", cells_x, cells_y);
+    if (n_models < 1 || n_models > PD_MAX_MODELS)
+        return fail(PD_E_SIZE, "n_models %d outside [1, %d]", n_models, PD_MAX_MODELS);
+    if (!blocks || !cells || !weights || !bias || !scores) return fail(PD_E_ARG, "NULL pointer argument");
+    return PD_OK;
+}
+
+int pd_score_windows_naive(const float* blocks, const uint8_t* cells, int cells_x, int cells_y, const float* weights,
+                           const float* bias, int n_models, float* scores, void* stream) {
+    if (int rc = check_score_args(blocks, cells, cells_x, cells_y, weights, bias, n_models, scores)) return rc;
+    return hip_status(launch_svm_naive(blocks, cells, cells_x, cells_y, weights, bias, n_models, scores,
+                                       (hipStream_t)stream),
+                      "svm naive launch");
+}
+
+int pd_score_windows_wave(const float* blocks, const uint8_t* cells, int cells_x, int cells_y, const float* weights,
+                          const float* bias, int n_models, float* scores, void* stream) {
+    if (int rc = check_score_args(blocks, cells, cells_x, cells_y, weights, bias, n_models, scores)) return rc;
+    return hip_status(launch_svm_wave(blocks, cells, cells_x, cells_y, weights, bias, n_models, scores,
+                                      (hipStream_t)stream),
+                      "svm wave launch");
+}
+
 int pd_lbp_blocks(const uint8_t* cells, int n, int hc, int wc, uint16_t* blocks, void* stream) {
     if (n < 1 || hc < 2 || wc < 2 || hc > PD_MAX_DIM / PD_CELL || wc > PD_MAX_DIM / PD_CELL ||
         (int64_t)n * PD_LBP_BINS * hc > INT32_MAX)

@@ -100,6 +100,30 @@ constexpr int MF_TILE_C = 64;
 
 __host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
+// ---- uniform LBP table (Section 4.2) -----------------------------------------
+// Codes with at most two circular 0/1 transitions take bins 0..57 in ascending
+// code order; all others share bin 58.  Each kernel source that needs it
+// places its own __constant__ copy (make_lbp_table() at compile time).
+struct LbpTable {
+    uint8_t bin[256];
+};
+
+constexpr int popcount8(int v) {
+    int n = 0;
+    for (int k = 0; k < 8; ++k) n += (v >> k) & 1;
+    return n;
+}
+
+constexpr LbpTable make_lbp_table() {
+    LbpTable t{};
+    int next = 0;
+    for (int c = 0; c < 256; ++c) {
+        const int rot = ((c >> 1) | (c << 7)) & 255;  // rotate right by one bit
+        t.bin[c] = (uint8_t)(popcount8(c ^ rot) <= 2 ? next++ : 58);
+    }
+    return t;
+}
+
 // Device buffers reached through tables in memory (LevelItem and the like)
 // are typed as global memory inside kernels: the compiler cannot infer the
 // address space of such pointers and would emit FLAT accesses, which also
@@ -276,5 +300,15 @@ hipError_t launch_window_labels(const float* scores, int nx, int ny, int wc, int
                                 float* labels, float* mask, hipStream_t s);
 
 hipError_t launch_zero_i32(int32_t* p, int n, hipStream_t s);
+
+// The paper's own mappings, as ablation baselines (baselines.hip).
+hipError_t launch_lbp_naive(const uint8_t* codes, int pitch, int wc, int hc, uint32_t* hist, hipStream_t s);
+hipError_t launch_lbp_scatter(const uint8_t* codes, int pitch, int wc, int hc, uint32_t* hist, hipStream_t s);
+hipError_t launch_hog_global(const uint8_t* img, int w, int h, int pitch, float clip, float eps, float* grad,
+                             float* blocks, hipStream_t s);
+hipError_t launch_svm_naive(const float* blocks, const uint8_t* cells, int wc, int hc, const float* w,
+                            const float* bias, int n_models, float* scores, hipStream_t s);
+hipError_t launch_svm_wave(const float* blocks, const uint8_t* cells, int wc, int hc, const float* w,
+                           const float* bias, int n_models, float* scores, hipStream_t s);
 
 }  // namespace pd
