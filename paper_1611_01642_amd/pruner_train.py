@@ -42,12 +42,14 @@ def level_maps(frame, weights, bias, threshold_dev, prm):
     return out
 
 
-def training_set(frames, weights, bias, threshold: float, prm=None):
-    """Per frame, the list of its levels' (cell map, labels, mask)."""
+def training_set(frames, weights, bias, threshold, prm=None):
+    """Per frame, the list of its levels' (cell map, labels, mask); threshold:
+    one value for every frame, or a sequence of one per frame."""
     torch = _torch()
     prm = prm or make_params()
-    thr = torch.tensor([threshold], dtype=torch.float64, device=frames[0].device)
-    return [level_maps(f, weights, bias, thr, prm) for f in frames]
+    thr = list(threshold) if hasattr(threshold, "__len__") else [threshold] * len(frames)
+    return [level_maps(f, weights, bias, torch.tensor([t], dtype=torch.float64, device=frames[0].device), prm)
+            for f, t in zip(frames, thr)]
 
 
 def train(data, init_params, epochs: int = 4, frames_per_step: int = 8, lr: float = 1e-3, seed: int = 0,
