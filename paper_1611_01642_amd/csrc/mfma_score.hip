@@ -100,7 +100,8 @@ struct RowRegs {
     static constexpr int SR = HOG ? MF_HOG_SR : MF_LBP_SR;
     static constexpr int NC = HOG ? PD_HOG_BLOCK : PD_LBP_BINS;
     static constexpr int N = (SR * NC + 255) / 256;
-    uint16_t v[N];
+    // HOG: BF16 bits; LBP: the raw count (converted when stored)
+    std::conditional_t<HOG, uint16_t, uint32_t> v[N];
 };
 
 // The per-thread offsets are taken once per tile: goff[q], the
@@ -132,12 +133,10 @@ __device__ __forceinline__ void load_row_fast(RowRegs<HOG>& r, const RowOffsets<
     const uint32_t roff = (uint32_t)min(y, hrows - 1) * (uint32_t)hcols * (HOG ? 2u : 1u);
 #pragma unroll
     for (int q = 0; q < RowRegs<HOG>::N; ++q) {
-        if (HOG) {
-            r.v[q] = __builtin_amdgcn_raw_buffer_load_b16(rsrc, o.goff[q], roff, 0);
-        } else {  // counts <= 64: exact in bf16
-            const uint32_t b = __builtin_amdgcn_raw_buffer_load_b8(rsrc, o.goff[q], roff, 0);
-            r.v[q] = (uint16_t)(__float_as_uint((float)b) >> 16);
-        }
+        // raw values: LBP counts are converted when stored, so that no
+        // instruction waits on these loads before the MFMAs they overlap
+        if (HOG) r.v[q] = __builtin_amdgcn_raw_buffer_load_b16(rsrc, o.goff[q], roff, 0);
+        else r.v[q] = __builtin_amdgcn_raw_buffer_load_b8(rsrc, o.goff[q], roff, 0);
     }
 }
 
@@ -145,7 +144,13 @@ template <bool HOG>
 __device__ __forceinline__ void store_row_fast(const RowRegs<HOG>& r, const RowOffsets<HOG>& o, __bf16* dst) {
     uint8_t* d = reinterpret_cast<uint8_t*>(dst);
 #pragma unroll
-    for (int q = 0; q < RowRegs<HOG>::N; ++q) *reinterpret_cast<uint16_t*>(d + o.soff[q]) = r.v[q];
+    for (int q = 0; q < RowRegs<HOG>::N; ++q) {
+        // LBP counts <= 64 are exact in BF16: the top half of their FP32 value
+        uint16_t v;
+        if constexpr (HOG) v = r.v[q];
+        else v = (uint16_t)(__float_as_uint((float)r.v[q]) >> 16);
+        *reinterpret_cast<uint16_t*>(d + o.soff[q]) = v;
+    }
 }
 
 template <int BSZ>
@@ -224,8 +229,11 @@ __device__ __forceinline__ void mfma_tile(const uint16_t* __restrict__ hog16, co
         auto step = [&](int a, RowRegs<HOG>& cur, RowRegs<HOG>& nxt) __attribute__((always_inline)) {
             SliceRegs<BSZ> nsl;
             const bool more = a + 1 < A;
-            if (a + 2 < A) load_row_fast<HOG>(nxt, ro, rsrc, i0 + a + MF_ROWS + 1, hcols, hrows);
-            if (more) load_slice<BSZ>(nsl, wsrc + (size_t)(a + 1) * BSZ);
+            // issued on every step (row and slice indices clamped), so the
+            // number of loads in flight is the same on every path and the
+            // stores below wait only for their own loads
+            load_row_fast<HOG>(nxt, ro, rsrc, i0 + a + MF_ROWS + 1, hcols, hrows);
+            load_slice<BSZ>(nsl, wsrc + (size_t)min(a + 1, A - 1) * BSZ);
             const __bf16* row = sm.ring[(a + wave) % MF_RING];
             const __bf16* bw = sm.bw[a & 1];
 #pragma unroll

@@ -14,12 +14,14 @@
 // y - a; window row y - 15 is complete after row y.
 //
 // Numerics: HOG features are BF16 and the HOG weights their BF16 part; LBP
-// counts are exact and the LBP weights are hi + lo BF16 halves (two MFMAs into
-// the same FP32 accumulator).  FP32 accumulation; fixed summation order.
+// counts are exact and the LBP weights are hi + lo BF16 halves (two MFMAs per A
+// fragment).  FP32 accumulation; fixed summation order.
 //
 // Tile: a workgroup of 4 waves owns 64 window columns of one level (16 per
 // wave) and streams down all feature rows; a row's loads are issued two rows
 // ahead, so they are in flight during two rows of MFMAs.
+#include <type_traits>
+
 #include "pd_internal.h"
 
 namespace pd {
@@ -79,7 +81,8 @@ struct RowRegs {
     static constexpr int SR = HOG ? RG_HOG_SR : RG_LBP_SR;
     static constexpr int NC = HOG ? PD_HOG_BLOCK : PD_LBP_BINS;
     static constexpr int N = (SR * NC + 255) / 256;
-    uint16_t v[N];
+    // HOG: BF16 bits; LBP: the raw count (converted when stored)
+    std::conditional_t<HOG, uint16_t, uint32_t> v[N];
 };
 
 // The per-thread offsets are taken once per tile: goff[q], the
@@ -111,12 +114,10 @@ __device__ __forceinline__ void load_row_fast(RowRegs<HOG>& r, const RowOffsets<
     const uint32_t roff = (uint32_t)min(y, hrows - 1) * (uint32_t)hcols * (HOG ? 2u : 1u);
 #pragma unroll
     for (int q = 0; q < RowRegs<HOG>::N; ++q) {
-        if (HOG) {
-            r.v[q] = __builtin_amdgcn_raw_buffer_load_b16(rsrc, o.goff[q], roff, 0);
-        } else {  // counts <= 64: exact in bf16
-            const uint32_t b = __builtin_amdgcn_raw_buffer_load_b8(rsrc, o.goff[q], roff, 0);
-            r.v[q] = (uint16_t)(__float_as_uint((float)b) >> 16);
-        }
+        // raw values: LBP counts are converted when stored, so that no
+        // instruction waits on these loads before the MFMAs they overlap
+        if (HOG) r.v[q] = __builtin_amdgcn_raw_buffer_load_b16(rsrc, o.goff[q], roff, 0);
+        else r.v[q] = __builtin_amdgcn_raw_buffer_load_b8(rsrc, o.goff[q], roff, 0);
     }
 }
 
@@ -124,7 +125,13 @@ template <bool HOG>
 __device__ __forceinline__ void store_row_fast(const RowRegs<HOG>& r, const RowOffsets<HOG>& o, __bf16* dst) {
     uint8_t* d = reinterpret_cast<uint8_t*>(dst);
 #pragma unroll
-    for (int q = 0; q < RowRegs<HOG>::N; ++q) *reinterpret_cast<uint16_t*>(d + o.soff[q]) = r.v[q];
+    for (int q = 0; q < RowRegs<HOG>::N; ++q) {
+        // LBP counts <= 64 are exact in BF16: the top half of their FP32 value
+        uint16_t v;
+        if constexpr (HOG) v = r.v[q];
+        else v = (uint16_t)(__float_as_uint((float)r.v[q]) >> 16);
+        *reinterpret_cast<uint16_t*>(d + o.soff[q]) = v;
+    }
 }
 
 __device__ __forceinline__ bf16x8 a_frag(const __bf16* p) {  // 8-byte aligned run of 8 bf16
@@ -181,16 +188,19 @@ __device__ __forceinline__ void rowgemm_tile(const LevelItem& it, const uint16_t
     auto step = [&](int y, RowRegs<true>& ch, RowRegs<false>& cl, RowRegs<true>& nh, RowRegs<false>& nl)
                     __attribute__((always_inline)) {
         const int cur = y & 1;
-        if (y + 2 < hc) {
-            if (y + 2 < hb) load_row_fast<true>(nh, oh, rh_src, y + 2, wb, hb);
-            load_row_fast<false>(nl, ol, rl_src, y + 2, wc, hc);
-        }
-        f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+        // issued on every step (the row index is clamped), so the number of
+        // loads in flight is the same on every path and the store of row
+        // y + 1 below waits only for its own loads
+        load_row_fast<true>(nh, oh, rh_src, y + 2, wb, hb);
+        load_row_fast<false>(nl, ol, rl_src, y + 2, wc, hc);
+        // three accumulators (HOG, LBP hi, LBP lo), so consecutive MFMAs do
+        // not wait on one another; summed in that order
+        f32x4 acc_h = {0.0f, 0.0f, 0.0f, 0.0f}, acc_lh = acc_h, acc_ll = acc_h;
         if (y < hb) {
             const __bf16* row = sm.hog[cur] + (16 * wave + mrow) * RG_HOG_C + 8 * kg;
 #pragma unroll
             for (int t = 0; t < RG_HOG_T; ++t)
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_frag(row + 32 * t), bh[t], acc, 0, 0, 0);
+                acc_h = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_frag(row + 32 * t), bh[t], acc_h, 0, 0, 0);
         }
         {
             const __bf16* row = sm.lbp[cur] + (16 * wave + mrow) * RG_LBP_C + 8 * kg;
@@ -198,10 +208,11 @@ __device__ __forceinline__ void rowgemm_tile(const LevelItem& it, const uint16_t
 #pragma unroll
             for (int t = 0; t < RG_LBP_T; ++t) {
                 const bf16x8 av = a_frag(row + 32 * t);
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bl[t * 64 + lane], acc, 0, 0, 0);
-                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bl[(RG_LBP_T + t) * 64 + lane], acc, 0, 0, 0);
+                acc_lh = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bl[t * 64 + lane], acc_lh, 0, 0, 0);
+                acc_ll = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bl[(RG_LBP_T + t) * 64 + lane], acc_ll, 0, 0, 0);
             }
         }
+        const f32x4 acc = (acc_h + acc_lh) + acc_ll;
         // acc[r] = P[y][window 4*kg + r][a = mrow] belongs to window row y - a
         {
             const int i = y - mrow;
@@ -216,7 +227,7 @@ __device__ __forceinline__ void rowgemm_tile(const LevelItem& it, const uint16_t
                 const float v = ring[i & 15][lane];
                 ring[i & 15][lane] = 0.0f;
                 const int j = j0 + 16 * wave + lane;
-                if (i < ny && j < nx) it.scores[(size_t)i * nx + j] = v + bias;
+                if (i < ny && j < nx) gmem(it.scores)[(size_t)i * nx + j] = v + bias;
             }
         }
         if (y + 1 < hc) {
