@@ -149,6 +149,9 @@ __device__ __forceinline__ void rowgemm_tile(const LevelItem& it, const uint16_t
     const int ny = it.ny, nx = it.nx;
     const int j0 = tx * RG_COLS;
     const int mrow = lane & 15, kg = lane >> 4;
+    // a wave whose 16 window columns lie past the level (a level's last tile)
+    // stages rows with the others but does no MFMA work
+    const bool col_live = j0 + 16 * wave < nx;
 
     // B fragments: HOG in registers, LBP hi/lo in LDS (shared by the 4 waves)
     bf16x8 bh[RG_HOG_T];
@@ -196,13 +199,13 @@ __device__ __forceinline__ void rowgemm_tile(const LevelItem& it, const uint16_t
         // three accumulators (HOG, LBP hi, LBP lo), so consecutive MFMAs do
         // not wait on one another; summed in that order
         f32x4 acc_h = {0.0f, 0.0f, 0.0f, 0.0f}, acc_lh = acc_h, acc_ll = acc_h;
-        if (y < hb) {
+        if (col_live && y < hb) {
             const __bf16* row = sm.hog[cur] + (16 * wave + mrow) * RG_HOG_C + 8 * kg;
 #pragma unroll
             for (int t = 0; t < RG_HOG_T; ++t)
                 acc_h = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_frag(row + 32 * t), bh[t], acc_h, 0, 0, 0);
         }
-        {
+        if (col_live) {
             const __bf16* row = sm.lbp[cur] + (16 * wave + mrow) * RG_LBP_C + 8 * kg;
             const bf16x8* bl = reinterpret_cast<const bf16x8*>(sm.blbp);
 #pragma unroll
