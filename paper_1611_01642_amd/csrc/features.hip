@@ -8,24 +8,23 @@
 // pixel row, plus the two halo bytes; neighbouring lanes read neighbouring
 // bytes, so the loads are coalesced) and processes its 64 pixels:
 //   * LBP: 3x3 code -> uniform bin -> +1 on a byte counter in a lane-private
-//     LDS word (plain read-modify-write: no atomics are needed because no other
-//     lane touches these words);
+//     LDS word (an LDS add; no other lane touches these words);
 //   * HOG: gradient -> magnitude and orientation -> votes into the cell's
-//     "direction partials" A[dir][bin] held in registers, where dir is the
-//     neighbouring cell (3x3) whose centre the bilinear spatial weight points
-//     at.  The linear orientation interpolation is evaluated for all nine bins
-//     as a hat function (at most two are non-zero), so every accumulator index
-//     is a compile-time constant.  Spatial weights are separable: a pixel row
-//     first accumulates per target column, then the row is folded into A with
-//     the row's two target weights.
+//     "direction partials" A[dir][bin], where dir is the neighbouring cell
+//     (3x3) whose centre the bilinear spatial weight points at.  A pixel's
+//     linear orientation interpolation touches two bins, b and b + 1, and its
+//     spatial weights two target columns and two target rows: eight
+//     read-add-writes of lane-private LDS accumulators addressed by b, with
+//     the weights taken as products of the separable factors.  After each half cell row the
+//     accumulators of a finished target row are read into registers.
 // A 16x16-pixel block's trilinear histogram (Algorithm 5) equals, for each of
 // its four cell slots t, the sum over its four cells s of A[s][t - s]: votes
 // towards cells outside the block are exactly the terms this sum leaves out,
 // so every pixel is processed once although blocks overlap by 50 %.  The block
 // of row by = cy - 1 is assembled when cell row cy is done, from the previous
-// row's partials (kept in LDS) and the current ones, with one-lane shuffles
-// for the right-hand neighbour; then L2-Hys and planar stores (coalesced).
-// Strips overlap by one cell column, chunks by one cell row.
+// row's partials (kept in registers) and the current ones, with one-lane
+// shuffles for the right-hand neighbour; then L2-Hys and planar stores
+// (coalesced).  Strips overlap by one cell column, chunks by one cell row.
 //
 // Sums run in a fixed order, so results are bitwise reproducible.
 #include "pd_internal.h"
@@ -61,16 +60,20 @@ __host__ __device__ constexpr float sw(int p, int d) {
 
 constexpr int LBP_WORDS = 15;  // 59 byte counters packed in words
 
-// Per lane, what the previous cell row leaves for the next: with the cell map,
-// its partials of dirs dy in {0, 1} (54 values); without it, the four block
-// slot sums they feed (36 values), which keeps a workgroup's LDS small enough
-// for three workgroups per CU.
-template <bool CM>
+// Orientation votes go to lane-private LDS accumulators [target cell
+// row][dx + 1][bin] (bin 9 is bin 0 again, folded in when the accumulators are
+// read), so a pixel adds to its two active bins at an address taken from its
+// bin index instead of evaluating all nine.
+constexpr int VOTE_BINS = PD_HOG_BINS + 1;
+constexpr int VOTE_SLOTS = 2 * 3 * VOTE_BINS;
+
+// What the previous cell row leaves for the next stays in registers, and the
+// workgroup's LDS (lookup table, byte counters, vote accumulators: 76 KB)
+// leaves room for two workgroups per CU.
 struct FeatShared {
-    static constexpr int PREV_VALS = CM ? 6 * PD_HOG_BINS : 4 * PD_HOG_BINS;
     uint32_t lut[256];                               // (increment << 7) | word
     uint32_t cnt[FT_WAVES][FT_W * LBP_WORDS];        // lane-private byte counters
-    float prev[FT_WAVES][PREV_VALS][FT_W];           // previous cell row's partials or slot sums
+    float vote[FT_WAVES][VOTE_SLOTS][FT_W];          // lane-private orientation votes
 };
 
 // One pixel row of a cell's neighbourhood: byte i (0..9) is pixel x0 - 1 + i.
@@ -93,8 +96,11 @@ __device__ __forceinline__ PixRow load_row(gptr<const uint8_t> __restrict__ img,
         r.lo = (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16) | ((uint32_t)p[3] << 24);
         r.hi = (uint32_t)p[4] | ((uint32_t)p[5] << 8) | ((uint32_t)p[6] << 16) | ((uint32_t)p[7] << 24);
     }
-    const uint32_t left = x0 > 0 ? (uint32_t)p[-1] : (r.lo & 255u);
-    const uint32_t right = x0 + 8 < w ? (uint32_t)p[8] : (r.hi >> 24);
+    // the halo bytes (clamped at the image edges) from their own addresses, so
+    // that no value depends on another load before it is used
+    const auto row = img + (size_t)y * pitch;
+    const uint32_t left = row[max(x0 - 1, 0)];
+    const uint32_t right = row[min(x0 + 8, w - 1)];
     r.halo = left | (right << 8);
     r.l0 = __builtin_amdgcn_perm(r.lo, r.halo, 0x06050400u);
     r.l1 = __builtin_amdgcn_alignbyte(r.hi, r.lo, 3);
@@ -145,7 +151,7 @@ __device__ __forceinline__ void features_strip(gptr<const uint8_t> __restrict__ 
                                                gptr<float> __restrict__ hog, gptr<uint16_t> __restrict__ hog16,
                                                gptr<uint8_t> __restrict__ lbp, gptr<float> __restrict__ cmap,
                                                gptr<uint16_t> __restrict__ cmap16, int ty, int tx, int ch, float clip,
-                                               float eps, FeatShared<CM>& sm, int wave, int group = 64) {
+                                               float eps, FeatShared& sm, int wave, int group = 64) {
     constexpr bool DO_HOG = (FEAT & PD_FEAT_HOG) != 0;
     constexpr bool DO_LBP = (FEAT & PD_FEAT_LBP) != 0;
     static_assert(!CM || (DO_HOG && DO_LBP), "the cell map needs HOG and LBP");
@@ -240,26 +246,46 @@ __device__ __forceinline__ void features_strip(gptr<const uint8_t> __restrict__ 
 #pragma unroll
         for (int k = 0; k < LBP_WORDS; ++k) cnt[k] = 0u;
     }
+    // this lane's vote accumulators, [slot][lane] (slot stride FT_W words, so
+    // the lanes of a wave hit distinct banks)
+    float* vote = &sm.vote[wave][0][lane];
+    if (DO_HOG) {
+#pragma unroll
+        for (int k = 0; k < VOTE_SLOTS; ++k) vote[k * FT_W] = 0.0f;
+    }
 
-    // [value][lane].  With CM, value (r*3 + c+1)*9 + k is the previous cell
+    // In registers.  With CM, value (r*3 + c+1)*9 + k is the previous cell
     // row's partial of dir (dy = r, dx = c); after the top half of the next
     // row, r = 0 also holds that row's dy = -1 votes (the other term of the
     // same slots).  Without CM, value (r*2 + c)*9 + k is the sum aimed at slot
     // (r, c) of the block whose top-left cell is this lane's in the previous
     // row, from that row's two cells (and, after the top half of the next row,
     // from the next row's dy = -1 votes).
-    float (*P)[FT_W] = sm.prev[wave];
+    float Pn[CM ? 6 * PD_HOG_BINS : 4 * PD_HOG_BINS];
+    auto PV = [&](int i) -> float& { return Pn[i]; };
     // the two terms one cell row gives slot (r, c), c in {0, 1}, of the block
     // starting at this lane's column: own dx = c and the right lane's dx = c - 1
     auto pair = [&](const float (&X)[3][PD_HOG_BINS], int c, int k) -> float {
         return X[1 + c][k] + __shfl_down(X[c][k], 1, 64);
     };
     float Aa[3][PD_HOG_BINS], Ab[3][PD_HOG_BINS];  // [dx+1][bin] for two target rows
+    // target row r's accumulators into X (bin 9 folded into bin 0), then
+    // cleared for the next votes
+    auto take = [&](int r, float (&X)[3][PD_HOG_BINS]) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            float* q = vote + (r * 3 + a) * VOTE_BINS * FT_W;
+#pragma unroll
+            for (int k = 0; k < PD_HOG_BINS; ++k) X[a][k] = q[k * FT_W];
+            X[a][0] += q[PD_HOG_BINS * FT_W];
+#pragma unroll
+            for (int k = 0; k < VOTE_BINS; ++k) q[k * FT_W] = 0.0f;
+        }
+    };
 
     // one pixel row: votes into Aa (upper target row) and Ab (lower target row)
     auto pixel_row = [&](int py, const PixRow& U, const PixRow& C, const PixRow& D, float s0, float s1,
                          bool count_lbp) {
-        float R[3][PD_HOG_BINS];
         // LBP codes of the row's 8 pixels, four per word (Algorithm 1's
         // neighbours in its bit order: up-left, up, up-right, right,
         // down-right, down, down-left, left)
@@ -277,20 +303,14 @@ __device__ __forceinline__ void features_strip(gptr<const uint8_t> __restrict__ 
                 code4[hw] = lbp_codes4(r);
             }
         }
-        if (DO_HOG) {
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-#pragma unroll
-                for (int k = 0; k < PD_HOG_BINS; ++k) R[a][k] = 0.0f;
-        }
 #pragma unroll
         for (int px = 0; px < PD_CELL; ++px) {
             const int L = px_at(C, px), Rt = px_at(C, px + 2);
             const int T = px_at(U, px + 1), B = px_at(D, px + 1);
             if (DO_LBP && count_lbp) {
                 const uint32_t e = sm.lut[(code4[px >> 2] >> (8 * (px & 3))) & 255u];
-                uint32_t* q = cnt + (e & 127u);
-                *q = *q + (e >> 7);
+                // an LDS add: no read of the counter word comes back to the lane
+                __hip_atomic_fetch_add(cnt + (e & 127u), e >> 7, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             }
             if (DO_HOG) {
                 const int dx = L - Rt;  // Algorithm 4
@@ -302,36 +322,28 @@ __device__ __forceinline__ void features_strip(gptr<const uint8_t> __restrict__ 
                 float u = atan_bins(r);                           // [0, 2.25] bins
                 u = (ay > ax) ? 4.5f - u : u;                     // first quadrant
                 float t = ((dx * dy < 0) ? 9.0f - u : u) - 0.5f;  // fold, centres 10+20k
-                t = t < 0.0f ? t + 9.0f : t;                      // [0, 9)
-                // magnitude x hat(t - k): with c_j = mag (j - t), the hat of bin
-                // k is the median of 0, c_{k+1} and -c_{k-1}; bin 0 also takes
-                // the wrapped side, max(0, c_1, -c_8)
-                const float mt = mag * t;
-                float c[PD_HOG_BINS + 1];
-                c[0] = -mt;
-#pragma unroll
-                for (int j = 1; j <= PD_HOG_BINS; ++j) c[j] = fmaf((float)j, mag, -mt);
-                float wv[PD_HOG_BINS];
-                wv[0] = fmaxf(fmaxf(c[1], -c[8]), 0.0f);
-#pragma unroll
-                for (int k = 1; k < PD_HOG_BINS; ++k) wv[k] = __builtin_amdgcn_fmed3f(0.0f, c[k + 1], -c[k - 1]);
+                t = t < 0.0f ? t + 9.0f : t;                      // [0, 9]
                 const int dxa = px < 4 ? -1 : 0;
+                // linear interpolation between bins b and b + 1 (t = 9, a
+                // rounding of t + 9 for tiny negative t, is bin 0: b = 8 gives
+                // it all to slot 9, which is bin 0); the four trilinear
+                // targets, target row tr (weight s0 or s1) by column dx (the
+                // pixel's two bilinear column weights)
+                const int b = min((int)t, PD_HOG_BINS - 1);
+                const float wb = mag * (t - (float)b), wa = mag - wb;
+                float* q = vote + b * FT_W;
 #pragma unroll
-                for (int q = 0; q < 2; ++q) {
-                    const float sx = sw(px, dxa + q);
+                for (int tr = 0; tr < 2; ++tr)
 #pragma unroll
-                    for (int k = 0; k < PD_HOG_BINS; ++k) R[dxa + q + 1][k] = fmaf(sx, wv[k], R[dxa + q + 1][k]);
-                }
+                    for (int c = 0; c < 2; ++c) {
+                        const float k = sw(px, dxa + c) * (tr ? s1 : s0);
+                        float* o = q + (tr * 3 + dxa + c + 1) * VOTE_BINS * FT_W;
+                        // plain read-add-write: LDS float atomics run far slower
+                        // than integer ones, and no other lane touches these words
+                        o[0] += wa * k;
+                        o[FT_W] += wb * k;
+                    }
             }
-        }
-        if (DO_HOG) {
-#pragma unroll
-            for (int a = 0; a < 3; ++a)
-#pragma unroll
-                for (int k = 0; k < PD_HOG_BINS; ++k) {
-                    Aa[a][k] = fmaf(s0, R[a][k], Aa[a][k]);
-                    Ab[a][k] = fmaf(s1, R[a][k], Ab[a][k]);
-                }
         }
     };
 
@@ -362,36 +374,37 @@ __device__ __forceinline__ void features_strip(gptr<const uint8_t> __restrict__ 
                 D = N;
             }
         }
+        if (DO_HOG) take(0, Aa);  // the top half's votes towards cell row -1
         if (DO_HOG) {
             if (cy > cy_start && !CM) {  // fold the dy = -1 votes into the top slots
 #pragma unroll
                 for (int k = 0; k < PD_HOG_BINS; ++k) {
-                    P[0 * 9 + k][lane] += pair(Aa, 0, k);
-                    P[1 * 9 + k][lane] += pair(Aa, 1, k);
+                    PV(0 * 9 + k) += pair(Aa, 0, k);
+                    PV(1 * 9 + k) += pair(Aa, 1, k);
                 }
             }
             if (cy > cy_start && CM) {  // fold the dy = -1 votes into the previous row's r = 0 terms
                 // the blocks' top slots first, summed as without CM
 #pragma unroll
                 for (int k = 0; k < PD_HOG_BINS; ++k) {
-                    top[0][k] = (P[1 * 9 + k][lane] + __shfl_down(P[0 * 9 + k][lane], 1, 64)) + pair(Aa, 0, k);
-                    top[1][k] = (P[2 * 9 + k][lane] + __shfl_down(P[1 * 9 + k][lane], 1, 64)) + pair(Aa, 1, k);
+                    top[0][k] = (PV(1 * 9 + k) + __shfl_down(PV(0 * 9 + k), 1, 64)) + pair(Aa, 0, k);
+                    top[1][k] = (PV(2 * 9 + k) + __shfl_down(PV(1 * 9 + k), 1, 64)) + pair(Aa, 1, k);
                 }
 #pragma unroll
                 for (int a = 0; a < 3; ++a)
 #pragma unroll
-                    for (int k = 0; k < PD_HOG_BINS; ++k) P[a * 9 + k][lane] += Aa[a][k];
+                    for (int k = 0; k < PD_HOG_BINS; ++k) PV(a * 9 + k) += Aa[a][k];
                 {
                     // cell row cy - 1 is complete: votes from rows cy - 2 (down9),
                     // cy - 1 and cy (P r = 0); then row cy - 1's downward votes
                     float hist[PD_HOG_BINS];
 #pragma unroll
                     for (int k = 0; k < PD_HOG_BINS; ++k)
-                        hist[k] = down9[k] + gather3(P[0 * 9 + k][lane], P[1 * 9 + k][lane], P[2 * 9 + k][lane]);
+                        hist[k] = down9[k] + gather3(PV(0 * 9 + k), PV(1 * 9 + k), PV(2 * 9 + k));
                     if (cy - 1 >= cy0) emit_cell(cy - 1, hist);
 #pragma unroll
                     for (int k = 0; k < PD_HOG_BINS; ++k)
-                        down9[k] = gather3(P[3 * 9 + k][lane], P[4 * 9 + k][lane], P[5 * 9 + k][lane]);
+                        down9[k] = gather3(PV(3 * 9 + k), PV(4 * 9 + k), PV(5 * 9 + k));
                 }
             }
 #pragma unroll
@@ -409,6 +422,10 @@ __device__ __forceinline__ void features_strip(gptr<const uint8_t> __restrict__ 
             C = D;
             D = N;
         }
+        if (DO_HOG) {  // the bottom half's votes towards cell rows +1 and 0
+            take(0, Aa);
+            take(1, Ab);
+        }
 
         // LBP histogram of this cell row
         if (DO_LBP) {
@@ -416,8 +433,12 @@ __device__ __forceinline__ void features_strip(gptr<const uint8_t> __restrict__ 
             if (own_row && lbp_col) {
                 const size_t plane = (size_t)hc * wc;
                 auto o = lbp + (size_t)cy * wc + cx;
-#pragma unroll 1
-                for (int k = 0; k < PD_LBP_BINS; ++k, o += plane) *o = (uint8_t)((cnt[k >> 2] >> (8 * (k & 3))) & 255u);
+                // the 15 counter words once, then one byte store per bin
+                uint32_t words[LBP_WORDS];
+#pragma unroll
+                for (int k = 0; k < LBP_WORDS; ++k) words[k] = cnt[k];
+#pragma unroll
+                for (int k = 0; k < PD_LBP_BINS; ++k, o += plane) *o = (uint8_t)(words[k >> 2] >> (8 * (k & 3)));
                 if (CM && cmap) {
                     auto c = cmap + ((size_t)PD_HOG_BINS * hc + cy) * wc + cx;
 #pragma unroll 1
@@ -467,10 +488,10 @@ __device__ __forceinline__ void features_strip(gptr<const uint8_t> __restrict__ 
                 float v[PD_HOG_BLOCK];
 #pragma unroll
                 for (int k = 0; k < PD_HOG_BINS; ++k) {
-                    v[0 * 9 + k] = P[0 * 9 + k][lane];
-                    v[1 * 9 + k] = P[1 * 9 + k][lane];
-                    v[2 * 9 + k] = P[2 * 9 + k][lane] + S[0][k];
-                    v[3 * 9 + k] = P[3 * 9 + k][lane] + S[1][k];
+                    v[0 * 9 + k] = PV(0 * 9 + k);
+                    v[1 * 9 + k] = PV(1 * 9 + k);
+                    v[2 * 9 + k] = PV(2 * 9 + k) + S[0][k];
+                    v[3 * 9 + k] = PV(3 * 9 + k) + S[1][k];
                 }
                 if (blk_col) store_block(v, cy - 1);
             }
@@ -480,18 +501,18 @@ __device__ __forceinline__ void features_strip(gptr<const uint8_t> __restrict__ 
                 for (int k = 0; k < PD_HOG_BINS; ++k) {
                     v[0 * 9 + k] = top[0][k];
                     v[1 * 9 + k] = top[1][k];
-                    v[2 * 9 + k] = (P[4 * 9 + k][lane] + __shfl_down(P[3 * 9 + k][lane], 1, 64)) + S[0][k];
-                    v[3 * 9 + k] = (P[5 * 9 + k][lane] + __shfl_down(P[4 * 9 + k][lane], 1, 64)) + S[1][k];
+                    v[2 * 9 + k] = (PV(4 * 9 + k) + __shfl_down(PV(3 * 9 + k), 1, 64)) + S[0][k];
+                    v[3 * 9 + k] = (PV(5 * 9 + k) + __shfl_down(PV(4 * 9 + k), 1, 64)) + S[1][k];
                 }
                 if (blk_col) store_block(v, cy - 1);
             }
             if (cy < cy_last && !CM) {  // this row's slot sums for the next row's blocks
 #pragma unroll
                 for (int k = 0; k < PD_HOG_BINS; ++k) {
-                    P[0 * 9 + k][lane] = S[0][k];
-                    P[1 * 9 + k][lane] = S[1][k];
-                    P[2 * 9 + k][lane] = pair(Aa, 0, k);
-                    P[3 * 9 + k][lane] = pair(Aa, 1, k);
+                    PV(0 * 9 + k) = S[0][k];
+                    PV(1 * 9 + k) = S[1][k];
+                    PV(2 * 9 + k) = pair(Aa, 0, k);
+                    PV(3 * 9 + k) = pair(Aa, 1, k);
                 }
             }
             if (cy < cy_last && CM) {  // this row's dy = 0 and dy = +1 partials become P
@@ -499,8 +520,8 @@ __device__ __forceinline__ void features_strip(gptr<const uint8_t> __restrict__ 
                 for (int a = 0; a < 3; ++a)
 #pragma unroll
                     for (int k = 0; k < PD_HOG_BINS; ++k) {
-                        P[a * 9 + k][lane] = Ab[a][k];
-                        P[(3 + a) * 9 + k][lane] = Aa[a][k];
+                        PV(a * 9 + k) = Ab[a][k];
+                        PV((3 + a) * 9 + k) = Aa[a][k];
                     }
             }
         }
@@ -514,8 +535,7 @@ __device__ __forceinline__ void features_strip(gptr<const uint8_t> __restrict__ 
 }
 
 // Indexed by the bit-reversed code that lbp_codes4 produces.
-template <bool CM>
-__device__ inline void init_lut(FeatShared<CM>& sm) {
+__device__ inline void init_lut(FeatShared& sm) {
     for (int c = threadIdx.x; c < 256; c += FT_WAVES * 64) {
         const int b = kLbp.bin[__brev(c) >> 24];
         sm.lut[c] = ((1u << (8 * (b & 3))) << 7) | (uint32_t)(b >> 2);
@@ -524,7 +544,7 @@ __device__ inline void init_lut(FeatShared<CM>& sm) {
 
 template <int FEAT, bool ALIGNED>
 __global__ void __launch_bounds__(FT_WAVES * 64) features_single_kernel(LevelItem it, float clip, float eps) {
-    __shared__ FeatShared<false> sm;
+    __shared__ FeatShared sm;
     init_lut(sm);
     __syncthreads();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -537,7 +557,7 @@ __global__ void __launch_bounds__(FT_WAVES * 64) features_single_kernel(LevelIte
 
 template <bool ALIGNED>
 __global__ void __launch_bounds__(FT_WAVES * 64) cellmap_single_kernel(LevelItem it, float clip, float eps) {
-    __shared__ FeatShared<true> sm;
+    __shared__ FeatShared sm;
     init_lut(sm);
     __syncthreads();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -552,7 +572,7 @@ __global__ void __launch_bounds__(FT_WAVES * 64) cellmap_single_kernel(LevelItem
 __global__ void __launch_bounds__(FT_WAVES * 64) cellmap_table_kernel(const LevelItem* __restrict__ items,
                                                             const Tile* __restrict__ tiles, int n_tiles, int ch,
                                                             float clip, float eps) {
-    __shared__ FeatShared<true> sm;
+    __shared__ FeatShared sm;
     init_lut(sm);
     __syncthreads();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -571,7 +591,7 @@ template <int FEAT>
 __global__ void __launch_bounds__(FT_WAVES * 64) features_table_kernel(const LevelItem* __restrict__ items,
                                                              const Tile* __restrict__ tiles, int n_tiles, int ch,
                                                              float clip, float eps) {
-    __shared__ FeatShared<false> sm;
+    __shared__ FeatShared sm;
     init_lut(sm);
     __syncthreads();
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
