@@ -15,13 +15,19 @@
 // one contiguous run of 7*36 (padded to 256) or 8*60 (LBP channels padded to
 // 60) values, which the MFMA A operand reads directly.
 //
-// Tile: a workgroup of 4 waves owns window rows i0..i0+3 (one per wave) x
-// window columns j0..j0+63 (4 MFMA row tiles of 16 per wave).  Loop over a:
-// the 4 waves need feature rows i0+a .. i0+a+3, so rows pass through a 5-slot
-// LDS ring (each row is loaded from HBM and converted once); the weight slice
-// of offset a (packed B fragments) is staged once and shared by the 4 waves.
-// A feature row's loads are issued two steps before it is stored (HBM
-// latency spans two steps of MFMAs), a weight slice's one step before.
+// Tile: a workgroup of 4 waves owns window rows i0..i0+3 x window columns
+// j0..j0+63 (4 MFMA row tiles of 16), and the waves split the K chunks
+// (chunk t goes to wave t % 4): every wave accumulates all 16 (row tile,
+// window row) pairs over its chunks, and the four partial sums meet in LDS
+// once per tile, in a fixed order.  The feature rows i0 .. i0+3+A-1 stream
+// through a two-slot LDS ring (each loaded from HBM and converted once; the
+// next row's loads are in flight during the current row's MFMAs).  For
+// feature row r a wave reads each of its A fragments once and multiplies it
+// with the B fragments of the up to four offsets a = r - i that reach its
+// window rows; the B fragments of an offset are loaded from L2 when the
+// offset first appears (one step ahead) into a register ring of four
+// offsets, so each serves the four row tiles.  Per MFMA that is a quarter of
+// an A fragment from LDS and a quarter of a B fragment from L2.
 #include <type_traits>
 
 #include "pd_internal.h"
@@ -43,15 +49,14 @@ constexpr int MF_HOG_SR = MF_COLS + PD_WIN_BLOCKS_X - 1;  // 70 staged blocks pe
 constexpr int MF_LBP_SR = MF_COLS + PD_WIN_CELLS_X - 1;   // 71 staged cells per row
 constexpr int MF_HOG_ROW = MF_HOG_SR * MF_HOG_C + 8;      // bf16 per staged row (+ zero tail)
 constexpr int MF_LBP_ROW = MF_LBP_SR * MF_LBP_C + 8;
-constexpr int MF_RING = MF_ROWS + 1;
 constexpr int MF_ROW_MAX = ((MF_LBP_ROW > MF_HOG_ROW ? MF_LBP_ROW : MF_HOG_ROW) + 7) / 8 * 8;  // 16-byte rows
-constexpr int MF_B_ELEMS = MF_LBP_T * 16 * 32;            // packed B of one offset (LBP is larger)
 
-struct MfmaShared {
-    __bf16 ring[MF_RING][MF_ROW_MAX];
-    __bf16 bw[2][MF_B_ELEMS];
+// Two staged feature rows; at the end of a tile the same memory holds the
+// waves' partial sums, [wave][row tile][window row][lane] x 4.
+union MfmaShared {
+    __bf16 ring[2][MF_ROW_MAX];
+    f32x4 red[4][4][MF_ROWS][64];
 };
-static_assert((sizeof(__bf16) * MF_RING * MF_ROW_MAX) % 16 == 0, "weight slices must stay 16-byte aligned");
 
 __device__ __forceinline__ uint16_t f2bf(float f) { return f32_to_bf16(f); }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
@@ -153,28 +158,11 @@ __device__ __forceinline__ void store_row_fast(const RowRegs<HOG>& r, const RowO
     }
 }
 
-template <int BSZ>
-struct SliceRegs {
-    static constexpr int N = (BSZ / 8 + 255) / 256;
-    u32x4 v[N];
-};
-
-template <int BSZ>
-__device__ __forceinline__ void load_slice(SliceRegs<BSZ>& r, const uint16_t* __restrict__ src) {
-#pragma unroll
-    for (int q = 0; q < SliceRegs<BSZ>::N; ++q) {
-        const int e = min((int)threadIdx.x + 256 * q, BSZ / 8 - 1);
-        r.v[q] = reinterpret_cast<const u32x4*>(src)[e];
-    }
-}
-
-template <int BSZ>
-__device__ __forceinline__ void store_slice(const SliceRegs<BSZ>& r, __bf16* dst) {
-#pragma unroll
-    for (int q = 0; q < SliceRegs<BSZ>::N; ++q) {
-        const int e = threadIdx.x + 256 * q;
-        if (e < BSZ / 8) reinterpret_cast<u32x4*>(dst)[e] = r.v[q];
-    }
+__device__ __forceinline__ bf16x8 a_frag(const __bf16* p) {  // 8-byte aligned run of 8 bf16
+    const uint2 lo = *reinterpret_cast<const uint2*>(p);
+    const uint2 hi = *reinterpret_cast<const uint2*>(p + 4);
+    const u32x4 v = {lo.x, lo.y, hi.x, hi.y};
+    return __builtin_bit_cast(bf16x8, v);
 }
 
 template <int FEAT>
@@ -187,97 +175,115 @@ __device__ __forceinline__ void mfma_tile(const uint16_t* __restrict__ hog16, co
     const int ny = hc - PD_WIN_CELLS_Y + 1, nx = wc - PD_WIN_CELLS_X + 1;
     const int i0 = ty * MF_ROWS, j0 = tx * MF_COLS;
     const int mrow = lane & 15, kg = lane >> 4;
-    f32x4 acc[4];
+    // acc[m][ii]: row tile m (window columns j0 + 16 m ..), window row i0 + ii
+    f32x4 acc[4][MF_ROWS];
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt) acc[mt] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int ii = 0; ii < MF_ROWS; ++ii) acc[m][ii] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 
-    // zero the LDS once: every value an MFMA reads is then finite
-    for (int e = threadIdx.x; e < (int)(sizeof(MfmaShared) / 4); e += 256) reinterpret_cast<uint32_t*>(&sm)[e] = 0u;
+    // zero the staged rows once: every value an MFMA reads is then finite
+    for (int e = threadIdx.x; e < (int)(sizeof(sm.ring) / 4); e += 256) reinterpret_cast<uint32_t*>(&sm.ring[0][0])[e] = 0u;
     __syncthreads();
 
     auto phase = [&](auto hog_tag) __attribute__((always_inline)) {
         constexpr bool HOG = decltype(hog_tag)::value;
-        constexpr int A = HOG ? PD_WIN_BLOCKS_Y : PD_WIN_CELLS_Y;
-        constexpr int T = HOG ? MF_HOG_T : MF_LBP_T;
+        constexpr int A = HOG ? PD_WIN_BLOCKS_Y : PD_WIN_CELLS_Y;  // offsets
+        constexpr int T = HOG ? MF_HOG_T : MF_LBP_T;                // K chunks
         constexpr int C = HOG ? MF_HOG_C : MF_LBP_C;
-        constexpr int BSZ = T * 16 * 32;  // bf16 per offset slice
+        constexpr int NQ = (T + 3) / 4;                            // chunks per wave (t = wave + 4 q)
+        constexpr int S = A + MF_ROWS - 1;                         // feature rows of the tile
         const int hrows = HOG ? hb : hc, hcols = HOG ? wb : wc;
         const uint16_t* wsrc = HOG ? wpk : wpk + PD_WIN_BLOCKS_Y * MF_HOG_T * 16 * 32;
-        // prologue: rows i0..i0+3 and the slice of offset 0 into LDS; row
-        // i0+4 (stored after step 0) into registers
         RowOffsets<HOG> ro;
         row_offsets<HOG>(ro, j0, hcols, hrows);
         const auto rsrc = planes_rsrc(HOG ? (const void*)hog16 : (const void*)lbp,
                                       (uint64_t)RowRegs<HOG>::NC * hrows * hcols * (HOG ? 2 : 1));
-        RowRegs<HOG> rows2[2];
-        {
-            for (int r = 0; r < MF_ROWS; ++r) {
-                load_row_fast<HOG>(rows2[0], ro, rsrc, i0 + r, hcols, hrows);
-                store_row_fast<HOG>(rows2[0], ro, sm.ring[r]);
-            }
-            SliceRegs<BSZ> sr;
-            load_slice<BSZ>(sr, wsrc);
-            store_slice<BSZ>(sr, sm.bw[0]);
-            if (A > 1) load_row_fast<HOG>(rows2[0], ro, rsrc, i0 + MF_ROWS, hcols, hrows);
-        }
+        // B fragment of offset a, chunk wave + 4 q: this lane's 8 bf16
+        auto load_b = [&](int a, int q) -> bf16x8 {
+            const int t = min(wave + 4 * q, T - 1);
+            const uint16_t* p = wsrc + ((size_t)(a * T + t) * 16 + mrow) * 32 + 8 * kg;
+            return __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(p));
+        };
+        RowRegs<HOG> rr;
+        load_row_fast<HOG>(rr, ro, rsrc, i0, hcols, hrows);
+        store_row_fast<HOG>(rr, ro, sm.ring[0]);
+        // ring of B fragments by offset a % 4; the offset of the next step is
+        // loaded one step ahead into bn
+        bf16x8 bq[4][NQ], bn[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) bn[q] = load_b(0, q);
         __syncthreads();
-        // Step a: MFMAs on rows i0+a .. i0+a+3 with the slice of offset a.
-        // The feature row it stores at its end (i0+a+4) was loaded one step
-        // earlier, and it issues the load of row i0+a+5 for the next step: a
-        // row's load has two steps of MFMAs to arrive.  The weight slice
-        // (L2-resident) is loaded one step ahead.
-        auto step = [&](int a, RowRegs<HOG>& cur, RowRegs<HOG>& nxt) __attribute__((always_inline)) {
-            SliceRegs<BSZ> nsl;
-            const bool more = a + 1 < A;
-            // issued on every step (row and slice indices clamped), so the
-            // number of loads in flight is the same on every path and the
-            // stores below wait only for their own loads
-            load_row_fast<HOG>(nxt, ro, rsrc, i0 + a + MF_ROWS + 1, hcols, hrows);
-            load_slice<BSZ>(nsl, wsrc + (size_t)min(a + 1, A - 1) * BSZ);
-            const __bf16* row = sm.ring[(a + wave) % MF_RING];
-            const __bf16* bw = sm.bw[a & 1];
+        // step s: feature row i0 + s (ring slot s & 1) against offsets s - ii
+        // of window rows ii = 0..3 (those with 0 <= s - ii < A)
+        auto step = [&](int s, auto slot_tag) __attribute__((always_inline)) {
+            constexpr int U = decltype(slot_tag)::value;  // s % 4
+            const bool more = s + 1 < S;
+            // the next row's loads, issued on every step (the row index is
+            // clamped), so the count of loads in flight is the same on every
+            // path; the new offset's B fragments move into the ring, and the
+            // next offset's are loaded
 #pragma unroll
-            for (int t = 0; t < T; ++t) {
-                const bf16x8 bf = *reinterpret_cast<const bf16x8*>(bw + (t * 16 + mrow) * 32 + 8 * kg);
+            for (int q = 0; q < NQ; ++q) bq[U][q] = bn[q];
+            load_row_fast<HOG>(rr, ro, rsrc, i0 + s + 1, hcols, hrows);
 #pragma unroll
-                for (int mt = 0; mt < 4; ++mt) {
-                    const __bf16* ap = row + (16 * mt + mrow) * C + 32 * t + 8 * kg;
-                    const uint2 lo = *reinterpret_cast<const uint2*>(ap);
-                    const uint2 hi = *reinterpret_cast<const uint2*>(ap + 4);
-                    const u32x4 av = {lo.x, lo.y, hi.x, hi.y};
-                    acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av), bf, acc[mt], 0,
-                                                                      0, 0);
+            for (int q = 0; q < NQ; ++q) bn[q] = load_b(min(s + 1, A - 1), q);
+            const __bf16* row = sm.ring[s & 1] + mrow * C + 8 * kg;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const int t = wave + 4 * q;
+                if (NQ * 4 > T && t >= T) break;  // uniform: the last wave has one chunk fewer
+                bf16x8 av[4];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) av[m] = a_frag(row + 16 * m * C + 32 * t);
+#pragma unroll
+                for (int ii = MF_ROWS - 1; ii >= 0; --ii) {
+                    const int a = s - ii;
+                    if (a < 0 || a >= A) continue;  // uniform
+                    const bf16x8 bf = bq[(U - ii) & 3][q];
+#pragma unroll
+                    for (int m = 0; m < 4; ++m)
+                        acc[m][ii] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[m], bf, acc[m][ii], 0, 0, 0);
                 }
             }
-            if (more) {  // slots not read in this step (see the ring indexing above)
-                store_row_fast<HOG>(cur, ro, sm.ring[(a + MF_ROWS) % MF_RING]);
-                store_slice<BSZ>(nsl, sm.bw[(a + 1) & 1]);
-            }
+            if (more) store_row_fast<HOG>(rr, ro, sm.ring[(s + 1) & 1]);
             __syncthreads();
         };
-        // two register sets for rows in flight, alternating (unrolled by two
-        // so that each is a fixed set of registers)
-        for (int a = 0; a < A; a += 2) {
-            step(a, rows2[0], rows2[1]);
-            if (a + 1 < A) step(a + 1, rows2[1], rows2[0]);
+        for (int s = 0; s < S; s += 4) {
+            step(s, std::integral_constant<int, 0>());
+            if (s + 1 < S) step(s + 1, std::integral_constant<int, 1>());
+            if (s + 2 < S) step(s + 2, std::integral_constant<int, 2>());
+            if (s + 3 < S) step(s + 3, std::integral_constant<int, 3>());
         }
     };
     if (FEAT & PD_FEAT_HOG) phase(std::integral_constant<bool, true>());
     if (FEAT & PD_FEAT_LBP) phase(std::integral_constant<bool, false>());
 
-    // D layout: lane holds column n = lane % 16 for window rows 4*(lane/16) + r
-    // of each 16-window tile; model n's score = column n + column n + 8.
+    // the waves' partial sums meet in LDS (the rows are no longer read: the
+    // last step ended on a barrier); wave w finishes window row i0 + w,
+    // adding the four partials in wave order
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int ii = 0; ii < MF_ROWS; ++ii) sm.red[wave][m][ii][lane] = acc[m][ii];
+    __syncthreads();
     const int i = i0 + wave;
 #pragma unroll
-    for (int mt = 0; mt < 4; ++mt) {
+    for (int m = 0; m < 4; ++m) {
+        f32x4 v = sm.red[0][m][wave][lane];
+#pragma unroll
+        for (int w = 1; w < 4; ++w) v += sm.red[w][m][wave][lane];
+        // D layout: lane holds column n = lane % 16 for window columns
+        // 4 * (lane / 16) + r of the row tile; model n's score = column n +
+        // column n + 8
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const float v = acc[mt][r];
-            const float lo = __shfl_down(v, 8, 16);
+            const float hi = v[r];
+            const float lo = __shfl_down(hi, 8, 16);
             const int n = lane & 15;
-            const int j = j0 + 16 * mt + 4 * (lane >> 4) + r;
+            const int j = j0 + 16 * m + 4 * (lane >> 4) + r;
             if (n < 8 && n < n_models && i < ny && j < nx)
-                scores[((size_t)n * ny + i) * nx + j] = (v + lo) + bias[n];
+                scores[((size_t)n * ny + i) * nx + j] = (hi + lo) + bias[n];
         }
     }
 }
