@@ -256,7 +256,8 @@ int pd_score_windows(const float* blocks, const uint8_t* cells, int cells_x, int
  * bf16(w - hi) (LBP counts are exact); HOG weights as hi only (HOG features
  * are BF16).  One model: per feature row, a GEMM of windows x (b, c) x the
  * model's row offsets, then diagonal sums; 2..8 models: windows x features x
- * (models, hi/lo).
+ * (models, hi/lo) for LBP and (models, two row offsets) for HOG, whose one
+ * BF16 part per weight leaves room for a second window row.
  *
  * pd_packed_models_bytes -- bytes of the packed model buffer (any n_models).
  * pd_pack_models -- packs weights (device float [n_models][11332], layout of

@@ -2,12 +2,13 @@
 // accumulation (Section 4.4, Algorithm 6, recast as a GEMM).
 //
 // GEMM view: rows = windows, K = the 11332 features of a window, columns =
-// models.  Each model's FP32 weight w is split into two BF16 numbers,
-// hi = bf16(w) and lo = bf16(w - hi), and both become GEMM columns, so the 16
-// columns of one v_mfma_f32_16x16x32_bf16 hold 8 models x {hi, lo}; a model's
-// score is column hi + column lo.  LBP features are exact small integers, so
-// their weights keep hi + lo (~16 bits); HOG features are BF16, and their
-// weights keep the BF16 part only (the lo column is zero for HOG rows).
+// models.  LBP features are exact small integers, so each model's FP32 LBP
+// weight w is split into two BF16 numbers, hi = bf16(w) and lo = bf16(w - hi),
+// and both become GEMM columns: the 16 columns of one
+// v_mfma_f32_16x16x32_bf16 hold 8 models x {hi, lo}, and a model's score is
+// column hi + column lo.  HOG features are BF16 and their weights keep the
+// BF16 part only, so a HOG MFMA's 16 columns hold 8 models at two offsets,
+// serving two window rows.
 //
 // The K range of a window splits by window row offset a (15 HOG block rows,
 // 16 LBP cell rows).  For a fixed a, window (i, j) reads feature row i + a,
@@ -44,6 +45,7 @@ constexpr int MF_ROWS = 4;                        // window rows per tile (one p
 constexpr int MF_HOG_C = PD_HOG_BLOCK;            // 36 channels per block
 constexpr int MF_LBP_C = 60;                      // 59 bins + 1 zero
 constexpr int MF_HOG_T = 8;                       // K chunks of 32 per offset: 7*36 = 252 -> 256
+constexpr int MF_HOG_P = PD_WIN_BLOCKS_Y + 1;     // HOG weight slices: offset pairs (a, a + 1), a = -1 .. 14
 constexpr int MF_LBP_T = 15;                      // 8*60 = 480
 constexpr int MF_HOG_SR = MF_COLS + PD_WIN_BLOCKS_X - 1;  // 70 staged blocks per row
 constexpr int MF_LBP_SR = MF_COLS + PD_WIN_CELLS_X - 1;   // 71 staged cells per row
@@ -62,11 +64,15 @@ __device__ __forceinline__ uint16_t f2bf(float f) { return f32_to_bf16(f); }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 // ---- weight packing --------------------------------------------------------
-// HOG: [a 15][t 8][n 16][32]; LBP: [a 16][t 15][n 16][32] bf16.  Column n < 8
-// is the hi part of model n, n >= 8 the lo part of model n - 8; K index
-// k = 32 t + kk maps to (b, c) = (k / C, k % C) of the offset row.
+// HOG: [p 16][t 8][n 16][32]; LBP: [a 16][t 15][n 16][32] bf16; K index
+// k = 32 t + kk maps to (b, c) = (k / C, k % C) of the offset row.  LBP:
+// column n < 8 is the hi part of model n, n >= 8 the lo part of model n - 8.
+// HOG features are BF16, and the HOG weights carry their BF16 part only, so
+// a HOG slice holds two offsets: p = a + 1 for the pair (a, a + 1), column
+// n < 8 model n at offset a, n >= 8 model n - 8 at offset a + 1 (zero outside
+// 0 .. 14): one MFMA then serves two window rows.
 __global__ void pack_weights_kernel(const float* __restrict__ w, int n_models, uint16_t* __restrict__ out) {
-    const int hog_n = PD_WIN_BLOCKS_Y * MF_HOG_T * 16 * 32;
+    const int hog_n = MF_HOG_P * MF_HOG_T * 16 * 32;
     const int lbp_n = PD_WIN_CELLS_Y * MF_LBP_T * 16 * 32;
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= hog_n + lbp_n) return;
@@ -83,7 +89,9 @@ __global__ void pack_weights_kernel(const float* __restrict__ w, int n_models, u
     if (m < n_models) {
         if (is_hog) {
             const int b = k / MF_HOG_C, c = k % MF_HOG_C;
-            if (b < PD_WIN_BLOCKS_X) v = w[(size_t)m * PD_FEATURE_DIM + (a * PD_WIN_BLOCKS_X + b) * PD_HOG_BLOCK + c];
+            const int off = n < 8 ? a - 1 : a;  // a is the slice index p here
+            if (b < PD_WIN_BLOCKS_X && off >= 0 && off < PD_WIN_BLOCKS_Y)
+                v = w[(size_t)m * PD_FEATURE_DIM + (off * PD_WIN_BLOCKS_X + b) * PD_HOG_BLOCK + c];
         } else {
             const int b = k / MF_LBP_C, c = k % MF_LBP_C;
             if (b < PD_WIN_CELLS_X && c < PD_LBP_BINS)
@@ -91,9 +99,8 @@ __global__ void pack_weights_kernel(const float* __restrict__ w, int n_models, u
         }
     }
     const uint16_t hi = f2bf(v);
-    // HOG features are BF16, so the HOG weights carry their BF16 part only;
     // LBP counts are exact, so LBP weights carry hi + lo
-    out[e] = n < 8 ? hi : (is_hog ? (uint16_t)0 : f2bf(v - bf2f(hi)));
+    out[e] = (is_hog || n < 8) ? hi : f2bf(v - bf2f(hi));
 }
 
 // ---- scoring -----------------------------------------------------------------
@@ -194,12 +201,14 @@ __device__ __forceinline__ void mfma_tile(const uint16_t* __restrict__ hog16, co
         constexpr int NQ = (T + 3) / 4;                            // chunks per wave (t = wave + 4 q)
         constexpr int S = A + MF_ROWS - 1;                         // feature rows of the tile
         const int hrows = HOG ? hb : hc, hcols = HOG ? wb : wc;
-        const uint16_t* wsrc = HOG ? wpk : wpk + PD_WIN_BLOCKS_Y * MF_HOG_T * 16 * 32;
+        const uint16_t* wsrc = HOG ? wpk : wpk + MF_HOG_P * MF_HOG_T * 16 * 32;
+        constexpr int NS = HOG ? MF_HOG_P : A;                     // weight slices
         RowOffsets<HOG> ro;
         row_offsets<HOG>(ro, j0, hcols, hrows);
         const auto rsrc = planes_rsrc(HOG ? (const void*)hog16 : (const void*)lbp,
                                       (uint64_t)RowRegs<HOG>::NC * hrows * hcols * (HOG ? 2 : 1));
-        // B fragment of offset a, chunk wave + 4 q: this lane's 8 bf16
+        // B fragment of slice a (HOG: the pair (a - 1, a)), chunk wave + 4 q:
+        // this lane's 8 bf16
         auto load_b = [&](int a, int q) -> bf16x8 {
             const int t = min(wave + 4 * q, T - 1);
             const uint16_t* p = wsrc + ((size_t)(a * T + t) * 16 + mrow) * 32 + 8 * kg;
@@ -227,7 +236,7 @@ __device__ __forceinline__ void mfma_tile(const uint16_t* __restrict__ hog16, co
             for (int q = 0; q < NQ; ++q) bq[U][q] = bn[q];
             load_row_fast<HOG>(rr, ro, rsrc, i0 + s + 1, hcols, hrows);
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) bn[q] = load_b(min(s + 1, A - 1), q);
+            for (int q = 0; q < NQ; ++q) bn[q] = load_b(min(s + 1, NS - 1), q);
             const __bf16* row = sm.ring[s & 1] + mrow * C + 8 * kg;
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
@@ -236,14 +245,31 @@ __device__ __forceinline__ void mfma_tile(const uint16_t* __restrict__ hog16, co
                 bf16x8 av[4];
 #pragma unroll
                 for (int m = 0; m < 4; ++m) av[m] = a_frag(row + 16 * m * C + 32 * t);
+                if constexpr (HOG) {
+                    // pairs (window rows 3, 2) with slice s - 2 into acc[m][0]
+                    // and (1, 0) with slice s into acc[m][1]
+                    if (s >= 2) {  // uniform; s - 2 <= 15 always
+                        const bf16x8 bf = bq[(U - 2) & 3][q];
 #pragma unroll
-                for (int ii = MF_ROWS - 1; ii >= 0; --ii) {
-                    const int a = s - ii;
-                    if (a < 0 || a >= A) continue;  // uniform
-                    const bf16x8 bf = bq[(U - ii) & 3][q];
+                        for (int m = 0; m < 4; ++m)
+                            acc[m][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[m], bf, acc[m][0], 0, 0, 0);
+                    }
+                    if (s < MF_HOG_P) {
+                        const bf16x8 bf = bq[U][q];
 #pragma unroll
-                    for (int m = 0; m < 4; ++m)
-                        acc[m][ii] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[m], bf, acc[m][ii], 0, 0, 0);
+                        for (int m = 0; m < 4; ++m)
+                            acc[m][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[m], bf, acc[m][1], 0, 0, 0);
+                    }
+                } else {
+#pragma unroll
+                    for (int ii = MF_ROWS - 1; ii >= 0; --ii) {
+                        const int a = s - ii;
+                        if (a < 0 || a >= A) continue;  // uniform
+                        const bf16x8 bf = bq[(U - ii) & 3][q];
+#pragma unroll
+                        for (int m = 0; m < 4; ++m)
+                            acc[m][ii] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[m], bf, acc[m][ii], 0, 0, 0);
+                    }
                 }
             }
             if (more) store_row_fast<HOG>(rr, ro, sm.ring[(s + 1) & 1]);
@@ -256,7 +282,25 @@ __device__ __forceinline__ void mfma_tile(const uint16_t* __restrict__ hog16, co
             if (s + 3 < S) step(s + 3, std::integral_constant<int, 3>());
         }
     };
-    if (FEAT & PD_FEAT_HOG) phase(std::integral_constant<bool, true>());
+    if (FEAT & PD_FEAT_HOG) {
+        phase(std::integral_constant<bool, true>());
+        // the HOG pair sums into the per-row layout: window row ii's HOG
+        // score of model n in column n (where the LBP hi part adds to it),
+        // columns 8..15 cleared for the LBP lo part
+        const bool low = (lane & 15) < 8;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const f32x4 p32 = acc[m][0], p10 = acc[m][1];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float r2 = __shfl_down(p32[r], 8, 16), r0 = __shfl_down(p10[r], 8, 16);
+                acc[m][3][r] = low ? p32[r] : 0.0f;
+                acc[m][2][r] = low ? r2 : 0.0f;
+                acc[m][1][r] = low ? p10[r] : 0.0f;
+                acc[m][0][r] = low ? r0 : 0.0f;
+            }
+        }
+    }
     if (FEAT & PD_FEAT_LBP) phase(std::integral_constant<bool, false>());
 
     // the waves' partial sums meet in LDS (the rows are no longer read: the
@@ -335,7 +379,7 @@ __global__ void __launch_bounds__(256) mfma_table_kernel(const LevelItem* __rest
 }  // namespace
 
 int64_t packed_weight_elems() {
-    return (int64_t)(PD_WIN_BLOCKS_Y * MF_HOG_T + PD_WIN_CELLS_Y * MF_LBP_T) * 16 * 32;
+    return (int64_t)(MF_HOG_P * MF_HOG_T + PD_WIN_CELLS_Y * MF_LBP_T) * 16 * 32;
 }
 
 hipError_t launch_pack_weights(const float* w, int n_models, uint16_t* out, hipStream_t s) {

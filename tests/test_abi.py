@@ -89,7 +89,8 @@ def test_argument_errors_enqueue_nothing():
     assert L.pd_pack_models(fake, 9, fake, nil) == pd.E_SIZE
     assert L.pd_score_windows_bf16(fake, fake, 8, 16, fake, fake, 9, fake, nil) == pd.E_SIZE
     assert L.pd_score_windows_bf16(fake, fake, 7, 16, fake, fake, 1, fake, nil) == pd.E_SIZE
-    assert L.pd_packed_models_bytes() == ((15 * 8 + 16 * 15) * 16 * 32 + (8 + 2 * 15) * 64 * 8) * 2
+    # 8-model slices (HOG: 16 offset pairs x 8 chunks, LBP: 16 offsets x 15 chunks) + the 1-model fragments
+    assert L.pd_packed_models_bytes() == ((16 * 8 + 16 * 15) * 16 * 32 + (8 + 2 * 15) * 64 * 8) * 2
     assert L.pd_score_windows(fake, fake, 7, 16, fake, fake, 1, fake, nil) == pd.E_SIZE
     assert L.pd_score_windows(fake, fake, 8, 16, fake, fake, 0, fake, nil) == pd.E_SIZE
     assert L.pd_score_windows(fake, fake, 8, 16, fake, fake, 17, fake, nil) == pd.E_SIZE
