@@ -214,9 +214,14 @@ __device__ __forceinline__ void mfma_tile(const uint16_t* __restrict__ hog16, co
             const uint16_t* p = wsrc + ((size_t)(a * T + t) * 16 + mrow) * 32 + 8 * kg;
             return __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(p));
         };
-        RowRegs<HOG> rr;
-        load_row_fast<HOG>(rr, ro, rsrc, i0, hcols, hrows);
-        store_row_fast<HOG>(rr, ro, sm.ring[0]);
+        // a row's loads are issued PF steps before it is stored: two for HOG,
+        // whose steps carry few MFMAs, one for LBP (its registers hold the
+        // larger B ring)
+        constexpr int PF = HOG ? 2 : 1;
+        RowRegs<HOG> rr[PF];
+        load_row_fast<HOG>(rr[0], ro, rsrc, i0, hcols, hrows);
+        store_row_fast<HOG>(rr[0], ro, sm.ring[0]);
+        if constexpr (PF == 2) load_row_fast<HOG>(rr[1], ro, rsrc, i0 + 1, hcols, hrows);
         // ring of B fragments by offset a % 4; the offset of the next step is
         // loaded one step ahead into bn
         bf16x8 bq[4][NQ], bn[NQ];
@@ -234,7 +239,7 @@ __device__ __forceinline__ void mfma_tile(const uint16_t* __restrict__ hog16, co
             // next offset's are loaded
 #pragma unroll
             for (int q = 0; q < NQ; ++q) bq[U][q] = bn[q];
-            load_row_fast<HOG>(rr, ro, rsrc, i0 + s + 1, hcols, hrows);
+            load_row_fast<HOG>(rr[PF == 2 ? (U & 1) : 0], ro, rsrc, i0 + s + PF, hcols, hrows);
 #pragma unroll
             for (int q = 0; q < NQ; ++q) bn[q] = load_b(min(s + 1, NS - 1), q);
             const __bf16* row = sm.ring[s & 1] + mrow * C + 8 * kg;
@@ -272,7 +277,7 @@ __device__ __forceinline__ void mfma_tile(const uint16_t* __restrict__ hog16, co
                     }
                 }
             }
-            if (more) store_row_fast<HOG>(rr, ro, sm.ring[(s + 1) & 1]);
+            if (more) store_row_fast<HOG>(rr[PF == 2 ? ((U + 1) & 1) : 0], ro, sm.ring[(s + 1) & 1]);
             __syncthreads();
         };
         for (int s = 0; s < S; s += 4) {
