@@ -111,15 +111,23 @@ template <bool HOG>
 struct RowRegs {
     static constexpr int SR = HOG ? MF_HOG_SR : MF_LBP_SR;
     static constexpr int NC = HOG ? PD_HOG_BLOCK : PD_LBP_BINS;
-    static constexpr int N = (SR * NC + 255) / 256;
-    // HOG: BF16 bits; LBP: the raw count (converted when stored)
+    // per plane row, HOG: SR BF16 values; LBP: the SR count bytes as 4-byte
+    // words (columns 4 d .. 4 d + 3)
+    static constexpr int UNITS = HOG ? SR : (SR + 3) / 4;
+    static constexpr int N = (UNITS * NC + 255) / 256;
+    // HOG: BF16 bits; LBP: four raw counts (converted when stored)
     std::conditional_t<HOG, uint16_t, uint32_t> v[N];
 };
 
 // The per-thread offsets are taken once per tile: goff[q], the
 // element's byte offset in the planes without the row (raw buffer loads add
 // the row's byte offset as a scalar), and soff[q], its byte offset in a ring
-// slot.  Clamped elements repeat the last one (same value, same slot).
+// slot (LBP: that of the word's first column).  Clamped elements repeat the
+// last one (same value, same slot).  An LBP word is read from inside its
+// plane row: where columns 4 d .. 4 d + 3 reach past the row's end, from
+// the row's last four bytes, and shifted down by the difference (kept in the
+// top byte of soff), so that its columns inside the row get their counts;
+// the rest (past the level, feeding no stored window) get finite values.
 template <bool HOG>
 struct RowOffsets {
     uint32_t goff[RowRegs<HOG>::N], soff[RowRegs<HOG>::N];
@@ -127,15 +135,23 @@ struct RowOffsets {
 
 template <bool HOG>
 __device__ __forceinline__ void row_offsets(RowOffsets<HOG>& o, int j0, int hcols, int hrows) {
-    constexpr int SR = RowRegs<HOG>::SR, NC = RowRegs<HOG>::NC;
+    constexpr int U = RowRegs<HOG>::UNITS, NC = RowRegs<HOG>::NC;
     constexpr int C = HOG ? MF_HOG_C : MF_LBP_C;
     const uint32_t plane = (uint32_t)hrows * (uint32_t)hcols;
 #pragma unroll
     for (int q = 0; q < RowRegs<HOG>::N; ++q) {
-        const int e = min((int)threadIdx.x + 256 * q, SR * NC - 1);
-        const int c = e / SR, col = e - (e / SR) * SR;
-        o.goff[q] = ((uint32_t)c * plane + (uint32_t)min(j0 + col, hcols - 1)) * (HOG ? 2u : 1u);
-        o.soff[q] = (uint32_t)(col * C + c) * 2u;
+        const int e = min((int)threadIdx.x + 256 * q, U * NC - 1);
+        const int c = e / U, u = e - (e / U) * U;
+        const int col = HOG ? u : 4 * u;
+        if constexpr (HOG) {
+            o.goff[q] = ((uint32_t)c * plane + (uint32_t)min(j0 + col, hcols - 1)) * 2u;
+            o.soff[q] = (uint32_t)(col * C + c) * 2u;
+        } else {
+            // hcols >= 8 (a level holds at least one window)
+            const int start = min(j0 + col, hcols - 4);
+            o.goff[q] = (uint32_t)c * plane + (uint32_t)start;
+            o.soff[q] = (uint32_t)(col * C + c) * 2u | (uint32_t)min(j0 + col - start, 3) << 24;
+        }
     }
 }
 
@@ -148,7 +164,7 @@ __device__ __forceinline__ void load_row_fast(RowRegs<HOG>& r, const RowOffsets<
         // raw values: LBP counts are converted when stored, so that no
         // instruction waits on these loads before the MFMAs they overlap
         if (HOG) r.v[q] = __builtin_amdgcn_raw_buffer_load_b16(rsrc, o.goff[q], roff, 0);
-        else r.v[q] = __builtin_amdgcn_raw_buffer_load_b8(rsrc, o.goff[q], roff, 0);
+        else r.v[q] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, o.goff[q], roff, 0);
     }
 }
 
@@ -157,11 +173,24 @@ __device__ __forceinline__ void store_row_fast(const RowRegs<HOG>& r, const RowO
     uint8_t* d = reinterpret_cast<uint8_t*>(dst);
 #pragma unroll
     for (int q = 0; q < RowRegs<HOG>::N; ++q) {
-        // LBP counts <= 64 are exact in BF16: the top half of their FP32 value
-        uint16_t v;
-        if constexpr (HOG) v = r.v[q];
-        else v = (uint16_t)(__float_as_uint((float)r.v[q]) >> 16);
-        *reinterpret_cast<uint16_t*>(d + o.soff[q]) = v;
+        if constexpr (HOG) {
+            *reinterpret_cast<uint16_t*>(d + o.soff[q]) = r.v[q];
+        } else {
+            // LBP counts <= 64 are exact in BF16: the top half of their FP32
+            // value; byte k of the word is column 4 d + k (its channel's
+            // slot MF_LBP_C values further on), the last word's column 71
+            // past the staged row is skipped
+            const uint32_t so = o.soff[q] & 0xffffffu;
+            const uint32_t w = r.v[q] >> (8u * (o.soff[q] >> 24));
+            const uint32_t col0 = so / (2u * MF_LBP_C);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t b = (w >> (8 * k)) & 255u;
+                if (k < 3 || col0 + 3 < (uint32_t)MF_LBP_SR)
+                    *reinterpret_cast<uint16_t*>(d + so + k * 2 * MF_LBP_C) =
+                        (uint16_t)(__float_as_uint((float)b) >> 16);
+            }
+        }
     }
 }
 
@@ -214,10 +243,8 @@ __device__ __forceinline__ void mfma_tile(const uint16_t* __restrict__ hog16, co
             const uint16_t* p = wsrc + ((size_t)(a * T + t) * 16 + mrow) * 32 + 8 * kg;
             return __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(p));
         };
-        // a row's loads are issued PF steps before it is stored: two for HOG,
-        // whose steps carry few MFMAs, one for LBP (its registers hold the
-        // larger B ring)
-        constexpr int PF = HOG ? 2 : 1;
+        // a row's loads are issued two steps before it is stored
+        constexpr int PF = 2;
         RowRegs<HOG> rr[PF];
         load_row_fast<HOG>(rr[0], ro, rsrc, i0, hcols, hrows);
         store_row_fast<HOG>(rr[0], ro, sm.ring[0]);
