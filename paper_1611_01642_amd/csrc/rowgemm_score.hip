@@ -49,7 +49,7 @@ constexpr int RG_PACKED = (RG_HOG_T + 2 * RG_LBP_T) * RG_FRAG;
 struct RowShared {
     __bf16 hog[2][RG_HOG_ROW];
     __bf16 lbp[2][RG_LBP_ROW];
-    __bf16 blbp[2 * RG_LBP_T * RG_FRAG];
+    __bf16 blbp[RG_LBP_T * RG_FRAG];  // the LBP weights' lo fragments
     float ring[4][16][16];  // per wave: window-row slot x window column
 };
 
@@ -80,15 +80,23 @@ template <bool HOG>
 struct RowRegs {
     static constexpr int SR = HOG ? RG_HOG_SR : RG_LBP_SR;
     static constexpr int NC = HOG ? PD_HOG_BLOCK : PD_LBP_BINS;
-    static constexpr int N = (SR * NC + 255) / 256;
-    // HOG: BF16 bits; LBP: the raw count (converted when stored)
+    // per plane row, HOG: SR BF16 values; LBP: the SR count bytes as 4-byte
+    // words (columns 4 d .. 4 d + 3)
+    static constexpr int UNITS = HOG ? SR : (SR + 3) / 4;
+    static constexpr int N = (UNITS * NC + 255) / 256;
+    // HOG: BF16 bits; LBP: four raw counts (converted when stored)
     std::conditional_t<HOG, uint16_t, uint32_t> v[N];
 };
 
 // The per-thread offsets are taken once per tile: goff[q], the
 // element's byte offset in the planes without the row (raw buffer loads add
 // the row's byte offset as a scalar), and soff[q], its byte offset in the
-// staged row.  Clamped elements repeat the last one (same value, same place).
+// staged row (LBP: that of the word's first column).  Clamped elements repeat
+// the last one (same value, same place).  An LBP word is read from inside its
+// plane row: where columns 4 d .. 4 d + 3 reach past the row's end, from the
+// row's last four bytes, and shifted down by the difference (kept in the top
+// byte of soff), so that its columns inside the row get their counts; the
+// rest (past the level, feeding no stored window) get finite values.
 template <bool HOG>
 struct RowOffsets {
     uint32_t goff[RowRegs<HOG>::N], soff[RowRegs<HOG>::N];
@@ -96,15 +104,23 @@ struct RowOffsets {
 
 template <bool HOG>
 __device__ __forceinline__ void row_offsets(RowOffsets<HOG>& o, int j0, int hcols, int hrows) {
-    constexpr int SR = RowRegs<HOG>::SR, NC = RowRegs<HOG>::NC;
+    constexpr int U = RowRegs<HOG>::UNITS, NC = RowRegs<HOG>::NC;
     constexpr int C = HOG ? RG_HOG_C : RG_LBP_C;
     const uint32_t plane = (uint32_t)hrows * (uint32_t)hcols;
 #pragma unroll
     for (int q = 0; q < RowRegs<HOG>::N; ++q) {
-        const int e = min((int)threadIdx.x + 256 * q, SR * NC - 1);
-        const int c = e / SR, col = e - (e / SR) * SR;
-        o.goff[q] = ((uint32_t)c * plane + (uint32_t)min(j0 + col, hcols - 1)) * (HOG ? 2u : 1u);
-        o.soff[q] = (uint32_t)(col * C + c) * 2u;
+        const int e = min((int)threadIdx.x + 256 * q, U * NC - 1);
+        const int c = e / U, u = e - (e / U) * U;
+        const int col = HOG ? u : 4 * u;
+        if constexpr (HOG) {
+            o.goff[q] = ((uint32_t)c * plane + (uint32_t)min(j0 + col, hcols - 1)) * 2u;
+            o.soff[q] = (uint32_t)(col * C + c) * 2u;
+        } else {
+            // hcols >= 8 (a level holds at least one window)
+            const int start = min(j0 + col, hcols - 4);
+            o.goff[q] = (uint32_t)c * plane + (uint32_t)start;
+            o.soff[q] = (uint32_t)(col * C + c) * 2u | (uint32_t)min(j0 + col - start, 3) << 24;
+        }
     }
 }
 
@@ -117,7 +133,7 @@ __device__ __forceinline__ void load_row_fast(RowRegs<HOG>& r, const RowOffsets<
         // raw values: LBP counts are converted when stored, so that no
         // instruction waits on these loads before the MFMAs they overlap
         if (HOG) r.v[q] = __builtin_amdgcn_raw_buffer_load_b16(rsrc, o.goff[q], roff, 0);
-        else r.v[q] = __builtin_amdgcn_raw_buffer_load_b8(rsrc, o.goff[q], roff, 0);
+        else r.v[q] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, o.goff[q], roff, 0);
     }
 }
 
@@ -126,11 +142,24 @@ __device__ __forceinline__ void store_row_fast(const RowRegs<HOG>& r, const RowO
     uint8_t* d = reinterpret_cast<uint8_t*>(dst);
 #pragma unroll
     for (int q = 0; q < RowRegs<HOG>::N; ++q) {
-        // LBP counts <= 64 are exact in BF16: the top half of their FP32 value
-        uint16_t v;
-        if constexpr (HOG) v = r.v[q];
-        else v = (uint16_t)(__float_as_uint((float)r.v[q]) >> 16);
-        *reinterpret_cast<uint16_t*>(d + o.soff[q]) = v;
+        if constexpr (HOG) {
+            *reinterpret_cast<uint16_t*>(d + o.soff[q]) = r.v[q];
+        } else {
+            // LBP counts <= 64 are exact in BF16: the top half of their FP32
+            // value; byte k of the word is column 4 d + k (its channel's slot
+            // RG_LBP_C values further on), the last word's column 71 past the
+            // staged row is skipped
+            const uint32_t so = o.soff[q] & 0xffffffu;
+            const uint32_t w = r.v[q] >> (8u * (o.soff[q] >> 24));
+            const uint32_t col0 = so / (2u * RG_LBP_C);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const uint32_t b = (w >> (8 * k)) & 255u;
+                if (k < 3 || col0 + 3 < (uint32_t)RG_LBP_SR)
+                    *reinterpret_cast<uint16_t*>(d + so + k * 2 * RG_LBP_C) =
+                        (uint16_t)(__float_as_uint((float)b) >> 16);
+            }
+        }
     }
 }
 
@@ -153,13 +182,16 @@ __device__ __forceinline__ void rowgemm_tile(const LevelItem& it, const uint16_t
     // stages rows with the others but does no MFMA work
     const bool col_live = j0 + 16 * wave < nx;
 
-    // B fragments: HOG in registers, LBP hi/lo in LDS (shared by the 4 waves)
-    bf16x8 bh[RG_HOG_T];
+    // B fragments: HOG and LBP hi in registers, LBP lo in LDS (shared by the
+    // 4 waves)
+    bf16x8 bh[RG_HOG_T], blh[RG_LBP_T];
     const u32x4* pk = reinterpret_cast<const u32x4*>(packed);
 #pragma unroll
     for (int t = 0; t < RG_HOG_T; ++t) bh[t] = __builtin_bit_cast(bf16x8, pk[t * 64 + lane]);
-    for (int e = threadIdx.x; e < 2 * RG_LBP_T * 64; e += 256)
-        reinterpret_cast<u32x4*>(sm.blbp)[e] = pk[RG_HOG_T * 64 + e];
+#pragma unroll
+    for (int t = 0; t < RG_LBP_T; ++t) blh[t] = __builtin_bit_cast(bf16x8, pk[(RG_HOG_T + t) * 64 + lane]);
+    for (int e = threadIdx.x; e < RG_LBP_T * 64; e += 256)
+        reinterpret_cast<u32x4*>(sm.blbp)[e] = pk[(RG_HOG_T + RG_LBP_T) * 64 + e];
     for (int e = threadIdx.x; e < 4 * 16 * 16; e += 256) (&sm.ring[0][0][0])[e] = 0.0f;
     // zero the staged rows once so every value an MFMA reads is finite
     for (int e = threadIdx.x; e < (int)(sizeof(sm.hog) + sizeof(sm.lbp)) / 4; e += 256)
@@ -211,8 +243,8 @@ __device__ __forceinline__ void rowgemm_tile(const LevelItem& it, const uint16_t
 #pragma unroll
             for (int t = 0; t < RG_LBP_T; ++t) {
                 const bf16x8 av = a_frag(row + 32 * t);
-                acc_lh = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bl[t * 64 + lane], acc_lh, 0, 0, 0);
-                acc_ll = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bl[(RG_LBP_T + t) * 64 + lane], acc_ll, 0, 0, 0);
+                acc_lh = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, blh[t], acc_lh, 0, 0, 0);
+                acc_ll = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bl[t * 64 + lane], acc_ll, 0, 0, 0);
             }
         }
         const f32x4 acc = (acc_h + acc_lh) + acc_ll;
