@@ -228,14 +228,16 @@ __device__ __forceinline__ void rowgemm_tile(const LevelItem& it, const uint16_t
         // y + 1 below waits only for its own loads
         load_row_fast<true>(nh, oh, rh_src, y + 2, wb, hb);
         load_row_fast<false>(nl, ol, rl_src, y + 2, wc, hc);
-        // three accumulators (HOG, LBP hi, LBP lo), so consecutive MFMAs do
-        // not wait on one another; summed in that order
-        f32x4 acc_h = {0.0f, 0.0f, 0.0f, 0.0f}, acc_lh = acc_h, acc_ll = acc_h;
+        // four accumulators (HOG even and odd chunks, LBP hi, LBP lo), so
+        // consecutive MFMAs do not wait on one another; summed in a fixed order
+        f32x4 acc_h = {0.0f, 0.0f, 0.0f, 0.0f}, acc_h1 = acc_h, acc_lh = acc_h, acc_ll = acc_h;
         if (col_live && y < hb) {
             const __bf16* row = sm.hog[cur] + (16 * wave + mrow) * RG_HOG_C + 8 * kg;
 #pragma unroll
-            for (int t = 0; t < RG_HOG_T; ++t)
+            for (int t = 0; t < RG_HOG_T; t += 2) {
                 acc_h = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_frag(row + 32 * t), bh[t], acc_h, 0, 0, 0);
+                acc_h1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_frag(row + 32 * t + 32), bh[t + 1], acc_h1, 0, 0, 0);
+            }
         }
         if (col_live) {
             const __bf16* row = sm.lbp[cur] + (16 * wave + mrow) * RG_LBP_C + 8 * kg;
@@ -247,7 +249,7 @@ __device__ __forceinline__ void rowgemm_tile(const LevelItem& it, const uint16_t
                 acc_ll = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bl[t * 64 + lane], acc_ll, 0, 0, 0);
             }
         }
-        const f32x4 acc = (acc_h + acc_lh) + acc_ll;
+        const f32x4 acc = ((acc_h + acc_h1) + acc_lh) + acc_ll;
         // acc[r] = P[y][window 4*kg + r][a = mrow] belongs to window row y - a
         {
             const int i = y - mrow;
