@@ -436,7 +436,7 @@ def bf16_error_report(pd, torch, dev, host, m=8, n_frames=2, margin=0.05):
 
 def pruned_leg(pd, torch, dev, frames, plain_boxes, wts, bias, thr, steps, warmup, n_train, n_cal, epochs,
                tune=False, cal_target=0.995):
-    """The chosen form: learned pruning + BF16 MFMA scoring with FP64 rescoring.
+    """Learned pruning + BF16 MFMA scoring with FP64 rescoring (one or more SVMs).
     The pruner is trained here (n_train synthetic frames, the project's own
     forward/backward kernels), K is calibrated for cal_target recall of the
     plain FP32 detector's boxes on n_cal held-out frames (above the 99 % goal,
@@ -465,7 +465,9 @@ def pruned_leg(pd, torch, dev, frames, plain_boxes, wts, bias, thr, steps, warmu
     el, st, cnt, el_eager = time_detect(pd, torch, frames, wts, bias, prm, thr, steps, warmup, tune=tune)
     B = len(frames)
     r_bench, _ = T.recall_at(frames, wts, bias, thr, pr, k, plain_boxes, bf)
-    return {"form": "learned pruning (top-K windows per frame) + BF16 MFMA scoring + FP64 rescore, 1 SVM",
+    m = int(wts.shape[0])
+    return {"form": "learned pruning (top-K windows per frame) + BF16 MFMA scoring + FP64 rescore, "
+                    f"{m} SVM{'s' if m > 1 else ''}",
             "recall_ok": bool(r_bench >= 0.99),
             "value": round(B * steps / el, 1), "unit": "frames/s", "ms_per_step": round(1000 * el / steps, 4),
             "eager_frames_per_s": round(B * steps / el_eager, 1), "keep_k": k, "keep_fraction": round(k / n_win, 4), "recall_target_calibration": cal_target,
@@ -685,6 +687,25 @@ def main():
                                    args.train_frames, args.cal_frames, args.epochs, tune=not args.no_tune,
                                    cal_target=args.cal_target)
         print(f"[bench] pruned: {out['pruned']['value']} frames/s at K {out['pruned']['keep_k']}",
+              file=sys.stderr, flush=True)
+        # the same with 8 SVMs (the pruner trained on the 8-model detector's
+        # decisions), beside unpruned BF16 with 8 SVMs
+        print("[bench] pruned + BF16 leg, 8 models", file=sys.stderr, flush=True)
+        w8 = torch.from_numpy(pd_synth.svm_weights(8)).to(dev)
+        b8 = torch.from_numpy(pd_synth.svm_bias(8)).to(dev)
+        thr8 = frame_thresholds(pd, torch, frames, w8, b8, pd.params())
+        det8 = pd.Detector(frames, w8, b8, pd.params(), cap=1024)
+        det8.run(thr8)
+        torch.cuda.synchronize()
+        boxes8, _ = det8.results()
+        del det8
+        leg8 = pruned_leg(pd, torch, dev, frames, boxes8, w8, b8, thr8, args.steps, args.warmup,
+                          args.train_frames, args.cal_frames, args.epochs, tune=not args.no_tune,
+                          cal_target=args.cal_target)
+        if "bf16" in out:
+            leg8["unpruned_bf16_value"] = out["bf16"]["bf16_8model"]["value"]
+        out["pruned_8model"] = leg8
+        print(f"[bench] pruned, 8 models: {leg8['value']} frames/s at K {leg8['keep_k']}",
               file=sys.stderr, flush=True)
     # the fastest one-SVM form meeting the bars: detections equal to the FP64
     # oracle's (plain FP32; BF16 with FP64 rescoring) or >= 99 % recall of them
