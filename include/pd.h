@@ -96,11 +96,11 @@ typedef struct pd_params {
     /* Tile and launch shapes of pd_detect (0 = default).  They change the
        work partition only, never a result; pd_autotune picks them.        */
     int32_t tune_feat_rows;  /* block rows per feature strip: 4..32 (8)    */
-    int32_t tune_score_rows; /* PD_PREC_F32 window rows per scoring lane:
+    int32_t tune_score_rows; /* PD_PREC_F32 window rows per scoring band:
                                 4, 8 or 16 (8)                             */
-    int32_t tune_grid;       /* 0: one workgroup per tile group; n > 0:
-                                feature and scoring grids of at most n
-                                workgroups looping over the tiles          */
+    int32_t tune_grid;       /* 0: default grids; n > 0: feature and
+                                scoring grids of at most n workgroups
+                                looping over the tiles                     */
     /* Learned window pruning (pd_detect; see the pruner section below):
        with prune_keep = K > 0 the network `pruner` (device float
        [PD_PRUNER_PARAMS]) runs on every level (BF16 MFMA) and, per frame,

@@ -14,7 +14,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpd.so")
-SOURCES = ["pd_api.hip", "resize.hip", "features.hip", "score.hip", "mfma_score.hip", "rowgemm_score.hip", "rescore.hip", "nms.hip", "pruner.hip", "lbp_blocks.hip", "video.hip", "noalloc.hip", "ctx.hip", "checkpoint.hip", "baselines.hip"]
+SOURCES = ["pd_api.hip", "resize.hip", "features.hip", "score.hip", "score32.hip", "mfma_score.hip", "rowgemm_score.hip", "rescore.hip", "nms.hip", "pruner.hip", "lbp_blocks.hip", "video.hip", "noalloc.hip", "ctx.hip", "checkpoint.hip", "baselines.hip"]
 ARCH = "gfx950"
 
 FLAGS = [

@@ -298,6 +298,7 @@ struct DetectLayout {
     std::vector<int64_t> cm_off, a1_off, a2_off, lg_off;  // per item (pruning)
     int64_t off_items = 0, off_tiles = 0, off_geoms = 0, off_first = 0, off_counters = 0, off_cscore = 0,
             off_ckey = 0, off_c64 = 0, off_near_count = 0, off_near_key = 0, off_packed = 0, off_orient = 0;
+    int64_t off_s32ctr = 0, off_s32pack = 0;  // FP32 scoring: band counters (zeroed with the others), packed weights
     int64_t off_sel_score = 0, off_sel_key = 0, off_sel_64 = 0;  // per frame, the top PD_MAX_CANDIDATES
     int64_t off_data = 0, total = 0;
     int64_t table_bytes = 0;  // bytes uploaded from the host (items .. geoms)
@@ -357,7 +358,7 @@ bool plan_detect(const pd_frame* frames, int n_frames, const pd_params* p, int n
             // table capacity for the finest tile shapes the tuning fields
             // allow, so the workspace size does not depend on them
             L.n_ft += (L.prune ? feat_tiles_x_cm(it.wc) : feat_tiles_x(it.wc)) * feat_tiles_y(it.hc, FT_MIN_ROWS);
-            L.n_sc += !L.bf16    ? score_tiles_x(it.nx) * score_tiles_y(it.ny, 4) * n_models
+            L.n_sc += !L.bf16    ? score32_band_capacity(it.nx, it.ny, it.wc)
                       : L.rowgemm ? ceil_div(it.nx, RG_TILE_C)
                                   : ceil_div(it.nx, MF_TILE_C) * ceil_div(it.ny, MF_TILE_R);
             L.n_cp += ceil_div(it.nx * it.ny, CP_N);
@@ -380,6 +381,10 @@ bool plan_detect(const pd_frame* frames, int n_frames, const pd_params* p, int n
     o = align_up(o + (int64_t)n_frames * 4, kAlign);
     L.off_near_count = o;  // per-frame near counters + the dense list length (+ kept tiles)
     o = align_up(o + (int64_t)(n_frames + 2) * 4, kAlign);
+    if (!L.bf16) {
+        L.off_s32ctr = o;
+        o = align_up(o + (int64_t)S32_COUNTERS * 4, kAlign);
+    }
     // candidate lists: room for every window of every frame
     L.off_cscore = o;
     o = align_up(o + L.n_windows * 4, kAlign);
@@ -400,6 +405,10 @@ bool plan_detect(const pd_frame* frames, int n_frames, const pd_params* p, int n
         o = align_up(o + (packed_weight_elems() + rowgemm_packed_elems()) * 2, kAlign);
         L.off_orient = o;
         o = align_up(o + ORIENT_BYTES, kAlign);
+    }
+    if (!L.bf16) {
+        L.off_s32pack = o;
+        o = align_up(o + score32_packed_floats(n_models) * 4, kAlign);
     }
     if (L.prune) {
         L.off_kth = o;
@@ -491,7 +500,10 @@ struct DetectRun {
     const LevelItem* items = nullptr;
     const Tile *t_rs = nullptr, *t_ft = nullptr, *t_sc = nullptr, *t_cp = nullptr;
     int nrs = 0, nft = 0, nsc = 0, ncp = 0;  // tiles in use
-    int nsc_half = 0;  // FP32 score tiles of half height, stored after the nsc others
+    XcdLists xs{};     // FP32 scoring: the band table's per-XCD lists
+    int s32_grid = 0;  // and its launch width
+    int32_t* s32_ctr = nullptr;
+    float* s32_pack = nullptr;
     const NmsGeom* geoms = nullptr;
     const int32_t* first = nullptr;
     int32_t* counters = nullptr;
@@ -533,7 +545,6 @@ void fill_tables(const pd_frame* frames, int n_frames, int n_models, const Tunin
     Tile* t_cp = t_sc + L.n_sc;
     Tile* t_pr = t_cp + L.n_cp;
     int q = 0, nrs = 0, nft = 0, nsc = 0, ncp = 0, npr = 0;
-    std::vector<Tile> half;  // FP32 score tiles of half height, appended after the others
     for (int f = 0; f < n_frames; ++f) {
         geoms[f].n_levels = L.level_count[f];
         geoms[f].cand_off = L.cand_off[f];
@@ -601,28 +612,6 @@ void fill_tables(const pd_frame* frames, int n_frames, int n_models, const Tunin
             } else if (L.bf16) {
                 for (int ty = 0; ty < ceil_div(it.ny, MF_TILE_R); ++ty)
                     for (int tx = 0; tx < ceil_div(it.nx, MF_TILE_C); ++tx) t_sc[nsc++] = Tile{q, ty, tx, 0};
-            } else {
-                // full 64-column tiles; the last columns in 32- or 16-lane
-                // groups, each on its own row chunk
-                const int nty = score_tiles_y(it.ny, tu.score_rows);
-                const int full = it.nx / SC_W, tail = it.nx - full * SC_W;
-                const int width = tail > 32 ? 64 : (tail > 16 ? 32 : 16);
-                // a tile covering only the level's last row chunk, with at most
-                // half of its rows valid, goes to the half-height list (not
-                // with pruning: the kept list is scored by one launch)
-                const int sr = tu.score_rows;
-                auto add = [&](const Tile& t, int groups) {
-                    const bool single = std::min(t.ty + groups, nty) - 1 == t.ty;
-                    if (!L.prune && sr >= 4 && single && it.ny - t.ty * sr <= sr / 2) half.push_back(t);
-                    else t_sc[nsc++] = t;
-                };
-                for (int m = 0; m < n_models; ++m) {
-                    for (int ty = 0; ty < nty; ++ty)
-                        for (int tx = 0; tx < full; ++tx) add(Tile{q, ty, tx, score_pad(m, 64)}, 1);
-                    if (tail > 0)
-                        for (int ty = 0; ty < nty; ty += SC_W / width)
-                            add(Tile{q, ty, full, score_pad(m, width)}, SC_W / width);
-                }
             }
             for (int c = 0; c < ceil_div(it.nx * it.ny, CP_N); ++c) t_cp[ncp++] = Tile{q, 0, c, 0};
         }
@@ -646,8 +635,7 @@ void fill_tables(const pd_frame* frames, int n_frames, int n_models, const Tunin
         const std::vector<Tile> by_item(t_ft, t_ft + nft);
         for (const Tile& t : by_item) t_ft[start[rows_of(t)]++] = t;
     }
-    R.nsc_half = (int)half.size();  // within capacity: one tile each, as without the split
-    for (int k = 0; k < R.nsc_half; ++k) t_sc[nsc + k] = half[k];
+    if (!L.bf16) nsc = score32_bands(items, q, tu.score_rows, tu.grid, t_sc, &R.xs, &R.s32_grid);
     const Tile* d_tiles = reinterpret_cast<const Tile*>(tbl + L.off_tiles);
     R.items = reinterpret_cast<const LevelItem*>(tbl + L.off_items);
     R.t_rs = d_tiles;
@@ -673,6 +661,10 @@ void fill_tables(const pd_frame* frames, int n_frames, int n_models, const Tunin
     R.packed = L.bf16 ? reinterpret_cast<uint16_t*>(ws + L.off_packed) : nullptr;
     R.orient = L.bf16 ? reinterpret_cast<double2*>(ws + L.off_orient) : nullptr;
     R.n_zero = (int)((L.off_cscore - L.off_counters) / 4);
+    if (!L.bf16) {
+        R.s32_ctr = reinterpret_cast<int32_t*>(ws + L.off_s32ctr);
+        R.s32_pack = reinterpret_cast<float*>(ws + L.off_s32pack);
+    }
     if (L.prune) {
         R.t_pr = d_tiles + L.n_rs + L.n_ft + L.n_sc + L.n_cp;
         R.npr = npr;
@@ -719,6 +711,7 @@ int enqueue_detect(const DetectRun& R, const DetectLayout& L, const Tuning& tu, 
     int rc;
     marks.mark(PD_STAGE_ZERO, s);
     if ((rc = hip_status(launch_zero_i32(R.counters, R.n_zero, s), "zero"))) return rc;
+    if (!L.bf16 && (rc = hip_status(launch_pack_score32(weights, n_models, R.s32_pack, s), "pack"))) return rc;
     if (L.bf16) {
         if ((rc = hip_status(launch_orient_table(R.orient, s), "gradient table"))) return rc;
         if ((rc = hip_status(launch_pack_weights(weights, n_models, R.packed, s), "pack"))) return rc;
@@ -738,24 +731,26 @@ int enqueue_detect(const DetectRun& R, const DetectLayout& L, const Tuning& tu, 
             return rc;
         if ((rc = hip_status(launch_topk(R.items, R.first, R.geoms, n_frames, params->prune_keep, R.kth, s), "top-k")))
             return rc;
-        const int rows = L.bf16 ? MF_TILE_R : tu.score_rows, cols = L.bf16 ? MF_TILE_C : SC_W;
-        if (L.rowgemm) {
+        if (!L.bf16) {
+            // FP32: bands span whole rows of 16-column tiles, which nearly
+            // always hold a kept window; the keep set acts in compaction
+            rc = hip_status(launch_score32_table(R.items, R.t_sc, R.xs, R.s32_grid, R.s32_pack, bias, n_models,
+                                                 params->features, tu.score_rows, R.s32_ctr, s),
+                            "score");
+        } else if (L.rowgemm) {
             // one model: the row-GEMM kernel scores whole 64-column strips, which
             // nearly always hold a kept window; the keep set acts in compaction
             rc = hip_status(launch_rowgemm_table(R.items, R.t_sc, R.nsc, R.packed + packed_weight_elems(), bias,
                                                  tu.grid, s),
                             "bf16 score");
         } else {
-            rc = hip_status(launch_tile_filter(R.items, R.t_sc, R.nsc, rows, cols, R.kth, R.kept, R.kept_count, s),
+            rc = hip_status(launch_tile_filter(R.items, R.t_sc, R.nsc, MF_TILE_R, MF_TILE_C, R.kth, R.kept,
+                                               R.kept_count, s),
                             "tile filter");
-            if (!rc && L.bf16)
+            if (!rc)
                 rc = hip_status(launch_mfma_table(R.items, R.kept, R.nsc, R.packed, bias, n_models, params->features,
                                                   tu.grid, s, R.kept_count),
                                 "bf16 score");
-            else if (!rc)
-                rc = hip_status(launch_score_table(R.items, R.kept, R.nsc, weights, bias, n_models, params->features,
-                                                   tu, s, R.kept_count),
-                                "score");
         }
         if (rc) return rc;
         marks.mark(PD_STAGE_COMPACT, s);
@@ -777,8 +772,8 @@ int enqueue_detect(const DetectRun& R, const DetectLayout& L, const Tuning& tu, 
                                                tu.grid, s),
                              "bf16 score")))
             return rc;
-    } else if ((rc = hip_status(launch_score_table(R.items, R.t_sc, R.nsc, weights, bias, n_models,
-                                                   params->features, tu, s, nullptr, R.nsc_half),
+    } else if ((rc = hip_status(launch_score32_table(R.items, R.t_sc, R.xs, R.s32_grid, R.s32_pack, bias, n_models,
+                                                     params->features, tu.score_rows, R.s32_ctr, s),
                                 "score"))) {
         return rc;
     }
@@ -1553,7 +1548,7 @@ int pd::detect_on_workspace(const pd_frame* frames, int n_frames, const float* w
         {L.off_items, (int64_t)L.n_items * (int64_t)sizeof(LevelItem)},
         {t0, R.nrs * tsz},
         {t0 + L.n_rs * tsz, R.nft * tsz},
-        {t0 + (L.n_rs + L.n_ft) * tsz, (int64_t)(R.nsc + R.nsc_half) * tsz},
+        {t0 + (L.n_rs + L.n_ft) * tsz, (int64_t)R.nsc * tsz},
         {t0 + (L.n_rs + L.n_ft + L.n_sc) * tsz, R.ncp * tsz},
         {t0 + (L.n_rs + L.n_ft + L.n_sc + L.n_cp) * tsz, R.npr * tsz},
         {L.off_geoms, L.table_bytes - L.off_geoms},

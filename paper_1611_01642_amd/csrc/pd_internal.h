@@ -183,7 +183,7 @@ __host__ __device__ inline int score_tiles_y(int ny, int rows = SC_R) { return c
 // Tile shapes and launch shapes chosen at run time (pd_params tuning fields).
 struct Tuning {
     int feat_rows = FT_CH;   // block rows per feature strip (2..32)
-    int score_rows = SC_R;   // FP32 scoring: window rows per lane (4, 8 or 16)
+    int score_rows = SC_R;   // FP32 scoring: window rows per band (4, 8 or 16)
     int grid = 0;            // 0: one workgroup per tile group; > 0: at most this many, looping
 };
 
@@ -204,12 +204,22 @@ hipError_t launch_features_cellmap_table(const LevelItem* items, const Tile* til
 
 hipError_t launch_score_single(const LevelItem& it, const float* w, const float* bias, int n_models,
                                int features, hipStream_t s);
-// n_dev (optional): the tile count is read from device memory (at most n_tiles).
-// n_half tiles after the n_tiles have at most half the
-// rows valid and compute only those.
-hipError_t launch_score_table(const LevelItem* items, const Tile* tiles, int n_tiles,
-                              const float* w, const float* bias, int n_models, int features,
-                              const Tuning& tu, hipStream_t s, const int* n_dev = nullptr, int n_half = 0);
+// FP32 scoring on the matrix cores (score32.hip): bands of window rows over
+// runs of 16-column tiles, in 8 lists (one per XCD) taken through counters.
+struct XcdLists {
+    int32_t start[9];
+};
+constexpr int S32_COUNTERS = 8 * PD_MAX_MODELS;  // per model and XCD
+int64_t score32_packed_floats(int n_models);
+// Builds the band table of `rows` window rows (4, 8 or 16) into out (room for
+// the sum of score32_band_capacity over the items); returns its entry count.
+int score32_bands(const LevelItem* items, int n_items, int rows, int grid_cap, Tile* out, XcdLists* xs, int* grid);
+int64_t score32_band_capacity(int nx, int ny, int wc);
+hipError_t launch_pack_score32(const float* w, int n_models, float* out, hipStream_t s);
+// ctr: S32_COUNTERS zeroed ints
+hipError_t launch_score32_table(const LevelItem* items, const Tile* bands, const XcdLists& xs, int grid,
+                                const float* packed, const float* bias, int n_models, int features, int rows,
+                                int* ctr, hipStream_t s);
 
 // Error reporting of the C ABI: sets the calling thread's message and
 // returns `code` (fail) or maps a HIP status (hip_status: PD_OK or PD_E_HIP).

@@ -1,4 +1,6 @@
-// Sliding-window linear-SVM scoring (Section 4.4, Algorithm 6) in FP32.
+// Sliding-window linear-SVM scoring (Section 4.4, Algorithm 6) in FP32 on the
+// vector ALUs, one image per call (pd_score_windows and the single-image
+// forms; batched detection scores on the matrix cores, score32.hip).
 //
 // The score of window (i, j) is a 2-D correlation of the feature planes with
 // the model:  s(i,j) = sum_c sum_a sum_b F_c[i+a][j+b] * W[a][b][c] + bias.
@@ -29,11 +31,6 @@ struct Patch {
     static constexpr int LBP_PQ = (LBP_N + 63) / 64;
     static constexpr int SIZE = HOG_N > LBP_N ? HOG_N : LBP_N;
 };
-template <int R>
-constexpr int patch_floats() {
-    constexpr int a = Patch<R, 64>::SIZE, b = Patch<R, 32>::SIZE, c = Patch<R, 16>::SIZE;
-    return a > b ? (a > c ? a : c) : (b > c ? b : c);
-}
 
 // R window rows per lane from row (ty + group) * STEP: a tile laid out on a
 // grid of STEP rows whose valid rows fit in R < STEP computes only those.
@@ -171,81 +168,10 @@ __global__ void __launch_bounds__(256) score_single_kernel(LevelItem it, const f
                            patches[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)]);
 }
 
-// Tiles of R window rows (pad: model and lane-group width).  Waves are
-// independent; with LOOP a capped grid strides over the table (a separate
-// instantiation: the loop costs registers the one-tile form does not need).
-// Without LOOP, the n_half tiles stored after the n_tiles have at most R / 2
-// valid rows: the blocks past those of the n_tiles compute only R / 2 rows
-// for them (LOOP computes all R rows of every tile: also correct, since rows
-// past the level are not stored).
-template <int FEAT, int R, bool LOOP>
-__global__ void __launch_bounds__(256) score_table_kernel(const LevelItem* __restrict__ items,
-                                                          const Tile* __restrict__ tiles, int n_tiles,
-                                                          const float* __restrict__ wt,
-                                                          const float* __restrict__ bias,
-                                                          const int* __restrict__ n_dev, int n_half) {
-    __shared__ float patches[SC_WAVES][patch_floats<R>()];
-    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    auto one = [&](int wave, auto r_tag) __attribute__((always_inline)) {
-        constexpr int RR = decltype(r_tag)::value;
-        const Tile tl = tiles[wave];
-        const LevelItem& it = items[tl.item];
-        const int m = tile_model(tl), width = tile_width(tl);
-        const float* w = wt + (size_t)m * PD_FEATURE_DIM;
-        const auto o = gmem(it.scores) + (size_t)m * it.ny * it.nx;
-        const auto hog = gmem(it.hog);
-        const auto lbp = gmem(it.lbp);
-        const int lane = threadIdx.x & 63;
-        if (width == 64)
-            score_tile<FEAT, RR, 64, R>(hog, lbp, it.wc, it.hc, w, bias[m], o, tl.ty, tl.tx, lane, patches[wv]);
-        else if (width == 32)
-            score_tile<FEAT, RR, 32, R>(hog, lbp, it.wc, it.hc, w, bias[m], o, tl.ty, tl.tx, lane, patches[wv]);
-        else
-            score_tile<FEAT, RR, 16, R>(hog, lbp, it.wc, it.hc, w, bias[m], o, tl.ty, tl.tx, lane, patches[wv]);
-    };
-    if constexpr (LOOP) {
-        const int n = (n_dev ? min(n_tiles, *n_dev) : n_tiles) + n_half;
-        for (int wave = blockIdx.x * SC_WAVES + wv; wave < n; wave += gridDim.x * SC_WAVES)
-            one(wave, std::integral_constant<int, R>());
-    } else {
-        const int main_blocks = ceil_div(n_tiles, SC_WAVES);  // before the device count applies
-        if constexpr (R >= 4) {
-            if ((int)blockIdx.x >= main_blocks) {
-                const int t = ((int)blockIdx.x - main_blocks) * SC_WAVES + wv;
-                if (t < n_half) one(n_tiles + t, std::integral_constant<int, R / 2>());
-                return;
-            }
-        }
-        if (n_dev) n_tiles = min(n_tiles, *n_dev);
-        const int wave = blockIdx.x * SC_WAVES + wv;
-        if (wave < n_tiles) one(wave, std::integral_constant<int, R>());
-    }
-}
-
 template <int FEAT>
 hipError_t score_single(const LevelItem& it, const float* w, const float* b, int m, hipStream_t s) {
     const int waves = score_tiles_x(it.nx) * score_tiles_y(it.ny) * m;
     score_single_kernel<FEAT><<<ceil_div(waves, SC_WAVES), 256, 0, s>>>(it, w, b, m);
-    return hipGetLastError();
-}
-
-template <int FEAT, int R>
-void launch_rows(bool loop, int grid, const LevelItem* items, const Tile* tiles, int n, const float* w,
-                 const float* b, const int* nd, int n_half, hipStream_t s) {
-    if (loop) score_table_kernel<FEAT, R, true><<<grid, 256, 0, s>>>(items, tiles, n, w, b, nd, n_half);
-    else score_table_kernel<FEAT, R, false><<<grid, 256, 0, s>>>(items, tiles, n, w, b, nd, n_half);
-}
-
-template <int FEAT>
-hipError_t score_table(const LevelItem* items, const Tile* tiles, int n, const float* w, const float* b,
-                       const Tuning& tu, hipStream_t s, const int* nd, int n_half) {
-    const int rows = tu.score_rows;
-    const int blocks = ceil_div(n, SC_WAVES) + ceil_div(n_half, SC_WAVES);
-    const bool loop = tu.grid > 0 && tu.grid < blocks;
-    const int grid = loop ? tu.grid : blocks;
-    if (rows == 16) launch_rows<FEAT, 16>(loop, grid, items, tiles, n, w, b, nd, n_half, s);
-    else if (rows == 4) launch_rows<FEAT, 4>(loop, grid, items, tiles, n, w, b, nd, n_half, s);
-    else launch_rows<FEAT, SC_R>(loop, grid, items, tiles, n, w, b, nd, n_half, s);
     return hipGetLastError();
 }
 
@@ -258,18 +184,6 @@ hipError_t launch_score_single(const LevelItem& it, const float* w, const float*
         case PD_FEAT_HOG: return score_single<PD_FEAT_HOG>(it, w, bias, n_models, s);
         case PD_FEAT_LBP: return score_single<PD_FEAT_LBP>(it, w, bias, n_models, s);
         default: return score_single<PD_FEAT_HOG | PD_FEAT_LBP>(it, w, bias, n_models, s);
-    }
-}
-
-hipError_t launch_score_table(const LevelItem* items, const Tile* tiles, int n_tiles, const float* w,
-                              const float* bias, int n_models, int features, const Tuning& tu, hipStream_t s,
-                              const int* n_dev, int n_half) {
-    (void)n_models;
-    if (n_tiles <= 0 && n_half <= 0) return hipSuccess;
-    switch (features & (PD_FEAT_HOG | PD_FEAT_LBP)) {
-        case PD_FEAT_HOG: return score_table<PD_FEAT_HOG>(items, tiles, n_tiles, w, bias, tu, s, n_dev, n_half);
-        case PD_FEAT_LBP: return score_table<PD_FEAT_LBP>(items, tiles, n_tiles, w, bias, tu, s, n_dev, n_half);
-        default: return score_table<PD_FEAT_HOG | PD_FEAT_LBP>(items, tiles, n_tiles, w, bias, tu, s, n_dev, n_half);
     }
 }
 

@@ -1,0 +1,464 @@
+// Window scoring in FP32 on the matrix cores (Section 4.4, Algorithm 6 recast
+// as a GEMM on v_mfma_f32_16x16x4_f32: FP32 products, FP32 sums).
+//
+// The score of window (i, j) is the 2-D correlation
+//   s(i, j) = sum_a sum_b sum_c F_c[i + a][j + b] * W[a][b][c] + bias.
+// With one model a GEMM needs a second column dimension, and here it is the
+// window's own column offsets: the 16 columns of an MFMA are 2 adjacent
+// window rows x 8 column offsets.  For window rows (i, i + 1) and feature
+// columns j0 .. j0 + 15,
+//   O[m][(s, b)] = sum over feature rows r = i .. i + 16 and channels c of
+//                  F_c[r][j0 + m] * W[r - i - s][b][c],
+// with W zero outside the model's 15 HOG block rows / 16 LBP cell rows and,
+// for HOG, past its 7 block columns: M = 16 feature columns, K = the pair's
+// 16 (HOG) / 17 (LBP) feature rows x channels, in chunks of 4 channels of
+// one row.  Window (i + s, j) then sums O[j + b - j0][(s, b)] over b = 0..7:
+// a diagonal of the tile, begun in the tile to its left (a carry of 7
+// windows per row).  The issued products are 1.13x the useful ones (the
+// 17th / 16th row for the pair's second window row, HOG's eighth column
+// offset) plus ragged tile and band edges; over the 1242x375 pyramid, 1.30x.
+// (With the 16 row offsets as the columns instead, a feature row is
+// multiplied with all 16 offsets, most of them outside the window grid near
+// a level's top and bottom: 1.92x.)
+//
+// A workgroup of 4 waves owns a band of window rows of one level and walks
+// a run of 64-column tiles left to right; wave u computes sub-tile u
+// (feature columns 16 u .. 16 u + 15 of the tile) for all the band's row
+// pairs, so the waves' MFMA work per row is equal.  Per tile, the band's
+// feature rows stream through LDS once for all four waves: a row's 64
+// columns of all channels arrive as 16-byte loads (812 pieces, up to four
+// per thread, two rows ahead in registers), are written sub-tile- and
+// channel-major, one barrier, then each wave reads its A fragments (one row,
+// 4 channels, 16 columns: one 4-byte read per lane, no bank conflicts) and
+// runs them against the B fragments of the pairs the row reaches, read from
+// the model's weights in LDS (one 4-byte read per lane and MFMA).  A window's
+// diagonal begins in the sub-tile to its left: each wave hands its carry to
+// the next through LDS (wave 3's to wave 0 of the next tile); a run that does
+// not start its row first recomputes the tile to its left, in wave 3 only.
+// Each feature row is fetched once per tile of a band, as whole 64-column
+// runs of each channel (a band covers a whole level of a 1242x375 frame).
+// Each window's sum runs in one order whatever the band, the run or the
+// batch: per sub-tile, feature rows ascending, within a row the HOG then the
+// LBP chunks; then the diagonal's b ascending within the window's sub-tile,
+// plus the carry (b ascending within the sub-tile to its left), plus the
+// bias.
+#include <algorithm>
+#include <cstdint>
+#include <vector>
+
+#include "pd_internal.h"
+
+namespace pd {
+namespace {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int S32_HOG_T = PD_HOG_BLOCK / 4;             // 9 chunks of 4 channels
+constexpr int S32_LBP_T = (PD_LBP_BINS + 3) / 4;         // 15: channel 59 has zero weight
+constexpr int S32_HOG_K = PD_WIN_BLOCKS_Y + 1;           // 16 feature rows per pair
+constexpr int S32_LBP_K = PD_WIN_CELLS_Y + 1;            // 17
+// Weight row a (-1 .. K - 1, zero outside the model) holds [t][b 8][c 4]
+// floats, plus 2: the s = 1 lanes then read 2 banks away from the s = 0 ones
+constexpr int S32_HOG_RS = S32_HOG_T * 32 + 2;
+constexpr int S32_LBP_RS = S32_LBP_T * 32 + 2;
+constexpr int S32_HOG_N = (S32_HOG_K + 1) * S32_HOG_RS;
+constexpr int S32_LBP_N = (S32_LBP_K + 1) * S32_LBP_RS;
+constexpr int S32_MODEL = (S32_HOG_N + S32_LBP_N + 3) / 4 * 4;  // floats per packed model (54 KB)
+constexpr int S32_WAVES = 4;                             // waves per workgroup (a band's row pairs)
+constexpr int S32_OS = 17;                               // row stride of a staged 16 x 16 O tile
+constexpr int S32_SUB = 16;                              // feature columns per sub-tile (one MFMA's M)
+constexpr int S32_TILE = S32_WAVES * S32_SUB;            // feature columns per tile
+constexpr int S32_GRID_MAX = 512;                        // two workgroups per CU
+// a staged feature row: HOG [sub-tile 4][36][16] floats, then LBP
+// [sub-tile 4][60][16] bytes (channel 59 is never written: its weight is
+// zero and any byte is finite); during a tile's write-back the same bytes
+// hold the waves' O tiles and the carries between sub-tiles
+constexpr int S32_STG_LBP = S32_WAVES * PD_HOG_BLOCK * S32_SUB * 4;
+constexpr int S32_STAGE = S32_STG_LBP + S32_WAVES * 60 * S32_SUB;
+constexpr int S32_PIECES_H = PD_HOG_BLOCK * S32_TILE / 4;  // 16-byte pieces of a staged row: 576 HOG
+constexpr int S32_PIECES = S32_PIECES_H + PD_LBP_BINS * S32_TILE / 16;  // + 236 LBP
+constexpr int S32_PPT = (S32_PIECES + 64 * S32_WAVES - 1) / (64 * S32_WAVES);  // pieces per thread (4)
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// ---- weight packing --------------------------------------------------------
+// Model m's floats at m * S32_MODEL: HOG rows a = -1 .. 15, then LBP rows
+// a = -1 .. 16; element (a, t, b, k) = W[a][b][4 t + k] (zero outside the
+// model: a < 0, a past its rows, HOG b = 7, LBP channel 59).
+__global__ void pack32_kernel(const float* __restrict__ w, int n_models, float* __restrict__ out) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n_models * S32_MODEL) return;
+    const int m = e / S32_MODEL, q = e - m * S32_MODEL;
+    const float* wm = w + (size_t)m * PD_FEATURE_DIM;
+    float v = 0.0f;
+    if (q < S32_HOG_N) {
+        const int row = q / S32_HOG_RS, x = q - row * S32_HOG_RS;
+        const int a = row - 1, t = x >> 5, b = (x >> 2) & 7, c = 4 * t + (x & 3);
+        if (x < S32_HOG_T * 32 && a >= 0 && a < PD_WIN_BLOCKS_Y && b < PD_WIN_BLOCKS_X)
+            v = wm[(a * PD_WIN_BLOCKS_X + b) * PD_HOG_BLOCK + c];
+    } else if (q < S32_HOG_N + S32_LBP_N) {
+        const int q2 = q - S32_HOG_N;
+        const int row = q2 / S32_LBP_RS, x = q2 - row * S32_LBP_RS;
+        const int a = row - 1, t = x >> 5, b = (x >> 2) & 7, c = 4 * t + (x & 3);
+        if (x < S32_LBP_T * 32 && a >= 0 && a < PD_WIN_CELLS_Y && c < PD_LBP_BINS)
+            v = wm[PD_HOG_DIM + (a * PD_WIN_CELLS_X + b) * PD_LBP_BINS + c];
+    }
+    out[e] = v;
+}
+
+// ---- scoring -----------------------------------------------------------------
+// Band table entry (Tile): item, ty = the band's first window row (even),
+// tx = its run's first tile, pad = the run's tile count.  The table holds 8
+// lists, one per XCD (entries xs.start[x] .. xs.start[x + 1] - 1, longest
+// first); the workgroups on XCD x take its entries in turn from the counter
+// ctr[model * 8 + x] (zero at launch).  NP: row pairs per band.
+template <int FEAT, int NP>
+__global__ void __launch_bounds__(64 * S32_WAVES) score32_kernel(const LevelItem* __restrict__ items,
+                                                                 const Tile* __restrict__ bands, XcdLists xs,
+                                                                 const float* __restrict__ packed,
+                                                                 const float* __restrict__ bias,
+                                                                 int* __restrict__ ctr) {
+    constexpr bool HOG = (FEAT & PD_FEAT_HOG) != 0, LBP = (FEAT & PD_FEAT_LBP) != 0;
+    constexpr int K = LBP ? S32_LBP_K : S32_HOG_K;  // feature rows per pair
+    // write-back scratch inside the staging bytes: per wave one O tile, then
+    // the carries of waves 0..2 for the next sub-tile ([pair][row s][window
+    // 0..7] floats; windows 8.. of a sub-tile lie within it)
+    constexpr int O_FLOATS = 16 * S32_OS, C_FLOATS = NP * 16;
+    static_assert((S32_WAVES * O_FLOATS + (S32_WAVES - 1) * C_FLOATS) * 4 <= S32_STAGE, "write-back scratch");
+    __shared__ float wsh[S32_MODEL];
+    __shared__ __attribute__((aligned(16))) uint8_t stg[S32_STAGE];
+    __shared__ float carry3[2][C_FLOATS];  // wave 3's carry into the next tile, by tile parity
+    __shared__ int item_k;
+    const int model = blockIdx.y;
+    {
+        const float4* src = reinterpret_cast<const float4*>(packed + (size_t)model * S32_MODEL);
+        float4* dst = reinterpret_cast<float4*>(wsh);
+        for (int e = threadIdx.x; e < S32_MODEL / 4; e += 64 * S32_WAVES) dst[e] = src[e];
+    }
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // = this wave's sub-tile
+    const int col = lane & 15, kk = lane >> 4;  // A: feature column, channel within the chunk
+    const int s = (lane >> 3) & 1, b = lane & 7;  // B: window row in the pair, column offset (kk: channel)
+    // this lane's B element of weight row a' - s (a' = row within the pair's K range), chunk 0
+    const float* bh = wsh + (1 - s) * S32_HOG_RS + 4 * b + kk;
+    const float* bl = wsh + S32_HOG_N + (1 - s) * S32_LBP_RS + 4 * b + kk;
+    // A element of chunk 0 in the staged row (this wave's sub-tile)
+    const float* ah = reinterpret_cast<const float*>(stg) + wave * PD_HOG_BLOCK * S32_SUB + lane;
+    const uint8_t* al = stg + S32_STG_LBP + wave * 60 * S32_SUB + lane;
+    float* const ow = reinterpret_cast<float*>(stg) + wave * O_FLOATS;
+    float* const cw = reinterpret_cast<float*>(stg) + S32_WAVES * O_FLOATS;  // carries of waves 0..2
+    const float bm = bias[model];
+    // write-back roles (lanes 0..31): window row e_s of the pair, window e_w
+    // of the 16 the sub-tile completes (its columns - 7 .. + 8)
+    const int e_s = (lane >> 4) & 1, e_w = lane & 15;
+    const float* oe = ow + 8 * e_s;
+    const int x = blockIdx.x & 7;  // this workgroup's XCD (workgroups are dealt to the 8 XCDs in turn)
+    const int first = xs.start[x], n_list = xs.start[x + 1] - first;
+    int* const my_ctr = ctr + model * 8 + x;
+    __syncthreads();
+
+    for (;;) {
+        if (tid == 0) item_k = __hip_atomic_fetch_add(my_ctr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const int k = item_k;
+        __syncthreads();
+        if (k >= n_list) break;  // the whole workgroup, once the list is taken
+        const Tile bt = bands[first + k];
+        const LevelItem& it = items[bt.item];
+        const int wc = it.wc, hc = it.hc, wb = wc - 1, hb = hc - 1, nx = it.nx, ny = it.ny;
+        const int i0 = bt.ty;
+        const int np = min(NP, (ny - i0 + 1) >> 1);  // pairs with a window row inside the level
+        const int nrows = 2 * np + K - 2;
+        const int n_sub = (wc + S32_SUB - 1) / S32_SUB;  // sub-tiles of the level's row
+        const uint32_t hplane = (uint32_t)hb * (uint32_t)wb, lplane = (uint32_t)hc * (uint32_t)wc;
+        const auto rh = planes_rsrc(it.hog, (uint64_t)PD_HOG_BLOCK * hplane * 4);
+        // the buffer checks each dword of a load against its range: a 16-byte
+        // LBP piece ending at the planes' end can start mid-dword, so the
+        // range reaches 3 bytes further (into the level's own score buffer,
+        // which follows its LBP planes) for that dword's valid bytes
+        const auto rl = planes_rsrc(it.lbp, (uint64_t)PD_LBP_BINS * lplane + 3);
+        const auto out = gmem(it.scores) + (size_t)model * ny * nx;
+        const int tx_end = bt.tx + bt.pad;
+        for (int tx = bt.tx > 0 ? bt.tx - 1 : 0; tx < tx_end; ++tx) {
+            const bool lead = tx < bt.tx;  // only wave 3's carry is wanted
+            const int j0 = tx * S32_TILE;
+            // this wave computes when its sub-tile holds level columns
+            const bool busy = 4 * tx + wave < n_sub && (!lead || wave == S32_WAVES - 1);
+            // this thread's pieces of a row, offsets without the row (a
+            // scalar): columns past the level's edge read whatever finite
+            // values follow (they reach only windows past the edge), and past
+            // the planes' end the buffer returns zeros
+            uint32_t voff[S32_PPT];
+            int kind[S32_PPT];  // 1 HOG, 2 LBP, 0 none
+            uint32_t sdst[S32_PPT];
+#pragma unroll
+            for (int q = 0; q < S32_PPT; ++q) {
+                const int e = tid + 64 * S32_WAVES * q;
+                if (HOG && e < S32_PIECES_H) {
+                    const int c = e / (S32_TILE / 4), c4 = e % (S32_TILE / 4);  // channel, 4-column group
+                    kind[q] = 1;
+                    voff[q] = ((uint32_t)c * hplane + (uint32_t)(j0 + 4 * c4)) * 4u;
+                    sdst[q] = (((c4 >> 2) * PD_HOG_BLOCK + c) * S32_SUB + 4 * (c4 & 3)) * 4;
+                } else if (LBP && e >= S32_PIECES_H && e < S32_PIECES) {
+                    const int e2 = e - S32_PIECES_H, c = e2 >> 2, u = e2 & 3;  // channel, sub-tile
+                    kind[q] = 2;
+                    voff[q] = (uint32_t)c * lplane + (uint32_t)(j0 + S32_SUB * u);
+                    sdst[q] = S32_STG_LBP + (u * 60 + c) * S32_SUB;
+                } else {
+                    kind[q] = 0;
+                    voff[q] = 0;
+                    sdst[q] = 0;
+                }
+            }
+            struct RowRegs {
+                u32x4 v[S32_PPT];
+            };
+            auto load = [&](int r, RowRegs& g) __attribute__((always_inline)) {
+                const uint32_t roh = (uint32_t)min(i0 + r, hb - 1) * (uint32_t)wb * 4u;
+                const uint32_t rol = (uint32_t)min(i0 + r, hc - 1) * (uint32_t)wc;
+#pragma unroll
+                for (int q = 0; q < S32_PPT; ++q) {
+                    if (kind[q] == 1)
+                        g.v[q] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rh, voff[q], roh, 0));
+                    else if (kind[q] == 2)
+                        g.v[q] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rl, voff[q], rol, 0));
+                }
+            };
+            auto stage = [&](const RowRegs& g) __attribute__((always_inline)) {
+#pragma unroll
+                for (int q = 0; q < S32_PPT; ++q)
+                    if (kind[q]) *reinterpret_cast<u32x4*>(stg + sdst[q]) = g.v[q];
+            };
+            f32x4 acc[NP];
+#pragma unroll
+            for (int p = 0; p < NP; ++p) acc[p] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+            float ha[S32_HOG_T], lf[S32_LBP_T];
+            // staged row r against the pairs that reach it (K row a' = r - 2 p)
+            auto mfmas = [&](int r) __attribute__((always_inline)) {
+                const int p_lo = max(0, (r - K + 2) >> 1), p_hi = min(np - 1, r >> 1);
+#pragma unroll
+                for (int p = 0; p < NP; ++p) {
+                    if (p < p_lo || p > p_hi) continue;  // uniform
+                    const int a = r - 2 * p;
+                    // the pair's B fragments are all read before its MFMAs
+                    if (HOG && a < S32_HOG_K) {
+                        const float* bq = bh + a * S32_HOG_RS;
+                        float bv[S32_HOG_T];
+#pragma unroll
+                        for (int t = 0; t < S32_HOG_T; ++t) bv[t] = bq[32 * t];
+#pragma unroll
+                        for (int t = 0; t < S32_HOG_T; ++t)
+                            acc[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(ha[t], bv[t], acc[p], 0, 0, 0);
+                    }
+                    if (LBP) {
+                        const float* bq = bl + a * S32_LBP_RS;
+                        float bv[S32_LBP_T];
+#pragma unroll
+                        for (int t = 0; t < S32_LBP_T; ++t) bv[t] = bq[32 * t];
+#pragma unroll
+                        for (int t = 0; t < S32_LBP_T; ++t)
+                            acc[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(lf[t], bv[t], acc[p], 0, 0, 0);
+                    }
+                }
+            };
+            // one staging slot: row r is written, barrier, every wave reads
+            // its A fragments, barrier (the slot is free again), MFMAs; the
+            // rows two ahead wait in registers
+            auto step = [&](int r, RowRegs& g) __attribute__((always_inline)) {
+                stage(g);
+                load(r + 2, g);
+                __syncthreads();
+                if (busy) {
+                    if constexpr (HOG) {
+#pragma unroll
+                        for (int t = 0; t < S32_HOG_T; ++t) ha[t] = ah[64 * t];
+                    }
+                    if constexpr (LBP) {
+#pragma unroll
+                        for (int t = 0; t < S32_LBP_T; ++t) lf[t] = (float)al[64 * t];
+                    }
+                }
+                __syncthreads();
+                if (busy) mfmas(r);
+            };
+            RowRegs g0, g1;
+            load(0, g0);
+            load(1, g1);
+            for (int r = 0; r < nrows; r += 2) {
+                step(r, g0);
+                if (r + 1 < nrows) step(r + 1, g1);
+            }
+            // write-back.  1: per pair, the O tile through this wave's LDS;
+            // lanes 0..31 sum their window's diagonal within the sub-tile
+            // (b = 7 - e_w .. 7) and the carry for the next sub-tile's window
+            // e_w (< 7: b = 0 .. 6 - e_w, columns 9 + e_w + b)
+            float* const cnext = wave == S32_WAVES - 1 ? carry3[tx & 1] : cw + wave * C_FLOATS;
+            float part[NP];
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                part[p] = 0.0f;
+                if (p >= np) continue;  // uniform
+#pragma unroll
+                for (int v = 0; v < 4; ++v) ow[(4 * kk + v) * S32_OS + col] = acc[p][v];
+                __builtin_amdgcn_wave_barrier();
+                if (lane < 32) {
+                    float sum = 0.0f;
+#pragma unroll
+                    for (int bb = 0; bb < 8; ++bb) {
+                        const int m = e_w - 7 + bb;
+                        sum += m >= 0 ? oe[max(m, 0) * S32_OS + bb] : 0.0f;
+                    }
+                    float next = 0.0f;
+#pragma unroll
+                    for (int bb = 0; bb < 7; ++bb) {
+                        const int m = 9 + e_w + bb;
+                        next += m < 16 ? oe[min(m, 15) * S32_OS + bb] : 0.0f;
+                    }
+                    part[p] = sum;
+                    if (e_w < 8) cnext[p * 16 + e_s * 8 + e_w] = next;
+                }
+                __builtin_amdgcn_wave_barrier();
+            }
+            __syncthreads();
+            // 2: each window adds the carry from the sub-tile to its left
+            // (wave 0: wave 3's of the previous tile, none at the row's start)
+            if (!lead && busy && lane < 32) {
+                const float* cin = wave > 0 ? cw + (wave - 1) * C_FLOATS : (tx > 0 ? carry3[(tx - 1) & 1] : nullptr);
+                const int jw = j0 + S32_SUB * wave - 7 + e_w;
+#pragma unroll
+                for (int p = 0; p < NP; ++p) {
+                    if (p >= np) break;  // uniform
+                    const float c = cin && e_w < 8 ? cin[p * 16 + e_s * 8 + e_w] : 0.0f;
+                    const int i = i0 + 2 * p + e_s;
+                    if (jw >= 0 && jw < nx && i < ny) out[(size_t)i * nx + jw] = (part[p] + c) + bm;
+                }
+            }
+            __syncthreads();  // the staging bytes are written again by the next tile
+        }
+    }
+}
+
+// row pairs per band for the tuning field's window rows per wave (4, 8, 16)
+constexpr int s32_pairs(int rows) { return rows == 4 ? 8 : rows == 16 ? 24 : 16; }
+
+template <int FEAT>
+void launch_feat(int rows, dim3 grid, const LevelItem* items, const Tile* bands, const XcdLists& xs,
+                 const float* packed, const float* bias, int* ctr, hipStream_t s) {
+    if (rows == 4) score32_kernel<FEAT, s32_pairs(4)><<<grid, 64 * S32_WAVES, 0, s>>>(items, bands, xs, packed, bias, ctr);
+    else if (rows == 16) score32_kernel<FEAT, s32_pairs(16)><<<grid, 64 * S32_WAVES, 0, s>>>(items, bands, xs, packed, bias, ctr);
+    else score32_kernel<FEAT, s32_pairs(8)><<<grid, 64 * S32_WAVES, 0, s>>>(items, bands, xs, packed, bias, ctr);
+}
+
+}  // namespace
+
+int64_t score32_packed_floats(int n_models) { return (int64_t)n_models * S32_MODEL; }
+
+// Bands of 4 x `rows` window rows (`rows` = 4, 8 or 16 per wave) over runs
+// of 16-column tiles, for every level of the table, as 8 lists, one per XCD,
+// each longest first.  With 16 frames or more each frame's bands go to one
+// XCD (frames dealt to the least loaded XCD, largest first), so the feature
+// rows of neighbouring tiles and bands meet in one L2; with fewer, the bands
+// themselves are dealt that way.  Runs: whole rows when the batch has enough
+// bands for the machine, else runs of at least 2 tiles (each after the
+// first recomputes one tile).  Returns the entry count; *grid is the launch
+// width (a multiple of 8, at most two workgroups per CU).
+int score32_bands(const LevelItem* items, int n_items, int rows, int grid_cap, Tile* out, XcdLists* xs,
+                  int* grid) {
+    const int P = s32_pairs(rows), band = 2 * P;
+    int64_t n_whole = 0, tiles = 0;
+    int n_frames = 0;
+    for (int q = 0; q < n_items; ++q) {
+        n_frames = std::max(n_frames, items[q].frame + 1);
+        if (items[q].nx <= 0 || items[q].ny <= 0) continue;
+        const int nb = ceil_div(items[q].ny, band);
+        n_whole += nb;
+        tiles += (int64_t)nb * ceil_div(items[q].wc, S32_TILE);  // 64-column tiles
+    }
+    const int run = n_whole >= 512 ? (1 << 30) : (int)std::max<int64_t>(2, (tiles + 1023) / 1024);
+    struct Band {
+        Tile t;
+        int64_t cost;
+    };
+    std::vector<Band> all;
+    std::vector<int64_t> frame_cost(n_frames, 0);
+    for (int q = 0; q < n_items; ++q) {
+        const LevelItem& it = items[q];
+        if (it.nx <= 0 || it.ny <= 0) continue;
+        const int nt = ceil_div(it.wc, S32_TILE);
+        for (int i0 = 0; i0 < it.ny; i0 += band) {
+            const int pairs = std::min(P, (it.ny - i0 + 1) / 2);
+            for (int tx = 0; tx < nt; tx += run) {
+                const int n = std::min(run, nt - tx);
+                // the workgroup's row steps (barriers) over its tiles
+                const int64_t cost = (int64_t)(n + (tx > 0)) * (2 * pairs + S32_LBP_K - 2);
+                all.push_back(Band{Tile{q, i0, tx, n}, cost});
+                frame_cost[it.frame] += cost;
+            }
+        }
+    }
+    auto by_cost = [](const Band& u, const Band& v) { return u.cost > v.cost; };
+    std::vector<int> xcd_of;  // per frame (16 frames or more)
+    int64_t load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    auto least = [&]() { return (int)(std::min_element(load, load + 8) - load); };
+    if (n_frames >= 16) {
+        std::vector<int> order(n_frames);
+        for (int f = 0; f < n_frames; ++f) order[f] = f;
+        std::stable_sort(order.begin(), order.end(), [&](int u, int v) { return frame_cost[u] > frame_cost[v]; });
+        xcd_of.assign(n_frames, 0);
+        for (int f : order) {
+            const int x = least();
+            xcd_of[f] = x;
+            load[x] += frame_cost[f];
+        }
+    }
+    std::stable_sort(all.begin(), all.end(), by_cost);
+    std::vector<std::vector<Tile>> lists(8);
+    for (const Band& u : all) {
+        int x;
+        if (n_frames >= 16) {
+            x = xcd_of[items[u.t.item].frame];
+        } else {
+            x = least();
+            load[x] += u.cost;
+        }
+        lists[x].push_back(u.t);
+    }
+    int n = 0;
+    for (int x = 0; x < 8; ++x) {
+        xs->start[x] = n;
+        for (const Tile& t : lists[x]) out[n++] = t;
+    }
+    xs->start[8] = n;
+    int g = ceil_div(std::max(n, 1), 8) * 8;
+    const int cap = grid_cap > 0 ? std::max(8, grid_cap / 8 * 8) : S32_GRID_MAX;
+    *grid = std::min(g, cap);
+    return n;
+}
+
+// Table capacity for one level: the shortest bands over runs of 2 tiles, the
+// finest the builder makes.
+int64_t score32_band_capacity(int nx, int ny, int wc) {
+    if (nx <= 0 || ny <= 0) return 0;
+    return (int64_t)ceil_div(ny, 2 * s32_pairs(4)) * ceil_div(ceil_div(wc, S32_TILE), 2);
+}
+
+hipError_t launch_pack_score32(const float* w, int n_models, float* out, hipStream_t s) {
+    const int n = n_models * S32_MODEL;
+    pack32_kernel<<<ceil_div(n, 256), 256, 0, s>>>(w, n_models, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_score32_table(const LevelItem* items, const Tile* bands, const XcdLists& xs, int grid,
+                                const float* packed, const float* bias, int n_models, int features, int rows,
+                                int* ctr, hipStream_t s) {
+    if (xs.start[8] <= 0 || n_models <= 0) return hipSuccess;
+    const dim3 g((unsigned)grid, (unsigned)n_models);
+    switch (features & (PD_FEAT_HOG | PD_FEAT_LBP)) {
+        case PD_FEAT_HOG: launch_feat<PD_FEAT_HOG>(rows, g, items, bands, xs, packed, bias, ctr, s); break;
+        case PD_FEAT_LBP: launch_feat<PD_FEAT_LBP>(rows, g, items, bands, xs, packed, bias, ctr, s); break;
+        default: launch_feat<PD_FEAT_HOG | PD_FEAT_LBP>(rows, g, items, bands, xs, packed, bias, ctr, s); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace pd
