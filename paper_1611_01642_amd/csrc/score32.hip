@@ -21,25 +21,29 @@
 // multiplied with all 16 offsets, most of them outside the window grid near
 // a level's top and bottom: 1.92x.)
 //
-// A workgroup of 4 waves owns a band of window rows of one level and walks
-// a run of 64-column tiles left to right; wave u computes sub-tile u
-// (feature columns 16 u .. 16 u + 15 of the tile) for all the band's row
-// pairs, so the waves' MFMA work per row is equal.  Per tile, the band's
-// feature rows stream through LDS once for all four waves: a row's 64
-// columns of all channels arrive as 16-byte loads (812 pieces, up to four
-// per thread, two rows ahead in registers), are written sub-tile- and
-// channel-major, one barrier, then each wave reads its A fragments (one row,
-// 4 channels, 16 columns: one 4-byte read per lane, no bank conflicts) and
-// runs them against the B fragments of the pairs the row reaches, read from
-// the model's weights in LDS (one 4-byte read per lane and MFMA).  A window's
-// diagonal begins in the sub-tile to its left: each wave hands its carry to
-// the next through LDS (wave 3's to wave 0 of the next tile); a run that does
-// not start its row first recomputes the tile to its left, in wave 3 only.
-// Each feature row is fetched once per tile of a band, as whole 64-column
-// runs of each channel (a band covers a whole level of a 1242x375 frame).
-// Each window's sum runs in one order whatever the band, the run or the
-// batch: per sub-tile, feature rows ascending, within a row the HOG then the
-// LBP chunks; then the diagonal's b ascending within the window's sub-tile,
+// A workgroup of 8 waves owns a band of window rows of one level and walks
+// a run of 64-column tiles left to right; wave (u, h) computes sub-tile u
+// (feature columns 16 u .. 16 u + 15 of the tile) for the band's row pairs
+// of parity h, so the waves' MFMA work per row differs by at most one pair.
+// Each wave streams its sub-tile's feature rows through its own LDS region,
+// with no barrier between waves: a row's 16 columns of all channels arrive
+// as 16-byte loads (203 pieces, up to four per lane, two rows ahead in
+// registers), are written channel-major, and read back as A fragments (one
+// row, 4 channels, 16 columns: one 4-byte read per lane, no bank conflicts);
+// the wave's LDS operations run in order, so the next row's writes follow
+// the current row's reads.  The A fragments run against the B fragments of
+// the wave's pairs that the row reaches, read from the model's weights in
+// LDS (one 4-byte read per lane and MFMA).  The two waves of a sub-tile load
+// the same rows, and the four sub-tiles of a tile share the rows' cache
+// lines, close in time, so each feature row is fetched from memory about
+// once per tile of a band (a band covers a whole level of a 1242x375
+// frame).  A window's diagonal begins in the sub-tile to its left: at the
+// end of a tile each wave hands its carry to the next through LDS (sub-tile
+// 3's to sub-tile 0 of the next tile); a run that does not start its row
+// first recomputes the tile to its left, in sub-tile 3 only.  Each window's
+// sum runs in one order whatever the band, the run or the batch: per
+// sub-tile, feature rows ascending, within a row the HOG then the LBP
+// chunks; then the diagonal's b ascending within the window's sub-tile,
 // plus the carry (b ascending within the sub-tile to its left), plus the
 // bias.
 #include <algorithm>
@@ -57,34 +61,38 @@ constexpr int S32_HOG_T = PD_HOG_BLOCK / 4;             // 9 chunks of 4 channel
 constexpr int S32_LBP_T = (PD_LBP_BINS + 3) / 4;         // 15: channel 59 has zero weight
 constexpr int S32_HOG_K = PD_WIN_BLOCKS_Y + 1;           // 16 feature rows per pair
 constexpr int S32_LBP_K = PD_WIN_CELLS_Y + 1;            // 17
-// Weight row a (-1 .. K - 1, zero outside the model) holds [t][b 8][c 4]
-// floats, plus 2: the s = 1 lanes then read 2 banks away from the s = 0 ones
+// Weight row a of the model (HOG 0 .. 14, LBP 0 .. 15) holds [t][b 8][c 4]
+// floats, plus 2: the s = 1 lanes then read 2 banks away from the s = 0 ones.
+// One zero row follows: the B fragments of rows a' - s outside the model
+// read it.
 constexpr int S32_HOG_RS = S32_HOG_T * 32 + 2;
 constexpr int S32_LBP_RS = S32_LBP_T * 32 + 2;
-constexpr int S32_HOG_N = (S32_HOG_K + 1) * S32_HOG_RS;
-constexpr int S32_LBP_N = (S32_LBP_K + 1) * S32_LBP_RS;
-constexpr int S32_MODEL = (S32_HOG_N + S32_LBP_N + 3) / 4 * 4;  // floats per packed model (54 KB)
-constexpr int S32_WAVES = 4;                             // waves per workgroup (a band's row pairs)
+constexpr int S32_HOG_N = PD_WIN_BLOCKS_Y * S32_HOG_RS;
+constexpr int S32_LBP_N = PD_WIN_CELLS_Y * S32_LBP_RS;
+constexpr int S32_ZERO = S32_HOG_N + S32_LBP_N;  // the zero row (S32_LBP_RS floats)
+constexpr int S32_MODEL = (S32_ZERO + S32_LBP_RS + 3) / 4 * 4;  // floats per packed model (50 KB)
+constexpr int S32_SUBS = 4;                              // sub-tiles per tile
+constexpr int S32_WAVES = 2 * S32_SUBS;                  // waves per workgroup: sub-tile x pair parity
 constexpr int S32_OS = 17;                               // row stride of a staged 16 x 16 O tile
 constexpr int S32_SUB = 16;                              // feature columns per sub-tile (one MFMA's M)
-constexpr int S32_TILE = S32_WAVES * S32_SUB;            // feature columns per tile
+constexpr int S32_TILE = S32_SUBS * S32_SUB;             // feature columns per tile
 constexpr int S32_GRID_MAX = 512;                        // two workgroups per CU
-// a staged feature row: HOG [sub-tile 4][36][16] floats, then LBP
-// [sub-tile 4][60][16] bytes (channel 59 is never written: its weight is
-// zero and any byte is finite); during a tile's write-back the same bytes
-// hold the waves' O tiles and the carries between sub-tiles
-constexpr int S32_STG_LBP = S32_WAVES * PD_HOG_BLOCK * S32_SUB * 4;
-constexpr int S32_STAGE = S32_STG_LBP + S32_WAVES * 60 * S32_SUB;
-constexpr int S32_PIECES_H = PD_HOG_BLOCK * S32_TILE / 4;  // 16-byte pieces of a staged row: 576 HOG
-constexpr int S32_PIECES = S32_PIECES_H + PD_LBP_BINS * S32_TILE / 16;  // + 236 LBP
-constexpr int S32_PPT = (S32_PIECES + 64 * S32_WAVES - 1) / (64 * S32_WAVES);  // pieces per thread (4)
+// a wave's staged feature row (its sub-tile): HOG [36][16] floats, then LBP
+// [60][16] bytes (channel 59 is never written: its weight is zero and any
+// byte is finite); during a tile's write-back the same bytes hold the wave's
+// O tile and its carries for the next sub-tile
+constexpr int S32_STG_LBP = PD_HOG_BLOCK * S32_SUB * 4;
+constexpr int S32_STAGE = S32_STG_LBP + 60 * S32_SUB;
+constexpr int S32_PIECES_H = PD_HOG_BLOCK * S32_SUB / 4;  // 16-byte pieces of a staged row: 144 HOG
+constexpr int S32_PIECES = S32_PIECES_H + PD_LBP_BINS;     // + 59 LBP
+constexpr int S32_PPT = (S32_PIECES + 63) / 64;            // pieces per lane (4)
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 // ---- weight packing --------------------------------------------------------
-// Model m's floats at m * S32_MODEL: HOG rows a = -1 .. 15, then LBP rows
-// a = -1 .. 16; element (a, t, b, k) = W[a][b][4 t + k] (zero outside the
-// model: a < 0, a past its rows, HOG b = 7, LBP channel 59).
+// Model m's floats at m * S32_MODEL: HOG rows a = 0 .. 14, then LBP rows
+// a = 0 .. 15, then the zero row; element (a, t, b, k) = W[a][b][4 t + k]
+// (zero for HOG b = 7 and LBP channel 59).
 __global__ void pack32_kernel(const float* __restrict__ w, int n_models, float* __restrict__ out) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n_models * S32_MODEL) return;
@@ -92,16 +100,14 @@ __global__ void pack32_kernel(const float* __restrict__ w, int n_models, float* 
     const float* wm = w + (size_t)m * PD_FEATURE_DIM;
     float v = 0.0f;
     if (q < S32_HOG_N) {
-        const int row = q / S32_HOG_RS, x = q - row * S32_HOG_RS;
-        const int a = row - 1, t = x >> 5, b = (x >> 2) & 7, c = 4 * t + (x & 3);
-        if (x < S32_HOG_T * 32 && a >= 0 && a < PD_WIN_BLOCKS_Y && b < PD_WIN_BLOCKS_X)
-            v = wm[(a * PD_WIN_BLOCKS_X + b) * PD_HOG_BLOCK + c];
-    } else if (q < S32_HOG_N + S32_LBP_N) {
+        const int a = q / S32_HOG_RS, x = q - a * S32_HOG_RS;
+        const int t = x >> 5, b = (x >> 2) & 7, c = 4 * t + (x & 3);
+        if (x < S32_HOG_T * 32 && b < PD_WIN_BLOCKS_X) v = wm[(a * PD_WIN_BLOCKS_X + b) * PD_HOG_BLOCK + c];
+    } else if (q < S32_ZERO) {
         const int q2 = q - S32_HOG_N;
-        const int row = q2 / S32_LBP_RS, x = q2 - row * S32_LBP_RS;
-        const int a = row - 1, t = x >> 5, b = (x >> 2) & 7, c = 4 * t + (x & 3);
-        if (x < S32_LBP_T * 32 && a >= 0 && a < PD_WIN_CELLS_Y && c < PD_LBP_BINS)
-            v = wm[PD_HOG_DIM + (a * PD_WIN_CELLS_X + b) * PD_LBP_BINS + c];
+        const int a = q2 / S32_LBP_RS, x = q2 - a * S32_LBP_RS;
+        const int t = x >> 5, b = (x >> 2) & 7, c = 4 * t + (x & 3);
+        if (x < S32_LBP_T * 32 && c < PD_LBP_BINS) v = wm[PD_HOG_DIM + (a * PD_WIN_CELLS_X + b) * PD_LBP_BINS + c];
     }
     out[e] = v;
 }
@@ -113,21 +119,20 @@ __global__ void pack32_kernel(const float* __restrict__ w, int n_models, float* 
 // first); the workgroups on XCD x take its entries in turn from the counter
 // ctr[model * 8 + x] (zero at launch).  NP: row pairs per band.
 template <int FEAT, int NP>
-__global__ void __launch_bounds__(64 * S32_WAVES) score32_kernel(const LevelItem* __restrict__ items,
-                                                                 const Tile* __restrict__ bands, XcdLists xs,
-                                                                 const float* __restrict__ packed,
-                                                                 const float* __restrict__ bias,
-                                                                 int* __restrict__ ctr) {
+__global__ void __launch_bounds__(64 * S32_WAVES) __attribute__((amdgpu_waves_per_eu(4)))
+score32_kernel(const LevelItem* __restrict__ items, const Tile* __restrict__ bands, XcdLists xs,
+               const float* __restrict__ packed, const float* __restrict__ bias, int* __restrict__ ctr) {
     constexpr bool HOG = (FEAT & PD_FEAT_HOG) != 0, LBP = (FEAT & PD_FEAT_LBP) != 0;
     constexpr int K = LBP ? S32_LBP_K : S32_HOG_K;  // feature rows per pair
-    // write-back scratch inside the staging bytes: per wave one O tile, then
-    // the carries of waves 0..2 for the next sub-tile ([pair][row s][window
-    // 0..7] floats; windows 8.. of a sub-tile lie within it)
-    constexpr int O_FLOATS = 16 * S32_OS, C_FLOATS = NP * 16;
-    static_assert((S32_WAVES * O_FLOATS + (S32_WAVES - 1) * C_FLOATS) * 4 <= S32_STAGE, "write-back scratch");
+    constexpr int NQ = NP / 2;                      // this wave's pairs: p = 2 q + h
+    // write-back scratch in the wave's staging bytes: its O tile, then its
+    // carries for the next sub-tile ([pair][row s][window 0..7] floats;
+    // windows 8.. of a sub-tile lie within it)
+    constexpr int O_FLOATS = 16 * S32_OS, C_FLOATS = NQ * 16;
+    static_assert((O_FLOATS + C_FLOATS) * 4 <= S32_STAGE, "write-back scratch");
     __shared__ float wsh[S32_MODEL];
-    __shared__ __attribute__((aligned(16))) uint8_t stg[S32_STAGE];
-    __shared__ float carry3[2][C_FLOATS];  // wave 3's carry into the next tile, by tile parity
+    __shared__ __attribute__((aligned(16))) uint8_t stg[S32_WAVES][S32_STAGE];
+    __shared__ float carry3[2][2][C_FLOATS];  // sub-tile 3's carry into the next tile, by tile parity and h
     __shared__ int item_k;
     const int model = blockIdx.y;
     {
@@ -136,22 +141,35 @@ __global__ void __launch_bounds__(64 * S32_WAVES) score32_kernel(const LevelItem
         for (int e = threadIdx.x; e < S32_MODEL / 4; e += 64 * S32_WAVES) dst[e] = src[e];
     }
     const int tid = threadIdx.x, lane = tid & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // = this wave's sub-tile
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int u = wave & (S32_SUBS - 1), h = wave / S32_SUBS;  // sub-tile, pair parity
     const int col = lane & 15, kk = lane >> 4;  // A: feature column, channel within the chunk
     const int s = (lane >> 3) & 1, b = lane & 7;  // B: window row in the pair, column offset (kk: channel)
-    // this lane's B element of weight row a' - s (a' = row within the pair's K range), chunk 0
-    const float* bh = wsh + (1 - s) * S32_HOG_RS + 4 * b + kk;
-    const float* bl = wsh + S32_HOG_N + (1 - s) * S32_LBP_RS + 4 * b + kk;
-    // A element of chunk 0 in the staged row (this wave's sub-tile)
-    const float* ah = reinterpret_cast<const float*>(stg) + wave * PD_HOG_BLOCK * S32_SUB + lane;
-    const uint8_t* al = stg + S32_STG_LBP + wave * 60 * S32_SUB + lane;
-    float* const ow = reinterpret_cast<float*>(stg) + wave * O_FLOATS;
-    float* const cw = reinterpret_cast<float*>(stg) + S32_WAVES * O_FLOATS;  // carries of waves 0..2
+    // this lane's B element of weight row a' - s (a' = row within the pair's
+    // K range), chunk 0; rows outside the model read the zero row
+    const int blane = 4 * b + kk;
+    auto b_hog = [&](int a) -> const float* {
+        const int w = a - s;
+        return wsh + ((unsigned)w < (unsigned)PD_WIN_BLOCKS_Y ? w * S32_HOG_RS : S32_ZERO) + blane;
+    };
+    auto b_lbp = [&](int a) -> const float* {
+        const int w = a - s;
+        return wsh + ((unsigned)w < (unsigned)PD_WIN_CELLS_Y ? S32_HOG_N + w * S32_LBP_RS : S32_ZERO) + blane;
+    };
+    uint8_t* const st = stg[wave];
+    float* const ow = reinterpret_cast<float*>(st);
+    float* const cw = ow + O_FLOATS;  // this wave's carries for the next sub-tile
     const float bm = bias[model];
     // write-back roles (lanes 0..31): window row e_s of the pair, window e_w
     // of the 16 the sub-tile completes (its columns - 7 .. + 8)
     const int e_s = (lane >> 4) & 1, e_w = lane & 15;
     const float* oe = ow + 8 * e_s;
+    // this lane's pieces of a staged row: e = lane + 64 q, written at byte
+    // 16 e; HOG (e < 144): channel e / 4, columns 4 (e % 4) ..; LBP: channel
+    // e - 144 (the LBP bytes start at 16 * 144)
+    static_assert(S32_STG_LBP == 16 * S32_PIECES_H, "pieces are laid out in order");
+    auto is_h = [&](int q) { return HOG && lane + 64 * q < S32_PIECES_H; };
+    auto is_l = [&](int q) { return LBP && lane + 64 * q >= S32_PIECES_H && lane + 64 * q < S32_PIECES; };
     const int x = blockIdx.x & 7;  // this workgroup's XCD (workgroups are dealt to the 8 XCDs in turn)
     const int first = xs.start[x], n_list = xs.start[x + 1] - first;
     int* const my_ctr = ctr + model * 8 + x;
@@ -180,126 +198,110 @@ __global__ void __launch_bounds__(64 * S32_WAVES) score32_kernel(const LevelItem
         const auto out = gmem(it.scores) + (size_t)model * ny * nx;
         const int tx_end = bt.tx + bt.pad;
         for (int tx = bt.tx > 0 ? bt.tx - 1 : 0; tx < tx_end; ++tx) {
-            const bool lead = tx < bt.tx;  // only wave 3's carry is wanted
-            const int j0 = tx * S32_TILE;
-            // this wave computes when its sub-tile holds level columns
-            const bool busy = 4 * tx + wave < n_sub && (!lead || wave == S32_WAVES - 1);
-            // this thread's pieces of a row, offsets without the row (a
-            // scalar): columns past the level's edge read whatever finite
-            // values follow (they reach only windows past the edge), and past
-            // the planes' end the buffer returns zeros
-            uint32_t voff[S32_PPT];
-            int kind[S32_PPT];  // 1 HOG, 2 LBP, 0 none
-            uint32_t sdst[S32_PPT];
+            const bool lead = tx < bt.tx;  // only sub-tile 3's carry is wanted
+            const int j0 = tx * S32_TILE + S32_SUB * u;  // this wave's first column
+            // this wave computes when its sub-tile holds level columns and
+            // it has pairs (uniform)
+            const bool busy = S32_SUBS * tx + u < n_sub && h < np && (!lead || u == S32_SUBS - 1);
+            f32x4 acc[NQ];
 #pragma unroll
-            for (int q = 0; q < S32_PPT; ++q) {
-                const int e = tid + 64 * S32_WAVES * q;
-                if (HOG && e < S32_PIECES_H) {
-                    const int c = e / (S32_TILE / 4), c4 = e % (S32_TILE / 4);  // channel, 4-column group
-                    kind[q] = 1;
-                    voff[q] = ((uint32_t)c * hplane + (uint32_t)(j0 + 4 * c4)) * 4u;
-                    sdst[q] = (((c4 >> 2) * PD_HOG_BLOCK + c) * S32_SUB + 4 * (c4 & 3)) * 4;
-                } else if (LBP && e >= S32_PIECES_H && e < S32_PIECES) {
-                    const int e2 = e - S32_PIECES_H, c = e2 >> 2, u = e2 & 3;  // channel, sub-tile
-                    kind[q] = 2;
-                    voff[q] = (uint32_t)c * lplane + (uint32_t)(j0 + S32_SUB * u);
-                    sdst[q] = S32_STG_LBP + (u * 60 + c) * S32_SUB;
-                } else {
-                    kind[q] = 0;
-                    voff[q] = 0;
-                    sdst[q] = 0;
-                }
-            }
-            struct RowRegs {
-                u32x4 v[S32_PPT];
-            };
-            auto load = [&](int r, RowRegs& g) __attribute__((always_inline)) {
-                const uint32_t roh = (uint32_t)min(i0 + r, hb - 1) * (uint32_t)wb * 4u;
-                const uint32_t rol = (uint32_t)min(i0 + r, hc - 1) * (uint32_t)wc;
+            for (int q = 0; q < NQ; ++q) acc[q] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+            if (busy) {
+                // piece offsets without the row (a scalar): columns past the
+                // level's edge read whatever finite values follow (they reach
+                // only windows past the edge), and past the planes' end the
+                // buffer returns zeros
+                uint32_t voff[S32_PPT];
 #pragma unroll
                 for (int q = 0; q < S32_PPT; ++q) {
-                    if (kind[q] == 1)
-                        g.v[q] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rh, voff[q], roh, 0));
-                    else if (kind[q] == 2)
-                        g.v[q] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rl, voff[q], rol, 0));
+                    const int e = lane + 64 * q;
+                    voff[q] = is_h(q) ? ((uint32_t)(e >> 2) * hplane + (uint32_t)(j0 + 4 * (e & 3))) * 4u
+                                      : (uint32_t)max(e - S32_PIECES_H, 0) * lplane + (uint32_t)j0;
                 }
-            };
-            auto stage = [&](const RowRegs& g) __attribute__((always_inline)) {
+                struct RowRegs {
+                    u32x4 v[S32_PPT];
+                };
+                auto load = [&](int r, RowRegs& g) __attribute__((always_inline)) {
+                    const uint32_t roh = (uint32_t)min(i0 + r, hb - 1) * (uint32_t)wb * 4u;
+                    const uint32_t rol = (uint32_t)min(i0 + r, hc - 1) * (uint32_t)wc;
 #pragma unroll
-                for (int q = 0; q < S32_PPT; ++q)
-                    if (kind[q]) *reinterpret_cast<u32x4*>(stg + sdst[q]) = g.v[q];
-            };
-            f32x4 acc[NP];
-#pragma unroll
-            for (int p = 0; p < NP; ++p) acc[p] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-            float ha[S32_HOG_T], lf[S32_LBP_T];
-            // staged row r against the pairs that reach it (K row a' = r - 2 p)
-            auto mfmas = [&](int r) __attribute__((always_inline)) {
-                const int p_lo = max(0, (r - K + 2) >> 1), p_hi = min(np - 1, r >> 1);
-#pragma unroll
-                for (int p = 0; p < NP; ++p) {
-                    if (p < p_lo || p > p_hi) continue;  // uniform
-                    const int a = r - 2 * p;
-                    // the pair's B fragments are all read before its MFMAs
-                    if (HOG && a < S32_HOG_K) {
-                        const float* bq = bh + a * S32_HOG_RS;
-                        float bv[S32_HOG_T];
-#pragma unroll
-                        for (int t = 0; t < S32_HOG_T; ++t) bv[t] = bq[32 * t];
-#pragma unroll
-                        for (int t = 0; t < S32_HOG_T; ++t)
-                            acc[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(ha[t], bv[t], acc[p], 0, 0, 0);
+                    for (int q = 0; q < S32_PPT; ++q) {
+                        if (is_h(q))
+                            g.v[q] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rh, voff[q], roh, 0));
+                        else if (is_l(q))
+                            g.v[q] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rl, voff[q], rol, 0));
                     }
-                    if (LBP) {
-                        const float* bq = bl + a * S32_LBP_RS;
-                        float bv[S32_LBP_T];
+                };
+                // row r: staged (after the previous row's reads, in the
+                // wave's LDS order), read back as A fragments, against this
+                // wave's pairs that reach it (K row a' = r - 2 p)
+                auto row = [&](int r, RowRegs& g, int r_next) __attribute__((always_inline)) {
 #pragma unroll
-                        for (int t = 0; t < S32_LBP_T; ++t) bv[t] = bq[32 * t];
-#pragma unroll
-                        for (int t = 0; t < S32_LBP_T; ++t)
-                            acc[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(lf[t], bv[t], acc[p], 0, 0, 0);
-                    }
-                }
-            };
-            // one staging slot: row r is written, barrier, every wave reads
-            // its A fragments, barrier (the slot is free again), MFMAs; the
-            // rows two ahead wait in registers
-            auto step = [&](int r, RowRegs& g) __attribute__((always_inline)) {
-                stage(g);
-                load(r + 2, g);
-                __syncthreads();
-                if (busy) {
+                    for (int q = 0; q < S32_PPT; ++q)
+                        if (is_h(q) || is_l(q)) *reinterpret_cast<u32x4*>(st + 16 * (lane + 64 * q)) = g.v[q];
+                    load(r_next, g);
+                    __builtin_amdgcn_wave_barrier();
+                    float ha[S32_HOG_T], lf[S32_LBP_T];
                     if constexpr (HOG) {
 #pragma unroll
-                        for (int t = 0; t < S32_HOG_T; ++t) ha[t] = ah[64 * t];
+                        for (int t = 0; t < S32_HOG_T; ++t) ha[t] = reinterpret_cast<const float*>(st)[64 * t + lane];
                     }
                     if constexpr (LBP) {
 #pragma unroll
-                        for (int t = 0; t < S32_LBP_T; ++t) lf[t] = (float)al[64 * t];
+                        for (int t = 0; t < S32_LBP_T; ++t) lf[t] = (float)st[S32_STG_LBP + 64 * t + lane];
                     }
-                }
-                __syncthreads();
-                if (busy) mfmas(r);
-            };
-            RowRegs g0, g1;
-            load(0, g0);
-            load(1, g1);
-            for (int r = 0; r < nrows; r += 2) {
-                step(r, g0);
-                if (r + 1 < nrows) step(r + 1, g1);
+                    __builtin_amdgcn_wave_barrier();
+                    const int p_lo = max(0, (r - K + 2) >> 1), p_hi = min(np - 1, r >> 1);
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q) {
+                        const int p = 2 * q + h;
+                        if (p < p_lo || p > p_hi) continue;  // uniform
+                        const int a = r - 2 * p;
+                        // the pair's B fragments (LDS reads the scheduler
+                        // interleaves with the MFMAs; the other waves of the
+                        // SIMD cover their latency)
+                        constexpr int NH = HOG ? S32_HOG_T : 0, NB = NH + (LBP ? S32_LBP_T : 0);
+                        float bv[NB];
+                        if (!HOG || a < S32_HOG_K) {
+#pragma unroll
+                            for (int t = 0; t < NH; ++t) bv[t] = b_hog(a)[32 * t];
+#pragma unroll
+                            for (int t = NH; t < NB; ++t) bv[t] = b_lbp(a)[32 * (t - NH)];
+#pragma unroll
+                            for (int t = 0; t < NH; ++t)
+                                acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(ha[t], bv[t], acc[q], 0, 0, 0);
+#pragma unroll
+                            for (int t = NH; t < NB; ++t)
+                                acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(lf[t - NH], bv[t], acc[q], 0, 0, 0);
+                        } else if constexpr (LBP) {  // a = 16: the LBP rows only
+#pragma unroll
+                            for (int t = 0; t < S32_LBP_T; ++t) bv[t] = b_lbp(a)[32 * t];
+#pragma unroll
+                            for (int t = 0; t < S32_LBP_T; ++t)
+                                acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(lf[t], bv[t], acc[q], 0, 0, 0);
+                        }
+                    }
+                };
+                // the next row's loads are issued as soon as this row is
+                // staged, and are in flight during its MFMAs (issued on every
+                // step: the row index is clamped)
+                RowRegs g;
+                load(0, g);
+                for (int r = 0; r < nrows; ++r) row(r, g, r + 1);
             }
             // write-back.  1: per pair, the O tile through this wave's LDS;
             // lanes 0..31 sum their window's diagonal within the sub-tile
             // (b = 7 - e_w .. 7) and the carry for the next sub-tile's window
             // e_w (< 7: b = 0 .. 6 - e_w, columns 9 + e_w + b)
-            float* const cnext = wave == S32_WAVES - 1 ? carry3[tx & 1] : cw + wave * C_FLOATS;
-            float part[NP];
+            float* const cnext = u == S32_SUBS - 1 ? carry3[tx & 1][h] : cw;
+            float part[NQ];
 #pragma unroll
-            for (int p = 0; p < NP; ++p) {
-                part[p] = 0.0f;
-                if (p >= np) continue;  // uniform
+            for (int q = 0; q < NQ; ++q) {
+                part[q] = 0.0f;
+                if (2 * q + h >= np) continue;  // uniform
+                __builtin_amdgcn_wave_barrier();
 #pragma unroll
-                for (int v = 0; v < 4; ++v) ow[(4 * kk + v) * S32_OS + col] = acc[p][v];
+                for (int v = 0; v < 4; ++v) ow[(4 * kk + v) * S32_OS + col] = acc[q][v];
                 __builtin_amdgcn_wave_barrier();
                 if (lane < 32) {
                     float sum = 0.0f;
@@ -314,23 +316,25 @@ __global__ void __launch_bounds__(64 * S32_WAVES) score32_kernel(const LevelItem
                         const int m = 9 + e_w + bb;
                         next += m < 16 ? oe[min(m, 15) * S32_OS + bb] : 0.0f;
                     }
-                    part[p] = sum;
-                    if (e_w < 8) cnext[p * 16 + e_s * 8 + e_w] = next;
+                    part[q] = sum;
+                    if (e_w < 8) cnext[q * 16 + e_s * 8 + e_w] = next;
                 }
-                __builtin_amdgcn_wave_barrier();
             }
             __syncthreads();
             // 2: each window adds the carry from the sub-tile to its left
-            // (wave 0: wave 3's of the previous tile, none at the row's start)
+            // (sub-tile 0: sub-tile 3's of the previous tile, none at the
+            // row's start)
             if (!lead && busy && lane < 32) {
-                const float* cin = wave > 0 ? cw + (wave - 1) * C_FLOATS : (tx > 0 ? carry3[(tx - 1) & 1] : nullptr);
-                const int jw = j0 + S32_SUB * wave - 7 + e_w;
+                const float* cin = u > 0 ? reinterpret_cast<const float*>(stg[wave - 1]) + O_FLOATS
+                                         : (tx > 0 ? carry3[(tx - 1) & 1][h] : nullptr);
+                const int jw = j0 - 7 + e_w;
 #pragma unroll
-                for (int p = 0; p < NP; ++p) {
+                for (int q = 0; q < NQ; ++q) {
+                    const int p = 2 * q + h;
                     if (p >= np) break;  // uniform
-                    const float c = cin && e_w < 8 ? cin[p * 16 + e_s * 8 + e_w] : 0.0f;
+                    const float c = cin && e_w < 8 ? cin[q * 16 + e_s * 8 + e_w] : 0.0f;
                     const int i = i0 + 2 * p + e_s;
-                    if (jw >= 0 && jw < nx && i < ny) out[(size_t)i * nx + jw] = (part[p] + c) + bm;
+                    if (jw >= 0 && jw < nx && i < ny) out[(size_t)i * nx + jw] = (part[q] + c) + bm;
                 }
             }
             __syncthreads();  // the staging bytes are written again by the next tile
