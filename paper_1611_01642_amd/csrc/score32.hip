@@ -142,7 +142,7 @@ score32_kernel(const LevelItem* __restrict__ items, const Tile* __restrict__ ban
     }
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int u = wave & (S32_SUBS - 1), h = wave / S32_SUBS;  // sub-tile, pair parity
+    const int h = wave / S32_SUBS;  // pair parity (the sub-tile rotates, below)
     const int col = lane & 15, kk = lane >> 4;  // A: feature column, channel within the chunk
     const int s = (lane >> 3) & 1, b = lane & 7;  // B: window row in the pair, column offset (kk: channel)
     // this lane's B element of weight row a' - s (a' = row within the pair's
@@ -199,6 +199,12 @@ score32_kernel(const LevelItem* __restrict__ items, const Tile* __restrict__ ban
         const int tx_end = bt.tx + bt.pad;
         for (int tx = bt.tx > 0 ? bt.tx - 1 : 0; tx < tx_end; ++tx) {
             const bool lead = tx < bt.tx;  // only sub-tile 3's carry is wanted
+            // this wave's sub-tile, rotated with the tile and the item: a
+            // row's last tile holds fewer sub-tiles, and the waves of a
+            // sub-tile share a SIMD, so a fixed mapping would leave the
+            // same SIMDs idle on every row's last tile
+            const int rot = (tx + k) & (S32_SUBS - 1);
+            const int u = (wave + rot) & (S32_SUBS - 1);
             const int j0 = tx * S32_TILE + S32_SUB * u;  // this wave's first column
             // this wave computes when its sub-tile holds level columns and
             // it has pairs (uniform)
@@ -252,6 +258,9 @@ score32_kernel(const LevelItem* __restrict__ items, const Tile* __restrict__ ban
                     }
                     __builtin_amdgcn_wave_barrier();
                     const int p_lo = max(0, (r - K + 2) >> 1), p_hi = min(np - 1, r >> 1);
+                    // while it runs MFMA chains a wave issues ahead of the
+                    // SIMD's waves that stage rows, keeping the MFMA pipe fed
+                    __builtin_amdgcn_s_setprio(2);
 #pragma unroll
                     for (int q = 0; q < NQ; ++q) {
                         const int p = 2 * q + h;
@@ -281,6 +290,7 @@ score32_kernel(const LevelItem* __restrict__ items, const Tile* __restrict__ ban
                                 acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(lf[t], bv[t], acc[q], 0, 0, 0);
                         }
                     }
+                    __builtin_amdgcn_s_setprio(0);
                 };
                 // the next row's loads are issued as soon as this row is
                 // staged, and are in flight during its MFMAs (issued on every
@@ -325,7 +335,8 @@ score32_kernel(const LevelItem* __restrict__ items, const Tile* __restrict__ ban
             // (sub-tile 0: sub-tile 3's of the previous tile, none at the
             // row's start)
             if (!lead && busy && lane < 32) {
-                const float* cin = u > 0 ? reinterpret_cast<const float*>(stg[wave - 1]) + O_FLOATS
+                const int w_left = ((u - 1 - rot) & (S32_SUBS - 1)) + S32_SUBS * h;  // the wave of sub-tile u - 1
+                const float* cin = u > 0 ? reinterpret_cast<const float*>(stg[w_left]) + O_FLOATS
                                          : (tx > 0 ? carry3[(tx - 1) & 1][h] : nullptr);
                 const int jw = j0 - 7 + e_w;
 #pragma unroll
