@@ -313,16 +313,25 @@ __device__ __forceinline__ void features_strip(gptr<const uint8_t> __restrict__ 
                 __hip_atomic_fetch_add(cnt + (e & 127u), e >> 7, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             }
             if (DO_HOG) {
-                const int dx = L - Rt;  // Algorithm 4
-                const int dy = T - B;
-                const int ax = abs(dx), ay = abs(dy);
-                const int mn = min(ax, ay), mx = max(ax, ay);
-                const float mag = __builtin_amdgcn_sqrtf((float)(dx * dx + dy * dy));
-                const float r = (float)mn * __builtin_amdgcn_rcpf((float)max(mx, 1));
-                float u = atan_bins(r);                           // [0, 2.25] bins
-                u = (ay > ax) ? 4.5f - u : u;                     // first quadrant
-                float t = ((dx * dy < 0) ? 9.0f - u : u) - 0.5f;  // fold, centres 10+20k
-                t = t < 0.0f ? t + 9.0f : t;                      // [0, 9]
+                // Algorithm 4, in FP32 from the start: the differences, their
+                // squares and products are integers below 2^24, so every step
+                // is exact, and |.| is a free source modifier
+                const float dx = (float)(L - Rt);
+                const float dy = (float)(T - B);
+                const float ax = fabsf(dx), ay = fabsf(dy);
+                const float mag = __builtin_amdgcn_sqrtf(fmaf(dy, dy, dx * dx));
+                const float r = fminf(ax, ay) * __builtin_amdgcn_rcpf(fmaxf(fmaxf(ax, ay), 1.0f));
+                const float u = atan_bins(r);  // [0, 2.25] bins
+                // the angle in the first quadrant as 4.5 + e, e in [-4.5, 0]
+                const float e = (ay > ax) ? -u : u - 4.5f;
+                // folded to [0, 9] bins: 4.5 - e where dx and dy differ in sign
+                // (e's sign bit flipped), else 4.5 + e; where one of them is
+                // zero the two forms give the same votes (0 and 9 bins are one
+                // orientation)
+                const float ef = __uint_as_float(__float_as_uint(e) ^
+                                                 ((__float_as_uint(dx) ^ __float_as_uint(dy)) & 0x80000000u));
+                float t = 4.0f + ef;           // angle - 0.5: bin centres 10 + 20k degrees at integers
+                t = t < 0.0f ? t + 9.0f : t;   // [0, 9]
                 const int dxa = px < 4 ? -1 : 0;
                 // linear interpolation between bins b and b + 1 (t = 9, a
                 // rounding of t + 9 for tiny negative t, is bin 0: b = 8 gives
