@@ -1,10 +1,11 @@
 // Threshold classification (Section 4.4) and non-maximum-suppression
 // refinement (Section 3; Section 4.1 step 5, done here on the GPU).
 //
-// compact: one thread per window; the window's score is the max over the
-//   models (lowest model index on ties); windows with score > threshold are
-//   appended to their frame's candidate list with an atomic counter.  A
-//   frame's list has room for every one of its windows, so none is dropped.
+// compact: four windows per thread, their loads in flight together; a
+//   window's score is the max over the models (lowest model index on ties);
+//   windows with score > threshold are appended to their frame's candidate
+//   list with an atomic counter.  A frame's list has room for every one of
+//   its windows, so none is dropped.
 // select: for a frame with more than PD_MAX_CANDIDATES candidates, the
 //   PD_MAX_CANDIDATES highest-scoring ones (score descending, then level, i,
 //   j ascending: a strict order, keys are distinct) by a radix select over
@@ -28,51 +29,69 @@ __global__ void zero_kernel(int32_t* p, int n) {
     if (i < n) p[i] = 0;
 }
 
-__global__ void __launch_bounds__(256) compact_kernel(const LevelItem* __restrict__ items,
-                                                      const Tile* __restrict__ tiles, int n_models,
-                                                      const double* __restrict__ thresholds, float margin,
-                                                      int32_t* __restrict__ counters,
-                                                      float* __restrict__ cand_score,
-                                                      int4* __restrict__ cand_key, double* __restrict__ cand_s64,
-                                                      int32_t* __restrict__ near_count,
-                                                      int4* __restrict__ near_key, int64_t near_cap, int n_frames,
-                                                      const float* __restrict__ kth) {
+__global__ void __launch_bounds__(CP_THREADS) compact_kernel(const LevelItem* __restrict__ items,
+                                                             const Tile* __restrict__ tiles, int n_models,
+                                                             const double* __restrict__ thresholds, float margin,
+                                                             int32_t* __restrict__ counters,
+                                                             float* __restrict__ cand_score,
+                                                             int4* __restrict__ cand_key, double* __restrict__ cand_s64,
+                                                             int32_t* __restrict__ near_count,
+                                                             int4* __restrict__ near_key, int64_t near_cap, int n_frames,
+                                                             const float* __restrict__ kth) {
     const Tile tl = tiles[blockIdx.x];
     const LevelItem& it = items[tl.item];
     const int n = it.nx * it.ny;
-    const int q = tl.tx * CP_N + threadIdx.x;
-    if (q >= n) return;
-    if (kth) {  // pruned: only windows the network keeps can be detections
-        const int wi = q / it.nx, wj = q - wi * it.nx;
-        if (!(it.logit[(size_t)(wi + PRUNER_WIN_DI) * it.wc + wj + PRUNER_WIN_DJ] >= kth[it.frame])) return;
+    const int q0 = tl.tx * CP_N + threadIdx.x;
+    if (q0 >= n) return;
+    // windows q0 + k * CP_THREADS: every load is issued before the first
+    // decision (windows past the level read its last one and are skipped)
+    int qk[CP_PER];
+    float best[CP_PER];
+    int bm[CP_PER];
+    bool keep[CP_PER];
+#pragma unroll
+    for (int k = 0; k < CP_PER; ++k) {
+        qk[k] = min(q0 + k * CP_THREADS, n - 1);
+        best[k] = it.scores[qk[k]];
+        bm[k] = 0;
+        keep[k] = true;
+        if (kth) {  // pruned: only windows the network keeps can be detections
+            const int wi = qk[k] / it.nx, wj = qk[k] - wi * it.nx;
+            keep[k] = it.logit[(size_t)(wi + PRUNER_WIN_DI) * it.wc + wj + PRUNER_WIN_DJ] >= kth[it.frame];
+        }
     }
-    const float* s = it.scores + q;
-    float best = s[0];
-    int bm = 0;
     for (int m = 1; m < n_models; ++m) {
-        const float v = s[(size_t)m * n];
-        if (v > best) {
-            best = v;
-            bm = m;
+#pragma unroll
+        for (int k = 0; k < CP_PER; ++k) {
+            const float v = it.scores[(size_t)m * n + qk[k]];
+            if (v > best[k]) {
+                best[k] = v;
+                bm[k] = m;
+            }
         }
     }
     const double thr = thresholds[it.frame];
-    const int i = q / it.nx;
-    if (margin > 0.0f && fabs((double)best - thr) < (double)margin) {
-        // too close to call in this precision: rescored in FP64.  near_count
-        // holds one counter per frame and, after them, the length of the
-        // dense list of all frames' near windows (room for every window of
-        // the batch: the bound is never reached)
-        atomicAdd(&near_count[it.frame], 1);
-        const int g = atomicAdd(&near_count[n_frames], 1);
-        if (g < near_cap) near_key[g] = make_int4(it.frame * PD_MAX_LEVELS + it.level, i, q - i * it.nx, bm);
-    } else if ((double)best > thr) {
-        const int pos = atomicAdd(&counters[it.frame], 1);
-        if (pos < it.cand_cap) {  // always: a window is appended once at most
-            const size_t o = (size_t)it.cand_off + pos;
-            cand_score[o] = best;
-            cand_key[o] = make_int4(it.level, i, q - i * it.nx, bm);
-            if (cand_s64) cand_s64[o] = __longlong_as_double(0x7ff8000000000000LL);
+#pragma unroll
+    for (int k = 0; k < CP_PER; ++k) {
+        const int q = q0 + k * CP_THREADS;
+        if (q >= n || !keep[k]) continue;
+        const int i = q / it.nx;
+        if (margin > 0.0f && fabs((double)best[k] - thr) < (double)margin) {
+            // too close to call in this precision: rescored in FP64.  near_count
+            // holds one counter per frame and, after them, the length of the
+            // dense list of all frames' near windows (room for every window of
+            // the batch: the bound is never reached)
+            atomicAdd(&near_count[it.frame], 1);
+            const int g = atomicAdd(&near_count[n_frames], 1);
+            if (g < near_cap) near_key[g] = make_int4(it.frame * PD_MAX_LEVELS + it.level, i, q - i * it.nx, bm[k]);
+        } else if ((double)best[k] > thr) {
+            const int pos = atomicAdd(&counters[it.frame], 1);
+            if (pos < it.cand_cap) {  // always: a window is appended once at most
+                const size_t o = (size_t)it.cand_off + pos;
+                cand_score[o] = best[k];
+                cand_key[o] = make_int4(it.level, i, q - i * it.nx, bm[k]);
+                if (cand_s64) cand_s64[o] = __longlong_as_double(0x7ff8000000000000LL);
+            }
         }
     }
 }
@@ -374,7 +393,7 @@ hipError_t launch_compact(const LevelItem* items, const Tile* tiles, int n_tiles
                           int4* cand_key, double* cand_s64, int32_t* near_count, int4* near_key, int64_t near_cap,
                           int n_frames, const float* kth, hipStream_t s) {
     if (n_tiles <= 0) return hipSuccess;
-    compact_kernel<<<n_tiles, 256, 0, s>>>(items, tiles, n_models, thresholds, margin, counters, cand_score, cand_key,
+    compact_kernel<<<n_tiles, CP_THREADS, 0, s>>>(items, tiles, n_models, thresholds, margin, counters, cand_score, cand_key,
                                            cand_s64, near_count, near_key, near_cap, n_frames, kth);
     return hipGetLastError();
 }

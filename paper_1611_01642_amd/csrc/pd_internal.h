@@ -92,8 +92,10 @@ constexpr int FT_WAVES = 4;  // waves (independent strips) per workgroup
 constexpr int SC_R = 8;
 constexpr int SC_W = 64;
 constexpr int SC_WAVES = 4;  // waves (independent tiles) per workgroup
-// compaction: windows per workgroup
-constexpr int CP_N = 256;
+// compaction: threads per workgroup, windows per thread, windows per workgroup
+constexpr int CP_THREADS = 256;
+constexpr int CP_PER = 4;
+constexpr int CP_N = CP_THREADS * CP_PER;
 // MFMA scoring tile: window rows x window columns
 constexpr int MF_TILE_R = 4;
 constexpr int MF_TILE_C = 64;

@@ -26,13 +26,17 @@ __device__ inline uint32_t q8_coord(int x, int n0, int nk) {
 
 constexpr int RS_BATCH = 8;  // loads in flight per thread while staging
 
+typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
+
 // Output rows y_base .. y_base + rows - 1 (rows <= RS_TY_MAX), columns
 // tx * RS_TX .. + RS_TX - 1.
 __device__ __forceinline__ void resize_tile(gptr<const uint8_t> __restrict__ src, int sw, int sh, int spitch,
                             gptr<uint8_t> __restrict__ dst, int w, int h, int pitch, int y_base, int rows, int tx) {
     __shared__ uint32_t xs[RS_TX];
     __shared__ uint32_t ys[RS_TY_MAX];
-    __shared__ __attribute__((aligned(16))) uint8_t stage[RS_LDS];
+    // 4 bytes past the rectangle's room: a right tap one column past the
+    // image's last one is read (and weighted 0) there
+    __shared__ __attribute__((aligned(16))) uint8_t stage[RS_LDS + 4];
     const int t = threadIdx.x;
     const int x_base = tx * RS_TX;
     if (w == sw && h == sh) {
@@ -121,18 +125,57 @@ __device__ __forceinline__ void resize_tile(gptr<const uint8_t> __restrict__ src
         xb[q] = min(xa[q] + 1, sw - 1);
         if (x0 + q < w) keep |= 255u << (8 * q);
     }
-    // (256-fx)(256-fy) p00 + fx (256-fy) p01 + (256-fx) fy p10 + fx fy p11,
-    // + 2^15, >> 16, grouped by row (the same integer)
-    auto pack4 = [&](auto ra, auto rb, int fy) -> uint32_t {
-        uint32_t packed = 0u;
+    if (staged) {
+        // Per column, the taps of both source rows side by side as 16-bit
+        // halves: (256 - fx) p0 + fx p1 for the two rows in one packed
+        // multiply and one packed multiply-add (at most 256 * 255 per half),
+        // then (256 - fy) top + fy bot + 2^15 as one dot product (below
+        // 2^25): the same integers as the scalar form.  The right tap is
+        // read at xa + 1 from the same address; where the image clamps it to
+        // xa its weight is 0 instead (256 p0 either way).
+        u16x2 wl[4], wr[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int top = (256 - wx[q]) * (int)ra[xa[q]] + wx[q] * (int)ra[xb[q]];
-            const int bot = (256 - wx[q]) * (int)rb[xa[q]] + wx[q] * (int)rb[xb[q]];
-            packed |= (uint32_t)(((256 - fy) * top + fy * bot + (1 << 15)) >> 16) << (8 * q);
+            const int f = xb[q] > xa[q] ? wx[q] : 0;
+            wl[q] = (u16x2)(uint16_t)(256 - f);
+            wr[q] = (u16x2)(uint16_t)f;
+            xa[q] -= sx0;
         }
-        return packed & keep;
-    };
+        for (int r = wave; r < rows; r += 4) {
+            const int y = y_base + r;
+            if (y >= h) break;
+            // wave-uniform row terms
+            const uint32_t sy = __builtin_amdgcn_readfirstlane(ys[r]);
+            const int ya = (int)(sy >> 8);
+            const int fy = (int)(sy & 255);
+            const int yb = min(ya + 1, sh - 1);
+            const int oa = (int)(reinterpret_cast<uintptr_t>(src + (size_t)ya * spitch + sx0) & 3);
+            const int ob = (int)(reinterpret_cast<uintptr_t>(src + (size_t)yb * spitch + sx0) & 3);
+            const uint8_t* ra = stage + (ya - sy0) * span_w * 4 + oa;
+            const uint8_t* rb = stage + (yb - sy0) * span_w * 4 + ob;
+            u16x2 fw;
+            fw.x = (uint16_t)(256 - fy);
+            fw.y = (uint16_t)fy;
+            uint32_t d[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                u16x2 p0, p1;
+                p0.x = ra[xa[q]];
+                p0.y = rb[xa[q]];
+                p1.x = ra[xa[q] + 1];
+                p1.y = rb[xa[q] + 1];
+                d[q] = __builtin_amdgcn_udot2(p0 * wl[q] + p1 * wr[q], fw, 1u << 15, false);
+            }
+            // the bytes at bits 16..23, one per column
+            const uint32_t packed = __builtin_amdgcn_perm(d[1], d[0], 0x0c0c0602u) |
+                                    __builtin_amdgcn_perm(d[3], d[2], 0x06020c0cu);
+            // pitch is a multiple of 16 >= w, so the 4-byte store stays in the row
+            *reinterpret_cast<gptr<uint32_t>>(dst + (size_t)y * pitch + x0) = packed & keep;
+        }
+        return;
+    }
+    // (256-fx)(256-fy) p00 + fx (256-fy) p01 + (256-fx) fy p10 + fx fy p11,
+    // + 2^15, >> 16, grouped by row (the same integer)
     for (int r = wave; r < rows; r += 4) {
         const int y = y_base + r;
         if (y >= h) break;
@@ -140,16 +183,16 @@ __device__ __forceinline__ void resize_tile(gptr<const uint8_t> __restrict__ src
         const int ya = (int)(sy >> 8);
         const int fy = (int)(sy & 255);
         const int yb = min(ya + 1, sh - 1);
-        uint32_t packed;
-        if (staged) {
-            const int oa = (int)(reinterpret_cast<uintptr_t>(src + (size_t)ya * spitch + sx0) & 3);
-            const int ob = (int)(reinterpret_cast<uintptr_t>(src + (size_t)yb * spitch + sx0) & 3);
-            packed = pack4(stage + (ya - sy0) * span_w * 4 + oa - sx0, stage + (yb - sy0) * span_w * 4 + ob - sx0, fy);
-        } else {
-            packed = pack4(src + (size_t)ya * spitch, src + (size_t)yb * spitch, fy);
+        const auto ra = src + (size_t)ya * spitch, rb = src + (size_t)yb * spitch;
+        uint32_t packed = 0u;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int top = (256 - wx[q]) * (int)ra[xa[q]] + wx[q] * (int)ra[xb[q]];
+            const int bot = (256 - wx[q]) * (int)rb[xa[q]] + wx[q] * (int)rb[xb[q]];
+            packed |= (uint32_t)(((256 - fy) * top + fy * bot + (1 << 15)) >> 16) << (8 * q);
         }
         // pitch is a multiple of 16 >= w, so the 4-byte store stays in the row
-        *reinterpret_cast<gptr<uint32_t>>(dst + (size_t)y * pitch + x0) = packed;
+        *reinterpret_cast<gptr<uint32_t>>(dst + (size_t)y * pitch + x0) = packed & keep;
     }
 }
 
