@@ -676,14 +676,16 @@ void fill_tables(const pd_frame* frames, int n_frames, int n_models, const Tunin
 }
 
 // The decision stages of one call, after the scores: threshold and
-// compaction (kth: pruned keep set, or NULL), FP64 rescoring of the windows
-// within the margin (BF16), the selection of the highest-scoring candidates
-// of an overlong list, NMS.
+// compaction (kth: pruned keep set, or NULL; skipped where the scoring kernel
+// took the decisions itself), FP64 rescoring of the windows within the margin
+// (BF16), the selection of the highest-scoring candidates of an overlong
+// list, NMS.
 int enqueue_decide(const DetectRun& R, const DetectLayout& L, const float* weights, const float* bias, int n_models,
                    const pd_params* params, const double* thresholds, int n_frames, pd_box* boxes, int cap,
-                   pd_counts* counts, StageMarks& marks, const float* kth, hipStream_t s) {
+                   pd_counts* counts, StageMarks& marks, const float* kth, bool decided, hipStream_t s) {
     int rc;
-    if ((rc = hip_status(launch_compact(R.items, R.t_cp, R.ncp, n_models, thresholds, L.bf16 ? params->margin : 0.0f,
+    if (!decided &&
+        (rc = hip_status(launch_compact(R.items, R.t_cp, R.ncp, n_models, thresholds, L.bf16 ? params->margin : 0.0f,
                                         R.counters, R.cscore, R.ckey, R.c64, R.near_count, R.near_key, R.near_cap,
                                         n_frames, kth, s),
                          "compact")))
@@ -735,7 +737,7 @@ int enqueue_detect(const DetectRun& R, const DetectLayout& L, const Tuning& tu, 
             // FP32: bands span whole rows of 16-column tiles, which nearly
             // always hold a kept window; the keep set acts in compaction
             rc = hip_status(launch_score32_table(R.items, R.t_sc, R.xs, R.s32_grid, R.s32_pack, bias, n_models,
-                                                 params->features, tu.score_rows, R.s32_ctr, s),
+                                                 params->features, tu.score_rows, R.s32_ctr, Decide32{}, s),
                             "score");
         } else if (L.rowgemm) {
             // one model: the row-GEMM kernel scores whole 64-column strips, which
@@ -755,13 +757,14 @@ int enqueue_detect(const DetectRun& R, const DetectLayout& L, const Tuning& tu, 
         if (rc) return rc;
         marks.mark(PD_STAGE_COMPACT, s);
         return enqueue_decide(R, L, weights, bias, n_models, params, thresholds, n_frames, boxes, cap, counts, marks,
-                              R.kth, s);
+                              R.kth, false, s);
     }
     if ((rc = hip_status(launch_features_table(R.items, R.t_ft, R.nft, params->features, params->clip, params->eps,
                                                tu, s),
                          "features")))
         return rc;
     marks.mark(PD_STAGE_SCORE, s);
+    bool decided = false;
     if (L.rowgemm) {
         if ((rc = hip_status(launch_rowgemm_table(R.items, R.t_sc, R.nsc, R.packed + packed_weight_elems(), bias,
                                                   tu.grid, s),
@@ -772,14 +775,20 @@ int enqueue_detect(const DetectRun& R, const DetectLayout& L, const Tuning& tu, 
                                                tu.grid, s),
                              "bf16 score")))
             return rc;
-    } else if ((rc = hip_status(launch_score32_table(R.items, R.t_sc, R.xs, R.s32_grid, R.s32_pack, bias, n_models,
-                                                     params->features, tu.score_rows, R.s32_ctr, s),
-                                "score"))) {
-        return rc;
+    } else {
+        // FP32 with one model: each window's score is final when stored, and
+        // the scoring kernel appends the candidates itself (bands of 4 or 8
+        // window rows per wave: the shapes with room for it)
+        decided = n_models == 1 && tu.score_rows != 16;
+        const Decide32 dec = decided ? Decide32{thresholds, R.counters, R.cscore, R.ckey} : Decide32{};
+        if ((rc = hip_status(launch_score32_table(R.items, R.t_sc, R.xs, R.s32_grid, R.s32_pack, bias, n_models,
+                                                  params->features, tu.score_rows, R.s32_ctr, dec, s),
+                             "score")))
+            return rc;
     }
     marks.mark(PD_STAGE_COMPACT, s);
     return enqueue_decide(R, L, weights, bias, n_models, params, thresholds, n_frames, boxes, cap, counts, marks,
-                          nullptr, s);
+                          nullptr, decided, s);
 }
 
 }  // namespace

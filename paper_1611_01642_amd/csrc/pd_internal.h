@@ -218,10 +218,19 @@ int64_t score32_packed_floats(int n_models);
 int score32_bands(const LevelItem* items, int n_items, int rows, int grid_cap, Tile* out, XcdLists* xs, int* grid);
 int64_t score32_band_capacity(int nx, int ny, int wc);
 hipError_t launch_pack_score32(const float* w, int n_models, float* out, hipStream_t s);
+// Threshold decisions taken as the FP32 scores are stored (one model, no
+// keep set): windows above their frame's threshold are appended to the
+// frame's candidate list as compaction appends them.  counters NULL: none.
+struct Decide32 {
+    const double* thr;   // per frame
+    int32_t* counters;   // per frame, zeroed: candidates appended
+    float* cscore;       // candidate lists (LevelItem::cand_off, cand_cap)
+    int4* ckey;
+};
 // ctr: S32_COUNTERS zeroed ints
 hipError_t launch_score32_table(const LevelItem* items, const Tile* bands, const XcdLists& xs, int grid,
                                 const float* packed, const float* bias, int n_models, int features, int rows,
-                                int* ctr, hipStream_t s);
+                                int* ctr, const Decide32& dec, hipStream_t s);
 
 // Error reporting of the C ABI: sets the calling thread's message and
 // returns `code` (fail) or maps a HIP status (hip_status: PD_OK or PD_E_HIP).

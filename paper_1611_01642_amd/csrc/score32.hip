@@ -121,7 +121,8 @@ __global__ void pack32_kernel(const float* __restrict__ w, int n_models, float* 
 template <int FEAT, int NP>
 __global__ void __launch_bounds__(64 * S32_WAVES) __attribute__((amdgpu_waves_per_eu(4)))
 score32_kernel(const LevelItem* __restrict__ items, const Tile* __restrict__ bands, XcdLists xs,
-               const float* __restrict__ packed, const float* __restrict__ bias, int* __restrict__ ctr) {
+               const float* __restrict__ packed, const float* __restrict__ bias, int* __restrict__ ctr,
+               Decide32 dec) {
     constexpr bool HOG = (FEAT & PD_FEAT_HOG) != 0, LBP = (FEAT & PD_FEAT_LBP) != 0;
     constexpr int K = LBP ? S32_LBP_K : S32_HOG_K;  // feature rows per pair
     constexpr int NQ = NP / 2;                      // this wave's pairs: p = 2 q + h
@@ -129,11 +130,23 @@ score32_kernel(const LevelItem* __restrict__ items, const Tile* __restrict__ ban
     // carries for the next sub-tile ([pair][row s][window 0..7] floats;
     // windows 8.. of a sub-tile lie within it)
     constexpr int O_FLOATS = 16 * S32_OS, C_FLOATS = NQ * 16;
+    // decisions in this kernel: each wave keeps its NQ x 32 stored scores in
+    // its O tile's bytes for them
+    constexpr bool DEC = NQ * 32 <= O_FLOATS;
     static_assert((O_FLOATS + C_FLOATS) * 4 <= S32_STAGE, "write-back scratch");
     __shared__ float wsh[S32_MODEL];
     __shared__ __attribute__((aligned(16))) uint8_t stg[S32_WAVES][S32_STAGE];
     __shared__ float carry3[2][2][C_FLOATS];  // sub-tile 3's carry into the next tile, by tile parity and h
     __shared__ int item_k;
+    // the decision terms of the current item (Decide32), read where the
+    // scores are stored: no register holds them through the tile loop
+    __shared__ struct {
+        double thr;
+        int32_t* count;  // NULL: no decisions here
+        float* score;
+        int4* key;
+        int cap, level;
+    } drec;
     const int model = blockIdx.y;
     {
         const float4* src = reinterpret_cast<const float4*>(packed + (size_t)model * S32_MODEL);
@@ -183,6 +196,16 @@ score32_kernel(const LevelItem* __restrict__ items, const Tile* __restrict__ ban
         if (k >= n_list) break;  // the whole workgroup, once the list is taken
         const Tile bt = bands[first + k];
         const LevelItem& it = items[bt.item];
+        if (DEC && tid == 0) {
+            drec.count = dec.counters ? dec.counters + it.frame : nullptr;
+            if (dec.counters) {
+                drec.thr = dec.thr[it.frame];
+                drec.score = dec.cscore + it.cand_off;
+                drec.key = dec.ckey + it.cand_off;
+                drec.cap = it.cand_cap;
+                drec.level = it.level;
+            }
+        }
         const int wc = it.wc, hc = it.hc, wb = wc - 1, hb = hc - 1, nx = it.nx, ny = it.ny;
         const int i0 = bt.ty;
         const int np = min(NP, (ny - i0 + 1) >> 1);  // pairs with a window row inside the level
@@ -345,7 +368,37 @@ score32_kernel(const LevelItem* __restrict__ items, const Tile* __restrict__ ban
                     if (p >= np) break;  // uniform
                     const float c = cin && e_w < 8 ? cin[q * 16 + e_s * 8 + e_w] : 0.0f;
                     const int i = i0 + 2 * p + e_s;
-                    if (jw >= 0 && jw < nx && i < ny) out[(size_t)i * nx + jw] = (part[q] + c) + bm;
+                    const bool in = jw >= 0 && jw < nx && i < ny;
+                    const float v = (part[q] + c) + bm;
+                    if (in) out[(size_t)i * nx + jw] = v;
+                    if (DEC) ow[q * 32 + lane] = in ? v : __builtin_nanf("");  // the O tile is consumed
+                }
+                int32_t* const count = DEC ? drec.count : nullptr;
+                if (count) {
+                    // the decisions (Section 4.4), in a loop of their own: the
+                    // wave's candidates take consecutive entries of the
+                    // frame's list, one atomic per wave and pair
+                    const double thr = drec.thr;
+#pragma unroll 1
+                    for (int q = 0; q < NQ; ++q) {
+                        const int p = 2 * q + h;
+                        if (p >= np) break;  // uniform
+                        const float v = ow[q * 32 + lane];
+                        const bool cand = (double)v > thr;  // false for NaN: no window
+                        const uint64_t m = __ballot(cand);
+                        if (!m) continue;
+                        const int first_lane = __builtin_ctzll(m);
+                        int base = 0;
+                        if (lane == first_lane) base = atomicAdd(count, __popcll(m));
+                        base = __shfl(base, first_lane, 64);
+                        if (cand) {
+                            const int pos = base + __popcll(m & ((1ull << lane) - 1ull));
+                            if (pos < drec.cap) {  // always: a window is appended once at most
+                                drec.score[pos] = v;
+                                drec.key[pos] = make_int4(drec.level, i0 + 2 * p + e_s, jw, 0);
+                            }
+                        }
+                    }
                 }
             }
             __syncthreads();  // the staging bytes are written again by the next tile
@@ -358,10 +411,13 @@ constexpr int s32_pairs(int rows) { return rows == 4 ? 8 : rows == 16 ? 24 : 16;
 
 template <int FEAT>
 void launch_feat(int rows, dim3 grid, const LevelItem* items, const Tile* bands, const XcdLists& xs,
-                 const float* packed, const float* bias, int* ctr, hipStream_t s) {
-    if (rows == 4) score32_kernel<FEAT, s32_pairs(4)><<<grid, 64 * S32_WAVES, 0, s>>>(items, bands, xs, packed, bias, ctr);
-    else if (rows == 16) score32_kernel<FEAT, s32_pairs(16)><<<grid, 64 * S32_WAVES, 0, s>>>(items, bands, xs, packed, bias, ctr);
-    else score32_kernel<FEAT, s32_pairs(8)><<<grid, 64 * S32_WAVES, 0, s>>>(items, bands, xs, packed, bias, ctr);
+                 const float* packed, const float* bias, int* ctr, const Decide32& dec, hipStream_t s) {
+    if (rows == 4)
+        score32_kernel<FEAT, s32_pairs(4)><<<grid, 64 * S32_WAVES, 0, s>>>(items, bands, xs, packed, bias, ctr, dec);
+    else if (rows == 16)
+        score32_kernel<FEAT, s32_pairs(16)><<<grid, 64 * S32_WAVES, 0, s>>>(items, bands, xs, packed, bias, ctr, dec);
+    else
+        score32_kernel<FEAT, s32_pairs(8)><<<grid, 64 * S32_WAVES, 0, s>>>(items, bands, xs, packed, bias, ctr, dec);
 }
 
 }  // namespace
@@ -465,13 +521,16 @@ hipError_t launch_pack_score32(const float* w, int n_models, float* out, hipStre
 
 hipError_t launch_score32_table(const LevelItem* items, const Tile* bands, const XcdLists& xs, int grid,
                                 const float* packed, const float* bias, int n_models, int features, int rows,
-                                int* ctr, hipStream_t s) {
+                                int* ctr, const Decide32& dec, hipStream_t s) {
     if (xs.start[8] <= 0 || n_models <= 0) return hipSuccess;
+    // the decisions need the max over the models, and the room of the shapes
+    // of 8 and 16 row pairs per band
+    if (dec.counters && (n_models != 1 || rows == 16)) return hipErrorInvalidValue;
     const dim3 g((unsigned)grid, (unsigned)n_models);
     switch (features & (PD_FEAT_HOG | PD_FEAT_LBP)) {
-        case PD_FEAT_HOG: launch_feat<PD_FEAT_HOG>(rows, g, items, bands, xs, packed, bias, ctr, s); break;
-        case PD_FEAT_LBP: launch_feat<PD_FEAT_LBP>(rows, g, items, bands, xs, packed, bias, ctr, s); break;
-        default: launch_feat<PD_FEAT_HOG | PD_FEAT_LBP>(rows, g, items, bands, xs, packed, bias, ctr, s); break;
+        case PD_FEAT_HOG: launch_feat<PD_FEAT_HOG>(rows, g, items, bands, xs, packed, bias, ctr, dec, s); break;
+        case PD_FEAT_LBP: launch_feat<PD_FEAT_LBP>(rows, g, items, bands, xs, packed, bias, ctr, dec, s); break;
+        default: launch_feat<PD_FEAT_HOG | PD_FEAT_LBP>(rows, g, items, bands, xs, packed, bias, ctr, dec, s); break;
     }
     return hipGetLastError();
 }
