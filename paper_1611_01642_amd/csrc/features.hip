@@ -356,14 +356,22 @@ __device__ __forceinline__ void features_strip(gptr<const uint8_t> __restrict__ 
         }
     };
 
+    // The first cell row's three leading neighbourhood rows.  A cell row's
+    // pixel loop ends holding the next cell row's (pixel rows 8 cy + 7 ..
+    // 8 cy + 9, inside the image for every cell row but the last), so they
+    // are loaded once per strip (clamped, so a lane group with no rows also
+    // reads inside the image).
+    PixRow U, C, D;
+    {
+        const int yb0 = PD_CELL * cy_start - 1 + ((CM && cy_start < cy0) ? 4 : 0);
+        U = load_row<ALIGNED>(img, pitch, w, min(max(yb0, 0), h - 1), x0);
+        C = load_row<ALIGNED>(img, pitch, w, min(yb0 + 1, h - 1), x0);
+        D = load_row<ALIGNED>(img, pitch, w, min(yb0 + 2, h - 1), x0);
+    }
     for (int cy = cy_start; cy <= cy_last; ++cy) {
         // CM's extra row above the strip: only its downward votes are needed
         const bool extra = CM && cy < cy0;
         const int yb = PD_CELL * cy - 1;  // pixel row of neighbourhood row 0
-        const int py0 = extra ? 4 : 0;
-        PixRow U = load_row<ALIGNED>(img, pitch, w, max(yb + py0, 0), x0);
-        PixRow C = load_row<ALIGNED>(img, pitch, w, min(yb + py0 + 1, h - 1), x0);
-        PixRow D = load_row<ALIGNED>(img, pitch, w, min(yb + py0 + 2, h - 1), x0);
         float top[2][PD_HOG_BINS];  // CM: top slots of the blocks of row cy - 1
         if (DO_HOG) {
 #pragma unroll
