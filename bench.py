@@ -176,12 +176,14 @@ def measured_traffic(kernel, batch, tuning):
     rec = json.load(open(path)).get(kernel)
     if not rec:
         return None
-    if any(tuning.get(k) != v for k, v in rec.get("tuning", {}).items()):
-        return None
     src = os.path.join(HERE, rec["source"])
     if hashlib.sha256(open(src, "rb").read()).hexdigest() != rec["sha256"]:
         return None
-    return rec["read_bytes"] + rec["write_bytes"]
+    # one record at one tile shape, or variants taken at several
+    for var in rec.get("variants", [rec]):
+        if all(tuning.get(k) == v for k, v in var.get("tuning", {}).items()):
+            return var["read_bytes"] + var["write_bytes"]
+    return None
 
 
 def frame_thresholds(pd, torch, frames, wts, bias, prm, chunk=256):
