@@ -114,7 +114,9 @@ struct RowRegs {
     // per plane row, HOG: SR BF16 values; LBP: the SR count bytes as 4-byte
     // words (columns 4 d .. 4 d + 3)
     static constexpr int UNITS = HOG ? SR : (SR + 3) / 4;
-    static constexpr int N = (UNITS * NC + 255) / 256;
+    // LBP: elements in blocks of 8 channels x UNITS words x 8 (64 channel
+    // slots, those past the 59th empty), the channel fastest within a block
+    static constexpr int N = HOG ? (UNITS * NC + 255) / 256 : (UNITS * 64 + 255) / 256;
     // HOG: BF16 bits; LBP: four raw counts (converted when stored)
     std::conditional_t<HOG, uint16_t, uint32_t> v[N];
 };
@@ -122,8 +124,8 @@ struct RowRegs {
 // The per-thread offsets are taken once per tile: goff[q], the
 // element's byte offset in the planes without the row (raw buffer loads add
 // the row's byte offset as a scalar), and soff[q], its byte offset in a ring
-// slot (LBP: that of the word's first column).  Clamped elements repeat the
-// last one (same value, same slot).  An LBP word is read from inside its
+// slot (LBP: that of the word's first column).  HOG elements past the last
+// are clamped to it (same value, same slot).  An LBP word is read from inside its
 // plane row: where columns 4 d .. 4 d + 3 reach past the row's end, from
 // the row's last four bytes, and shifted down by the difference (kept in the
 // top byte of soff), so that its columns inside the row get their counts;
@@ -140,17 +142,28 @@ __device__ __forceinline__ void row_offsets(RowOffsets<HOG>& o, int j0, int hcol
     const uint32_t plane = (uint32_t)hrows * (uint32_t)hcols;
 #pragma unroll
     for (int q = 0; q < RowRegs<HOG>::N; ++q) {
-        const int e = min((int)threadIdx.x + 256 * q, U * NC - 1);
-        const int c = e / U, u = e - (e / U) * U;
-        const int col = HOG ? u : 4 * u;
         if constexpr (HOG) {
+            const int e = min((int)threadIdx.x + 256 * q, U * NC - 1);
+            const int c = e / U, col = e - (e / U) * U;
             o.goff[q] = ((uint32_t)c * plane + (uint32_t)min(j0 + col, hcols - 1)) * 2u;
             o.soff[q] = (uint32_t)(col * C + c) * 2u;
         } else {
+            // lanes by 8 channels x 8 words: a wave's staging writes fall in
+            // 32 banks (words 4 columns apart are 120 dwords apart, channels
+            // 2 bytes), its loads in 8 plane rows of 32 contiguous bytes.
+            // Slots past the last channel or element load channel 58's word
+            // and store nothing (bit 31 of soff).
+            const int g = (int)threadIdx.x + 256 * q;
+            const int cl = g & 7, rest = g >> 3;
+            const int uu = rest % U, cb = rest / U;
+            const int cc = 8 * cb + cl;
+            const bool valid = cc < NC && cb < 8;
+            const int cs = min(cc, NC - 1), col4 = 4 * uu;
             // hcols >= 8 (a level holds at least one window)
-            const int start = min(j0 + col, hcols - 4);
-            o.goff[q] = (uint32_t)c * plane + (uint32_t)start;
-            o.soff[q] = (uint32_t)(col * C + c) * 2u | (uint32_t)min(j0 + col - start, 3) << 24;
+            const int start = min(j0 + col4, hcols - 4);
+            o.goff[q] = (uint32_t)cs * plane + (uint32_t)start;
+            o.soff[q] = (uint32_t)(col4 * C + cs) * 2u | (uint32_t)min(j0 + col4 - start, 3) << 24 |
+                        (valid ? 0u : 0x80000000u);
         }
     }
 }
@@ -180,8 +193,9 @@ __device__ __forceinline__ void store_row_fast(const RowRegs<HOG>& r, const RowO
             // value; byte k of the word is column 4 d + k (its channel's
             // slot MF_LBP_C values further on), the last word's column 71
             // past the staged row is skipped
+            if (o.soff[q] & 0x80000000u) continue;
             const uint32_t so = o.soff[q] & 0xffffffu;
-            const uint32_t w = r.v[q] >> (8u * (o.soff[q] >> 24));
+            const uint32_t w = r.v[q] >> (8u * ((o.soff[q] >> 24) & 3u));
             const uint32_t col0 = so / (2u * MF_LBP_C);
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
